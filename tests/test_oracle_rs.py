@@ -1,0 +1,188 @@
+"""Pins of the oracle's recursive skeletonization and DD-PCG (Sections 3.2, 5)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cmatvec, dd, ie, pcg, precond, rs
+from oracle.cpqr import interp_decomp
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
+
+
+def _leaf_proxy_matrix(prob, sd, bi, n_pxy=64, ratio=1.5):
+    """Proxy/near matrix of a leaf box, rebuilt independently of rs.factor_subdomain."""
+    lo, hi, st, cnt = sd.leaves[bi]
+    p = np.arange(st, st + cnt)
+    others = np.setdiff1d(np.arange(len(sd.index)), p)
+    lo, hi = np.array(lo), np.array(hi)
+    ctr = 0.5 * (lo + hi) / prob.n
+    R = ratio * np.max(hi - lo) / prob.n
+    xo = prob.x[sd.index[others]]
+    near = others[np.linalg.norm(xo - ctr, axis=1) < R]
+    th = 2 * np.pi * np.arange(n_pxy) / n_pxy
+    pxy = ctr + R * np.stack([np.cos(th), np.sin(th)], axis=1)
+    xp = prob.x[sd.index[p]]
+    Kp = -np.log(np.linalg.norm(pxy[:, None, :] - xp[None, :, :], axis=2)) / (2 * np.pi)
+    Y = np.vstack([prob.block(sd.index[near], sd.index[p]), Kp * prob.weight * prob.c[sd.index[p]]])
+    return p, others, Y
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-8])
+def test_proxy_id_error_against_full_far_field(tol):
+    # the proxy trick must give an ID of the whole off-diagonal block A_qp (e:id_err)
+    prob = ie.Problem(2, 64)
+    part = dd.Partition(2, 64, 16, 1, dd.CBD)
+    sd = part.subdomains[0]
+    for bi in [0, 9, 27, 63]:
+        p, q, Y = _leaf_proxy_matrix(prob, sd, bi)
+        k, perm, T = interp_decomp(Y, tol)
+        Aqp = prob.block(sd.index[q], sd.index[p])
+        err = np.linalg.norm(Aqp[:, perm[k:]] - Aqp[:, perm[:k]] @ T, 2)
+        assert err <= 20 * tol * np.linalg.norm(Aqp, 2), (bi, err / np.linalg.norm(Aqp, 2))
+        assert 0 < k < len(p)
+
+
+def test_first_level_matches_independent_proxy_build():
+    prob = ie.Problem(2, 32)
+    part = dd.Partition(2, 32, 8, 1, dd.CBD)
+    sd = part.subdomains[3]
+    f = rs.factor_subdomain(prob, part, sd, 1e-6)
+    for bi in range(len(sd.leaves)):
+        p, q, Y = _leaf_proxy_matrix(prob, sd, bi)
+        k, perm, T = interp_decomp(Y, 1e-6)
+        b = f.levels[0][bi]
+        assert np.array_equal(b.sk, p[perm[:k]]) and np.array_equal(b.rd, p[perm[k:]])
+        assert np.allclose(b.T, T, rtol=1e-10, atol=1e-12)
+
+
+def test_elimination_identity_on_one_box():
+    # (e:al)-(e:b): with the box's own L_p U_r, the (r, r) block becomes I and the
+    # (s, s) block becomes B_ss, using the exact block matrix of the box
+    prob = ie.Problem(2, 32)
+    part = dd.Partition(2, 32, 8, 1, dd.CBD)
+    sd = part.subdomains[0]
+    f = rs.factor_subdomain(prob, part, sd, 1e-6)
+    b = f.levels[0][5]
+    idx = np.concatenate([b.rd, b.sk])
+    App = prob.block(sd.index[idx], sd.index[idx])
+    nr, k = len(b.rd), len(b.sk)
+    L = np.eye(nr + k)
+    L[nr:, :nr] = -b.T            # L_p in (r, s) order
+    Ginv = np.linalg.inv(b.G)
+    Brr = b.G.T @ b.G
+    Bsr = b.E @ b.G
+    U = np.eye(nr + k)
+    U[:nr, :nr] = Ginv
+    U[:nr, nr:] = -np.linalg.solve(Brr, Bsr.T)
+    C = U.T @ L.T @ App @ L @ U
+    assert np.allclose(C[:nr, :nr], np.eye(nr), atol=1e-9)
+    assert np.allclose(C[:nr, nr:], 0, atol=1e-9 * np.abs(App).max())
+    assert np.allclose(C[nr:, nr:], b.Bss, rtol=1e-9, atol=1e-12 * np.abs(App).max())
+
+
+def test_tight_tolerance_reproduces_exact_subdomain_solve():
+    prob = ie.Problem(2, 32)
+    part = dd.Partition(2, 32, 8, 1, dd.CBD)
+    R = rs.RSPreconditioner(prob, part, 1e-15)
+    E = precond.ExactPreconditioner(prob, part)
+    r = synth.rhs(prob.N, 2, seed=4).T
+    z1, z2 = R.apply(r), E.apply(r)
+    assert np.linalg.norm(z1 - z2) <= 1e-9 * np.linalg.norm(z2)
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-6, 1e-8])
+def test_rs_apply_error_scales_with_tol(tol):
+    prob = ie.Problem(2, 64)
+    part = dd.Partition(2, 64, 16, 1, dd.CBD)
+    R = rs.RSPreconditioner(prob, part, tol)
+    E = precond.ExactPreconditioner(prob, part)
+    r = synth.rhs(prob.N, 1, seed=0)[0]
+    z1, z2 = R.apply(r), E.apply(r)
+    rel = np.linalg.norm(z1 - z2) / np.linalg.norm(z2)
+    assert rel <= 100 * tol
+    assert rel >= 1e-3 * tol      # compression really happened
+
+
+def test_pcg_with_rs_matches_dense_solve():
+    # first workload of the benchmark family: 64^2 cell grid, CBD m = 16, tol 1e-8,
+    # PCG to 1e-10; solution within 1e-8 of the dense Cholesky solve
+    prob = ie.Problem(2, 64)
+    part = dd.Partition(2, 64, 16, 1, dd.CBD)
+    R = rs.RSPreconditioner(prob, part, 1e-8)
+    A = prob.dense()
+    f = synth.rhs(prob.N, 1, seed=0)[0]
+    u, it, rr = pcg.pcg(lambda X: A @ X, R.apply, f, tol=1e-10, maxit=200)
+    ud = np.linalg.solve(A, f)
+    assert rr <= 1e-10
+    assert np.linalg.norm(u - ud) <= 1e-8 * np.linalg.norm(ud)
+    assert it <= 25
+
+
+def test_variable_coefficients_and_multiple_rhs():
+    n = 48
+    b = synth.coef_smooth(2, n)
+    prob = ie.Problem(2, n, b=b, c=b)
+    part = dd.Partition(2, n, 12, 1, dd.CBD)
+    R = rs.RSPreconditioner(prob, part, 1e-6)
+    A = prob.dense()
+    F = synth.rhs(prob.N, 3, seed=2).T
+    U, its, rr = pcg.pcg(lambda X: A @ X, R.apply, F, tol=1e-10, maxit=200)
+    Ud = np.linalg.solve(A, F)
+    assert np.all(rr <= 1e-10)
+    assert np.linalg.norm(U - Ud) <= 1e-8 * np.linalg.norm(Ud)
+    # multiple right-hand sides are independent columns
+    u0, it0, _ = pcg.pcg(lambda X: A @ X, R.apply, F[:, 0], tol=1e-10, maxit=200)
+    assert it0 == its[0]
+    assert np.allclose(u0, U[:, 0], rtol=0, atol=1e-12 * np.abs(u0).max())
+
+
+def test_iteration_count_stays_flat_with_N():
+    # Section 5: n_it = O(1) as N grows with N/M fixed (CBD)
+    its = []
+    for n in (32, 64, 128):
+        prob = ie.Problem(2, n)
+        part = dd.Partition(2, n, n // 4, 1, dd.CBD)
+        R = rs.RSPreconditioner(prob, part, 1e-6)
+        f = synth.rhs(prob.N, 1, seed=0)[0]
+        _, it, rr = pcg.pcg(lambda X: cmatvec.matvec(prob, X), R.apply, f, tol=1e-10, maxit=200)
+        assert rr <= 1e-10
+        its.append(it)
+    assert max(its) - min(its) <= 4, its
+
+
+def test_schwarz_with_leaf_tiles_and_3d():
+    # RS inside large single-region subdomains (leaf tiles) and in 3D
+    prob = ie.Problem(2, 64)
+    part = dd.Partition(2, 64, 2, 8, dd.SCHWARZ, leaf_side=8)
+    R = rs.RSPreconditioner(prob, part, 1e-8)
+    E = precond.ExactPreconditioner(prob, part)
+    r = synth.rhs(prob.N, 1, seed=0)[0]
+    assert np.linalg.norm(R.apply(r) - E.apply(r)) <= 1e-5 * np.linalg.norm(E.apply(r))
+    p3 = ie.Problem(3, 12)
+    part3 = dd.Partition(3, 12, 4, 1, dd.CBD)
+    R3 = rs.RSPreconditioner(p3, part3, 1e-6, n_pxy=256)
+    E3 = precond.ExactPreconditioner(p3, part3)
+    r3 = synth.rhs(p3.N, 1, seed=0)[0]
+    assert np.linalg.norm(R3.apply(r3) - E3.apply(r3)) <= 1e-3 * np.linalg.norm(E3.apply(r3))
+
+
+@pytest.mark.slow
+def test_last_level_dofs_soft_pin():
+    g = GOLD["t_cbd_strong_2d_S"]
+    prob = ie.Problem(2, g["n"])
+    for row in g["rows"][:3]:
+        part = dd.Partition(2, g["n"], row["m"], 1, dd.CBD)
+        R = rs.RSPreconditioner(prob, part, g["tol"])
+        S = max(s["S"] for s in R.stats())
+        assert abs(S - row["S"]) <= 0.1 * row["S"], (row, S)
+
+
+def test_not_spd_detected():
+    prob = ie.Problem(2, 16)
+    prob.a_self = -prob.a_self      # planted mistake: negative diagonal
+    part = dd.Partition(2, 16, 4, 1, dd.CBD)
+    with pytest.raises(rs.NotSPDError):
+        rs.RSPreconditioner(prob, part, 1e-6)
