@@ -1,0 +1,182 @@
+"""Benchmark of the CBD-RS-PCG hot path on one MI355X.
+
+Workload (2D, 512^2 grid, N = 262144): Laplace first-kind IE with smooth
+coefficients b = c = 1 + 0.5 sin(2 pi x1) cos(2 pi x2); CBD decomposition with
+64^2 partitions, overlap 1 (4 subdomains); RS factors with ID tolerance 1e-6 and
+64 proxy points at 1.5 box sides; 64 right-hand sides f ~ N(0,1) (seed 0);
+PCG to relative residual 1e-10.
+
+One step = the whole hot path on resident inputs: RS factorization of all
+subdomains (mixed form: FP64 ID, FP32 elimination/storage/apply) + PCG on the
+64 right-hand sides at once (FP64 matvec and recurrences).  `value` is the PCG
+solve time of one step in seconds.  After the timed steps, the plain FP64 form
+(FP64 factors, one right-hand side at a time) is timed on a few columns and
+scaled to 64, and the oracle's dense matvec is timed on sampled rows for the
+CPU baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PCG solve time (s) & RS factor GFLOP/s at 2D 512^2, mixed vs FP64, rel res 1e-10"
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
+FP32_PEAK_TFLOPS = 157.3
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--m", type=int, default=64)
+    ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--fp64-cols", type=int, default=2,
+                    help="columns solved one at a time to time the plain FP64 form")
+    ap.add_argument("--cpu-rows", type=int, default=192,
+                    help="rows of the oracle's dense matvec timed for the CPU baseline (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the "
+              "path is described in the design notes and not implemented", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2108_12574_amd as cbd
+    import synth
+
+    dev = torch.device("cuda:0")
+    n, nrhs = args.n, args.nrhs
+    N = n * n
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    coef = torch.tensor(synth.coef_smooth(2, n))
+    P = cbd.Problem(2, n, b=coef, c=coef, device=dev)
+    part = cbd.Partition(P, args.m, 1, cbd.MODE_CBD, 0)
+    F_rhs = torch.tensor(synth.rhs(N, nrhs, seed=0), device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        t0 = time.perf_counter()
+        fac = cbd.Factor(P, part, tol=args.tol, n_pxy=64, proxy_ratio=1.5, precision=cbd.PREC_FP32)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        u, its, rr = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return fac, its, rr, t1 - t0, t2 - t1
+
+    for w in range(args.warmup):
+        step()
+        log("warmup step %d done" % w)
+    cbd.timing.reset()
+    cbd.timing.enable(True)
+    torch.cuda.synchronize()
+    tf, ts, its_all, rr_all = [], [], [], []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        fac, its, rr, a, b = step()
+        tf.append(a)
+        ts.append(b)
+        its_all.append(its)
+        rr_all.append(max(rr))
+        log("step %d: factor %.3f s, pcg %.3f s, iterations %d-%d" % (k, a, b, min(its), max(its)))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    cbd.timing.enable(False)
+    mv_ms, mv_n = cbd.timing.get("matvec")
+    ap_ms, ap_n = cbd.timing.get("apply")
+    st = fac.stats()
+    factor_s = float(np.mean(tf))
+    pcg_s = float(np.mean(ts))
+    n_it = its_all[-1]
+
+    # matvec roofline: product flops 2 N^2 nrhs per launch (kernel evaluations extra)
+    mv_avg_s = mv_ms / 1e3 / max(mv_n, 1)
+    mv_flops = 2.0 * N * N * nrhs
+    achieved = mv_flops / mv_avg_s / 1e12
+
+    # plain FP64 form: FP64 factors, right-hand sides one at a time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac64 = cbd.Factor(P, part, tol=args.tol, n_pxy=64, proxy_ratio=1.5, precision=cbd.PREC_FP64)
+    torch.cuda.synchronize()
+    f64_factor = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    its64 = []
+    for c in range(args.fp64_cols):
+        _, it, _ = cbd.pcg_solve(P, fac64, F_rhs[c], tol=1e-10, maxit=200)
+        its64.append(it)
+    torch.cuda.synchronize()
+    f64_per_col = (time.perf_counter() - t0) / args.fp64_cols
+    f64_pcg = f64_per_col * nrhs
+    log("fp64 form: factor %.3f s, %.3f s per column" % (f64_factor, f64_per_col))
+
+    cpu = None
+    if args.cpu_rows > 0:
+        from oracle import cmatvec, ie
+        O = ie.Problem(2, n, b=coef.numpy(), c=coef.numpy())
+        rows = np.random.default_rng(0).choice(N, args.cpu_rows, replace=False)
+        X = F_rhs.cpu().numpy().T.copy()
+        t0 = time.perf_counter()
+        cmatvec.matvec(O, X, rows=rows)
+        t_rows = time.perf_counter() - t0
+        per_matvec = t_rows * N / args.cpu_rows
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": per_matvec * max(n_it), "unit": "s", "cores": threads, "kind": "oracle",
+               "sample": "oracle dense FP64 matvec (plain C, OpenMP) on %d of %d rows x %d RHS "
+                         "(%.2f s), scaled by N/rows to one matvec (%.1f s) and by the %d PCG "
+                         "iterations; the oracle's RS apply and factor are not included"
+                         % (args.cpu_rows, N, nrhs, t_rows, per_matvec, max(n_it))}
+        log("cpu baseline sample %.2f s" % t_rows)
+
+    out = {
+        "metric": METRIC,
+        "value": pcg_s,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_total / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (matvec, PCG, ID) + f32 (RS elimination, factor storage, apply)",
+        "data": "synthetic",
+        "config": {"workload": "2D Laplace IE %d^2 (N=%d), b=c=1+0.5sin(2pi x1)cos(2pi x2), CBD "
+                               "m=%d delta=1, RS tol %g, 64 proxy pts at 1.5 box sides, %d RHS "
+                               "N(0,1) seed 0, PCG rel res 1e-10" % (n, N, args.m, args.tol, nrhs),
+                   "global_batch": nrhs, "parallelism": "single GPU"},
+        "factor_s": factor_s,
+        "factor_gflops": st["flops"] / factor_s / 1e9,
+        "factor_flops": st["flops"],
+        "S_last_level": st["S"],
+        "factor_bytes": st["bytes"],
+        "n_it": [min(n_it), max(n_it)],
+        "max_relres": max(rr_all),
+        "matvec_avg_ms": mv_avg_s * 1e3,
+        "apply_avg_ms": ap_ms / max(ap_n, 1),
+        "fp64_form": {"factor_s": f64_factor, "pcg_s_est": f64_pcg, "cols_timed": args.fp64_cols,
+                      "n_it": its64,
+                      "note": "PCG time measured on %d columns solved one at a time, scaled to %d"
+                              % (args.fp64_cols, nrhs)},
+        "speedup_mixed_vs_fp64": {"pcg": f64_pcg / pcg_s, "factor": f64_factor / factor_s,
+                                  "total": (f64_pcg + f64_factor) / (pcg_s + factor_s)},
+        "roofline": {"kernel": "kernel_matvec (FP64, %d RHS)" % nrhs, "bound": "alu",
+                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "work": "2 N^2 nrhs FP64 flops per launch (N^2 kernel evaluations extra)"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/* cbd.h - C ABI of the MI355X (gfx950) implementation of the coloring-based
+ * overlapping domain-decomposition (CBD) preconditioner with recursive-
+ * skeletonization (RS) subdomain solvers for SPD first-kind integral equations
+ * (Chen & Biros, "Overlapping domain decomposition preconditioner for integral
+ * equations", arXiv 2108.12574).
+ *
+ * Conventions shared by every call:
+ *  - Grid points of the n^d grid are numbered g = j1 + n*j2 (+ n^2*j3), 0-based,
+ *    x fastest.  N = n^d.
+ *  - Vectors with several right-hand sides are N x nrhs, column-major: column r
+ *    (right-hand side r) is contiguous, i.e. a row-major (nrhs, N) array.  All
+ *    vectors are FP64 device memory.
+ *  - "device" pointers are HIP device allocations owned by the caller; the
+ *    library keeps no reference to them after the call returns, except where a
+ *    handle documents that it views them (cbd_problem views its four arrays).
+ *  - Handles are host objects owned by the library and released with the
+ *    matching *_free call.  A factor owns the device memory holding the factors.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue work
+ *    on it and return; calls that return host results (ranks, iteration counts,
+ *    statistics) synchronize the stream first.
+ *  - Return value: 0 = success, < 0 = error (nothing usable was produced; the
+ *    message is in cbd_last_error()), > 0 = warning (result produced).
+ */
+#ifndef CBD_H
+#define CBD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CBD_OK 0
+#define CBD_EARG (-1)        /* invalid argument (sizes, modes, NULL pointers) */
+#define CBD_EHIP (-2)        /* a HIP runtime call failed */
+#define CBD_ENOTSPD (-3)     /* a Cholesky factorization met a non-positive pivot */
+#define CBD_ENOMEM (-4)      /* device or host allocation failed */
+#define CBD_WNOTCONV 1       /* PCG stopped at maxit before reaching tol */
+
+#define CBD_GRID_CELL 0      /* x_t = (j_t + 1/2)/n (Section 2.1) */
+#define CBD_GRID_NODE 1      /* 2D only: x_t = j_t/(n-1), weight and diagonal at h = 1/n */
+
+#define CBD_MODE_JACOBI 0    /* Omega_i = P_i (non-overlapping), table t:dd */
+#define CBD_MODE_SCHWARZ 1   /* Omega_i = extended P_i, (e:first) */
+#define CBD_MODE_CBD 2       /* Omega_i = union of same-color extended P_k, (e:cbd) */
+
+#define CBD_PREC_FP64 0      /* factors built, stored and applied in FP64 */
+#define CBD_PREC_FP32 1      /* factors built, stored and applied in FP32; apply input/output FP64 */
+
+typedef struct cbd_problem_s* cbd_problem;
+typedef struct cbd_partition_s* cbd_partition;
+typedef struct cbd_factor_s* cbd_factor;
+
+/* Options of the RS factorization (Section 3.2). */
+typedef struct {
+    double tol;          /* relative accuracy eps of every ID, (e:id_err) */
+    int n_pxy;           /* proxy points on the circle (2D) / sphere (3D) around a box */
+    double proxy_ratio;  /* proxy radius / box side (1.5 in the paper's footnote to Section 5) */
+    int precision;       /* CBD_PREC_FP64 or CBD_PREC_FP32 */
+    int exact;           /* 1: no compression; every A_i is factored by dense Cholesky
+                            (the naive CBD of Section 5.1) */
+} cbd_rs_opts;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* cbd_last_error(void);
+
+/* ie_assemble - discretize the integral equation of Section 2.1, (e:ie)/(e:int)
+ * with a = 0, on the n^d grid: A_ij = b_i h^d K(x_i - x_j) c_j (i != j),
+ * A_ii = b_i c_i * (exact integral of K over the h-cell), K of (e:k).
+ *  d: 2 or 3; n >= 2; grid: CBD_GRID_*.
+ *  b, c: device, N values each, or NULL for 1.  SPD requires b = c > 0.
+ *  pts (device, d*N, SoA: pts[t*N + g]), diag (device, N), w (device, N: column
+ *  scale h^d c_j), rowscale (device, N: b_i): outputs, caller-owned; the
+ *  returned problem views them, so they must outlive it.
+ *  On success *out holds a new problem handle. */
+int ie_assemble(int d, int n, int grid, const double* b, const double* c,
+                double* pts, double* diag, double* w, double* rowscale,
+                void* stream, cbd_problem* out);
+int cbd_problem_free(cbd_problem p);
+
+/* dd_partition - build the domain decomposition of Sections 2.2-2.3 and the
+ * box hierarchy RS uses inside every subdomain (Section 3.2) for the n^d grid.
+ * Host only: needs no GPU.
+ *  d: 2 or 3; n: points per axis;
+ *  m: partitions per axis (n % m == 0); delta: extension layers per side
+ *  (ignored for JACOBI; CBD with m > 2 needs 2*delta <= n/m); mode: CBD_MODE_*;
+ *  leaf_side: 0 = every extended partition is one leaf box, else leaf boxes are
+ *  leaf_side-wide tiles of it.  The coloring is c(k) = sum_t (k_t mod 2) 2^(t-1).
+ *  On success *out holds a new partition handle. */
+int dd_partition(int d, int n, int m, int delta, int mode, int leaf_side, cbd_partition* out);
+int cbd_partition_free(cbd_partition q);
+
+/* Introspection of a partition (host arrays, caller-allocated).
+ *  dd_partition_info: number of subdomains D, tile levels Lt, region levels Lr,
+ *    total local DOFs sum_i |I_i|.
+ *  dd_subdomain_info: |I_i|, number of leaf boxes, root level.
+ *  dd_subdomain_index: I_i (|I_i| ints) in local order.
+ *  dd_level_boxes: boxes of subdomain i at `level`: count; if lohi != NULL the
+ *    cell bounding boxes (2*d ints per box: lo[0..d), hi[0..d)); if parent != NULL
+ *    the index of each box's parent at level+1 (-1 at the root level). */
+int dd_partition_info(cbd_partition q, int* D, int* Lt, int* Lr, long* total);
+int dd_subdomain_info(cbd_partition q, int i, int* size, int* n_leaves, int* root_level);
+int dd_subdomain_index(cbd_partition q, int i, int* index);
+int dd_level_boxes(cbd_partition q, int i, int level, int* n_boxes, int* lohi, int* parent);
+
+/* rs_factor_batched - RS factorization of every subdomain matrix A_i = R_i A R_i^T
+ * (e:ai) of the partition, level by level: at each level every box of every
+ * subdomain is compressed with an ID of its proxy/near-field matrix ((e:id), the
+ * proxy trick) and eliminated ((e:al), (e:alu), (e:b)); the last Schur complement
+ * (e:schur) of each subdomain is factored by Cholesky.  All boxes of one level,
+ * across all subdomains, are processed by the same kernel launches.
+ * The factor keeps (per box) skeleton/redundant index lists, T, E = B_sr G^{-1},
+ * G^{-1} (B_rr = G^T G) and B_ss, in opts->precision.  It allocates its own
+ * device memory (released by rs_factor_free) and synchronizes `stream` once per
+ * level to read the ranks.  The partition must be of the problem's grid (same d
+ * and n, cell-centred points).  Errors: CBD_ENOTSPD names the level and box. */
+int rs_factor_batched(cbd_problem p, cbd_partition q, const cbd_rs_opts* opts,
+                      void* stream, cbd_factor* out);
+int rs_factor_free(cbd_factor f);
+
+/* Statistics of a factor: per subdomain DOFs at the last level (S_i, array of D
+ * ints, may be NULL), the number of compressed levels, the bytes of factor
+ * storage, and the algorithmic flops of the factorization (ID by truncated CPQR,
+ * elimination and root Cholesky; formulas in the design notes). */
+int rs_factor_stats(cbd_factor f, int* S, int* n_levels, size_t* bytes, double* flops);
+
+/* Per-level ranks: number of boxes at `level` (all subdomains, in batch order)
+ * and, if ranks != NULL, k per box; if np != NULL, active DOFs per box; if sub
+ * != NULL, the subdomain of each box. */
+int rs_factor_level(cbd_factor f, int level, int* n_boxes, int* ranks, int* np, int* sub);
+
+/* Copy one box's factor to the host as FP64 (tests).  box is the index within
+ * subdomain i at `level` (the partition's order).  sk (k ints), rd (n_r ints):
+ * local indices of skeleton / redundant DOFs; T, E: k x n_r column-major;
+ * Ginv: n_r x n_r column-major upper triangular; Bss: k x k.  Any output may be
+ * NULL.  *k and *nr are always written. */
+int rs_factor_box(cbd_factor f, int i, int level, int box, int* k, int* nr,
+                  int* sk, int* rd, double* T, double* E, double* Ginv, double* Bss);
+/* Root of subdomain i: S, local indices (S ints), G^{-1} of S = G^T G (S x S). */
+int rs_factor_root(cbd_factor f, int i, int* S, int* idx, double* Ginv);
+
+/* rs_apply - z = T^{-1} r = sum_i R_i^T A_i^{-1} R_i r, (e:ad), with every A_i^{-1}
+ * applied through its RS factor: gather, forward sweep over levels, root solve,
+ * backward sweep, and a deterministic scatter-add over overlapping subdomains.
+ *  r, z: device, N x nrhs column-major FP64 (may not alias). */
+int rs_apply(cbd_factor f, int nrhs, const double* r, double* z, void* stream);
+
+/* kernel_matvec - y = A x with A of ie_assemble, entries generated on the fly in
+ * FP64 (the dense product; the paper uses FFTs for it, Section 5).
+ *  x, y: device, N x nrhs column-major FP64 (may not alias). */
+int kernel_matvec(cbd_problem p, int nrhs, const double* x, double* y, void* stream);
+
+/* pcg_solve - preconditioned CG (Section 5) on A u = f for nrhs independent
+ * right-hand sides: u0 = 0, stop a column when ||r||_2/||f||_2 <= tol; beta =
+ * r+.z+/r.z, or r+.(z+ - z)/r.z when flexible != 0.  f (device, N x nrhs),
+ * u (device, N x nrhs, output).  f_ = NULL factor means no preconditioner.
+ *  ws: device workspace of at least pcg_workspace_bytes(N, nrhs) bytes.
+ *  iters, relres: host arrays of nrhs (matvec count, final recurrence residual).
+ *  Returns CBD_WNOTCONV if a column did not converge within maxit. */
+size_t pcg_workspace_bytes(long N, int nrhs);
+int pcg_solve(cbd_problem p, cbd_factor f_, int nrhs, const double* f, double* u,
+              double tol, int maxit, int flexible, void* ws, size_t ws_bytes,
+              int* iters, double* relres, void* stream);
+
+/* Kernel timing with HIP events recorded on the launching stream around every
+ * launch of the named kernel family ("matvec", "apply", "factor"): enable,
+ * read (total milliseconds and launch count since the last reset), reset. */
+int cbd_timing_enable(int on);
+int cbd_timing_get(const char* name, double* total_ms, long* launches);
+int cbd_timing_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

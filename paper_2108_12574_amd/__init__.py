@@ -1,0 +1,232 @@
+"""MI355X (gfx950) coloring-based overlapping domain-decomposition preconditioner
+with recursive-skeletonization subdomain solvers (Chen & Biros, arXiv 2108.12574).
+
+Thin Python binding of libcbd.so (C ABI in include/cbd.h).  Every step of the
+method runs in the library's HIP kernels; this module only marshals arguments.
+PyTorch provides device memory (FP64 CUDA tensors of shape (nrhs, N), i.e.
+N x nrhs column-major) and the current stream.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (GRID_CELL, GRID_NODE, MODE_CBD, MODE_JACOBI, MODE_SCHWARZ, PREC_FP32,
+                   PREC_FP64, CbdError, check, lib)
+
+__all__ = ["Problem", "Partition", "Factor", "pcg_solve", "timing", "CbdError",
+           "GRID_CELL", "GRID_NODE", "MODE_JACOBI", "MODE_SCHWARZ", "MODE_CBD",
+           "PREC_FP64", "PREC_FP32"]
+
+
+def _free(fn, obj):
+    """Release a library handle (quietly at interpreter shutdown)."""
+    h = getattr(obj, "handle", None)
+    L = getattr(_lib, "_lib", None) if _lib is not None else None
+    if h and L is not None:
+        try:
+            getattr(L, fn)(h)
+        except Exception:
+            pass
+    obj.handle = None
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _vec(x, N, device):
+    """Check/normalize a (N,) or (nrhs, N) FP64 device tensor."""
+    if x.dim() == 1:
+        x = x.unsqueeze(0)
+    if x.dtype != torch.float64 or x.device != device or x.shape[1] != N:
+        raise ValueError("expected float64 tensor of shape (nrhs, %d) on %s" % (N, device))
+    return x.contiguous()
+
+
+class Problem:
+    """Discretized IE (ie_assemble): A_ij = b_i h^d K(x_i - x_j) c_j, closed-form diagonal."""
+
+    def __init__(self, d, n, grid=GRID_CELL, b=None, c=None, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.d, self.n, self.grid = d, n, grid
+        self.N = n ** d
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.pts = torch.empty(d * self.N, **f64)
+        self.diag = torch.empty(self.N, **f64)
+        self.w = torch.empty(self.N, **f64)
+        self.rowscale = torch.empty(self.N, **f64)
+        self._b = None if b is None else torch.as_tensor(b, **f64).contiguous()
+        self._c = None if c is None else torch.as_tensor(c, **f64).contiguous()
+        h = ctypes.c_void_p()
+        check(lib().ie_assemble(d, n, grid, _ptr(self._b), _ptr(self._c), _ptr(self.pts),
+                                _ptr(self.diag), _ptr(self.w), _ptr(self.rowscale),
+                                _stream(self.device), ctypes.byref(h)))
+        self.handle = h
+
+    def matvec(self, x):
+        """y = A x for x of shape (N,) or (nrhs, N) (kernel_matvec)."""
+        one = x.dim() == 1
+        x = _vec(x, self.N, self.device)
+        y = torch.empty_like(x)
+        check(lib().kernel_matvec(self.handle, x.shape[0], _ptr(x), _ptr(y), _stream(self.device)))
+        return y[0] if one else y
+
+    def __del__(self):
+        _free("cbd_problem_free", self)
+
+
+class Partition:
+    """Domain decomposition and RS box hierarchy (dd_partition); host only.
+
+    `grid` is a Problem, or a (d, n) pair (no GPU needed then).
+    """
+
+    def __init__(self, grid, m, delta=1, mode=MODE_CBD, leaf_side=0):
+        d, n = (grid.d, grid.n) if isinstance(grid, Problem) else grid
+        self.d, self.n = d, n
+        h = ctypes.c_void_p()
+        check(lib().dd_partition(d, n, m, delta, mode, leaf_side, ctypes.byref(h)))
+        self.handle = h
+        D, Lt, Lr, tot = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_long()
+        check(lib().dd_partition_info(h, ctypes.byref(D), ctypes.byref(Lt), ctypes.byref(Lr),
+                                      ctypes.byref(tot)))
+        self.D, self.Lt, self.Lr, self.total = D.value, Lt.value, Lr.value, tot.value
+
+    def subdomain(self, i):
+        """(index list, number of leaves, root level) of subdomain i."""
+        size, nl, rl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().dd_subdomain_info(self.handle, i, ctypes.byref(size), ctypes.byref(nl),
+                                      ctypes.byref(rl)))
+        idx = (ctypes.c_int * size.value)()
+        check(lib().dd_subdomain_index(self.handle, i, idx))
+        return list(idx), nl.value, rl.value
+
+    def level_boxes(self, i, level):
+        """(lo/hi bounds, parent index) of the boxes of subdomain i at a level."""
+        nb = ctypes.c_int()
+        check(lib().dd_level_boxes(self.handle, i, level, ctypes.byref(nb), None, None))
+        d = self.d
+        lohi = (ctypes.c_int * (2 * d * nb.value))()
+        par = (ctypes.c_int * nb.value)()
+        check(lib().dd_level_boxes(self.handle, i, level, ctypes.byref(nb), lohi, par))
+        boxes = [(list(lohi[b * 2 * d:b * 2 * d + d]), list(lohi[b * 2 * d + d:(b + 1) * 2 * d]))
+                 for b in range(nb.value)]
+        return boxes, list(par)
+
+    def __del__(self):
+        _free("cbd_partition_free", self)
+
+
+class Factor:
+    """RS factors of all subdomain matrices (rs_factor_batched) and T^{-1} (rs_apply)."""
+
+    def __init__(self, problem, partition, tol=1e-6, n_pxy=64, proxy_ratio=1.5,
+                 precision=PREC_FP64, exact=False):
+        self.problem, self.partition = problem, partition
+        self.precision = precision
+        opts = _lib.RSOpts(tol, n_pxy, proxy_ratio, precision, 1 if exact else 0)
+        h = ctypes.c_void_p()
+        check(lib().rs_factor_batched(problem.handle, partition.handle, ctypes.byref(opts),
+                                      _stream(problem.device), ctypes.byref(h)))
+        self.handle = h
+
+    def apply(self, r):
+        """z = T^{-1} r for r of shape (N,) or (nrhs, N)."""
+        one = r.dim() == 1
+        r = _vec(r, self.problem.N, self.problem.device)
+        z = torch.empty_like(r)
+        check(lib().rs_apply(self.handle, r.shape[0], _ptr(r), _ptr(z), _stream(self.problem.device)))
+        return z[0] if one else z
+
+    def stats(self):
+        D = self.partition.D
+        S = (ctypes.c_int * D)()
+        nl, nb, fl = ctypes.c_int(), ctypes.c_size_t(), ctypes.c_double()
+        check(lib().rs_factor_stats(self.handle, S, ctypes.byref(nl), ctypes.byref(nb), ctypes.byref(fl)))
+        return {"S": list(S), "levels": nl.value, "bytes": nb.value, "flops": fl.value}
+
+    def level(self, level):
+        """(ranks, np, subdomain) per box of a batch level (level == levels: the roots)."""
+        nb = ctypes.c_int()
+        check(lib().rs_factor_level(self.handle, level, ctypes.byref(nb), None, None, None))
+        k, npp, sub = ((ctypes.c_int * nb.value)() for _ in range(3))
+        check(lib().rs_factor_level(self.handle, level, ctypes.byref(nb), k, npp, sub))
+        return list(k), list(npp), list(sub)
+
+    def box(self, i, level, b):
+        """Host FP64 copy of one box factor: dict(sk, rd, T, E, Ginv, Bss)."""
+        import numpy as np
+        k, nr = ctypes.c_int(), ctypes.c_int()
+        check(lib().rs_factor_box(self.handle, i, level, b, ctypes.byref(k), ctypes.byref(nr),
+                                  None, None, None, None, None, None))
+        k, nr = k.value, nr.value
+        sk, rd = np.zeros(k, np.int32), np.zeros(nr, np.int32)
+        T, E = np.zeros(k * nr), np.zeros(k * nr)
+        Gi, Bss = np.zeros(nr * nr), np.zeros(k * k)
+        ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        kk, nn = ctypes.c_int(), ctypes.c_int()
+        check(lib().rs_factor_box(self.handle, i, level, b, ctypes.byref(kk), ctypes.byref(nn),
+                                  ip(sk), ip(rd), dp(T), dp(E), dp(Gi), dp(Bss)))
+        f = lambda a, r, c: a.reshape(c, r).T   # column-major r x c
+        return {"sk": sk, "rd": rd, "T": f(T, k, nr), "E": f(E, k, nr), "Ginv": f(Gi, nr, nr),
+                "Bss": f(Bss, k, k)}
+
+    def root(self, i):
+        import numpy as np
+        S = ctypes.c_int()
+        check(lib().rs_factor_root(self.handle, i, ctypes.byref(S), None, None))
+        idx = np.zeros(S.value, np.int32)
+        Gi = np.zeros(S.value * S.value)
+        check(lib().rs_factor_root(self.handle, i, ctypes.byref(S),
+                                   idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                   Gi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return idx, Gi.reshape(S.value, S.value).T
+
+    def __del__(self):
+        _free("rs_factor_free", self)
+
+
+def pcg_solve(problem, factor, f, tol=1e-10, maxit=200, flexible=False):
+    """PCG on A u = f (pcg_solve).  f: (N,) or (nrhs, N).  Returns (u, iters, relres)."""
+    one = f.dim() == 1
+    f = _vec(f, problem.N, problem.device)
+    nrhs = f.shape[0]
+    u = torch.empty_like(f)
+    nb = lib().pcg_workspace_bytes(problem.N, nrhs)
+    ws = torch.empty(nb, dtype=torch.uint8, device=problem.device)
+    iters = (ctypes.c_int * nrhs)()
+    relres = (ctypes.c_double * nrhs)()
+    rc = lib().pcg_solve(problem.handle, factor.handle if factor is not None else None, nrhs,
+                         _ptr(f), _ptr(u), tol, maxit, 1 if flexible else 0, _ptr(ws), nb,
+                         iters, relres, _stream(problem.device))
+    check(rc, allow_warning=True)
+    its, rr = list(iters), list(relres)
+    if one:
+        return u[0], its[0], rr[0]
+    return u, its, rr
+
+
+class timing:
+    """HIP-event timers the library records around its launches (per family)."""
+
+    @staticmethod
+    def enable(on=True):
+        check(lib().cbd_timing_enable(1 if on else 0))
+
+    @staticmethod
+    def reset():
+        check(lib().cbd_timing_reset())
+
+    @staticmethod
+    def get(name):
+        ms, n = ctypes.c_double(), ctypes.c_long()
+        check(lib().cbd_timing_get(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

@@ -1,0 +1,1064 @@
+// Host runtime of libcbd: the C ABI of include/cbd.h, the domain decomposition
+// and box hierarchy (Sections 2.2-2.3, 3.2), the level-batched RS factorization
+// driver, the preconditioner apply and the PCG loop (Section 5).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cbd.h"
+#include "internal.h"
+
+using namespace cbd;
+
+// ---------------------------------------------------------------------------
+// errors, timing
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                           \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess) return fail(CBD_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char* cbd_last_error(void) { return g_err.c_str(); }
+
+namespace {
+
+std::mutex g_tmx;
+bool g_timing = false;
+struct PendingTimer {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::vector<PendingTimer> g_pending;
+std::map<std::string, std::pair<double, long>> g_acc;
+
+// Records HIP events on `stream` around a launch sequence when timing is on.
+struct ScopedTimer {
+    std::string name;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on = false;
+    ScopedTimer(const char* n, hipStream_t st) : name(n), s(st) {
+        std::lock_guard<std::mutex> lk(g_tmx);
+        if (!g_timing) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+        (void)hipEventRecord(a, s);
+        on = true;
+    }
+    ~ScopedTimer() {
+        if (!on) return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_tmx);
+        g_pending.push_back({name, a, b});
+    }
+};
+
+void resolve_timers() {
+    std::lock_guard<std::mutex> lk(g_tmx);
+    for (auto& p : g_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            auto& acc = g_acc[p.name];
+            acc.first += ms;
+            acc.second += 1;
+        }
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    g_pending.clear();
+}
+
+}  // namespace
+
+extern "C" int cbd_timing_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_tmx);
+    g_timing = on != 0;
+    return CBD_OK;
+}
+
+extern "C" int cbd_timing_get(const char* name, double* total_ms, long* launches) {
+    if (!name) return fail(CBD_EARG, "cbd_timing_get: name is NULL");
+    resolve_timers();
+    std::lock_guard<std::mutex> lk(g_tmx);
+    auto it = g_acc.find(name);
+    if (total_ms) *total_ms = it == g_acc.end() ? 0.0 : it->second.first;
+    if (launches) *launches = it == g_acc.end() ? 0 : it->second.second;
+    return CBD_OK;
+}
+
+extern "C" int cbd_timing_reset(void) {
+    resolve_timers();
+    std::lock_guard<std::mutex> lk(g_tmx);
+    g_acc.clear();
+    return CBD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// problem
+// ---------------------------------------------------------------------------
+struct cbd_problem_s {
+    int d, n, grid;
+    long N;
+    double h, weight, a_self;
+    double *pts, *diag, *w, *rs;
+    ProblemView view() const { return ProblemView{d, n, N, pts, diag, w, rs}; }
+};
+
+// Exact integral of K over the cell [-h/2, h/2]^d (diagonal of (e:a_2d)/(e:a_3d)).
+static double self_cell(int d, double h) {
+    const double pi = 3.14159265358979323846;
+    if (d == 2) return -(h * h / (2.0 * pi)) * (std::log(h) - 0.5 * std::log(2.0) - 1.5 + pi / 4.0);
+    return (3.0 * h * h / (4.0 * pi)) * (std::log(2.0 + std::sqrt(3.0)) - pi / 6.0);
+}
+
+extern "C" int ie_assemble(int d, int n, int grid, const double* b, const double* c, double* pts,
+                           double* diag, double* w, double* rowscale, void* stream,
+                           cbd_problem* out) {
+    if (!out) return fail(CBD_EARG, "ie_assemble: out is NULL");
+    if (d != 2 && d != 3) return fail(CBD_EARG, "ie_assemble: d must be 2 or 3");
+    if (n < 2) return fail(CBD_EARG, "ie_assemble: n must be >= 2");
+    if (grid != CBD_GRID_CELL && grid != CBD_GRID_NODE) return fail(CBD_EARG, "ie_assemble: bad grid");
+    if (grid == CBD_GRID_NODE && d != 2) return fail(CBD_EARG, "ie_assemble: node grid is 2D only");
+    if (!pts || !diag || !w || !rowscale) return fail(CBD_EARG, "ie_assemble: output pointer is NULL");
+    long N = 1;
+    for (int t = 0; t < d; ++t) N *= n;
+    if (N > (1L << 30)) return fail(CBD_EARG, "ie_assemble: N too large");
+    auto* p = new cbd_problem_s;
+    p->d = d;
+    p->n = n;
+    p->grid = grid;
+    p->N = N;
+    p->h = 1.0 / n;
+    p->weight = std::pow(p->h, d);
+    p->a_self = self_cell(d, p->h);
+    p->pts = pts;
+    p->diag = diag;
+    p->w = w;
+    p->rs = rowscale;
+    hipStream_t s = (hipStream_t)stream;
+    launch_assemble(d, n, grid, b, c, pts, diag, w, rowscale, p->a_self, p->weight, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete p;
+        return fail(CBD_EHIP, std::string("ie_assemble launch: ") + hipGetErrorString(e));
+    }
+    *out = p;
+    return CBD_OK;
+}
+
+extern "C" int cbd_problem_free(cbd_problem p) {
+    delete p;
+    return CBD_OK;
+}
+
+extern "C" int kernel_matvec(cbd_problem p, int nrhs, const double* x, double* y, void* stream) {
+    if (!p || !x || !y || nrhs < 1) return fail(CBD_EARG, "kernel_matvec: bad argument");
+    if (x == y) return fail(CBD_EARG, "kernel_matvec: x and y alias");
+    hipStream_t s = (hipStream_t)stream;
+    {
+        ScopedTimer tm("matvec", s);
+        launch_matvec(p->view(), nrhs, x, y, s);
+    }
+    HIPCHK(hipGetLastError());
+    return CBD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// partition and box hierarchy
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Leaf {
+    int lo[3], hi[3];
+    int start, count;
+};
+struct PBox {
+    int lo[3], hi[3];
+    std::vector<int> children;
+    int parent = -1;
+    int first_leaf = 0;
+};
+struct Sub {
+    std::vector<int> index;                 // global indices in local order
+    std::vector<Leaf> leaves;
+    std::vector<std::vector<PBox>> levels;  // levels[l] boxes
+    int root_level = 0;
+    long offset = 0;                        // first slot of this subdomain
+};
+
+int ceil_log2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+}  // namespace
+
+struct cbd_partition_s {
+    int d, n, m, delta, mode, leaf_side, Lt, Lr;
+    std::vector<Sub> subs;
+    long total = 0;
+    // device copies, uploaded on first use
+    int* d_cidx = nullptr;      // slot -> global index
+    int* d_inv_ptr = nullptr;   // N+1
+    int* d_inv_slot = nullptr;  // total
+    std::vector<int> cidx;
+    int upload() {
+        if (d_cidx) return CBD_OK;
+        long N = 1;
+        for (int t = 0; t < d; ++t) N *= n;
+        std::vector<int> cnt(N + 1, 0);
+        for (long e = 0; e < total; ++e) cnt[cidx[e] + 1]++;
+        for (long g = 0; g < N; ++g) cnt[g + 1] += cnt[g];
+        std::vector<int> slot(total), fill(cnt.begin(), cnt.end() - 1);
+        for (long e = 0; e < total; ++e) slot[fill[cidx[e]]++] = (int)e;
+        HIPCHK(hipMalloc(&d_cidx, sizeof(int) * total));
+        HIPCHK(hipMalloc(&d_inv_ptr, sizeof(int) * (N + 1)));
+        HIPCHK(hipMalloc(&d_inv_slot, sizeof(int) * total));
+        HIPCHK(hipMemcpy(d_cidx, cidx.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_inv_ptr, cnt.data(), sizeof(int) * (N + 1), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_inv_slot, slot.data(), sizeof(int) * total, hipMemcpyHostToDevice));
+        return CBD_OK;
+    }
+    ~cbd_partition_s() {
+        if (d_cidx) (void)hipFree(d_cidx);
+        if (d_inv_ptr) (void)hipFree(d_inv_ptr);
+        if (d_inv_slot) (void)hipFree(d_inv_slot);
+    }
+};
+
+extern "C" int dd_partition(int d, int n, int m, int delta, int mode, int leaf_side,
+                            cbd_partition* out) {
+    if (!out) return fail(CBD_EARG, "dd_partition: NULL argument");
+    if (d != 2 && d != 3) return fail(CBD_EARG, "dd_partition: d must be 2 or 3");
+    if (n < 2) return fail(CBD_EARG, "dd_partition: n must be >= 2");
+    if (m < 1 || n % m != 0) return fail(CBD_EARG, "dd_partition: n must be a multiple of m");
+    if (delta < 0 || leaf_side < 0) return fail(CBD_EARG, "dd_partition: negative delta or leaf_side");
+    if (mode != CBD_MODE_JACOBI && mode != CBD_MODE_SCHWARZ && mode != CBD_MODE_CBD)
+        return fail(CBD_EARG, "dd_partition: unknown mode");
+    if (mode == CBD_MODE_JACOBI) delta = 0;
+    const int s = n / m;
+    if (mode == CBD_MODE_CBD && m > 2 && 2 * delta > s)
+        return fail(CBD_EARG, "dd_partition: CBD needs 2*delta <= n/m");
+
+    struct Region {
+        int kp[3], lo[3], hi[3];
+    };
+    int M = 1;
+    for (int t = 0; t < d; ++t) M *= m;
+    const int D = (mode == CBD_MODE_CBD) ? (1 << d) : M;
+    std::vector<std::vector<Region>> regs(D);
+    for (int kl = 0; kl < M; ++kl) {
+        int k[3] = {0, 0, 0}, r = kl;
+        for (int t = 0; t < d; ++t) {
+            k[t] = r % m;
+            r /= m;
+        }
+        Region g{};
+        for (int t = 0; t < d; ++t) {
+            g.lo[t] = std::max(0, k[t] * s - delta);
+            g.hi[t] = std::min(n, (k[t] + 1) * s + delta);
+            g.kp[t] = (mode == CBD_MODE_CBD) ? k[t] / 2 : 0;
+        }
+        int target = kl;
+        if (mode == CBD_MODE_CBD) {
+            target = 0;
+            for (int t = 0; t < d; ++t) target += (k[t] % 2) << t;
+        }
+        regs[target].push_back(g);
+    }
+    auto tiles = [&](const int* lo, const int* hi, int* T) {
+        for (int t = 0; t < d; ++t)
+            T[t] = leaf_side <= 0 ? 1 : (hi[t] - lo[t] + leaf_side - 1) / leaf_side;
+    };
+    int qmax = 1, rmax = 1;
+    for (auto& rl : regs)
+        for (auto& g : rl) {
+            int T[3];
+            tiles(g.lo, g.hi, T);
+            for (int t = 0; t < d; ++t) {
+                qmax = std::max(qmax, T[t]);
+                rmax = std::max(rmax, g.kp[t] + 1);
+            }
+        }
+    auto* q = new cbd_partition_s;
+    q->d = d;
+    q->n = n;
+    q->m = m;
+    q->delta = delta;
+    q->mode = mode;
+    q->leaf_side = leaf_side;
+    q->Lt = ceil_log2(qmax);
+    q->Lr = ceil_log2(rmax);
+    q->subs.resize(D);
+    long offset = 0;
+    for (int i = 0; i < D; ++i) {
+        Sub& sd = q->subs[i];
+        sd.offset = offset;
+        std::vector<std::array<int, 6>> leaf_key;   // kp[3], q[3]
+        for (auto& g : regs[i]) {
+            int T[3] = {1, 1, 1};
+            tiles(g.lo, g.hi, T);
+            int nt = 1;
+            for (int t = 0; t < d; ++t) nt *= T[t];
+            for (int ql = 0; ql < nt; ++ql) {
+                int qq[3] = {0, 0, 0}, r = ql;
+                for (int t = 0; t < d; ++t) {
+                    qq[t] = r % T[t];
+                    r /= T[t];
+                }
+                Leaf lf{};
+                for (int t = 0; t < d; ++t) {
+                    if (leaf_side <= 0) {
+                        lf.lo[t] = g.lo[t];
+                        lf.hi[t] = g.hi[t];
+                    } else {
+                        lf.lo[t] = g.lo[t] + qq[t] * leaf_side;
+                        lf.hi[t] = std::min(g.hi[t], g.lo[t] + (qq[t] + 1) * leaf_side);
+                    }
+                }
+                lf.start = (int)sd.index.size();
+                // points of the tile, x fastest
+                int ext[3] = {1, 1, 1};
+                for (int t = 0; t < d; ++t) ext[t] = lf.hi[t] - lf.lo[t];
+                for (int c2 = 0; c2 < (d == 3 ? ext[2] : 1); ++c2)
+                    for (int c1 = 0; c1 < ext[1]; ++c1)
+                        for (int c0 = 0; c0 < ext[0]; ++c0) {
+                            long g0 = lf.lo[0] + c0, g1 = lf.lo[1] + c1, g2 = d == 3 ? lf.lo[2] + c2 : 0;
+                            sd.index.push_back((int)(g0 + (long)n * g1 + (long)n * n * g2));
+                        }
+                lf.count = (int)sd.index.size() - lf.start;
+                sd.leaves.push_back(lf);
+                std::array<int, 6> key{};
+                for (int t = 0; t < d; ++t) {
+                    key[t] = g.kp[t];
+                    key[3 + t] = qq[t];
+                }
+                leaf_key.push_back(key);
+            }
+        }
+        offset += (long)sd.index.size();
+        // levels: a leaf's key at level l decides its box; boxes in order of first appearance
+        std::vector<int> leaf_box_prev;
+        for (int l = 0;; ++l) {
+            std::map<std::array<int, 6>, int> where;
+            std::vector<PBox> boxes;
+            std::vector<int> leaf_box(sd.leaves.size());
+            const int sr_ = std::max(0, l - q->Lt), sq_ = std::min(l, q->Lt);
+            for (size_t li = 0; li < sd.leaves.size(); ++li) {
+                std::array<int, 6> key{};
+                for (int t = 0; t < d; ++t) {
+                    key[t] = leaf_key[li][t] >> sr_;
+                    key[3 + t] = leaf_key[li][3 + t] >> sq_;
+                }
+                auto it = where.find(key);
+                int bi;
+                if (it == where.end()) {
+                    bi = (int)boxes.size();
+                    where[key] = bi;
+                    PBox b;
+                    for (int t = 0; t < 3; ++t) {
+                        b.lo[t] = sd.leaves[li].lo[t];
+                        b.hi[t] = sd.leaves[li].hi[t];
+                    }
+                    b.first_leaf = (int)li;
+                    boxes.push_back(b);
+                } else {
+                    bi = it->second;
+                }
+                PBox& b = boxes[bi];
+                for (int t = 0; t < d; ++t) {
+                    b.lo[t] = std::min(b.lo[t], sd.leaves[li].lo[t]);
+                    b.hi[t] = std::max(b.hi[t], sd.leaves[li].hi[t]);
+                }
+                leaf_box[li] = bi;
+            }
+            if (l > 0) {
+                auto& prev = sd.levels[l - 1];
+                for (size_t c = 0; c < prev.size(); ++c) {
+                    int pb = leaf_box[prev[c].first_leaf];
+                    boxes[pb].children.push_back((int)c);
+                    prev[c].parent = pb;
+                }
+            }
+            sd.levels.push_back(std::move(boxes));
+            leaf_box_prev = leaf_box;
+            if (sd.levels.back().size() == 1) {
+                sd.root_level = l;
+                break;
+            }
+        }
+    }
+    q->total = offset;
+    q->cidx.resize(offset);
+    for (auto& sd : q->subs)
+        for (size_t e = 0; e < sd.index.size(); ++e) q->cidx[sd.offset + e] = sd.index[e];
+    *out = q;
+    return CBD_OK;
+}
+
+extern "C" int cbd_partition_free(cbd_partition q) {
+    delete q;
+    return CBD_OK;
+}
+
+extern "C" int dd_partition_info(cbd_partition q, int* D, int* Lt, int* Lr, long* total) {
+    if (!q) return fail(CBD_EARG, "dd_partition_info: NULL partition");
+    if (D) *D = (int)q->subs.size();
+    if (Lt) *Lt = q->Lt;
+    if (Lr) *Lr = q->Lr;
+    if (total) *total = q->total;
+    return CBD_OK;
+}
+
+extern "C" int dd_subdomain_info(cbd_partition q, int i, int* size, int* n_leaves, int* root_level) {
+    if (!q || i < 0 || i >= (int)q->subs.size()) return fail(CBD_EARG, "dd_subdomain_info: bad index");
+    const Sub& sd = q->subs[i];
+    if (size) *size = (int)sd.index.size();
+    if (n_leaves) *n_leaves = (int)sd.leaves.size();
+    if (root_level) *root_level = sd.root_level;
+    return CBD_OK;
+}
+
+extern "C" int dd_subdomain_index(cbd_partition q, int i, int* index) {
+    if (!q || !index || i < 0 || i >= (int)q->subs.size()) return fail(CBD_EARG, "dd_subdomain_index: bad argument");
+    std::memcpy(index, q->subs[i].index.data(), sizeof(int) * q->subs[i].index.size());
+    return CBD_OK;
+}
+
+extern "C" int dd_level_boxes(cbd_partition q, int i, int level, int* n_boxes, int* lohi, int* parent) {
+    if (!q || i < 0 || i >= (int)q->subs.size()) return fail(CBD_EARG, "dd_level_boxes: bad subdomain");
+    const Sub& sd = q->subs[i];
+    if (level < 0 || level > sd.root_level) return fail(CBD_EARG, "dd_level_boxes: bad level");
+    const auto& bx = sd.levels[level];
+    if (n_boxes) *n_boxes = (int)bx.size();
+    for (size_t b = 0; b < bx.size(); ++b) {
+        if (lohi)
+            for (int t = 0; t < q->d; ++t) {
+                lohi[b * 2 * q->d + t] = bx[b].lo[t];
+                lohi[b * 2 * q->d + q->d + t] = bx[b].hi[t];
+            }
+        if (parent) parent[b] = bx[b].parent;
+    }
+    return CBD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// factor
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+T* dalloc(size_t n, int& rc) {
+    T* p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, sizeof(T) * n) != hipSuccess) {
+        rc = fail(CBD_ENOMEM, "hipMalloc failed");
+        return nullptr;
+    }
+    return p;
+}
+
+struct Level {
+    bool root = false;
+    int nbox = 0;
+    std::vector<BoxMeta> meta;
+    std::vector<int> k, sr;             // host copies after the level ran
+    std::vector<int> box_sub, box_idx;  // subdomain and partition box index of each batch box
+    std::vector<int> sub_start;         // first batch index of each subdomain (-1: absent)
+    int np_max = 0, m_max = 0;
+    long tot_act = 0, tot_f = 0;
+    BoxMeta* d_meta = nullptr;
+    int *d_act = nullptr, *d_sr = nullptr, *d_perm = nullptr, *d_k = nullptr;
+    void* d_F = nullptr;
+    void release() {
+        if (d_meta) (void)hipFree(d_meta);
+        if (d_act) (void)hipFree(d_act);
+        if (d_sr) (void)hipFree(d_sr);
+        if (d_perm) (void)hipFree(d_perm);
+        if (d_k) (void)hipFree(d_k);
+        if (d_F) (void)hipFree(d_F);
+        d_meta = nullptr;
+        d_act = d_sr = d_perm = d_k = nullptr;
+        d_F = nullptr;
+    }
+};
+
+// grow-only device buffer
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t b) {
+        if (b <= bytes) return CBD_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (hipMalloc(&p, b) != hipSuccess) return fail(CBD_ENOMEM, "hipMalloc of workspace failed");
+        bytes = b;
+        return CBD_OK;
+    }
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+struct cbd_factor_s {
+    cbd_problem_s* prob;
+    cbd_partition_s* part;
+    int prec;
+    size_t esize;
+    std::vector<Level> levels;   // compressed levels, then the root level
+    int n_compress = 0;
+    std::vector<int> S;
+    size_t bytes = 0;
+    double flops = 0.0;
+    DevBuf v;                    // local vectors of the apply
+    ~cbd_factor_s() {
+        for (auto& l : levels) l.release();
+    }
+};
+
+namespace {
+
+double cpqr_flops(double m, double n, double k) {
+    return 4.0 * m * n * k - 2.0 * (m + n) * k * k + 4.0 * k * k * k / 3.0;
+}
+double elim_flops(double k, double nr) {
+    // T solve, B_sr, B_rr (symmetric), Cholesky, G^{-1}, E, B_ss (symmetric)
+    return k * k * nr + 2.0 * k * k * nr + 2.0 * nr * nr * k + nr * nr * nr / 3.0 + nr * nr * nr / 3.0 +
+           k * nr * nr + k * k * nr;
+}
+
+// Proxy surface directions: equispaced circle (2D), golden-angle sphere (3D).
+std::vector<double> proxy_dirs(int d, int npxy) {
+    std::vector<double> dir((size_t)npxy * d);
+    const double pi = 3.14159265358979323846;
+    for (int j = 0; j < npxy; ++j) {
+        if (d == 2) {
+            double th = 2.0 * pi * j / npxy;
+            dir[j * 2] = std::cos(th);
+            dir[j * 2 + 1] = std::sin(th);
+        } else {
+            double z = 1.0 - (2.0 * j + 1.0) / npxy;
+            double rr = std::sqrt(1.0 - z * z);
+            double phi = j * (pi * (3.0 - std::sqrt(5.0)));
+            dir[j * 3] = rr * std::cos(phi);
+            dir[j * 3 + 1] = rr * std::sin(phi);
+            dir[j * 3 + 2] = z;
+        }
+    }
+    return dir;
+}
+
+template <typename R>
+int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipStream_t s,
+                cbd_factor_s* F) {
+    int rc = Q->upload();
+    if (rc) return rc;
+    const int d = P->d, n = P->n;
+    const ProblemView PV = P->view();
+    const int D = (int)Q->subs.size();
+    const int npxy = o->exact ? 0 : o->n_pxy;
+    // The ID (proxy matrix, pivoted QR, T) always runs in FP64: at tol ~ 1e-6 the
+    // FP32 round-off floor of the recomputed column norms reaches the tolerance
+    // and the ranks inflate.  Elimination, storage and apply use R.
+    const double tie = 1e-10;
+    std::vector<double> hdir = proxy_dirs(d, std::max(npxy, 1));
+    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf;
+    if ((rc = dirbuf.ensure(sizeof(double) * hdir.size()))) return rc;
+    HIPCHK(hipMemcpyAsync(dirbuf.p, hdir.data(), sizeof(double) * hdir.size(), hipMemcpyHostToDevice, s));
+    if ((rc = statbuf.ensure(sizeof(int)))) return rc;
+    HIPCHK(hipMemsetAsync(statbuf.p, 0, sizeof(int), s));
+    int* d_status = (int*)statbuf.p;
+
+    int Lmax = 0;
+    if (!o->exact)
+        for (auto& sd : Q->subs) Lmax = std::max(Lmax, sd.root_level);
+    F->n_compress = Lmax;
+    // grid coordinates of a global index
+    auto coord = [&](int g, int t) {
+        for (int u = 0; u < t; ++u) g /= n;
+        return g % n;
+    };
+
+    for (int l = 0; l <= Lmax; ++l) {
+        const bool root = (l == Lmax);
+        F->levels.emplace_back();
+        Level& L = F->levels.back();
+        L.root = root;
+        L.sub_start.assign(D, -1);
+        std::vector<std::vector<int>> act;      // slot lists per batch box
+        std::vector<std::vector<ChildRef<R>>> chl;
+        std::vector<int> blo, bhi;              // box bounds (3 per box)
+        for (int i = 0; i < D; ++i) {
+            const Sub& sd = Q->subs[i];
+            if (!root && (o->exact || sd.root_level <= l)) continue;
+            L.sub_start[i] = L.nbox;
+            // which partition level the boxes of this batch come from
+            const int pl = root ? (o->exact ? -1 : sd.root_level) : l;
+            const int nb = root ? 1 : (int)sd.levels[l].size();
+            for (int b = 0; b < nb; ++b) {
+                std::vector<int> a;
+                std::vector<ChildRef<R>> ch;
+                int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+                if (pl < 0) {   // exact: the whole subdomain
+                    for (size_t e = 0; e < sd.index.size(); ++e) a.push_back((int)(sd.offset + e));
+                } else {
+                    const PBox& pb = sd.levels[pl][b];
+                    for (int t = 0; t < 3; ++t) {
+                        lo[t] = pb.lo[t];
+                        hi[t] = pb.hi[t];
+                    }
+                    if (pl == 0) {
+                        const Leaf& lf = sd.leaves[b];
+                        for (int e = 0; e < lf.count; ++e) a.push_back((int)(sd.offset + lf.start + e));
+                    } else {
+                        const Level& PLv = F->levels[pl - 1];
+                        for (int c : pb.children) {
+                            const int cb = PLv.sub_start[i] + c;
+                            const BoxMeta& cm = PLv.meta[cb];
+                            const int kc = PLv.k[cb], nrc = cm.np - kc;
+                            const R* bss = (const R*)PLv.d_F + cm.f + 2L * kc * nrc + (long)nrc * nrc;
+                            for (int e = 0; e < kc; ++e) {
+                                a.push_back(PLv.sr[cm.act + e]);
+                                ch.push_back(ChildRef<R>{bss, kc, e});
+                            }
+                        }
+                    }
+                }
+                act.push_back(std::move(a));
+                chl.push_back(std::move(ch));
+                for (int t = 0; t < 3; ++t) {
+                    blo.push_back(lo[t]);
+                    bhi.push_back(hi[t]);
+                }
+                L.box_sub.push_back(i);
+                L.box_idx.push_back(b);
+                L.nbox++;
+            }
+        }
+        // near fields (compressed levels only), per subdomain
+        std::vector<std::vector<int>> nearl(L.nbox);
+        if (!root) {
+            for (int i = 0; i < D; ++i) {
+                if (L.sub_start[i] < 0) continue;
+                const int b0 = L.sub_start[i];
+                const int nb = (int)Q->subs[i].levels[l].size();
+                for (int b = 0; b < nb; ++b) {
+                    const int B = b0 + b;
+                    int Lside = 0;
+                    long c2[3];
+                    for (int t = 0; t < d; ++t) {
+                        Lside = std::max(Lside, bhi[B * 3 + t] - blo[B * 3 + t]);
+                        c2[t] = blo[B * 3 + t] + bhi[B * 3 + t];
+                    }
+                    const double R2 = (2.0 * o->proxy_ratio * Lside) * (2.0 * o->proxy_ratio * Lside);
+                    for (int b2 = 0; b2 < nb; ++b2) {
+                        if (b2 == b) continue;
+                        const int B2 = b0 + b2;
+                        double md = 0.0;
+                        for (int t = 0; t < d; ++t) {
+                            double lo2 = 2.0 * blo[B2 * 3 + t], hi2 = 2.0 * bhi[B2 * 3 + t];
+                            double dd = std::max(0.0, std::max(lo2 - c2[t], c2[t] - hi2));
+                            md += dd * dd;
+                        }
+                        if (md >= R2) continue;
+                        for (int slot : act[B2]) {
+                            const int g = Q->cidx[slot];
+                            double s2 = 0.0;
+                            for (int t = 0; t < d; ++t) {
+                                double off = 2.0 * coord(g, t) + 1.0 - (double)c2[t];
+                                s2 += off * off;
+                            }
+                            if (s2 < R2) nearl[B].push_back(slot);
+                        }
+                    }
+                }
+            }
+        }
+        // metadata and offsets
+        long o_act = 0, o_near = 0, o_y = 0, o_app = 0, o_f = 0, o_ch = 0;
+        L.meta.resize(L.nbox);
+        for (int B = 0; B < L.nbox; ++B) {
+            BoxMeta& M = L.meta[B];
+            std::memset(&M, 0, sizeof(M));
+            M.sub = L.box_sub[B];
+            M.np = (int)act[B].size();
+            M.nnear = (int)nearl[B].size();
+            M.m = root ? 0 : M.nnear + npxy;
+            M.act = o_act;
+            M.near = o_near;
+            M.y = o_y;
+            M.app = o_app;
+            M.f = o_f;
+            M.ch = chl[B].empty() ? -1 : o_ch;
+            int Lside = 0;
+            for (int t = 0; t < d; ++t) {
+                M.ctr[t] = 0.5 * (blo[B * 3 + t] + bhi[B * 3 + t]) * P->h;
+                Lside = std::max(Lside, bhi[B * 3 + t] - blo[B * 3 + t]);
+            }
+            M.rho = o->proxy_ratio * Lside * P->h;
+            const long np = M.np;
+            o_act += np;
+            o_near += M.nnear;
+            o_y += std::max((long)M.m, np) * np;
+            o_app += np * np;
+            o_f += np * np;
+            o_ch += (long)chl[B].size();
+            L.np_max = std::max(L.np_max, M.np);
+            L.m_max = std::max(L.m_max, M.m);
+        }
+        L.tot_act = o_act;
+        L.tot_f = o_f;
+        // device arrays of the level (kept for the apply)
+        L.d_meta = dalloc<BoxMeta>(L.nbox, rc);
+        L.d_act = dalloc<int>(o_act, rc);
+        L.d_sr = dalloc<int>(o_act, rc);
+        L.d_perm = dalloc<int>(o_act, rc);
+        L.d_k = dalloc<int>(L.nbox, rc);
+        L.d_F = dalloc<R>(o_f, rc);
+        if (rc) return rc;
+        F->bytes += sizeof(R) * (size_t)o_f;
+        if ((rc = ybuf.ensure(sizeof(double) * std::max(o_y, 1L)))) return rc;
+        if ((rc = wbuf.ensure(sizeof(R) * std::max(o_y, 1L)))) return rc;
+        if ((rc = t64buf.ensure(sizeof(double) * std::max(o_f, 1L)))) return rc;
+        if ((rc = appbuf.ensure(sizeof(R) * std::max(o_app, 1L)))) return rc;
+        if ((rc = nearbuf.ensure(sizeof(int) * std::max(o_near, 1L)))) return rc;
+        if ((rc = chbuf.ensure(sizeof(ChildRef<R>) * std::max(o_ch, 1L)))) return rc;
+        std::vector<int> hact, hnear;
+        std::vector<ChildRef<R>> hch;
+        hact.reserve(o_act);
+        hnear.reserve(o_near);
+        hch.reserve(o_ch);
+        for (int B = 0; B < L.nbox; ++B) {
+            hact.insert(hact.end(), act[B].begin(), act[B].end());
+            hnear.insert(hnear.end(), nearl[B].begin(), nearl[B].end());
+            hch.insert(hch.end(), chl[B].begin(), chl[B].end());
+        }
+        HIPCHK(hipMemcpyAsync(L.d_meta, L.meta.data(), sizeof(BoxMeta) * L.nbox, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(L.d_act, hact.data(), sizeof(int) * o_act, hipMemcpyHostToDevice, s));
+        if (o_near)
+            HIPCHK(hipMemcpyAsync(nearbuf.p, hnear.data(), sizeof(int) * o_near, hipMemcpyHostToDevice, s));
+        if (o_ch)
+            HIPCHK(hipMemcpyAsync(chbuf.p, hch.data(), sizeof(ChildRef<R>) * o_ch, hipMemcpyHostToDevice, s));
+        double* Y = (double*)ybuf.p;
+        double* T64 = (double*)t64buf.p;
+        R* Wk = (R*)wbuf.p;
+        R* App = (R*)appbuf.p;
+        R* FF = (R*)L.d_F;
+        if (!root) {
+            const size_t shm = (size_t)(L.np_max + L.m_max) * sizeof(double) + (size_t)L.np_max * sizeof(int);
+            if (shm > 65536)
+                return fail(CBD_EARG, "rs_factor_batched: box too large for the ID kernel's LDS at level " +
+                                          std::to_string(l) + " (np " + std::to_string(L.np_max) + ", rows " +
+                                          std::to_string(L.m_max) + ")");
+            launch_proxy_matrix<double>(PV, L.nbox, L.d_meta, L.d_act, (const int*)nearbuf.p, Q->d_cidx,
+                                        (const double*)dirbuf.p, npxy, Y, s);
+            launch_cpqr<double>(L.nbox, L.d_meta, Y, L.d_act, L.d_sr, L.d_perm, L.d_k, T64, o->tol, tie,
+                                L.m_max, L.np_max, s);
+        } else {
+            // root boxes: no compression, k = 0, identity order
+            std::vector<int> zeros(L.nbox, 0), ident(o_act);
+            for (int B = 0; B < L.nbox; ++B)
+                for (int e = 0; e < L.meta[B].np; ++e) ident[L.meta[B].act + e] = e;
+            HIPCHK(hipMemcpyAsync(L.d_k, zeros.data(), sizeof(int) * L.nbox, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(L.d_perm, ident.data(), sizeof(int) * o_act, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(L.d_sr, hact.data(), sizeof(int) * o_act, hipMemcpyHostToDevice, s));
+            // the host vectors must stay alive until the copies finish
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        launch_box_matrix<R>(PV, L.nbox, L.d_meta, L.d_act, Q->d_cidx,
+                             o_ch ? (const ChildRef<R>*)chbuf.p : nullptr, App, s);
+        launch_eliminate<R>(L.nbox, L.d_meta, L.d_perm, L.d_k, App, T64, Wk, FF, d_status, s);
+        HIPCHK(hipGetLastError());
+        L.k.resize(L.nbox);
+        L.sr.resize(o_act);
+        int status = 0;
+        HIPCHK(hipMemcpyAsync(L.k.data(), L.d_k, sizeof(int) * L.nbox, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(L.sr.data(), L.d_sr, sizeof(int) * o_act, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (status) {
+            const int B = status - 1;
+            return fail(CBD_ENOTSPD, "rs_factor_batched: Cholesky breakdown at level " + std::to_string(l) +
+                                         (root ? " (root)" : "") + ", subdomain " +
+                                         std::to_string(L.box_sub[B]) + ", box " + std::to_string(L.box_idx[B]));
+        }
+        for (int B = 0; B < L.nbox; ++B) {
+            const double np = L.meta[B].np, k = L.k[B], nr = np - k;
+            if (!root) F->flops += cpqr_flops(L.meta[B].m, np, k);
+            F->flops += elim_flops(k, nr);
+        }
+    }
+    F->S.assign(D, 0);
+    const Level& RL = F->levels.back();
+    for (int B = 0; B < RL.nbox; ++B) F->S[RL.box_sub[B]] = RL.meta[B].np;
+    return CBD_OK;
+}
+
+}  // namespace
+
+extern "C" int rs_factor_batched(cbd_problem p, cbd_partition q, const cbd_rs_opts* o, void* stream,
+                                 cbd_factor* out) {
+    if (!p || !q || !o || !out) return fail(CBD_EARG, "rs_factor_batched: NULL argument");
+    if (q->d != p->d || q->n != p->n)
+        return fail(CBD_EARG, "rs_factor_batched: partition is for another grid");
+    if (p->grid != CBD_GRID_CELL) return fail(CBD_EARG, "rs_factor_batched: RS needs the cell-centred grid");
+    if (!o->exact && (o->n_pxy < 1 || !(o->tol >= 0.0) || !(o->proxy_ratio > 0.75)))
+        return fail(CBD_EARG, "rs_factor_batched: need n_pxy >= 1, tol >= 0, proxy_ratio > 0.75");
+    if (o->precision != CBD_PREC_FP64 && o->precision != CBD_PREC_FP32)
+        return fail(CBD_EARG, "rs_factor_batched: unknown precision");
+    hipStream_t s = (hipStream_t)stream;
+    auto* F = new cbd_factor_s;
+    F->prob = p;
+    F->part = q;
+    F->prec = o->precision;
+    F->esize = o->precision == CBD_PREC_FP64 ? 8 : 4;
+    int rc;
+    {
+        ScopedTimer tm("factor", s);
+        rc = o->precision == CBD_PREC_FP64 ? factor_impl<double>(p, q, o, s, F)
+                                           : factor_impl<float>(p, q, o, s, F);
+    }
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        delete F;
+        return rc;
+    }
+    *out = F;
+    return CBD_OK;
+}
+
+extern "C" int rs_factor_free(cbd_factor f) {
+    delete f;
+    return CBD_OK;
+}
+
+extern "C" int rs_factor_stats(cbd_factor f, int* S, int* n_levels, size_t* bytes, double* flops) {
+    if (!f) return fail(CBD_EARG, "rs_factor_stats: NULL factor");
+    if (S) std::memcpy(S, f->S.data(), sizeof(int) * f->S.size());
+    if (n_levels) *n_levels = f->n_compress;
+    if (bytes) *bytes = f->bytes;
+    if (flops) *flops = f->flops;
+    return CBD_OK;
+}
+
+extern "C" int rs_factor_level(cbd_factor f, int level, int* n_boxes, int* ranks, int* np, int* sub) {
+    if (!f || level < 0 || level >= (int)f->levels.size()) return fail(CBD_EARG, "rs_factor_level: bad level");
+    const Level& L = f->levels[level];
+    if (n_boxes) *n_boxes = L.nbox;
+    for (int B = 0; B < L.nbox; ++B) {
+        if (ranks) ranks[B] = L.k[B];
+        if (np) np[B] = L.meta[B].np;
+        if (sub) sub[B] = L.box_sub[B];
+    }
+    return CBD_OK;
+}
+
+namespace {
+int copy_box(cbd_factor f, const Level& L, int B, int* k, int* nr, int* sk, int* rd, double* T,
+             double* E, double* Gi, double* Bss) {
+    const BoxMeta& M = L.meta[B];
+    const int kk = L.k[B], nn = M.np - kk;
+    const long off = f->part->subs[M.sub].offset;
+    *k = kk;
+    *nr = nn;
+    for (int e = 0; e < kk; ++e)
+        if (sk) sk[e] = (int)(L.sr[M.act + e] - off);
+    for (int e = 0; e < nn; ++e)
+        if (rd) rd[e] = (int)(L.sr[M.act + kk + e] - off);
+    const long cnt = (long)M.np * M.np;
+    std::vector<double> buf(cnt);
+    if (f->prec == CBD_PREC_FP64) {
+        HIPCHK(hipMemcpy(buf.data(), (const double*)L.d_F + M.f, sizeof(double) * cnt, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> fb(cnt);
+        HIPCHK(hipMemcpy(fb.data(), (const float*)L.d_F + M.f, sizeof(float) * cnt, hipMemcpyDeviceToHost));
+        for (long e = 0; e < cnt; ++e) buf[e] = fb[e];
+    }
+    const long nt = (long)kk * nn;
+    if (T) std::memcpy(T, buf.data(), sizeof(double) * nt);
+    if (E) std::memcpy(E, buf.data() + nt, sizeof(double) * nt);
+    if (Gi) std::memcpy(Gi, buf.data() + 2 * nt, sizeof(double) * nn * nn);
+    if (Bss) std::memcpy(Bss, buf.data() + 2 * nt + (long)nn * nn, sizeof(double) * kk * kk);
+    return CBD_OK;
+}
+}  // namespace
+
+extern "C" int rs_factor_box(cbd_factor f, int i, int level, int box, int* k, int* nr, int* sk, int* rd,
+                             double* T, double* E, double* Ginv, double* Bss) {
+    if (!f || !k || !nr || level < 0 || level >= f->n_compress)
+        return fail(CBD_EARG, "rs_factor_box: bad argument");
+    const Level& L = f->levels[level];
+    if (i < 0 || i >= (int)L.sub_start.size() || L.sub_start[i] < 0)
+        return fail(CBD_EARG, "rs_factor_box: subdomain has no boxes at this level");
+    const int nb = (int)f->part->subs[i].levels[level].size();
+    if (box < 0 || box >= nb) return fail(CBD_EARG, "rs_factor_box: bad box");
+    return copy_box(f, L, L.sub_start[i] + box, k, nr, sk, rd, T, E, Ginv, Bss);
+}
+
+extern "C" int rs_factor_root(cbd_factor f, int i, int* S, int* idx, double* Ginv) {
+    if (!f || !S) return fail(CBD_EARG, "rs_factor_root: bad argument");
+    const Level& L = f->levels.back();
+    if (i < 0 || i >= (int)L.sub_start.size() || L.sub_start[i] < 0)
+        return fail(CBD_EARG, "rs_factor_root: bad subdomain");
+    int k, nr;
+    int rc = copy_box(f, L, L.sub_start[i], &k, &nr, nullptr, idx, nullptr, nullptr, Ginv, nullptr);
+    *S = nr;
+    return rc;
+}
+
+template <typename R>
+static int apply_impl(cbd_factor f, int nrhs, const double* r, double* z, hipStream_t s) {
+    cbd_partition_s* Q = f->part;
+    int rc = f->v.ensure(sizeof(R) * (size_t)Q->total * nrhs);
+    if (rc) return rc;
+    R* v = (R*)f->v.p;
+    for (const Level& L : f->levels)
+        if ((size_t)2 * L.np_max * sizeof(R) > 65536)
+            return fail(CBD_EARG, "rs_apply: box of " + std::to_string(L.np_max) + " DOFs exceeds the LDS of the apply kernel");
+    launch_gather<R>(r, f->prob->N, nrhs, Q->d_cidx, Q->total, v, s);
+    const int nl = (int)f->levels.size();
+    for (int l = 0; l < nl; ++l) {
+        const Level& L = f->levels[l];
+        launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, true, s);
+    }
+    for (int l = nl - 1; l >= 0; --l) {
+        const Level& L = f->levels[l];
+        launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, false, s);
+    }
+    launch_scatter<R>(v, nrhs, Q->d_inv_ptr, Q->d_inv_slot, f->prob->N, z, s);
+    HIPCHK(hipGetLastError());
+    return CBD_OK;
+}
+
+extern "C" int rs_apply(cbd_factor f, int nrhs, const double* r, double* z, void* stream) {
+    if (!f || !r || !z || nrhs < 1) return fail(CBD_EARG, "rs_apply: bad argument");
+    if (r == z) return fail(CBD_EARG, "rs_apply: r and z alias");
+    hipStream_t s = (hipStream_t)stream;
+    ScopedTimer tm("apply", s);
+    return f->prec == CBD_PREC_FP64 ? apply_impl<double>(f, nrhs, r, z, s) : apply_impl<float>(f, nrhs, r, z, s);
+}
+
+// ---------------------------------------------------------------------------
+// PCG
+// ---------------------------------------------------------------------------
+namespace {
+struct PcgWs {
+    double *r, *z, *p, *q, *zold, *partial, *rz, *pq, *rr, *rznew, *alpha, *beta, *fn2;
+    int* active;
+};
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+size_t carve(PcgWs* w, void* base, long N, int nrhs) {
+    size_t vec = align256(sizeof(double) * (size_t)N * nrhs);
+    size_t sc = align256(sizeof(double) * nrhs);
+    size_t off = 0;
+    char* b = (char*)base;
+    auto take = [&](size_t n) {
+        char* p = b ? b + off : nullptr;
+        off += n;
+        return p;
+    };
+    double** vecs[5] = {&w->r, &w->z, &w->p, &w->q, &w->zold};
+    for (auto v : vecs) *v = (double*)take(vec);
+    w->partial = (double*)take(align256(sizeof(double) * (size_t)nrhs * kDotBlocks));
+    double** scal[8] = {&w->rz, &w->pq, &w->rr, &w->rznew, &w->alpha, &w->beta, &w->fn2, nullptr};
+    for (int i = 0; i < 7; ++i) *scal[i] = (double*)take(sc);
+    w->active = (int*)take(align256(sizeof(int) * nrhs));
+    return off;
+}
+}  // namespace
+
+extern "C" size_t pcg_workspace_bytes(long N, int nrhs) {
+    PcgWs w;
+    return carve(&w, nullptr, N, nrhs);
+}
+
+extern "C" int pcg_solve(cbd_problem p, cbd_factor fac, int nrhs, const double* f, double* u, double tol,
+                         int maxit, int flexible, void* ws, size_t ws_bytes, int* iters, double* relres,
+                         void* stream) {
+    if (!p || !f || !u || !ws || !iters || !relres || nrhs < 1 || maxit < 0)
+        return fail(CBD_EARG, "pcg_solve: bad argument");
+    const long N = p->N;
+    if (ws_bytes < pcg_workspace_bytes(N, nrhs)) return fail(CBD_EARG, "pcg_solve: workspace too small");
+    if (fac && fac->prob != p) return fail(CBD_EARG, "pcg_solve: factor belongs to another problem");
+    hipStream_t s = (hipStream_t)stream;
+    PcgWs w;
+    carve(&w, ws, N, nrhs);
+    const long NV = N * nrhs;
+    int rc;
+    auto precond = [&](const double* in, double* outv) -> int {
+        if (fac) return rs_apply(fac, nrhs, in, outv, s);
+        launch_copy(outv, in, NV, s);
+        return CBD_OK;
+    };
+    launch_fill(u, 0.0, NV, s);
+    launch_copy(w.r, f, NV, s);
+    launch_dot(f, f, N, nrhs, w.partial, w.fn2, s);
+    std::vector<double> fn2(nrhs), rr(nrhs);
+    std::vector<int> active(nrhs);
+    HIPCHK(hipMemcpyAsync(fn2.data(), w.fn2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int n_active = 0;
+    for (int c = 0; c < nrhs; ++c) {
+        active[c] = fn2[c] > 0.0;
+        n_active += active[c];
+        iters[c] = 0;
+        relres[c] = active[c] ? 1.0 : 0.0;
+    }
+    HIPCHK(hipMemcpyAsync(w.active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    if ((rc = precond(w.r, w.z))) return rc;
+    launch_copy(w.p, w.z, NV, s);
+    launch_dot(w.r, w.z, N, nrhs, w.partial, w.rz, s);
+    for (int it = 1; it <= maxit && n_active > 0; ++it) {
+        if ((rc = kernel_matvec(p, nrhs, w.p, w.q, s))) return rc;
+        launch_dot(w.p, w.q, N, nrhs, w.partial, w.pq, s);
+        launch_pcg_alpha(w.rz, w.pq, w.active, w.alpha, nrhs, s);
+        launch_pcg_update_ur(u, w.r, w.p, w.q, w.alpha, N, nrhs, s);
+        launch_dot(w.r, w.r, N, nrhs, w.partial, w.rr, s);
+        HIPCHK(hipMemcpyAsync(rr.data(), w.rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        n_active = 0;
+        for (int c = 0; c < nrhs; ++c) {
+            if (!active[c]) continue;
+            iters[c] = it;
+            relres[c] = std::sqrt(rr[c] / fn2[c]);
+            if (relres[c] <= tol) active[c] = 0;
+            n_active += active[c];
+        }
+        if (n_active == 0) break;
+        HIPCHK(hipMemcpyAsync(w.active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        if (flexible) launch_copy(w.zold, w.z, NV, s);
+        if ((rc = precond(w.r, w.z))) return rc;
+        if (flexible) {
+            launch_sub(w.q, w.z, w.zold, NV, s);   // q is free until the next matvec
+            launch_dot(w.r, w.q, N, nrhs, w.partial, w.rznew, s);
+            launch_pcg_beta(w.rznew, w.rz, w.active, w.beta, nrhs, s);
+            launch_dot(w.r, w.z, N, nrhs, w.partial, w.rz, s);
+        } else {
+            launch_dot(w.r, w.z, N, nrhs, w.partial, w.rznew, s);
+            launch_pcg_beta(w.rznew, w.rz, w.active, w.beta, nrhs, s);
+        }
+        launch_pcg_update_p(w.p, w.z, w.beta, N, nrhs, s);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    // keep active[] on the host alive until the last async copy is done (synchronized above)
+    return n_active > 0 ? CBD_WNOTCONV : CBD_OK;
+}

@@ -1,0 +1,120 @@
+// Internal declarations shared by the host runtime (host.cpp) and the HIP
+// kernels (*.hip) of libcbd.  Not part of the public ABI (include/cbd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace cbd {
+
+constexpr double kInv2Pi = 0.15915494309189533577;   // 1/(2 pi)
+constexpr double kInv4Pi = 0.07957747154594766788;   // 1/(4 pi)
+
+// Read-only view of a discretized problem, passed to kernels by value.
+struct ProblemView {
+    int d;
+    int n;
+    long N;
+    const double* pts;   // SoA: pts[t*N + g]
+    const double* diag;  // b_i c_i A_ii
+    const double* w;     // h^d c_j (column scale)
+    const double* rs;    // b_i (row scale)
+};
+
+// Laplace kernel value K(r) from r^2 (Section 2.1, (e:k)).
+template <int D>
+__device__ __forceinline__ double laplace_from_r2(double r2) {
+    if constexpr (D == 2) {
+        return -0.5 * kInv2Pi * log(r2);        // -(1/2pi) log r = -(1/4pi) log r^2
+    } else {
+        return kInv4Pi * rsqrt(r2);             // 1/(4 pi r)
+    }
+}
+
+// Entry A_bc[gi][gj] of the discretized operator, generated on the fly in FP64.
+template <int D>
+__device__ __forceinline__ double matrix_entry(const ProblemView& P, long gi, long gj) {
+    if (gi == gj) return P.diag[gi];
+    double r2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        double dx = P.pts[t * P.N + gi] - P.pts[t * P.N + gj];
+        r2 += dx * dx;
+    }
+    return P.rs[gi] * laplace_from_r2<D>(r2) * P.w[gj];
+}
+
+// One box of a level batch of the RS factorization.
+struct BoxMeta {
+    int sub;        // subdomain
+    int np;         // active DOFs of the box (columns of its ID)
+    int nnear;      // near-field rows of its proxy matrix
+    int m;          // rows of the proxy matrix = nnear + n_pxy (0 for a root box)
+    long act;       // offset of its slot lists (act, sr, perm) in the level arrays
+    long near;      // offset of its near-field list
+    long y;         // offset of its proxy-matrix / elimination scratch (elements)
+    long app;       // offset of its box matrix A_pp (np x np, elements)
+    long f;         // offset of its factor slot (np x np elements) in the level's factor array
+    long ch;        // offset of its child-info entries, -1 for a box made of grid points
+    double ctr[3];  // proxy centre
+    double rho;     // proxy radius
+};
+
+// Where an active DOF of a parent box sits in its child's B_ss.
+template <typename R>
+struct ChildRef {
+    const R* bss;   // child's B_ss (k_c x k_c, column-major)
+    int ldk;        // k_c
+    int pos;        // position of the DOF among the child's skeletons
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+
+void launch_assemble(int d, int n, int grid, const double* b, const double* c, double* pts,
+                     double* diag, double* w, double* rs, double a_self, double weight,
+                     hipStream_t s);
+void launch_matvec(const ProblemView& P, int nrhs, const double* x, double* y, hipStream_t s);
+
+template <typename R>
+void launch_proxy_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, const int* act,
+                         const int* nearl, const int* cidx, const double* pxdir, int npxy,
+                         R* Y, hipStream_t s);
+template <typename R>
+void launch_cpqr(int nbox, const BoxMeta* meta, R* Y, const int* act, int* sr, int* perm,
+                 int* k, R* F, double tol, double tie, int m_max, int np_max, hipStream_t s);
+template <typename R>
+void launch_box_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, const int* act,
+                       const int* cidx, const ChildRef<R>* ch, R* App, hipStream_t s);
+template <typename R>
+void launch_eliminate(int nbox, const BoxMeta* meta, const int* perm, const int* k,
+                      const R* App, const double* T64, R* Wk, R* F, int* status, hipStream_t s);
+
+template <typename R>
+void launch_gather(const double* r, long N, int nrhs, const int* cidx, long total, R* v,
+                   hipStream_t s);
+template <typename R>
+void launch_scatter(const R* v, int nrhs, const int* inv_ptr, const int* inv_slot, long N,
+                    double* z, hipStream_t s);
+template <typename R>
+void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int* k, const R* F,
+                        R* v, int nrhs, int np_max, bool forward, hipStream_t s);
+
+// PCG vector kernels (FP64).
+void launch_dot(const double* a, const double* b, long N, int nrhs, double* partial,
+                double* out, hipStream_t s);
+void launch_pcg_alpha(const double* rz, const double* pq, const int* active, double* alpha,
+                      int nrhs, hipStream_t s);
+void launch_pcg_update_ur(double* u, double* r, const double* p, const double* q,
+                          const double* alpha, long N, int nrhs, hipStream_t s);
+void launch_pcg_beta(const double* rz_new, double* rz, const int* active, double* beta,
+                     int nrhs, hipStream_t s);
+void launch_pcg_update_p(double* p, const double* z, const double* beta, long N, int nrhs,
+                         hipStream_t s);
+void launch_copy(double* dst, const double* src, long n, hipStream_t s);
+void launch_fill(double* dst, double v, long n, hipStream_t s);
+void launch_sub(double* dst, const double* a, const double* b, long n, hipStream_t s);
+
+constexpr int kDotBlocks = 256;   // partial sums per right-hand side in launch_dot
+
+}  // namespace cbd

@@ -1,0 +1,147 @@
+// FP64 vector kernels of preconditioned CG (Section 5).  Vectors are N x nrhs
+// column-major; per-right-hand-side scalars live on the device.
+#include "internal.h"
+
+namespace cbd {
+
+constexpr int kVecThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    return s;
+}
+
+// partial[c*kDotBlocks + blk] = sum over the blk-th strided share of a[:,c].b[:,c]
+__global__ __launch_bounds__(kVecThreads) void k_dot_partial(const double* __restrict__ a,
+                                                             const double* __restrict__ b, long N,
+                                                             double* __restrict__ partial) {
+    __shared__ double red[kVecThreads / 64];
+    const int c = blockIdx.y;
+    const double* ac = a + (long)c * N;
+    const double* bc = b + (long)c * N;
+    double s = 0.0;
+    for (long i = (long)blockIdx.x * kVecThreads + threadIdx.x; i < N; i += (long)gridDim.x * kVecThreads)
+        s += ac[i] * bc[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial[c * kDotBlocks + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_dot_final(const double* __restrict__ partial,
+                                                           double* __restrict__ out) {
+    __shared__ double red[kVecThreads / 64];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < kDotBlocks; i += kVecThreads) s += partial[c * kDotBlocks + i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[c] = s;
+}
+
+void launch_dot(const double* a, const double* b, long N, int nrhs, double* partial, double* out,
+                hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks, nrhs), dim3(kVecThreads), 0, s, a, b, N,
+                       partial);
+    hipLaunchKernelGGL(k_dot_final, dim3(nrhs), dim3(kVecThreads), 0, s, partial, out);
+}
+
+__global__ void k_pcg_alpha(const double* rz, const double* pq, const int* active, double* alpha,
+                            int nrhs) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nrhs) alpha[c] = (active[c] && pq[c] != 0.0) ? rz[c] / pq[c] : 0.0;
+}
+
+void launch_pcg_alpha(const double* rz, const double* pq, const int* active, double* alpha,
+                      int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, s, rz, pq, active, alpha,
+                       nrhs);
+}
+
+__global__ void k_pcg_update_ur(double* __restrict__ u, double* __restrict__ r,
+                                const double* __restrict__ p, const double* __restrict__ q,
+                                const double* __restrict__ alpha, long N) {
+    const int c = blockIdx.y;
+    const double a = alpha[c];
+    if (a == 0.0) return;
+    const long off = (long)c * N;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
+        u[off + i] += a * p[off + i];
+        r[off + i] -= a * q[off + i];
+    }
+}
+
+void launch_pcg_update_ur(double* u, double* r, const double* p, const double* q,
+                          const double* alpha, long N, int nrhs, hipStream_t s) {
+    int blocks = (int)((N + kVecThreads - 1) / kVecThreads);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_pcg_update_ur, dim3(blocks, nrhs), dim3(kVecThreads), 0, s, u, r, p, q,
+                       alpha, N);
+}
+
+__global__ void k_pcg_beta(const double* rz_new, double* rz, const int* active, double* beta,
+                           int nrhs) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nrhs) {
+        beta[c] = (active[c] && rz[c] != 0.0) ? rz_new[c] / rz[c] : 0.0;
+        if (active[c]) rz[c] = rz_new[c];
+    }
+}
+
+void launch_pcg_beta(const double* rz_new, double* rz, const int* active, double* beta, int nrhs,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_beta, dim3((nrhs + 63) / 64), dim3(64), 0, s, rz_new, rz, active, beta,
+                       nrhs);
+}
+
+__global__ void k_pcg_update_p(double* __restrict__ p, const double* __restrict__ z,
+                               const double* __restrict__ beta, long N) {
+    const int c = blockIdx.y;
+    const double b = beta[c];
+    const long off = (long)c * N;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x)
+        p[off + i] = z[off + i] + b * p[off + i];
+}
+
+void launch_pcg_update_p(double* p, const double* z, const double* beta, long N, int nrhs,
+                         hipStream_t s) {
+    int blocks = (int)((N + kVecThreads - 1) / kVecThreads);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_pcg_update_p, dim3(blocks, nrhs), dim3(kVecThreads), 0, s, p, z, beta, N);
+}
+
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+__global__ void k_fill(double* __restrict__ dst, double v, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dst[i] = v;
+}
+__global__ void k_sub(double* __restrict__ dst, const double* __restrict__ a,
+                      const double* __restrict__ b, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dst[i] = a[i] - b[i];
+}
+
+static int vec_blocks(long n) {
+    long b = (n + kVecThreads - 1) / kVecThreads;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+void launch_copy(double* dst, const double* src, long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, dst, src, n);
+}
+void launch_fill(double* dst, double v, long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, dst, v, n);
+}
+void launch_sub(double* dst, const double* a, const double* b, long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, dst, a, b, n);
+}
+
+}  // namespace cbd

@@ -1,0 +1,77 @@
+"""CPU tests of the C ABI: the library loads and exports every declared symbol,
+and its host-only partition logic matches the oracle's decomposition exactly."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2108_12574_amd as cbd
+from paper_2108_12574_amd import _lib
+from oracle import dd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "cbd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = cbd.lib()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(L, name), name
+    # the binding declares exactly the header's functions
+    assert sorted(n for n, _, _ in _lib.SIGNATURES) == names
+
+
+def test_errors_are_reported_without_gpu():
+    L = cbd.lib()
+    import ctypes
+    h = ctypes.c_void_p()
+    assert L.dd_partition(2, 30, 4, 1, cbd.MODE_CBD, 0, ctypes.byref(h)) == _lib.EARG
+    assert b"multiple" in L.cbd_last_error()
+    assert L.dd_partition(2, 32, 8, 3, cbd.MODE_CBD, 0, ctypes.byref(h)) == _lib.EARG
+    assert L.dd_partition(4, 32, 8, 1, cbd.MODE_CBD, 0, ctypes.byref(h)) == _lib.EARG
+    with pytest.raises(cbd.CbdError):
+        cbd.Partition((2, 30), 4)
+
+
+CASES = [
+    (2, 64, 16, 1, dd.CBD, 0),
+    (2, 256, 4, 8, dd.SCHWARZ, 8),
+    (2, 48, 12, 1, dd.CBD, 0),
+    (2, 60, 6, 2, dd.CBD, 4),
+    (2, 32, 4, 1, dd.JACOBI, 0),
+    (2, 16, 2, 1, dd.CBD, 0),
+    (3, 32, 4, 1, dd.CBD, 0),
+    (3, 12, 4, 1, dd.SCHWARZ, 3),
+    (2, 512, 64, 1, dd.CBD, 0),
+]
+
+
+@pytest.mark.parametrize("d,n,m,delta,mode,leaf", CASES)
+def test_partition_matches_oracle(d, n, m, delta, mode, leaf):
+    ref = dd.Partition(d, n, m, delta, mode, leaf)
+    got = cbd.Partition((d, n), m, delta, mode, leaf)
+    assert got.D == ref.D and got.Lt == ref.Lt and got.Lr == ref.Lr
+    assert got.total == sum(len(s.index) for s in ref.subdomains)
+    for i, sd in enumerate(ref.subdomains):
+        idx, nleaves, root = got.subdomain(i)
+        assert np.array_equal(np.array(idx), sd.index)
+        assert nleaves == len(sd.leaves) and root == sd.root_level
+        for l in range(sd.root_level + 1):
+            boxes, parent = got.level_boxes(i, l)
+            assert len(boxes) == len(sd.levels[l])
+            for b, box in enumerate(sd.levels[l]):
+                assert boxes[b] == (box.lo, box.hi)
+            if l < sd.root_level:
+                for c, pb in enumerate(sd.levels[l + 1]):
+                    for ch in pb.children:
+                        assert parent[ch] == c
+            else:
+                assert parent == [-1]
