@@ -22,11 +22,51 @@ struct ProblemView {
     const double* rs;    // b_i (row scale)
 };
 
+// Natural logarithm of a positive, finite, normal double.  Range reduction
+// x = m 2^e with m in [sqrt(1/2), sqrt(2)), then log m = 2 atanh(s) with
+// s = (m - 1)/(m + 1), |s| <= 0.1716, summed as the Taylor series of atanh up
+// to s^21 (truncation < 1e-17 relative); e ln 2 uses a two-term split of ln 2
+// whose leading term has 25 significant bits, so e * ln2_hi is exact.  The
+// quotient uses the hardware reciprocal refined by Newton steps.  Accuracy is
+// a few ulp, checked through the matvec against the oracle's libm.
+__device__ __forceinline__ double log_pos(double x) {
+    constexpr double kLn2Hi = 0x1.62e42fp-1;
+    constexpr double kLn2Lo = 0x1.df473de6af279p-26;
+    constexpr double kSqrtHalf = 0.70710678118654752440;
+    double m = __builtin_amdgcn_frexp_mant(x);          // [0.5, 1)
+    int e = __builtin_amdgcn_frexp_exp(x);
+    const bool lo = m < kSqrtHalf;
+    m = lo ? m + m : m;
+    e = lo ? e - 1 : e;
+    const double f = m - 1.0;                            // exact
+    const double t = m + 1.0;
+    double r = __builtin_amdgcn_rcp(t);
+    r = fma(fma(-t, r, 1.0), r, r);
+    r = fma(fma(-t, r, 1.0), r, r);
+    double s = f * r;
+    s = fma(fma(-s, t, f), r, s);                        // s = f / t to ~0.5 ulp
+    const double z = s * s;
+    double q = 1.0 / 21.0;
+    q = fma(q, z, 1.0 / 19.0);
+    q = fma(q, z, 1.0 / 17.0);
+    q = fma(q, z, 1.0 / 15.0);
+    q = fma(q, z, 1.0 / 13.0);
+    q = fma(q, z, 1.0 / 11.0);
+    q = fma(q, z, 1.0 / 9.0);
+    q = fma(q, z, 1.0 / 7.0);
+    q = fma(q, z, 1.0 / 5.0);
+    q = fma(q, z, 1.0 / 3.0);
+    const double s2 = s + s;
+    const double logm = fma(s2 * z, q, s2);              // 2s (1 + z/3 + z^2/5 + ...)
+    const double de = (double)e;
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, logm));
+}
+
 // Laplace kernel value K(r) from r^2 (Section 2.1, (e:k)).
 template <int D>
 __device__ __forceinline__ double laplace_from_r2(double r2) {
     if constexpr (D == 2) {
-        return -0.5 * kInv2Pi * log(r2);        // -(1/2pi) log r = -(1/4pi) log r^2
+        return -0.5 * kInv2Pi * log_pos(r2);    // -(1/2pi) log r = -(1/4pi) log r^2
     } else {
         return kInv4Pi * rsqrt(r2);             // 1/(4 pi r)
     }
