@@ -536,6 +536,10 @@ struct cbd_factor_s {
 
 namespace {
 
+// Levels with at least this many boxes run the ID with one workgroup per box;
+// fewer boxes use the stepped QR that spreads each box over many workgroups.
+constexpr int kStepBoxes = 1024;
+
 double cpqr_flops(double m, double n, double k) {
     return 4.0 * m * n * k - 2.0 * (m + n) * k * k + 4.0 * k * k * k / 3.0;
 }
@@ -580,7 +584,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
     // and the ranks inflate.  Elimination, storage and apply use R.
     const double tie = 1e-10;
     std::vector<double> hdir = proxy_dirs(d, std::max(npxy, 1));
-    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf;
+    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf;
     if ((rc = dirbuf.ensure(sizeof(double) * hdir.size()))) return rc;
     HIPCHK(hipMemcpyAsync(dirbuf.p, hdir.data(), sizeof(double) * hdir.size(), hipMemcpyHostToDevice, s));
     if ((rc = statbuf.ensure(sizeof(int)))) return rc;
@@ -717,7 +721,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             const long np = M.np;
             o_act += np;
             o_near += M.nnear;
-            o_y += std::max((long)M.m, np) * np;
+            o_y += std::max((long)M.m * np, np * np + 16 * np);   // proxy matrix, or elimination scratch
             o_app += np * np;
             o_f += np * np;
             o_ch += (long)chl[B].size();
@@ -763,15 +767,44 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         R* App = (R*)appbuf.p;
         R* FF = (R*)L.d_F;
         if (!root) {
-            const size_t shm = (size_t)(L.np_max + L.m_max) * sizeof(double) + (size_t)L.np_max * sizeof(int);
-            if (shm > 65536)
-                return fail(CBD_EARG, "rs_factor_batched: box too large for the ID kernel's LDS at level " +
-                                          std::to_string(l) + " (np " + std::to_string(L.np_max) + ", rows " +
-                                          std::to_string(L.m_max) + ")");
             launch_proxy_matrix<double>(PV, L.nbox, L.d_meta, L.d_act, (const int*)nearbuf.p, Q->d_cidx,
                                         (const double*)dirbuf.p, npxy, Y, s);
-            launch_cpqr<double>(L.nbox, L.d_meta, Y, L.d_act, L.d_sr, L.d_perm, L.d_k, T64, o->tol, tie,
-                                L.m_max, L.np_max, s);
+            const size_t shm = (size_t)(L.np_max + L.m_max) * sizeof(double) + (size_t)L.np_max * sizeof(int);
+            if (L.nbox >= kStepBoxes && shm <= 65536) {
+                // many boxes: one workgroup per box
+                launch_cpqr(L.nbox, L.d_meta, Y, L.d_act, L.d_sr, L.d_perm, L.d_k, T64, o->tol, tie,
+                            L.m_max, L.np_max, s);
+            } else {
+                // few (or large) boxes: stepped QR, every launch spread over all boxes' columns
+                if ((size_t)L.m_max * sizeof(double) > 65536)
+                    return fail(CBD_EARG, "rs_factor_batched: proxy matrix of " + std::to_string(L.m_max) +
+                                              " rows exceeds the LDS of the QR update kernel");
+                if ((rc = qrbuf.ensure(sizeof(double) * (3 * o_act + 2 * L.nbox) + sizeof(int) * (o_act + 2 * L.nbox))))
+                    return rc;
+                QrState st;
+                st.norms = (double*)qrbuf.p;
+                st.alpha = st.norms + o_act;
+                st.beta = st.alpha + o_act;
+                st.nu0 = st.beta + L.nbox;
+                st.pv = (int*)(st.nu0 + L.nbox);
+                st.done = st.pv + o_act;
+                st.k = st.done + L.nbox;
+                launch_qr_init(L.nbox, L.np_max, L.d_meta, Y, st, s);
+                int jmax = 0;
+                for (const BoxMeta& M : L.meta) jmax = std::max(jmax, std::min(M.m, M.np));
+                std::vector<int> done(L.nbox);
+                for (int j = 0; j <= jmax; ++j) {
+                    launch_qr_step(L.nbox, L.np_max, L.m_max, L.d_meta, Y, st, j, o->tol, tie, s);
+                    if (j % 8 == 7) {
+                        HIPCHK(hipMemcpyAsync(done.data(), st.done, sizeof(int) * L.nbox, hipMemcpyDeviceToHost, s));
+                        HIPCHK(hipStreamSynchronize(s));
+                        bool all = true;
+                        for (int v : done) all = all && v;
+                        if (all) break;
+                    }
+                }
+                launch_qr_finish(L.nbox, L.d_meta, Y, st, L.d_act, L.d_sr, L.d_perm, L.d_k, T64, s);
+            }
         } else {
             // root boxes: no compression, k = 0, identity order
             std::vector<int> zeros(L.nbox, 0), ident(o_act);

@@ -120,9 +120,25 @@ template <typename R>
 void launch_proxy_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, const int* act,
                          const int* nearl, const int* cidx, const double* pxdir, int npxy,
                          R* Y, hipStream_t s);
-template <typename R>
-void launch_cpqr(int nbox, const BoxMeta* meta, R* Y, const int* act, int* sr, int* perm,
-                 int* k, R* F, double tol, double tie, int m_max, int np_max, hipStream_t s);
+void launch_cpqr(int nbox, const BoxMeta* meta, double* Y, const int* act, int* sr, int* perm,
+                 int* k, double* T64, double tol, double tie, int m_max, int np_max, hipStream_t s);
+
+// State of the stepped pivoted QR between launches (per-level device arrays).
+struct QrState {
+    double* norms;   // remaining column norms, per box at its act offset
+    double* alpha;   // diagonal of R, per box at its act offset
+    int* pv;         // column order, per box at its act offset
+    double* beta;    // per box: 2 / ||v||^2 of the current reflector
+    double* nu0;     // per box: largest column norm of Y
+    int* done;       // per box: stopped
+    int* k;          // per box: rank once stopped
+};
+void launch_qr_init(int nbox, int np_max, const BoxMeta* meta, const double* Y, const QrState& st,
+                    hipStream_t s);
+void launch_qr_step(int nbox, int np_max, int m_max, const BoxMeta* meta, double* Y, const QrState& st,
+                    int j, double tol, double tie, hipStream_t s);
+void launch_qr_finish(int nbox, const BoxMeta* meta, double* Y, const QrState& st, const int* act,
+                      int* sr, int* perm, int* k, double* T64, hipStream_t s);
 template <typename R>
 void launch_box_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, const int* act,
                        const int* cidx, const ChildRef<R>* ch, R* App, hipStream_t s);

@@ -84,57 +84,93 @@ void launch_proxy_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, co
 }
 
 // ---- truncated CPQR and T = R11^{-1} R12 -----------------------------------
-// Businger-Golub pivoting with norms recomputed from the trailing block at every
-// step; stop when the largest remaining norm is <= tol * (largest norm of Y).
-// Ties: the lowest column position whose norm is within tie * nu0 of the max.
-// Writes k, the pivot order (perm: positions, sr: slot ids, skeletons first),
-// and T (k x nr, column-major) at the start of the box's factor slot.
-template <typename R>
+// Businger-Golub pivoting: at every step the column with the largest remaining
+// norm (over the rows not yet eliminated) is swapped to the front and reduced by
+// a Householder reflection; stop when that norm is <= tol * nu0 (nu0: largest
+// column norm of Y).  Ties: the lowest column position whose norm is within
+// tie * nu0 of the maximum.  The remaining norms are recomputed from the updated
+// trailing block in the same pass as the reflection (no down-dating).
+// Outputs: k, the pivot order (perm: positions, sr: slot ids, skeletons first),
+// and T (k x nr, column-major) at the box's factor offset of T64.
+
+// Back substitution T = R11^{-1} R12 (R in the first k rows of Yb), one column per thread.
+__device__ void id_coefficients(const double* Yb, int m, int np, int k, double* T) {
+    const int nr = np - k;
+    for (int c = threadIdx.x; c < nr; c += kThreads) {
+        const double* rc = Yb + (long)(k + c) * m;
+        for (int a = k - 1; a >= 0; --a) {
+            double s = rc[a];
+            for (int b = a + 1; b < k; ++b) s -= Yb[a + (long)b * m] * T[b + (long)c * k];
+            T[a + (long)c * k] = s / Yb[a + (long)a * m];
+        }
+    }
+}
+
+// Householder update of trailing columns c in [c_lo, c_hi) (c > j) with the
+// reflector v (LDS, rows j..m-1), then their norm over rows j+1..m-1.
+__device__ __forceinline__ void reflect_columns(double* Yb, int m, int j, int c_lo, int c_hi,
+                                                const double* v, double beta, double* norms) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int c = c_lo + wid; c < c_hi; c += kWaves) {
+        double* col = Yb + (long)c * m;
+        double s = 0;
+        for (int r = j + lane; r < m; r += 64) s += v[r - j] * col[r];
+        s = wave_sum(s) * beta;
+        double q = 0;
+        for (int r = j + lane; r < m; r += 64) {
+            const double y = col[r] - s * v[r - j];
+            col[r] = y;
+            if (r > j) q += y * y;
+        }
+        q = wave_sum(q);
+        if (lane == 0) norms[c] = sqrt(q);
+    }
+}
+
+// One workgroup per box (levels with many boxes).
 __global__ __launch_bounds__(kThreads) void k_cpqr(const BoxMeta* __restrict__ meta,
-                                                   R* __restrict__ Y, const int* __restrict__ act,
+                                                   double* __restrict__ Y, const int* __restrict__ act,
                                                    int* __restrict__ sr, int* __restrict__ perm,
-                                                   int* __restrict__ kout, R* __restrict__ F,
-                                                   R tol, R tie) {
+                                                   int* __restrict__ kout, double* __restrict__ T64,
+                                                   double tol, double tie) {
     extern __shared__ char smem_raw[];
-    __shared__ R red[kWaves];
+    __shared__ double red[kWaves];
     __shared__ int redi[kWaves];
-    __shared__ R s_nu0, s_thr;
+    __shared__ double s_nu0, s_thr;
     __shared__ int s_stop, s_piv, s_k;
 
     const BoxMeta M = meta[blockIdx.x];
     const int m = M.m, np = M.np;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    R* Yb = Y + M.y;
-    R* norms = reinterpret_cast<R*>(smem_raw);   // np
-    R* v = norms + np;                           // m
-    int* pv = reinterpret_cast<int*>(v + m);     // np
+    double* Yb = Y + M.y;
+    double* norms = reinterpret_cast<double*>(smem_raw);   // np
+    double* v = norms + np;                                 // m
+    int* pv = reinterpret_cast<int*>(v + m);                // np
 
     for (int c = tid; c < np; c += kThreads) pv[c] = c;
+    for (int c = wid; c < np; c += kWaves) {
+        const double* col = Yb + (long)c * m;
+        double q = 0;
+        for (int r = lane; r < m; r += 64) q += col[r] * col[r];
+        q = wave_sum(q);
+        if (lane == 0) norms[c] = sqrt(q);
+    }
     if (tid == 0) s_k = 0;
     __syncthreads();
 
     const int kmax = m < np ? m : np;
     for (int j = 0; j < kmax; ++j) {
-        // remaining column norms
-        for (int c = j + wid; c < np; c += kWaves) {
-            R s = 0;
-            const R* col = Yb + (long)c * m;
-            for (int r = j + lane; r < m; r += 64) s += col[r] * col[r];
-            s = wave_sum(s);
-            if (lane == 0) norms[c] = sqrt(s);
-        }
-        __syncthreads();
-        R lmax = 0;
+        double lmax = 0;
         for (int c = j + tid; c < np; c += kThreads) lmax = norms[c] > lmax ? norms[c] : lmax;
         lmax = wave_max(lmax);
         if (lane == 0) red[wid] = lmax;
         __syncthreads();
         if (tid == 0) {
-            R mx = red[0];
+            double mx = red[0];
             for (int w = 1; w < kWaves; ++w) mx = red[w] > mx ? red[w] : mx;
             if (j == 0) s_nu0 = mx;
-            const R nu0 = s_nu0;
-            s_stop = (nu0 == (R)0) || (mx <= tol * nu0);
+            const double nu0 = s_nu0;
+            s_stop = (nu0 == 0.0) || (mx <= tol * nu0);
             s_thr = mx - tie * nu0;
         }
         __syncthreads();
@@ -152,36 +188,30 @@ __global__ __launch_bounds__(kThreads) void k_cpqr(const BoxMeta* __restrict__ m
         }
         __syncthreads();
         const int piv = s_piv;
-        const R xn = norms[piv];
+        const double xn = norms[piv];
         if (piv != j) {
-            R* cj = Yb + (long)j * m;
-            R* cp = Yb + (long)piv * m;
+            double* cj = Yb + (long)j * m;
+            double* cp = Yb + (long)piv * m;
             for (int r = tid; r < m; r += kThreads) {
-                R t = cj[r];
+                const double t = cj[r];
                 cj[r] = cp[r];
                 cp[r] = t;
             }
-            if (tid == 0) {
-                int t = pv[j];
-                pv[j] = pv[piv];
-                pv[piv] = t;
-            }
         }
         __syncthreads();
-        const R x0 = Yb[j + (long)j * m];
-        const R alpha = x0 >= (R)0 ? -xn : xn;
-        const R ax0 = x0 >= (R)0 ? x0 : -x0;
-        const R vn2 = (R)2 * xn * xn + (R)2 * ax0 * xn;   // ||x - alpha e1||^2
+        // (column piv now holds the old column j; its norm is recomputed below)
+        if (tid == 0 && piv != j) {
+            const int t = pv[j];
+            pv[j] = pv[piv];
+            pv[piv] = t;
+        }
+        const double x0 = Yb[j + (long)j * m];
+        const double alpha = x0 >= 0.0 ? -xn : xn;
+        const double vn2 = 2.0 * xn * xn + 2.0 * fabs(x0) * xn;   // ||x - alpha e1||^2
         for (int r = j + tid; r < m; r += kThreads) v[r - j] = (r == j) ? x0 - alpha : Yb[r + (long)j * m];
         __syncthreads();
-        const R beta = vn2 > (R)0 ? (R)2 / vn2 : (R)0;
-        for (int c = j + 1 + wid; c < np; c += kWaves) {
-            R* col = Yb + (long)c * m;
-            R s = 0;
-            for (int r = j + lane; r < m; r += 64) s += v[r - j] * col[r];
-            s = wave_sum(s) * beta;
-            for (int r = j + lane; r < m; r += 64) col[r] -= s * v[r - j];
-        }
+        const double beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+        reflect_columns(Yb, m, j, j + 1, np, v, beta, norms);
         if (tid == 0) {
             Yb[j + (long)j * m] = alpha;
             s_k = j + 1;
@@ -190,31 +220,187 @@ __global__ __launch_bounds__(kThreads) void k_cpqr(const BoxMeta* __restrict__ m
     }
     __syncthreads();
     const int k = s_k;
-    const int nr = np - k;
     if (tid == 0) kout[blockIdx.x] = k;
     for (int c = tid; c < np; c += kThreads) {
         perm[M.act + c] = pv[c];
         sr[M.act + c] = act[M.act + pv[c]];
     }
-    // T = R11^{-1} R12 by back substitution, one column per thread
-    R* T = F + M.f;
-    for (int c = tid; c < nr; c += kThreads) {
-        const R* rc = Yb + (long)(k + c) * m;
-        for (int a = k - 1; a >= 0; --a) {
-            R s = rc[a];
-            for (int b = a + 1; b < k; ++b) s -= Yb[a + (long)b * m] * T[b + (long)c * k];
-            T[a + (long)c * k] = s / Yb[a + (long)a * m];
+    id_coefficients(Yb, m, np, k, T64 + M.f);
+}
+
+void launch_cpqr(int nbox, const BoxMeta* meta, double* Y, const int* act, int* sr, int* perm, int* k,
+                 double* T64, double tol, double tie, int m_max, int np_max, hipStream_t s) {
+    if (nbox == 0) return;
+    size_t shm = (size_t)(np_max + m_max) * sizeof(double) + (size_t)np_max * sizeof(int);
+    hipLaunchKernelGGL(k_cpqr, dim3(nbox), dim3(kThreads), shm, s, meta, Y, act, sr, perm, k, T64, tol,
+                       tie);
+}
+
+// Stepped form for levels with few, large boxes: one launch pair per pivot step
+// (pivot + reflector: one workgroup per box; update: kQrCols columns per
+// workgroup), so that all CUs share the reflections of the few boxes.  The
+// state between launches lives in per-box device arrays (QrState).
+constexpr int kQrCols = 16;
+
+__global__ __launch_bounds__(kThreads) void k_qr_init(const BoxMeta* __restrict__ meta,
+                                                      const double* __restrict__ Y, QrState st) {
+    const BoxMeta M = meta[blockIdx.x];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int c0 = blockIdx.y * kQrCols;
+    const int c1 = min(M.np, c0 + kQrCols);
+    for (int c = c0 + wid; c < c1; c += kWaves) {
+        const double* col = Y + M.y + (long)c * M.m;
+        double q = 0;
+        for (int r = lane; r < M.m; r += 64) q += col[r] * col[r];
+        q = wave_sum(q);
+        if (lane == 0) {
+            st.norms[M.act + c] = sqrt(q);
+            st.pv[M.act + c] = c;
         }
+    }
+    if (blockIdx.y == 0 && threadIdx.x == 0) {
+        const int kmax = min(M.m, M.np);
+        st.done[blockIdx.x] = kmax == 0;
+        st.k[blockIdx.x] = 0;
     }
 }
 
-template <typename R>
-void launch_cpqr(int nbox, const BoxMeta* meta, R* Y, const int* act, int* sr, int* perm, int* k,
-                 R* F, double tol, double tie, int m_max, int np_max, hipStream_t s) {
+__global__ __launch_bounds__(kThreads) void k_qr_pivot(const BoxMeta* __restrict__ meta,
+                                                       double* __restrict__ Y, QrState st, int j,
+                                                       double tol, double tie) {
+    __shared__ double red[kWaves];
+    __shared__ int redi[kWaves];
+    __shared__ double s_thr;
+    __shared__ int s_stop, s_piv;
+    const int b = blockIdx.x;
+    if (st.done[b]) return;
+    const BoxMeta M = meta[b];
+    const int m = M.m, np = M.np;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int kmax = min(m, np);
+    if (j >= kmax) {
+        if (tid == 0) {
+            st.done[b] = 1;
+            st.k[b] = kmax;
+        }
+        return;
+    }
+    double* Yb = Y + M.y;
+    double* norms = st.norms + M.act;
+    double lmax = 0;
+    for (int c = j + tid; c < np; c += kThreads) lmax = norms[c] > lmax ? norms[c] : lmax;
+    lmax = wave_max(lmax);
+    if (lane == 0) red[wid] = lmax;
+    __syncthreads();
+    if (tid == 0) {
+        double mx = red[0];
+        for (int w = 1; w < kWaves; ++w) mx = red[w] > mx ? red[w] : mx;
+        if (j == 0) st.nu0[b] = mx;
+        const double nu0 = j == 0 ? mx : st.nu0[b];
+        s_stop = (nu0 == 0.0) || (mx <= tol * nu0);
+        s_thr = mx - tie * nu0;
+        if (s_stop) {
+            st.done[b] = 1;
+            st.k[b] = j;
+        }
+    }
+    __syncthreads();
+    if (s_stop) return;
+    int lmin = INT_MAX;
+    for (int c = j + tid; c < np; c += kThreads)
+        if (norms[c] >= s_thr) { lmin = c; break; }
+    lmin = wave_min_int(lmin);
+    if (lane == 0) redi[wid] = lmin;
+    __syncthreads();
+    if (tid == 0) {
+        int p = redi[0];
+        for (int w = 1; w < kWaves; ++w) p = redi[w] < p ? redi[w] : p;
+        s_piv = p;
+    }
+    __syncthreads();
+    const int piv = s_piv;
+    const double xn = norms[piv];
+    if (piv != j) {
+        double* cj = Yb + (long)j * m;
+        double* cp = Yb + (long)piv * m;
+        for (int r = tid; r < m; r += kThreads) {
+            const double t = cj[r];
+            cj[r] = cp[r];
+            cp[r] = t;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        if (piv != j) {
+            int* pv = st.pv + M.act;
+            const int t = pv[j];
+            pv[j] = pv[piv];
+            pv[piv] = t;
+            norms[piv] = norms[j];
+        }
+        const double x0 = Yb[j + (long)j * m];
+        const double alpha = x0 >= 0.0 ? -xn : xn;
+        const double vn2 = 2.0 * xn * xn + 2.0 * fabs(x0) * xn;
+        Yb[j + (long)j * m] = x0 - alpha;            // the reflector occupies column j
+        st.alpha[M.act + j] = alpha;
+        st.beta[b] = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_qr_update(const BoxMeta* __restrict__ meta,
+                                                        double* __restrict__ Y, QrState st, int j) {
+    extern __shared__ char smem_raw[];
+    const int b = blockIdx.x;
+    if (st.done[b]) return;
+    const BoxMeta M = meta[b];
+    const int c0 = max(j + 1, (int)blockIdx.y * kQrCols);
+    const int c1 = min(M.np, (int)(blockIdx.y + 1) * kQrCols);
+    if (c0 >= c1) return;
+    double* Yb = Y + M.y;
+    double* v = reinterpret_cast<double*>(smem_raw);
+    for (int r = j + threadIdx.x; r < M.m; r += kThreads) v[r - j] = Yb[r + (long)j * M.m];
+    __syncthreads();
+    reflect_columns(Yb, M.m, j, c0, c1, v, st.beta[b], st.norms + M.act);
+}
+
+__global__ __launch_bounds__(kThreads) void k_qr_finish(const BoxMeta* __restrict__ meta,
+                                                        double* __restrict__ Y, QrState st,
+                                                        const int* __restrict__ act, int* __restrict__ sr,
+                                                        int* __restrict__ perm, int* __restrict__ kout,
+                                                        double* __restrict__ T64) {
+    const int b = blockIdx.x;
+    const BoxMeta M = meta[b];
+    const int kmax = min(M.m, M.np);
+    const int k = st.done[b] ? st.k[b] : kmax;
+    double* Yb = Y + M.y;
+    for (int j = threadIdx.x; j < k; j += kThreads) Yb[j + (long)j * M.m] = st.alpha[M.act + j];
+    if (threadIdx.x == 0) kout[b] = k;
+    for (int c = threadIdx.x; c < M.np; c += kThreads) {
+        const int p = st.pv[M.act + c];
+        perm[M.act + c] = p;
+        sr[M.act + c] = act[M.act + p];
+    }
+    __syncthreads();
+    id_coefficients(Yb, M.m, M.np, k, T64 + M.f);
+}
+
+void launch_qr_init(int nbox, int np_max, const BoxMeta* meta, const double* Y, const QrState& st,
+                    hipStream_t s) {
     if (nbox == 0) return;
-    size_t shm = (size_t)(np_max + m_max) * sizeof(R) + (size_t)np_max * sizeof(int);
-    hipLaunchKernelGGL((k_cpqr<R>), dim3(nbox), dim3(kThreads), shm, s, meta, Y, act, sr, perm, k, F,
-                       (R)tol, (R)tie);
+    hipLaunchKernelGGL(k_qr_init, dim3(nbox, (np_max + kQrCols - 1) / kQrCols), dim3(kThreads), 0, s, meta,
+                       Y, st);
+}
+void launch_qr_step(int nbox, int np_max, int m_max, const BoxMeta* meta, double* Y, const QrState& st,
+                    int j, double tol, double tie, hipStream_t s) {
+    if (nbox == 0) return;
+    hipLaunchKernelGGL(k_qr_pivot, dim3(nbox), dim3(kThreads), 0, s, meta, Y, st, j, tol, tie);
+    hipLaunchKernelGGL(k_qr_update, dim3(nbox, (np_max + kQrCols - 1) / kQrCols), dim3(kThreads),
+                       (size_t)m_max * sizeof(double), s, meta, Y, st, j);
+}
+void launch_qr_finish(int nbox, const BoxMeta* meta, double* Y, const QrState& st, const int* act,
+                      int* sr, int* perm, int* k, double* T64, hipStream_t s) {
+    if (nbox == 0) return;
+    hipLaunchKernelGGL(k_qr_finish, dim3(nbox), dim3(kThreads), 0, s, meta, Y, st, act, sr, perm, k, T64);
 }
 
 // ---- box matrix A_pp --------------------------------------------------------
@@ -263,12 +449,140 @@ void launch_box_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, cons
                            App);
 }
 
+// ---- workgroup-level MFMA GEMM ----------------------------------------------
+// Matrix-core instruction per precision: v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32
+// (A: lane l holds row l%16, k l/16; B: column l%16, k l/16).  The accumulator
+// layouts differ (checked with an in-bounds probe): register v of lane l holds
+// row 4v + l/16 (f64) or 4(l/16) + v (f32) of column l%16.
+template <typename R>
+struct Mma;
+template <>
+struct Mma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int v, int lane) { return 4 * v + (lane >> 4); }
+};
+template <>
+struct Mma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int v, int lane) { return 4 * (lane >> 4) + v; }
+};
+
+// C (M x N, column-major, ldc) = beta C + alpha op(A) op(B), op(A) M x K, op(B) K x N;
+// ta/tb select the transposes (A[k + i*lda] / B[j + k*ldb]).  All threads of the
+// workgroup call it; 16 x 16 output tiles are spread over the waves.  With
+// upper != 0 tiles entirely below the diagonal are skipped (symmetric results
+// whose upper triangle is used).  Ends with a workgroup barrier.
+template <typename R>
+__device__ void wg_gemm(int M, int N, int K, R alpha, const R* A, int lda, bool ta, const R* B, int ldb,
+                        bool tb, R beta, R* C, int ldc, bool upper = false) {
+    typedef typename Mma<R>::v4 v4;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int t = wid; t < tm * tn; t += kWaves) {
+        const int i0 = (t % tm) << 4, j0 = (t / tm) << 4;
+        if (upper && i0 > j0 + 15) continue;
+        v4 acc = {0, 0, 0, 0};
+        const int i = i0 + li, j = j0 + li;
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int kk = k0 + lk;
+            R a = 0, b = 0;
+            if (i < M && kk < K) a = ta ? A[kk + (long)i * lda] : A[i + (long)kk * lda];
+            if (j < N && kk < K) b = tb ? B[j + (long)kk * ldb] : B[kk + (long)j * ldb];
+            acc = Mma<R>::op(a, b, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ii = i0 + Mma<R>::row(v, lane), jj = j0 + li;
+            if (ii < M && jj < N) {
+                R* c = C + ii + (long)jj * ldc;
+                *c = (beta == (R)0 ? (R)0 : beta * *c) + alpha * acc[v];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+constexpr int kBlk = 16;   // block size of the blocked Cholesky / triangular inverse
+
+// Blocked right-looking Cholesky of the upper triangle of S (n x n, lds): S = G^T G,
+// G overwrites the upper triangle.  Returns false on a non-positive pivot.
+template <typename R>
+__device__ bool wg_cholesky_upper(int n, R* S, int lds, int* s_fail) {
+    const int tid = threadIdx.x;
+    for (int J = 0; J < n; J += kBlk) {
+        const int jb = min(kBlk, n - J);
+        for (int jj = 0; jj < jb; ++jj) {
+            const int c = J + jj;
+            if (tid == 0) {
+                const R d = S[c + (long)c * lds];
+                if (!(d > (R)0)) *s_fail = 1;
+                else S[c + (long)c * lds] = sqrt(d);
+            }
+            __syncthreads();
+            if (*s_fail) return false;
+            const R g = S[c + (long)c * lds];
+            for (int q = c + 1 + tid; q < n; q += kThreads) S[c + (long)q * lds] /= g;
+            __syncthreads();
+            // rows c+1 .. J+jb-1 of the block row, all columns right of the diagonal
+            const int rows = jb - jj - 1, cols = n - c - 1;
+            for (long e = tid; e < (long)rows * cols; e += kThreads) {
+                const int a = c + 1 + (int)(e % rows), q = c + 1 + (int)(e / rows);
+                if (q >= a) S[a + (long)q * lds] -= S[c + (long)a * lds] * S[c + (long)q * lds];
+            }
+            __syncthreads();
+        }
+        const int rem = n - J - jb;
+        if (rem > 0) {
+            const R* P = S + J + (long)(J + jb) * lds;   // jb x rem panel of G
+            wg_gemm<R>(rem, rem, jb, (R)-1, P, lds, true, P, lds, false, (R)1,
+                       S + (J + jb) + (long)(J + jb) * lds, lds, true);
+        }
+    }
+    return true;
+}
+
+// X = G^{-1} for upper-triangular G (n x n, ldg), column-block by column-block:
+// X_JJ = G_JJ^{-1};  X_{0:J,J} = -X_{0:J,0:J} (G_{0:J,J} X_JJ).  W: n x kBlk scratch.
+template <typename R>
+__device__ void wg_triangular_inverse(int n, const R* G, int ldg, R* X, R* W) {
+    const int tid = threadIdx.x;
+    for (long e = tid; e < (long)n * n; e += kThreads) {
+        const int a = (int)(e % n), c = (int)(e / n);
+        if (a > c) X[e] = (R)0;
+    }
+    for (int J = 0; J < n; J += kBlk) {
+        const int jb = min(kBlk, n - J);
+        for (int c = J + tid; c < J + jb; c += kThreads) {
+            X[c + (long)c * n] = (R)1 / G[c + (long)c * ldg];
+            for (int a = c - 1; a >= J; --a) {
+                R s = 0;
+                for (int b = a + 1; b <= c; ++b) s += G[a + (long)b * ldg] * X[b + (long)c * n];
+                X[a + (long)c * n] = -s / G[a + (long)a * ldg];
+            }
+        }
+        __syncthreads();
+        if (J > 0) {
+            wg_gemm<R>(J, jb, jb, (R)1, G + (long)J * ldg, ldg, false, X + J + (long)J * n, n, false, (R)0, W, J);
+            wg_gemm<R>(J, jb, J, (R)-1, X, n, false, W, J, false, (R)0, X + (long)J * n, n);
+        }
+    }
+}
+
 // ---- compress-then-eliminate -------------------------------------------------
 // With the box matrix permuted to (s, r) order:
 //   B_sr = A_sr - A_ss T,  B_rr = A_rr - T^T A_sr - B_sr^T T   ((e:al))
 //   B_rr = G^T G,  E = B_sr G^{-1},  B_ss = A_ss - E E^T      ((e:alu), (e:b))
-// The factor slot (np x np elements) receives [T | E | G^{-1} | B_ss].
+// B_rr is formed and factored on its upper triangle (it is symmetric in exact
+// arithmetic).  The factor slot (np x np elements) receives [T | E | G^{-1} | B_ss].
 // A root box has k = 0: its slot receives G^{-1} of the whole box matrix.
+// Scratch per box: np^2 + kBlk*np elements at its y offset.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restrict__ meta,
                                                         const int* __restrict__ perm,
@@ -288,12 +602,14 @@ __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restric
     R* Ass = Wk + M.y;
     R* Bsr = Ass + (long)k * k;
     R* Brr = Bsr + (long)k * nr;
+    R* W = Brr + (long)nr * nr;
     R* Fb = F + M.f;
     R* T = Fb;
     R* E = Fb + (long)k * nr;
     R* Gi = E + (long)k * nr;
     R* Bss = Gi + (long)nr * nr;
 
+    for (long e = tid; e < (long)k * nr; e += kThreads) T[e] = (R)T64[M.f + e];
     for (long e = tid; e < (long)k * k; e += kThreads) {
         const int a = (int)(e % k), c = (int)(e / k);
         Ass[e] = A[pv[a] + (long)pv[c] * np];
@@ -306,91 +622,24 @@ __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restric
         const int i = (int)(e % nr), c = (int)(e / nr);
         Brr[e] = A[pv[k + i] + (long)pv[k + c] * np];
     }
-    // T of the ID (computed in FP64) in the factor's precision
-    for (long e = tid; e < (long)k * nr; e += kThreads) T[e] = (R)T64[M.f + e];
     if (tid == 0) s_fail = 0;
     __syncthreads();
 
     if (k > 0 && nr > 0) {
-        // B_rr -= T^T A_sr   (Bsr still holds A_sr)
-        for (long e = tid; e < (long)nr * nr; e += kThreads) {
-            const int i = (int)(e % nr), c = (int)(e / nr);
-            R s = 0;
-            for (int a = 0; a < k; ++a) s += T[a + (long)i * k] * Bsr[a + (long)c * k];
-            Brr[e] -= s;
-        }
-        __syncthreads();
-        // B_sr = A_sr - A_ss T  (in place: each entry reads only its own A_sr value)
-        for (long e = tid; e < (long)k * nr; e += kThreads) {
-            const int a = (int)(e % k), i = (int)(e / k);
-            R s = 0;
-            for (int b = 0; b < k; ++b) s += Ass[a + (long)b * k] * T[b + (long)i * k];
-            Bsr[e] -= s;
-        }
-        __syncthreads();
-        // B_rr -= B_sr^T T
-        for (long e = tid; e < (long)nr * nr; e += kThreads) {
-            const int i = (int)(e % nr), c = (int)(e / nr);
-            R s = 0;
-            for (int a = 0; a < k; ++a) s += Bsr[a + (long)i * k] * T[a + (long)c * k];
-            Brr[e] -= s;
-        }
-        __syncthreads();
+        wg_gemm<R>(nr, nr, k, (R)-1, T, k, true, Bsr, k, false, (R)1, Brr, nr, true);   // - T^T A_sr
+        wg_gemm<R>(k, nr, k, (R)-1, Ass, k, false, T, k, false, (R)1, Bsr, k);          // B_sr
+        wg_gemm<R>(nr, nr, k, (R)-1, Bsr, k, true, T, k, false, (R)1, Brr, nr, true);   // - B_sr^T T
     }
-    // symmetrize the upper triangle
-    for (long e = tid; e < (long)nr * nr; e += kThreads) {
-        const int i = (int)(e % nr), c = (int)(e / nr);
-        if (i < c) Brr[e] = (R)0.5 * (Brr[e] + Brr[c + (long)i * nr]);
-    }
-    __syncthreads();
-    // right-looking Cholesky, upper triangle in place: B_rr = G^T G
-    for (int j = 0; j < nr; ++j) {
-        if (tid == 0) {
-            const R dj = Brr[j + (long)j * nr];
-            if (!(dj > (R)0)) s_fail = 1;
-            else Brr[j + (long)j * nr] = sqrt(dj);
-        }
-        __syncthreads();
-        if (s_fail) break;
-        const R g = Brr[j + (long)j * nr];
-        for (int c = j + 1 + tid; c < nr; c += kThreads) Brr[j + (long)c * nr] /= g;
-        __syncthreads();
-        const int rem = nr - j - 1;
-        for (long e = tid; e < (long)rem * rem; e += kThreads) {
-            const int a = j + 1 + (int)(e % rem), c = j + 1 + (int)(e / rem);
-            if (a <= c) Brr[a + (long)c * nr] -= Brr[j + (long)a * nr] * Brr[j + (long)c * nr];
-        }
-        __syncthreads();
-    }
-    if (s_fail) {
+    if (!wg_cholesky_upper<R>(nr, Brr, nr, &s_fail)) {
         if (tid == 0) status[0] = blockIdx.x + 1;
         return;
     }
-    // G^{-1} (upper): column c solves G x = e_c by back substitution
-    for (int c = tid; c < nr; c += kThreads) {
-        for (int a = nr - 1; a > c; --a) Gi[a + (long)c * nr] = (R)0;
-        Gi[c + (long)c * nr] = (R)1 / Brr[c + (long)c * nr];
-        for (int a = c - 1; a >= 0; --a) {
-            R s = 0;
-            for (int b = a + 1; b <= c; ++b) s += Brr[a + (long)b * nr] * Gi[b + (long)c * nr];
-            Gi[a + (long)c * nr] = -s / Brr[a + (long)a * nr];
-        }
-    }
-    __syncthreads();
-    // E = B_sr G^{-1}
-    for (long e = tid; e < (long)k * nr; e += kThreads) {
-        const int a = (int)(e % k), i = (int)(e / k);
-        R s = 0;
-        for (int j = 0; j <= i; ++j) s += Bsr[a + (long)j * k] * Gi[j + (long)i * nr];
-        E[e] = s;
-    }
-    __syncthreads();
-    // B_ss = A_ss - E E^T
-    for (long e = tid; e < (long)k * k; e += kThreads) {
-        const int a = (int)(e % k), c = (int)(e / k);
-        R s = 0;
-        for (int i = 0; i < nr; ++i) s += E[a + (long)i * k] * E[c + (long)i * k];
-        Bss[e] = Ass[e] - s;
+    wg_triangular_inverse<R>(nr, Brr, nr, Gi, W);
+    if (k > 0) {
+        wg_gemm<R>(k, nr, nr, (R)1, Bsr, k, false, Gi, nr, false, (R)0, E, k);           // E = B_sr G^{-1}
+        for (long e = tid; e < (long)k * k; e += kThreads) Bss[e] = Ass[e];
+        __syncthreads();
+        wg_gemm<R>(k, k, nr, (R)-1, E, k, false, E, k, true, (R)1, Bss, k);              // B_ss = A_ss - E E^T
     }
 }
 
@@ -528,8 +777,6 @@ void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int*
 template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta*, const int*,
                                           const int*, const int*, const double*, int, double*,
                                           hipStream_t);
-template void launch_cpqr<double>(int, const BoxMeta*, double*, const int*, int*, int*, int*, double*,
-                                  double, double, int, int, hipStream_t);
 #define CBD_INST(R)                                                                                 \
     template void launch_box_matrix<R>(const ProblemView&, int, const BoxMeta*, const int*,         \
                                        const int*, const ChildRef<R>*, R*, hipStream_t);            \
