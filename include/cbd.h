@@ -59,6 +59,9 @@ typedef struct {
     int precision;       /* CBD_PREC_FP64 or CBD_PREC_FP32 */
     int exact;           /* 1: no compression; every A_i is factored by dense Cholesky
                             (the naive CBD of Section 5.1) */
+    const float* mlp;    /* device parameters of the rank predictor (rank_mlp_*), or NULL.
+                            Used only to schedule the pivoted QR; ranks and factors are
+                            decided by the QR and do not depend on it. */
 } cbd_rs_opts;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -138,6 +141,40 @@ int rs_factor_box(cbd_factor f, int i, int level, int box, int* k, int* nr,
                   int* sk, int* rd, double* T, double* E, double* Ginv, double* Bss);
 /* Root of subdomain i: S, local indices (S ints), G^{-1} of S = G^T G (S x S). */
 int rs_factor_root(cbd_factor f, int i, int* S, int* idx, double* Ginv);
+
+/* Skeleton-rank predictor (not in the paper: the project's learned part).  A
+ * 3-layer MLP (width CBD_MLP_WIDTH, ReLU) maps CBD_MLP_FEATURES features of a box,
+ * known before its ID, to log2(k + 1), k the rank its pivoted QR finds ((e:id)).
+ * Weights are used rounded to bfloat16; activations and sums are FP32.  The
+ * factorization uses the predictions to size the first, unchecked run of the
+ * stepped QR of a level; the QR's stopping rule still decides every rank.
+ *  params: device, rank_mlp_params() floats, layout W1 (64 x 6, row-major), b1 (64),
+ *  W2 (64 x 64), b2 (64), W3 (64), b3 (1).  X: device, n x 6 row-major.
+ *  Features: level/4, log2(box side in cells)/4, log2(active DOFs)/8,
+ *  log2(near-field DOFs + 1)/8, -log10(tol)/8, d/3.
+ *  rank_mlp_forward: y (device, n) = predictions.
+ *  rank_mlp_loss_grad: mean squared error against t (device, n) into loss (device, 1,
+ *  may be NULL) and its gradient into grad (device, like params); the weight
+ *  gradient is taken at the rounded weights; ws: device, rank_mlp_workspace_bytes(n).
+ *  rank_mlp_adam: one Adam step (beta 0.9 / 0.999, eps 1e-8) on params with moment
+ *  buffers m, v (device, like params, zero before step 1); step counts from 1.
+ *  rs_factor_features: training pairs of a factor's level: features (host, nbox x 6)
+ *  and ranks (host, nbox), either may be NULL.
+ *  rs_factor_schedule: stream synchronizations of the factorization, launch pairs of
+ *  the stepped QR, boxes whose rank exceeded the predicted budget, and the mean
+ *  absolute rank prediction error (0 without a predictor). */
+#define CBD_MLP_FEATURES 6
+#define CBD_MLP_WIDTH 64
+int rank_mlp_params(void);
+size_t rank_mlp_workspace_bytes(int n);
+int rank_mlp_forward(const float* params, int n, const float* X, float* y, void* stream);
+int rank_mlp_loss_grad(const float* params, int n, const float* X, const float* t, float* grad,
+                       float* loss, void* ws, size_t ws_bytes, void* stream);
+int rank_mlp_adam(float* params, const float* grad, float* m, float* v, int step, float lr,
+                  void* stream);
+int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* X, int* k);
+int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
+                       double* mean_abs_err);
 
 /* rs_apply - z = T^{-1} r = sum_i R_i^T A_i^{-1} R_i r, (e:ad), with every A_i^{-1}
  * applied through its RS factor: gather, forward sweep over levels, root solve,

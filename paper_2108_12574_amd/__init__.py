@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (GRID_CELL, GRID_NODE, MODE_CBD, MODE_JACOBI, MODE_SCHWARZ, PREC_FP32,
                    PREC_FP64, CbdError, check, lib)
 
-__all__ = ["Problem", "Partition", "Factor", "pcg_solve", "timing", "CbdError",
+__all__ = ["Problem", "Partition", "Factor", "RankMLP", "pcg_solve", "timing", "CbdError",
            "GRID_CELL", "GRID_NODE", "MODE_JACOBI", "MODE_SCHWARZ", "MODE_CBD",
            "PREC_FP64", "PREC_FP32"]
 
@@ -128,10 +128,11 @@ class Factor:
     """RS factors of all subdomain matrices (rs_factor_batched) and T^{-1} (rs_apply)."""
 
     def __init__(self, problem, partition, tol=1e-6, n_pxy=64, proxy_ratio=1.5,
-                 precision=PREC_FP64, exact=False):
+                 precision=PREC_FP64, exact=False, mlp=None):
         self.problem, self.partition = problem, partition
         self.precision = precision
-        opts = _lib.RSOpts(tol, n_pxy, proxy_ratio, precision, 1 if exact else 0)
+        opts = _lib.RSOpts(tol, n_pxy, proxy_ratio, precision, 1 if exact else 0,
+                           mlp.params.data_ptr() if mlp is not None else None)
         h = ctypes.c_void_p()
         check(lib().rs_factor_batched(problem.handle, partition.handle, ctypes.byref(opts),
                                       _stream(problem.device), ctypes.byref(h)))
@@ -179,6 +180,33 @@ class Factor:
         return {"sk": sk, "rd": rd, "T": f(T, k, nr), "E": f(E, k, nr), "Ginv": f(Gi, nr, nr),
                 "Bss": f(Bss, k, k)}
 
+    def features(self, level):
+        """Training pairs of one compressed level: (features (nbox, 6) float32, ranks (nbox,))."""
+        import numpy as np
+        nb = ctypes.c_int()
+        check(lib().rs_factor_features(self.handle, level, ctypes.byref(nb), None, None))
+        X = np.zeros((nb.value, RankMLP.F), np.float32)
+        k = np.zeros(nb.value, np.int32)
+        check(lib().rs_factor_features(self.handle, level, ctypes.byref(nb),
+                                       X.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                       k.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+        return X, k
+
+    def all_features(self):
+        import numpy as np
+        parts = [self.features(l) for l in range(self.stats()["levels"])]
+        if not parts:
+            return np.zeros((0, RankMLP.F), np.float32), np.zeros(0, np.int32)
+        return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
+
+    def schedule(self):
+        """(stream synchronizations, stepped-QR launch pairs, mispredicted boxes, mean |k - k_pred|)."""
+        s, q, m, e = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        check(lib().rs_factor_schedule(self.handle, ctypes.byref(s), ctypes.byref(q), ctypes.byref(m),
+                                       ctypes.byref(e)))
+        return {"host_syncs": s.value, "qr_steps": q.value, "mispredicted": m.value,
+                "mean_abs_err": e.value}
+
     def root(self, i):
         import numpy as np
         S = ctypes.c_int()
@@ -192,6 +220,61 @@ class Factor:
 
     def __del__(self):
         _free("rs_factor_free", self)
+
+
+class RankMLP:
+    """Skeleton-rank predictor (rank_mlp_*): parameters on the device, trained by the
+    library's forward/backward/Adam kernels on (features, log2(k + 1)) pairs."""
+
+    F = 6
+
+    def __init__(self, params, device="cuda"):
+        self.device = torch.device(device)
+        self.params = torch.as_tensor(params, dtype=torch.float32).to(self.device).contiguous()
+        if self.params.numel() != lib().rank_mlp_params():
+            raise ValueError("expected %d parameters" % lib().rank_mlp_params())
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+
+    def _dev(self, a):
+        return torch.as_tensor(a, dtype=torch.float32).to(self.device).contiguous()
+
+    def forward(self, X):
+        X = self._dev(X)
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=self.device)
+        check(lib().rank_mlp_forward(_ptr(self.params), X.shape[0], _ptr(X), _ptr(y), _stream(self.device)))
+        return y
+
+    def loss_grad(self, X, t):
+        X, t = self._dev(X), self._dev(t)
+        n = X.shape[0]
+        ws = torch.empty(lib().rank_mlp_workspace_bytes(n), dtype=torch.uint8, device=self.device)
+        g = torch.empty_like(self.params)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        check(lib().rank_mlp_loss_grad(_ptr(self.params), n, _ptr(X), _ptr(t), _ptr(g), _ptr(loss), _ptr(ws),
+                                       ws.numel(), _stream(self.device)))
+        return loss, g
+
+    def adam(self, g, lr):
+        self.step += 1
+        check(lib().rank_mlp_adam(_ptr(self.params), _ptr(g), _ptr(self.m), _ptr(self.v), self.step,
+                                  ctypes.c_float(lr), _stream(self.device)))
+
+    def train(self, X, k, steps=600, lr=1e-2):
+        """Full-batch Adam on log2(k + 1); returns the final loss."""
+        import math
+        X = self._dev(X)
+        t = self._dev(torch.log2(torch.as_tensor(k, dtype=torch.float32) + 1.0))
+        loss = None
+        for s in range(steps):
+            loss, g = self.loss_grad(X, t)
+            self.adam(g, lr * (0.5 * (1 + math.cos(math.pi * s / steps))) + 1e-4)
+        return float(loss.item())
+
+    def predict_ranks(self, X):
+        y = self.forward(X)
+        return torch.clamp(torch.round(torch.exp2(y) - 1.0), min=0).to(torch.int64)
 
 
 def pcg_solve(problem, factor, f, tol=1e-10, maxit=200, flexible=False):

@@ -18,7 +18,7 @@ OK, EARG, EHIP, ENOTSPD, ENOMEM, WNOTCONV = 0, -1, -2, -3, -4, 1
 class RSOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("n_pxy", ctypes.c_int),
                 ("proxy_ratio", ctypes.c_double), ("precision", ctypes.c_int),
-                ("exact", ctypes.c_int)]
+                ("exact", ctypes.c_int), ("mlp", ctypes.c_void_p)]
 
 
 # (name, restype, argtypes) of every exported symbol of include/cbd.h
@@ -44,6 +44,13 @@ SIGNATURES = [
     ("kernel_matvec", _i, [_vp, _i, _vp, _vp, _vp]),
     ("pcg_workspace_bytes", _sz, [_l, _i]),
     ("pcg_solve", _i, [_vp, _vp, _i, _vp, _vp, _d, _i, _i, _vp, _sz, _ip, _dp, _vp]),
+    ("rank_mlp_params", _i, []),
+    ("rank_mlp_workspace_bytes", _sz, [_i]),
+    ("rank_mlp_forward", _i, [_vp, _i, _vp, _vp, _vp]),
+    ("rank_mlp_loss_grad", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("rank_mlp_adam", _i, [_vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp]),
+    ("rs_factor_features", _i, [_vp, _i, _ip, ctypes.POINTER(ctypes.c_float), _ip]),
+    ("rs_factor_schedule", _i, [_vp, _ip, _ip, _ip, _dp]),
     ("cbd_timing_enable", _i, [_i]),
     ("cbd_timing_get", _i, [ctypes.c_char_p, _dp, ctypes.POINTER(_l)]),
     ("cbd_timing_reset", _i, []),

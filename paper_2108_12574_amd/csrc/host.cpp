@@ -479,6 +479,7 @@ struct Level {
     std::vector<BoxMeta> meta;
     std::vector<int> k, sr;             // host copies after the level ran
     std::vector<int> box_sub, box_idx;  // subdomain and partition box index of each batch box
+    std::vector<int> side;              // box side in cells (proxy geometry)
     std::vector<int> sub_start;         // first batch index of each subdomain (-1: absent)
     int np_max = 0, m_max = 0;
     long tot_act = 0, tot_f = 0;
@@ -522,6 +523,13 @@ struct cbd_factor_s {
     cbd_problem_s* prob;
     cbd_partition_s* part;
     int prec;
+    double tol = 0.0;
+    // scheduling statistics of the factorization
+    int host_syncs = 0;       // stream synchronizations issued by the factorization
+    int qr_steps = 0;         // launch pairs of the stepped pivoted QR
+    int mispredicted = 0;     // stepped boxes whose rank exceeded the predicted step budget
+    double pred_abs_err = 0.0;
+    int pred_count = 0;
     size_t esize;
     std::vector<Level> levels;   // compressed levels, then the root level
     int n_compress = 0;
@@ -547,6 +555,16 @@ double elim_flops(double k, double nr) {
     // T solve, B_sr, B_rr (symmetric), Cholesky, G^{-1}, E, B_ss (symmetric)
     return k * k * nr + 2.0 * k * k * nr + 2.0 * nr * nr * k + nr * nr * nr / 3.0 + nr * nr * nr / 3.0 +
            k * nr * nr + k * k * nr;
+}
+
+// Features of a box known before its ID (input of the rank predictor).
+void box_features(int level, int side, int np, int nnear, double tol, int d, float* out) {
+    out[0] = (float)level / 4.f;
+    out[1] = (float)std::log2((double)std::max(side, 1)) / 4.f;
+    out[2] = (float)std::log2((double)std::max(np, 1)) / 8.f;
+    out[3] = (float)std::log2((double)nnear + 1.0) / 8.f;
+    out[4] = (float)(-std::log10(std::max(tol, 1e-300))) / 8.f;
+    out[5] = (float)d / 3.f;
 }
 
 // Proxy surface directions: equispaced circle (2D), golden-angle sphere (3D).
@@ -584,7 +602,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
     // and the ranks inflate.  Elimination, storage and apply use R.
     const double tie = 1e-10;
     std::vector<double> hdir = proxy_dirs(d, std::max(npxy, 1));
-    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf;
+    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf, mlpbuf;
     if ((rc = dirbuf.ensure(sizeof(double) * hdir.size()))) return rc;
     HIPCHK(hipMemcpyAsync(dirbuf.p, hdir.data(), sizeof(double) * hdir.size(), hipMemcpyHostToDevice, s));
     if ((rc = statbuf.ensure(sizeof(int)))) return rc;
@@ -718,6 +736,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 Lside = std::max(Lside, bhi[B * 3 + t] - blo[B * 3 + t]);
             }
             M.rho = o->proxy_ratio * Lside * P->h;
+            L.side.push_back(Lside);
             const long np = M.np;
             o_act += np;
             o_near += M.nnear;
@@ -766,6 +785,26 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         R* Wk = (R*)wbuf.p;
         R* App = (R*)appbuf.p;
         R* FF = (R*)L.d_F;
+        std::vector<int> kpred;
+        if (!root && o->mlp) {
+            std::vector<float> feats((size_t)L.nbox * kMlpFeatures), yhat(L.nbox);
+            for (int B = 0; B < L.nbox; ++B)
+                box_features(l, L.side[B], L.meta[B].np, L.meta[B].nnear, o->tol, d, &feats[(size_t)B * kMlpFeatures]);
+            if ((rc = mlpbuf.ensure(sizeof(float) * (size_t)L.nbox * (kMlpFeatures + 1)))) return rc;
+            float* dX = (float*)mlpbuf.p;
+            float* dy = dX + (size_t)L.nbox * kMlpFeatures;
+            HIPCHK(hipMemcpyAsync(dX, feats.data(), sizeof(float) * feats.size(), hipMemcpyHostToDevice, s));
+            launch_mlp_forward(o->mlp, L.nbox, dX, dy, nullptr, nullptr, s);
+            HIPCHK(hipMemcpyAsync(yhat.data(), dy, sizeof(float) * L.nbox, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            F->host_syncs++;
+            kpred.resize(L.nbox);
+            for (int B = 0; B < L.nbox; ++B) {
+                const int kmax = std::min(L.meta[B].m, L.meta[B].np);
+                const double kp = std::exp2((double)yhat[B]) - 1.0;
+                kpred[B] = std::max(0, std::min(kmax, (int)std::lround(std::isfinite(kp) ? kp : (double)kmax)));
+            }
+        }
         if (!root) {
             launch_proxy_matrix<double>(PV, L.nbox, L.d_meta, L.d_act, (const int*)nearbuf.p, Q->d_cidx,
                                         (const double*)dirbuf.p, npxy, Y, s);
@@ -793,15 +832,33 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 int jmax = 0;
                 for (const BoxMeta& M : L.meta) jmax = std::max(jmax, std::min(M.m, M.np));
                 std::vector<int> done(L.nbox);
-                for (int j = 0; j <= jmax; ++j) {
+                auto all_done = [&](bool& all) -> int {
+                    HIPCHK(hipMemcpyAsync(done.data(), st.done, sizeof(int) * L.nbox, hipMemcpyDeviceToHost, s));
+                    HIPCHK(hipStreamSynchronize(s));
+                    F->host_syncs++;
+                    all = true;
+                    for (int v : done) all = all && v;
+                    return CBD_OK;
+                };
+                // With predicted ranks, the first steps run without checks: up to the largest
+                // predicted rank plus a margin.  The QR's own stopping rule decides every rank;
+                // a box still running after the budget falls back to checked steps.
+                int j = 0;
+                bool all = false;
+                if (!kpred.empty()) {
+                    int kmax_pred = 0;
+                    for (int kp : kpred) kmax_pred = std::max(kmax_pred, kp);
+                    const int budget = std::min(jmax + 1, (kmax_pred * 11 + 9) / 10 + 2);
+                    for (; j < budget; ++j) launch_qr_step(L.nbox, L.np_max, L.m_max, L.d_meta, Y, st, j, o->tol, tie, s);
+                    F->qr_steps += budget;
+                    if ((rc = all_done(all))) return rc;
+                    if (!all)
+                        for (int v : done) F->mispredicted += !v;
+                }
+                for (; !all && j <= jmax; ++j) {
                     launch_qr_step(L.nbox, L.np_max, L.m_max, L.d_meta, Y, st, j, o->tol, tie, s);
-                    if (j % 8 == 7) {
-                        HIPCHK(hipMemcpyAsync(done.data(), st.done, sizeof(int) * L.nbox, hipMemcpyDeviceToHost, s));
-                        HIPCHK(hipStreamSynchronize(s));
-                        bool all = true;
-                        for (int v : done) all = all && v;
-                        if (all) break;
-                    }
+                    F->qr_steps++;
+                    if (j % 8 == 7 && (rc = all_done(all))) return rc;
                 }
                 launch_qr_finish(L.nbox, L.d_meta, Y, st, L.d_act, L.d_sr, L.d_perm, L.d_k, T64, s);
             }
@@ -815,6 +872,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             HIPCHK(hipMemcpyAsync(L.d_sr, hact.data(), sizeof(int) * o_act, hipMemcpyHostToDevice, s));
             // the host vectors must stay alive until the copies finish
             HIPCHK(hipStreamSynchronize(s));
+            F->host_syncs++;
         }
         launch_box_matrix<R>(PV, L.nbox, L.d_meta, L.d_act, Q->d_cidx,
                              o_ch ? (const ChildRef<R>*)chbuf.p : nullptr, App, s);
@@ -827,6 +885,11 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         HIPCHK(hipMemcpyAsync(L.sr.data(), L.d_sr, sizeof(int) * o_act, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        F->host_syncs++;
+        for (size_t B = 0; B < kpred.size(); ++B) {
+            F->pred_abs_err += std::abs(kpred[B] - L.k[B]);
+            F->pred_count++;
+        }
         if (status) {
             const int B = status - 1;
             return fail(CBD_ENOTSPD, "rs_factor_batched: Cholesky breakdown at level " + std::to_string(l) +
@@ -863,6 +926,7 @@ extern "C" int rs_factor_batched(cbd_problem p, cbd_partition q, const cbd_rs_op
     F->part = q;
     F->prec = o->precision;
     F->esize = o->precision == CBD_PREC_FP64 ? 8 : 4;
+    F->tol = o->tol;
     int rc;
     {
         ScopedTimer tm("factor", s);
@@ -987,6 +1051,62 @@ extern "C" int rs_apply(cbd_factor f, int nrhs, const double* r, double* z, void
     hipStream_t s = (hipStream_t)stream;
     ScopedTimer tm("apply", s);
     return f->prec == CBD_PREC_FP64 ? apply_impl<double>(f, nrhs, r, z, s) : apply_impl<float>(f, nrhs, r, z, s);
+}
+
+// ---------------------------------------------------------------------------
+// skeleton-rank predictor
+// ---------------------------------------------------------------------------
+extern "C" int rank_mlp_params(void) { return kMlpParams; }
+
+extern "C" size_t rank_mlp_workspace_bytes(int n) {
+    return sizeof(float) * (size_t)(2 + 4 * kMlpWidth) * (size_t)std::max(n, 0);
+}
+
+extern "C" int rank_mlp_forward(const float* params, int n, const float* X, float* y, void* stream) {
+    if (!params || n < 0 || (n > 0 && (!X || !y))) return fail(CBD_EARG, "rank_mlp_forward: bad argument");
+    launch_mlp_forward(params, n, X, y, nullptr, nullptr, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return CBD_OK;
+}
+
+extern "C" int rank_mlp_loss_grad(const float* params, int n, const float* X, const float* t, float* grad,
+                                  float* loss, void* ws, size_t ws_bytes, void* stream) {
+    if (!params || !X || !t || !grad || !ws || n < 1) return fail(CBD_EARG, "rank_mlp_loss_grad: bad argument");
+    if (ws_bytes < rank_mlp_workspace_bytes(n)) return fail(CBD_EARG, "rank_mlp_loss_grad: workspace too small");
+    launch_mlp_loss_grad(params, n, X, t, grad, loss, (float*)ws, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return CBD_OK;
+}
+
+extern "C" int rank_mlp_adam(float* params, const float* grad, float* m, float* v, int step, float lr,
+                             void* stream) {
+    if (!params || !grad || !m || !v || step < 1) return fail(CBD_EARG, "rank_mlp_adam: bad argument");
+    launch_mlp_adam(params, grad, m, v, step, lr, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return CBD_OK;
+}
+
+extern "C" int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* X, int* k) {
+    if (!f || !n_boxes || level < 0 || level >= f->n_compress)
+        return fail(CBD_EARG, "rs_factor_features: bad argument");
+    const Level& L = f->levels[level];
+    *n_boxes = L.nbox;
+    for (int B = 0; B < L.nbox; ++B) {
+        if (X) box_features(level, L.side[B], L.meta[B].np, L.meta[B].nnear, f->tol, f->prob->d,
+                            X + (size_t)B * kMlpFeatures);
+        if (k) k[B] = L.k[B];
+    }
+    return CBD_OK;
+}
+
+extern "C" int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
+                                  double* mean_abs_err) {
+    if (!f) return fail(CBD_EARG, "rs_factor_schedule: NULL factor");
+    if (host_syncs) *host_syncs = f->host_syncs;
+    if (qr_steps) *qr_steps = f->qr_steps;
+    if (mispredicted) *mispredicted = f->mispredicted;
+    if (mean_abs_err) *mean_abs_err = f->pred_count ? f->pred_abs_err / f->pred_count : 0.0;
+    return CBD_OK;
 }
 
 // ---------------------------------------------------------------------------

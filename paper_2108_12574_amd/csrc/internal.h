@@ -173,4 +173,16 @@ void launch_sub(double* dst, const double* a, const double* b, long n, hipStream
 
 constexpr int kDotBlocks = 256;   // partial sums per right-hand side in launch_dot
 
+// Skeleton-rank predictor (mlp.hip).
+constexpr int kMlpFeatures = 6;
+constexpr int kMlpWidth = 64;
+constexpr int kMlpParams = kMlpWidth * kMlpFeatures + kMlpWidth + kMlpWidth * kMlpWidth + kMlpWidth +
+                           kMlpWidth + 1;
+void launch_mlp_forward(const float* p, int n, const float* X, float* y, float* z1, float* z2,
+                        hipStream_t s);
+// ws: (2 + 4 * kMlpWidth) * n floats
+void launch_mlp_loss_grad(const float* p, int n, const float* X, const float* t, float* grad,
+                          float* loss, float* ws, hipStream_t s);
+void launch_mlp_adam(float* p, const float* g, float* m, float* v, int step, float lr, hipStream_t s);
+
 }  // namespace cbd
