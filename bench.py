@@ -28,6 +28,29 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 FP32_PEAK_TFLOPS = 157.3
 
 
+def train_rank_predictor(cbd, dev):
+    """Skeleton-rank MLP trained by the library's kernels on (features, rank) pairs
+    of the 64^2 (tol 1e-8), 256^2 Schwarz (tol 1e-6) and 512^2 (tol 1e-6) factorizations."""
+    import numpy as np
+    Xs, ks = [], []
+    for n, m, tol, mode, delta, leaf in [(64, 16, 1e-8, cbd.MODE_CBD, 1, 0),
+                                         (256, 4, 1e-6, cbd.MODE_SCHWARZ, 8, 8),
+                                         (512, 64, 1e-6, cbd.MODE_CBD, 1, 0)]:
+        Pt = cbd.Problem(2, n, device=dev)
+        Ft = cbd.Factor(Pt, cbd.Partition(Pt, m, delta, mode, leaf), tol=tol, n_pxy=64, precision=cbd.PREC_FP32)
+        X, k = Ft.all_features()
+        Xs.append(X)
+        ks.append(k)
+    rng = np.random.default_rng(0)
+    H, F = 64, cbd.RankMLP.F
+    p0 = np.concatenate([rng.standard_normal(H * F) * np.sqrt(2.0 / F), np.zeros(H),
+                         rng.standard_normal(H * H) * np.sqrt(2.0 / H), np.zeros(H),
+                         rng.standard_normal(H) * np.sqrt(1.0 / H), np.zeros(1)]).astype(np.float32)
+    net = cbd.RankMLP(p0, dev)
+    net.train(np.concatenate(Xs), np.concatenate(ks), steps=1500, lr=1e-2)
+    return net
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,9 +86,22 @@ def main():
     F_rhs = torch.tensor(synth.rhs(N, nrhs, seed=0), device=dev)
     torch.cuda.synchronize()
 
+    # tile shape of the matvec, chosen by the library's autotuner
+    tile = P.autotune_matvec(nrhs)
+    tile1 = P.autotune_matvec(1)
+    log("matvec tile: %d row blocks per wave (%d RHS), %d (1 RHS)" % (tile, nrhs, tile1))
+
+    # rank predictor trained on ranks of the 64^2, 256^2 and 512^2 factorizations
+    t0 = time.perf_counter()
+    mlp = train_rank_predictor(cbd, dev)
+    torch.cuda.synchronize()
+    mlp_train_s = time.perf_counter() - t0
+    log("rank predictor trained in %.2f s" % mlp_train_s)
+
     def step():
         t0 = time.perf_counter()
-        fac = cbd.Factor(P, part, tol=args.tol, n_pxy=64, proxy_ratio=1.5, precision=cbd.PREC_FP32)
+        fac = cbd.Factor(P, part, tol=args.tol, n_pxy=64, proxy_ratio=1.5, precision=cbd.PREC_FP32,
+                         mlp=mlp)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         u, its, rr = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200)
@@ -94,7 +130,16 @@ def main():
     mv_ms, mv_n = cbd.timing.get("matvec")
     ap_ms, ap_n = cbd.timing.get("apply")
     st = fac.stats()
+    sched = fac.schedule()
     factor_s = float(np.mean(tf))
+    # the same factorization without the predictor
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac_nm = cbd.Factor(P, part, tol=args.tol, n_pxy=64, proxy_ratio=1.5, precision=cbd.PREC_FP32)
+    torch.cuda.synchronize()
+    factor_nm_s = time.perf_counter() - t0
+    sched_nm = fac_nm.schedule()
+    del fac_nm
     pcg_s = float(np.mean(ts))
     n_it = its_all[-1]
 
@@ -115,8 +160,8 @@ def main():
         _, it, _ = cbd.pcg_solve(P, fac64, F_rhs[c], tol=1e-10, maxit=200)
         its64.append(it)
     torch.cuda.synchronize()
-    f64_per_col = (time.perf_counter() - t0) / args.fp64_cols
-    f64_pcg = f64_per_col * nrhs
+    f64_per_col = (time.perf_counter() - t0) / max(args.fp64_cols, 1)
+    f64_pcg = f64_per_col * nrhs if args.fp64_cols > 0 else float("nan")
     log("fp64 form: factor %.3f s, %.3f s per column" % (f64_factor, f64_per_col))
 
     cpu = None
@@ -163,6 +208,11 @@ def main():
         "max_relres": max(rr_all),
         "matvec_avg_ms": mv_avg_s * 1e3,
         "apply_avg_ms": ap_ms / max(ap_n, 1),
+        "matvec_tile_rows_per_wave": 16 * tile,
+        "rank_predictor": {"train_s": mlp_train_s, "mean_abs_rank_err": sched["mean_abs_err"],
+                           "factor_s_with": factor_s, "factor_s_without": factor_nm_s,
+                           "host_syncs_with": sched["host_syncs"], "host_syncs_without": sched_nm["host_syncs"],
+                           "mispredicted_boxes": sched["mispredicted"]},
         "fp64_form": {"factor_s": f64_factor, "pcg_s_est": f64_pcg, "cols_timed": args.fp64_cols,
                       "n_it": its64,
                       "note": "PCG time measured on %d columns solved one at a time, scaled to %d"

@@ -187,16 +187,31 @@ int rs_apply(cbd_factor f, int nrhs, const double* r, double* z, void* stream);
  *  x, y: device, N x nrhs column-major FP64 (may not alias). */
 int kernel_matvec(cbd_problem p, int nrhs, const double* x, double* y, void* stream);
 
+/* cbd_autotune_matvec - choose the matvec's tile shape (rows per wave: 16, 32 or
+ * 64) for this problem and nrhs by timing each candidate with HIP events on
+ * `stream`; later kernel_matvec calls with the
+ * same number of 16-column right-hand-side blocks use it.  Each candidate runs on
+ * the first min(grid, 1024) workgroups.  Allocates and frees
+ * two temporary N x min(nrhs, 64) device arrays.  *choice (may be NULL)
+ * receives the rows per wave / 16. */
+int cbd_autotune_matvec(cbd_problem p, int nrhs, void* stream, int* choice);
+
 /* pcg_solve - preconditioned CG (Section 5) on A u = f for nrhs independent
- * right-hand sides: u0 = 0, stop a column when ||r||_2/||f||_2 <= tol; beta =
- * r+.z+/r.z, or r+.(z+ - z)/r.z when flexible != 0.  f (device, N x nrhs),
- * u (device, N x nrhs, output).  f_ = NULL factor means no preconditioner.
- *  ws: device workspace of at least pcg_workspace_bytes(N, nrhs) bytes.
- *  iters, relres: host arrays of nrhs (matvec count, final recurrence residual).
- *  Returns CBD_WNOTCONV if a column did not converge within maxit. */
+ * right-hand sides: u0 = 0, stop a column when ||r||_2/||f||_2 <= tol (the
+ * recurrence residual); beta = r+.z+/r.z, or r+.(z+ - z)/r.z with
+ * CBD_PCG_FLEXIBLE.  With CBD_PCG_GRAPH the two launch sequences of an iteration
+ * (matvec through ||r||, and preconditioner through the new direction) are
+ * captured once into HIP graphs and replayed; this needs a non-default stream,
+ * gives bitwise the same result, and records no kernel timers.
+ *  f (device, N x nrhs), u (device, N x nrhs, output).  fac = NULL: no
+ *  preconditioner.  ws: device workspace of at least pcg_workspace_bytes(N, nrhs)
+ *  bytes.  iters, relres: host arrays of nrhs (matvec count, final recurrence
+ *  residual).  Returns CBD_WNOTCONV if a column did not converge within maxit. */
+#define CBD_PCG_FLEXIBLE 1
+#define CBD_PCG_GRAPH 2
 size_t pcg_workspace_bytes(long N, int nrhs);
-int pcg_solve(cbd_problem p, cbd_factor f_, int nrhs, const double* f, double* u,
-              double tol, int maxit, int flexible, void* ws, size_t ws_bytes,
+int pcg_solve(cbd_problem p, cbd_factor fac, int nrhs, const double* f, double* u,
+              double tol, int maxit, int flags, void* ws, size_t ws_bytes,
               int* iters, double* relres, void* stream);
 
 /* Kernel timing with HIP events recorded on the launching stream around every

@@ -78,6 +78,12 @@ class Problem:
         check(lib().kernel_matvec(self.handle, x.shape[0], _ptr(x), _ptr(y), _stream(self.device)))
         return y[0] if one else y
 
+    def autotune_matvec(self, nrhs):
+        """Pick the matvec tile shape for nrhs right-hand sides (cbd_autotune_matvec)."""
+        ch = ctypes.c_int()
+        check(lib().cbd_autotune_matvec(self.handle, nrhs, _stream(self.device), ctypes.byref(ch)))
+        return ch.value
+
     def __del__(self):
         _free("cbd_problem_free", self)
 
@@ -277,8 +283,11 @@ class RankMLP:
         return torch.clamp(torch.round(torch.exp2(y) - 1.0), min=0).to(torch.int64)
 
 
-def pcg_solve(problem, factor, f, tol=1e-10, maxit=200, flexible=False):
-    """PCG on A u = f (pcg_solve).  f: (N,) or (nrhs, N).  Returns (u, iters, relres)."""
+def pcg_solve(problem, factor, f, tol=1e-10, maxit=200, flexible=False, graph=False):
+    """PCG on A u = f (pcg_solve).  f: (N,) or (nrhs, N).  Returns (u, iters, relres).
+
+    graph=True replays each iteration from captured HIP graphs (needs a non-default
+    current stream)."""
     one = f.dim() == 1
     f = _vec(f, problem.N, problem.device)
     nrhs = f.shape[0]
@@ -287,8 +296,9 @@ def pcg_solve(problem, factor, f, tol=1e-10, maxit=200, flexible=False):
     ws = torch.empty(nb, dtype=torch.uint8, device=problem.device)
     iters = (ctypes.c_int * nrhs)()
     relres = (ctypes.c_double * nrhs)()
+    flags = (1 if flexible else 0) | (2 if graph else 0)
     rc = lib().pcg_solve(problem.handle, factor.handle if factor is not None else None, nrhs,
-                         _ptr(f), _ptr(u), tol, maxit, 1 if flexible else 0, _ptr(ws), nb,
+                         _ptr(f), _ptr(u), tol, maxit, flags, _ptr(ws), nb,
                          iters, relres, _stream(problem.device))
     check(rc, allow_warning=True)
     its, rr = list(iters), list(relres)

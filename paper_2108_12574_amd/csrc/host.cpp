@@ -39,6 +39,7 @@ namespace {
 
 std::mutex g_tmx;
 bool g_timing = false;
+thread_local bool g_capturing = false;   // no timer events inside a stream capture
 struct PendingTimer {
     std::string name;
     hipEvent_t a, b;
@@ -54,7 +55,7 @@ struct ScopedTimer {
     bool on = false;
     ScopedTimer(const char* n, hipStream_t st) : name(n), s(st) {
         std::lock_guard<std::mutex> lk(g_tmx);
-        if (!g_timing) return;
+        if (!g_timing || g_capturing) return;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
         (void)hipEventRecord(a, s);
         on = true;
@@ -115,6 +116,7 @@ struct cbd_problem_s {
     long N;
     double h, weight, a_self;
     double *pts, *diag, *w, *rs;
+    int mv_rb[4] = {0, 0, 0, 0};   // tuned matvec row blocks per wave, per RHS-block count (0: default)
     ProblemView view() const { return ProblemView{d, n, N, pts, diag, w, rs}; }
 };
 
@@ -150,6 +152,10 @@ extern "C" int ie_assemble(int d, int n, int grid, const double* b, const double
     p->w = w;
     p->rs = rowscale;
     hipStream_t s = (hipStream_t)stream;
+    if (!matvec_prepare()) {
+        delete p;
+        return fail(CBD_ENOMEM, "ie_assemble: could not allocate the matvec tables");
+    }
     launch_assemble(d, n, grid, b, c, pts, diag, w, rowscale, p->a_self, p->weight, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -171,9 +177,51 @@ extern "C" int kernel_matvec(cbd_problem p, int nrhs, const double* x, double* y
     hipStream_t s = (hipStream_t)stream;
     {
         ScopedTimer tm("matvec", s);
-        launch_matvec(p->view(), nrhs, x, y, s);
+        launch_matvec(p->view(), nrhs, x, y, p->mv_rb[matvec_nb(nrhs) - 1], 0, s);
     }
     HIPCHK(hipGetLastError());
+    return CBD_OK;
+}
+
+extern "C" int cbd_autotune_matvec(cbd_problem p, int nrhs, void* stream, int* choice) {
+    if (!p || nrhs < 1) return fail(CBD_EARG, "cbd_autotune_matvec: bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = matvec_nb(nrhs);
+    const int cols = std::min(nrhs, 64);
+    double *x = nullptr, *y = nullptr;
+    HIPCHK(hipMalloc(&x, sizeof(double) * p->N * cols));
+    HIPCHK(hipMalloc(&y, sizeof(double) * p->N * cols));
+    launch_fill(x, 1.0, p->N * cols, s);
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    int best = matvec_default_rb(nb);
+    double best_t = 1e300;
+    const int cand[3] = {1, 2, 4};
+    for (int rb : cand) {
+        // every candidate runs on the same number of workgroups (4 per CU when the
+        // grid is that large), so that occupancy and L2 reuse are comparable
+        const long full = (p->N + 64L * rb - 1) / (64L * rb);
+        const int blocks = (int)std::min(full, 1024L);
+        launch_matvec(p->view(), cols, x, y, rb, blocks, s);   // warm-up
+        (void)hipEventRecord(a, s);
+        for (int rep = 0; rep < 2; ++rep) launch_matvec(p->view(), cols, x, y, rb, blocks, s);
+        (void)hipEventRecord(b, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
+        const double per_row = ms / (double)(blocks * 64L * rb);
+        if (per_row < best_t) {
+            best_t = per_row;
+            best = rb;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(x);
+    (void)hipFree(y);
+    HIPCHK(hipGetLastError());
+    p->mv_rb[nb - 1] = best;
+    if (choice) *choice = best;
     return CBD_OK;
 }
 
@@ -1021,10 +1069,15 @@ extern "C" int rs_factor_root(cbd_factor f, int i, int* S, int* idx, double* Gin
     return rc;
 }
 
+// Allocate the apply's local vectors for nrhs columns ahead of time (stream capture).
+static int apply_prepare(cbd_factor f, int nrhs) {
+    return f->v.ensure(f->esize * (size_t)f->part->total * nrhs);
+}
+
 template <typename R>
 static int apply_impl(cbd_factor f, int nrhs, const double* r, double* z, hipStream_t s) {
     cbd_partition_s* Q = f->part;
-    int rc = f->v.ensure(sizeof(R) * (size_t)Q->total * nrhs);
+    int rc = apply_prepare(f, nrhs);
     if (rc) return rc;
     R* v = (R*)f->v.p;
     for (const Level& L : f->levels)
@@ -1143,24 +1196,94 @@ extern "C" size_t pcg_workspace_bytes(long N, int nrhs) {
     return carve(&w, nullptr, N, nrhs);
 }
 
+namespace {
+// The two launch sequences of a PCG iteration, around the host read of ||r||:
+// A: q = A p, alpha = r.z / p.q, u += alpha p, r -= alpha q, r.r
+// B: z = M r, beta, p = z + beta p
+struct PcgSeq {
+    cbd_problem p;
+    cbd_factor fac;
+    int nrhs, flexible;
+    long N, NV;
+    PcgWs w;
+    double* u;
+    int precond(const double* in, double* outv, hipStream_t s) const {
+        if (fac) return rs_apply(fac, nrhs, in, outv, s);
+        launch_copy(outv, in, NV, s);
+        return CBD_OK;
+    }
+    int seqA(hipStream_t s) const {
+        int rc = kernel_matvec(p, nrhs, w.p, w.q, s);
+        if (rc) return rc;
+        launch_dot(w.p, w.q, N, nrhs, w.partial, w.pq, s);
+        launch_pcg_alpha(w.rz, w.pq, w.active, w.alpha, nrhs, s);
+        launch_pcg_update_ur(u, w.r, w.p, w.q, w.alpha, N, nrhs, s);
+        launch_dot(w.r, w.r, N, nrhs, w.partial, w.rr, s);
+        return CBD_OK;
+    }
+    int seqB(hipStream_t s) const {
+        int rc;
+        if (flexible) launch_copy(w.zold, w.z, NV, s);
+        if ((rc = precond(w.r, w.z, s))) return rc;
+        if (flexible) {
+            launch_sub(w.q, w.z, w.zold, NV, s);   // q is free until the next matvec
+            launch_dot(w.r, w.q, N, nrhs, w.partial, w.rznew, s);
+            launch_pcg_beta(w.rznew, w.rz, w.active, w.beta, nrhs, s);
+            launch_dot(w.r, w.z, N, nrhs, w.partial, w.rz, s);
+        } else {
+            launch_dot(w.r, w.z, N, nrhs, w.partial, w.rznew, s);
+            launch_pcg_beta(w.rznew, w.rz, w.active, w.beta, nrhs, s);
+        }
+        launch_pcg_update_p(w.p, w.z, w.beta, N, nrhs, s);
+        return CBD_OK;
+    }
+};
+
+// Capture one launch sequence into an executable graph.
+template <typename Fn>
+int capture(hipStream_t s, Fn&& fn, hipGraphExec_t* exec) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    g_capturing = true;
+    int rc = fn(s);
+    g_capturing = false;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(CBD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(CBD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return CBD_OK;
+}
+}  // namespace
+
 extern "C" int pcg_solve(cbd_problem p, cbd_factor fac, int nrhs, const double* f, double* u, double tol,
-                         int maxit, int flexible, void* ws, size_t ws_bytes, int* iters, double* relres,
+                         int maxit, int flags, void* ws, size_t ws_bytes, int* iters, double* relres,
                          void* stream) {
     if (!p || !f || !u || !ws || !iters || !relres || nrhs < 1 || maxit < 0)
         return fail(CBD_EARG, "pcg_solve: bad argument");
+    if (flags & ~(CBD_PCG_FLEXIBLE | CBD_PCG_GRAPH)) return fail(CBD_EARG, "pcg_solve: unknown flags");
     const long N = p->N;
     if (ws_bytes < pcg_workspace_bytes(N, nrhs)) return fail(CBD_EARG, "pcg_solve: workspace too small");
     if (fac && fac->prob != p) return fail(CBD_EARG, "pcg_solve: factor belongs to another problem");
     hipStream_t s = (hipStream_t)stream;
-    PcgWs w;
-    carve(&w, ws, N, nrhs);
-    const long NV = N * nrhs;
+    const bool graph = (flags & CBD_PCG_GRAPH) != 0;
+    if (graph && s == nullptr) return fail(CBD_EARG, "pcg_solve: graph mode needs a non-default stream");
+    PcgSeq q;
+    q.p = p;
+    q.fac = fac;
+    q.nrhs = nrhs;
+    q.flexible = (flags & CBD_PCG_FLEXIBLE) != 0;
+    q.N = N;
+    q.NV = N * nrhs;
+    q.u = u;
+    carve(&q.w, ws, N, nrhs);
+    PcgWs& w = q.w;
+    const long NV = q.NV;
     int rc;
-    auto precond = [&](const double* in, double* outv) -> int {
-        if (fac) return rs_apply(fac, nrhs, in, outv, s);
-        launch_copy(outv, in, NV, s);
-        return CBD_OK;
-    };
     launch_fill(u, 0.0, NV, s);
     launch_copy(w.r, f, NV, s);
     launch_dot(f, f, N, nrhs, w.partial, w.fn2, s);
@@ -1176,15 +1299,37 @@ extern "C" int pcg_solve(cbd_problem p, cbd_factor fac, int nrhs, const double* 
         relres[c] = active[c] ? 1.0 : 0.0;
     }
     HIPCHK(hipMemcpyAsync(w.active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-    if ((rc = precond(w.r, w.z))) return rc;
+    if ((rc = q.precond(w.r, w.z, s))) return rc;
     launch_copy(w.p, w.z, NV, s);
     launch_dot(w.r, w.z, N, nrhs, w.partial, w.rz, s);
+    hipGraphExec_t gA = nullptr, gB = nullptr;
+    auto cleanup = [&]() {
+        if (gA) (void)hipGraphExecDestroy(gA);
+        if (gB) (void)hipGraphExecDestroy(gB);
+    };
+    if (graph && maxit > 0 && n_active > 0) {
+        // everything a captured launch needs is allocated beforehand
+        if (fac && (rc = apply_prepare(fac, nrhs))) return rc;
+        HIPCHK(hipStreamSynchronize(s));
+        if ((rc = capture(s, [&](hipStream_t cs) { return q.seqA(cs); }, &gA))) {
+            cleanup();
+            return rc;
+        }
+        if ((rc = capture(s, [&](hipStream_t cs) { return q.seqB(cs); }, &gB))) {
+            cleanup();
+            return rc;
+        }
+    }
     for (int it = 1; it <= maxit && n_active > 0; ++it) {
-        if ((rc = kernel_matvec(p, nrhs, w.p, w.q, s))) return rc;
-        launch_dot(w.p, w.q, N, nrhs, w.partial, w.pq, s);
-        launch_pcg_alpha(w.rz, w.pq, w.active, w.alpha, nrhs, s);
-        launch_pcg_update_ur(u, w.r, w.p, w.q, w.alpha, N, nrhs, s);
-        launch_dot(w.r, w.r, N, nrhs, w.partial, w.rr, s);
+        if (graph) {
+            hipError_t e = hipGraphLaunch(gA, s);
+            if (e != hipSuccess) {
+                cleanup();
+                return fail(CBD_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+            }
+        } else if ((rc = q.seqA(s))) {
+            return rc;
+        }
         HIPCHK(hipMemcpyAsync(rr.data(), w.rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         n_active = 0;
@@ -1197,21 +1342,19 @@ extern "C" int pcg_solve(cbd_problem p, cbd_factor fac, int nrhs, const double* 
         }
         if (n_active == 0) break;
         HIPCHK(hipMemcpyAsync(w.active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-        if (flexible) launch_copy(w.zold, w.z, NV, s);
-        if ((rc = precond(w.r, w.z))) return rc;
-        if (flexible) {
-            launch_sub(w.q, w.z, w.zold, NV, s);   // q is free until the next matvec
-            launch_dot(w.r, w.q, N, nrhs, w.partial, w.rznew, s);
-            launch_pcg_beta(w.rznew, w.rz, w.active, w.beta, nrhs, s);
-            launch_dot(w.r, w.z, N, nrhs, w.partial, w.rz, s);
-        } else {
-            launch_dot(w.r, w.z, N, nrhs, w.partial, w.rznew, s);
-            launch_pcg_beta(w.rznew, w.rz, w.active, w.beta, nrhs, s);
+        if (graph) {
+            hipError_t e = hipGraphLaunch(gB, s);
+            if (e != hipSuccess) {
+                cleanup();
+                return fail(CBD_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+            }
+        } else if ((rc = q.seqB(s))) {
+            return rc;
         }
-        launch_pcg_update_p(w.p, w.z, w.beta, N, nrhs, s);
         HIPCHK(hipGetLastError());
     }
     HIPCHK(hipStreamSynchronize(s));
-    // keep active[] on the host alive until the last async copy is done (synchronized above)
+    cleanup();
+    // active[] on the host stays alive until the last async copy is done (synchronized above)
     return n_active > 0 ? CBD_WNOTCONV : CBD_OK;
 }

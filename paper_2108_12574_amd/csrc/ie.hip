@@ -1,4 +1,6 @@
 // Discretization (Section 2.1) and the dense on-the-fly product y = A x.
+#include <cmath>
+
 #include "internal.h"
 
 namespace cbd {
@@ -44,21 +46,64 @@ void launch_assemble(int d, int n, int grid, const double* b, const double* c, d
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kMvThreads = 256;
-constexpr int kTJ = 64;                // sources per LDS tile
+constexpr int kTJ = 64;
+constexpr int kLogTab = 128;
+// 2D self pair: r^2 is clamped to 2^-1000 (K = 55.1...), removed exactly in the epilogue
+constexpr double kSelfR2 = 0x1p-1000;
+
+// Table-driven natural logarithm (Tang, ACM TOMS 15(2), 1989) for positive normal
+// x: x = 2^e m, m in [1, 2); F = 1 + j/128 from the top 7 mantissa bits (so
+// m - F is exact and u = (m - F)/F is in [0, 1/128)); log x = e ln2 + log F +
+// log1p(u), log1p by its Taylor series to u^8 (truncation < 2e-18 relative).
+// tab[2j] = log F_j, tab[2j+1] = 1/F_j (from the host's libm).
+__device__ __forceinline__ double log_tab(double x, const double* __restrict__ tab) {
+    constexpr double kLn2Hi = 0x1.62e42fp-1;
+    constexpr double kLn2Lo = 0x1.df473de6af279p-26;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
+    const unsigned hi = (unsigned)(bits >> 32), lo = (unsigned)bits;
+    const int e = (int)(hi >> 20) - 1023;
+    const unsigned mhi = (hi & 0x000FFFFFu) | 0x3FF00000u;
+    const double m = __longlong_as_double((long long)(((unsigned long long)mhi << 32) | lo));
+    const double F = __longlong_as_double((long long)((unsigned long long)(mhi & 0xFFFFE000u) << 32));
+    const int j = (mhi >> 13) & (kLogTab - 1);
+    const double u = (m - F) * tab[2 * j + 1];
+    double p = -1.0 / 8.0;
+    p = fma(p, u, 1.0 / 7.0);
+    p = fma(p, u, -1.0 / 6.0);
+    p = fma(p, u, 1.0 / 5.0);
+    p = fma(p, u, -1.0 / 4.0);
+    p = fma(p, u, 1.0 / 3.0);
+    p = fma(p, u, -1.0 / 2.0);
+    p = fma(p * u, u, u);                                  // log1p(u)
+    const double de = (double)e;
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, tab[2 * j]) + p);
+}
+
+template <int D>
+__device__ __forceinline__ double kernel_r2(double r2, const double* __restrict__ tab) {
+    if constexpr (D == 2)
+        return -0.5 * kInv2Pi * log_tab(r2, tab);
+    else
+        return kInv4Pi * rsqrt(r2);
+}                // sources per LDS tile
 constexpr int kLdw = 66;               // LDS row stride of the [j][rhs] tile (doubles)
 
 template <int D, int NB, int kRB>
 __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
                                                        const double* __restrict__ x,
-                                                       double* __restrict__ y) {
+                                                       double* __restrict__ y,
+                                                       const double* __restrict__ logtab) {
     __shared__ double sxj[D][kTJ];
     __shared__ double swx[kTJ * kLdw];
+    __shared__ double stab[2 * kLogTab];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const long N = P.N;
     const int r0 = blockIdx.y * 64;
     const long ibase = (long)blockIdx.x * (4 * kRB * 16) + wave * (kRB * 16);
     const int li = lane & 15, lk = lane >> 4;
+    if (D == 2)
+        for (int e = tid; e < 2 * kLogTab; e += kMvThreads) stab[e] = logtab[e];
 
     double xi[kRB][D];
     long irow[kRB];
@@ -94,7 +139,6 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
 #pragma unroll 1
         for (int ks = 0; ks < kTJ / 4; ++ks) {
             const int jj = ks * 4 + lk;
-            const long j = j0 + jj;
             double xj[D];
 #pragma unroll
             for (int t = 0; t < D; ++t) xj[t] = sxj[t][jj];
@@ -107,8 +151,13 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
                     const double dx = xi[rb][t] - xj[t];
                     r2 = fma(dx, dx, r2);
                 }
-                const double kv = laplace_from_r2<D>(r2);
-                a[rb] = (j == irow[rb]) ? 0.0 : kv;
+                if constexpr (D == 2) {
+                    // the pair i == j enters as K(kSelfR2); the epilogue removes it
+                    a[rb] = kernel_r2<D>(fmax(r2, kSelfR2), stab);
+                } else {
+                    const double kv = kernel_r2<D>(r2, stab);
+                    a[rb] = (j0 + jj == irow[rb]) ? 0.0 : kv;
+                }
             }
             double b[NB];
 #pragma unroll
@@ -128,44 +177,90 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
             const long i = ibase + rb * 16 + 4 * v + lk;
             if (i >= N) continue;
             const double bi = P.rs[i], di = P.diag[i];
+            // 2D: remove the self pair, which entered as K(kSelfR2) w_i x_i
+            const double selfw = (D == 2) ? kernel_r2<D>(kSelfR2, stab) * P.w[i] : 0.0;
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int r = r0 + nb * 16 + li;
                 if (r < nrhs) {
                     const long o = (long)r * N + i;
-                    y[o] = bi * acc[rb][nb][v] + di * x[o];
+                    const double xo = x[o];
+                    y[o] = bi * (acc[rb][nb][v] - selfw * xo) + di * xo;
                 }
             }
         }
     }
 }
 
-template <int D, int NB, int RB>
-static void matvec_launch(const ProblemView& P, int nrhs, const double* x, double* y, hipStream_t s) {
-    const int rows = 4 * RB * 16;
-    dim3 grid((int)((P.N + rows - 1) / rows), (nrhs + 63) / 64);
-    hipLaunchKernelGGL((k_matvec<D, NB, RB>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y);
+// log F_j and 1/F_j, F_j = 1 + j/128, uploaded once per device.
+static const double* log_table() {
+    static double* dtab[64] = {nullptr};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) return nullptr;
+    if (!dtab[dev]) {
+        double h[2 * kLogTab];
+        for (int j = 0; j < kLogTab; ++j) {
+            const double F = 1.0 + j / 128.0;
+            h[2 * j] = std::log(F);
+            h[2 * j + 1] = 1.0 / F;
+        }
+        double* d = nullptr;
+        if (hipMalloc(&d, sizeof(h)) != hipSuccess) return nullptr;
+        if (hipMemcpy(d, h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+        dtab[dev] = d;
+    }
+    return dtab[dev];
 }
 
-// Row blocks per wave: 4 while the accumulators (RB * NB * 4 doubles) leave room
-// for two waves per SIMD, else 2.
-template <int D>
-static void matvec_d(const ProblemView& P, int nrhs, const double* x, double* y, hipStream_t s) {
-    const int groups = (nrhs + 63) / 64;
-    const int nb = groups > 1 ? 4 : (nrhs + 15) / 16;
-    switch (nb) {
-        case 1: matvec_launch<D, 1, 4>(P, nrhs, x, y, s); break;
-        case 2: matvec_launch<D, 2, 4>(P, nrhs, x, y, s); break;
-        case 3: matvec_launch<D, 3, 2>(P, nrhs, x, y, s); break;
-        default: matvec_launch<D, 4, 2>(P, nrhs, x, y, s); break;
+bool matvec_prepare() { return log_table() != nullptr; }
+
+template <int D, int NB, int RB>
+static void matvec_launch(const ProblemView& P, int nrhs, const double* x, double* y, int max_blocks,
+                          hipStream_t s) {
+    const int rows = 4 * RB * 16;
+    int blocks = (int)((P.N + rows - 1) / rows);
+    if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
+    dim3 grid(blocks, (nrhs + 63) / 64);
+    hipLaunchKernelGGL((k_matvec<D, NB, RB>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y, log_table());
+}
+
+template <int D, int NB>
+static void matvec_rb(const ProblemView& P, int nrhs, const double* x, double* y, int rb, int max_blocks,
+                      hipStream_t s) {
+    switch (rb) {
+        case 1: matvec_launch<D, NB, 1>(P, nrhs, x, y, max_blocks, s); break;
+        case 2: matvec_launch<D, NB, 2>(P, nrhs, x, y, max_blocks, s); break;
+        default: matvec_launch<D, NB, 4>(P, nrhs, x, y, max_blocks, s); break;
     }
 }
 
-void launch_matvec(const ProblemView& P, int nrhs, const double* x, double* y, hipStream_t s) {
-    if (P.d == 2)
-        matvec_d<2>(P, nrhs, x, y, s);
-    else
-        matvec_d<3>(P, nrhs, x, y, s);
+// Right-hand-side blocks of 16 handled per launch column (the grid's y covers groups of 64).
+int matvec_nb(int nrhs) { return nrhs > 64 ? 4 : (nrhs + 15) / 16; }
+
+// Default row blocks per wave: 4 while the accumulators (RB * NB * 4 doubles)
+// leave room for three waves per SIMD, else 2.
+int matvec_default_rb(int nb) { return nb <= 2 ? 4 : 2; }
+
+void launch_matvec(const ProblemView& P, int nrhs, const double* x, double* y, int rb, int max_blocks,
+                   hipStream_t s) {
+    const int nb = matvec_nb(nrhs);
+    if (rb <= 0) rb = matvec_default_rb(nb);
+    if (P.d == 2) {
+        switch (nb) {
+            case 1: matvec_rb<2, 1>(P, nrhs, x, y, rb, max_blocks, s); break;
+            case 2: matvec_rb<2, 2>(P, nrhs, x, y, rb, max_blocks, s); break;
+            case 3: matvec_rb<2, 3>(P, nrhs, x, y, rb, max_blocks, s); break;
+            default: matvec_rb<2, 4>(P, nrhs, x, y, rb, max_blocks, s); break;
+        }
+    } else {
+        switch (nb) {
+            case 1: matvec_rb<3, 1>(P, nrhs, x, y, rb, max_blocks, s); break;
+            case 2: matvec_rb<3, 2>(P, nrhs, x, y, rb, max_blocks, s); break;
+            case 3: matvec_rb<3, 3>(P, nrhs, x, y, rb, max_blocks, s); break;
+            default: matvec_rb<3, 4>(P, nrhs, x, y, rb, max_blocks, s); break;
+        }
+    }
 }
 
 }  // namespace cbd

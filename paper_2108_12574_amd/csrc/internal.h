@@ -114,7 +114,13 @@ struct ChildRef {
 void launch_assemble(int d, int n, int grid, const double* b, const double* c, double* pts,
                      double* diag, double* w, double* rs, double a_self, double weight,
                      hipStream_t s);
-void launch_matvec(const ProblemView& P, int nrhs, const double* x, double* y, hipStream_t s);
+// rb: row blocks of 16 per wave (0: default); max_blocks > 0 limits the grid to the
+// first rows (used by the tile autotuner).
+void launch_matvec(const ProblemView& P, int nrhs, const double* x, double* y, int rb, int max_blocks,
+                   hipStream_t s);
+int matvec_nb(int nrhs);
+bool matvec_prepare();   // per-device constant tables of the matvec (call outside stream capture)
+int matvec_default_rb(int nb);
 
 template <typename R>
 void launch_proxy_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, const int* act,

@@ -285,3 +285,31 @@ def test_full_size_pcg_residual_sampled(cfg3, prec):
     for c in range(4):
         rms = np.sqrt(np.mean(res[:, c] ** 2))
         assert rms <= 1e-8 * np.linalg.norm(f[c]) / np.sqrt(O.N)
+
+
+@pytest.mark.parametrize("prec,flexible", [(0, False), (1, True)], ids=["fp64", "fp32_flexible"])
+def test_pcg_graph_replay_matches_eager(cfg1, prec, flexible):
+    # two captured graphs replayed every iteration, with host work and a
+    # synchronization between replays; the result equals the eager solve bitwise
+    P, O, part, opart, R = cfg1
+    F = cbd.Factor(P, part, tol=1e-8, n_pxy=64, precision=prec)
+    f = torch.tensor(synth.rhs(O.N, 3, seed=4), device=DEV)
+    s = torch.cuda.Stream(device=DEV)
+    with torch.cuda.stream(s):
+        ue, ie_, re_ = cbd.pcg_solve(P, F, f, tol=1e-10, maxit=200, flexible=flexible)
+        for rep in range(2):
+            ug, ig, rg = cbd.pcg_solve(P, F, f, tol=1e-10, maxit=200, flexible=flexible, graph=True)
+            s.synchronize()
+            assert ig == ie_ and rg == re_
+            assert torch.equal(ug, ue)
+    assert max(re_) <= 1e-10
+
+
+def test_autotune_matvec_keeps_results(cfg3):
+    P, O, part = cfg3
+    x = torch.tensor(synth.rhs(O.N, 64, seed=0), device=DEV)
+    y0 = P.matvec(x)
+    choice = P.autotune_matvec(64)
+    assert choice in (1, 2, 4)
+    y1 = P.matvec(x)
+    assert torch.allclose(y0, y1, rtol=1e-13, atol=1e-13 * y0.abs().max().item())
