@@ -24,6 +24,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "PCG solve time (s) & RS factor GFLOP/s at 2D 512^2, mixed vs FP64, rel res 1e-10"
+
+# The workloads (cell-centred grids, Laplace kernel, closed-form diagonal, PCG to 1e-10).
+# "512sq" is the measured configuration; the others are run for the design notes.
+WORKLOADS = {
+    "64sq": dict(d=2, n=64, m=16, mode="cbd", delta=1, leaf=0, tol=1e-8, npxy=64, nrhs=1,
+                 prec="fp64", coef=False, label="2D 64^2, CBD m=16, tol 1e-8, 1 RHS, FP64"),
+    "256sq": dict(d=2, n=256, m=4, mode="schwarz", delta=8, leaf=8, tol=1e-6, npxy=64, nrhs=1,
+                  prec="fp64", coef=False,
+                  label="2D 256^2, Schwarz 4x4 subdomains, overlap one 8x8 leaf, tol 1e-6, 1 RHS, FP64"),
+    "512sq": dict(d=2, n=512, m=64, mode="cbd", delta=1, leaf=0, tol=1e-6, npxy=64, nrhs=64,
+                  prec="fp32", coef=True,
+                  label="2D 512^2 (N=262144), b=c=1+0.5sin(2pi x1)cos(2pi x2), CBD m=64 delta=1, "
+                        "RS tol 1e-6, 64 proxy pts at 1.5 box sides, 64 RHS N(0,1) seed 0, PCG rel res 1e-10"),
+    "32cube": dict(d=3, n=32, m=8, mode="cbd", delta=1, leaf=0, tol=1e-6, npxy=256, nrhs=16,
+                   prec="fp32", coef=False,
+                   label="3D 32^3, CBD m=8 (8 subdomains), tol 1e-6, 256 proxy pts, 16 RHS, FP32 factors"),
+    "1024sq": dict(d=2, n=1024, m=128, mode="cbd", delta=1, leaf=0, tol=1e-6, npxy=64, nrhs=1,
+                   prec="fp32", coef=False,
+                   label="2D 1024^2 (N=1048576), CBD m=128, tol 1e-6, 1 RHS, FP32 factors with the rank predictor"),
+}
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 FP32_PEAK_TFLOPS = 157.3
 
@@ -45,14 +65,17 @@ def measured_traffic():
 
 def train_rank_predictor(cbd, dev):
     """Skeleton-rank MLP trained by the library's kernels on (features, rank) pairs
-    of the 64^2 (tol 1e-8), 256^2 Schwarz (tol 1e-6) and 512^2 (tol 1e-6) factorizations."""
+    of the 64^2 (tol 1e-8), 256^2 Schwarz (tol 1e-6) and 512^2 (tol 1e-6)
+    factorizations, plus a small 3D one (16^3, tol 1e-6)."""
     import numpy as np
     Xs, ks = [], []
-    for n, m, tol, mode, delta, leaf in [(64, 16, 1e-8, cbd.MODE_CBD, 1, 0),
-                                         (256, 4, 1e-6, cbd.MODE_SCHWARZ, 8, 8),
-                                         (512, 64, 1e-6, cbd.MODE_CBD, 1, 0)]:
-        Pt = cbd.Problem(2, n, device=dev)
-        Ft = cbd.Factor(Pt, cbd.Partition(Pt, m, delta, mode, leaf), tol=tol, n_pxy=64, precision=cbd.PREC_FP32)
+    for d, n, m, tol, mode, delta, leaf, npxy in [(2, 64, 16, 1e-8, cbd.MODE_CBD, 1, 0, 64),
+                                                  (2, 256, 4, 1e-6, cbd.MODE_SCHWARZ, 8, 8, 64),
+                                                  (2, 512, 64, 1e-6, cbd.MODE_CBD, 1, 0, 64),
+                                                  (3, 16, 4, 1e-6, cbd.MODE_CBD, 1, 0, 256)]:
+        Pt = cbd.Problem(d, n, device=dev)
+        Ft = cbd.Factor(Pt, cbd.Partition(Pt, m, delta, mode, leaf), tol=tol, n_pxy=npxy,
+                        precision=cbd.PREC_FP32)
         X, k = Ft.all_features()
         Xs.append(X)
         ks.append(k)
@@ -71,10 +94,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--m", type=int, default=64)
-    ap.add_argument("--nrhs", type=int, default=64)
-    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--workload", default="512sq", choices=sorted(WORKLOADS))
     ap.add_argument("--fp64-cols", type=int, default=2,
                     help="columns solved one at a time to time the plain FP64 form")
     ap.add_argument("--cpu-rows", type=int, default=192,
@@ -92,12 +112,15 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
-    n, nrhs = args.n, args.nrhs
-    N = n * n
+    W = WORKLOADS[args.workload]
+    d, n, nrhs, tol, npxy = W["d"], W["n"], W["nrhs"], W["tol"], W["npxy"]
+    mode = {"cbd": cbd.MODE_CBD, "schwarz": cbd.MODE_SCHWARZ}[W["mode"]]
+    prec = {"fp32": cbd.PREC_FP32, "fp64": cbd.PREC_FP64}[W["prec"]]
+    N = n ** d
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    coef = torch.tensor(synth.coef_smooth(2, n))
-    P = cbd.Problem(2, n, b=coef, c=coef, device=dev)
-    part = cbd.Partition(P, args.m, 1, cbd.MODE_CBD, 0)
+    coef = torch.tensor(synth.coef_smooth(d, n)) if W["coef"] else None
+    P = cbd.Problem(d, n, b=coef, c=coef, device=dev)
+    part = cbd.Partition(P, W["m"], W["delta"], mode, W["leaf"])
     F_rhs = torch.tensor(synth.rhs(N, nrhs, seed=0), device=dev)
     torch.cuda.synchronize()
 
@@ -115,8 +138,7 @@ def main():
 
     def step():
         t0 = time.perf_counter()
-        fac = cbd.Factor(P, part, tol=args.tol, n_pxy=64, proxy_ratio=1.5, precision=cbd.PREC_FP32,
-                         mlp=mlp)
+        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         u, its, rr = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200)
@@ -150,7 +172,7 @@ def main():
     # the same factorization without the predictor
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fac_nm = cbd.Factor(P, part, tol=args.tol, n_pxy=64, proxy_ratio=1.5, precision=cbd.PREC_FP32)
+    fac_nm = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec)
     torch.cuda.synchronize()
     factor_nm_s = time.perf_counter() - t0
     sched_nm = fac_nm.schedule()
@@ -166,7 +188,7 @@ def main():
     # plain FP64 form: FP64 factors, right-hand sides one at a time
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fac64 = cbd.Factor(P, part, tol=args.tol, n_pxy=64, proxy_ratio=1.5, precision=cbd.PREC_FP64)
+    fac64 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_FP64)
     torch.cuda.synchronize()
     f64_factor = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -182,7 +204,7 @@ def main():
     cpu = None
     if args.cpu_rows > 0:
         from oracle import cmatvec, ie
-        O = ie.Problem(2, n, b=coef.numpy(), c=coef.numpy())
+        O = ie.Problem(d, n, b=None if coef is None else coef.numpy(), c=None if coef is None else coef.numpy())
         rows = np.random.default_rng(0).choice(N, args.cpu_rows, replace=False)
         X = F_rhs.cpu().numpy().T.copy()
         t0 = time.perf_counter()
@@ -208,12 +230,11 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 (matvec, PCG, ID) + f32 (RS elimination, factor storage, apply)",
+        "dtype": ("f64 (matvec, PCG, ID) + f32 (RS elimination, factor storage, apply)"
+                  if prec == cbd.PREC_FP32 else "f64"),
         "data": "synthetic",
-        "config": {"workload": "2D Laplace IE %d^2 (N=%d), b=c=1+0.5sin(2pi x1)cos(2pi x2), CBD "
-                               "m=%d delta=1, RS tol %g, 64 proxy pts at 1.5 box sides, %d RHS "
-                               "N(0,1) seed 0, PCG rel res 1e-10" % (n, N, args.m, args.tol, nrhs),
-                   "global_batch": nrhs, "parallelism": "single GPU"},
+        "config": {"workload": W["label"], "name": args.workload, "global_batch": nrhs,
+                   "parallelism": "single GPU"},
         "factor_s": factor_s,
         "factor_gflops": st["flops"] / factor_s / 1e9,
         "factor_flops": st["flops"],
@@ -237,7 +258,7 @@ def main():
         "roofline": {"kernel": "kernel_matvec (FP64, %d RHS)" % nrhs, "bound": "mfma",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic() if (n, nrhs) == (512, 64) else None,
+                     "traffic": measured_traffic() if args.workload == "512sq" else None,
                      "work": "2 N^2 nrhs FP64 flops per launch on FP64 MFMA (the N^2 kernel "
                              "evaluations run on the VALU and are not counted)"},
         "cpu_baseline": cpu,

@@ -585,6 +585,7 @@ struct cbd_factor_s {
     size_t bytes = 0;
     double flops = 0.0;
     DevBuf v;                    // local vectors of the apply
+    DevBuf t1, t2;               // root-level buffers of the apply for large roots
     ~cbd_factor_s() {
         for (auto& l : levels) l.release();
     }
@@ -650,7 +651,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
     // and the ranks inflate.  Elimination, storage and apply use R.
     const double tie = 1e-10;
     std::vector<double> hdir = proxy_dirs(d, std::max(npxy, 1));
-    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf, mlpbuf;
+    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf, mlpbuf, listbuf;
     if ((rc = dirbuf.ensure(sizeof(double) * hdir.size()))) return rc;
     HIPCHK(hipMemcpyAsync(dirbuf.p, hdir.data(), sizeof(double) * hdir.size(), hipMemcpyHostToDevice, s));
     if ((rc = statbuf.ensure(sizeof(int)))) return rc;
@@ -788,7 +789,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             const long np = M.np;
             o_act += np;
             o_near += M.nnear;
-            o_y += std::max((long)M.m * np, np * np + 16 * np);   // proxy matrix, or elimination scratch
+            o_y += std::max((long)M.m * np, np * np + kScratchCols * np);   // proxy matrix, or elimination scratch
             o_app += np * np;
             o_f += np * np;
             o_ch += (long)chl[B].size();
@@ -924,7 +925,36 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         }
         launch_box_matrix<R>(PV, L.nbox, L.d_meta, L.d_act, Q->d_cidx,
                              o_ch ? (const ChildRef<R>*)chbuf.p : nullptr, App, s);
-        launch_eliminate<R>(L.nbox, L.d_meta, L.d_perm, L.d_k, App, T64, Wk, FF, d_status, s);
+        // boxes with many DOFs: Cholesky and inverse as multi-workgroup launch sequences
+        std::vector<int> small, big;
+        int np_big = 0;
+        for (int B = 0; B < L.nbox; ++B) {
+            if (L.meta[B].np >= kBigBox) {
+                big.push_back(B);
+                np_big = std::max(np_big, L.meta[B].np);
+            } else {
+                small.push_back(B);
+            }
+        }
+        if (big.empty()) {
+            launch_eliminate<R>(L.nbox, L.d_meta, nullptr, 0, L.d_perm, L.d_k, App, T64, Wk, FF, d_status, s);
+        } else {
+            if ((rc = listbuf.ensure(sizeof(int) * L.nbox))) return rc;
+            int* d_small = (int*)listbuf.p;
+            int* d_big = d_small + small.size();
+            std::vector<int> lists(small);
+            lists.insert(lists.end(), big.begin(), big.end());
+            HIPCHK(hipMemcpyAsync(d_small, lists.data(), sizeof(int) * lists.size(), hipMemcpyHostToDevice, s));
+            launch_eliminate<R>((int)small.size(), L.d_meta, d_small, 0, L.d_perm, L.d_k, App, T64, Wk, FF,
+                                d_status, s);
+            launch_eliminate<R>((int)big.size(), L.d_meta, d_big, 1, L.d_perm, L.d_k, App, T64, Wk, FF,
+                                d_status, s);
+            launch_big_cholesky_inverse<R>((int)big.size(), np_big, L.d_meta, d_big, L.d_k, Wk, FF, d_status, s);
+            launch_eliminate<R>((int)big.size(), L.d_meta, d_big, 2, L.d_perm, L.d_k, App, T64, Wk, FF,
+                                d_status, s);
+            HIPCHK(hipStreamSynchronize(s));   // `lists` is read by the copy above
+            F->host_syncs++;
+        }
         HIPCHK(hipGetLastError());
         L.k.resize(L.nbox);
         L.sr.resize(o_act);
@@ -1069,9 +1099,19 @@ extern "C" int rs_factor_root(cbd_factor f, int i, int* S, int* idx, double* Gin
     return rc;
 }
 
-// Allocate the apply's local vectors for nrhs columns ahead of time (stream capture).
+// Large root boxes are applied by GEMMs through global buffers instead of LDS.
+static bool root_uses_gemm(const Level& L) { return L.root && L.np_max >= kBigBox; }
+
+// Allocate the apply's buffers for nrhs columns ahead of time (stream capture).
 static int apply_prepare(cbd_factor f, int nrhs) {
-    return f->v.ensure(f->esize * (size_t)f->part->total * nrhs);
+    int rc = f->v.ensure(f->esize * (size_t)f->part->total * nrhs);
+    if (rc) return rc;
+    const Level& R = f->levels.back();
+    if (root_uses_gemm(R)) {
+        const size_t b = f->esize * (size_t)R.nbox * R.np_max * nrhs;
+        if ((rc = f->t1.ensure(b)) || (rc = f->t2.ensure(b))) return rc;
+    }
+    return CBD_OK;
 }
 
 template <typename R>
@@ -1081,16 +1121,22 @@ static int apply_impl(cbd_factor f, int nrhs, const double* r, double* z, hipStr
     if (rc) return rc;
     R* v = (R*)f->v.p;
     for (const Level& L : f->levels)
-        if ((size_t)2 * L.np_max * sizeof(R) > 65536)
+        if (!root_uses_gemm(L) && (size_t)2 * L.np_max * sizeof(R) > 65536)
             return fail(CBD_EARG, "rs_apply: box of " + std::to_string(L.np_max) + " DOFs exceeds the LDS of the apply kernel");
     launch_gather<R>(r, f->prob->N, nrhs, Q->d_cidx, Q->total, v, s);
     const int nl = (int)f->levels.size();
     for (int l = 0; l < nl; ++l) {
         const Level& L = f->levels[l];
+        if (root_uses_gemm(L)) {   // forward and backward root solve at once
+            launch_root_apply<R>(L.nbox, L.np_max, 0, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs,
+                                 (R*)f->t1.p, (R*)f->t2.p, s);
+            continue;
+        }
         launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, true, s);
     }
     for (int l = nl - 1; l >= 0; --l) {
         const Level& L = f->levels[l];
+        if (root_uses_gemm(L)) continue;
         launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, false, s);
     }
     launch_scatter<R>(v, nrhs, Q->d_inv_ptr, Q->d_inv_slot, f->prob->N, z, s);

@@ -148,9 +148,22 @@ void launch_qr_finish(int nbox, const BoxMeta* meta, double* Y, const QrState& s
 template <typename R>
 void launch_box_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, const int* act,
                        const int* cidx, const ChildRef<R>* ch, R* App, hipStream_t s);
+// phase 0: whole elimination per box; 1: up to B_rr; 2: E and B_ss (list: box indices or NULL)
 template <typename R>
-void launch_eliminate(int nbox, const BoxMeta* meta, const int* perm, const int* k,
-                      const R* App, const double* T64, R* Wk, R* F, int* status, hipStream_t s);
+void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, int phase, const int* perm,
+                      const int* k, const R* App, const double* T64, R* Wk, R* F, int* status,
+                      hipStream_t s);
+// multi-workgroup blocked Cholesky of B_rr and G^{-1} for the boxes in list (after phase 1)
+template <typename R>
+void launch_big_cholesky_inverse(int nbig, int nr_max, const BoxMeta* meta, const int* list, const int* k,
+                                 R* Wk, R* F, int* status, hipStream_t s);
+// v_root <- G^{-1} G^{-T} v_root for every (k = 0) box of a root level, via buffers t1, t2
+// of nbox * np_max * nrhs elements each
+template <typename R>
+void launch_root_apply(int nbox, int np_max, int unused, const BoxMeta* meta, const int* sr, const int* k,
+                       const R* F, R* v, int nrhs, R* t1, R* t2, hipStream_t s);
+constexpr int kBigBox = 512;        // boxes with at least this many DOFs use the multi-workgroup path
+constexpr int kScratchCols = 64;    // elimination scratch per box: np^2 + kScratchCols * np
 
 template <typename R>
 void launch_gather(const double* r, long N, int nrhs, const int* cidx, long total, R* v,

@@ -582,73 +582,256 @@ __device__ void wg_triangular_inverse(int n, const R* G, int ldg, R* X, R* W) {
 // B_rr is formed and factored on its upper triangle (it is symmetric in exact
 // arithmetic).  The factor slot (np x np elements) receives [T | E | G^{-1} | B_ss].
 // A root box has k = 0: its slot receives G^{-1} of the whole box matrix.
-// Scratch per box: np^2 + kBlk*np elements at its y offset.
+// Scratch per box: np^2 + kBig*np elements at its y offset.
+//
+// phase 0: everything in one workgroup (boxes of moderate size);
+// phase 1: up to B_rr (the large boxes, whose Cholesky and inverse then run as
+//          multi-workgroup launch sequences); phase 2: E and B_ss afterwards.
+constexpr int kBig = 64;   // block size of the multi-workgroup Cholesky / inverse
+
+template <typename R>
+struct ElimView {
+    int k, nr, np;
+    R *Ass, *Bsr, *Brr, *W, *T, *E, *Gi, *Bss;
+};
+
+template <typename R>
+__device__ __forceinline__ ElimView<R> elim_view(const BoxMeta& M, int k, R* Wk, R* F) {
+    ElimView<R> v;
+    v.k = k;
+    v.np = M.np;
+    v.nr = M.np - k;
+    v.Ass = Wk + M.y;
+    v.Bsr = v.Ass + (long)k * k;
+    v.Brr = v.Bsr + (long)k * v.nr;
+    v.W = v.Brr + (long)v.nr * v.nr;
+    v.T = F + M.f;
+    v.E = v.T + (long)k * v.nr;
+    v.Gi = v.E + (long)k * v.nr;
+    v.Bss = v.Gi + (long)v.nr * v.nr;
+    return v;
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restrict__ meta,
+                                                        const int* __restrict__ list,
                                                         const int* __restrict__ perm,
                                                         const int* __restrict__ kk,
                                                         const R* __restrict__ App,
                                                         const double* __restrict__ T64,
                                                         R* __restrict__ Wk, R* __restrict__ F,
-                                                        int* __restrict__ status) {
+                                                        int* __restrict__ status, int phase) {
     __shared__ int s_fail;
-    const BoxMeta M = meta[blockIdx.x];
-    const int np = M.np;
-    const int k = kk[blockIdx.x];
-    const int nr = np - k;
+    const int b = list ? list[blockIdx.x] : blockIdx.x;
+    const BoxMeta M = meta[b];
+    const ElimView<R> V = elim_view<R>(M, kk[b], Wk, F);
+    const int np = V.np, k = V.k, nr = V.nr;
     const int tid = threadIdx.x;
-    const int* pv = perm + M.act;
-    const R* A = App + M.app;
-    R* Ass = Wk + M.y;
-    R* Bsr = Ass + (long)k * k;
-    R* Brr = Bsr + (long)k * nr;
-    R* W = Brr + (long)nr * nr;
-    R* Fb = F + M.f;
-    R* T = Fb;
-    R* E = Fb + (long)k * nr;
-    R* Gi = E + (long)k * nr;
-    R* Bss = Gi + (long)nr * nr;
+    if (phase != 2) {
+        const int* pv = perm + M.act;
+        const R* A = App + M.app;
+        for (long e = tid; e < (long)k * nr; e += kThreads) V.T[e] = (R)T64[M.f + e];
+        for (long e = tid; e < (long)k * k; e += kThreads) {
+            const int a = (int)(e % k), c = (int)(e / k);
+            V.Ass[e] = A[pv[a] + (long)pv[c] * np];
+        }
+        for (long e = tid; e < (long)k * nr; e += kThreads) {
+            const int a = (int)(e % k), i = (int)(e / k);
+            V.Bsr[e] = A[pv[a] + (long)pv[k + i] * np];
+        }
+        for (long e = tid; e < (long)nr * nr; e += kThreads) {
+            const int i = (int)(e % nr), c = (int)(e / nr);
+            V.Brr[e] = A[pv[k + i] + (long)pv[k + c] * np];
+            if (phase == 1 && i > c) V.Gi[e] = (R)0;   // lower triangle of G^{-1}
+        }
+        if (tid == 0) s_fail = 0;
+        __syncthreads();
+        if (k > 0 && nr > 0) {
+            wg_gemm<R>(nr, nr, k, (R)-1, V.T, k, true, V.Bsr, k, false, (R)1, V.Brr, nr, true);   // - T^T A_sr
+            wg_gemm<R>(k, nr, k, (R)-1, V.Ass, k, false, V.T, k, false, (R)1, V.Bsr, k);          // B_sr
+            wg_gemm<R>(nr, nr, k, (R)-1, V.Bsr, k, true, V.T, k, false, (R)1, V.Brr, nr, true);   // - B_sr^T T
+        }
+        if (phase == 1) return;
+        if (!wg_cholesky_upper<R>(nr, V.Brr, nr, &s_fail)) {
+            if (tid == 0) status[0] = b + 1;
+            return;
+        }
+        wg_triangular_inverse<R>(nr, V.Brr, nr, V.Gi, V.W);
+    }
+    if (k > 0) {
+        wg_gemm<R>(k, nr, nr, (R)1, V.Bsr, k, false, V.Gi, nr, false, (R)0, V.E, k);     // E = B_sr G^{-1}
+        for (long e = tid; e < (long)k * k; e += kThreads) V.Bss[e] = V.Ass[e];
+        __syncthreads();
+        wg_gemm<R>(k, k, nr, (R)-1, V.E, k, false, V.E, k, true, (R)1, V.Bss, k);        // B_ss = A_ss - E E^T
+    }
+}
 
-    for (long e = tid; e < (long)k * nr; e += kThreads) T[e] = (R)T64[M.f + e];
-    for (long e = tid; e < (long)k * k; e += kThreads) {
-        const int a = (int)(e % k), c = (int)(e / k);
-        Ass[e] = A[pv[a] + (long)pv[c] * np];
-    }
-    for (long e = tid; e < (long)k * nr; e += kThreads) {
-        const int a = (int)(e % k), i = (int)(e / k);
-        Bsr[e] = A[pv[a] + (long)pv[k + i] * np];
-    }
-    for (long e = tid; e < (long)nr * nr; e += kThreads) {
-        const int i = (int)(e % nr), c = (int)(e / nr);
-        Brr[e] = A[pv[k + i] + (long)pv[k + c] * np];
+// Multi-workgroup blocked Cholesky of B_rr (upper, in place) and G^{-1}, for the
+// large boxes in `list`; block column J of width kBig per launch step.
+// Diagonal block: Cholesky and inverse in LDS (one workgroup per box); the
+// inverse goes to the diagonal block of G^{-1}.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_bchol_diag(const BoxMeta* __restrict__ meta,
+                                                         const int* __restrict__ list,
+                                                         const int* __restrict__ kk, R* __restrict__ Wk,
+                                                         R* __restrict__ F, int J, int* __restrict__ status) {
+    __shared__ R sA[kBig][kBig + 1];
+    __shared__ R sZ[kBig][kBig + 1];
+    __shared__ int s_fail;
+    const int b = list[blockIdx.x];
+    const ElimView<R> V = elim_view<R>(meta[b], kk[b], Wk, F);
+    const int nr = V.nr;
+    if (J >= nr) return;
+    const int jb = min(kBig, nr - J), tid = threadIdx.x;
+    for (int e = tid; e < jb * jb; e += kThreads) {
+        const int a = e % jb, c = e / jb;
+        sA[a][c] = V.Brr[(J + a) + (long)(J + c) * nr];
     }
     if (tid == 0) s_fail = 0;
     __syncthreads();
-
-    if (k > 0 && nr > 0) {
-        wg_gemm<R>(nr, nr, k, (R)-1, T, k, true, Bsr, k, false, (R)1, Brr, nr, true);   // - T^T A_sr
-        wg_gemm<R>(k, nr, k, (R)-1, Ass, k, false, T, k, false, (R)1, Bsr, k);          // B_sr
-        wg_gemm<R>(nr, nr, k, (R)-1, Bsr, k, true, T, k, false, (R)1, Brr, nr, true);   // - B_sr^T T
+    for (int j = 0; j < jb; ++j) {
+        if (tid == 0) {
+            const R d = sA[j][j];
+            if (!(d > (R)0)) s_fail = 1;
+            else sA[j][j] = sqrt(d);
+        }
+        __syncthreads();
+        if (s_fail) break;
+        for (int c = j + 1 + tid; c < jb; c += kThreads) sA[j][c] /= sA[j][j];
+        __syncthreads();
+        const int rem = jb - j - 1;
+        for (int e = tid; e < rem * rem; e += kThreads) {
+            const int a = j + 1 + e % rem, c = j + 1 + e / rem;
+            if (a <= c) sA[a][c] -= sA[j][a] * sA[j][c];
+        }
+        __syncthreads();
     }
-    if (!wg_cholesky_upper<R>(nr, Brr, nr, &s_fail)) {
-        if (tid == 0) status[0] = blockIdx.x + 1;
+    if (s_fail) {
+        if (tid == 0) status[0] = b + 1;
         return;
     }
-    wg_triangular_inverse<R>(nr, Brr, nr, Gi, W);
-    if (k > 0) {
-        wg_gemm<R>(k, nr, nr, (R)1, Bsr, k, false, Gi, nr, false, (R)0, E, k);           // E = B_sr G^{-1}
-        for (long e = tid; e < (long)k * k; e += kThreads) Bss[e] = Ass[e];
-        __syncthreads();
-        wg_gemm<R>(k, k, nr, (R)-1, E, k, false, E, k, true, (R)1, Bss, k);              // B_ss = A_ss - E E^T
+    // Z = G_JJ^{-1}, column c by back substitution
+    for (int c = tid; c < jb; c += kThreads) {
+        for (int a = jb - 1; a > c; --a) sZ[a][c] = (R)0;
+        sZ[c][c] = (R)1 / sA[c][c];
+        for (int a = c - 1; a >= 0; --a) {
+            R s = 0;
+            for (int q = a + 1; q <= c; ++q) s += sA[a][q] * sZ[q][c];
+            sZ[a][c] = -s / sA[a][a];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < jb * jb; e += kThreads) {
+        const int a = e % jb, c = e / jb;
+        if (a <= c) V.Brr[(J + a) + (long)(J + c) * nr] = sA[a][c];
+        V.Gi[(J + a) + (long)(J + c) * nr] = sZ[a][c];
+    }
+}
+
+// Panel rows J..J+jb of G right of the block: G_J,c = Z^T A_J,c (Z = G_JJ^{-1}),
+// kPanel columns per workgroup (each workgroup reads and writes only its columns).
+constexpr int kPanel = 128;
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_bchol_panel(const BoxMeta* __restrict__ meta,
+                                                          const int* __restrict__ list,
+                                                          const int* __restrict__ kk, R* __restrict__ Wk,
+                                                          R* __restrict__ F, int J) {
+    const int b = list[blockIdx.x];
+    const ElimView<R> V = elim_view<R>(meta[b], kk[b], Wk, F);
+    const int nr = V.nr;
+    if (J >= nr) return;
+    const int jb = min(kBig, nr - J);
+    const int c0 = J + jb + blockIdx.y * kPanel;
+    if (c0 >= nr) return;
+    const int nc = min(kPanel, nr - c0);
+    R* tmp = V.W + (long)c0 * kBig;   // jb x nc, column-major with ld kBig (columns private to this workgroup)
+    wg_gemm<R>(jb, nc, jb, (R)1, V.Gi + J + (long)J * nr, nr, true, V.Brr + J + (long)c0 * nr, nr, false, (R)0,
+               tmp, kBig);
+    for (int e = threadIdx.x; e < jb * nc; e += kThreads) {
+        const int a = e % jb, c = e / jb;
+        V.Brr[(J + a) + (long)(c0 + c) * nr] = tmp[a + (long)c * kBig];
+    }
+}
+
+// Trailing update of the upper triangle: S_{rows,cols} -= G_{J,rows}^T G_{J,cols}, one 64 x 64 tile per workgroup.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_bchol_update(const BoxMeta* __restrict__ meta,
+                                                           const int* __restrict__ list,
+                                                           const int* __restrict__ kk, R* __restrict__ Wk,
+                                                           R* __restrict__ F, int J) {
+    const int b = list[blockIdx.x];
+    const ElimView<R> V = elim_view<R>(meta[b], kk[b], Wk, F);
+    const int nr = V.nr;
+    if (J >= nr) return;
+    const int jb = min(kBig, nr - J);
+    const int base = J + jb, rem = nr - base;
+    if (rem <= 0) return;
+    const int tiles = (rem + 63) / 64;
+    const long t = blockIdx.y;
+    if (t >= (long)tiles * (tiles + 1) / 2) return;
+    // t -> (ti <= tj): tj = floor((sqrt(8t + 1) - 1) / 2)
+    int tj = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((long)(tj + 1) * (tj + 2) / 2 <= t) ++tj;
+    while ((long)tj * (tj + 1) / 2 > t) --tj;
+    const int ti = (int)(t - (long)tj * (tj + 1) / 2);
+    const int r0 = base + ti * 64, q0 = base + tj * 64;
+    const R* P = V.Brr + J;   // panel rows J.., column c at P + c*nr
+    wg_gemm<R>(min(64, nr - r0), min(64, nr - q0), jb, (R)-1, P + (long)r0 * nr, nr, true, P + (long)q0 * nr, nr,
+               false, (R)1, V.Brr + r0 + (long)q0 * nr, nr, ti == tj);
+}
+
+// Inverse, block column J > 0: V = G_{0:J,J} Z_J (into W), then
+// X_{rows,J} = -X_{rows,rows0:J} V_{rows0:J}, 64 rows per workgroup.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_binv(const BoxMeta* __restrict__ meta,
+                                                   const int* __restrict__ list, const int* __restrict__ kk,
+                                                   R* __restrict__ Wk, R* __restrict__ F, int J, int stage) {
+    const int b = list[blockIdx.x];
+    const ElimView<R> V = elim_view<R>(meta[b], kk[b], Wk, F);
+    const int nr = V.nr;
+    if (J >= nr) return;
+    const int jb = min(kBig, nr - J);
+    const int r0 = blockIdx.y * 64;
+    if (r0 >= J) return;
+    const int rows = min(64, J - r0);
+    if (stage == 0) {
+        wg_gemm<R>(rows, jb, jb, (R)1, V.Brr + r0 + (long)J * nr, nr, false, V.Gi + J + (long)J * nr, nr, false,
+                   (R)0, V.W + r0, nr);
+    } else {
+        wg_gemm<R>(rows, jb, J - r0, (R)-1, V.Gi + r0 + (long)r0 * nr, nr, false, V.W + r0, nr, false, (R)0,
+                   V.Gi + r0 + (long)J * nr, nr);
     }
 }
 
 template <typename R>
-void launch_eliminate(int nbox, const BoxMeta* meta, const int* perm, const int* k, const R* App,
-                      const double* T64, R* Wk, R* F, int* status, hipStream_t s) {
+void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, int phase, const int* perm, const int* k,
+                      const R* App, const double* T64, R* Wk, R* F, int* status, hipStream_t s) {
     if (nbox == 0) return;
-    hipLaunchKernelGGL((k_eliminate<R>), dim3(nbox), dim3(kThreads), 0, s, meta, perm, k, App, T64, Wk,
-                       F, status);
+    hipLaunchKernelGGL((k_eliminate<R>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App, T64, Wk,
+                       F, status, phase);
+}
+
+template <typename R>
+void launch_big_cholesky_inverse(int nbig, int nr_max, const BoxMeta* meta, const int* list, const int* k,
+                                 R* Wk, R* F, int* status, hipStream_t s) {
+    if (nbig == 0) return;
+    for (int J = 0; J < nr_max; J += kBig) {
+        hipLaunchKernelGGL((k_bchol_diag<R>), dim3(nbig), dim3(kThreads), 0, s, meta, list, k, Wk, F, J, status);
+        const int rem = nr_max - J - kBig;
+        if (rem > 0) {
+            hipLaunchKernelGGL((k_bchol_panel<R>), dim3(nbig, (rem + kPanel - 1) / kPanel), dim3(kThreads), 0, s,
+                               meta, list, k, Wk, F, J);
+            const int tiles = (rem + 63) / 64;
+            hipLaunchKernelGGL((k_bchol_update<R>), dim3(nbig, tiles * (tiles + 1) / 2), dim3(kThreads), 0, s,
+                               meta, list, k, Wk, F, J);
+        }
+    }
+    for (int J = kBig; J < nr_max; J += kBig) {
+        const int chunks = (J + 63) / 64;
+        hipLaunchKernelGGL((k_binv<R>), dim3(nbig, chunks), dim3(kThreads), 0, s, meta, list, k, Wk, F, J, 0);
+        hipLaunchKernelGGL((k_binv<R>), dim3(nbig, chunks), dim3(kThreads), 0, s, meta, list, k, Wk, F, J, 1);
+    }
 }
 
 // ---- apply ------------------------------------------------------------------
@@ -773,6 +956,59 @@ void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int*
                        forward ? 1 : 0);
 }
 
+// Root boxes too large for the LDS apply: v_root <- G^{-1} G^{-T} v_root as two
+// MFMA GEMMs over 64-row chunks, through box-contiguous buffers (column-major,
+// ld np, one region of `ts` elements per box).
+template <typename R>
+__global__ void k_root_move(const BoxMeta* __restrict__ meta, const int* __restrict__ sr, R* __restrict__ v,
+                            int nrhs, R* __restrict__ t, long ts, int to_buffer) {
+    const int b = blockIdx.x;
+    const BoxMeta M = meta[b];
+    const long n = (long)M.np * nrhs;
+    for (long e = (long)blockIdx.y * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.y * blockDim.x) {
+        const int j = (int)(e % M.np), c = (int)(e / M.np);
+        R* vv = v + (long)sr[M.act + j] * nrhs + c;
+        R* tt = t + b * ts + j + (long)c * M.np;
+        if (to_buffer) *tt = *vv;
+        else *vv = *tt;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_root_trmm(const BoxMeta* __restrict__ meta, const R* __restrict__ F,
+                                                        int nrhs, const R* __restrict__ in, R* __restrict__ out,
+                                                        long ts, int transpose) {
+    const int b = blockIdx.x;
+    const BoxMeta M = meta[b];
+    const int n = M.np;
+    const int r0 = blockIdx.y * 64;
+    if (r0 >= n) return;
+    const int rows = min(64, n - r0);
+    const R* Gi = F + M.f;
+    const R* x = in + b * ts;
+    R* y = out + b * ts;
+    if (transpose) {   // y_rows = (G^{-1})^T x: entries G^{-1}[j][i], j <= i
+        const int K = min(n, r0 + 64);
+        wg_gemm<R>(rows, nrhs, K, (R)1, Gi + (long)r0 * n, n, true, x, n, false, (R)0, y + r0, n);
+    } else {           // y_rows = G^{-1} x: entries G^{-1}[i][j], j >= i
+        wg_gemm<R>(rows, nrhs, n - r0, (R)1, Gi + r0 + (long)r0 * n, n, false, x + r0, n, false, (R)0, y + r0, n);
+    }
+}
+
+template <typename R>
+void launch_root_apply(int nbox, int np_max, int unused, const BoxMeta* meta, const int* sr, const int* k,
+                       const R* F, R* v, int nrhs, R* t1, R* t2, hipStream_t s) {
+    (void)unused;
+    (void)k;
+    if (nbox == 0) return;
+    const long ts = (long)np_max * nrhs;
+    const int chunks = (np_max + 63) / 64;
+    hipLaunchKernelGGL((k_root_move<R>), dim3(nbox, 64), dim3(256), 0, s, meta, sr, v, nrhs, t1, ts, 1);
+    hipLaunchKernelGGL((k_root_trmm<R>), dim3(nbox, chunks), dim3(kThreads), 0, s, meta, F, nrhs, t1, t2, ts, 1);
+    hipLaunchKernelGGL((k_root_trmm<R>), dim3(nbox, chunks), dim3(kThreads), 0, s, meta, F, nrhs, t2, t1, ts, 0);
+    hipLaunchKernelGGL((k_root_move<R>), dim3(nbox, 64), dim3(256), 0, s, meta, sr, v, nrhs, t1, ts, 0);
+}
+
 // explicit instantiations
 template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta*, const int*,
                                           const int*, const int*, const double*, int, double*,
@@ -780,8 +1016,12 @@ template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta
 #define CBD_INST(R)                                                                                 \
     template void launch_box_matrix<R>(const ProblemView&, int, const BoxMeta*, const int*,         \
                                        const int*, const ChildRef<R>*, R*, hipStream_t);            \
-    template void launch_eliminate<R>(int, const BoxMeta*, const int*, const int*, const R*,       \
-                                      const double*, R*, R*, int*, hipStream_t);                    \
+    template void launch_eliminate<R>(int, const BoxMeta*, const int*, int, const int*, const int*, \
+                                      const R*, const double*, R*, R*, int*, hipStream_t);          \
+    template void launch_big_cholesky_inverse<R>(int, int, const BoxMeta*, const int*, const int*, R*, \
+                                                 R*, int*, hipStream_t);                            \
+    template void launch_root_apply<R>(int, int, int, const BoxMeta*, const int*, const int*, const R*, \
+                                       R*, int, R*, R*, hipStream_t);                               \
     template void launch_gather<R>(const double*, long, int, const int*, long, R*, hipStream_t);   \
     template void launch_scatter<R>(const R*, int, const int*, const int*, long, double*,          \
                                     hipStream_t);                                                   \

@@ -313,3 +313,36 @@ def test_autotune_matvec_keeps_results(cfg3):
     assert choice in (1, 2, 4)
     y1 = P.matvec(x)
     assert torch.allclose(y0, y1, rtol=1e-13, atol=1e-13 * y0.abs().max().item())
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_large_boxes_exact_subsolves(prec):
+    # subdomains of 625 points: Cholesky and inverse by the multi-workgroup path
+    # (blocked, batched over boxes), roots applied by GEMMs
+    P, O = gpu_problem(2, 48)
+    part = cbd.Partition(P, 2, 1, cbd.MODE_CBD, 0)
+    F = cbd.Factor(P, part, exact=True, precision=prec)
+    assert min(F.stats()["S"]) >= 512
+    E = precond.ExactPreconditioner(O, dd.Partition(2, 48, 2, 1, dd.CBD))
+    r = synth.rhs(O.N, 5, seed=6)
+    z = F.apply(torch.tensor(r, device=DEV)).cpu().numpy()
+    assert rel(z, E.apply(r.T).T) <= (1e-11 if prec == 0 else 2e-4)
+
+
+def test_large_roots_match_oracle():
+    # 128^2, CBD m = 32, tol 1e-8: roots above 512 DOFs go through the multi-workgroup path
+    P, O = gpu_problem(2, 128)
+    part = cbd.Partition(P, 32, 1, cbd.MODE_CBD, 0)
+    opart = dd.Partition(2, 128, 32, 1, dd.CBD)
+    R = rs.RSPreconditioner(O, opart, 1e-8, n_pxy=64)
+    F = cbd.Factor(P, part, tol=1e-8, n_pxy=64)
+    S = F.stats()["S"]
+    print("roots", S, flush=True)
+    assert min(S) >= 512
+    for i in range(4):
+        idx, Gi = F.root(i)
+        assert np.array_equal(idx, R.subs[i].root)
+        assert rel(Gi, np.linalg.inv(R.subs[i].root_G)) <= 1e-8
+    r = synth.rhs(O.N, 3, seed=1)
+    z = F.apply(torch.tensor(r, device=DEV)).cpu().numpy()
+    assert rel(z, R.apply(r.T).T) <= 1e-10
