@@ -185,6 +185,15 @@ def main():
     mv_flops = 2.0 * N * N * nrhs
     achieved = mv_flops / mv_avg_s / 1e12
 
+    # the paper's matvec (FFT on the uniform grid) with the same factors, for comparison
+    P.fft_prepare(max_pairs=8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, its_fft, rr_fft = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200, fft=True)
+    torch.cuda.synchronize()
+    pcg_fft_s = time.perf_counter() - t0
+    log("pcg with the FFT matvec: %.3f s, iterations %d-%d" % (pcg_fft_s, min(its_fft), max(its_fft)))
+
     # plain FP64 form: FP64 factors, right-hand sides one at a time
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -245,6 +254,10 @@ def main():
         "matvec_avg_ms": mv_avg_s * 1e3,
         "apply_avg_ms": ap_ms / max(ap_n, 1),
         "matvec_tile_rows_per_wave": 16 * tile,
+        "pcg_with_fft_matvec": {"pcg_s": pcg_fft_s, "n_it": [min(its_fft), max(its_fft)],
+                                "max_relres": max(rr_fft),
+                                "note": "same factors; products with A by circulant-embedding FFT (Section 5 of "
+                                        "the paper) instead of the dense on-the-fly matvec"},
         "rank_predictor": {"train_s": mlp_train_s, "mean_abs_rank_err": sched["mean_abs_err"],
                            "factor_s_with": factor_s, "factor_s_without": factor_nm_s,
                            "host_syncs_with": sched["host_syncs"], "host_syncs_without": sched_nm["host_syncs"],

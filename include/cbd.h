@@ -187,6 +187,18 @@ int rs_apply(cbd_factor f, int nrhs, const double* r, double* z, void* stream);
  *  x, y: device, N x nrhs column-major FP64 (may not alias). */
 int kernel_matvec(cbd_problem p, int nrhs, const double* x, double* y, void* stream);
 
+/* cbd_fft_prepare / kernel_matvec_fft - y = A x by FFT, the paper's matvec on the
+ * uniform grid (Section 5): the kernel part is the aperiodic convolution of w o x
+ * with g[delta] = K(spacing |delta|) (g[0] = 0), computed by circulant embedding
+ * in a P^d grid (P the smallest power of two >= 2n - 1, at most 4096); the
+ * diagonal term is added exactly.  Two right-hand sides share one complex
+ * transform.  cbd_fft_prepare allocates the embedded kernel's transform and a
+ * workspace of max_pairs complex P^d arrays (owned by the problem, freed with
+ * it) and synchronizes `stream`; kernel_matvec_fft then takes the same x, y as
+ * kernel_matvec (N x nrhs column-major, FP64, no aliasing). */
+int cbd_fft_prepare(cbd_problem p, int max_pairs, void* stream);
+int kernel_matvec_fft(cbd_problem p, int nrhs, const double* x, double* y, void* stream);
+
 /* cbd_autotune_matvec - choose the matvec's tile shape (rows per wave: 16, 32 or
  * 64) for this problem and nrhs by timing each candidate with HIP events on
  * `stream`; later kernel_matvec calls with the
@@ -202,13 +214,15 @@ int cbd_autotune_matvec(cbd_problem p, int nrhs, void* stream, int* choice);
  * CBD_PCG_FLEXIBLE.  With CBD_PCG_GRAPH the two launch sequences of an iteration
  * (matvec through ||r||, and preconditioner through the new direction) are
  * captured once into HIP graphs and replayed; this needs a non-default stream,
- * gives bitwise the same result, and records no kernel timers.
+ * gives bitwise the same result, and records no kernel timers.  CBD_PCG_FFT uses
+ * kernel_matvec_fft for the products with A (after cbd_fft_prepare).
  *  f (device, N x nrhs), u (device, N x nrhs, output).  fac = NULL: no
  *  preconditioner.  ws: device workspace of at least pcg_workspace_bytes(N, nrhs)
  *  bytes.  iters, relres: host arrays of nrhs (matvec count, final recurrence
  *  residual).  Returns CBD_WNOTCONV if a column did not converge within maxit. */
 #define CBD_PCG_FLEXIBLE 1
 #define CBD_PCG_GRAPH 2
+#define CBD_PCG_FFT 4
 size_t pcg_workspace_bytes(long N, int nrhs);
 int pcg_solve(cbd_problem p, cbd_factor fac, int nrhs, const double* f, double* u,
               double tol, int maxit, int flags, void* ws, size_t ws_bytes,

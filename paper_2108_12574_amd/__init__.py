@@ -78,6 +78,18 @@ class Problem:
         check(lib().kernel_matvec(self.handle, x.shape[0], _ptr(x), _ptr(y), _stream(self.device)))
         return y[0] if one else y
 
+    def fft_prepare(self, max_pairs=8):
+        """Set up the FFT matvec (cbd_fft_prepare)."""
+        check(lib().cbd_fft_prepare(self.handle, max_pairs, _stream(self.device)))
+
+    def matvec_fft(self, x):
+        """y = A x by FFT (kernel_matvec_fft); needs fft_prepare()."""
+        one = x.dim() == 1
+        x = _vec(x, self.N, self.device)
+        y = torch.empty_like(x)
+        check(lib().kernel_matvec_fft(self.handle, x.shape[0], _ptr(x), _ptr(y), _stream(self.device)))
+        return y[0] if one else y
+
     def autotune_matvec(self, nrhs):
         """Pick the matvec tile shape for nrhs right-hand sides (cbd_autotune_matvec)."""
         ch = ctypes.c_int()
@@ -283,7 +295,7 @@ class RankMLP:
         return torch.clamp(torch.round(torch.exp2(y) - 1.0), min=0).to(torch.int64)
 
 
-def pcg_solve(problem, factor, f, tol=1e-10, maxit=200, flexible=False, graph=False):
+def pcg_solve(problem, factor, f, tol=1e-10, maxit=200, flexible=False, graph=False, fft=False):
     """PCG on A u = f (pcg_solve).  f: (N,) or (nrhs, N).  Returns (u, iters, relres).
 
     graph=True replays each iteration from captured HIP graphs (needs a non-default
@@ -296,7 +308,7 @@ def pcg_solve(problem, factor, f, tol=1e-10, maxit=200, flexible=False, graph=Fa
     ws = torch.empty(nb, dtype=torch.uint8, device=problem.device)
     iters = (ctypes.c_int * nrhs)()
     relres = (ctypes.c_double * nrhs)()
-    flags = (1 if flexible else 0) | (2 if graph else 0)
+    flags = (1 if flexible else 0) | (2 if graph else 0) | (4 if fft else 0)
     rc = lib().pcg_solve(problem.handle, factor.handle if factor is not None else None, nrhs,
                          _ptr(f), _ptr(u), tol, maxit, flags, _ptr(ws), nb,
                          iters, relres, _stream(problem.device))

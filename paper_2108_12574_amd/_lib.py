@@ -42,6 +42,8 @@ SIGNATURES = [
     ("rs_factor_root", _i, [_vp, _i, _ip, _ip, _dp]),
     ("rs_apply", _i, [_vp, _i, _vp, _vp, _vp]),
     ("kernel_matvec", _i, [_vp, _i, _vp, _vp, _vp]),
+    ("cbd_fft_prepare", _i, [_vp, _i, _vp]),
+    ("kernel_matvec_fft", _i, [_vp, _i, _vp, _vp, _vp]),
     ("cbd_autotune_matvec", _i, [_vp, _i, _vp, _ip]),
     ("pcg_workspace_bytes", _sz, [_l, _i]),
     ("pcg_solve", _i, [_vp, _vp, _i, _vp, _vp, _d, _i, _i, _vp, _sz, _ip, _dp, _vp]),

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcbd.so")
-SOURCES = ["host.cpp", "ie.hip", "rs.hip", "pcg.hip", "mlp.hip"]
+SOURCES = ["host.cpp", "ie.hip", "rs.hip", "pcg.hip", "mlp.hip", "fft.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -117,6 +117,16 @@ struct cbd_problem_s {
     double h, weight, a_self;
     double *pts, *diag, *w, *rs;
     int mv_rb[4] = {0, 0, 0, 0};   // tuned matvec row blocks per wave, per RHS-block count (0: default)
+    // FFT matvec state (cbd_fft_prepare)
+    int fft_P = 0, fft_logP = 0, fft_pairs = 0;
+    double* fft_ghat = nullptr;
+    double2* fft_tw = nullptr;
+    double2* fft_buf = nullptr;
+    ~cbd_problem_s() {
+        if (fft_ghat) (void)hipFree(fft_ghat);
+        if (fft_tw) (void)hipFree(fft_tw);
+        if (fft_buf) (void)hipFree(fft_buf);
+    }
     ProblemView view() const { return ProblemView{d, n, N, pts, diag, w, rs}; }
 };
 
@@ -178,6 +188,55 @@ extern "C" int kernel_matvec(cbd_problem p, int nrhs, const double* x, double* y
     {
         ScopedTimer tm("matvec", s);
         launch_matvec(p->view(), nrhs, x, y, p->mv_rb[matvec_nb(nrhs) - 1], 0, s);
+    }
+    HIPCHK(hipGetLastError());
+    return CBD_OK;
+}
+
+extern "C" int cbd_fft_prepare(cbd_problem p, int max_pairs, void* stream) {
+    if (!p || max_pairs < 1) return fail(CBD_EARG, "cbd_fft_prepare: bad argument");
+    int P = 2, logP = 1;
+    while (P < 2 * p->n - 1) {
+        P <<= 1;
+        ++logP;
+    }
+    if (P > 4096) return fail(CBD_EARG, "cbd_fft_prepare: transform length above 4096 (n > 2048)");
+    long vol = 1;
+    for (int t = 0; t < p->d; ++t) vol *= P;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->fft_ghat) (void)hipFree(p->fft_ghat);
+    if (p->fft_tw) (void)hipFree(p->fft_tw);
+    if (p->fft_buf) (void)hipFree(p->fft_buf);
+    p->fft_ghat = nullptr;
+    p->fft_tw = nullptr;
+    p->fft_buf = nullptr;
+    p->fft_P = 0;
+    HIPCHK(hipMalloc(&p->fft_ghat, sizeof(double) * vol));
+    HIPCHK(hipMalloc(&p->fft_tw, sizeof(double2) * (P / 2)));
+    HIPCHK(hipMalloc(&p->fft_buf, sizeof(double2) * vol * max_pairs));
+    std::vector<double2> tw(P / 2);
+    const double pi = 3.14159265358979323846;
+    for (int k = 0; k < P / 2; ++k) tw[k] = make_double2(std::cos(2.0 * pi * k / P), -std::sin(2.0 * pi * k / P));
+    HIPCHK(hipMemcpy(p->fft_tw, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice));
+    const double spacing = p->grid == CBD_GRID_CELL ? 1.0 / p->n : 1.0 / (p->n - 1);
+    launch_fft_prepare(p->view(), P, logP, spacing, p->fft_buf, p->fft_ghat, p->fft_tw, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    p->fft_P = P;
+    p->fft_logP = logP;
+    p->fft_pairs = max_pairs;
+    return CBD_OK;
+}
+
+extern "C" int kernel_matvec_fft(cbd_problem p, int nrhs, const double* x, double* y, void* stream) {
+    if (!p || !x || !y || nrhs < 1) return fail(CBD_EARG, "kernel_matvec_fft: bad argument");
+    if (x == y) return fail(CBD_EARG, "kernel_matvec_fft: x and y alias");
+    if (!p->fft_P) return fail(CBD_EARG, "kernel_matvec_fft: call cbd_fft_prepare first");
+    hipStream_t s = (hipStream_t)stream;
+    {
+        ScopedTimer tm("matvec_fft", s);
+        launch_matvec_fft(p->view(), p->fft_P, p->fft_logP, p->fft_ghat, p->fft_tw, p->fft_buf, p->fft_pairs, nrhs,
+                          x, y, s);
     }
     HIPCHK(hipGetLastError());
     return CBD_OK;
@@ -1258,8 +1317,9 @@ struct PcgSeq {
         launch_copy(outv, in, NV, s);
         return CBD_OK;
     }
+    int fft = 0;
     int seqA(hipStream_t s) const {
-        int rc = kernel_matvec(p, nrhs, w.p, w.q, s);
+        int rc = fft ? kernel_matvec_fft(p, nrhs, w.p, w.q, s) : kernel_matvec(p, nrhs, w.p, w.q, s);
         if (rc) return rc;
         launch_dot(w.p, w.q, N, nrhs, w.partial, w.pq, s);
         launch_pcg_alpha(w.rz, w.pq, w.active, w.alpha, nrhs, s);
@@ -1311,7 +1371,8 @@ extern "C" int pcg_solve(cbd_problem p, cbd_factor fac, int nrhs, const double* 
                          void* stream) {
     if (!p || !f || !u || !ws || !iters || !relres || nrhs < 1 || maxit < 0)
         return fail(CBD_EARG, "pcg_solve: bad argument");
-    if (flags & ~(CBD_PCG_FLEXIBLE | CBD_PCG_GRAPH)) return fail(CBD_EARG, "pcg_solve: unknown flags");
+    if (flags & ~(CBD_PCG_FLEXIBLE | CBD_PCG_GRAPH | CBD_PCG_FFT)) return fail(CBD_EARG, "pcg_solve: unknown flags");
+    if ((flags & CBD_PCG_FFT) && !p->fft_P) return fail(CBD_EARG, "pcg_solve: CBD_PCG_FFT needs cbd_fft_prepare");
     const long N = p->N;
     if (ws_bytes < pcg_workspace_bytes(N, nrhs)) return fail(CBD_EARG, "pcg_solve: workspace too small");
     if (fac && fac->prob != p) return fail(CBD_EARG, "pcg_solve: factor belongs to another problem");
@@ -1323,6 +1384,7 @@ extern "C" int pcg_solve(cbd_problem p, cbd_factor fac, int nrhs, const double* 
     q.fac = fac;
     q.nrhs = nrhs;
     q.flexible = (flags & CBD_PCG_FLEXIBLE) != 0;
+    q.fft = (flags & CBD_PCG_FFT) != 0;
     q.N = N;
     q.NV = N * nrhs;
     q.u = u;

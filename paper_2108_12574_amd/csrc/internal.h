@@ -175,6 +175,13 @@ template <typename R>
 void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int* k, const R* F,
                         R* v, int nrhs, int np_max, bool forward, hipStream_t s);
 
+// Matvec by FFT (fft.hip): ghat (P^d reals) is the transform of the kernel's circulant
+// generator; tw[k] = exp(-2 pi i k / P), k < P/2; buf holds max_pairs complex P^d arrays.
+void launch_fft_prepare(const ProblemView& Pv, int P, int logP, double spacing, double2* gbuf, double* ghat,
+                        const double2* tw, hipStream_t s);
+void launch_matvec_fft(const ProblemView& Pv, int P, int logP, const double* ghat, const double2* tw,
+                       double2* buf, int max_pairs, int nrhs, const double* x, double* y, hipStream_t s);
+
 // PCG vector kernels (FP64).
 void launch_dot(const double* a, const double* b, long N, int nrhs, double* partial,
                 double* out, hipStream_t s);
