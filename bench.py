@@ -194,6 +194,24 @@ def main():
     pcg_fft_s = time.perf_counter() - t0
     log("pcg with the FFT matvec: %.3f s, iterations %d-%d" % (pcg_fft_s, min(its_fft), max(its_fft)))
 
+    # the bfloat16-GEMM variant of the factors (Schur products on bf16 operands)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bf16 = None
+    try:
+        fac_bf = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_BF16GEMM, mlp=mlp)
+        torch.cuda.synchronize()
+        bf_factor = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, its_bf, rr_bf = cbd.pcg_solve(P, fac_bf, F_rhs, tol=1e-10, maxit=400, flexible=True)
+        torch.cuda.synchronize()
+        bf16 = {"factor_s": bf_factor, "pcg_s": time.perf_counter() - t0, "n_it": [min(its_bf), max(its_bf)],
+                "max_relres": max(rr_bf), "pcg": "flexible"}
+        del fac_bf
+    except cbd.CbdError as e:
+        bf16 = {"error": str(e)}
+    log("bf16-GEMM variant: %s" % bf16)
+
     # plain FP64 form: FP64 factors, right-hand sides one at a time
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -254,6 +272,7 @@ def main():
         "matvec_avg_ms": mv_avg_s * 1e3,
         "apply_avg_ms": ap_ms / max(ap_n, 1),
         "matvec_tile_rows_per_wave": 16 * tile,
+        "bf16_gemm_variant": bf16,
         "pcg_with_fft_matvec": {"pcg_s": pcg_fft_s, "n_it": [min(its_fft), max(its_fft)],
                                 "max_relres": max(rr_fft),
                                 "note": "same factors; products with A by circulant-embedding FFT (Section 5 of "

@@ -46,6 +46,8 @@ extern "C" {
 
 #define CBD_PREC_FP64 0      /* factors built, stored and applied in FP64 */
 #define CBD_PREC_FP32 1      /* factors built, stored and applied in FP32; apply input/output FP64 */
+#define CBD_PREC_BF16GEMM 2  /* as FP32, with the Schur-complement products (B_sr, B_rr, E, B_ss) on
+                                bfloat16 operands with FP32 accumulation */
 
 typedef struct cbd_problem_s* cbd_problem;
 typedef struct cbd_partition_s* cbd_partition;
@@ -56,7 +58,7 @@ typedef struct {
     double tol;          /* relative accuracy eps of every ID, (e:id_err) */
     int n_pxy;           /* proxy points on the circle (2D) / sphere (3D) around a box */
     double proxy_ratio;  /* proxy radius / box side (1.5 in the paper's footnote to Section 5) */
-    int precision;       /* CBD_PREC_FP64 or CBD_PREC_FP32 */
+    int precision;       /* CBD_PREC_FP64, CBD_PREC_FP32 or CBD_PREC_BF16GEMM */
     int exact;           /* 1: no compression; every A_i is factored by dense Cholesky
                             (the naive CBD of Section 5.1) */
     const float* mlp;    /* device parameters of the rank predictor (rank_mlp_*), or NULL.

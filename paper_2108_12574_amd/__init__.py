@@ -11,12 +11,12 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (GRID_CELL, GRID_NODE, MODE_CBD, MODE_JACOBI, MODE_SCHWARZ, PREC_FP32,
-                   PREC_FP64, CbdError, check, lib)
+from ._lib import (GRID_CELL, GRID_NODE, MODE_CBD, MODE_JACOBI, MODE_SCHWARZ, PREC_BF16GEMM,
+                   PREC_FP32, PREC_FP64, CbdError, check, lib)
 
 __all__ = ["Problem", "Partition", "Factor", "RankMLP", "pcg_solve", "timing", "CbdError",
            "GRID_CELL", "GRID_NODE", "MODE_JACOBI", "MODE_SCHWARZ", "MODE_CBD",
-           "PREC_FP64", "PREC_FP32"]
+           "PREC_FP64", "PREC_FP32", "PREC_BF16GEMM"]
 
 
 def _free(fn, obj):

@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libcbd.so")
 
 GRID_CELL, GRID_NODE = 0, 1
 MODE_JACOBI, MODE_SCHWARZ, MODE_CBD = 0, 1, 2
-PREC_FP64, PREC_FP32 = 0, 1
+PREC_FP64, PREC_FP32, PREC_BF16GEMM = 0, 1, 2
 OK, EARG, EHIP, ENOTSPD, ENOMEM, WNOTCONV = 0, -1, -2, -3, -4, 1
 
 

@@ -709,6 +709,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
     // FP32 round-off floor of the recomputed column norms reaches the tolerance
     // and the ranks inflate.  Elimination, storage and apply use R.
     const double tie = 1e-10;
+    const bool bf16 = o->precision == CBD_PREC_BF16GEMM;
     std::vector<double> hdir = proxy_dirs(d, std::max(npxy, 1));
     DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf, mlpbuf, listbuf;
     if ((rc = dirbuf.ensure(sizeof(double) * hdir.size()))) return rc;
@@ -996,7 +997,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             }
         }
         if (big.empty()) {
-            launch_eliminate<R>(L.nbox, L.d_meta, nullptr, 0, L.d_perm, L.d_k, App, T64, Wk, FF, d_status, s);
+            launch_eliminate<R>(L.nbox, L.d_meta, nullptr, 0, L.d_perm, L.d_k, App, T64, Wk, FF, d_status, bf16, s);
         } else {
             if ((rc = listbuf.ensure(sizeof(int) * L.nbox))) return rc;
             int* d_small = (int*)listbuf.p;
@@ -1005,12 +1006,12 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             lists.insert(lists.end(), big.begin(), big.end());
             HIPCHK(hipMemcpyAsync(d_small, lists.data(), sizeof(int) * lists.size(), hipMemcpyHostToDevice, s));
             launch_eliminate<R>((int)small.size(), L.d_meta, d_small, 0, L.d_perm, L.d_k, App, T64, Wk, FF,
-                                d_status, s);
+                                d_status, bf16, s);
             launch_eliminate<R>((int)big.size(), L.d_meta, d_big, 1, L.d_perm, L.d_k, App, T64, Wk, FF,
-                                d_status, s);
+                                d_status, bf16, s);
             launch_big_cholesky_inverse<R>((int)big.size(), np_big, L.d_meta, d_big, L.d_k, Wk, FF, d_status, s);
             launch_eliminate<R>((int)big.size(), L.d_meta, d_big, 2, L.d_perm, L.d_k, App, T64, Wk, FF,
-                                d_status, s);
+                                d_status, bf16, s);
             HIPCHK(hipStreamSynchronize(s));   // `lists` is read by the copy above
             F->host_syncs++;
         }
@@ -1055,7 +1056,7 @@ extern "C" int rs_factor_batched(cbd_problem p, cbd_partition q, const cbd_rs_op
     if (p->grid != CBD_GRID_CELL) return fail(CBD_EARG, "rs_factor_batched: RS needs the cell-centred grid");
     if (!o->exact && (o->n_pxy < 1 || !(o->tol >= 0.0) || !(o->proxy_ratio > 0.75)))
         return fail(CBD_EARG, "rs_factor_batched: need n_pxy >= 1, tol >= 0, proxy_ratio > 0.75");
-    if (o->precision != CBD_PREC_FP64 && o->precision != CBD_PREC_FP32)
+    if (o->precision != CBD_PREC_FP64 && o->precision != CBD_PREC_FP32 && o->precision != CBD_PREC_BF16GEMM)
         return fail(CBD_EARG, "rs_factor_batched: unknown precision");
     hipStream_t s = (hipStream_t)stream;
     auto* F = new cbd_factor_s;
@@ -1063,6 +1064,7 @@ extern "C" int rs_factor_batched(cbd_problem p, cbd_partition q, const cbd_rs_op
     F->part = q;
     F->prec = o->precision;
     F->esize = o->precision == CBD_PREC_FP64 ? 8 : 4;
+    F->prec = o->precision == CBD_PREC_FP64 ? CBD_PREC_FP64 : CBD_PREC_FP32;   // storage precision
     F->tol = o->tol;
     int rc;
     {

@@ -149,10 +149,11 @@ template <typename R>
 void launch_box_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, const int* act,
                        const int* cidx, const ChildRef<R>* ch, R* App, hipStream_t s);
 // phase 0: whole elimination per box; 1: up to B_rr; 2: E and B_ss (list: box indices or NULL)
+// bf16: Schur-complement products with bfloat16 operands and FP32 accumulation (R = float)
 template <typename R>
 void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, int phase, const int* perm,
                       const int* k, const R* App, const double* T64, R* Wk, R* F, int* status,
-                      hipStream_t s);
+                      bool bf16, hipStream_t s);
 // multi-workgroup blocked Cholesky of B_rr and G^{-1} for the boxes in list (after phase 1)
 template <typename R>
 void launch_big_cholesky_inverse(int nbig, int nr_max, const BoxMeta* meta, const int* list, const int* k,

@@ -509,6 +509,64 @@ __device__ void wg_gemm(int M, int N, int K, R alpha, const R* A, int lda, bool 
     __syncthreads();
 }
 
+// The same product with bfloat16 operands (rounded to nearest even) and FP32
+// accumulation, on v_mfma_f32_16x16x16bf16_1k: A[i][k] in lane i + 16 (k/4),
+// element k%4; B[k][j] in lane j + 16 (k/4), element k%4; accumulator as f32.
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float x) {
+    unsigned u = __float_as_uint(x);
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    return (short)u;
+}
+
+__device__ void wg_gemm_bf16(int M, int N, int K, float alpha, const float* A, int lda, bool ta, const float* B,
+                             int ldb, bool tb, float beta, float* C, int ldc, bool upper = false) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int t = wid; t < tm * tn; t += kWaves) {
+        const int i0 = (t % tm) << 4, j0 = (t / tm) << 4;
+        if (upper && i0 > j0 + 15) continue;
+        v4 acc = {0, 0, 0, 0};
+        const int i = i0 + li, j = j0 + li;
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            v4s a, b;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int kk = k0 + 4 * lk + e;
+                float va = 0.f, vb = 0.f;
+                if (i < M && kk < K) va = ta ? A[kk + (long)i * lda] : A[i + (long)kk * lda];
+                if (j < N && kk < K) vb = tb ? B[j + (long)kk * ldb] : B[kk + (long)j * ldb];
+                a[e] = bf16_bits(va);
+                b[e] = bf16_bits(vb);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ii = i0 + 4 * lk + v, jj = j0 + li;
+            if (ii < M && jj < N) {
+                float* c = C + ii + (long)jj * ldc;
+                *c = (beta == 0.f ? 0.f : beta * *c) + alpha * acc[v];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Schur-complement products of the elimination: FP64/FP32 MFMA, or bfloat16
+// operands with FP32 accumulation when BF16 is set (float storage only).
+template <typename R, bool BF16>
+__device__ __forceinline__ void schur_gemm(int M, int N, int K, R alpha, const R* A, int lda, bool ta, const R* B,
+                                           int ldb, bool tb, R beta, R* C, int ldc, bool upper = false) {
+    if constexpr (BF16)
+        wg_gemm_bf16(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, upper);
+    else
+        wg_gemm<R>(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, upper);
+}
+
 constexpr int kBlk = 16;   // block size of the blocked Cholesky / triangular inverse
 
 // Blocked right-looking Cholesky of the upper triangle of S (n x n, lds): S = G^T G,
@@ -612,7 +670,7 @@ __device__ __forceinline__ ElimView<R> elim_view(const BoxMeta& M, int k, R* Wk,
     return v;
 }
 
-template <typename R>
+template <typename R, bool BF16>
 __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restrict__ meta,
                                                         const int* __restrict__ list,
                                                         const int* __restrict__ perm,
@@ -647,9 +705,9 @@ __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restric
         if (tid == 0) s_fail = 0;
         __syncthreads();
         if (k > 0 && nr > 0) {
-            wg_gemm<R>(nr, nr, k, (R)-1, V.T, k, true, V.Bsr, k, false, (R)1, V.Brr, nr, true);   // - T^T A_sr
-            wg_gemm<R>(k, nr, k, (R)-1, V.Ass, k, false, V.T, k, false, (R)1, V.Bsr, k);          // B_sr
-            wg_gemm<R>(nr, nr, k, (R)-1, V.Bsr, k, true, V.T, k, false, (R)1, V.Brr, nr, true);   // - B_sr^T T
+            schur_gemm<R, BF16>(nr, nr, k, (R)-1, V.T, k, true, V.Bsr, k, false, (R)1, V.Brr, nr, true);   // - T^T A_sr
+            schur_gemm<R, BF16>(k, nr, k, (R)-1, V.Ass, k, false, V.T, k, false, (R)1, V.Bsr, k);          // B_sr
+            schur_gemm<R, BF16>(nr, nr, k, (R)-1, V.Bsr, k, true, V.T, k, false, (R)1, V.Brr, nr, true);   // - B_sr^T T
         }
         if (phase == 1) return;
         if (!wg_cholesky_upper<R>(nr, V.Brr, nr, &s_fail)) {
@@ -659,10 +717,10 @@ __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restric
         wg_triangular_inverse<R>(nr, V.Brr, nr, V.Gi, V.W);
     }
     if (k > 0) {
-        wg_gemm<R>(k, nr, nr, (R)1, V.Bsr, k, false, V.Gi, nr, false, (R)0, V.E, k);     // E = B_sr G^{-1}
+        schur_gemm<R, BF16>(k, nr, nr, (R)1, V.Bsr, k, false, V.Gi, nr, false, (R)0, V.E, k);     // E = B_sr G^{-1}
         for (long e = tid; e < (long)k * k; e += kThreads) V.Bss[e] = V.Ass[e];
         __syncthreads();
-        wg_gemm<R>(k, k, nr, (R)-1, V.E, k, false, V.E, k, true, (R)1, V.Bss, k);        // B_ss = A_ss - E E^T
+        schur_gemm<R, BF16>(k, k, nr, (R)-1, V.E, k, false, V.E, k, true, (R)1, V.Bss, k);        // B_ss = A_ss - E E^T
     }
 }
 
@@ -806,10 +864,17 @@ __global__ __launch_bounds__(kThreads) void k_binv(const BoxMeta* __restrict__ m
 
 template <typename R>
 void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, int phase, const int* perm, const int* k,
-                      const R* App, const double* T64, R* Wk, R* F, int* status, hipStream_t s) {
+                      const R* App, const double* T64, R* Wk, R* F, int* status, bool bf16, hipStream_t s) {
     if (nbox == 0) return;
-    hipLaunchKernelGGL((k_eliminate<R>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App, T64, Wk,
-                       F, status, phase);
+    if constexpr (sizeof(R) == 4) {
+        if (bf16) {
+            hipLaunchKernelGGL((k_eliminate<R, true>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App,
+                               T64, Wk, F, status, phase);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_eliminate<R, false>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App, T64,
+                       Wk, F, status, phase);
 }
 
 template <typename R>
@@ -1017,7 +1082,7 @@ template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta
     template void launch_box_matrix<R>(const ProblemView&, int, const BoxMeta*, const int*,         \
                                        const int*, const ChildRef<R>*, R*, hipStream_t);            \
     template void launch_eliminate<R>(int, const BoxMeta*, const int*, int, const int*, const int*, \
-                                      const R*, const double*, R*, R*, int*, hipStream_t);          \
+                                      const R*, const double*, R*, R*, int*, bool, hipStream_t);    \
     template void launch_big_cholesky_inverse<R>(int, int, const BoxMeta*, const int*, const int*, R*, \
                                                  R*, int*, hipStream_t);                            \
     template void launch_root_apply<R>(int, int, int, const BoxMeta*, const int*, const int*, const R*, \

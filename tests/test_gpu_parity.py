@@ -346,3 +346,21 @@ def test_large_roots_match_oracle():
     r = synth.rhs(O.N, 3, seed=1)
     z = F.apply(torch.tensor(r, device=DEV)).cpu().numpy()
     assert rel(z, R.apply(r.T).T) <= 1e-10
+
+
+def test_bf16_gemm_variant(cfg1):
+    # Schur-complement products on bfloat16 operands (FP32 accumulation): the
+    # preconditioner is less accurate, FP64 PCG still reaches 1e-10 and the
+    # solution still matches the dense solve
+    P, O, part, opart, R = cfg1
+    F = cbd.Factor(P, part, tol=1e-8, n_pxy=64, precision=cbd.PREC_BF16GEMM)
+    r = synth.rhs(O.N, 2, seed=0)
+    z = F.apply(torch.tensor(r, device=DEV)).cpu().numpy()
+    err = rel(z, R.apply(r.T).T)
+    print("bf16 apply error vs FP64 oracle %.2e" % err, flush=True)
+    assert err <= 5e-2
+    f = r[0]
+    u, it, rr = cbd.pcg_solve(P, F, torch.tensor(f, device=DEV), tol=1e-10, maxit=300, flexible=True)
+    ud = np.linalg.solve(O.dense(), f)
+    print("bf16 pcg iterations", it, flush=True)
+    assert rr <= 1e-10 and rel(u.cpu().numpy(), ud) <= 1e-8
