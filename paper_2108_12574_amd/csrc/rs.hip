@@ -93,18 +93,8 @@ void launch_proxy_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, co
 // Outputs: k, the pivot order (perm: positions, sr: slot ids, skeletons first),
 // and T (k x nr, column-major) at the box's factor offset of T64.
 
-// Back substitution T = R11^{-1} R12 (R in the first k rows of Yb), one column per thread.
-__device__ void id_coefficients(const double* Yb, int m, int np, int k, double* T) {
-    const int nr = np - k;
-    for (int c = threadIdx.x; c < nr; c += kThreads) {
-        const double* rc = Yb + (long)(k + c) * m;
-        for (int a = k - 1; a >= 0; --a) {
-            double s = rc[a];
-            for (int b = a + 1; b < k; ++b) s -= Yb[a + (long)b * m] * T[b + (long)c * k];
-            T[a + (long)c * k] = s / Yb[a + (long)a * m];
-        }
-    }
-}
+// T = R11^{-1} R12 (R in the first k rows of Yb, T k x nr with ld k); defined below.
+__device__ void id_coefficients(const double* Yb, int m, int np, int k, double* T);
 
 // Householder update of trailing columns c in [c_lo, c_hi) (c > j) with the
 // reflector v (LDS, rows j..m-1), then their norm over rows j+1..m-1.
@@ -565,6 +555,34 @@ __device__ __forceinline__ void schur_gemm(int M, int N, int K, R alpha, const R
         wg_gemm_bf16(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, upper);
     else
         wg_gemm<R>(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, upper);
+}
+
+// T = R11^{-1} R12 by blocked back substitution over 16-row blocks, bottom up:
+// T_I = R_II^{-1} (R12_I - R_{I,>I} T_{>I}); the update is an MFMA GEMM, the
+// diagonal solve one column per thread.  All threads of the workgroup call it.
+__device__ void id_coefficients(const double* Yb, int m, int np, int k, double* T) {
+    const int nr = np - k;
+    for (long e = threadIdx.x; e < (long)k * nr; e += kThreads) {
+        const int a = (int)(e % k), c = (int)(e / k);
+        T[e] = Yb[a + (long)(k + c) * m];
+    }
+    __syncthreads();
+    const int nblk = (k + 15) / 16;
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        const int I = bi * 16, ib = min(16, k - I), rest = k - (I + ib);
+        if (rest > 0)
+            wg_gemm<double>(ib, nr, rest, -1.0, Yb + I + (long)(I + ib) * m, m, false, T + I + ib, k, false, 1.0,
+                            T + I, k);
+        for (int c = threadIdx.x; c < nr; c += kThreads) {
+            double* tc = T + (long)c * k;
+            for (int a = I + ib - 1; a >= I; --a) {
+                double sum = tc[a];
+                for (int q = a + 1; q < I + ib; ++q) sum -= Yb[a + (long)q * m] * tc[q];
+                tc[a] = sum / Yb[a + (long)a * m];
+            }
+        }
+        __syncthreads();
+    }
 }
 
 constexpr int kBlk = 16;   // block size of the blocked Cholesky / triangular inverse
