@@ -257,11 +257,12 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f64 (matvec, PCG, ID) + f32 (RS elimination, factor storage, apply)"
-                  if prec == cbd.PREC_FP32 else "f64"),
+        "dtype": "f64+f32" if prec == cbd.PREC_FP32 else "f64",
+        "dtype_detail": ("f64: matvec, PCG recurrences, ID; f32: RS elimination, factor storage, apply"
+                         if prec == cbd.PREC_FP32 else "f64 throughout"),
         "data": "synthetic",
-        "config": {"workload": W["label"], "name": args.workload, "global_batch": nrhs,
-                   "parallelism": "single GPU"},
+        "config": {"workload": W["label"], "name": args.workload, "nrhs": nrhs, "n": n, "d": d,
+                   "gpus": 1},
         "factor_s": factor_s,
         "factor_gflops": st["flops"] / factor_s / 1e9,
         "factor_flops": st["flops"],

@@ -364,3 +364,97 @@ def test_bf16_gemm_variant(cfg1):
     ud = np.linalg.solve(O.dense(), f)
     print("bf16 pcg iterations", it, flush=True)
     assert rr <= 1e-10 and rel(u.cpu().numpy(), ud) <= 1e-8
+
+
+def _single_leaf_factor_3d(O, sd, b, tol=1e-6, npxy=256, ratio=1.5):
+    lo, hi, st, cnt = sd.leaves[b]
+    p = np.arange(st, st + cnt)
+    others = np.setdiff1d(np.arange(len(sd.index)), p)
+    lo, hi = np.array(lo), np.array(hi)
+    n = O.n
+    J = np.stack([sd.index % n, (sd.index // n) % n, sd.index // (n * n)], axis=1)
+    off = 2 * J[others] + 1 - (lo + hi)
+    near = others[np.sum(off * off, axis=1) < (2 * ratio * np.max(hi - lo)) ** 2]
+    ctr = 0.5 * (lo + hi) / n
+    R = ratio * np.max(hi - lo) / n
+    pxy = ctr + R * rs.proxy_directions(3, npxy)
+    xp = O.x[sd.index[p]]
+    Kp = 1.0 / (4 * np.pi * np.linalg.norm(pxy[:, None] - xp[None], axis=2))
+    Y = np.vstack([O.block(sd.index[near], sd.index[p]), Kp * O.weight * O.c[sd.index[p]]])
+    k, perm, T = interp_decomp(Y, tol)
+    return p[perm[:k]], T
+
+
+def test_full_size_3d_sampled():
+    # 3D 32^3, CBD m = 8, tol 1e-6, 256 proxy points, FP32 factors, 16 RHS:
+    # sampled leaf IDs against the oracle, and the true residual on sampled rows
+    P, O = gpu_problem(3, 32)
+    part = cbd.Partition(P, 8, 1, cbd.MODE_CBD, 0)
+    F = cbd.Factor(P, part, tol=1e-6, n_pxy=256, precision=cbd.PREC_FP32)
+    opart = dd.Partition(3, 32, 8, 1, dd.CBD)
+    rng = np.random.default_rng(3)
+    for i in (0, 5):
+        sd = opart.subdomains[i]
+        for b in rng.choice(len(sd.leaves), 2, replace=False):
+            sk, T = _single_leaf_factor_3d(O, sd, int(b))
+            g = F.box(i, 0, int(b))
+            assert np.array_equal(g["sk"], sk), (i, b)
+            assert rel(g["T"], T) <= 1e-5
+    f = synth.rhs(O.N, 16, seed=0)
+    U, its, rrs = cbd.pcg_solve(P, F, torch.tensor(f, device=DEV), tol=1e-10, maxit=200)
+    assert max(rrs) <= 1e-10 and max(its) <= 40
+    rows = rng.choice(O.N, 48, replace=False)
+    res = f[:, rows].T - cmatvec.matvec(O, U.cpu().numpy().T, rows=rows)
+    for c in range(16):
+        assert np.sqrt(np.mean(res[:, c] ** 2)) <= 1e-8 * np.linalg.norm(f[c]) / np.sqrt(O.N)
+
+
+def test_full_size_schwarz_256_sampled_subdomains():
+    # 256^2, Schwarz 4 x 4 subdomains, overlap one 8 x 8 leaf tile, tol 1e-6, FP64:
+    # three of the sixteen subdomains (corner, edge, interior) compared box by box
+    P, O = gpu_problem(2, 256)
+    part = cbd.Partition(P, 4, 8, cbd.MODE_SCHWARZ, 8)
+    F = cbd.Factor(P, part, tol=1e-6, n_pxy=64)
+    opart = dd.Partition(2, 256, 4, 8, dd.SCHWARZ, 8)
+    for i in (0, 1, 5):
+        print("subdomain", i, flush=True)
+        sd = opart.subdomains[i]
+        f = rs.factor_subdomain(O, opart, sd, 1e-6, 64)
+        for l in range(sd.root_level):
+            for b in range(len(sd.levels[l])):
+                g = F.box(i, l, b)
+                o = f.levels[l][b]
+                assert np.array_equal(g["sk"], o.sk) and np.array_equal(g["rd"], o.rd), (i, l, b)
+                if len(o.rd) and len(o.sk):
+                    assert rel(g["T"], o.T) <= 1e-8
+        idx, Gi = F.root(i)
+        assert np.array_equal(idx, f.root)
+    fr = synth.rhs(O.N, 1, seed=0)[0]
+    u, it, rr = cbd.pcg_solve(P, F, torch.tensor(fr, device=DEV), tol=1e-10, maxit=200)
+    assert rr <= 1e-10 and it <= 40
+    rows = np.random.default_rng(4).choice(O.N, 64, replace=False)
+    res = fr[rows] - cmatvec.matvec(O, u.cpu().numpy(), rows=rows)
+    assert np.sqrt(np.mean(res ** 2)) <= 1e-8 * np.linalg.norm(fr) / np.sqrt(O.N)
+
+
+def test_full_size_1024_fft_sampled():
+    # 1024^2, CBD m = 128, tol 1e-6, FP32 factors: sampled leaf IDs; PCG (FFT products)
+    # to 1e-10 with the true residual checked by the oracle on sampled rows
+    P, O = gpu_problem(2, 1024)
+    part = cbd.Partition(P, 128, 1, cbd.MODE_CBD, 0)
+    F = cbd.Factor(P, part, tol=1e-6, n_pxy=64, precision=cbd.PREC_FP32)
+    opart = dd.Partition(2, 1024, 128, 1, dd.CBD)
+    rng = np.random.default_rng(5)
+    for i in (1, 2):
+        sd = opart.subdomains[i]
+        for b in rng.choice(len(sd.leaves), 2, replace=False):
+            sk, rd, T = _single_leaf_factor(O, sd, int(b))
+            g = F.box(i, 0, int(b))
+            assert np.array_equal(g["sk"], sk)
+    P.fft_prepare(max_pairs=1)
+    fr = synth.rhs(O.N, 1, seed=0)[0]
+    u, it, rr = cbd.pcg_solve(P, F, torch.tensor(fr, device=DEV), tol=1e-10, maxit=200, fft=True)
+    assert rr <= 1e-10 and it <= 40
+    rows = rng.choice(O.N, 16, replace=False)
+    res = fr[rows] - cmatvec.matvec(O, u.cpu().numpy(), rows=rows)
+    assert np.sqrt(np.mean(res ** 2)) <= 1e-8 * np.linalg.norm(fr) / np.sqrt(O.N)
