@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "PCG solve time (s) & RS factor GFLOP/s at 2D 512^2, mixed vs FP64, rel res 1e-10"
 
 # The workloads (cell-centred grids, Laplace kernel, closed-form diagonal, PCG to 1e-10).
-# "512sq" is the measured configuration; the others are run for the design notes.
+# "512sq" is the default measured configuration; the others are selectable with --workload.
 WORKLOADS = {
     "64sq": dict(d=2, n=64, m=16, mode="cbd", delta=1, leaf=0, tol=1e-8, npxy=64, nrhs=1,
                  prec="fp64", coef=False, label="2D 64^2, CBD m=16, tol 1e-8, 1 RHS, FP64"),
@@ -102,7 +102,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the "
-              "path is described in the design notes and not implemented", file=sys.stderr)
+              "path is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

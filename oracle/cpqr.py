@@ -7,7 +7,7 @@ QR: at each step the column with the largest remaining 2-norm is moved to the
 front and eliminated with a Householder reflection.  With Y[:, perm] = Q R,
 T = R11^{-1} R12.
 
-Readings (listed in the design notes):
+Readings (where the paper leaves a choice):
 * rank rule: stop at the first step j whose largest remaining column norm is
   <= tol * (largest column norm of Y); k = j.  All-zero Y gives k = 0;
 * column norms are recomputed from the remaining block at every step (no

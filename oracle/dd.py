@@ -6,7 +6,7 @@ block-Jacobi subdomains (table t:dd); and the hierarchical partitioning of a
 subdomain used by recursive skeletonization (Section 3.2, around (e:oi) and
 (e:schur): leaf regions, merged by spatial proximity until one box is left).
 
-Readings (listed in the design notes):
+Readings (where the paper leaves a choice):
 * extension by `delta` layers per side, clipped at the domain boundary;
 * coloring c(k) = sum_t (k_t mod 2) 2^(t-1) (2^d colors, the theorem of Section 2.3);
 * leaf boxes: each extended partition of a subdomain is a region; a region is one

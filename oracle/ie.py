@@ -5,7 +5,7 @@ Nystrom/collocation on a uniform grid with matrix entries (e:a_2d)/(e:a_3d).
 The variable-coefficient form follows the model equation (e:int) with a = 0
 and b = c (SPD case): A_bc = diag(b) A diag(c).
 
-Conventions (readings of the paper, listed in the design notes):
+Conventions (readings where the paper leaves a choice):
 * point index g = j1 + n*j2 (+ n^2*j3), x fastest, 0-based j;
 * "cell" grid: x_t = (j_t + 1/2) h, h = 1/n (the text's convention, Section 2.1);
 * "node" grid (2D only, used to reproduce the printed 2D eigenvalue tables):
