@@ -46,47 +46,44 @@ void launch_assemble(int d, int n, int grid, const double* b, const double* c, d
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kMvThreads = 256;
-constexpr int kTJ = 64;
-constexpr int kLogTab = 128;
-// 2D self pair: r^2 is clamped to 2^-1000 (K = 55.1...), removed exactly in the epilogue
-constexpr double kSelfR2 = 0x1p-1000;
+constexpr int kTJ = 64;                // sources per LDS tile
+constexpr int kLdw = 66;               // LDS row stride of the [j][rhs] tile (doubles)
+constexpr int kLogTab = 1024;
 
-// Table-driven natural logarithm (Tang, ACM TOMS 15(2), 1989) for positive normal
-// x: x = 2^e m, m in [1, 2); F = 1 + j/128 from the top 7 mantissa bits (so
-// m - F is exact and u = (m - F)/F is in [0, 1/128)); log x = e ln2 + log F +
-// log1p(u), log1p by its Taylor series to u^8 (truncation < 2e-18 relative).
-// tab[2j] = log F_j, tab[2j+1] = 1/F_j (from the host's libm).
-__device__ __forceinline__ double log_tab(double x, const double* __restrict__ tab) {
-    constexpr double kLn2Hi = 0x1.62e42fp-1;
-    constexpr double kLn2Lo = 0x1.df473de6af279p-26;
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
-    const unsigned hi = (unsigned)(bits >> 32), lo = (unsigned)bits;
-    const int e = (int)(hi >> 20) - 1023;
-    const unsigned mhi = (hi & 0x000FFFFFu) | 0x3FF00000u;
-    const double m = __longlong_as_double((long long)(((unsigned long long)mhi << 32) | lo));
-    const double F = __longlong_as_double((long long)((unsigned long long)(mhi & 0xFFFFE000u) << 32));
-    const int j = (mhi >> 13) & (kLogTab - 1);
-    const double u = (m - F) * tab[2 * j + 1];
-    double p = -1.0 / 8.0;
-    p = fma(p, u, 1.0 / 7.0);
-    p = fma(p, u, -1.0 / 6.0);
-    p = fma(p, u, 1.0 / 5.0);
-    p = fma(p, u, -1.0 / 4.0);
-    p = fma(p, u, 1.0 / 3.0);
-    p = fma(p, u, -1.0 / 2.0);
-    p = fma(p * u, u, u);                                  // log1p(u)
-    const double de = (double)e;
-    return fma(de, kLn2Hi, fma(de, kLn2Lo, tab[2 * j]) + p);
+// 2D kernel value from r^2: K = -(1/2pi) log r = c log r^2, c = -1/(4 pi).
+// Table-driven logarithm (after Tang, ACM TOMS 15(2), 1989), with the constant c
+// folded into the table and the polynomial: r^2 = 2^e m, m in [1/2, 1) (frexp);
+// F_j = (1 + j/1024)/2 from the top 10 fraction bits of m, so u = m/F_j - 1 lies
+// in [0, 2^-10); c log r^2 = e (c ln2) + c log F_j + c log1p(u), with log1p(u) by
+// its Taylor series to u^4 (truncation below 2e-17 absolute, under one rounding of
+// the result).  tab[2j] = c log F_j and tab[2j+1] = 1/F_j, rounded from long
+// double on the host.  r^2 = 0 (the pair i = j) gives e = 0, m = 0 and a finite
+// value, which the product's epilogue removes again.
+__device__ __forceinline__ double klog_r2(double x, const double* __restrict__ tab) {
+    constexpr double c = -kInv4Pi;
+    constexpr double cln2 = -kInv4Pi * 0.69314718055994530942;
+    const int e = __builtin_amdgcn_frexp_exp(x);
+    const double m = __builtin_amdgcn_frexp_mant(x);
+    const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(x) >> 32);
+    const unsigned off = (hi >> 6) & ((kLogTab - 1) << 4);   // byte offset of entry j
+    const double2 t = *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(tab) + off);
+    const double u = fma(m, t.y, -1.0);
+    double p = -c / 4.0;
+    p = fma(p, u, c / 3.0);
+    p = fma(p, u, -c / 2.0);
+    p = fma(p, u, c);
+    return fma((double)e, cln2, fma(p, u, t.x));
 }
 
 template <int D>
 __device__ __forceinline__ double kernel_r2(double r2, const double* __restrict__ tab) {
     if constexpr (D == 2)
-        return -0.5 * kInv2Pi * log_tab(r2, tab);
+        return klog_r2(r2, tab);
     else
         return kInv4Pi * rsqrt(r2);
-}                // sources per LDS tile
-constexpr int kLdw = 66;               // LDS row stride of the [j][rhs] tile (doubles)
+}
+
+static_assert(kMvThreads == 4 * kTJ, "the staging assigns one source per thread and 4 threads per source");
 
 template <int D, int NB, int kRB>
 __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
@@ -95,7 +92,7 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
                                                        const double* __restrict__ logtab) {
     __shared__ double sxj[D][kTJ];
     __shared__ double swx[kTJ * kLdw];
-    __shared__ double stab[2 * kLogTab];
+    __shared__ __attribute__((aligned(16))) double stab[2 * kLogTab];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const long N = P.N;
@@ -122,18 +119,28 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
 
     for (long j0 = 0; j0 < N; j0 += kTJ) {
         __syncthreads();
-        // stage the tile: coordinates and w_j x_j (zero for padding sources / columns)
-        for (int e = tid; e < D * kTJ; e += kMvThreads) {
-            const int t = e / kTJ, jj = e % kTJ;
-            const long j = j0 + jj;
-            sxj[t][jj] = j < N ? P.pts[t * N + j] : 8.0 + t;
-        }
-        for (int e = tid; e < NB * 16 * kTJ; e += kMvThreads) {
-            const int r = e / kTJ, jj = e % kTJ;
-            const long j = j0 + jj;
-            double v = 0.0;
-            if (j < N && r0 + r < nrhs) v = P.w[j] * x[(long)(r0 + r) * N + j];
-            swx[jj * kLdw + r] = v;
+        // stage the tile: coordinates and w_j x_j (zero for padding sources / columns);
+        // thread t stages source j0 + t % 64 for right-hand sides t / 64 + 4 q.  The
+        // loads use clamped, always valid indices and are masked afterwards, so all
+        // of them are in flight at once.
+        {
+            const int sj = tid & (kTJ - 1), sr = tid >> 6;
+            const long j = j0 + sj;
+            const bool jin = j < N;
+            const long jc = jin ? j : N - 1;
+            const double wj = jin ? P.w[jc] : 0.0;
+            if (sr < D) sxj[sr][sj] = jin ? P.pts[sr * N + jc] : 8.0 + sr;
+            double v[NB * 4];
+#pragma unroll
+            for (int q = 0; q < NB * 4; ++q) {
+                const int rr = min(r0 + sr + 4 * q, nrhs - 1);
+                v[q] = x[(long)rr * N + jc];
+            }
+#pragma unroll
+            for (int q = 0; q < NB * 4; ++q) {
+                const int r = sr + 4 * q;
+                swx[sj * kLdw + r] = (r0 + r < nrhs) ? wj * v[q] : 0.0;
+            }
         }
         __syncthreads();
 #pragma unroll 1
@@ -152,8 +159,8 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
                     r2 = fma(dx, dx, r2);
                 }
                 if constexpr (D == 2) {
-                    // the pair i == j enters as K(kSelfR2); the epilogue removes it
-                    a[rb] = kernel_r2<D>(fmax(r2, kSelfR2), stab);
+                    // the pair i == j enters with the finite value at r^2 = 0; the epilogue removes it
+                    a[rb] = kernel_r2<D>(r2, stab);
                 } else {
                     const double kv = kernel_r2<D>(r2, stab);
                     a[rb] = (j0 + jj == irow[rb]) ? 0.0 : kv;
@@ -177,8 +184,8 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
             const long i = ibase + rb * 16 + 4 * v + lk;
             if (i >= N) continue;
             const double bi = P.rs[i], di = P.diag[i];
-            // 2D: remove the self pair, which entered as K(kSelfR2) w_i x_i
-            const double selfw = (D == 2) ? kernel_r2<D>(kSelfR2, stab) * P.w[i] : 0.0;
+            // 2D: remove the self pair, which entered with the value at r^2 = 0
+            const double selfw = (D == 2) ? kernel_r2<D>(0.0, stab) * P.w[i] : 0.0;
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int r = r0 + nb * 16 + li;
@@ -192,18 +199,19 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
     }
 }
 
-// log F_j and 1/F_j, F_j = 1 + j/128, uploaded once per device.
+// c log F_j and 1/F_j (F_j = (1 + j/1024)/2, c = -1/(4 pi)), uploaded once per device.
 static const double* log_table() {
     static double* dtab[64] = {nullptr};
     int dev = 0;
     (void)hipGetDevice(&dev);
     if (dev < 0 || dev >= 64) return nullptr;
     if (!dtab[dev]) {
-        double h[2 * kLogTab];
+        static double h[2 * kLogTab];
+        const long double c = -0.25L / 3.141592653589793238462643383279502884L;
         for (int j = 0; j < kLogTab; ++j) {
-            const double F = 1.0 + j / 128.0;
-            h[2 * j] = std::log(F);
-            h[2 * j + 1] = 1.0 / F;
+            const long double F = 0.5L + (long double)j / (2.0L * kLogTab);
+            h[2 * j] = (double)(c * std::log(F));
+            h[2 * j + 1] = (double)(1.0L / F);
         }
         double* d = nullptr;
         if (hipMalloc(&d, sizeof(h)) != hipSuccess) return nullptr;
