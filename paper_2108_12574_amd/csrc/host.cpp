@@ -260,7 +260,8 @@ extern "C" int cbd_autotune_matvec(cbd_problem p, int nrhs, void* stream, int* c
     for (int rb : cand) {
         // every candidate runs on the same number of workgroups (4 per CU when the
         // grid is that large), so that occupancy and L2 reuse are comparable
-        const long full = (p->N + 64L * rb - 1) / (64L * rb);
+        const long rows = matvec_rows_per_block(rb);
+        const long full = (p->N + rows - 1) / rows;
         const int blocks = (int)std::min(full, 1024L);
         launch_matvec(p->view(), cols, x, y, rb, blocks, s);   // warm-up
         (void)hipEventRecord(a, s);
@@ -268,7 +269,7 @@ extern "C" int cbd_autotune_matvec(cbd_problem p, int nrhs, void* stream, int* c
         (void)hipEventRecord(b, s);
         float ms = 0.f;
         if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
-        const double per_row = ms / (double)(blocks * 64L * rb);
+        const double per_row = ms / (double)(blocks * rows);
         if (per_row < best_t) {
             best_t = per_row;
             best = rb;

@@ -34,10 +34,12 @@ void launch_assemble(int d, int n, int grid, const double* b, const double* c, d
                        w, rs, a_self, weight);
 }
 
-// y = A x on FP64 matrix cores.  A 256-thread workgroup owns 256 rows i (4 waves
-// x RB = 4 row blocks of 16) and up to 64 right-hand sides (NB blocks of 16).
-// Sources j stream through LDS in tiles of kTJ points (coordinates and w_j x_j,
-// stored [j][rhs]).  Per K-step of 4 sources every lane generates one kernel
+// y = A x on FP64 matrix cores.  A workgroup of kMvWaves waves owns
+// kMvWaves * RB * 16 rows i (RB row blocks of 16 per wave) and up to 64
+// right-hand sides (NB blocks of 16).  Sources j stream through LDS in tiles of
+// kTJ points: coordinates, and w_j x_j stored [rhs][j] with a row stride of
+// kTJ + 2 doubles, so that the staging writes and the B-operand reads both spread
+// over the LDS banks.  Per K-step of 4 sources every lane generates one kernel
 // value K(x_i - x_j) per row block on the VALU (lane l: i = l % 16, j = l / 16),
 // which is the A operand of v_mfma_f64_16x16x4f64 for all NB right-hand-side
 // blocks; the B operand is w_j x_j read from LDS (lane l: j = l / 16,
@@ -46,8 +48,9 @@ void launch_assemble(int d, int n, int grid, const double* b, const double* c, d
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kMvThreads = 256;
+constexpr int kMvWaves = kMvThreads / 64;
 constexpr int kTJ = 64;                // sources per LDS tile
-constexpr int kLdw = 66;               // LDS row stride of the [j][rhs] tile (doubles)
+constexpr int kLdw = kTJ + 2;          // LDS row stride of the [rhs][j] tile (doubles)
 constexpr int kLogTab = 1024;
 
 // 2D kernel value from r^2: K = -(1/2pi) log r = c log r^2, c = -1/(4 pi).
@@ -83,7 +86,8 @@ __device__ __forceinline__ double kernel_r2(double r2, const double* __restrict_
         return kInv4Pi * rsqrt(r2);
 }
 
-static_assert(kMvThreads == 4 * kTJ, "the staging assigns one source per thread and 4 threads per source");
+constexpr int kSR = kMvThreads / kTJ;  // staging threads per source
+static_assert(kMvThreads % kTJ == 0 && 64 % kSR == 0, "staging layout");
 
 template <int D, int NB, int kRB>
 __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
@@ -91,13 +95,13 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
                                                        double* __restrict__ y,
                                                        const double* __restrict__ logtab) {
     __shared__ double sxj[D][kTJ];
-    __shared__ double swx[kTJ * kLdw];
+    __shared__ double swx[64 * kLdw];
     __shared__ __attribute__((aligned(16))) double stab[2 * kLogTab];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const long N = P.N;
     const int r0 = blockIdx.y * 64;
-    const long ibase = (long)blockIdx.x * (4 * kRB * 16) + wave * (kRB * 16);
+    const long ibase = (long)blockIdx.x * (kMvWaves * kRB * 16) + wave * (kRB * 16);
     const int li = lane & 15, lk = lane >> 4;
     if (D == 2)
         for (int e = tid; e < 2 * kLogTab; e += kMvThreads) stab[e] = logtab[e];
@@ -120,26 +124,27 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
     for (long j0 = 0; j0 < N; j0 += kTJ) {
         __syncthreads();
         // stage the tile: coordinates and w_j x_j (zero for padding sources / columns);
-        // thread t stages source j0 + t % 64 for right-hand sides t / 64 + 4 q.  The
-        // loads use clamped, always valid indices and are masked afterwards, so all
-        // of them are in flight at once.
+        // thread t stages source j0 + t % kTJ for right-hand sides t / kTJ + kSR q.
+        // The loads use clamped, always valid indices and are masked afterwards, so
+        // all of them are in flight at once.
         {
-            const int sj = tid & (kTJ - 1), sr = tid >> 6;
+            const int sj = tid % kTJ, sr = tid / kTJ;
             const long j = j0 + sj;
             const bool jin = j < N;
             const long jc = jin ? j : N - 1;
             const double wj = jin ? P.w[jc] : 0.0;
             if (sr < D) sxj[sr][sj] = jin ? P.pts[sr * N + jc] : 8.0 + sr;
-            double v[NB * 4];
+            constexpr int kQ = NB * 16 / kSR;
+            double v[kQ];
 #pragma unroll
-            for (int q = 0; q < NB * 4; ++q) {
-                const int rr = min(r0 + sr + 4 * q, nrhs - 1);
+            for (int q = 0; q < kQ; ++q) {
+                const int rr = min(r0 + sr + kSR * q, nrhs - 1);
                 v[q] = x[(long)rr * N + jc];
             }
 #pragma unroll
-            for (int q = 0; q < NB * 4; ++q) {
-                const int r = sr + 4 * q;
-                swx[sj * kLdw + r] = (r0 + r < nrhs) ? wj * v[q] : 0.0;
+            for (int q = 0; q < kQ; ++q) {
+                const int r = sr + kSR * q;
+                swx[r * kLdw + sj] = (r0 + r < nrhs) ? wj * v[q] : 0.0;
             }
         }
         __syncthreads();
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
             }
             double b[NB];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) b[nb] = swx[jj * kLdw + nb * 16 + li];
+            for (int nb = 0; nb < NB; ++nb) b[nb] = swx[(nb * 16 + li) * kLdw + jj];
 #pragma unroll
             for (int rb = 0; rb < kRB; ++rb)
 #pragma unroll
@@ -226,7 +231,7 @@ bool matvec_prepare() { return log_table() != nullptr; }
 template <int D, int NB, int RB>
 static void matvec_launch(const ProblemView& P, int nrhs, const double* x, double* y, int max_blocks,
                           hipStream_t s) {
-    const int rows = 4 * RB * 16;
+    const int rows = matvec_rows_per_block(RB);
     int blocks = (int)((P.N + rows - 1) / rows);
     if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
     dim3 grid(blocks, (nrhs + 63) / 64);
@@ -242,6 +247,8 @@ static void matvec_rb(const ProblemView& P, int nrhs, const double* x, double* y
         default: matvec_launch<D, NB, 4>(P, nrhs, x, y, max_blocks, s); break;
     }
 }
+
+int matvec_rows_per_block(int rb) { return kMvWaves * 16 * rb; }
 
 // Right-hand-side blocks of 16 handled per launch column (the grid's y covers groups of 64).
 int matvec_nb(int nrhs) { return nrhs > 64 ? 4 : (nrhs + 15) / 16; }

@@ -118,6 +118,7 @@ void launch_assemble(int d, int n, int grid, const double* b, const double* c, d
 // first rows (used by the tile autotuner).
 void launch_matvec(const ProblemView& P, int nrhs, const double* x, double* y, int rb, int max_blocks,
                    hipStream_t s);
+int matvec_rows_per_block(int rb);
 int matvec_nb(int nrhs);
 bool matvec_prepare();   // per-device constant tables of the matvec (call outside stream capture)
 int matvec_default_rb(int nb);
