@@ -97,8 +97,9 @@ def main():
     ap.add_argument("--workload", default="512sq", choices=sorted(WORKLOADS))
     ap.add_argument("--fp64-cols", type=int, default=2,
                     help="columns solved one at a time to time the plain FP64 form")
-    ap.add_argument("--cpu-rows", type=int, default=192,
-                    help="rows of the oracle's dense matvec timed for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-rows", type=int, default=-1,
+                    help="rows of the oracle's dense matvec timed for the CPU baseline (0: skip; "
+                         "-1: about 12 s of host work, 16384 rows at 512^2 with 64 RHS)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the "
@@ -229,6 +230,9 @@ def main():
     log("fp64 form: factor %.3f s, %.3f s per column" % (f64_factor, f64_per_col))
 
     cpu = None
+    if args.cpu_rows < 0:
+        # the row cost is proportional to N * nrhs
+        args.cpu_rows = int(min(N, max(64, 16384.0 * (512 ** 2 * 64) / (float(N) * nrhs))))
     if args.cpu_rows > 0:
         from oracle import cmatvec, ie
         O = ie.Problem(d, n, b=None if coef is None else coef.numpy(), c=None if coef is None else coef.numpy())
