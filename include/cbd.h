@@ -49,6 +49,10 @@ extern "C" {
 #define CBD_PREC_BF16GEMM 2  /* as FP32, with the Schur-complement products (B_sr, B_rr, E, B_ss) on
                                 bfloat16 operands with FP32 accumulation */
 
+#define CBD_ROWS_AUTO 0      /* cbd_rs_opts.row_compression: see below */
+#define CBD_ROWS_NEVER 1
+#define CBD_ROWS_ALWAYS 2
+
 typedef struct cbd_problem_s* cbd_problem;
 typedef struct cbd_partition_s* cbd_partition;
 typedef struct cbd_factor_s* cbd_factor;
@@ -64,6 +68,12 @@ typedef struct {
     const float* mlp;    /* device parameters of the rank predictor (rank_mlp_*), or NULL.
                             Used only to schedule the pivoted QR; ranks and factors are
                             decided by the QR and do not depend on it. */
+    int row_compression; /* levels of the stepped pivoted QR: reduce each proxy matrix to
+                            its triangular factor R by an unpivoted Householder QR first
+                            (equal column norms, pivots and ID in exact arithmetic, fewer
+                            rows to stream per pivot step).  CBD_ROWS_AUTO (0): on levels
+                            whose matrices are at least twice as tall as wide and stream
+                            at least 512 MB per step; CBD_ROWS_NEVER; CBD_ROWS_ALWAYS */
 } cbd_rs_opts;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -166,8 +176,10 @@ int rs_factor_root(cbd_factor f, int i, int* S, int* idx, double* Ginv);
  *  rs_factor_features: training pairs of a factor's level: features (host, nbox x 6)
  *  and ranks (host, nbox), either may be NULL.
  *  rs_factor_schedule: stream synchronizations of the factorization, launch pairs of
- *  the stepped QR, boxes whose rank exceeded the predicted budget, and the mean
- *  absolute rank prediction error (0 without a predictor). */
+ *  the stepped QR, boxes whose rank exceeded the predicted budget, the mean
+ *  absolute rank prediction error (0 without a predictor), and the number of
+ *  levels whose proxy matrices were row-compressed before the pivoted QR.  Any
+ *  output may be NULL. */
 #define CBD_MLP_FEATURES 6
 #define CBD_MLP_WIDTH 64
 int rank_mlp_params(void);
@@ -179,7 +191,7 @@ int rank_mlp_adam(float* params, const float* grad, float* m, float* v, int step
                   void* stream);
 int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* X, int* k);
 int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
-                       double* mean_abs_err);
+                       double* mean_abs_err, int* row_compressed);
 
 /* rs_apply - z = T^{-1} r = sum_i R_i^T A_i^{-1} R_i r, (e:ad), with every A_i^{-1}
  * applied through its RS factor: gather, forward sweep over levels, root solve,

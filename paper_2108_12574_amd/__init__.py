@@ -12,11 +12,11 @@ import torch
 
 from . import _lib
 from ._lib import (GRID_CELL, GRID_NODE, MODE_CBD, MODE_JACOBI, MODE_SCHWARZ, PREC_BF16GEMM,
-                   PREC_FP32, PREC_FP64, CbdError, check, lib)
+                   PREC_FP32, PREC_FP64, ROWS_ALWAYS, ROWS_AUTO, ROWS_NEVER, CbdError, check, lib)
 
 __all__ = ["Problem", "Partition", "Factor", "RankMLP", "pcg_solve", "timing", "CbdError",
            "GRID_CELL", "GRID_NODE", "MODE_JACOBI", "MODE_SCHWARZ", "MODE_CBD",
-           "PREC_FP64", "PREC_FP32", "PREC_BF16GEMM"]
+           "PREC_FP64", "PREC_FP32", "PREC_BF16GEMM", "ROWS_AUTO", "ROWS_NEVER", "ROWS_ALWAYS"]
 
 
 def _free(fn, obj):
@@ -146,11 +146,11 @@ class Factor:
     """RS factors of all subdomain matrices (rs_factor_batched) and T^{-1} (rs_apply)."""
 
     def __init__(self, problem, partition, tol=1e-6, n_pxy=64, proxy_ratio=1.5,
-                 precision=PREC_FP64, exact=False, mlp=None):
+                 precision=PREC_FP64, exact=False, mlp=None, row_compression=ROWS_AUTO):
         self.problem, self.partition = problem, partition
         self.precision = precision
         opts = _lib.RSOpts(tol, n_pxy, proxy_ratio, precision, 1 if exact else 0,
-                           mlp.params.data_ptr() if mlp is not None else None)
+                           mlp.params.data_ptr() if mlp is not None else None, row_compression)
         h = ctypes.c_void_p()
         check(lib().rs_factor_batched(problem.handle, partition.handle, ctypes.byref(opts),
                                       _stream(problem.device), ctypes.byref(h)))
@@ -218,12 +218,13 @@ class Factor:
         return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
 
     def schedule(self):
-        """(stream synchronizations, stepped-QR launch pairs, mispredicted boxes, mean |k - k_pred|)."""
-        s, q, m, e = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        """Stream synchronizations, stepped-QR launch pairs, mispredicted boxes, mean |k - k_pred|
+        and row-compressed levels of the factorization (rs_factor_schedule)."""
+        s, q, m, e, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
         check(lib().rs_factor_schedule(self.handle, ctypes.byref(s), ctypes.byref(q), ctypes.byref(m),
-                                       ctypes.byref(e)))
+                                       ctypes.byref(e), ctypes.byref(c)))
         return {"host_syncs": s.value, "qr_steps": q.value, "mispredicted": m.value,
-                "mean_abs_err": e.value}
+                "mean_abs_err": e.value, "row_compressed": c.value}
 
     def root(self, i):
         import numpy as np

@@ -12,13 +12,14 @@ LIB_PATH = os.path.join(HERE, "libcbd.so")
 GRID_CELL, GRID_NODE = 0, 1
 MODE_JACOBI, MODE_SCHWARZ, MODE_CBD = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_BF16GEMM = 0, 1, 2
+ROWS_AUTO, ROWS_NEVER, ROWS_ALWAYS = 0, 1, 2
 OK, EARG, EHIP, ENOTSPD, ENOMEM, WNOTCONV = 0, -1, -2, -3, -4, 1
 
 
 class RSOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("n_pxy", ctypes.c_int),
                 ("proxy_ratio", ctypes.c_double), ("precision", ctypes.c_int),
-                ("exact", ctypes.c_int), ("mlp", ctypes.c_void_p)]
+                ("exact", ctypes.c_int), ("mlp", ctypes.c_void_p), ("row_compression", ctypes.c_int)]
 
 
 # (name, restype, argtypes) of every exported symbol of include/cbd.h
@@ -53,7 +54,7 @@ SIGNATURES = [
     ("rank_mlp_loss_grad", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("rank_mlp_adam", _i, [_vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp]),
     ("rs_factor_features", _i, [_vp, _i, _ip, ctypes.POINTER(ctypes.c_float), _ip]),
-    ("rs_factor_schedule", _i, [_vp, _ip, _ip, _ip, _dp]),
+    ("rs_factor_schedule", _i, [_vp, _ip, _ip, _ip, _dp, _ip]),
     ("cbd_timing_enable", _i, [_i]),
     ("cbd_timing_get", _i, [ctypes.c_char_p, _dp, ctypes.POINTER(_l)]),
     ("cbd_timing_reset", _i, []),

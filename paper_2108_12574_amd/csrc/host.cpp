@@ -636,6 +636,7 @@ struct cbd_factor_s {
     int host_syncs = 0;       // stream synchronizations issued by the factorization
     int qr_steps = 0;         // launch pairs of the stepped pivoted QR
     int mispredicted = 0;     // stepped boxes whose rank exceeded the predicted step budget
+    int hqr_levels = 0;       // stepped levels whose proxy matrices were row-compressed first
     double pred_abs_err = 0.0;
     int pred_count = 0;
     size_t esize;
@@ -712,7 +713,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
     const double tie = 1e-10;
     const bool bf16 = o->precision == CBD_PREC_BF16GEMM;
     std::vector<double> hdir = proxy_dirs(d, std::max(npxy, 1));
-    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf, mlpbuf, listbuf;
+    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf, mlpbuf, listbuf, hqrbuf;
     if ((rc = dirbuf.ensure(sizeof(double) * hdir.size()))) return rc;
     HIPCHK(hipMemcpyAsync(dirbuf.p, hdir.data(), sizeof(double) * hdir.size(), hipMemcpyHostToDevice, s));
     if ((rc = statbuf.ensure(sizeof(int)))) return rc;
@@ -896,6 +897,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         R* App = (R*)appbuf.p;
         R* FF = (R*)L.d_F;
         std::vector<int> kpred;
+        std::vector<BoxMeta> cm;   // compact metadata of row-compressed boxes (host copy kept for the upload)
         if (!root && o->mlp) {
             std::vector<float> feats((size_t)L.nbox * kMlpFeatures), yhat(L.nbox);
             for (int B = 0; B < L.nbox; ++B)
@@ -924,9 +926,48 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 launch_cpqr(L.nbox, L.d_meta, Y, L.d_act, L.d_sr, L.d_perm, L.d_k, T64, o->tol, tie,
                             L.m_max, L.np_max, s);
             } else {
-                // few (or large) boxes: stepped QR, every launch spread over all boxes' columns
-                if ((size_t)L.m_max * sizeof(double) > 65536)
-                    return fail(CBD_EARG, "rs_factor_batched: proxy matrix of " + std::to_string(L.m_max) +
+                // few (or large) boxes: stepped QR, every launch spread over all boxes' columns.
+                // Tall proxy matrices are first reduced to their triangular factor R (same
+                // column norms, pivots and ID in exact arithmetic), so each pivot step
+                // streams min(m, np) rows instead of m.
+                long sum_y = 0, sum_r = 0;
+                int k_max = 0;
+                for (const BoxMeta& M : L.meta) {
+                    sum_y += (long)M.m * M.np;
+                    sum_r += (long)std::min(M.m, M.np) * M.np;
+                    k_max = std::max(k_max, std::min(M.m, M.np));
+                }
+                const BoxMeta* qmeta = L.d_meta;
+                double* QY = Y;
+                int q_m_max = L.m_max;
+                const bool tall = sum_y >= 2 * sum_r && (double)sum_y * sizeof(double) >= 512.0 * (1 << 20);
+                if (o->row_compression == CBD_ROWS_ALWAYS || (o->row_compression == CBD_ROWS_AUTO && tall)) {
+                    cm = L.meta;
+                    long o_r = 0;
+                    q_m_max = 0;
+                    for (BoxMeta& M : cm) {
+                        M.m = std::min(M.m, M.np);
+                        M.y = o_r;
+                        o_r += (long)M.m * M.np;
+                        q_m_max = std::max(q_m_max, M.m);
+                    }
+                    const size_t nv = (size_t)L.nbox * kHqrVbuf(L.m_max);
+                    if ((rc = hqrbuf.ensure(sizeof(BoxMeta) * L.nbox +
+                                            sizeof(double) * ((size_t)L.nbox * kHqrTw + o_act + nv + std::max(o_r, 1L)))))
+                        return rc;
+                    BoxMeta* d_cm = (BoxMeta*)hqrbuf.p;
+                    double* Tw = (double*)(d_cm + L.nbox);
+                    double* halpha = Tw + (size_t)L.nbox * kHqrTw;
+                    double* Vb = halpha + o_act;
+                    double* Rc = Vb + nv;
+                    HIPCHK(hipMemcpyAsync(d_cm, cm.data(), sizeof(BoxMeta) * L.nbox, hipMemcpyHostToDevice, s));
+                    launch_hqr(L.nbox, L.np_max, L.m_max, k_max, L.d_meta, Y, Tw, halpha, Vb, d_cm, Rc, s);
+                    F->hqr_levels++;
+                    qmeta = d_cm;
+                    QY = Rc;
+                }
+                if ((size_t)q_m_max * sizeof(double) > 65536)
+                    return fail(CBD_EARG, "rs_factor_batched: proxy matrix of " + std::to_string(q_m_max) +
                                               " rows exceeds the LDS of the QR update kernel");
                 if ((rc = qrbuf.ensure(sizeof(double) * (3 * o_act + 2 * L.nbox) + sizeof(int) * (o_act + 2 * L.nbox))))
                     return rc;
@@ -938,7 +979,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 st.pv = (int*)(st.nu0 + L.nbox);
                 st.done = st.pv + o_act;
                 st.k = st.done + L.nbox;
-                launch_qr_init(L.nbox, L.np_max, L.d_meta, Y, st, s);
+                launch_qr_init(L.nbox, L.np_max, qmeta, QY, st, s);
                 int jmax = 0;
                 for (const BoxMeta& M : L.meta) jmax = std::max(jmax, std::min(M.m, M.np));
                 std::vector<int> done(L.nbox);
@@ -959,18 +1000,18 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                     int kmax_pred = 0;
                     for (int kp : kpred) kmax_pred = std::max(kmax_pred, kp);
                     const int budget = std::min(jmax + 1, (kmax_pred * 11 + 9) / 10 + 2);
-                    for (; j < budget; ++j) launch_qr_step(L.nbox, L.np_max, L.m_max, L.d_meta, Y, st, j, o->tol, tie, s);
+                    for (; j < budget; ++j) launch_qr_step(L.nbox, L.np_max, q_m_max, qmeta, QY, st, j, o->tol, tie, s);
                     F->qr_steps += budget;
                     if ((rc = all_done(all))) return rc;
                     if (!all)
                         for (int v : done) F->mispredicted += !v;
                 }
                 for (; !all && j <= jmax; ++j) {
-                    launch_qr_step(L.nbox, L.np_max, L.m_max, L.d_meta, Y, st, j, o->tol, tie, s);
+                    launch_qr_step(L.nbox, L.np_max, q_m_max, qmeta, QY, st, j, o->tol, tie, s);
                     F->qr_steps++;
                     if (j % 8 == 7 && (rc = all_done(all))) return rc;
                 }
-                launch_qr_finish(L.nbox, L.d_meta, Y, st, L.d_act, L.d_sr, L.d_perm, L.d_k, T64, s);
+                launch_qr_finish(L.nbox, L.np_max, qmeta, QY, st, L.d_act, L.d_sr, L.d_perm, L.d_k, T64, s);
             }
         } else {
             // root boxes: no compression, k = 0, identity order
@@ -1261,12 +1302,13 @@ extern "C" int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* 
 }
 
 extern "C" int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
-                                  double* mean_abs_err) {
+                                  double* mean_abs_err, int* row_compressed) {
     if (!f) return fail(CBD_EARG, "rs_factor_schedule: NULL factor");
     if (host_syncs) *host_syncs = f->host_syncs;
     if (qr_steps) *qr_steps = f->qr_steps;
     if (mispredicted) *mispredicted = f->mispredicted;
     if (mean_abs_err) *mean_abs_err = f->pred_count ? f->pred_abs_err / f->pred_count : 0.0;
+    if (row_compressed) *row_compressed = f->hqr_levels;
     return CBD_OK;
 }
 

@@ -144,8 +144,16 @@ void launch_qr_init(int nbox, int np_max, const BoxMeta* meta, const double* Y, 
                     hipStream_t s);
 void launch_qr_step(int nbox, int np_max, int m_max, const BoxMeta* meta, double* Y, const QrState& st,
                     int j, double tol, double tie, hipStream_t s);
-void launch_qr_finish(int nbox, const BoxMeta* meta, double* Y, const QrState& st, const int* act,
+void launch_qr_finish(int nbox, int np_max, const BoxMeta* meta, double* Y, const QrState& st, const int* act,
                       int* sr, int* perm, int* k, double* T64, hipStream_t s);
+// Row compression before the stepped pivoted QR: Householder QR of every box's Y
+// (meta), then R (min(m, np) x np) into Rc at the offsets of cmeta.  Tw: nbox x
+// kHqrTw doubles; alpha: one double per active DOF (meta's act offsets); Vbuf:
+// nbox x kHqrVbuf(m_max) doubles of reflector staging.
+constexpr int kHqrTw = 32 * 32;
+inline long kHqrVbuf(int m_max) { return 2L * m_max * 32; }
+void launch_hqr(int nbox, int np_max, int m_max, int k_max, const BoxMeta* meta, double* Y, double* Tw,
+                double* alpha, double* Vbuf, const BoxMeta* cmeta, double* Rc, hipStream_t s);
 template <typename R>
 void launch_box_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, const int* act,
                        const int* cidx, const ChildRef<R>* ch, R* App, hipStream_t s);

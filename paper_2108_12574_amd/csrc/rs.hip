@@ -93,8 +93,10 @@ void launch_proxy_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, co
 // Outputs: k, the pivot order (perm: positions, sr: slot ids, skeletons first),
 // and T (k x nr, column-major) at the box's factor offset of T64.
 
-// T = R11^{-1} R12 (R in the first k rows of Yb, T k x nr with ld k); defined below.
-__device__ void id_coefficients(const double* Yb, int m, int np, int k, double* T);
+// Columns [c_lo, c_hi) of T = R11^{-1} R12 (R in the first k rows of Yb, ld m;
+// T k x nr with ld k); defined below.  Columns are independent, so the T of a box
+// may be split over workgroups.
+__device__ void id_coefficients(const double* Yb, int m, int np, int k, double* T, int c_lo, int c_hi);
 
 // Householder update of trailing columns c in [c_lo, c_hi) (c > j) with the
 // reflector v (LDS, rows j..m-1), then their norm over rows j+1..m-1.
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_cpqr(const BoxMeta* __restrict__ m
         perm[M.act + c] = pv[c];
         sr[M.act + c] = act[M.act + pv[c]];
     }
-    id_coefficients(Yb, m, np, k, T64 + M.f);
+    id_coefficients(Yb, m, np, k, T64 + M.f, 0, np - k);
 }
 
 void launch_cpqr(int nbox, const BoxMeta* meta, double* Y, const int* act, int* sr, int* perm, int* k,
@@ -356,8 +358,7 @@ __global__ __launch_bounds__(kThreads) void k_qr_update(const BoxMeta* __restric
 __global__ __launch_bounds__(kThreads) void k_qr_finish(const BoxMeta* __restrict__ meta,
                                                         double* __restrict__ Y, QrState st,
                                                         const int* __restrict__ act, int* __restrict__ sr,
-                                                        int* __restrict__ perm, int* __restrict__ kout,
-                                                        double* __restrict__ T64) {
+                                                        int* __restrict__ perm, int* __restrict__ kout) {
     const int b = blockIdx.x;
     const BoxMeta M = meta[b];
     const int kmax = min(M.m, M.np);
@@ -370,8 +371,18 @@ __global__ __launch_bounds__(kThreads) void k_qr_finish(const BoxMeta* __restric
         perm[M.act + c] = p;
         sr[M.act + c] = act[M.act + p];
     }
-    __syncthreads();
-    id_coefficients(Yb, M.m, M.np, k, T64 + M.f);
+}
+
+// T = R11^{-1} R12 of the stepped boxes, kCoeffCols columns of T per workgroup.
+constexpr int kCoeffCols = 64;
+__global__ __launch_bounds__(kThreads) void k_qr_coeff(const BoxMeta* __restrict__ meta,
+                                                       const double* __restrict__ Y, const int* __restrict__ kin,
+                                                       double* __restrict__ T64) {
+    const BoxMeta M = meta[blockIdx.x];
+    const int k = kin[blockIdx.x];
+    const int c_lo = blockIdx.y * kCoeffCols, c_hi = min(M.np - k, c_lo + kCoeffCols);
+    if (c_lo >= c_hi) return;
+    id_coefficients(Y + M.y, M.m, M.np, k, T64 + M.f, c_lo, c_hi);
 }
 
 void launch_qr_init(int nbox, int np_max, const BoxMeta* meta, const double* Y, const QrState& st,
@@ -387,10 +398,276 @@ void launch_qr_step(int nbox, int np_max, int m_max, const BoxMeta* meta, double
     hipLaunchKernelGGL(k_qr_update, dim3(nbox, (np_max + kQrCols - 1) / kQrCols), dim3(kThreads),
                        (size_t)m_max * sizeof(double), s, meta, Y, st, j);
 }
-void launch_qr_finish(int nbox, const BoxMeta* meta, double* Y, const QrState& st, const int* act,
+void launch_qr_finish(int nbox, int np_max, const BoxMeta* meta, double* Y, const QrState& st, const int* act,
                       int* sr, int* perm, int* k, double* T64, hipStream_t s) {
     if (nbox == 0) return;
-    hipLaunchKernelGGL(k_qr_finish, dim3(nbox), dim3(kThreads), 0, s, meta, Y, st, act, sr, perm, k, T64);
+    hipLaunchKernelGGL(k_qr_finish, dim3(nbox), dim3(kThreads), 0, s, meta, Y, st, act, sr, perm, k);
+    hipLaunchKernelGGL(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s,
+                       meta, Y, k, T64);
+}
+
+// ---- row compression of tall proxy matrices ---------------------------------
+// Householder QR without pivoting, Y = Q R, by panels of kHqrPanel columns in
+// the compact WY form H_1 ... H_w = I - V T V^T (T upper triangular).  Column
+// norms of every trailing block, and with them the pivots, the stopping step and
+// R11, R12 of the truncated pivoted QR, are invariant under Q^T, so the pivoted
+// QR can run on the min(m, np) x np factor R instead of the m x np matrix Y.
+// Reflectors: v_c = Y[c:, c] - alpha_c e_1 kept in place of column c (rows >= c),
+// beta_c = 2 / ||v_c||^2, alpha_c (the diagonal of R) in a side array.  Each
+// panel's reflectors are also written, zero-padded, to a per-box buffer in two
+// layouts (Vc: m x kHqrPanel column-major; Vt: kHqrPanel x m) for the MFMA
+// operands of the trailing update.
+constexpr int kHqrPanel = 32;
+static_assert(kHqrPanel * kHqrPanel == kHqrTw, "T slot size");
+
+constexpr int kHqrThreads = 512;   // panel workgroup: more rows in flight per step
+constexpr int kHqrWaves = kHqrThreads / 64;
+
+// One workgroup per box.  Step jj: one pass over the panel rows computes, for
+// every other panel column q, v_jj . Y[:, j0+q] (q < jj: a column of the Gram
+// matrix of the reflectors, for T; q > jj: the reflection coefficients); a
+// second pass applies the reflection and accumulates the next column's norm.
+__global__ __launch_bounds__(kHqrThreads) void k_hqr_panel(const BoxMeta* __restrict__ meta, double* __restrict__ Y,
+                                                        int j0, double* __restrict__ Tw,
+                                                        double* __restrict__ alpha, double* __restrict__ Vbuf,
+                                                        long vstride) {
+    __shared__ double red[kHqrPanel][kHqrWaves];
+    __shared__ double s_sc[kHqrPanel];
+    __shared__ double s_T[kHqrPanel * kHqrPanel];
+    __shared__ double s_x0, s_xn2;
+    const int b = blockIdx.x;
+    const BoxMeta M = meta[b];
+    const int m = M.m, np = M.np, kmax = min(m, np);
+    if (j0 >= kmax) return;
+    const int w = min(kHqrPanel, kmax - j0);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double* Yb = Y + M.y;
+    double* P = Yb + (long)j0 * m;          // panel column q at P + q * m
+    for (int e = tid; e < kHqrPanel * kHqrPanel; e += kHqrThreads) s_T[e] = 0.0;
+    // norm^2 of the first column over rows j0..
+    {
+        double q = 0.0;
+        for (int r = j0 + tid; r < m; r += kHqrThreads) q += P[r] * P[r];
+        q = wave_sum(q);
+        if (lane == 0) red[0][wid] = q;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int v = 0; v < kHqrWaves; ++v) t += red[0][v];
+            s_xn2 = t;
+        }
+        __syncthreads();
+    }
+    for (int jj = 0; jj < w; ++jj) {
+        const int c = j0 + jj;
+        double* vc = P + (long)jj * m;
+        // reflector of column c
+        if (tid == 0) {
+            const double xn = sqrt(s_xn2);
+            const double x0 = vc[c];
+            const double al = x0 >= 0.0 ? -xn : xn;
+            const double vn2 = 2.0 * xn * xn + 2.0 * fabs(x0) * xn;
+            const double beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+            vc[c] = x0 - al;
+            alpha[M.act + c] = al;
+            s_T[jj + jj * kHqrPanel] = beta;
+        }
+        __syncthreads();
+        // pass 1: v . Y[:, j0 + q] for every panel column q != jj (rows c..).  All
+        // loads are unconditional (column index clamped into the panel) so that they
+        // are in flight together; the unused products are masked.
+        double part[kHqrPanel];
+#pragma unroll
+        for (int q = 0; q < kHqrPanel; ++q) part[q] = 0.0;
+        for (int r = c + tid; r < m; r += kHqrThreads) {
+            const double v = vc[r];
+            double y[kHqrPanel];
+#pragma unroll
+            for (int q = 0; q < kHqrPanel; ++q) y[q] = P[r + (long)min(q, w - 1) * m];
+#pragma unroll
+            for (int q = 0; q < kHqrPanel; ++q) part[q] += (q != jj && q < w) ? v * y[q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kHqrPanel; ++q) {
+            if (q == jj || q >= w) continue;
+            const double t = wave_sum(part[q]);
+            if (lane == 0) red[q][wid] = t;
+        }
+        __syncthreads();
+        const double beta = s_T[jj + jj * kHqrPanel];
+        if (tid < w && tid != jj) {
+            double t = 0.0;
+            for (int v = 0; v < kHqrWaves; ++v) t += red[tid][v];
+            s_sc[tid] = tid > jj ? beta * t : t;     // reflection coefficient, or Gram entry G[tid][jj]
+        }
+        __syncthreads();
+        // T[0:jj, jj] = -beta T[0:jj, 0:jj] G[0:jj, jj]
+        if (tid < jj) {
+            double t = 0.0;
+            for (int a2 = tid; a2 < jj; ++a2) t += s_T[tid + a2 * kHqrPanel] * s_sc[a2];
+            s_T[tid + jj * kHqrPanel] = -beta * t;
+        }
+        // pass 2: Y[:, j0 + q] -= s_q v for q > jj (rows c..), and the next column's
+        // norm; loads clamped to the columns jj+1..w-1 as in pass 1
+        double nx = 0.0;
+        if (jj + 1 < w) {
+            for (int r = c + tid; r < m; r += kHqrThreads) {
+                const double v = vc[r];
+                double y[kHqrPanel];
+#pragma unroll
+                for (int q = 0; q < kHqrPanel; ++q) y[q] = P[r + (long)min(max(q, jj + 1), w - 1) * m];
+#pragma unroll
+                for (int q = 0; q < kHqrPanel; ++q) {
+                    if (q <= jj || q >= w) continue;
+                    const double yn = y[q] - s_sc[q] * v;
+                    P[r + (long)q * m] = yn;
+                    if (q == jj + 1 && r > c) nx += yn * yn;
+                }
+            }
+        }
+        nx = wave_sum(nx);
+        if (lane == 0) red[0][wid] = nx;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int v = 0; v < kHqrWaves; ++v) t += red[0][v];
+            s_xn2 = t;
+        }
+        __syncthreads();
+    }
+    double* Tb = Tw + (long)b * kHqrTw;
+    for (int e = tid; e < kHqrPanel * kHqrPanel; e += kHqrThreads) Tb[e] = s_T[e];
+    // zero-padded reflectors in both layouts (rows j0..m-1)
+    double* Vc = Vbuf + (long)b * vstride;
+    double* Vt = Vc + (long)m * kHqrPanel;
+    for (long e = tid; e < (long)(m - j0) * kHqrPanel; e += kHqrThreads) {
+        const int r = j0 + (int)(e % (m - j0)), a = (int)(e / (m - j0));
+        const double v = (a < w && r >= j0 + a) ? P[r + (long)a * m] : 0.0;
+        Vc[r + (long)a * m] = v;
+    }
+    for (long e = tid; e < (long)(m - j0) * kHqrPanel; e += kHqrThreads) {
+        const int a = (int)(e % kHqrPanel), r = j0 + (int)(e / kHqrPanel);
+        const double v = (a < w && r >= j0 + a) ? P[r + (long)a * m] : 0.0;
+        Vt[a + (long)r * kHqrPanel] = v;
+    }
+}
+
+// Trailing columns c >= j0 + w, 16 per workgroup: A <- A - V (T^T (V^T A)), both
+// products on FP64 MFMA (v_mfma_f64_16x16x4f64).  W = V^T A splits its rows over
+// the waves; A - V W' takes 16-row tiles per wave.
+__global__ __launch_bounds__(kThreads) void k_hqr_update(const BoxMeta* __restrict__ meta, double* __restrict__ Y,
+                                                         int j0, const double* __restrict__ Tw,
+                                                         const double* __restrict__ Vbuf, long vstride) {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __shared__ double s_T[kHqrPanel * kHqrPanel];
+    __shared__ double s_P[kWaves][kHqrPanel * 16];
+    __shared__ double s_W[kHqrPanel * 16];
+    const int b = blockIdx.x;
+    const BoxMeta M = meta[b];
+    const int m = M.m, np = M.np, kmax = min(m, np);
+    if (j0 >= kmax) return;
+    const int w = min(kHqrPanel, kmax - j0);
+    const int c0 = (int)blockIdx.y * 16;
+    const int lo = max(j0 + w, c0), hi = min(np, c0 + 16);
+    if (lo >= hi) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    double* Yb = Y + M.y;
+    const double* Vc = Vbuf + (long)b * vstride;
+    const double* Vt = Vc + (long)m * kHqrPanel;
+    const double* Tb = Tw + (long)b * kHqrTw;
+    for (int e = tid; e < kHqrPanel * kHqrPanel; e += kThreads) s_T[e] = Tb[e];
+    const int col = c0 + li;
+    const bool cin = col >= lo && col < hi;
+    const double* ycol = Yb + (long)(cin ? col : lo) * m;
+    // W = V^T A: rows j0.. in 4-row steps, step s on wave s % kWaves
+    v4 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
+    for (int r0 = j0 + 4 * wid; r0 < m; r0 += 4 * kWaves) {
+        const int r = r0 + lk;
+        const bool rin = r < m;
+        const double a0 = rin ? Vt[li + (long)r * kHqrPanel] : 0.0;
+        const double a1 = rin ? Vt[16 + li + (long)r * kHqrPanel] : 0.0;
+        const double bb = (rin && cin) ? ycol[r] : 0.0;
+        w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb, w0, 0, 0, 0);
+        w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb, w1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int a = 4 * v + lk;            // accumulator row
+        s_P[wid][a + li * kHqrPanel] = w0[v];
+        s_P[wid][16 + a + li * kHqrPanel] = w1[v];
+    }
+    __syncthreads();
+    for (int e = tid; e < kHqrPanel * 16; e += kThreads) {
+        double t = 0.0;
+        for (int v = 0; v < kWaves; ++v) t += s_P[v][e];
+        s_W[e] = t;
+    }
+    __syncthreads();
+    // W' = -T^T W (T upper triangular: row a of T^T has entries a2 <= a), into s_P[0]
+    for (int e = tid; e < kHqrPanel * 16; e += kThreads) {
+        const int a = e % kHqrPanel, cc = e / kHqrPanel;
+        double t = 0.0;
+        for (int a2 = 0; a2 <= a; ++a2) t += s_T[a2 + a * kHqrPanel] * s_W[a2 + cc * kHqrPanel];
+        s_P[0][e] = -t;
+    }
+    __syncthreads();
+    // A += V W' over 16-row tiles (rows j0..m-1)
+    const double* Wn = s_P[0];
+    for (int t0 = j0 + 16 * wid; t0 < m; t0 += 16 * kWaves) {
+        v4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = t0 + 4 * v + lk;
+            acc[v] = (r < m && cin) ? ycol[r] : 0.0;
+        }
+        const int ra = t0 + li;
+#pragma unroll
+        for (int ks = 0; ks < kHqrPanel / 4; ++ks) {
+            const int a = 4 * ks + lk;
+            const double av = ra < m ? Vc[ra + (long)a * m] : 0.0;
+            const double bv = Wn[a + li * kHqrPanel];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        if (cin) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = t0 + 4 * v + lk;
+                if (r < m) Yb[r + (long)col * m] = acc[v];
+            }
+        }
+    }
+}
+
+// R (min(m, np) x np, zero below the diagonal) of every box into the compact
+// layout of cmeta (cmeta[b].y; cmeta[b].m = min(m, np)).
+__global__ __launch_bounds__(kThreads) void k_hqr_compact(const BoxMeta* __restrict__ meta,
+                                                          const double* __restrict__ Y,
+                                                          const double* __restrict__ alpha,
+                                                          const BoxMeta* __restrict__ cmeta,
+                                                          double* __restrict__ Rc) {
+    const int b = blockIdx.x;
+    const BoxMeta M = meta[b];
+    const int mr = cmeta[b].m;
+    const double* Yb = Y + M.y;
+    double* Rb = Rc + cmeta[b].y;
+    for (long e = (long)blockIdx.y * kThreads + threadIdx.x; e < (long)mr * M.np; e += (long)gridDim.y * kThreads) {
+        const int r = (int)(e % mr), c = (int)(e / mr);
+        Rb[e] = r < c ? Yb[r + (long)c * M.m] : (r == c ? alpha[M.act + c] : 0.0);
+    }
+}
+
+void launch_hqr(int nbox, int np_max, int m_max, int k_max, const BoxMeta* meta, double* Y, double* Tw,
+                double* alpha, double* Vbuf, const BoxMeta* cmeta, double* Rc, hipStream_t s) {
+    if (nbox == 0) return;
+    const long vstride = 2L * m_max * kHqrPanel;
+    const int ct = (np_max + 15) / 16;
+    for (int j0 = 0; j0 < k_max; j0 += kHqrPanel) {
+        hipLaunchKernelGGL(k_hqr_panel, dim3(nbox), dim3(kHqrThreads), 0, s, meta, Y, j0, Tw, alpha, Vbuf, vstride);
+        if (j0 + kHqrPanel < np_max)
+            hipLaunchKernelGGL(k_hqr_update, dim3(nbox, ct), dim3(kThreads), 0, s, meta, Y, j0, Tw, Vbuf, vstride);
+    }
+    hipLaunchKernelGGL(k_hqr_compact, dim3(nbox, 16), dim3(kThreads), 0, s, meta, Y, alpha, cmeta, Rc);
 }
 
 // ---- box matrix A_pp --------------------------------------------------------
@@ -560,11 +837,13 @@ __device__ __forceinline__ void schur_gemm(int M, int N, int K, R alpha, const R
 // T = R11^{-1} R12 by blocked back substitution over 16-row blocks, bottom up:
 // T_I = R_II^{-1} (R12_I - R_{I,>I} T_{>I}); the update is an MFMA GEMM, the
 // diagonal solve one column per thread.  All threads of the workgroup call it.
-__device__ void id_coefficients(const double* Yb, int m, int np, int k, double* T) {
-    const int nr = np - k;
+__device__ void id_coefficients(const double* Yb, int m, int np, int k, double* T, int c_lo, int c_hi) {
+    const int nr = c_hi - c_lo;
+    if (nr <= 0 || k == 0) return;
+    T += (long)c_lo * k;
     for (long e = threadIdx.x; e < (long)k * nr; e += kThreads) {
         const int a = (int)(e % k), c = (int)(e / k);
-        T[e] = Yb[a + (long)(k + c) * m];
+        T[e] = Yb[a + (long)(k + c_lo + c) * m];
     }
     __syncthreads();
     const int nblk = (k + 15) / 16;

@@ -75,3 +75,14 @@ def test_partition_matches_oracle(d, n, m, delta, mode, leaf):
                         assert parent[ch] == c
             else:
                 assert parent == [-1]
+
+
+def test_header_constants_match_the_binding():
+    # every #define CBD_<NAME> <int> of the header equals the binding's <NAME> where it has one
+    hdr = open(os.path.join(ROOT, "include", "cbd.h")).read()
+    seen = 0
+    for name, val in re.findall(r"#define CBD_([A-Z0-9_]+)\s+\(?(-?\d+)\)?", hdr):
+        if hasattr(_lib, name):
+            assert getattr(_lib, name) == int(val), name
+            seen += 1
+    assert seen >= 15

@@ -458,3 +458,40 @@ def test_full_size_1024_fft_sampled():
     rows = rng.choice(O.N, 16, replace=False)
     res = fr[rows] - cmatvec.matvec(O, u.cpu().numpy(), rows=rows)
     assert np.sqrt(np.mean(res ** 2)) <= 1e-8 * np.linalg.norm(fr) / np.sqrt(O.N)
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_row_compression_keeps_the_ids(case):
+    # the pivoted QR on the Householder R of each tall proxy matrix picks the same
+    # skeletons as on the matrix itself (equal column norms in exact arithmetic);
+    # T agrees to the conditioning of R11
+    if case == "2d":
+        P, _ = gpu_problem(2, 64)
+        part, tol, npxy = cbd.Partition(P, 16, 1, cbd.MODE_CBD, 0), 1e-8, 64
+    else:
+        P, _ = gpu_problem(3, 16)
+        part, tol, npxy = cbd.Partition(P, 4, 1, cbd.MODE_CBD, 0), 1e-6, 256
+    Fc = cbd.Factor(P, part, tol=tol, n_pxy=npxy, row_compression=cbd.ROWS_ALWAYS)
+    Fp = cbd.Factor(P, part, tol=tol, n_pxy=npxy, row_compression=cbd.ROWS_NEVER)
+    sc, sp = Fc.schedule(), Fp.schedule()
+    print(case, "row-compressed levels", sc["row_compressed"], "vs", sp["row_compressed"], flush=True)
+    assert sc["row_compressed"] > 0 and sp["row_compressed"] == 0
+    nlev = Fc.stats()["levels"]
+    for l in range(nlev):
+        assert Fc.level(l) == Fp.level(l), l
+    worst, nbox = 0.0, 0
+    for l in range(nlev):
+        count = {}
+        for i in Fc.level(l)[2]:
+            b = count.get(i, 0)
+            count[i] = b + 1
+            gc, gp = Fc.box(i, l, b), Fp.box(i, l, b)
+            assert np.array_equal(gc["sk"], gp["sk"]) and np.array_equal(gc["rd"], gp["rd"]), (l, i, b)
+            if gc["T"].size:
+                worst = max(worst, rel(gc["T"], gp["T"]))
+            nbox += 1
+    print(case, nbox, "boxes, max rel T difference", worst, flush=True)
+    assert worst <= 1e-6
+    r = torch.tensor(synth.rhs(P.N, 2, seed=1), device=DEV)
+    zc, zp = Fc.apply(r), Fp.apply(r)
+    assert (zc - zp).norm() <= 1e-8 * zp.norm()
