@@ -4,12 +4,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/cbd.h"
@@ -725,10 +727,17 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         for (auto& sd : Q->subs) Lmax = std::max(Lmax, sd.root_level);
     F->n_compress = Lmax;
     // grid coordinates of a global index
-    auto coord = [&](int g, int t) {
-        for (int u = 0; u < t; ++u) g /= n;
-        return g % n;
-    };
+    // half-cell coordinates 2 j_t + 1 of every slot (near-field tests in integers)
+    const long nslot = (long)Q->cidx.size();
+    std::vector<int> hc((size_t)d * nslot);
+    for (long e = 0; e < nslot; ++e) {
+        int g = Q->cidx[e];
+        for (int t = 0; t < d; ++t) {
+            hc[(size_t)t * nslot + e] = 2 * (g % n) + 1;
+            g /= n;
+        }
+    }
+    const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
 
     for (int l = 0; l <= Lmax; ++l) {
         const bool root = (l == Lmax);
@@ -786,23 +795,58 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 L.nbox++;
             }
         }
-        // near fields (compressed levels only), per subdomain
+        // near fields (compressed levels only), per subdomain.  Candidate boxes come
+        // from a uniform bucket grid over the boxes' lower corners (cell = the
+        // largest box side), so the search is linear in the number of boxes.
         std::vector<std::vector<int>> nearl(L.nbox);
         if (!root) {
             for (int i = 0; i < D; ++i) {
                 if (L.sub_start[i] < 0) continue;
                 const int b0 = L.sub_start[i];
                 const int nb = (int)Q->subs[i].levels[l].size();
+                int smax = 1, glo[3] = {INT_MAX, INT_MAX, INT_MAX}, ghi[3] = {0, 0, 0};
+                for (int b = 0; b < nb; ++b)
+                    for (int t = 0; t < d; ++t) {
+                        smax = std::max(smax, bhi[(b0 + b) * 3 + t] - blo[(b0 + b) * 3 + t]);
+                        glo[t] = std::min(glo[t], blo[(b0 + b) * 3 + t]);
+                        ghi[t] = std::max(ghi[t], blo[(b0 + b) * 3 + t]);
+                    }
+                int gdim[3] = {1, 1, 1};
+                for (int t = 0; t < d; ++t) gdim[t] = (ghi[t] - glo[t]) / smax + 1;
+                std::vector<std::vector<int>> bucket((size_t)gdim[0] * gdim[1] * gdim[2]);
+                auto cell_of = [&](int t, int x) { return std::min(gdim[t] - 1, std::max(0, (x - glo[t]) / smax)); };
                 for (int b = 0; b < nb; ++b) {
+                    long cidx = 0;
+                    for (int t = d - 1; t >= 0; --t) cidx = cidx * gdim[t] + cell_of(t, blo[(b0 + b) * 3 + t]);
+                    bucket[cidx].push_back(b);
+                }
+                // boxes are independent: split them over host threads
+                auto near_of = [&](int b) {
                     const int B = b0 + b;
                     int Lside = 0;
-                    long c2[3];
+                    long c2[3] = {0, 0, 0};
                     for (int t = 0; t < d; ++t) {
                         Lside = std::max(Lside, bhi[B * 3 + t] - blo[B * 3 + t]);
                         c2[t] = blo[B * 3 + t] + bhi[B * 3 + t];
                     }
-                    const double R2 = (2.0 * o->proxy_ratio * Lside) * (2.0 * o->proxy_ratio * Lside);
-                    for (int b2 = 0; b2 < nb; ++b2) {
+                    const double rad = o->proxy_ratio * Lside;          // grid units
+                    const double R2 = (2.0 * rad) * (2.0 * rad);        // half-cell units, squared
+                    int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
+                    for (int t = 0; t < d; ++t) {
+                        // a box reaching within rad of the centre has its lower corner in
+                        // [centre - rad - smax, centre + rad]
+                        clo[t] = cell_of(t, (int)std::floor(0.5 * c2[t] - rad) - smax);
+                        chi[t] = cell_of(t, (int)std::ceil(0.5 * c2[t] + rad));
+                    }
+                    std::vector<int> cand;
+                    for (int z = clo[2]; z <= chi[2]; ++z)
+                        for (int y = clo[1]; y <= chi[1]; ++y)
+                            for (int x = clo[0]; x <= chi[0]; ++x) {
+                                const auto& bk = bucket[((size_t)z * gdim[1] + y) * gdim[0] + x];
+                                cand.insert(cand.end(), bk.begin(), bk.end());
+                            }
+                    std::sort(cand.begin(), cand.end());   // the order of an all-pairs scan
+                    for (int b2 : cand) {
                         if (b2 == b) continue;
                         const int B2 = b0 + b2;
                         double md = 0.0;
@@ -813,15 +857,25 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                         }
                         if (md >= R2) continue;
                         for (int slot : act[B2]) {
-                            const int g = Q->cidx[slot];
-                            double s2 = 0.0;
+                            long s2 = 0;
                             for (int t = 0; t < d; ++t) {
-                                double off = 2.0 * coord(g, t) + 1.0 - (double)c2[t];
+                                const long off = hc[(size_t)t * nslot + slot] - c2[t];
                                 s2 += off * off;
                             }
-                            if (s2 < R2) nearl[B].push_back(slot);
+                            if ((double)s2 < R2) nearl[B].push_back(slot);
                         }
                     }
+                };
+                const int nt = std::min(nthreads, std::max(1, nb / 64));
+                if (nt <= 1) {
+                    for (int b = 0; b < nb; ++b) near_of(b);
+                } else {
+                    std::vector<std::thread> pool;
+                    for (int w = 0; w < nt; ++w)
+                        pool.emplace_back([&, w] {
+                            for (int b = w; b < nb; b += nt) near_of(b);
+                        });
+                    for (auto& th : pool) th.join();
                 }
             }
         }
