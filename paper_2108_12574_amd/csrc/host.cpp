@@ -1103,11 +1103,11 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             HIPCHK(hipMemcpyAsync(d_small, lists.data(), sizeof(int) * lists.size(), hipMemcpyHostToDevice, s));
             launch_eliminate<R>((int)small.size(), L.d_meta, d_small, 0, L.d_perm, L.d_k, App, T64, Wk, FF,
                                 d_status, bf16, s);
-            launch_eliminate<R>((int)big.size(), L.d_meta, d_big, 1, L.d_perm, L.d_k, App, T64, Wk, FF,
-                                d_status, bf16, s);
+            launch_big_schur<R>((int)big.size(), np_big, L.d_meta, d_big, 1, L.d_perm, L.d_k, App, T64, Wk, FF,
+                                bf16, s);
             launch_big_cholesky_inverse<R>((int)big.size(), np_big, L.d_meta, d_big, L.d_k, Wk, FF, d_status, s);
-            launch_eliminate<R>((int)big.size(), L.d_meta, d_big, 2, L.d_perm, L.d_k, App, T64, Wk, FF,
-                                d_status, bf16, s);
+            launch_big_schur<R>((int)big.size(), np_big, L.d_meta, d_big, 2, L.d_perm, L.d_k, App, T64, Wk, FF,
+                                bf16, s);
             HIPCHK(hipStreamSynchronize(s));   // `lists` is read by the copy above
             F->host_syncs++;
         }

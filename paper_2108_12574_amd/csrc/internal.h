@@ -163,6 +163,11 @@ template <typename R>
 void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, int phase, const int* perm,
                       const int* k, const R* App, const double* T64, R* Wk, R* F, int* status,
                       bool bf16, hipStream_t s);
+// the elimination of the boxes in list as multi-workgroup launches: phase 1 up to B_rr,
+// phase 2 E and B_ss (the same arithmetic as launch_eliminate's phases 1 and 2)
+template <typename R>
+void launch_big_schur(int nbig, int np_max, const BoxMeta* meta, const int* list, int phase, const int* perm,
+                      const int* k, const R* App, const double* T64, R* Wk, R* F, bool bf16, hipStream_t s);
 // multi-workgroup blocked Cholesky of B_rr and G^{-1} for the boxes in list (after phase 1)
 template <typename R>
 void launch_big_cholesky_inverse(int nbig, int nr_max, const BoxMeta* meta, const int* list, const int* k,

@@ -745,33 +745,48 @@ struct Mma<float> {
 // workgroup call it; 16 x 16 output tiles are spread over the waves.  With
 // upper != 0 tiles entirely below the diagonal are skipped (symmetric results
 // whose upper triangle is used).  Ends with a workgroup barrier.
+// One 16 x 16 tile (rows i0.., columns j0..) of C = beta C_in + alpha op(A) op(B),
+// computed by one wave; C_in may be C itself.
+template <typename R>
+__device__ __forceinline__ void tile_gemm(int i0, int j0, int M, int N, int K, R alpha, const R* A, int lda,
+                                          bool ta, const R* B, int ldb, bool tb, R beta, const R* Cin, R* C,
+                                          int ldc) {
+    typedef typename Mma<R>::v4 v4;
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    v4 acc = {0, 0, 0, 0};
+    const int i = i0 + li, j = j0 + li;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int kk = k0 + lk;
+        R a = 0, b = 0;
+        if (i < M && kk < K) a = ta ? A[kk + (long)i * lda] : A[i + (long)kk * lda];
+        if (j < N && kk < K) b = tb ? B[j + (long)kk * ldb] : B[kk + (long)j * ldb];
+        acc = Mma<R>::op(a, b, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int ii = i0 + Mma<R>::row(v, lane), jj = j0 + li;
+        if (ii < M && jj < N) {
+            const long o = ii + (long)jj * ldc;
+            C[o] = (beta == (R)0 ? (R)0 : beta * Cin[o]) + alpha * acc[v];
+        }
+    }
+}
+
+// C (M x N, column-major, ldc) = beta C + alpha op(A) op(B), op(A) M x K, op(B) K x N;
+// ta/tb select the transposes (A[k + i*lda] / B[j + k*ldb]).  All threads of the
+// workgroup call it; 16 x 16 output tiles are spread over the waves.  With
+// upper != 0 tiles entirely below the diagonal are skipped (symmetric results
+// whose upper triangle is used).  Ends with a workgroup barrier.
 template <typename R>
 __device__ void wg_gemm(int M, int N, int K, R alpha, const R* A, int lda, bool ta, const R* B, int ldb,
                         bool tb, R beta, R* C, int ldc, bool upper = false) {
-    typedef typename Mma<R>::v4 v4;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wid = threadIdx.x >> 6;
     const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
-    const int li = lane & 15, lk = lane >> 4;
     for (int t = wid; t < tm * tn; t += kWaves) {
         const int i0 = (t % tm) << 4, j0 = (t / tm) << 4;
         if (upper && i0 > j0 + 15) continue;
-        v4 acc = {0, 0, 0, 0};
-        const int i = i0 + li, j = j0 + li;
-        for (int k0 = 0; k0 < K; k0 += 4) {
-            const int kk = k0 + lk;
-            R a = 0, b = 0;
-            if (i < M && kk < K) a = ta ? A[kk + (long)i * lda] : A[i + (long)kk * lda];
-            if (j < N && kk < K) b = tb ? B[j + (long)kk * ldb] : B[kk + (long)j * ldb];
-            acc = Mma<R>::op(a, b, acc);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int ii = i0 + Mma<R>::row(v, lane), jj = j0 + li;
-            if (ii < M && jj < N) {
-                R* c = C + ii + (long)jj * ldc;
-                *c = (beta == (R)0 ? (R)0 : beta * *c) + alpha * acc[v];
-            }
-        }
+        tile_gemm<R>(i0, j0, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, C, ldc);
     }
     __syncthreads();
 }
@@ -787,38 +802,45 @@ __device__ __forceinline__ short bf16_bits(float x) {
     return (short)u;
 }
 
+__device__ __forceinline__ void tile_gemm_bf16(int i0, int j0, int M, int N, int K, float alpha, const float* A,
+                                               int lda, bool ta, const float* B, int ldb, bool tb, float beta,
+                                               const float* Cin, float* C, int ldc) {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    v4 acc = {0, 0, 0, 0};
+    const int i = i0 + li, j = j0 + li;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        v4s a, b;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int kk = k0 + 4 * lk + e;
+            float va = 0.f, vb = 0.f;
+            if (i < M && kk < K) va = ta ? A[kk + (long)i * lda] : A[i + (long)kk * lda];
+            if (j < N && kk < K) vb = tb ? B[j + (long)kk * ldb] : B[kk + (long)j * ldb];
+            a[e] = bf16_bits(va);
+            b[e] = bf16_bits(vb);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int ii = i0 + 4 * lk + v, jj = j0 + li;
+        if (ii < M && jj < N) {
+            const long o = ii + (long)jj * ldc;
+            C[o] = (beta == 0.f ? 0.f : beta * Cin[o]) + alpha * acc[v];
+        }
+    }
+}
+
 __device__ void wg_gemm_bf16(int M, int N, int K, float alpha, const float* A, int lda, bool ta, const float* B,
                              int ldb, bool tb, float beta, float* C, int ldc, bool upper = false) {
-    typedef float v4 __attribute__((ext_vector_type(4)));
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wid = threadIdx.x >> 6;
     const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
-    const int li = lane & 15, lk = lane >> 4;
     for (int t = wid; t < tm * tn; t += kWaves) {
         const int i0 = (t % tm) << 4, j0 = (t / tm) << 4;
         if (upper && i0 > j0 + 15) continue;
-        v4 acc = {0, 0, 0, 0};
-        const int i = i0 + li, j = j0 + li;
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            v4s a, b;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int kk = k0 + 4 * lk + e;
-                float va = 0.f, vb = 0.f;
-                if (i < M && kk < K) va = ta ? A[kk + (long)i * lda] : A[i + (long)kk * lda];
-                if (j < N && kk < K) vb = tb ? B[j + (long)kk * ldb] : B[kk + (long)j * ldb];
-                a[e] = bf16_bits(va);
-                b[e] = bf16_bits(vb);
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int ii = i0 + 4 * lk + v, jj = j0 + li;
-            if (ii < M && jj < N) {
-                float* c = C + ii + (long)jj * ldc;
-                *c = (beta == 0.f ? 0.f : beta * *c) + alpha * acc[v];
-            }
-        }
+        tile_gemm_bf16(i0, j0, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, C, ldc);
     }
     __syncthreads();
 }
@@ -1018,6 +1040,109 @@ __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restric
         for (long e = tid; e < (long)k * k; e += kThreads) V.Bss[e] = V.Ass[e];
         __syncthreads();
         schur_gemm<R, BF16>(k, k, nr, (R)-1, V.E, k, false, V.E, k, true, (R)1, V.Bss, k);        // B_ss = A_ss - E E^T
+    }
+}
+
+// Large boxes (np >= kBigBox): the gathers and Schur products of the elimination as
+// multi-workgroup launches.  Every workgroup takes kWaves 16 x 16 output tiles of
+// one box's product, with the per-tile arithmetic of the one-workgroup path.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_big_gather(const BoxMeta* __restrict__ meta,
+                                                         const int* __restrict__ list,
+                                                         const int* __restrict__ perm,
+                                                         const int* __restrict__ kk,
+                                                         const R* __restrict__ App,
+                                                         const double* __restrict__ T64,
+                                                         R* __restrict__ Wk, R* __restrict__ F) {
+    const int b = list[blockIdx.x];
+    const BoxMeta M = meta[b];
+    const ElimView<R> V = elim_view<R>(M, kk[b], Wk, F);
+    const int np = V.np, k = V.k, nr = V.nr;
+    const int* pv = perm + M.act;
+    const R* A = App + M.app;
+    const long n1 = (long)k * nr, n2 = n1 + (long)k * k, n3 = n2 + (long)k * nr, n4 = n3 + (long)nr * nr;
+    for (long e = (long)blockIdx.y * kThreads + threadIdx.x; e < n4; e += (long)gridDim.y * kThreads) {
+        if (e < n1) {
+            V.T[e] = (R)T64[M.f + e];
+        } else if (e < n2) {
+            const long q = e - n1;
+            const int a = (int)(q % k), c = (int)(q / k);
+            V.Ass[q] = A[pv[a] + (long)pv[c] * np];
+        } else if (e < n3) {
+            const long q = e - n2;
+            const int a = (int)(q % k), i = (int)(q / k);
+            V.Bsr[q] = A[pv[a] + (long)pv[k + i] * np];
+        } else {
+            const long q = e - n3;
+            const int i = (int)(q % nr), c = (int)(q / nr);
+            V.Brr[q] = A[pv[k + i] + (long)pv[k + c] * np];
+            if (i > c) V.Gi[q] = (R)0;   // lower triangle of G^{-1}
+        }
+    }
+}
+
+// op 0: B_rr -= T^T A_sr; 1: B_sr = A_sr - A_ss T; 2: B_rr -= B_sr^T T (B_rr: upper
+// triangle); 3: E = B_sr G^{-1}; 4: B_ss = A_ss - E E^T.
+template <typename R, bool BF16>
+__global__ __launch_bounds__(kThreads) void k_big_gemm(const BoxMeta* __restrict__ meta,
+                                                       const int* __restrict__ list, const int* __restrict__ kk,
+                                                       R* __restrict__ Wk, R* __restrict__ F, int op) {
+    const int b = list[blockIdx.x];
+    const ElimView<R> V = elim_view<R>(meta[b], kk[b], Wk, F);
+    const int k = V.k, nr = V.nr;
+    if (k == 0 || (op < 3 && nr == 0)) return;
+    int Mm, Nn, Kk, lda, ldb, ldc;
+    R alpha, beta;
+    const R *A, *B, *Cin;
+    R* C;
+    bool ta = false, tb = false, upper = false;
+    switch (op) {
+        case 0: Mm = nr; Nn = nr; Kk = k; alpha = -1; A = V.T; lda = k; ta = true; B = V.Bsr; ldb = k;
+                beta = 1; C = V.Brr; Cin = C; ldc = nr; upper = true; break;
+        case 1: Mm = k; Nn = nr; Kk = k; alpha = -1; A = V.Ass; lda = k; B = V.T; ldb = k;
+                beta = 1; C = V.Bsr; Cin = C; ldc = k; break;
+        case 2: Mm = nr; Nn = nr; Kk = k; alpha = -1; A = V.Bsr; lda = k; ta = true; B = V.T; ldb = k;
+                beta = 1; C = V.Brr; Cin = C; ldc = nr; upper = true; break;
+        case 3: Mm = k; Nn = nr; Kk = nr; alpha = 1; A = V.Bsr; lda = k; B = V.Gi; ldb = nr;
+                beta = 0; C = V.E; Cin = C; ldc = k; break;
+        default: Mm = k; Nn = k; Kk = nr; alpha = -1; A = V.E; lda = k; B = V.E; ldb = k; tb = true;
+                 beta = 1; C = V.Bss; Cin = V.Ass; ldc = k; break;
+    }
+    const int tm = (Mm + 15) >> 4, tn = (Nn + 15) >> 4;
+    const int t = (int)blockIdx.y * kWaves + (threadIdx.x >> 6);
+    if (t >= tm * tn) return;
+    const int i0 = (t % tm) << 4, j0 = (t / tm) << 4;
+    if (upper && i0 > j0 + 15) return;
+    if constexpr (BF16)
+        tile_gemm_bf16(i0, j0, Mm, Nn, Kk, alpha, A, lda, ta, B, ldb, tb, beta, Cin, C, ldc);
+    else
+        tile_gemm<R>(i0, j0, Mm, Nn, Kk, alpha, A, lda, ta, B, ldb, tb, beta, Cin, C, ldc);
+}
+
+template <typename R>
+void launch_big_schur(int nbig, int np_max, const BoxMeta* meta, const int* list, int phase, const int* perm,
+                      const int* k, const R* App, const double* T64, R* Wk, R* F, bool bf16, hipStream_t s) {
+    if (nbig == 0) return;
+    const int t1 = (np_max + 15) / 16;
+    const dim3 grid(nbig, (t1 * t1 + kWaves - 1) / kWaves);
+    auto gemm = [&](int op) {
+        if constexpr (sizeof(R) == 4) {
+            if (bf16) {
+                hipLaunchKernelGGL((k_big_gemm<R, true>), grid, dim3(kThreads), 0, s, meta, list, k, Wk, F, op);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_big_gemm<R, false>), grid, dim3(kThreads), 0, s, meta, list, k, Wk, F, op);
+    };
+    if (phase == 1) {
+        hipLaunchKernelGGL((k_big_gather<R>), dim3(nbig, 64), dim3(kThreads), 0, s, meta, list, perm, k, App, T64,
+                           Wk, F);
+        gemm(0);
+        gemm(1);
+        gemm(2);
+    } else {
+        gemm(3);
+        gemm(4);
     }
 }
 
@@ -1380,6 +1505,8 @@ template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta
                                        const int*, const ChildRef<R>*, R*, hipStream_t);            \
     template void launch_eliminate<R>(int, const BoxMeta*, const int*, int, const int*, const int*, \
                                       const R*, const double*, R*, R*, int*, bool, hipStream_t);    \
+    template void launch_big_schur<R>(int, int, const BoxMeta*, const int*, int, const int*, const int*, \
+                                      const R*, const double*, R*, R*, bool, hipStream_t);          \
     template void launch_big_cholesky_inverse<R>(int, int, const BoxMeta*, const int*, const int*, R*, \
                                                  R*, int*, hipStream_t);                            \
     template void launch_root_apply<R>(int, int, int, const BoxMeta*, const int*, const int*, const R*, \
