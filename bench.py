@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--workload", default="512sq", choices=sorted(WORKLOADS))
     ap.add_argument("--fp64-cols", type=int, default=2,
                     help="columns solved one at a time to time the plain FP64 form")
+    ap.add_argument("--factor-only", action="store_true",
+                    help="run one factorization of the workload (no predictor, no PCG) and print its time; "
+                         "for counter profiles of the factor kernels")
     ap.add_argument("--cpu-rows", type=int, default=-1,
                     help="rows of the oracle's dense matvec timed for the CPU baseline (0: skip; "
                          "-1: about 12 s of host work, 16384 rows at 512^2 with 64 RHS)")
@@ -124,6 +127,16 @@ def main():
     part = cbd.Partition(P, W["m"], W["delta"], mode, W["leaf"])
     F_rhs = torch.tensor(synth.rhs(N, nrhs, seed=0), device=dev)
     torch.cuda.synchronize()
+
+    if args.factor_only:
+        t0 = time.perf_counter()
+        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        st = fac.stats()
+        print(json.dumps({"workload": W["label"], "factor_s": t, "factor_flops": st["flops"],
+                          "factor_gflops": st["flops"] / t / 1e9, "schedule": fac.schedule()}))
+        return
 
     # tile shape of the matvec, chosen by the library's autotuner
     tile = P.autotune_matvec(nrhs)
