@@ -72,8 +72,8 @@ typedef struct {
                             its triangular factor R by an unpivoted Householder QR first
                             (equal column norms, pivots and ID in exact arithmetic, fewer
                             rows to stream per pivot step).  CBD_ROWS_AUTO (0): on levels
-                            whose matrices are at least twice as tall as wide and stream
-                            at least 512 MB per step; CBD_ROWS_NEVER; CBD_ROWS_ALWAYS */
+                            whose matrices are at least twice as tall as wide and hold at
+                            least 32 MB together; CBD_ROWS_NEVER; CBD_ROWS_ALWAYS */
 } cbd_rs_opts;
 
 /* Message of the last failed call on this thread ("" if none). */

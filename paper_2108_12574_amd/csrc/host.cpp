@@ -994,7 +994,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 const BoxMeta* qmeta = L.d_meta;
                 double* QY = Y;
                 int q_m_max = L.m_max;
-                const bool tall = sum_y >= 2 * sum_r && (double)sum_y * sizeof(double) >= 512.0 * (1 << 20);
+                const bool tall = sum_y >= 2 * sum_r && (double)sum_y * sizeof(double) >= 32.0 * (1 << 20);
                 if (o->row_compression == CBD_ROWS_ALWAYS || (o->row_compression == CBD_ROWS_AUTO && tall)) {
                     cm = L.meta;
                     long o_r = 0;

@@ -552,11 +552,162 @@ __global__ __launch_bounds__(kHqrThreads) void k_hqr_panel(const BoxMeta* __rest
     }
 }
 
+// Register-resident panel for matrices of at most 512 * RR rows below j0: every
+// thread keeps rows j0 + tid + 512 i (i < RR) of the kHqrRegW panel columns in
+// registers, so that a step costs two workgroup reductions and no memory pass.
+// Same reflectors, T and outputs as k_hqr_panel (panel width kHqrRegW).
+constexpr int kHqrRegW = 16;
+constexpr int kHqrRegThreads = 512;
+
+template <int RR>
+__global__ __launch_bounds__(kHqrRegThreads) void k_hqr_panel_reg(const BoxMeta* __restrict__ meta,
+                                                                  double* __restrict__ Y, int j0,
+                                                                  double* __restrict__ Tw,
+                                                                  double* __restrict__ alpha,
+                                                                  double* __restrict__ Vbuf, long vstride) {
+    constexpr int W = kHqrRegW, NW = kHqrRegThreads / 64;
+    __shared__ double red[W][NW];
+    __shared__ double s_sc[W];
+    __shared__ double s_T[kHqrPanel * kHqrPanel];
+    __shared__ double s_xn2;
+    const int b = blockIdx.x;
+    const BoxMeta M = meta[b];
+    const int m = M.m, np = M.np, kmax = min(m, np);
+    if (j0 >= kmax) return;
+    const int w = min(W, kmax - j0);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double* P = Y + M.y + (long)j0 * m;      // panel column q at P + q * m
+    for (int e = tid; e < kHqrPanel * kHqrPanel; e += kHqrRegThreads) s_T[e] = 0.0;
+    double y[RR][W];
+#pragma unroll
+    for (int i = 0; i < RR; ++i) {
+        const int r = j0 + tid + kHqrRegThreads * i;
+        const int rc = min(r, m - 1);
+#pragma unroll
+        for (int q = 0; q < W; ++q) y[i][q] = P[rc + (long)min(q, w - 1) * m];
+#pragma unroll
+        for (int q = 0; q < W; ++q) y[i][q] = (r < m && q < w) ? y[i][q] : 0.0;
+    }
+    auto block_sum = [&](double v, int slot) {
+        v = wave_sum(v);
+        if (lane == 0) red[slot][wid] = v;
+    };
+    {
+        double q0 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RR; ++i) q0 += y[i][0] * y[i][0];
+        block_sum(q0, 0);
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int v = 0; v < NW; ++v) t += red[0][v];
+            s_xn2 = t;
+        }
+        __syncthreads();
+    }
+    for (int jj = 0; jj < w; ++jj) {
+        const int c = j0 + jj;
+        // row c is row slot 0 of thread jj
+        if (tid == jj) {
+            double x0 = 0.0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) x0 = q == jj ? y[0][q] : x0;
+            const double xn = sqrt(s_xn2);
+            const double al = x0 >= 0.0 ? -xn : xn;
+            const double vn2 = 2.0 * xn * xn + 2.0 * fabs(x0) * xn;
+            const double beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+#pragma unroll
+            for (int q = 0; q < W; ++q)
+                if (q == jj) y[0][q] = x0 - al;
+            alpha[M.act + c] = al;
+            s_T[jj + jj * kHqrPanel] = beta;
+        }
+        __syncthreads();
+        double v[RR];
+#pragma unroll
+        for (int i = 0; i < RR; ++i) {
+            const int r = j0 + tid + kHqrRegThreads * i;
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) t = q == jj ? y[i][q] : t;
+            v[i] = r >= c ? t : 0.0;
+        }
+        // v . column q for every q != jj: Gram column (q < jj) or reflection coefficient (q > jj)
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            if (q == jj || q >= w) continue;
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < RR; ++i) t += v[i] * y[i][q];
+            block_sum(t, q);
+        }
+        __syncthreads();
+        const double beta = s_T[jj + jj * kHqrPanel];
+        if (tid < w && tid != jj) {
+            double t = 0.0;
+            for (int u = 0; u < NW; ++u) t += red[tid][u];
+            s_sc[tid] = tid > jj ? beta * t : t;
+        }
+        __syncthreads();
+        if (tid < jj) {
+            double t = 0.0;
+            for (int a2 = tid; a2 < jj; ++a2) t += s_T[tid + a2 * kHqrPanel] * s_sc[a2];
+            s_T[tid + jj * kHqrPanel] = -beta * t;
+        }
+        // reflection of the columns q > jj, and the next column's norm (rows > c)
+        double nx = 0.0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            if (q <= jj || q >= w) continue;
+            const double sq = s_sc[q];
+#pragma unroll
+            for (int i = 0; i < RR; ++i) y[i][q] -= sq * v[i];
+            if (q == jj + 1) {
+#pragma unroll
+                for (int i = 0; i < RR; ++i) {
+                    const int r = j0 + tid + kHqrRegThreads * i;
+                    if (r > c) nx += y[i][q] * y[i][q];
+                }
+            }
+        }
+        block_sum(nx, 0);
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int u = 0; u < NW; ++u) t += red[0][u];
+            s_xn2 = t;
+        }
+        __syncthreads();
+    }
+    // panel back to Y, reflectors (zero-padded to kHqrPanel columns) to the staging buffer
+    double* Vc = Vbuf + (long)b * vstride;
+    double* Vt = Vc + (long)m * kHqrPanel;
+#pragma unroll
+    for (int i = 0; i < RR; ++i) {
+        const int r = j0 + tid + kHqrRegThreads * i;
+        if (r >= m) continue;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            if (q >= w) continue;
+            P[r + (long)q * m] = y[i][q];
+        }
+#pragma unroll
+        for (int a = 0; a < kHqrPanel; ++a) {
+            double vv = 0.0;
+            if (a < W) vv = (a < w && r >= j0 + a) ? y[i][a < W ? a : 0] : 0.0;
+            Vc[r + (long)a * m] = vv;
+            Vt[a + (long)r * kHqrPanel] = vv;
+        }
+    }
+    double* Tb = Tw + (long)b * kHqrTw;
+    for (int e = tid; e < kHqrPanel * kHqrPanel; e += kHqrRegThreads) Tb[e] = s_T[e];
+}
+
 // Trailing columns c >= j0 + w, 16 per workgroup: A <- A - V (T^T (V^T A)), both
 // products on FP64 MFMA (v_mfma_f64_16x16x4f64).  W = V^T A splits its rows over
 // the waves; A - V W' takes 16-row tiles per wave.
 __global__ __launch_bounds__(kThreads) void k_hqr_update(const BoxMeta* __restrict__ meta, double* __restrict__ Y,
-                                                         int j0, const double* __restrict__ Tw,
+                                                         int j0, int pw, const double* __restrict__ Tw,
                                                          const double* __restrict__ Vbuf, long vstride) {
     typedef double v4 __attribute__((ext_vector_type(4)));
     __shared__ double s_T[kHqrPanel * kHqrPanel];
@@ -566,7 +717,7 @@ __global__ __launch_bounds__(kThreads) void k_hqr_update(const BoxMeta* __restri
     const BoxMeta M = meta[b];
     const int m = M.m, np = M.np, kmax = min(m, np);
     if (j0 >= kmax) return;
-    const int w = min(kHqrPanel, kmax - j0);
+    const int w = min(pw, kmax - j0);
     const int c0 = (int)blockIdx.y * 16;
     const int lo = max(j0 + w, c0), hi = min(np, c0 + 16);
     if (lo >= hi) return;
@@ -662,10 +813,25 @@ void launch_hqr(int nbox, int np_max, int m_max, int k_max, const BoxMeta* meta,
     if (nbox == 0) return;
     const long vstride = 2L * m_max * kHqrPanel;
     const int ct = (np_max + 15) / 16;
-    for (int j0 = 0; j0 < k_max; j0 += kHqrPanel) {
-        hipLaunchKernelGGL(k_hqr_panel, dim3(nbox), dim3(kHqrThreads), 0, s, meta, Y, j0, Tw, alpha, Vbuf, vstride);
-        if (j0 + kHqrPanel < np_max)
-            hipLaunchKernelGGL(k_hqr_update, dim3(nbox, ct), dim3(kThreads), 0, s, meta, Y, j0, Tw, Vbuf, vstride);
+    // panels held in registers when every matrix has at most 2560 rows
+    const int rr = (m_max + kHqrRegThreads - 1) / kHqrRegThreads;
+    const int pw = rr <= 5 ? kHqrRegW : kHqrPanel;
+    for (int j0 = 0; j0 < k_max; j0 += pw) {
+        if (rr <= 2)
+            hipLaunchKernelGGL(k_hqr_panel_reg<2>, dim3(nbox), dim3(kHqrRegThreads), 0, s, meta, Y, j0, Tw, alpha,
+                               Vbuf, vstride);
+        else if (rr == 3)
+            hipLaunchKernelGGL(k_hqr_panel_reg<3>, dim3(nbox), dim3(kHqrRegThreads), 0, s, meta, Y, j0, Tw, alpha,
+                               Vbuf, vstride);
+        else if (rr <= 5)
+            hipLaunchKernelGGL(k_hqr_panel_reg<5>, dim3(nbox), dim3(kHqrRegThreads), 0, s, meta, Y, j0, Tw, alpha,
+                               Vbuf, vstride);
+        else
+            hipLaunchKernelGGL(k_hqr_panel, dim3(nbox), dim3(kHqrThreads), 0, s, meta, Y, j0, Tw, alpha, Vbuf,
+                               vstride);
+        if (j0 + pw < np_max)
+            hipLaunchKernelGGL(k_hqr_update, dim3(nbox, ct), dim3(kThreads), 0, s, meta, Y, j0, pw, Tw, Vbuf,
+                               vstride);
     }
     hipLaunchKernelGGL(k_hqr_compact, dim3(nbox, 16), dim3(kThreads), 0, s, meta, Y, alpha, cmeta, Rc);
 }

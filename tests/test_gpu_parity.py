@@ -460,14 +460,18 @@ def test_full_size_1024_fft_sampled():
     assert np.sqrt(np.mean(res ** 2)) <= 1e-8 * np.linalg.norm(fr) / np.sqrt(O.N)
 
 
-@pytest.mark.parametrize("case", ["2d", "3d"])
+@pytest.mark.parametrize("case", ["2d", "2d512", "3d"])
 def test_row_compression_keeps_the_ids(case):
     # the pivoted QR on the Householder R of each tall proxy matrix picks the same
     # skeletons as on the matrix itself (equal column norms in exact arithmetic);
-    # T agrees to the conditioning of R11
+    # T agrees to the conditioning of R11.  2d512: the benchmark layout, whose
+    # stepped levels have proxy matrices of up to about 2000 rows
     if case == "2d":
         P, _ = gpu_problem(2, 64)
         part, tol, npxy = cbd.Partition(P, 16, 1, cbd.MODE_CBD, 0), 1e-8, 64
+    elif case == "2d512":
+        P, _ = gpu_problem(2, 512, coef=True)
+        part, tol, npxy = cbd.Partition(P, 64, 1, cbd.MODE_CBD, 0), 1e-6, 64
     else:
         P, _ = gpu_problem(3, 16)
         part, tol, npxy = cbd.Partition(P, 4, 1, cbd.MODE_CBD, 0), 1e-6, 256
@@ -482,7 +486,10 @@ def test_row_compression_keeps_the_ids(case):
     worst, nbox = 0.0, 0
     for l in range(nlev):
         count = {}
-        for i in Fc.level(l)[2]:
+        subs = Fc.level(l)[2]
+        if case == "2d512" and len(subs) >= 1024:
+            continue   # levels of the one-workgroup QR: not row-compressed
+        for i in subs:
             b = count.get(i, 0)
             count[i] = b + 1
             gc, gp = Fc.box(i, l, b), Fp.box(i, l, b)
