@@ -99,23 +99,53 @@ void launch_proxy_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, co
 __device__ void id_coefficients(const double* Yb, int m, int np, int k, double* T, int c_lo, int c_hi);
 
 // Householder update of trailing columns c in [c_lo, c_hi) (c > j) with the
-// reflector v (LDS, rows j..m-1), then their norm over rows j+1..m-1.
+// reflector v (LDS, rows j..m-1), then their norm over rows j+1..m-1.  Wave w
+// takes the columns c_lo + w + kWaves t, four at a time, so that the loads of
+// four columns are in flight together; each column's arithmetic (and so its
+// rounding) does not depend on the grouping.
 __device__ __forceinline__ void reflect_columns(double* Yb, int m, int j, int c_lo, int c_hi,
                                                 const double* v, double beta, double* norms) {
+    constexpr int G = 4;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int c = c_lo + wid; c < c_hi; c += kWaves) {
-        double* col = Yb + (long)c * m;
-        double s = 0;
-        for (int r = j + lane; r < m; r += 64) s += v[r - j] * col[r];
-        s = wave_sum(s) * beta;
-        double q = 0;
-        for (int r = j + lane; r < m; r += 64) {
-            const double y = col[r] - s * v[r - j];
-            col[r] = y;
-            if (r > j) q += y * y;
+    for (int c0 = c_lo + wid; c0 < c_hi; c0 += G * kWaves) {
+        double* col[G];
+        bool ok[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int c = c0 + u * kWaves;
+            ok[u] = c < c_hi;
+            col[u] = Yb + (long)(ok[u] ? c : c0) * m;
         }
-        q = wave_sum(q);
-        if (lane == 0) norms[c] = sqrt(q);
+        double sd[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) sd[u] = 0.0;
+        for (int r = j + lane; r < m; r += 64) {
+            const double vv = v[r - j];
+#pragma unroll
+            for (int u = 0; u < G; ++u) sd[u] += vv * col[u][r];
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) sd[u] = wave_sum(sd[u]) * beta;
+        double q[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) q[u] = 0.0;
+        for (int r = j + lane; r < m; r += 64) {
+            const double vv = v[r - j];
+            double y[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) y[u] = col[u][r] - sd[u] * vv;
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                if (!ok[u]) continue;
+                col[u][r] = y[u];
+                if (r > j) q[u] += y[u] * y[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            q[u] = wave_sum(q[u]);
+            if (lane == 0 && ok[u]) norms[c0 + u * kWaves] = sqrt(q[u]);
+        }
     }
 }
 
