@@ -43,6 +43,11 @@ WORKLOADS = {
     "1024sq": dict(d=2, n=1024, m=128, mode="cbd", delta=1, leaf=0, tol=1e-6, npxy=64, nrhs=1,
                    prec="fp32", coef=False,
                    label="2D 1024^2 (N=1048576), CBD m=128, tol 1e-6, 1 RHS, FP32 factors with the rank predictor"),
+    # the paper's comparison system: global RS, one non-overlapping subdomain (the whole grid)
+    "global512": dict(d=2, n=512, m=1, mode="jacobi", delta=0, leaf=8, tol=1e-6, npxy=64, nrhs=64,
+                      prec="fp32", coef=True,
+                      label="2D 512^2, global RS (one subdomain, 8x8 leaf tiles), b=c=1+0.5sin(2pi x1)cos(2pi x2), "
+                            "tol 1e-6, 64 proxy pts, 64 RHS, FP32 factors"),
 }
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 FP32_PEAK_TFLOPS = 157.3
@@ -118,7 +123,7 @@ def main():
     dev = torch.device("cuda:0")
     W = WORKLOADS[args.workload]
     d, n, nrhs, tol, npxy = W["d"], W["n"], W["nrhs"], W["tol"], W["npxy"]
-    mode = {"cbd": cbd.MODE_CBD, "schwarz": cbd.MODE_SCHWARZ}[W["mode"]]
+    mode = {"cbd": cbd.MODE_CBD, "schwarz": cbd.MODE_SCHWARZ, "jacobi": cbd.MODE_JACOBI}[W["mode"]]
     prec = {"fp32": cbd.PREC_FP32, "fp64": cbd.PREC_FP64}[W["prec"]]
     N = n ** d
     log = lambda *a: print(*a, file=sys.stderr, flush=True)

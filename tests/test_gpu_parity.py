@@ -167,7 +167,8 @@ def test_exact_subsolves_match_oracle(mode, m, delta):
     dict(d=2, n=64, m=2, delta=8, mode=1, leaf=8, tol=1e-6, npxy=64, coef=False),     # Schwarz, leaf tiles
     dict(d=2, n=60, m=6, delta=2, mode=2, leaf=4, tol=1e-6, npxy=48, coef=False),     # CBD + tiles, ragged
     dict(d=3, n=16, m=4, delta=1, mode=2, leaf=0, tol=1e-6, npxy=256, coef=False),    # 3D
-], ids=["coef", "schwarz_tiles", "cbd_tiles", "3d"])
+    dict(d=2, n=64, m=1, delta=0, mode=0, leaf=8, tol=1e-8, npxy=64, coef=False),     # global RS
+], ids=["coef", "schwarz_tiles", "cbd_tiles", "3d", "global_rs"])
 def test_factor_and_apply_other_layouts(case):
     print("case", case, flush=True)
     P, O = gpu_problem(case["d"], case["n"], case["coef"])
@@ -502,3 +503,19 @@ def test_row_compression_keeps_the_ids(case):
     r = torch.tensor(synth.rhs(P.N, 2, seed=1), device=DEV)
     zc, zp = Fc.apply(r), Fp.apply(r)
     assert (zc - zp).norm() <= 1e-8 * zp.norm()
+
+
+def test_global_rs_preconditioner_pcg():
+    # global RS (one non-overlapping subdomain: the whole grid, 8 x 8 leaf tiles), the
+    # paper's comparison system: at tol 1e-8 it is nearly the inverse, so PCG needs few
+    # iterations; u against the oracle's dense solve
+    P, O = gpu_problem(2, 64)
+    part = cbd.Partition(P, 1, 0, cbd.MODE_JACOBI, 8)
+    F = cbd.Factor(P, part, tol=1e-8, n_pxy=64)
+    assert len(F.stats()["S"]) == 1
+    f = synth.rhs(O.N, 2, seed=0)
+    u, it, rr = cbd.pcg_solve(P, F, torch.tensor(f, device=DEV), tol=1e-10, maxit=50)
+    print("global RS: iterations", it, "root", F.stats()["S"], flush=True)
+    assert max(it) <= 6 and max(rr) <= 1e-10
+    ud = np.linalg.solve(O.dense(), f.T).T
+    assert rel(u.cpu().numpy(), ud) <= 1e-8
