@@ -32,6 +32,7 @@ from scipy.linalg import cholesky, solve_triangular, cho_solve
 
 from . import ie
 from .cpqr import interp_decomp, TIE_FP64
+from . import sketch
 
 
 class NotSPDError(RuntimeError):
@@ -70,11 +71,14 @@ class SubdomainFactor:
         self.root = None       # local indices of the root DOFs
         self.root_G = None     # upper Cholesky factor of the last Schur complement
         self.root_A = None
+        self.sketched = 0      # boxes whose ID came from a sketch
 
 
 def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP64,
-                     keep_matrices=False):
-    """RS factorization of A_i for one subdomain (Section 3.2)."""
+                     keep_matrices=False, sketch_seed=None, sub=0):
+    """RS factorization of A_i for one subdomain (Section 3.2).  With sketch_seed set,
+    every ID is the randomized one of oracle.sketch (subdomain index `sub` enters
+    the box keys of the random signs)."""
     if prob.grid != ie.GRID_CELL:
         raise ValueError("RS is defined on the cell-centred grid")
     d, n, h = prob.d, prob.n, prob.h
@@ -109,7 +113,13 @@ def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP6
             diff = pxy[:, None, :] - X[p][None, :, :]
             Yp = ie.kernel(d, np.sqrt(np.sum(diff * diff, axis=2))) * w[p][None, :]
             Y = np.vstack([Yn, Yp])
-            k, perm, T = interp_decomp(Y, tol, tie)
+            if sketch_seed is None:
+                k, perm, T = interp_decomp(Y, tol, tie)
+            else:
+                rowkeys = np.concatenate([gidx[near], prob.N + np.arange(len(dirs))])
+                k, perm, T, used = sketch.interp_decomp_sketched(
+                    Y, tol, sketch_seed, sketch.box_key(sub, l, bi), rowkeys, tie)
+                f.sketched += int(used)
             ps, pr = perm[:k], perm[k:]
             App = boxmat[bi]
             Ass = App[np.ix_(ps, ps)]
@@ -167,10 +177,11 @@ def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP6
 class RSPreconditioner:
     """T^{-1} = sum_i R_i^T A_i^{-1} R_i (e:ad) with A_i^{-1} applied through RS factors."""
 
-    def __init__(self, prob, part, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP64):
+    def __init__(self, prob, part, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP64, sketch_seed=None):
         self.prob, self.part = prob, part
-        self.subs = [factor_subdomain(prob, part, sd, tol, n_pxy, proxy_ratio, tie)
-                     for sd in part.subdomains]
+        self.subs = [factor_subdomain(prob, part, sd, tol, n_pxy, proxy_ratio, tie,
+                                      sketch_seed=sketch_seed, sub=i)
+                     for i, sd in enumerate(part.subdomains)]
 
     def apply_sub(self, i, v):
         """A_i^{-1} v approximately, v of shape (n_i, nrhs) in local numbering."""
