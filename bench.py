@@ -213,6 +213,23 @@ def main():
     pcg_fft_s = time.perf_counter() - t0
     log("pcg with the FFT matvec: %.3f s, iterations %d-%d" % (pcg_fft_s, min(its_fft), max(its_fft)))
 
+    # randomized IDs: the CPQR of a random-sign sketch of each proxy matrix (the scheme of
+    # the paper's last 3D runs); same predictor, same PCG
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac_sk = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=1)
+    torch.cuda.synchronize()
+    sk_factor = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, its_sk, rr_sk = cbd.pcg_solve(P, fac_sk, F_rhs, tol=1e-10, maxit=200)
+    torch.cuda.synchronize()
+    sk_sched = fac_sk.schedule()
+    sketched = {"factor_s": sk_factor, "factor_gflops": fac_sk.stats()["flops"] / sk_factor / 1e9,
+                "pcg_s": time.perf_counter() - t0, "n_it": [min(its_sk), max(its_sk)], "max_relres": max(rr_sk),
+                "sketched_boxes": sk_sched["sketched"], "fallback_boxes": sk_sched["sketch_fallbacks"]}
+    del fac_sk
+    log("sketched IDs: %s" % sketched)
+
     # the bfloat16-GEMM variant of the factors (Schur products on bf16 operands)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -295,6 +312,7 @@ def main():
         "matvec_avg_ms": mv_avg_s * 1e3,
         "apply_avg_ms": ap_ms / max(ap_n, 1),
         "matvec_tile_rows_per_wave": 16 * tile,
+        "sketched_id_variant": sketched,
         "bf16_gemm_variant": bf16,
         "pcg_with_fft_matvec": {"pcg_s": pcg_fft_s, "n_it": [min(its_fft), max(its_fft)],
                                 "max_relres": max(rr_fft),

@@ -74,6 +74,17 @@ typedef struct {
                             rows to stream per pivot step).  CBD_ROWS_AUTO (0): on levels
                             whose matrices are at least twice as tall as wide and hold at
                             least 32 MB together; CBD_ROWS_NEVER; CBD_ROWS_ALWAYS */
+    int id_sketch;       /* 1: randomized IDs.  A box with n_p active DOFs and m proxy rows
+                            takes the truncated CPQR of Z = Omega Y, Omega ell x m of random
+                            signs, ell = ceil(3 n_p / 5) + 8, when ell < min(m, n_p); a sketch
+                            whose rank exceeds ell - 8 is discarded for the deterministic ID.
+                            0: deterministic IDs everywhere */
+    unsigned long long sketch_seed;  /* seed of the random signs: the splitmix64 output
+                            function of seed + key G1 + i G2 + rowkey G3 (mod 2^64), sign
+                            from its top bit; key = (subdomain << 40) | (level << 32) | box,
+                            rowkey = grid index of a near-field point or N + q for proxy
+                            point q; G1 = 0x9E3779B97F4A7C15, G2 = 0xD1B54A32D192ED03,
+                            G3 = 0x8CB92BA72F3D8DD7 */
 } cbd_rs_opts;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -177,9 +188,9 @@ int rs_factor_root(cbd_factor f, int i, int* S, int* idx, double* Ginv);
  *  and ranks (host, nbox), either may be NULL.
  *  rs_factor_schedule: stream synchronizations of the factorization, launch pairs of
  *  the stepped QR, boxes whose rank exceeded the predicted budget, the mean
- *  absolute rank prediction error (0 without a predictor), and the number of
- *  levels whose proxy matrices were row-compressed before the pivoted QR.  Any
- *  output may be NULL. */
+ *  absolute rank prediction error (0 without a predictor), the number of batches
+ *  whose proxy matrices were row-compressed before the pivoted QR, the boxes whose
+ *  ID came from a sketch and those whose sketch saturated.  Any output may be NULL. */
 #define CBD_MLP_FEATURES 6
 #define CBD_MLP_WIDTH 64
 int rank_mlp_params(void);
@@ -191,7 +202,7 @@ int rank_mlp_adam(float* params, const float* grad, float* m, float* v, int step
                   void* stream);
 int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* X, int* k);
 int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
-                       double* mean_abs_err, int* row_compressed);
+                       double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks);
 
 /* rs_apply - z = T^{-1} r = sum_i R_i^T A_i^{-1} R_i r, (e:ad), with every A_i^{-1}
  * applied through its RS factor: gather, forward sweep over levels, root solve,

@@ -638,7 +638,9 @@ struct cbd_factor_s {
     int host_syncs = 0;       // stream synchronizations issued by the factorization
     int qr_steps = 0;         // launch pairs of the stepped pivoted QR
     int mispredicted = 0;     // stepped boxes whose rank exceeded the predicted step budget
-    int hqr_levels = 0;       // stepped levels whose proxy matrices were row-compressed first
+    int hqr_levels = 0;       // stepped batches whose proxy matrices were row-compressed first
+    int sketched = 0;         // boxes whose ID came from a sketch
+    int sketch_fallbacks = 0; // boxes whose sketch saturated (deterministic ID instead)
     double pred_abs_err = 0.0;
     int pred_count = 0;
     size_t esize;
@@ -659,6 +661,14 @@ namespace {
 // Levels with at least this many boxes run the ID with one workgroup per box;
 // fewer boxes use the stepped QR that spreads each box over many workgroups.
 constexpr int kStepBoxes = 1024;
+
+// Randomized ID: rows of the sketch of an m x np proxy matrix (0: no sketch), and the
+// margin below ell that a sketch's rank must stay under to be accepted.
+constexpr int kSketchOver = 8;
+int sketch_rows(int m, int np) {
+    const int ell = (3 * np + 4) / 5 + kSketchOver;
+    return ell < std::min(m, np) ? ell : 0;
+}
 
 double cpqr_flops(double m, double n, double k) {
     return 4.0 * m * n * k - 2.0 * (m + n) * k * k + 4.0 * k * k * k / 3.0;
@@ -715,7 +725,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
     const double tie = 1e-10;
     const bool bf16 = o->precision == CBD_PREC_BF16GEMM;
     std::vector<double> hdir = proxy_dirs(d, std::max(npxy, 1));
-    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf, mlpbuf, listbuf, hqrbuf;
+    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf, mlpbuf, listbuf, hqrbuf, idbuf, zbuf;
     if ((rc = dirbuf.ensure(sizeof(double) * hdir.size()))) return rc;
     HIPCHK(hipMemcpyAsync(dirbuf.p, hdir.data(), sizeof(double) * hdir.size(), hipMemcpyHostToDevice, s));
     if ((rc = statbuf.ensure(sizeof(int)))) return rc;
@@ -951,7 +961,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         R* App = (R*)appbuf.p;
         R* FF = (R*)L.d_F;
         std::vector<int> kpred;
-        std::vector<BoxMeta> cm;   // compact metadata of row-compressed boxes (host copy kept for the upload)
+        std::vector<int> kall, sk_ell;   // ranks (host copy kept for the upload) and sketch rows per box
         if (!root && o->mlp) {
             std::vector<float> feats((size_t)L.nbox * kMlpFeatures), yhat(L.nbox);
             for (int B = 0; B < L.nbox; ++B)
@@ -974,99 +984,189 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         if (!root) {
             launch_proxy_matrix<double>(PV, L.nbox, L.d_meta, L.d_act, (const int*)nearbuf.p, Q->d_cidx,
                                         (const double*)dirbuf.p, npxy, Y, s);
-            const size_t shm = (size_t)(L.np_max + L.m_max) * sizeof(double) + (size_t)L.np_max * sizeof(int);
-            if (L.nbox >= kStepBoxes && shm <= 65536) {
-                // many boxes: one workgroup per box
-                launch_cpqr(L.nbox, L.d_meta, Y, L.d_act, L.d_sr, L.d_perm, L.d_k, T64, o->tol, tie,
-                            L.m_max, L.np_max, s);
-            } else {
-                // few (or large) boxes: stepped QR, every launch spread over all boxes' columns.
-                // Tall proxy matrices are first reduced to their triangular factor R (same
-                // column norms, pivots and ID in exact arithmetic), so each pivot step
-                // streams min(m, np) rows instead of m.
-                long sum_y = 0, sum_r = 0;
-                int k_max = 0;
-                for (const BoxMeta& M : L.meta) {
-                    sum_y += (long)M.m * M.np;
-                    sum_r += (long)std::min(M.m, M.np) * M.np;
-                    k_max = std::max(k_max, std::min(M.m, M.np));
+            // The ID of a batch of boxes (bm: their metadata, m rows of Ymat each, at the
+            // offsets bm[].y), with k into kb (host, one per batch box).
+            auto id_batch = [&](const std::vector<BoxMeta>& bm, double* Ymat, const std::vector<int>& bpred,
+                                std::vector<int>& kb) -> int {
+                const int nb = (int)bm.size();
+                kb.assign(nb, 0);
+                if (nb == 0) return CBD_OK;
+                int m_max = 0, np_max = 0;
+                for (const BoxMeta& M : bm) {
+                    m_max = std::max(m_max, M.m);
+                    np_max = std::max(np_max, M.np);
                 }
-                const BoxMeta* qmeta = L.d_meta;
-                double* QY = Y;
-                int q_m_max = L.m_max;
-                const bool tall = sum_y >= 2 * sum_r && (double)sum_y * sizeof(double) >= 32.0 * (1 << 20);
-                if (o->row_compression == CBD_ROWS_ALWAYS || (o->row_compression == CBD_ROWS_AUTO && tall)) {
-                    cm = L.meta;
-                    long o_r = 0;
-                    q_m_max = 0;
-                    for (BoxMeta& M : cm) {
-                        M.m = std::min(M.m, M.np);
-                        M.y = o_r;
-                        o_r += (long)M.m * M.np;
-                        q_m_max = std::max(q_m_max, M.m);
+                int rc2;
+                if ((rc2 = idbuf.ensure(sizeof(BoxMeta) * nb + sizeof(int) * nb))) return rc2;
+                BoxMeta* d_bm = (BoxMeta*)idbuf.p;
+                int* d_kb = (int*)(d_bm + nb);
+                HIPCHK(hipMemcpyAsync(d_bm, bm.data(), sizeof(BoxMeta) * nb, hipMemcpyHostToDevice, s));
+                const size_t shm = (size_t)(np_max + m_max) * sizeof(double) + (size_t)np_max * sizeof(int);
+                std::vector<BoxMeta> cmh;   // compact metadata of row-compressed boxes
+                if (nb >= kStepBoxes && shm <= 65536) {
+                    // many boxes: one workgroup per box
+                    launch_cpqr(nb, d_bm, Ymat, L.d_act, L.d_sr, L.d_perm, d_kb, T64, o->tol, tie, m_max, np_max, s);
+                } else {
+                    // few (or large) boxes: stepped QR, every launch spread over all boxes' columns.
+                    // Tall proxy matrices are first reduced to their triangular factor R (same
+                    // column norms, pivots and ID in exact arithmetic), so each pivot step
+                    // streams min(m, np) rows instead of m.
+                    long sum_y = 0, sum_r = 0;
+                    int k_max = 0;
+                    for (const BoxMeta& M : bm) {
+                        sum_y += (long)M.m * M.np;
+                        sum_r += (long)std::min(M.m, M.np) * M.np;
+                        k_max = std::max(k_max, std::min(M.m, M.np));
                     }
-                    const size_t nv = (size_t)L.nbox * kHqrVbuf(L.m_max);
-                    if ((rc = hqrbuf.ensure(sizeof(BoxMeta) * L.nbox +
-                                            sizeof(double) * ((size_t)L.nbox * kHqrTw + o_act + nv + std::max(o_r, 1L)))))
+                    const BoxMeta* qmeta = d_bm;
+                    double* QY = Ymat;
+                    int q_m_max = m_max;
+                    const bool tall = sum_y >= 2 * sum_r && (double)sum_y * sizeof(double) >= 32.0 * (1 << 20);
+                    if (o->row_compression == CBD_ROWS_ALWAYS || (o->row_compression == CBD_ROWS_AUTO && tall)) {
+                        cmh = bm;
+                        long o_r = 0;
+                        q_m_max = 0;
+                        for (BoxMeta& M : cmh) {
+                            M.m = std::min(M.m, M.np);
+                            M.y = o_r;
+                            o_r += (long)M.m * M.np;
+                            q_m_max = std::max(q_m_max, M.m);
+                        }
+                        const size_t nv = (size_t)nb * kHqrVbuf(m_max);
+                        if ((rc2 = hqrbuf.ensure(sizeof(BoxMeta) * nb +
+                                                 sizeof(double) * ((size_t)nb * kHqrTw + o_act + nv + std::max(o_r, 1L)))))
+                            return rc2;
+                        BoxMeta* d_cm = (BoxMeta*)hqrbuf.p;
+                        double* Tw = (double*)(d_cm + nb);
+                        double* halpha = Tw + (size_t)nb * kHqrTw;
+                        double* Vb = halpha + o_act;
+                        double* Rc = Vb + nv;
+                        HIPCHK(hipMemcpyAsync(d_cm, cmh.data(), sizeof(BoxMeta) * nb, hipMemcpyHostToDevice, s));
+                        launch_hqr(nb, np_max, m_max, k_max, d_bm, Ymat, Tw, halpha, Vb, d_cm, Rc, s);
+                        F->hqr_levels++;
+                        qmeta = d_cm;
+                        QY = Rc;
+                    }
+                    if ((size_t)q_m_max * sizeof(double) > 65536)
+                        return fail(CBD_EARG, "rs_factor_batched: proxy matrix of " + std::to_string(q_m_max) +
+                                                  " rows exceeds the LDS of the QR update kernel");
+                    if ((rc2 = qrbuf.ensure(sizeof(double) * (3 * o_act + 2 * nb) + sizeof(int) * (o_act + 2 * nb))))
+                        return rc2;
+                    QrState st;
+                    st.norms = (double*)qrbuf.p;
+                    st.alpha = st.norms + o_act;
+                    st.beta = st.alpha + o_act;
+                    st.nu0 = st.beta + nb;
+                    st.pv = (int*)(st.nu0 + nb);
+                    st.done = st.pv + o_act;
+                    st.k = st.done + nb;
+                    launch_qr_init(nb, np_max, qmeta, QY, st, s);
+                    int jmax = 0;
+                    for (const BoxMeta& M : bm) jmax = std::max(jmax, std::min(M.m, M.np));
+                    std::vector<int> done(nb);
+                    auto all_done = [&](bool& all) -> int {
+                        HIPCHK(hipMemcpyAsync(done.data(), st.done, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+                        HIPCHK(hipStreamSynchronize(s));
+                        F->host_syncs++;
+                        all = true;
+                        for (int v : done) all = all && v;
+                        return CBD_OK;
+                    };
+                    // With predicted ranks, the first steps run without checks: up to the largest
+                    // predicted rank plus a margin.  The QR's own stopping rule decides every rank;
+                    // a box still running after the budget falls back to checked steps.
+                    int j = 0;
+                    bool all = false;
+                    if (!bpred.empty()) {
+                        int kmax_pred = 0;
+                        for (int kp : bpred) kmax_pred = std::max(kmax_pred, kp);
+                        const int budget = std::min(jmax + 1, (kmax_pred * 11 + 9) / 10 + 2);
+                        for (; j < budget; ++j) launch_qr_step(nb, np_max, q_m_max, qmeta, QY, st, j, o->tol, tie, s);
+                        F->qr_steps += budget;
+                        if ((rc2 = all_done(all))) return rc2;
+                        if (!all)
+                            for (int v : done) F->mispredicted += !v;
+                    }
+                    for (; !all && j <= jmax; ++j) {
+                        launch_qr_step(nb, np_max, q_m_max, qmeta, QY, st, j, o->tol, tie, s);
+                        F->qr_steps++;
+                        if (j % 8 == 7 && (rc2 = all_done(all))) return rc2;
+                    }
+                    launch_qr_finish(nb, np_max, qmeta, QY, st, L.d_act, L.d_sr, L.d_perm, d_kb, T64, s);
+                }
+                HIPCHK(hipMemcpyAsync(kb.data(), d_kb, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                F->host_syncs++;
+                return CBD_OK;
+            };
+            kall.assign(L.nbox, 0);
+            sk_ell.assign(L.nbox, 0);
+            std::vector<int> det;   // boxes with the deterministic ID
+            if (o->id_sketch) {
+                // randomized ID: the CPQR of Z = Omega Y (ell x np, random signs), ell from
+                // the box shape; a saturated sketch falls back to the deterministic ID
+                std::vector<BoxMeta> zm;
+                std::vector<int> zb, zpred;
+                std::vector<unsigned long long> keys(L.nbox);
+                std::vector<BoxMeta> zall(L.meta);
+                long o_z = 0;
+                for (int B = 0; B < L.nbox; ++B) {
+                    const BoxMeta& M = L.meta[B];
+                    const int ell = sketch_rows(M.m, M.np);
+                    keys[B] = ((unsigned long long)L.box_sub[B] << 40) | ((unsigned long long)l << 32) |
+                              (unsigned long long)L.box_idx[B];
+                    zall[B].m = ell;
+                    zall[B].y = o_z;
+                    o_z += (long)ell * M.np;
+                    if (ell) {
+                        sk_ell[B] = ell;
+                        zm.push_back(zall[B]);
+                        zb.push_back(B);
+                        if (!kpred.empty()) zpred.push_back(std::min(kpred[B], ell));
+                    } else {
+                        det.push_back(B);
+                    }
+                }
+                if (!zb.empty()) {
+                    if ((rc = zbuf.ensure(sizeof(BoxMeta) * L.nbox + sizeof(unsigned long long) * L.nbox +
+                                          sizeof(double) * std::max(o_z, 1L))))
                         return rc;
-                    BoxMeta* d_cm = (BoxMeta*)hqrbuf.p;
-                    double* Tw = (double*)(d_cm + L.nbox);
-                    double* halpha = Tw + (size_t)L.nbox * kHqrTw;
-                    double* Vb = halpha + o_act;
-                    double* Rc = Vb + nv;
-                    HIPCHK(hipMemcpyAsync(d_cm, cm.data(), sizeof(BoxMeta) * L.nbox, hipMemcpyHostToDevice, s));
-                    launch_hqr(L.nbox, L.np_max, L.m_max, k_max, L.d_meta, Y, Tw, halpha, Vb, d_cm, Rc, s);
-                    F->hqr_levels++;
-                    qmeta = d_cm;
-                    QY = Rc;
+                    BoxMeta* d_zall = (BoxMeta*)zbuf.p;
+                    unsigned long long* d_keys = (unsigned long long*)(d_zall + L.nbox);
+                    double* Z = (double*)(d_keys + L.nbox);
+                    HIPCHK(hipMemcpyAsync(d_zall, zall.data(), sizeof(BoxMeta) * L.nbox, hipMemcpyHostToDevice, s));
+                    HIPCHK(hipMemcpyAsync(d_keys, keys.data(), sizeof(unsigned long long) * L.nbox,
+                                          hipMemcpyHostToDevice, s));
+                    launch_sketch(L.nbox, L.np_max, L.d_meta, d_zall, Y, (const int*)nearbuf.p, Q->d_cidx, P->N,
+                                  o->sketch_seed, d_keys, Z, s);
+                    std::vector<int> kz;
+                    if ((rc = id_batch(zm, Z, zpred, kz))) return rc;
+                    for (size_t e = 0; e < zb.size(); ++e) {
+                        if (kz[e] > sk_ell[zb[e]] - kSketchOver) {
+                            det.push_back(zb[e]);       // saturated sketch
+                            sk_ell[zb[e]] = 0;
+                            F->sketch_fallbacks++;
+                        } else {
+                            kall[zb[e]] = kz[e];
+                            F->sketched++;
+                        }
+                    }
                 }
-                if ((size_t)q_m_max * sizeof(double) > 65536)
-                    return fail(CBD_EARG, "rs_factor_batched: proxy matrix of " + std::to_string(q_m_max) +
-                                              " rows exceeds the LDS of the QR update kernel");
-                if ((rc = qrbuf.ensure(sizeof(double) * (3 * o_act + 2 * L.nbox) + sizeof(int) * (o_act + 2 * L.nbox))))
-                    return rc;
-                QrState st;
-                st.norms = (double*)qrbuf.p;
-                st.alpha = st.norms + o_act;
-                st.beta = st.alpha + o_act;
-                st.nu0 = st.beta + L.nbox;
-                st.pv = (int*)(st.nu0 + L.nbox);
-                st.done = st.pv + o_act;
-                st.k = st.done + L.nbox;
-                launch_qr_init(L.nbox, L.np_max, qmeta, QY, st, s);
-                int jmax = 0;
-                for (const BoxMeta& M : L.meta) jmax = std::max(jmax, std::min(M.m, M.np));
-                std::vector<int> done(L.nbox);
-                auto all_done = [&](bool& all) -> int {
-                    HIPCHK(hipMemcpyAsync(done.data(), st.done, sizeof(int) * L.nbox, hipMemcpyDeviceToHost, s));
-                    HIPCHK(hipStreamSynchronize(s));
-                    F->host_syncs++;
-                    all = true;
-                    for (int v : done) all = all && v;
-                    return CBD_OK;
-                };
-                // With predicted ranks, the first steps run without checks: up to the largest
-                // predicted rank plus a margin.  The QR's own stopping rule decides every rank;
-                // a box still running after the budget falls back to checked steps.
-                int j = 0;
-                bool all = false;
-                if (!kpred.empty()) {
-                    int kmax_pred = 0;
-                    for (int kp : kpred) kmax_pred = std::max(kmax_pred, kp);
-                    const int budget = std::min(jmax + 1, (kmax_pred * 11 + 9) / 10 + 2);
-                    for (; j < budget; ++j) launch_qr_step(L.nbox, L.np_max, q_m_max, qmeta, QY, st, j, o->tol, tie, s);
-                    F->qr_steps += budget;
-                    if ((rc = all_done(all))) return rc;
-                    if (!all)
-                        for (int v : done) F->mispredicted += !v;
-                }
-                for (; !all && j <= jmax; ++j) {
-                    launch_qr_step(L.nbox, L.np_max, q_m_max, qmeta, QY, st, j, o->tol, tie, s);
-                    F->qr_steps++;
-                    if (j % 8 == 7 && (rc = all_done(all))) return rc;
-                }
-                launch_qr_finish(L.nbox, L.np_max, qmeta, QY, st, L.d_act, L.d_sr, L.d_perm, L.d_k, T64, s);
+                std::sort(det.begin(), det.end());
+            } else {
+                for (int B = 0; B < L.nbox; ++B) det.push_back(B);
             }
+            if (!det.empty()) {
+                std::vector<BoxMeta> dm;
+                std::vector<int> dpred, kd;
+                for (int B : det) {
+                    dm.push_back(L.meta[B]);
+                    if (!kpred.empty()) dpred.push_back(kpred[B]);
+                }
+                if ((rc = id_batch(dm, Y, dpred, kd))) return rc;
+                for (size_t e = 0; e < det.size(); ++e) kall[det[e]] = kd[e];
+            }
+            HIPCHK(hipMemcpyAsync(L.d_k, kall.data(), sizeof(int) * L.nbox, hipMemcpyHostToDevice, s));
         } else {
             // root boxes: no compression, k = 0, identity order
             std::vector<int> zeros(L.nbox, 0), ident(o_act);
@@ -1132,7 +1232,10 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         }
         for (int B = 0; B < L.nbox; ++B) {
             const double np = L.meta[B].np, k = L.k[B], nr = np - k;
-            if (!root) F->flops += cpqr_flops(L.meta[B].m, np, k);
+            if (!root) {
+                const int ell = B < (int)sk_ell.size() ? sk_ell[B] : 0;
+                F->flops += ell ? 2.0 * ell * L.meta[B].m * np + cpqr_flops(ell, np, k) : cpqr_flops(L.meta[B].m, np, k);
+            }
             F->flops += elim_flops(k, nr);
         }
     }
@@ -1356,13 +1459,15 @@ extern "C" int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* 
 }
 
 extern "C" int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
-                                  double* mean_abs_err, int* row_compressed) {
+                                  double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks) {
     if (!f) return fail(CBD_EARG, "rs_factor_schedule: NULL factor");
     if (host_syncs) *host_syncs = f->host_syncs;
     if (qr_steps) *qr_steps = f->qr_steps;
     if (mispredicted) *mispredicted = f->mispredicted;
     if (mean_abs_err) *mean_abs_err = f->pred_count ? f->pred_abs_err / f->pred_count : 0.0;
     if (row_compressed) *row_compressed = f->hqr_levels;
+    if (sketched) *sketched = f->sketched;
+    if (sketch_fallbacks) *sketch_fallbacks = f->sketch_fallbacks;
     return CBD_OK;
 }
 

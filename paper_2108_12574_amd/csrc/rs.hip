@@ -866,6 +866,69 @@ void launch_hqr(int nbox, int np_max, int m_max, int k_max, const BoxMeta* meta,
     hipLaunchKernelGGL(k_hqr_compact, dim3(nbox, 16), dim3(kThreads), 0, s, meta, Y, alpha, cmeta, Rc);
 }
 
+// ---- randomized ID: the sketch Z = Omega Y -----------------------------------
+// Omega (ell x m per box) holds random signs from a counter-based hash: the
+// splitmix64 output function of seed + key * G1 + i * G2 + rowkey * G3 (mod 2^64),
+// top bit 0 -> +1, 1 -> -1; key = (subdomain << 40) | (level << 32) | box, rowkey =
+// global index of a near-field row's point, N + q for proxy row q.  Z (ell x np,
+// column-major) on FP64 MFMA: each wave one 16 x 16 tile of Z, the sign operand
+// generated per lane, Y read as the B operand.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kThreads) void k_sketch(const BoxMeta* __restrict__ meta,
+                                                     const BoxMeta* __restrict__ zmeta,
+                                                     const double* __restrict__ Y, const int* __restrict__ nearl,
+                                                     const int* __restrict__ cidx, long N, unsigned long long seed,
+                                                     const unsigned long long* __restrict__ keys,
+                                                     double* __restrict__ Z) {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    const int b = blockIdx.x;
+    const BoxMeta M = meta[b];
+    const int ell = zmeta[b].m, np = M.np, m = M.m;
+    if (ell == 0) return;
+    const int tm = (ell + 15) >> 4, tn = (np + 15) >> 4;
+    const int t = (int)blockIdx.y * kWaves + (threadIdx.x >> 6);
+    if (t >= tm * tn) return;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int i0 = (t % tm) << 4, c0 = (t / tm) << 4;
+    const int i = i0 + li, c = c0 + li;
+    const unsigned long long base = seed + keys[b] * 0x9E3779B97F4A7C15ull + (unsigned long long)i * 0xD1B54A32D192ED03ull;
+    const double* Yb = Y + M.y;
+    v4 acc = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < m; k0 += 4) {
+        const int row = k0 + lk;
+        double a = 0.0, bv = 0.0;
+        if (row < m) {
+            if (i < ell) {
+                const long rk = row < M.nnear ? (long)cidx[nearl[M.near + row]] : N + (row - M.nnear);
+                const unsigned long long h = mix64(base + (unsigned long long)rk * 0x8CB92BA72F3D8DD7ull);
+                a = (h >> 63) ? -1.0 : 1.0;
+            }
+            if (c < np) bv = Yb[row + (long)c * m];
+        }
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+    }
+    double* Zb = Z + zmeta[b].y;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int ii = i0 + 4 * v + lk;
+        if (ii < ell && c < np) Zb[ii + (long)c * ell] = acc[v];
+    }
+}
+
+void launch_sketch(int nbox, int np_max, const BoxMeta* meta, const BoxMeta* zmeta, const double* Y,
+                   const int* nearl, const int* cidx, long N, unsigned long long seed,
+                   const unsigned long long* keys, double* Z, hipStream_t s) {
+    if (nbox == 0) return;
+    const int t1 = (np_max + 15) / 16;   // ell < np for every sketched box
+    hipLaunchKernelGGL(k_sketch, dim3(nbox, (t1 * t1 + kWaves - 1) / kWaves), dim3(kThreads), 0, s, meta, zmeta,
+                       Y, nearl, cidx, N, seed, keys, Z);
+}
+
 // ---- box matrix A_pp --------------------------------------------------------
 // Boxes made of grid points take kernel entries; a parent box takes its
 // children's B_ss on the diagonal blocks and kernel entries between children.

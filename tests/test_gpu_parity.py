@@ -519,3 +519,51 @@ def test_global_rs_preconditioner_pcg():
     assert max(it) <= 6 and max(rr) <= 1e-10
     ud = np.linalg.solve(O.dense(), f.T).T
     assert rel(u.cpu().numpy(), ud) <= 1e-8
+
+
+@pytest.mark.parametrize("case", ["2d128", "64sq_tol1e-8", "3d16"])
+def test_sketched_ids_match_oracle(case):
+    # randomized IDs (random-sign sketch, same counter-based signs on both sides):
+    # skeletons, T, E, G^{-1}, B_ss equal to the oracle's sketched RS box by box,
+    # including the boxes whose sketch saturated and fell back
+    if case == "2d128":
+        d, n, m, tol, npxy = 2, 128, 16, 1e-6, 64
+    elif case == "64sq_tol1e-8":
+        d, n, m, tol, npxy = 2, 64, 16, 1e-8, 64
+    else:
+        d, n, m, tol, npxy = 3, 16, 4, 1e-4, 256     # the paper's 3D runs use loose tolerances
+    P, O = gpu_problem(d, n)
+    part = cbd.Partition(P, m, 1, cbd.MODE_CBD, 0)
+    opart = dd.Partition(d, n, m, 1, dd.CBD)
+    R = rs.RSPreconditioner(O, opart, tol, n_pxy=npxy, sketch_seed=12345)
+    F = cbd.Factor(P, part, tol=tol, n_pxy=npxy, sketch_seed=12345)
+    sch = F.schedule()
+    osk = sum(s.sketched for s in R.subs)
+    print(case, "sketched", sch["sketched"], "fallbacks", sch["sketch_fallbacks"], "oracle sketched", osk, flush=True)
+    assert sch["sketched"] == osk and osk > 0
+    nbox = _compare_factor(F, R, opart, tol_T=1e-7)
+    assert sch["sketched"] <= nbox
+    r = synth.rhs(O.N, 3, seed=4)
+    z = F.apply(torch.tensor(r, device=DEV)).cpu().numpy()
+    assert rel(z, R.apply(r.T).T) <= 1e-10
+
+
+def test_sketched_ids_full_size_pcg():
+    # 512^2 benchmark layout with randomized IDs (FP32 factors): PCG reaches 1e-10 in
+    # about as many iterations as with deterministic IDs; true residual on sampled rows
+    P, O = gpu_problem(2, 512, coef=True)
+    part = cbd.Partition(P, 64, 1, cbd.MODE_CBD, 0)
+    F0 = cbd.Factor(P, part, tol=1e-6, n_pxy=64, precision=cbd.PREC_FP32)
+    F1 = cbd.Factor(P, part, tol=1e-6, n_pxy=64, precision=cbd.PREC_FP32, sketch_seed=1)
+    sch = F1.schedule()
+    print("sketched", sch["sketched"], "fallbacks", sch["sketch_fallbacks"], flush=True)
+    assert sch["sketched"] > 0.9 * sum(len(F1.level(l)[0]) for l in range(F1.stats()["levels"]))
+    f = synth.rhs(O.N, 2, seed=0)
+    ft = torch.tensor(f, device=DEV)
+    _, it0, _ = cbd.pcg_solve(P, F0, ft, tol=1e-10, maxit=200)
+    u, it1, rr = cbd.pcg_solve(P, F1, ft, tol=1e-10, maxit=200)
+    print("iterations deterministic", it0, "sketched", it1, flush=True)
+    assert max(rr) <= 1e-10 and max(it1) <= max(it0) + 2
+    rows = np.random.default_rng(2).choice(O.N, 32, replace=False)
+    res = f[0][rows] - cmatvec.matvec(O, u[0].cpu().numpy(), rows=rows)
+    assert np.sqrt(np.mean(res ** 2)) <= 1e-8 * np.linalg.norm(f[0]) / np.sqrt(O.N)
