@@ -44,6 +44,16 @@ WORKLOADS = {
                    prec="fp32", coef=False,
                    label="2D 1024^2 (N=1048576), CBD m=128, tol 1e-6, 1 RHS, FP32 factors with the rank predictor"),
     # the paper's comparison system: global RS, one non-overlapping subdomain (the whole grid)
+    # 3D at the paper's weak-scaling layout (N/M = 512 points per partition) and its
+    # tolerance (1e-3), with randomized IDs as in the paper's last 3D runs
+    "64cube": dict(d=3, n=64, m=8, mode="cbd", delta=1, leaf=0, tol=1e-3, npxy=256, nrhs=16,
+                   prec="fp32", coef=False, sketch=True,
+                   label="3D 64^3 (N=262144), CBD m=8 (N/M=512), tol 1e-3, 256 proxy pts, sketched IDs, "
+                         "16 RHS, FP32 factors"),
+    "128cube": dict(d=3, n=128, m=16, mode="cbd", delta=1, leaf=0, tol=1e-3, npxy=256, nrhs=1,
+                    prec="fp32", coef=False, sketch=True, fft=True,
+                    label="3D 128^3 (N=2097152), CBD m=16 (N/M=512), tol 1e-3, 256 proxy pts, sketched IDs, "
+                          "1 RHS, FP32 factors, FFT matvec in PCG"),
     "global512": dict(d=2, n=512, m=1, mode="jacobi", delta=0, leaf=8, tol=1e-6, npxy=64, nrhs=64,
                       prec="fp32", coef=True,
                       label="2D 512^2, global RS (one subdomain, 8x8 leaf tiles), b=c=1+0.5sin(2pi x1)cos(2pi x2), "
@@ -125,6 +135,8 @@ def main():
     d, n, nrhs, tol, npxy = W["d"], W["n"], W["nrhs"], W["tol"], W["npxy"]
     mode = {"cbd": cbd.MODE_CBD, "schwarz": cbd.MODE_SCHWARZ, "jacobi": cbd.MODE_JACOBI}[W["mode"]]
     prec = {"fp32": cbd.PREC_FP32, "fp64": cbd.PREC_FP64}[W["prec"]]
+    sk_seed = 1 if W.get("sketch") else None      # randomized IDs
+    use_fft = bool(W.get("fft"))                   # PCG products by FFT (workloads too large for the dense form)
     N = n ** d
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     coef = torch.tensor(synth.coef_smooth(d, n)) if W["coef"] else None
@@ -135,7 +147,7 @@ def main():
 
     if args.factor_only:
         t0 = time.perf_counter()
-        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec)
+        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, sketch_seed=sk_seed)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         st = fac.stats()
@@ -143,6 +155,7 @@ def main():
                           "factor_gflops": st["flops"] / t / 1e9, "schedule": fac.schedule()}))
         return
 
+    P.fft_prepare(max_pairs=8)
     # tile shape of the matvec, chosen by the library's autotuner
     tile = P.autotune_matvec(nrhs)
     tile1 = P.autotune_matvec(1)
@@ -157,10 +170,10 @@ def main():
 
     def step():
         t0 = time.perf_counter()
-        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp)
+        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=sk_seed)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        u, its, rr = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200)
+        u, its, rr = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200, fft=use_fft)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return fac, its, rr, t1 - t0, t2 - t1
@@ -191,7 +204,7 @@ def main():
     # the same factorization without the predictor
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fac_nm = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec)
+    fac_nm = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, sketch_seed=sk_seed)
     torch.cuda.synchronize()
     factor_nm_s = time.perf_counter() - t0
     sched_nm = fac_nm.schedule()
@@ -199,13 +212,20 @@ def main():
     pcg_s = float(np.mean(ts))
     n_it = its_all[-1]
 
+    if mv_n == 0:
+        # the PCG used FFT products: time one dense product for the roofline record
+        cbd.timing.reset()
+        cbd.timing.enable(True)
+        P.matvec(F_rhs)
+        torch.cuda.synchronize()
+        cbd.timing.enable(False)
+        mv_ms, mv_n = cbd.timing.get("matvec")
     # matvec roofline: product flops 2 N^2 nrhs per launch (kernel evaluations extra)
     mv_avg_s = mv_ms / 1e3 / max(mv_n, 1)
     mv_flops = 2.0 * N * N * nrhs
     achieved = mv_flops / mv_avg_s / 1e12
 
     # the paper's matvec (FFT on the uniform grid) with the same factors, for comparison
-    P.fft_prepare(max_pairs=8)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, its_fft, rr_fft = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200, fft=True)
@@ -221,7 +241,7 @@ def main():
     torch.cuda.synchronize()
     sk_factor = time.perf_counter() - t0
     t0 = time.perf_counter()
-    _, its_sk, rr_sk = cbd.pcg_solve(P, fac_sk, F_rhs, tol=1e-10, maxit=200)
+    _, its_sk, rr_sk = cbd.pcg_solve(P, fac_sk, F_rhs, tol=1e-10, maxit=200, fft=use_fft)
     torch.cuda.synchronize()
     sk_sched = fac_sk.schedule()
     sketched = {"factor_s": sk_factor, "factor_gflops": fac_sk.stats()["flops"] / sk_factor / 1e9,
@@ -235,11 +255,12 @@ def main():
     t0 = time.perf_counter()
     bf16 = None
     try:
-        fac_bf = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_BF16GEMM, mlp=mlp)
+        fac_bf = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_BF16GEMM, mlp=mlp,
+                            sketch_seed=sk_seed)
         torch.cuda.synchronize()
         bf_factor = time.perf_counter() - t0
         t0 = time.perf_counter()
-        _, its_bf, rr_bf = cbd.pcg_solve(P, fac_bf, F_rhs, tol=1e-10, maxit=400, flexible=True)
+        _, its_bf, rr_bf = cbd.pcg_solve(P, fac_bf, F_rhs, tol=1e-10, maxit=400, flexible=True, fft=use_fft)
         torch.cuda.synchronize()
         bf16 = {"factor_s": bf_factor, "pcg_s": time.perf_counter() - t0, "n_it": [min(its_bf), max(its_bf)],
                 "max_relres": max(rr_bf), "pcg": "flexible"}
@@ -251,17 +272,18 @@ def main():
     # plain FP64 form: FP64 factors, right-hand sides one at a time
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fac64 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_FP64)
+    fac64 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_FP64, sketch_seed=sk_seed)
     torch.cuda.synchronize()
     f64_factor = time.perf_counter() - t0
     t0 = time.perf_counter()
     its64 = []
-    for c in range(args.fp64_cols):
-        _, it, _ = cbd.pcg_solve(P, fac64, F_rhs[c], tol=1e-10, maxit=200)
+    ncols = min(args.fp64_cols, nrhs)
+    for c in range(ncols):
+        _, it, _ = cbd.pcg_solve(P, fac64, F_rhs[c], tol=1e-10, maxit=200, fft=use_fft)
         its64.append(it)
     torch.cuda.synchronize()
-    f64_per_col = (time.perf_counter() - t0) / max(args.fp64_cols, 1)
-    f64_pcg = f64_per_col * nrhs if args.fp64_cols > 0 else float("nan")
+    f64_per_col = (time.perf_counter() - t0) / max(ncols, 1)
+    f64_pcg = f64_per_col * nrhs if ncols > 0 else float("nan")
     log("fp64 form: factor %.3f s, %.3f s per column" % (f64_factor, f64_per_col))
 
     cpu = None
@@ -322,10 +344,10 @@ def main():
                            "factor_s_with": factor_s, "factor_s_without": factor_nm_s,
                            "host_syncs_with": sched["host_syncs"], "host_syncs_without": sched_nm["host_syncs"],
                            "mispredicted_boxes": sched["mispredicted"]},
-        "fp64_form": {"factor_s": f64_factor, "pcg_s_est": f64_pcg, "cols_timed": args.fp64_cols,
+        "fp64_form": {"factor_s": f64_factor, "pcg_s_est": f64_pcg, "cols_timed": ncols,
                       "n_it": its64,
                       "note": "PCG time measured on %d columns solved one at a time, scaled to %d"
-                              % (args.fp64_cols, nrhs)},
+                              % (ncols, nrhs)},
         "speedup_mixed_vs_fp64": {"pcg": f64_pcg / pcg_s, "factor": f64_factor / factor_s,
                                   "total": (f64_pcg + f64_factor) / (pcg_s + factor_s)},
         "roofline": {"kernel": "kernel_matvec (FP64, %d RHS)" % nrhs, "bound": "mfma",
