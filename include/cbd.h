@@ -85,6 +85,10 @@ typedef struct {
                             rowkey = grid index of a near-field point or N + q for proxy
                             point q; G1 = 0x9E3779B97F4A7C15, G2 = 0xD1B54A32D192ED03,
                             G3 = 0x8CB92BA72F3D8DD7 */
+    size_t workspace_bytes;  /* bound on the factorization's scratch per level (proxy
+                            matrices, elimination work, FP64 T, box matrices): a level's boxes
+                            are processed in chunks of consecutive boxes within it; 0: 64 GiB.
+                            Factor storage is not counted */
 } cbd_rs_opts;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -190,7 +194,9 @@ int rs_factor_root(cbd_factor f, int i, int* S, int* idx, double* Ginv);
  *  the stepped QR, boxes whose rank exceeded the predicted budget, the mean
  *  absolute rank prediction error (0 without a predictor), the number of batches
  *  whose proxy matrices were row-compressed before the pivoted QR, the boxes whose
- *  ID came from a sketch and those whose sketch saturated.  Any output may be NULL. */
+ *  ID came from a sketch and those whose sketch saturated, and the number of level
+ *  chunks processed (the number of levels when no level was split).  Any output may
+ *  be NULL. */
 #define CBD_MLP_FEATURES 6
 #define CBD_MLP_WIDTH 64
 int rank_mlp_params(void);
@@ -202,7 +208,8 @@ int rank_mlp_adam(float* params, const float* grad, float* m, float* v, int step
                   void* stream);
 int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* X, int* k);
 int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
-                       double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks);
+                       double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks,
+                       int* chunks);
 
 /* rs_apply - z = T^{-1} r = sum_i R_i^T A_i^{-1} R_i r, (e:ad), with every A_i^{-1}
  * applied through its RS factor: gather, forward sweep over levels, root solve,

@@ -146,12 +146,14 @@ class Factor:
     """RS factors of all subdomain matrices (rs_factor_batched) and T^{-1} (rs_apply)."""
 
     def __init__(self, problem, partition, tol=1e-6, n_pxy=64, proxy_ratio=1.5,
-                 precision=PREC_FP64, exact=False, mlp=None, row_compression=ROWS_AUTO, sketch_seed=None):
+                 precision=PREC_FP64, exact=False, mlp=None, row_compression=ROWS_AUTO, sketch_seed=None,
+                 workspace_bytes=0):
         self.problem, self.partition = problem, partition
         self.precision = precision
         opts = _lib.RSOpts(tol, n_pxy, proxy_ratio, precision, 1 if exact else 0,
                            mlp.params.data_ptr() if mlp is not None else None, row_compression,
-                           0 if sketch_seed is None else 1, 0 if sketch_seed is None else int(sketch_seed))
+                           0 if sketch_seed is None else 1, 0 if sketch_seed is None else int(sketch_seed),
+                           int(workspace_bytes))
         h = ctypes.c_void_p()
         check(lib().rs_factor_batched(problem.handle, partition.handle, ctypes.byref(opts),
                                       _stream(problem.device), ctypes.byref(h)))
@@ -222,12 +224,13 @@ class Factor:
         """Stream synchronizations, stepped-QR launch pairs, mispredicted boxes, mean |k - k_pred|
         and row-compressed levels of the factorization (rs_factor_schedule)."""
         s, q, m, e, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
-        sk, fb = ctypes.c_int(), ctypes.c_int()
+        sk, fb, ch = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         check(lib().rs_factor_schedule(self.handle, ctypes.byref(s), ctypes.byref(q), ctypes.byref(m),
-                                       ctypes.byref(e), ctypes.byref(c), ctypes.byref(sk), ctypes.byref(fb)))
+                                       ctypes.byref(e), ctypes.byref(c), ctypes.byref(sk), ctypes.byref(fb),
+                                       ctypes.byref(ch)))
         return {"host_syncs": s.value, "qr_steps": q.value, "mispredicted": m.value,
                 "mean_abs_err": e.value, "row_compressed": c.value, "sketched": sk.value,
-                "sketch_fallbacks": fb.value}
+                "sketch_fallbacks": fb.value, "chunks": ch.value}
 
     def root(self, i):
         import numpy as np

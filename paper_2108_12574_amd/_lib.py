@@ -20,7 +20,8 @@ class RSOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("n_pxy", ctypes.c_int),
                 ("proxy_ratio", ctypes.c_double), ("precision", ctypes.c_int),
                 ("exact", ctypes.c_int), ("mlp", ctypes.c_void_p), ("row_compression", ctypes.c_int),
-                ("id_sketch", ctypes.c_int), ("sketch_seed", ctypes.c_ulonglong)]
+                ("id_sketch", ctypes.c_int), ("sketch_seed", ctypes.c_ulonglong),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 # (name, restype, argtypes) of every exported symbol of include/cbd.h
@@ -55,7 +56,7 @@ SIGNATURES = [
     ("rank_mlp_loss_grad", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("rank_mlp_adam", _i, [_vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp]),
     ("rs_factor_features", _i, [_vp, _i, _ip, ctypes.POINTER(ctypes.c_float), _ip]),
-    ("rs_factor_schedule", _i, [_vp, _ip, _ip, _ip, _dp, _ip, _ip, _ip]),
+    ("rs_factor_schedule", _i, [_vp, _ip, _ip, _ip, _dp, _ip, _ip, _ip, _ip]),
     ("cbd_timing_enable", _i, [_i]),
     ("cbd_timing_get", _i, [ctypes.c_char_p, _dp, ctypes.POINTER(_l)]),
     ("cbd_timing_reset", _i, []),

@@ -641,6 +641,7 @@ struct cbd_factor_s {
     int hqr_levels = 0;       // stepped batches whose proxy matrices were row-compressed first
     int sketched = 0;         // boxes whose ID came from a sketch
     int sketch_fallbacks = 0; // boxes whose sketch saturated (deterministic ID instead)
+    int chunks = 0;           // level chunks (more than the number of levels when the workspace is bounded)
     double pred_abs_err = 0.0;
     int pred_count = 0;
     size_t esize;
@@ -933,10 +934,39 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         L.d_F = dalloc<R>(o_f, rc);
         if (rc) return rc;
         F->bytes += sizeof(R) * (size_t)o_f;
-        if ((rc = ybuf.ensure(sizeof(double) * std::max(o_y, 1L)))) return rc;
-        if ((rc = wbuf.ensure(sizeof(R) * std::max(o_y, 1L)))) return rc;
-        if ((rc = t64buf.ensure(sizeof(double) * std::max(o_f, 1L)))) return rc;
-        if ((rc = appbuf.ensure(sizeof(R) * std::max(o_app, 1L)))) return rc;
+        // The level's boxes go through the proxy matrices, IDs and elimination in chunks
+        // of consecutive boxes whose scratch (Y, elimination work, FP64 T, box matrices)
+        // fits the workspace budget; the factor arrays stay level-wide.
+        std::vector<int> cut{0};
+        long cy = 0, cf = 0, ca = 0, my = 1, mf = 1, ma = 1;
+        {
+            const double budget = o->workspace_bytes ? (double)o->workspace_bytes : 64.0 * (1L << 30);
+            double acc = 0.0;
+            for (int B = 0; B < L.nbox; ++B) {
+                const BoxMeta& M = L.meta[B];
+                const long yb = std::max((long)M.m * M.np, (long)M.np * M.np + kScratchCols * M.np);
+                const long fb = (long)M.np * M.np;
+                const double bytes = (double)yb * (2 * sizeof(double) + sizeof(R)) + (double)fb * (sizeof(double) + sizeof(R));
+                if (B > cut.back() && acc + bytes > budget) {
+                    cut.push_back(B);
+                    acc = 0.0;
+                    cy = cf = ca = 0;
+                }
+                acc += bytes;
+                cy += yb;
+                cf += fb;
+                ca += fb;
+                my = std::max(my, cy);
+                mf = std::max(mf, cf);
+                ma = std::max(ma, ca);
+            }
+            cut.push_back(L.nbox);
+        }
+        F->chunks += (int)cut.size() - 1;
+        if ((rc = ybuf.ensure(sizeof(double) * my))) return rc;
+        if ((rc = wbuf.ensure(sizeof(R) * my))) return rc;
+        if ((rc = t64buf.ensure(sizeof(double) * mf))) return rc;
+        if ((rc = appbuf.ensure(sizeof(R) * ma))) return rc;
         if ((rc = nearbuf.ensure(sizeof(int) * std::max(o_near, 1L)))) return rc;
         if ((rc = chbuf.ensure(sizeof(ChildRef<R>) * std::max(o_ch, 1L)))) return rc;
         std::vector<int> hact, hnear;
@@ -955,10 +985,6 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             HIPCHK(hipMemcpyAsync(nearbuf.p, hnear.data(), sizeof(int) * o_near, hipMemcpyHostToDevice, s));
         if (o_ch)
             HIPCHK(hipMemcpyAsync(chbuf.p, hch.data(), sizeof(ChildRef<R>) * o_ch, hipMemcpyHostToDevice, s));
-        double* Y = (double*)ybuf.p;
-        double* T64 = (double*)t64buf.p;
-        R* Wk = (R*)wbuf.p;
-        R* App = (R*)appbuf.p;
         R* FF = (R*)L.d_F;
         std::vector<int> kpred;
         std::vector<int> kall, sk_ell;   // ranks (host copy kept for the upload) and sketch rows per box
@@ -981,8 +1007,21 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 kpred[B] = std::max(0, std::min(kmax, (int)std::lround(std::isfinite(kp) ? kp : (double)kmax)));
             }
         }
+        kall.assign(L.nbox, 0);
+        sk_ell.assign(L.nbox, 0);
+        for (size_t ci = 0; ci + 1 < cut.size(); ++ci) {
+        const int b0 = cut[ci], b1 = cut[ci + 1], nbc = b1 - b0;
+        // chunk-based views: the level's offsets (meta y, f, app) land in the chunk buffers
+        double* Y = (double*)ybuf.p - L.meta[b0].y;
+        double* T64 = (double*)t64buf.p - L.meta[b0].f;
+        R* Wk = (R*)wbuf.p - L.meta[b0].y;
+        R* App = (R*)appbuf.p - L.meta[b0].app;
+        const BoxMeta* d_meta_c = L.d_meta + b0;
+        int* d_k_c = L.d_k + b0;
+        int np_max_c = 0;
+        for (int B = b0; B < b1; ++B) np_max_c = std::max(np_max_c, L.meta[B].np);
         if (!root) {
-            launch_proxy_matrix<double>(PV, L.nbox, L.d_meta, L.d_act, (const int*)nearbuf.p, Q->d_cidx,
+            launch_proxy_matrix<double>(PV, nbc, d_meta_c, L.d_act, (const int*)nearbuf.p, Q->d_cidx,
                                         (const double*)dirbuf.p, npxy, Y, s);
             // The ID of a batch of boxes (bm: their metadata, m rows of Ymat each, at the
             // offsets bm[].y), with k into kb (host, one per batch box).
@@ -1099,28 +1138,26 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 F->host_syncs++;
                 return CBD_OK;
             };
-            kall.assign(L.nbox, 0);
-            sk_ell.assign(L.nbox, 0);
             std::vector<int> det;   // boxes with the deterministic ID
             if (o->id_sketch) {
                 // randomized ID: the CPQR of Z = Omega Y (ell x np, random signs), ell from
                 // the box shape; a saturated sketch falls back to the deterministic ID
                 std::vector<BoxMeta> zm;
                 std::vector<int> zb, zpred;
-                std::vector<unsigned long long> keys(L.nbox);
-                std::vector<BoxMeta> zall(L.meta);
+                std::vector<unsigned long long> keys(nbc);
+                std::vector<BoxMeta> zall(L.meta.begin() + b0, L.meta.begin() + b1);
                 long o_z = 0;
-                for (int B = 0; B < L.nbox; ++B) {
+                for (int B = b0; B < b1; ++B) {
                     const BoxMeta& M = L.meta[B];
                     const int ell = sketch_rows(M.m, M.np);
-                    keys[B] = ((unsigned long long)L.box_sub[B] << 40) | ((unsigned long long)l << 32) |
-                              (unsigned long long)L.box_idx[B];
-                    zall[B].m = ell;
-                    zall[B].y = o_z;
+                    keys[B - b0] = ((unsigned long long)L.box_sub[B] << 40) | ((unsigned long long)l << 32) |
+                                   (unsigned long long)L.box_idx[B];
+                    zall[B - b0].m = ell;
+                    zall[B - b0].y = o_z;
                     o_z += (long)ell * M.np;
                     if (ell) {
                         sk_ell[B] = ell;
-                        zm.push_back(zall[B]);
+                        zm.push_back(zall[B - b0]);
                         zb.push_back(B);
                         if (!kpred.empty()) zpred.push_back(std::min(kpred[B], ell));
                     } else {
@@ -1128,16 +1165,16 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                     }
                 }
                 if (!zb.empty()) {
-                    if ((rc = zbuf.ensure(sizeof(BoxMeta) * L.nbox + sizeof(unsigned long long) * L.nbox +
+                    if ((rc = zbuf.ensure(sizeof(BoxMeta) * nbc + sizeof(unsigned long long) * nbc +
                                           sizeof(double) * std::max(o_z, 1L))))
                         return rc;
                     BoxMeta* d_zall = (BoxMeta*)zbuf.p;
-                    unsigned long long* d_keys = (unsigned long long*)(d_zall + L.nbox);
-                    double* Z = (double*)(d_keys + L.nbox);
-                    HIPCHK(hipMemcpyAsync(d_zall, zall.data(), sizeof(BoxMeta) * L.nbox, hipMemcpyHostToDevice, s));
-                    HIPCHK(hipMemcpyAsync(d_keys, keys.data(), sizeof(unsigned long long) * L.nbox,
+                    unsigned long long* d_keys = (unsigned long long*)(d_zall + nbc);
+                    double* Z = (double*)(d_keys + nbc);
+                    HIPCHK(hipMemcpyAsync(d_zall, zall.data(), sizeof(BoxMeta) * nbc, hipMemcpyHostToDevice, s));
+                    HIPCHK(hipMemcpyAsync(d_keys, keys.data(), sizeof(unsigned long long) * nbc,
                                           hipMemcpyHostToDevice, s));
-                    launch_sketch(L.nbox, L.np_max, L.d_meta, d_zall, Y, (const int*)nearbuf.p, Q->d_cidx, P->N,
+                    launch_sketch(nbc, np_max_c, d_meta_c, d_zall, Y, (const int*)nearbuf.p, Q->d_cidx, P->N,
                                   o->sketch_seed, d_keys, Z, s);
                     std::vector<int> kz;
                     if ((rc = id_batch(zm, Z, zpred, kz))) return rc;
@@ -1154,7 +1191,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 }
                 std::sort(det.begin(), det.end());
             } else {
-                for (int B = 0; B < L.nbox; ++B) det.push_back(B);
+                for (int B = b0; B < b1; ++B) det.push_back(B);
             }
             if (!det.empty()) {
                 std::vector<BoxMeta> dm;
@@ -1166,8 +1203,8 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 if ((rc = id_batch(dm, Y, dpred, kd))) return rc;
                 for (size_t e = 0; e < det.size(); ++e) kall[det[e]] = kd[e];
             }
-            HIPCHK(hipMemcpyAsync(L.d_k, kall.data(), sizeof(int) * L.nbox, hipMemcpyHostToDevice, s));
-        } else {
+            HIPCHK(hipMemcpyAsync(d_k_c, kall.data() + b0, sizeof(int) * nbc, hipMemcpyHostToDevice, s));
+        } else if (ci == 0) {
             // root boxes: no compression, k = 0, identity order
             std::vector<int> zeros(L.nbox, 0), ident(o_act);
             for (int B = 0; B < L.nbox; ++B)
@@ -1179,38 +1216,53 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             HIPCHK(hipStreamSynchronize(s));
             F->host_syncs++;
         }
-        launch_box_matrix<R>(PV, L.nbox, L.d_meta, L.d_act, Q->d_cidx,
+        launch_box_matrix<R>(PV, nbc, d_meta_c, L.d_act, Q->d_cidx,
                              o_ch ? (const ChildRef<R>*)chbuf.p : nullptr, App, s);
         // boxes with many DOFs: Cholesky and inverse as multi-workgroup launch sequences
+        // (lists hold chunk-local box indices)
         std::vector<int> small, big;
         int np_big = 0;
-        for (int B = 0; B < L.nbox; ++B) {
+        for (int B = b0; B < b1; ++B) {
             if (L.meta[B].np >= kBigBox) {
-                big.push_back(B);
+                big.push_back(B - b0);
                 np_big = std::max(np_big, L.meta[B].np);
             } else {
-                small.push_back(B);
+                small.push_back(B - b0);
             }
         }
         if (big.empty()) {
-            launch_eliminate<R>(L.nbox, L.d_meta, nullptr, 0, L.d_perm, L.d_k, App, T64, Wk, FF, d_status, bf16, s);
+            launch_eliminate<R>(nbc, d_meta_c, nullptr, 0, L.d_perm, d_k_c, App, T64, Wk, FF, d_status, bf16, s);
         } else {
-            if ((rc = listbuf.ensure(sizeof(int) * L.nbox))) return rc;
+            if ((rc = listbuf.ensure(sizeof(int) * nbc))) return rc;
             int* d_small = (int*)listbuf.p;
             int* d_big = d_small + small.size();
             std::vector<int> lists(small);
             lists.insert(lists.end(), big.begin(), big.end());
             HIPCHK(hipMemcpyAsync(d_small, lists.data(), sizeof(int) * lists.size(), hipMemcpyHostToDevice, s));
-            launch_eliminate<R>((int)small.size(), L.d_meta, d_small, 0, L.d_perm, L.d_k, App, T64, Wk, FF,
+            launch_eliminate<R>((int)small.size(), d_meta_c, d_small, 0, L.d_perm, d_k_c, App, T64, Wk, FF,
                                 d_status, bf16, s);
-            launch_big_schur<R>((int)big.size(), np_big, L.d_meta, d_big, 1, L.d_perm, L.d_k, App, T64, Wk, FF,
+            launch_big_schur<R>((int)big.size(), np_big, d_meta_c, d_big, 1, L.d_perm, d_k_c, App, T64, Wk, FF,
                                 bf16, s);
-            launch_big_cholesky_inverse<R>((int)big.size(), np_big, L.d_meta, d_big, L.d_k, Wk, FF, d_status, s);
-            launch_big_schur<R>((int)big.size(), np_big, L.d_meta, d_big, 2, L.d_perm, L.d_k, App, T64, Wk, FF,
+            launch_big_cholesky_inverse<R>((int)big.size(), np_big, d_meta_c, d_big, d_k_c, Wk, FF, d_status, s);
+            launch_big_schur<R>((int)big.size(), np_big, d_meta_c, d_big, 2, L.d_perm, d_k_c, App, T64, Wk, FF,
                                 bf16, s);
             HIPCHK(hipStreamSynchronize(s));   // `lists` is read by the copy above
             F->host_syncs++;
         }
+        if (cut.size() > 2) {
+            // a breakdown names a chunk-local box: check before the next chunk
+            int st_c = 0;
+            HIPCHK(hipMemcpyAsync(&st_c, d_status, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            F->host_syncs++;
+            if (st_c) {
+                const int B = b0 + st_c - 1;
+                return fail(CBD_ENOTSPD, "rs_factor_batched: Cholesky breakdown at level " + std::to_string(l) +
+                                             (root ? " (root)" : "") + ", subdomain " +
+                                             std::to_string(L.box_sub[B]) + ", box " + std::to_string(L.box_idx[B]));
+            }
+        }
+        }   // chunks
         HIPCHK(hipGetLastError());
         L.k.resize(L.nbox);
         L.sr.resize(o_act);
@@ -1459,7 +1511,8 @@ extern "C" int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* 
 }
 
 extern "C" int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
-                                  double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks) {
+                                  double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks,
+                                  int* chunks) {
     if (!f) return fail(CBD_EARG, "rs_factor_schedule: NULL factor");
     if (host_syncs) *host_syncs = f->host_syncs;
     if (qr_steps) *qr_steps = f->qr_steps;
@@ -1468,6 +1521,7 @@ extern "C" int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, 
     if (row_compressed) *row_compressed = f->hqr_levels;
     if (sketched) *sketched = f->sketched;
     if (sketch_fallbacks) *sketch_fallbacks = f->sketch_fallbacks;
+    if (chunks) *chunks = f->chunks;
     return CBD_OK;
 }
 

@@ -567,3 +567,37 @@ def test_sketched_ids_full_size_pcg():
     rows = np.random.default_rng(2).choice(O.N, 32, replace=False)
     res = f[0][rows] - cmatvec.matvec(O, u[0].cpu().numpy(), rows=rows)
     assert np.sqrt(np.mean(res ** 2)) <= 1e-8 * np.linalg.norm(f[0]) / np.sqrt(O.N)
+
+
+@pytest.mark.parametrize("case", ["cfg1", "cfg1_sketch", "big_roots"])
+def test_chunked_levels_give_the_same_factors(case):
+    # a small workspace budget splits every level into chunks of consecutive boxes;
+    # each box's factor is the one of the unsplit level
+    if case == "big_roots":
+        P, _ = gpu_problem(2, 128)
+        part, tol, seed = cbd.Partition(P, 8, 1, cbd.MODE_CBD, 0), 1e-6, None
+    else:
+        P, _ = gpu_problem(2, 64)
+        part, tol = cbd.Partition(P, 16, 1, cbd.MODE_CBD, 0), 1e-8
+        seed = 7 if case == "cfg1_sketch" else None
+    F0 = cbd.Factor(P, part, tol=tol, n_pxy=64, sketch_seed=seed)
+    F1 = cbd.Factor(P, part, tol=tol, n_pxy=64, sketch_seed=seed, workspace_bytes=2 << 20)
+    s0, s1 = F0.schedule(), F1.schedule()
+    nlev = F0.stats()["levels"]
+    print(case, "chunks", s0["chunks"], "->", s1["chunks"], flush=True)
+    assert s0["chunks"] == nlev + 1 and s1["chunks"] > s0["chunks"]
+    for l in range(nlev + 1):
+        assert F0.level(l) == F1.level(l), l
+    for l in range(nlev):
+        count = {}
+        for i in F0.level(l)[2]:
+            b = count.get(i, 0)
+            count[i] = b + 1
+            g0, g1 = F0.box(i, l, b), F1.box(i, l, b)
+            assert np.array_equal(g0["sk"], g1["sk"]) and np.array_equal(g0["rd"], g1["rd"])
+            for key in ("T", "E", "Ginv", "Bss"):
+                if g0[key].size:
+                    assert rel(g1[key], g0[key]) <= 1e-9, (l, i, b, key)
+    r = torch.tensor(synth.rhs(P.N, 2, seed=3), device=DEV)
+    z0, z1 = F0.apply(r), F1.apply(r)
+    assert (z1 - z0).norm() <= 1e-10 * z0.norm()
