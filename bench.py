@@ -54,6 +54,10 @@ WORKLOADS = {
                     prec="fp32", coef=False, sketch=True, fft=True,
                     label="3D 128^3 (N=2097152), CBD m=16 (N/M=512), tol 1e-3, 256 proxy pts, sketched IDs, "
                           "1 RHS, FP32 factors, FFT matvec in PCG"),
+    "256cube": dict(d=3, n=256, m=32, mode="cbd", delta=1, leaf=0, tol=1e-3, npxy=256, nrhs=1,
+                    prec="fp32", coef=False, sketch=True, fft=True, dense=False, variants=False,
+                    label="3D 256^3 (N=16777216), CBD m=32 (N/M=512), tol 1e-3, 256 proxy pts, sketched IDs, "
+                          "1 RHS, FP32 factors, FFT matvec in PCG (no dense product: 2.8e14 pairs)"),
     "global512": dict(d=2, n=512, m=1, mode="jacobi", delta=0, leaf=8, tol=1e-6, npxy=64, nrhs=64,
                       prec="fp32", coef=True,
                       label="2D 512^2, global RS (one subdomain, 8x8 leaf tiles), b=c=1+0.5sin(2pi x1)cos(2pi x2), "
@@ -137,6 +141,8 @@ def main():
     prec = {"fp32": cbd.PREC_FP32, "fp64": cbd.PREC_FP64}[W["prec"]]
     sk_seed = 1 if W.get("sketch") else None      # randomized IDs
     use_fft = bool(W.get("fft"))                   # PCG products by FFT (workloads too large for the dense form)
+    dense = W.get("dense", True)                   # time the dense matvec (autotune, roofline)
+    full = W.get("variants", True)                 # the variants (no predictor, FFT, sketch, bf16, FP64 form)
     N = n ** d
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     coef = torch.tensor(synth.coef_smooth(d, n)) if W["coef"] else None
@@ -157,8 +163,8 @@ def main():
 
     P.fft_prepare(max_pairs=8)
     # tile shape of the matvec, chosen by the library's autotuner
-    tile = P.autotune_matvec(nrhs)
-    tile1 = P.autotune_matvec(1)
+    tile = P.autotune_matvec(nrhs) if dense else 0
+    tile1 = P.autotune_matvec(1) if dense else 0
     log("matvec tile: %d row blocks per wave (%d RHS), %d (1 RHS)" % (tile, nrhs, tile1))
 
     # rank predictor trained on ranks of the 64^2, 256^2 and 512^2 factorizations
@@ -202,17 +208,19 @@ def main():
     sched = fac.schedule()
     factor_s = float(np.mean(tf))
     # the same factorization without the predictor
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fac_nm = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, sketch_seed=sk_seed)
-    torch.cuda.synchronize()
-    factor_nm_s = time.perf_counter() - t0
-    sched_nm = fac_nm.schedule()
-    del fac_nm
+    factor_nm_s, sched_nm = None, {"host_syncs": None}
+    if full:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac_nm = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, sketch_seed=sk_seed)
+        torch.cuda.synchronize()
+        factor_nm_s = time.perf_counter() - t0
+        sched_nm = fac_nm.schedule()
+        del fac_nm
     pcg_s = float(np.mean(ts))
     n_it = its_all[-1]
 
-    if mv_n == 0:
+    if mv_n == 0 and dense:
         # the PCG used FFT products: time one dense product for the roofline record
         cbd.timing.reset()
         cbd.timing.enable(True)
@@ -221,75 +229,78 @@ def main():
         cbd.timing.enable(False)
         mv_ms, mv_n = cbd.timing.get("matvec")
     # matvec roofline: product flops 2 N^2 nrhs per launch (kernel evaluations extra)
-    mv_avg_s = mv_ms / 1e3 / max(mv_n, 1)
+    mv_avg_s = mv_ms / 1e3 / mv_n if mv_n else None
     mv_flops = 2.0 * N * N * nrhs
-    achieved = mv_flops / mv_avg_s / 1e12
+    achieved = mv_flops / mv_avg_s / 1e12 if mv_avg_s else None
 
-    # the paper's matvec (FFT on the uniform grid) with the same factors, for comparison
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, its_fft, rr_fft = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200, fft=True)
-    torch.cuda.synchronize()
-    pcg_fft_s = time.perf_counter() - t0
-    log("pcg with the FFT matvec: %.3f s, iterations %d-%d" % (pcg_fft_s, min(its_fft), max(its_fft)))
-
-    # randomized IDs: the CPQR of a random-sign sketch of each proxy matrix (the scheme of
-    # the paper's last 3D runs); same predictor, same PCG
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fac_sk = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=1)
-    torch.cuda.synchronize()
-    sk_factor = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    _, its_sk, rr_sk = cbd.pcg_solve(P, fac_sk, F_rhs, tol=1e-10, maxit=200, fft=use_fft)
-    torch.cuda.synchronize()
-    sk_sched = fac_sk.schedule()
-    sketched = {"factor_s": sk_factor, "factor_gflops": fac_sk.stats()["flops"] / sk_factor / 1e9,
-                "pcg_s": time.perf_counter() - t0, "n_it": [min(its_sk), max(its_sk)], "max_relres": max(rr_sk),
-                "sketched_boxes": sk_sched["sketched"], "fallback_boxes": sk_sched["sketch_fallbacks"]}
-    del fac_sk
-    log("sketched IDs: %s" % sketched)
-
-    # the bfloat16-GEMM variant of the factors (Schur products on bf16 operands)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    bf16 = None
-    try:
-        fac_bf = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_BF16GEMM, mlp=mlp,
-                            sketch_seed=sk_seed)
+    pcg_fft_s, its_fft, rr_fft, sketched, bf16 = None, [0], [0.0], None, None
+    f64_factor, f64_pcg, ncols, its64 = None, None, 0, []
+    if full:
+        # the paper's matvec (FFT on the uniform grid) with the same factors, for comparison
         torch.cuda.synchronize()
-        bf_factor = time.perf_counter() - t0
         t0 = time.perf_counter()
-        _, its_bf, rr_bf = cbd.pcg_solve(P, fac_bf, F_rhs, tol=1e-10, maxit=400, flexible=True, fft=use_fft)
+        _, its_fft, rr_fft = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200, fft=True)
         torch.cuda.synchronize()
-        bf16 = {"factor_s": bf_factor, "pcg_s": time.perf_counter() - t0, "n_it": [min(its_bf), max(its_bf)],
-                "max_relres": max(rr_bf), "pcg": "flexible"}
-        del fac_bf
-    except cbd.CbdError as e:
-        bf16 = {"error": str(e)}
-    log("bf16-GEMM variant: %s" % bf16)
+        pcg_fft_s = time.perf_counter() - t0
+        log("pcg with the FFT matvec: %.3f s, iterations %d-%d" % (pcg_fft_s, min(its_fft), max(its_fft)))
 
-    # plain FP64 form: FP64 factors, right-hand sides one at a time
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fac64 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_FP64, sketch_seed=sk_seed)
-    torch.cuda.synchronize()
-    f64_factor = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    its64 = []
-    ncols = min(args.fp64_cols, nrhs)
-    for c in range(ncols):
-        _, it, _ = cbd.pcg_solve(P, fac64, F_rhs[c], tol=1e-10, maxit=200, fft=use_fft)
-        its64.append(it)
-    torch.cuda.synchronize()
-    f64_per_col = (time.perf_counter() - t0) / max(ncols, 1)
-    f64_pcg = f64_per_col * nrhs if ncols > 0 else float("nan")
-    log("fp64 form: factor %.3f s, %.3f s per column" % (f64_factor, f64_per_col))
+        # randomized IDs: the CPQR of a random-sign sketch of each proxy matrix (the scheme of
+        # the paper's last 3D runs); same predictor, same PCG
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac_sk = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=1)
+        torch.cuda.synchronize()
+        sk_factor = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, its_sk, rr_sk = cbd.pcg_solve(P, fac_sk, F_rhs, tol=1e-10, maxit=200, fft=use_fft)
+        torch.cuda.synchronize()
+        sk_sched = fac_sk.schedule()
+        sketched = {"factor_s": sk_factor, "factor_gflops": fac_sk.stats()["flops"] / sk_factor / 1e9,
+                    "pcg_s": time.perf_counter() - t0, "n_it": [min(its_sk), max(its_sk)], "max_relres": max(rr_sk),
+                    "sketched_boxes": sk_sched["sketched"], "fallback_boxes": sk_sched["sketch_fallbacks"]}
+        del fac_sk
+        log("sketched IDs: %s" % sketched)
+
+        # the bfloat16-GEMM variant of the factors (Schur products on bf16 operands)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bf16 = None
+        try:
+            fac_bf = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_BF16GEMM, mlp=mlp,
+                                sketch_seed=sk_seed)
+            torch.cuda.synchronize()
+            bf_factor = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            _, its_bf, rr_bf = cbd.pcg_solve(P, fac_bf, F_rhs, tol=1e-10, maxit=400, flexible=True, fft=use_fft)
+            torch.cuda.synchronize()
+            bf16 = {"factor_s": bf_factor, "pcg_s": time.perf_counter() - t0, "n_it": [min(its_bf), max(its_bf)],
+                    "max_relres": max(rr_bf), "pcg": "flexible"}
+            del fac_bf
+        except cbd.CbdError as e:
+            bf16 = {"error": str(e)}
+        log("bf16-GEMM variant: %s" % bf16)
+
+        # plain FP64 form: FP64 factors, right-hand sides one at a time
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac64 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_FP64, sketch_seed=sk_seed)
+        torch.cuda.synchronize()
+        f64_factor = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        its64 = []
+        ncols = min(args.fp64_cols, nrhs)
+        for c in range(ncols):
+            _, it, _ = cbd.pcg_solve(P, fac64, F_rhs[c], tol=1e-10, maxit=200, fft=use_fft)
+            its64.append(it)
+        torch.cuda.synchronize()
+        f64_per_col = (time.perf_counter() - t0) / max(ncols, 1)
+        f64_pcg = f64_per_col * nrhs if ncols > 0 else float("nan")
+        log("fp64 form: factor %.3f s, %.3f s per column" % (f64_factor, f64_per_col))
 
     cpu = None
     if args.cpu_rows < 0:
         # the row cost is proportional to N * nrhs
-        args.cpu_rows = int(min(N, max(64, 16384.0 * (512 ** 2 * 64) / (float(N) * nrhs))))
+        args.cpu_rows = int(min(N, max(64, 16384.0 * (512 ** 2 * 64) / (float(N) * nrhs) / (4 if d == 3 else 1))))
     if args.cpu_rows > 0:
         from oracle import cmatvec, ie
         O = ie.Problem(d, n, b=None if coef is None else coef.numpy(), c=None if coef is None else coef.numpy())
@@ -331,7 +342,7 @@ def main():
         "factor_bytes": st["bytes"],
         "n_it": [min(n_it), max(n_it)],
         "max_relres": max(rr_all),
-        "matvec_avg_ms": mv_avg_s * 1e3,
+        "matvec_avg_ms": mv_avg_s * 1e3 if mv_avg_s else None,
         "apply_avg_ms": ap_ms / max(ap_n, 1),
         "matvec_tile_rows_per_wave": 16 * tile,
         "sketched_id_variant": sketched,
@@ -339,7 +350,7 @@ def main():
         "pcg_with_fft_matvec": {"pcg_s": pcg_fft_s, "n_it": [min(its_fft), max(its_fft)],
                                 "max_relres": max(rr_fft),
                                 "note": "same factors; products with A by circulant-embedding FFT (Section 5 of "
-                                        "the paper) instead of the dense on-the-fly matvec"},
+                                        "the paper) instead of the dense on-the-fly matvec"} if full else None,
         "rank_predictor": {"train_s": mlp_train_s, "mean_abs_rank_err": sched["mean_abs_err"],
                            "factor_s_with": factor_s, "factor_s_without": factor_nm_s,
                            "host_syncs_with": sched["host_syncs"], "host_syncs_without": sched_nm["host_syncs"],
@@ -347,15 +358,15 @@ def main():
         "fp64_form": {"factor_s": f64_factor, "pcg_s_est": f64_pcg, "cols_timed": ncols,
                       "n_it": its64,
                       "note": "PCG time measured on %d columns solved one at a time, scaled to %d"
-                              % (ncols, nrhs)},
+                              % (ncols, nrhs)} if full else None,
         "speedup_mixed_vs_fp64": {"pcg": f64_pcg / pcg_s, "factor": f64_factor / factor_s,
-                                  "total": (f64_pcg + f64_factor) / (pcg_s + factor_s)},
+                                  "total": (f64_pcg + f64_factor) / (pcg_s + factor_s)} if full else None,
         "roofline": {"kernel": "kernel_matvec (FP64, %d RHS)" % nrhs, "bound": "mfma",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic() if args.workload == "512sq" else None,
                      "work": "2 N^2 nrhs FP64 flops per launch on FP64 MFMA (the N^2 kernel "
-                             "evaluations run on the VALU and are not counted)"},
+                             "evaluations run on the VALU and are not counted)"} if achieved else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
