@@ -1231,7 +1231,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             }
         }
         if (big.empty()) {
-            launch_eliminate<R>(nbc, d_meta_c, nullptr, 0, L.d_perm, d_k_c, App, T64, Wk, FF, d_status, bf16, s);
+            launch_eliminate<R>(nbc, d_meta_c, nullptr, L.d_perm, d_k_c, App, T64, Wk, FF, d_status, bf16, s);
         } else {
             if ((rc = listbuf.ensure(sizeof(int) * nbc))) return rc;
             int* d_small = (int*)listbuf.p;
@@ -1239,7 +1239,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             std::vector<int> lists(small);
             lists.insert(lists.end(), big.begin(), big.end());
             HIPCHK(hipMemcpyAsync(d_small, lists.data(), sizeof(int) * lists.size(), hipMemcpyHostToDevice, s));
-            launch_eliminate<R>((int)small.size(), d_meta_c, d_small, 0, L.d_perm, d_k_c, App, T64, Wk, FF,
+            launch_eliminate<R>((int)small.size(), d_meta_c, d_small, L.d_perm, d_k_c, App, T64, Wk, FF,
                                 d_status, bf16, s);
             launch_big_schur<R>((int)big.size(), np_big, d_meta_c, d_big, 1, L.d_perm, d_k_c, App, T64, Wk, FF,
                                 bf16, s);

@@ -162,14 +162,14 @@ void launch_hqr(int nbox, int np_max, int m_max, int k_max, const BoxMeta* meta,
 template <typename R>
 void launch_box_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, const int* act,
                        const int* cidx, const ChildRef<R>* ch, R* App, hipStream_t s);
-// phase 0: whole elimination per box; 1: up to B_rr; 2: E and B_ss (list: box indices or NULL)
+// the whole elimination of each box in one workgroup (list: box indices or NULL)
 // bf16: Schur-complement products with bfloat16 operands and FP32 accumulation (R = float)
 template <typename R>
-void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, int phase, const int* perm,
+void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, const int* perm,
                       const int* k, const R* App, const double* T64, R* Wk, R* F, int* status,
                       bool bf16, hipStream_t s);
 // the elimination of the boxes in list as multi-workgroup launches: phase 1 up to B_rr,
-// phase 2 E and B_ss (the same arithmetic as launch_eliminate's phases 1 and 2)
+// phase 2 E and B_ss (the arithmetic of launch_eliminate, spread over many workgroups)
 template <typename R>
 void launch_big_schur(int nbig, int np_max, const BoxMeta* meta, const int* list, int phase, const int* perm,
                       const int* k, const R* App, const double* T64, R* Wk, R* F, bool bf16, hipStream_t s);

@@ -1220,9 +1220,9 @@ __device__ void wg_triangular_inverse(int n, const R* G, int ldg, R* X, R* W) {
 // A root box has k = 0: its slot receives G^{-1} of the whole box matrix.
 // Scratch per box: np^2 + kBig*np elements at its y offset.
 //
-// phase 0: everything in one workgroup (boxes of moderate size);
-// phase 1: up to B_rr (the large boxes, whose Cholesky and inverse then run as
-//          multi-workgroup launch sequences); phase 2: E and B_ss afterwards.
+// Boxes of moderate size: the whole elimination in one workgroup (k_eliminate).
+// Large boxes: the same steps as multi-workgroup launch sequences (k_big_gather,
+// k_big_gemm, the blocked Cholesky and inverse).
 constexpr int kBig = 64;   // block size of the multi-workgroup Cholesky / inverse
 
 template <typename R>
@@ -1256,14 +1256,14 @@ __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restric
                                                         const R* __restrict__ App,
                                                         const double* __restrict__ T64,
                                                         R* __restrict__ Wk, R* __restrict__ F,
-                                                        int* __restrict__ status, int phase) {
+                                                        int* __restrict__ status) {
     __shared__ int s_fail;
     const int b = list ? list[blockIdx.x] : blockIdx.x;
     const BoxMeta M = meta[b];
     const ElimView<R> V = elim_view<R>(M, kk[b], Wk, F);
     const int np = V.np, k = V.k, nr = V.nr;
     const int tid = threadIdx.x;
-    if (phase != 2) {
+    {
         const int* pv = perm + M.act;
         const R* A = App + M.app;
         for (long e = tid; e < (long)k * nr; e += kThreads) V.T[e] = (R)T64[M.f + e];
@@ -1278,7 +1278,6 @@ __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restric
         for (long e = tid; e < (long)nr * nr; e += kThreads) {
             const int i = (int)(e % nr), c = (int)(e / nr);
             V.Brr[e] = A[pv[k + i] + (long)pv[k + c] * np];
-            if (phase == 1 && i > c) V.Gi[e] = (R)0;   // lower triangle of G^{-1}
         }
         if (tid == 0) s_fail = 0;
         __syncthreads();
@@ -1287,7 +1286,6 @@ __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restric
             schur_gemm<R, BF16>(k, nr, k, (R)-1, V.Ass, k, false, V.T, k, false, (R)1, V.Bsr, k);          // B_sr
             schur_gemm<R, BF16>(nr, nr, k, (R)-1, V.Bsr, k, true, V.T, k, false, (R)1, V.Brr, nr, true);   // - B_sr^T T
         }
-        if (phase == 1) return;
         if (!wg_cholesky_upper<R>(nr, V.Brr, nr, &s_fail)) {
             if (tid == 0) status[0] = b + 1;
             return;
@@ -1544,18 +1542,18 @@ __global__ __launch_bounds__(kThreads) void k_binv(const BoxMeta* __restrict__ m
 }
 
 template <typename R>
-void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, int phase, const int* perm, const int* k,
+void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, const int* perm, const int* k,
                       const R* App, const double* T64, R* Wk, R* F, int* status, bool bf16, hipStream_t s) {
     if (nbox == 0) return;
     if constexpr (sizeof(R) == 4) {
         if (bf16) {
             hipLaunchKernelGGL((k_eliminate<R, true>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App,
-                               T64, Wk, F, status, phase);
+                               T64, Wk, F, status);
             return;
         }
     }
     hipLaunchKernelGGL((k_eliminate<R, false>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App, T64,
-                       Wk, F, status, phase);
+                       Wk, F, status);
 }
 
 template <typename R>
@@ -1762,7 +1760,7 @@ template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta
 #define CBD_INST(R)                                                                                 \
     template void launch_box_matrix<R>(const ProblemView&, int, const BoxMeta*, const int*,         \
                                        const int*, const ChildRef<R>*, R*, hipStream_t);            \
-    template void launch_eliminate<R>(int, const BoxMeta*, const int*, int, const int*, const int*, \
+    template void launch_eliminate<R>(int, const BoxMeta*, const int*, const int*, const int*, \
                                       const R*, const double*, R*, R*, int*, bool, hipStream_t);    \
     template void launch_big_schur<R>(int, int, const BoxMeta*, const int*, int, const int*, const int*, \
                                       const R*, const double*, R*, R*, bool, hipStream_t);          \
