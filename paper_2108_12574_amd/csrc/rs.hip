@@ -762,15 +762,19 @@ __global__ __launch_bounds__(kThreads) void k_hqr_update(const BoxMeta* __restri
     const bool cin = col >= lo && col < hi;
     const double* ycol = Yb + (long)(cin ? col : lo) * m;
     // W = V^T A: rows j0.. in 4-row steps, step s on wave s % kWaves
+    // (reflectors w..31 are zero: a panel of at most 16 skips the second half)
+    const bool two = w > 16;
     v4 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
     for (int r0 = j0 + 4 * wid; r0 < m; r0 += 4 * kWaves) {
         const int r = r0 + lk;
         const bool rin = r < m;
         const double a0 = rin ? Vt[li + (long)r * kHqrPanel] : 0.0;
-        const double a1 = rin ? Vt[16 + li + (long)r * kHqrPanel] : 0.0;
         const double bb = (rin && cin) ? ycol[r] : 0.0;
         w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb, w0, 0, 0, 0);
-        w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb, w1, 0, 0, 0);
+        if (two) {
+            const double a1 = rin ? Vt[16 + li + (long)r * kHqrPanel] : 0.0;
+            w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb, w1, 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -804,11 +808,20 @@ __global__ __launch_bounds__(kThreads) void k_hqr_update(const BoxMeta* __restri
         }
         const int ra = t0 + li;
 #pragma unroll
-        for (int ks = 0; ks < kHqrPanel / 4; ++ks) {
+        for (int ks = 0; ks < kHqrPanel / 8; ++ks) {
             const int a = 4 * ks + lk;
             const double av = ra < m ? Vc[ra + (long)a * m] : 0.0;
             const double bv = Wn[a + li * kHqrPanel];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        if (two) {
+#pragma unroll
+            for (int ks = kHqrPanel / 8; ks < kHqrPanel / 4; ++ks) {
+                const int a = 4 * ks + lk;
+                const double av = ra < m ? Vc[ra + (long)a * m] : 0.0;
+                const double bv = Wn[a + li * kHqrPanel];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
         }
         if (cin) {
 #pragma unroll
