@@ -615,7 +615,11 @@ struct DevBuf {
     size_t bytes = 0;
     int ensure(size_t b) {
         if (b <= bytes) return CBD_OK;
-        if (p) (void)hipFree(p);
+        if (p) {
+            // queued kernels of an earlier level may still use the old buffer
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
         if (hipMalloc(&p, b) != hipSuccess) return fail(CBD_ENOMEM, "hipMalloc of workspace failed");
@@ -623,7 +627,10 @@ struct DevBuf {
         return CBD_OK;
     }
     ~DevBuf() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(p);
+        }
     }
 };
 
@@ -729,14 +736,16 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
     DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf, mlpbuf, listbuf, hqrbuf, idbuf, zbuf;
     if ((rc = dirbuf.ensure(sizeof(double) * hdir.size()))) return rc;
     HIPCHK(hipMemcpyAsync(dirbuf.p, hdir.data(), sizeof(double) * hdir.size(), hipMemcpyHostToDevice, s));
-    if ((rc = statbuf.ensure(sizeof(int)))) return rc;
-    HIPCHK(hipMemsetAsync(statbuf.p, 0, sizeof(int), s));
-    int* d_status = (int*)statbuf.p;
 
     int Lmax = 0;
     if (!o->exact)
         for (auto& sd : Q->subs) Lmax = std::max(Lmax, sd.root_level);
     F->n_compress = Lmax;
+    // one Cholesky-breakdown slot per level, read once at the end: the host plans a
+    // level while the previous level's elimination runs
+    if ((rc = statbuf.ensure(sizeof(int) * (Lmax + 1)))) return rc;
+    HIPCHK(hipMemsetAsync(statbuf.p, 0, sizeof(int) * (Lmax + 1), s));
+    std::vector<std::vector<int>> keep;   // host sources of uploads still in flight
     // grid coordinates of a global index
     // half-cell coordinates 2 j_t + 1 of every slot (near-field tests in integers)
     const long nslot = (long)Q->cidx.size();
@@ -1020,6 +1029,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         int* d_k_c = L.d_k + b0;
         int np_max_c = 0;
         for (int B = b0; B < b1; ++B) np_max_c = std::max(np_max_c, L.meta[B].np);
+        int* d_status = (int*)statbuf.p + l;
         if (!root) {
             launch_proxy_matrix<double>(PV, nbc, d_meta_c, L.d_act, (const int*)nearbuf.p, Q->d_cidx,
                                         (const double*)dirbuf.p, npxy, Y, s);
@@ -1203,7 +1213,16 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 if ((rc = id_batch(dm, Y, dpred, kd))) return rc;
                 for (size_t e = 0; e < det.size(); ++e) kall[det[e]] = kd[e];
             }
-            HIPCHK(hipMemcpyAsync(d_k_c, kall.data() + b0, sizeof(int) * nbc, hipMemcpyHostToDevice, s));
+            // ranks and skeleton lists of the chunk to the host now (the ID is complete), so
+            // that the next level can be planned while this chunk's elimination runs
+            L.k.resize(L.nbox);
+            L.sr.resize(o_act);
+            for (int B = b0; B < b1; ++B) L.k[B] = kall[B];
+            const long a0 = L.meta[b0].act, a1 = b1 < L.nbox ? L.meta[b1].act : o_act;
+            HIPCHK(hipMemcpyAsync(d_k_c, L.k.data() + b0, sizeof(int) * nbc, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(L.sr.data() + a0, L.d_sr + a0, sizeof(int) * (a1 - a0), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            F->host_syncs++;
         } else if (ci == 0) {
             // root boxes: no compression, k = 0, identity order
             std::vector<int> zeros(L.nbox, 0), ident(o_act);
@@ -1215,6 +1234,8 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             // the host vectors must stay alive until the copies finish
             HIPCHK(hipStreamSynchronize(s));
             F->host_syncs++;
+            L.k.assign(L.nbox, 0);
+            L.sr = hact;
         }
         launch_box_matrix<R>(PV, nbc, d_meta_c, L.d_act, Q->d_cidx,
                              o_ch ? (const ChildRef<R>*)chbuf.p : nullptr, App, s);
@@ -1236,7 +1257,8 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             if ((rc = listbuf.ensure(sizeof(int) * nbc))) return rc;
             int* d_small = (int*)listbuf.p;
             int* d_big = d_small + small.size();
-            std::vector<int> lists(small);
+            keep.emplace_back(small);
+            std::vector<int>& lists = keep.back();
             lists.insert(lists.end(), big.begin(), big.end());
             HIPCHK(hipMemcpyAsync(d_small, lists.data(), sizeof(int) * lists.size(), hipMemcpyHostToDevice, s));
             launch_eliminate<R>((int)small.size(), d_meta_c, d_small, L.d_perm, d_k_c, App, T64, Wk, FF,
@@ -1246,8 +1268,6 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             launch_big_cholesky_inverse<R>((int)big.size(), np_big, d_meta_c, d_big, d_k_c, Wk, FF, d_status, s);
             launch_big_schur<R>((int)big.size(), np_big, d_meta_c, d_big, 2, L.d_perm, d_k_c, App, T64, Wk, FF,
                                 bf16, s);
-            HIPCHK(hipStreamSynchronize(s));   // `lists` is read by the copy above
-            F->host_syncs++;
         }
         if (cut.size() > 2) {
             // a breakdown names a chunk-local box: check before the next chunk
@@ -1264,23 +1284,9 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         }
         }   // chunks
         HIPCHK(hipGetLastError());
-        L.k.resize(L.nbox);
-        L.sr.resize(o_act);
-        int status = 0;
-        HIPCHK(hipMemcpyAsync(L.k.data(), L.d_k, sizeof(int) * L.nbox, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(L.sr.data(), L.d_sr, sizeof(int) * o_act, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        F->host_syncs++;
         for (size_t B = 0; B < kpred.size(); ++B) {
             F->pred_abs_err += std::abs(kpred[B] - L.k[B]);
             F->pred_count++;
-        }
-        if (status) {
-            const int B = status - 1;
-            return fail(CBD_ENOTSPD, "rs_factor_batched: Cholesky breakdown at level " + std::to_string(l) +
-                                         (root ? " (root)" : "") + ", subdomain " +
-                                         std::to_string(L.box_sub[B]) + ", box " + std::to_string(L.box_idx[B]));
         }
         for (int B = 0; B < L.nbox; ++B) {
             const double np = L.meta[B].np, k = L.k[B], nr = np - k;
@@ -1290,6 +1296,19 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             }
             F->flops += elim_flops(k, nr);
         }
+    }
+    // breakdowns (one slot per level; a split level was checked chunk by chunk)
+    std::vector<int> status(Lmax + 1, 0);
+    HIPCHK(hipMemcpyAsync(status.data(), statbuf.p, sizeof(int) * (Lmax + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    F->host_syncs++;
+    for (int l = 0; l <= Lmax; ++l) {
+        if (!status[l]) continue;
+        const Level& L = F->levels[l];
+        const int B = status[l] - 1;
+        return fail(CBD_ENOTSPD, "rs_factor_batched: Cholesky breakdown at level " + std::to_string(l) +
+                                     (l == Lmax ? " (root)" : "") + ", subdomain " + std::to_string(L.box_sub[B]) +
+                                     ", box " + std::to_string(L.box_idx[B]));
     }
     F->S.assign(D, 0);
     const Level& RL = F->levels.back();
