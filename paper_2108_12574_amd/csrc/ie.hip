@@ -51,15 +51,17 @@ constexpr int kMvThreads = 256;
 constexpr int kMvWaves = kMvThreads / 64;
 constexpr int kTJ = 64;                // sources per LDS tile
 constexpr int kLdw = kTJ + 2;          // LDS row stride of the [rhs][j] tile (doubles)
-constexpr int kLogTab = 1024;
+constexpr int kLogBits = 11;
+constexpr int kLogTab = 1 << kLogBits;
 
 // 2D kernel value from r^2: K = -(1/2pi) log r = c log r^2, c = -1/(4 pi).
 // Table-driven logarithm (after Tang, ACM TOMS 15(2), 1989), with the constant c
 // folded into the table and the polynomial: r^2 = 2^e m, m in [1/2, 1) (frexp);
-// F_j = (1 + j/1024)/2 from the top 10 fraction bits of m, so u = m/F_j - 1 lies
-// in [0, 2^-10); c log r^2 = e (c ln2) + c log F_j + c log1p(u), with log1p(u) by
-// its Taylor series to u^4 (truncation below 2e-17 absolute, under one rounding of
-// the result).  tab[2j] = c log F_j and tab[2j+1] = 1/F_j, rounded from long
+// the top 11 fraction bits of m select the interval [1/2 + j/4096, 1/2 + (j+1)/4096)
+// and its midpoint F_j, so u = m/F_j - 1 lies in (-2^-12, 2^-12);
+// c log r^2 = e (c ln2) + c log F_j + c log1p(u), with log1p(u) by its Taylor series
+// to u^3 (alternating, so the truncation is below u^4/4 < 9e-16, i.e. 7e-17 absolute
+// after the factor c).  tab[2j] = c log F_j and tab[2j+1] = 1/F_j, rounded from long
 // double on the host.  r^2 = 0 (the pair i = j) gives e = 0, m = 0 and a finite
 // value, which the product's epilogue removes again.
 __device__ __forceinline__ double klog_r2(double x, const double* __restrict__ tab) {
@@ -68,11 +70,11 @@ __device__ __forceinline__ double klog_r2(double x, const double* __restrict__ t
     const int e = __builtin_amdgcn_frexp_exp(x);
     const double m = __builtin_amdgcn_frexp_mant(x);
     const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(x) >> 32);
-    const unsigned off = (hi >> 6) & ((kLogTab - 1) << 4);   // byte offset of entry j
+    // the high word holds the top 20 fraction bits; entry j is 16 bytes
+    const unsigned off = (hi >> (16 - kLogBits)) & ((kLogTab - 1) << 4);
     const double2 t = *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(tab) + off);
     const double u = fma(m, t.y, -1.0);
-    double p = -c / 4.0;
-    p = fma(p, u, c / 3.0);
+    double p = c / 3.0;
     p = fma(p, u, -c / 2.0);
     p = fma(p, u, c);
     return fma((double)e, cln2, fma(p, u, t.x));
@@ -86,6 +88,15 @@ __device__ __forceinline__ double kernel_r2(double r2, const double* __restrict_
         return kInv4Pi * rsqrt(r2);
 }
 
+// LDS of the product, small arrays first so that every access keeps a 16-bit immediate
+// offset; the log table only in 2D
+template <int D>
+struct MvShared {
+    double sxj[D][kTJ];
+    double swx[64 * kLdw];
+    alignas(16) double stab[D == 2 ? 2 * kLogTab : 2];
+};
+
 constexpr int kSR = kMvThreads / kTJ;  // staging threads per source
 static_assert(kMvThreads % kTJ == 0 && 64 % kSR == 0, "staging layout");
 
@@ -94,9 +105,7 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
                                                        const double* __restrict__ x,
                                                        double* __restrict__ y,
                                                        const double* __restrict__ logtab) {
-    __shared__ double sxj[D][kTJ];
-    __shared__ double swx[64 * kLdw];
-    __shared__ __attribute__((aligned(16))) double stab[2 * kLogTab];
+    __shared__ MvShared<D> sh;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const long N = P.N;
@@ -104,7 +113,7 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
     const long ibase = (long)blockIdx.x * (kMvWaves * kRB * 16) + wave * (kRB * 16);
     const int li = lane & 15, lk = lane >> 4;
     if (D == 2)
-        for (int e = tid; e < 2 * kLogTab; e += kMvThreads) stab[e] = logtab[e];
+        for (int e = tid; e < 2 * kLogTab; e += kMvThreads) sh.stab[e] = logtab[e];
 
     double xi[kRB][D];
     long irow[kRB];
@@ -133,7 +142,7 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
             const bool jin = j < N;
             const long jc = jin ? j : N - 1;
             const double wj = jin ? P.w[jc] : 0.0;
-            if (sr < D) sxj[sr][sj] = jin ? P.pts[sr * N + jc] : 8.0 + sr;
+            if (sr < D) sh.sxj[sr][sj] = jin ? P.pts[sr * N + jc] : 8.0 + sr;
             constexpr int kQ = NB * 16 / kSR;
             double v[kQ];
 #pragma unroll
@@ -144,7 +153,7 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
                 const int r = sr + kSR * q;
-                swx[r * kLdw + sj] = (r0 + r < nrhs) ? wj * v[q] : 0.0;
+                sh.swx[r * kLdw + sj] = (r0 + r < nrhs) ? wj * v[q] : 0.0;
             }
         }
         __syncthreads();
@@ -153,7 +162,7 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
             const int jj = ks * 4 + lk;
             double xj[D];
 #pragma unroll
-            for (int t = 0; t < D; ++t) xj[t] = sxj[t][jj];
+            for (int t = 0; t < D; ++t) xj[t] = sh.sxj[t][jj];
             double a[kRB];
 #pragma unroll
             for (int rb = 0; rb < kRB; ++rb) {
@@ -165,15 +174,15 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
                 }
                 if constexpr (D == 2) {
                     // the pair i == j enters with the finite value at r^2 = 0; the epilogue removes it
-                    a[rb] = kernel_r2<D>(r2, stab);
+                    a[rb] = kernel_r2<D>(r2, sh.stab);
                 } else {
-                    const double kv = kernel_r2<D>(r2, stab);
+                    const double kv = kernel_r2<D>(r2, sh.stab);
                     a[rb] = (j0 + jj == irow[rb]) ? 0.0 : kv;
                 }
             }
             double b[NB];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) b[nb] = swx[(nb * 16 + li) * kLdw + jj];
+            for (int nb = 0; nb < NB; ++nb) b[nb] = sh.swx[(nb * 16 + li) * kLdw + jj];
 #pragma unroll
             for (int rb = 0; rb < kRB; ++rb)
 #pragma unroll
@@ -190,7 +199,7 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
             if (i >= N) continue;
             const double bi = P.rs[i], di = P.diag[i];
             // 2D: remove the self pair, which entered with the value at r^2 = 0
-            const double selfw = (D == 2) ? kernel_r2<D>(0.0, stab) * P.w[i] : 0.0;
+            const double selfw = (D == 2) ? kernel_r2<D>(0.0, sh.stab) * P.w[i] : 0.0;
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int r = r0 + nb * 16 + li;
@@ -204,7 +213,7 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
     }
 }
 
-// c log F_j and 1/F_j (F_j = (1 + j/1024)/2, c = -1/(4 pi)), uploaded once per device.
+// c log F_j and 1/F_j (F_j = (1 + (j + 1/2)/2048)/2, c = -1/(4 pi)), uploaded once per device.
 static const double* log_table() {
     static double* dtab[64] = {nullptr};
     int dev = 0;
@@ -214,7 +223,7 @@ static const double* log_table() {
         static double h[2 * kLogTab];
         const long double c = -0.25L / 3.141592653589793238462643383279502884L;
         for (int j = 0; j < kLogTab; ++j) {
-            const long double F = 0.5L + (long double)j / (2.0L * kLogTab);
+            const long double F = 0.5L + ((long double)j + 0.5L) / (2.0L * kLogTab);
             h[2 * j] = (double)(c * std::log(F));
             h[2 * j + 1] = (double)(1.0L / F);
         }

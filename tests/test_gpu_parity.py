@@ -601,3 +601,43 @@ def test_chunked_levels_give_the_same_factors(case):
     r = torch.tensor(synth.rhs(P.N, 2, seed=3), device=DEV)
     z0, z1 = F0.apply(r), F1.apply(r)
     assert (z1 - z0).norm() <= 1e-10 * z0.norm()
+
+
+# Fixed N, varying partition count M (the paper's strong-scaling tables t:cbd_strong_2d and
+# t:cbd_strong_3d: tolerance 1e-3, plain kernel without coefficients, proxy radius 1.5; the
+# 3D rows there use randomized IDs).  S, the last-level size of a subdomain (the largest of
+# the 4 or 8 here), grows as M^(1/2) in 2D and M^(2/3) in 3D (the paper's rank theorem), and
+# the PCG iteration counts stay about constant.  Printed values from those tables: (m, S, n_it).
+_STRONG = {
+    "2d": dict(d=2, n=256, npxy=64, seed=None, rows=[(8, 64, 26), (16, 114, 26), (32, 213, 24), (64, 407, 22)]),
+    "3d": dict(d=3, n=32, npxy=256, seed=1, rows=[(4, 527, 33), (8, 1358, 32), (16, 4120, 28)]),
+}
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_partition_count_sweep(case):
+    import time
+    c = _STRONG[case]
+    d, n = c["d"], c["n"]
+    P, O = gpu_problem(d, n)
+    f = torch.tensor(synth.rhs(O.N, 1, seed=0)[0], device=DEV)
+    S_prev = None
+    for m, S_paper, it_paper in c["rows"]:
+        part = cbd.Partition(P, m, 1, cbd.MODE_CBD, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = cbd.Factor(P, part, tol=1e-3, n_pxy=c["npxy"], proxy_ratio=1.5, sketch_seed=c["seed"])
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        S = max(F.stats()["S"])
+        u, it, rr = cbd.pcg_solve(P, F, f, tol=1e-10, maxit=200)
+        print("%s N=%d^%d M=%d^%d: S %d (paper %d), factor %.3f s, PCG iterations %d (paper %d), rel res %.2e"
+              % (case, n, d, m, d, S, S_paper, tf, it, it_paper, rr), flush=True)
+        assert rr <= 1e-10
+        assert it <= it_paper + 10
+        assert 0.5 * S_paper <= S <= 2.0 * S_paper
+        if S_prev is not None:
+            # 2^d times more partitions: S grows by about 2 (2D) or 4 (3D)
+            lo, hi = (1.4, 2.6) if d == 2 else (2.0, 5.0)
+            assert lo <= S / S_prev <= hi, (S_prev, S)
+        S_prev = S
