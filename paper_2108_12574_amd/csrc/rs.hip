@@ -149,6 +149,70 @@ __device__ __forceinline__ void reflect_columns(double* Yb, int m, int j, int c_
     }
 }
 
+// Register-resident form of reflect_columns for m - j <= 64 NR rows: a wave loads
+// all rows of G columns at once (clamped addresses, masked values), so the loads
+// of a column are in flight together and the column is read once; the per-lane
+// sums run over the same rows in the same order as reflect_columns, so the
+// results are the same.
+template <int NR>
+__device__ __forceinline__ void reflect_columns_reg(double* Yb, int m, int j, int c_lo, int c_hi,
+                                                    const double* v, double beta, double* norms) {
+    constexpr int G = NR > 12 ? 1 : 2;
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // column bases in SGPRs
+    const int rows = m - j;
+    for (int c0 = c_lo + wid; c0 < c_hi; c0 += G * kWaves) {
+        double* col[G];
+        bool ok[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int c = c0 + u * kWaves;
+            ok[u] = c < c_hi;
+            col[u] = Yb + (long)(ok[u] ? c : c0) * m + j;
+        }
+        double a[G][NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int rr = min(lane + 64 * i, rows - 1);
+#pragma unroll
+            for (int u = 0; u < G; ++u) a[u][i] = col[u][rr];
+        }
+        double sd[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) sd[u] = 0.0;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int rr = lane + 64 * i;
+            const double vv = rr < rows ? v[rr] : 0.0;
+#pragma unroll
+            for (int u = 0; u < G; ++u) sd[u] += vv * a[u][i];
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) sd[u] = wave_sum(sd[u]) * beta;
+        double q[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) q[u] = 0.0;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int rr = lane + 64 * i;
+            if (rr < rows) {
+                const double vv = v[rr];
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    const double y = a[u][i] - sd[u] * vv;
+                    if (ok[u]) col[u][rr] = y;
+                    if (rr > 0) q[u] += y * y;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            q[u] = wave_sum(q[u]);
+            if (lane == 0 && ok[u]) norms[c0 + u * kWaves] = sqrt(q[u]);
+        }
+    }
+}
+
 // One workgroup per box (levels with many boxes).
 __global__ __launch_bounds__(kThreads) void k_cpqr(const BoxMeta* __restrict__ meta,
                                                    double* __restrict__ Y, const int* __restrict__ act,
@@ -369,6 +433,7 @@ __global__ __launch_bounds__(kThreads) void k_qr_pivot(const BoxMeta* __restrict
     }
 }
 
+template <int NR>
 __global__ __launch_bounds__(kThreads) void k_qr_update(const BoxMeta* __restrict__ meta,
                                                         double* __restrict__ Y, QrState st, int j) {
     extern __shared__ char smem_raw[];
@@ -382,7 +447,10 @@ __global__ __launch_bounds__(kThreads) void k_qr_update(const BoxMeta* __restric
     double* v = reinterpret_cast<double*>(smem_raw);
     for (int r = j + threadIdx.x; r < M.m; r += kThreads) v[r - j] = Yb[r + (long)j * M.m];
     __syncthreads();
-    reflect_columns(Yb, M.m, j, c0, c1, v, st.beta[b], st.norms + M.act);
+    if constexpr (NR == 0)
+        reflect_columns(Yb, M.m, j, c0, c1, v, st.beta[b], st.norms + M.act);
+    else
+        reflect_columns_reg<NR>(Yb, M.m, j, c0, c1, v, st.beta[b], st.norms + M.act);
 }
 
 __global__ __launch_bounds__(kThreads) void k_qr_finish(const BoxMeta* __restrict__ meta,
@@ -425,8 +493,24 @@ void launch_qr_step(int nbox, int np_max, int m_max, const BoxMeta* meta, double
                     int j, double tol, double tie, hipStream_t s) {
     if (nbox == 0) return;
     hipLaunchKernelGGL(k_qr_pivot, dim3(nbox), dim3(kThreads), 0, s, meta, Y, st, j, tol, tie);
-    hipLaunchKernelGGL(k_qr_update, dim3(nbox, (np_max + kQrCols - 1) / kQrCols), dim3(kThreads),
-                       (size_t)m_max * sizeof(double), s, meta, Y, st, j);
+    // rows of the update: at most m_max - j; the register form holds up to 64 NR of them
+    const int cb = (m_max - j + 63) / 64;
+    const dim3 grid(nbox, (np_max + kQrCols - 1) / kQrCols);
+    const size_t shm = (size_t)m_max * sizeof(double);
+    if (cb <= 2)
+        hipLaunchKernelGGL(k_qr_update<2>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+    else if (cb <= 4)
+        hipLaunchKernelGGL(k_qr_update<4>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+    else if (cb <= 8)
+        hipLaunchKernelGGL(k_qr_update<8>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+    else if (cb <= 12)
+        hipLaunchKernelGGL(k_qr_update<12>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+    else if (cb <= 16)
+        hipLaunchKernelGGL(k_qr_update<16>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+    else if (cb <= 24)
+        hipLaunchKernelGGL(k_qr_update<24>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+    else
+        hipLaunchKernelGGL(k_qr_update<0>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
 }
 void launch_qr_finish(int nbox, int np_max, const BoxMeta* meta, double* Y, const QrState& st, const int* act,
                       int* sr, int* perm, int* k, double* T64, hipStream_t s) {
