@@ -297,7 +297,13 @@ __global__ __launch_bounds__(kThreads) void k_cpqr(const BoxMeta* __restrict__ m
         for (int r = j + tid; r < m; r += kThreads) v[r - j] = (r == j) ? x0 - alpha : Yb[r + (long)j * m];
         __syncthreads();
         const double beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-        reflect_columns(Yb, m, j, j + 1, np, v, beta, norms);
+        // (the row count is uniform over the workgroup)
+        if (m - j <= 256)
+            reflect_columns_reg<4>(Yb, m, j, j + 1, np, v, beta, norms);
+        else if (m - j <= 512)
+            reflect_columns_reg<8>(Yb, m, j, j + 1, np, v, beta, norms);
+        else
+            reflect_columns(Yb, m, j, j + 1, np, v, beta, norms);
         if (tid == 0) {
             Yb[j + (long)j * m] = alpha;
             s_k = j + 1;
