@@ -96,7 +96,7 @@ class Problem:
         check(lib().cbd_autotune_matvec(self.handle, nrhs, _stream(self.device), ctypes.byref(ch)))
         return ch.value
 
-    def __del__(self):
+    def __del__(self, _free=_free):   # bound now: module globals are gone at shutdown
         _free("cbd_problem_free", self)
 
 
@@ -138,7 +138,7 @@ class Partition:
                  for b in range(nb.value)]
         return boxes, list(par)
 
-    def __del__(self):
+    def __del__(self, _free=_free):   # bound now: module globals are gone at shutdown
         _free("cbd_partition_free", self)
 
 
@@ -243,7 +243,7 @@ class Factor:
                                    Gi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return idx, Gi.reshape(S.value, S.value).T
 
-    def __del__(self):
+    def __del__(self, _free=_free):   # bound now: module globals are gone at shutdown
         _free("rs_factor_free", self)
 
 
