@@ -982,44 +982,93 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
     return z ^ (z >> 31);
 }
 
+// Z = Omega Y on FP64 MFMA, a 64 x 128 tile of Z per workgroup (wave w: rows
+// 16 w .. 16 w + 15 of the tile, eight 16 x 16 accumulators).  Rows of Y stream
+// through LDS in chunks of kSkK: the chunk's rows of Y (coalesced column
+// segments) and the tile's signs for them (each drawn once per workgroup; the
+// row keys looked up once per chunk).  Every entry of Z sums over the rows in
+// steps of four in ascending order.
+constexpr int kSkI = 64, kSkC = 128, kSkK = 32;
+constexpr int kSkLdA = kSkI + 16;    // LDS row strides (doubles) that spread the operand reads over the banks
+constexpr int kSkLdB = kSkC + 1;
+
 __global__ __launch_bounds__(kThreads) void k_sketch(const BoxMeta* __restrict__ meta,
                                                      const BoxMeta* __restrict__ zmeta,
                                                      const double* __restrict__ Y, const int* __restrict__ nearl,
                                                      const int* __restrict__ cidx, long N, unsigned long long seed,
                                                      const unsigned long long* __restrict__ keys,
-                                                     double* __restrict__ Z) {
+                                                     double* __restrict__ Z, int ti) {
     typedef double v4 __attribute__((ext_vector_type(4)));
+    __shared__ double sA[kSkK * kSkLdA];
+    __shared__ double sB[kSkK * kSkLdB];
+    __shared__ unsigned long long srk[kSkK];
     const int b = blockIdx.x;
     const BoxMeta M = meta[b];
     const int ell = zmeta[b].m, np = M.np, m = M.m;
-    if (ell == 0) return;
-    const int tm = (ell + 15) >> 4, tn = (np + 15) >> 4;
-    const int t = (int)blockIdx.y * kWaves + (threadIdx.x >> 6);
-    if (t >= tm * tn) return;
-    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-    const int i0 = (t % tm) << 4, c0 = (t / tm) << 4;
-    const int i = i0 + li, c = c0 + li;
-    const unsigned long long base = seed + keys[b] * 0x9E3779B97F4A7C15ull + (unsigned long long)i * 0xD1B54A32D192ED03ull;
+    const int i0 = (int)(blockIdx.y % ti) * kSkI, c0 = (int)(blockIdx.y / ti) * kSkC;
+    if (ell == 0 || i0 >= ell || c0 >= np) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
     const double* Yb = Y + M.y;
-    v4 acc = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < m; k0 += 4) {
-        const int row = k0 + lk;
-        double a = 0.0, bv = 0.0;
-        if (row < m) {
-            if (i < ell) {
-                const long rk = row < M.nnear ? (long)cidx[nearl[M.near + row]] : N + (row - M.nnear);
-                const unsigned long long h = mix64(base + (unsigned long long)rk * 0x8CB92BA72F3D8DD7ull);
+    const unsigned long long kb = seed + keys[b] * 0x9E3779B97F4A7C15ull;
+    v4 acc[kSkC / 16];
+#pragma unroll
+    for (int t = 0; t < kSkC / 16; ++t) acc[t] = v4{0, 0, 0, 0};
+    // staging roles: Y column c0 + sc, rows sh*16 .. sh*16+15 of the chunk; signs of row
+    // i0 + lane for chunk rows w + 4q
+    const int sc = tid >> 1, sh = tid & 1;
+    const int cy = min(c0 + sc, np - 1);
+    const bool cin = c0 + sc < np;
+    const int ia = i0 + lane;
+    const unsigned long long ki = kb + (unsigned long long)ia * 0xD1B54A32D192ED03ull;
+    for (int k0 = 0; k0 < m; k0 += kSkK) {
+        __syncthreads();
+        if (tid < kSkK) {
+            const int row = k0 + tid;
+            unsigned long long rk = 0;
+            if (row < m) rk = row < M.nnear ? (unsigned long long)cidx[nearl[M.near + row]] : (unsigned long long)(N + (row - M.nnear));
+            srk[tid] = rk;
+        }
+        {
+            double yv[16];
+            const double* col = Yb + (long)cy * m;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) yv[q] = col[min(k0 + sh * 16 + q, m - 1)];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int kk = sh * 16 + q;
+                sB[kk * kSkLdB + sc] = (cin && k0 + kk < m) ? yv[q] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kSkK / kWaves; ++q) {
+            const int kk = w + kWaves * q;
+            double a = 0.0;
+            if (k0 + kk < m && ia < ell) {
+                const unsigned long long h = mix64(ki + srk[kk] * 0x8CB92BA72F3D8DD7ull);
                 a = (h >> 63) ? -1.0 : 1.0;
             }
-            if (c < np) bv = Yb[row + (long)c * m];
+            sA[kk * kSkLdA + lane] = a;
         }
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+        __syncthreads();
+#pragma unroll 2
+        for (int ks = 0; ks < kSkK / 4; ++ks) {
+            const int kk = ks * 4 + lk;
+            const double a = sA[kk * kSkLdA + w * 16 + li];
+#pragma unroll
+            for (int t = 0; t < kSkC / 16; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sB[kk * kSkLdB + t * 16 + li], acc[t], 0, 0, 0);
+        }
     }
     double* Zb = Z + zmeta[b].y;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int ii = i0 + 4 * v + lk;
-        if (ii < ell && c < np) Zb[ii + (long)c * ell] = acc[v];
+    for (int t = 0; t < kSkC / 16; ++t) {
+        const int c = c0 + t * 16 + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ii = i0 + w * 16 + 4 * v + lk;
+            if (ii < ell && c < np) Zb[ii + (long)c * ell] = acc[t][v];
+        }
     }
 }
 
@@ -1027,9 +1076,10 @@ void launch_sketch(int nbox, int np_max, const BoxMeta* meta, const BoxMeta* zme
                    const int* nearl, const int* cidx, long N, unsigned long long seed,
                    const unsigned long long* keys, double* Z, hipStream_t s) {
     if (nbox == 0) return;
-    const int t1 = (np_max + 15) / 16;   // ell < np for every sketched box
-    hipLaunchKernelGGL(k_sketch, dim3(nbox, (t1 * t1 + kWaves - 1) / kWaves), dim3(kThreads), 0, s, meta, zmeta,
-                       Y, nearl, cidx, N, seed, keys, Z);
+    // ell < np for every sketched box, so np_max bounds both dimensions of Z
+    const int ti = (np_max + kSkI - 1) / kSkI, tc = (np_max + kSkC - 1) / kSkC;
+    hipLaunchKernelGGL(k_sketch, dim3(nbox, ti * tc), dim3(kThreads), 0, s, meta, zmeta, Y, nearl, cidx, N, seed,
+                       keys, Z, ti);
 }
 
 // ---- box matrix A_pp --------------------------------------------------------
