@@ -213,7 +213,9 @@ __device__ __forceinline__ void reflect_columns_reg(double* Yb, int m, int j, in
     }
 }
 
-// One workgroup per box (levels with many boxes).
+// One workgroup per box (levels with many boxes).  The column update keeps up to
+// 64 NRMAX rows in registers (the instantiation is chosen by the largest box).
+template <int NRMAX>
 __global__ __launch_bounds__(kThreads) void k_cpqr(const BoxMeta* __restrict__ meta,
                                                    double* __restrict__ Y, const int* __restrict__ act,
                                                    int* __restrict__ sr, int* __restrict__ perm,
@@ -302,6 +304,10 @@ __global__ __launch_bounds__(kThreads) void k_cpqr(const BoxMeta* __restrict__ m
             reflect_columns_reg<4>(Yb, m, j, j + 1, np, v, beta, norms);
         else if (m - j <= 512)
             reflect_columns_reg<8>(Yb, m, j, j + 1, np, v, beta, norms);
+        else if (NRMAX >= 12 && m - j <= 768)
+            reflect_columns_reg<(NRMAX >= 12 ? 12 : 8)>(Yb, m, j, j + 1, np, v, beta, norms);
+        else if (NRMAX >= 16 && m - j <= 1024)
+            reflect_columns_reg<(NRMAX >= 16 ? 16 : 8)>(Yb, m, j, j + 1, np, v, beta, norms);
         else
             reflect_columns(Yb, m, j, j + 1, np, v, beta, norms);
         if (tid == 0) {
@@ -324,8 +330,12 @@ void launch_cpqr(int nbox, const BoxMeta* meta, double* Y, const int* act, int* 
                  double* T64, double tol, double tie, int m_max, int np_max, hipStream_t s) {
     if (nbox == 0) return;
     size_t shm = (size_t)(np_max + m_max) * sizeof(double) + (size_t)np_max * sizeof(int);
-    hipLaunchKernelGGL(k_cpqr, dim3(nbox), dim3(kThreads), shm, s, meta, Y, act, sr, perm, k, T64, tol,
-                       tie);
+    if (m_max <= 512)
+        hipLaunchKernelGGL(k_cpqr<8>, dim3(nbox), dim3(kThreads), shm, s, meta, Y, act, sr, perm, k, T64, tol,
+                           tie);
+    else
+        hipLaunchKernelGGL(k_cpqr<16>, dim3(nbox), dim3(kThreads), shm, s, meta, Y, act, sr, perm, k, T64, tol,
+                           tie);
 }
 
 // Stepped form for levels with few, large boxes: one launch pair per pivot step
