@@ -1156,7 +1156,8 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 std::vector<int> zb, zpred;
                 std::vector<unsigned long long> keys(nbc);
                 std::vector<BoxMeta> zall(L.meta.begin() + b0, L.meta.begin() + b1);
-                long o_z = 0;
+                std::vector<long> boff(nbc, 0);   // offsets of the boxes' sign words
+                long o_z = 0, o_bits = 0, mw_max = 0;
                 for (int B = b0; B < b1; ++B) {
                     const BoxMeta& M = L.meta[B];
                     const int ell = sketch_rows(M.m, M.np);
@@ -1165,6 +1166,10 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                     zall[B - b0].m = ell;
                     zall[B - b0].y = o_z;
                     o_z += (long)ell * M.np;
+                    boff[B - b0] = o_bits;
+                    const long mw = (long)M.m * ((ell + 31) / 32);
+                    o_bits += mw;
+                    mw_max = std::max(mw_max, mw);
                     if (ell) {
                         sk_ell[B] = ell;
                         zm.push_back(zall[B - b0]);
@@ -1176,16 +1181,20 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 }
                 if (!zb.empty()) {
                     if ((rc = zbuf.ensure(sizeof(BoxMeta) * nbc + sizeof(unsigned long long) * nbc +
-                                          sizeof(double) * std::max(o_z, 1L))))
+                                          sizeof(long) * nbc + sizeof(double) * std::max(o_z, 1L) +
+                                          sizeof(unsigned) * std::max(o_bits, 1L))))
                         return rc;
                     BoxMeta* d_zall = (BoxMeta*)zbuf.p;
                     unsigned long long* d_keys = (unsigned long long*)(d_zall + nbc);
-                    double* Z = (double*)(d_keys + nbc);
+                    long* d_boff = (long*)(d_keys + nbc);
+                    double* Z = (double*)(d_boff + nbc);
+                    unsigned* d_bits = (unsigned*)(Z + std::max(o_z, 1L));
                     HIPCHK(hipMemcpyAsync(d_zall, zall.data(), sizeof(BoxMeta) * nbc, hipMemcpyHostToDevice, s));
                     HIPCHK(hipMemcpyAsync(d_keys, keys.data(), sizeof(unsigned long long) * nbc,
                                           hipMemcpyHostToDevice, s));
-                    launch_sketch(nbc, np_max_c, d_meta_c, d_zall, Y, (const int*)nearbuf.p, Q->d_cidx, P->N,
-                                  o->sketch_seed, d_keys, Z, s);
+                    HIPCHK(hipMemcpyAsync(d_boff, boff.data(), sizeof(long) * nbc, hipMemcpyHostToDevice, s));
+                    launch_sketch(nbc, np_max_c, mw_max, d_meta_c, d_zall, Y, (const int*)nearbuf.p, Q->d_cidx,
+                                  P->N, o->sketch_seed, d_keys, d_boff, d_bits, Z, s);
                     std::vector<int> kz;
                     if ((rc = id_batch(zm, Z, zpred, kz))) return rc;
                     for (size_t e = 0; e < zb.size(); ++e) {

@@ -148,9 +148,9 @@ void launch_qr_finish(int nbox, int np_max, const BoxMeta* meta, double* Y, cons
                       int* sr, int* perm, int* k, double* T64, hipStream_t s);
 // Randomized ID: Z = Omega Y for every box with zmeta[b].m = ell > 0 (Z at zmeta[b].y,
 // ell x np column-major); keys: one box key per box.
-void launch_sketch(int nbox, int np_max, const BoxMeta* meta, const BoxMeta* zmeta, const double* Y,
+void launch_sketch(int nbox, int np_max, long mw_max, const BoxMeta* meta, const BoxMeta* zmeta, const double* Y,
                    const int* nearl, const int* cidx, long N, unsigned long long seed,
-                   const unsigned long long* keys, double* Z, hipStream_t s);
+                   const unsigned long long* keys, const long* boff, unsigned* bits, double* Z, hipStream_t s);
 // Row compression before the stepped pivoted QR: Householder QR of every box's Y
 // (meta), then R (min(m, np) x np) into Rc at the offsets of cmeta.  Tw: nbox x
 // kHqrTw doubles; alpha: one double per active DOF (meta's act offsets); Vbuf:

@@ -992,11 +992,44 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
     return z ^ (z >> 31);
 }
 
+// The signs of Omega, one bit each: word w of row `row` of box b holds the signs of
+// sketch rows 32 w .. 32 w + 31 for that row of Y (bit u: 1 for -1), at
+// bits + boff[b] + row * nw + w, nw = ceil(ell / 32).  One thread per word.
+__global__ __launch_bounds__(kThreads) void k_sketch_signs(const BoxMeta* __restrict__ meta,
+                                                           const BoxMeta* __restrict__ zmeta,
+                                                           const int* __restrict__ nearl,
+                                                           const int* __restrict__ cidx, long N,
+                                                           unsigned long long seed,
+                                                           const unsigned long long* __restrict__ keys,
+                                                           const long* __restrict__ boff,
+                                                           unsigned* __restrict__ bits) {
+    const int b = blockIdx.x;
+    const int ell = zmeta[b].m;
+    if (ell == 0) return;
+    const BoxMeta M = meta[b];
+    const int nw = (ell + 31) >> 5;
+    const long e = (long)blockIdx.y * kThreads + threadIdx.x;
+    if (e >= (long)M.m * nw) return;
+    const int row = (int)(e / nw), wd = (int)(e % nw);
+    const unsigned long long rk =
+        row < M.nnear ? (unsigned long long)cidx[nearl[M.near + row]] : (unsigned long long)(N + (row - M.nnear));
+    const unsigned long long base = seed + keys[b] * 0x9E3779B97F4A7C15ull + rk * 0x8CB92BA72F3D8DD7ull;
+    unsigned hw = 0;
+    for (int u = 0; u < 32; ++u) {
+        const int i = wd * 32 + u;
+        if (i < ell) {
+            const unsigned long long h = mix64(base + (unsigned long long)i * 0xD1B54A32D192ED03ull);
+            hw |= (unsigned)(h >> 63) << u;
+        }
+    }
+    bits[boff[b] + e] = hw;
+}
+
 // Z = Omega Y on FP64 MFMA, a 64 x 128 tile of Z per workgroup (wave w: rows
 // 16 w .. 16 w + 15 of the tile, eight 16 x 16 accumulators).  Rows of Y stream
-// through LDS in chunks of kSkK: the chunk's rows of Y (coalesced column
-// segments) and the tile's signs for them (each drawn once per workgroup; the
-// row keys looked up once per chunk).  Every entry of Z sums over the rows in
+// through LDS in chunks of kSkK (coalesced column segments), with the tile's
+// signs for them expanded from the bit words; the next chunk's loads are issued
+// before the current chunk is multiplied.  Every entry of Z sums over the rows in
 // steps of four in ascending order.
 constexpr int kSkI = 64, kSkC = 128, kSkK = 32;
 constexpr int kSkLdA = kSkI + 16;    // LDS row strides (doubles) that spread the operand reads over the banks
@@ -1004,61 +1037,58 @@ constexpr int kSkLdB = kSkC + 1;
 
 __global__ __launch_bounds__(kThreads) void k_sketch(const BoxMeta* __restrict__ meta,
                                                      const BoxMeta* __restrict__ zmeta,
-                                                     const double* __restrict__ Y, const int* __restrict__ nearl,
-                                                     const int* __restrict__ cidx, long N, unsigned long long seed,
-                                                     const unsigned long long* __restrict__ keys,
+                                                     const double* __restrict__ Y,
+                                                     const long* __restrict__ boff,
+                                                     const unsigned* __restrict__ bits,
                                                      double* __restrict__ Z, int ti) {
     typedef double v4 __attribute__((ext_vector_type(4)));
     __shared__ double sA[kSkK * kSkLdA];
     __shared__ double sB[kSkK * kSkLdB];
-    __shared__ unsigned long long srk[kSkK];
     const int b = blockIdx.x;
     const BoxMeta M = meta[b];
     const int ell = zmeta[b].m, np = M.np, m = M.m;
     const int i0 = (int)(blockIdx.y % ti) * kSkI, c0 = (int)(blockIdx.y / ti) * kSkC;
     if (ell == 0 || i0 >= ell || c0 >= np) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
-    const double* Yb = Y + M.y;
-    const unsigned long long kb = seed + keys[b] * 0x9E3779B97F4A7C15ull;
     v4 acc[kSkC / 16];
 #pragma unroll
     for (int t = 0; t < kSkC / 16; ++t) acc[t] = v4{0, 0, 0, 0};
-    // staging roles: Y column c0 + sc, rows sh*16 .. sh*16+15 of the chunk; signs of row
-    // i0 + lane for chunk rows w + 4q
-    const int sc = tid >> 1, sh = tid & 1;
-    const int cy = min(c0 + sc, np - 1);
-    const bool cin = c0 + sc < np;
-    const int ia = i0 + lane;
-    const unsigned long long ki = kb + (unsigned long long)ia * 0xD1B54A32D192ED03ull;
+    // staging roles: chunk row sr of Y columns c0 + 32 w + 2 q + (lane >> 5) (each load
+    // instruction reads two 32-row column segments); signs of sketch row i0 + lane for
+    // chunk rows w + 4q
+    const int sr = lane & 31, sc0 = w * 32 + (lane >> 5);
+    const double* Ybox = Y + M.y;
+    const int ia = i0 + lane, nw = (ell + 31) >> 5;
+    const bool iin = ia < ell;
+    const unsigned* brow = bits + boff[b] + min(ia >> 5, nw - 1);
+    const int ib = ia & 31;
+    constexpr int kQ = kSkK / kWaves;
+    double yv[16];
+    unsigned sw[kQ];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        yv[q] = Ybox[(long)min(c0 + sc0 + 2 * q, np - 1) * m + min(sr, m - 1)];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) sw[q] = brow[(long)min(w + kWaves * q, m - 1) * nw];
     for (int k0 = 0; k0 < m; k0 += kSkK) {
         __syncthreads();
-        if (tid < kSkK) {
-            const int row = k0 + tid;
-            unsigned long long rk = 0;
-            if (row < m) rk = row < M.nnear ? (unsigned long long)cidx[nearl[M.near + row]] : (unsigned long long)(N + (row - M.nnear));
-            srk[tid] = rk;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int cc = sc0 + 2 * q;
+            sB[sr * kSkLdB + cc] = (c0 + cc < np && k0 + sr < m) ? yv[q] : 0.0;
         }
-        {
-            double yv[16];
-            const double* col = Yb + (long)cy * m;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) yv[q] = col[min(k0 + sh * 16 + q, m - 1)];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int kk = sh * 16 + q;
-                sB[kk * kSkLdB + sc] = (cin && k0 + kk < m) ? yv[q] : 0.0;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kSkK / kWaves; ++q) {
+        for (int q = 0; q < kQ; ++q) {
             const int kk = w + kWaves * q;
-            double a = 0.0;
-            if (k0 + kk < m && ia < ell) {
-                const unsigned long long h = mix64(ki + srk[kk] * 0x8CB92BA72F3D8DD7ull);
-                a = (h >> 63) ? -1.0 : 1.0;
-            }
-            sA[kk * kSkLdA + lane] = a;
+            sA[kk * kSkLdA + lane] = (iin && k0 + kk < m) ? (((sw[q] >> ib) & 1u) ? -1.0 : 1.0) : 0.0;
+        }
+        if (k0 + kSkK < m) {
+            const int k1 = k0 + kSkK;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                yv[q] = Ybox[(long)min(c0 + sc0 + 2 * q, np - 1) * m + min(k1 + sr, m - 1)];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) sw[q] = brow[(long)min(k1 + w + kWaves * q, m - 1) * nw];
         }
         __syncthreads();
 #pragma unroll 2
@@ -1082,14 +1112,15 @@ __global__ __launch_bounds__(kThreads) void k_sketch(const BoxMeta* __restrict__
     }
 }
 
-void launch_sketch(int nbox, int np_max, const BoxMeta* meta, const BoxMeta* zmeta, const double* Y,
+void launch_sketch(int nbox, int np_max, long mw_max, const BoxMeta* meta, const BoxMeta* zmeta, const double* Y,
                    const int* nearl, const int* cidx, long N, unsigned long long seed,
-                   const unsigned long long* keys, double* Z, hipStream_t s) {
+                   const unsigned long long* keys, const long* boff, unsigned* bits, double* Z, hipStream_t s) {
     if (nbox == 0) return;
+    hipLaunchKernelGGL(k_sketch_signs, dim3(nbox, (unsigned)((mw_max + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                       s, meta, zmeta, nearl, cidx, N, seed, keys, boff, bits);
     // ell < np for every sketched box, so np_max bounds both dimensions of Z
     const int ti = (np_max + kSkI - 1) / kSkI, tc = (np_max + kSkC - 1) / kSkC;
-    hipLaunchKernelGGL(k_sketch, dim3(nbox, ti * tc), dim3(kThreads), 0, s, meta, zmeta, Y, nearl, cidx, N, seed,
-                       keys, Z, ti);
+    hipLaunchKernelGGL(k_sketch, dim3(nbox, ti * tc), dim3(kThreads), 0, s, meta, zmeta, Y, boff, bits, Z, ti);
 }
 
 // ---- box matrix A_pp --------------------------------------------------------
