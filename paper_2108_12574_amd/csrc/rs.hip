@@ -1193,6 +1193,93 @@ struct Mma<float> {
     static __device__ __forceinline__ int row(int v, int lane) { return 4 * (lane >> 4) + v; }
 };
 
+// One 64 x 64 tile (rows i0.., columns j0..) of C = beta C_in + alpha op(A) op(B),
+// computed by the whole workgroup: k runs in chunks of kBgK through LDS (op(A) and
+// op(B) stored k-major, each loaded along its contiguous direction), wave w takes
+// the 32 x 32 quadrant (w & 1, w >> 1) as 2 x 2 MFMA tiles.  Every entry sums over
+// k in steps of four in ascending order, as tile_gemm does.  With upper set, the
+// 16 x 16 tiles entirely below the diagonal are not written.  Ends with a barrier.
+constexpr int kBgK = 32;
+template <typename R>
+struct BgShared {
+    R a[kBgK][64 + 16];   // row stride 80: the operand reads of a wave fall in distinct banks
+    R b[kBgK][64 + 16];
+};
+
+template <typename R, bool ta, bool tb>
+__device__ void block_gemm64(BgShared<R>& sh, int i0, int j0, int M, int N, int K, R alpha, const R* A, int lda,
+                             const R* B, int ldb, R beta, const R* Cin, R* C, int ldc, bool upper) {
+    typedef typename Mma<R>::v4 v4;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
+    v4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = v4{0, 0, 0, 0};
+    // staging: along the contiguous direction of each operand
+    //   rows-contiguous (A untransposed, B transposed): index x = tid % 64, k = tid / 64 + 4 q
+    //   k-contiguous (A transposed, B untransposed):   k = tid % 32, index x = tid / 32 + 8 q
+    for (int k0 = 0; k0 < K; k0 += kBgK) {
+        R ra[8], rb[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int x, kk;
+            if (!ta) { x = tid & 63; kk = (tid >> 6) + 4 * q; } else { kk = tid & 31; x = (tid >> 5) + 8 * q; }
+            const int gi = min(i0 + x, M - 1), gk = min(k0 + kk, K - 1);
+            ra[q] = ta ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int x, kk;
+            if (tb) { x = tid & 63; kk = (tid >> 6) + 4 * q; } else { kk = tid & 31; x = (tid >> 5) + 8 * q; }
+            const int gj = min(j0 + x, N - 1), gk = min(k0 + kk, K - 1);
+            rb[q] = tb ? B[gj + (long)gk * ldb] : B[gk + (long)gj * ldb];
+        }
+        __syncthreads();   // the previous chunk's operands are no longer read
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int x, kk;
+            if (!ta) { x = tid & 63; kk = (tid >> 6) + 4 * q; } else { kk = tid & 31; x = (tid >> 5) + 8 * q; }
+            sh.a[kk][x] = (i0 + x < M && k0 + kk < K) ? ra[q] : (R)0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int x, kk;
+            if (tb) { x = tid & 63; kk = (tid >> 6) + 4 * q; } else { kk = tid & 31; x = (tid >> 5) + 8 * q; }
+            sh.b[kk][x] = (j0 + x < N && k0 + kk < K) ? rb[q] : (R)0;
+        }
+        __syncthreads();
+        const int ks_end = min(kBgK, K - k0);
+        for (int ks = 0; ks < ks_end; ks += 4) {
+            const int kk = ks + lk;
+            const R a0 = sh.a[kk][wi + li], a1 = sh.a[kk][wi + 16 + li];
+            const R b0 = sh.b[kk][wj + li], b1 = sh.b[kk][wj + 16 + li];
+            acc[0][0] = Mma<R>::op(a0, b0, acc[0][0]);
+            acc[0][1] = Mma<R>::op(a0, b1, acc[0][1]);
+            acc[1][0] = Mma<R>::op(a1, b0, acc[1][0]);
+            acc[1][1] = Mma<R>::op(a1, b1, acc[1][1]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int ti0 = i0 + wi + 16 * a, tj0 = j0 + wj + 16 * c;
+            if (upper && ti0 > tj0 + 15) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ii = ti0 + Mma<R>::row(v, lane), jj = tj0 + li;
+                if (ii < M && jj < N) {
+                    const long o = ii + (long)jj * ldc;
+                    C[o] = (beta == (R)0 ? (R)0 : beta * Cin[o]) + alpha * acc[a][c][v];
+                }
+            }
+        }
+    __syncthreads();
+}
+
 // C (M x N, column-major, ldc) = beta C + alpha op(A) op(B), op(A) M x K, op(B) K x N;
 // ta/tb select the transposes (A[k + i*lda] / B[j + k*ldb]).  All threads of the
 // workgroup call it; 16 x 16 output tiles are spread over the waves.  With
@@ -1209,11 +1296,31 @@ __device__ __forceinline__ void tile_gemm(int i0, int j0, int M, int N, int K, R
     const int li = lane & 15, lk = lane >> 4;
     v4 acc = {0, 0, 0, 0};
     const int i = i0 + li, j = j0 + li;
-    for (int k0 = 0; k0 < K; k0 += 4) {
+    // the lane's row of op(A) and column of op(B) (clamped to a valid one and masked),
+    // walked in steps of 4 along k; blocks of kU steps load before they multiply
+    constexpr int kU = 8;
+    const bool iok = i < M, jok = j < N;
+    const long sa = ta ? 1 : lda, sb = tb ? ldb : 1;
+    const R* pa = (ta ? A + (long)(iok ? i : 0) * lda : A + (iok ? i : 0)) + lk * sa;
+    const R* pb = (tb ? B + (jok ? j : 0) : B + (long)(jok ? j : 0) * ldb) + lk * sb;
+    int k0 = 0;
+    for (; k0 + 4 * kU <= K; k0 += 4 * kU) {
+        R a[kU], b[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            a[u] = pa[(long)(4 * u) * sa];
+            b[u] = pb[(long)(4 * u) * sb];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc = Mma<R>::op(iok ? a[u] : (R)0, jok ? b[u] : (R)0, acc);
+        pa += (long)(4 * kU) * sa;
+        pb += (long)(4 * kU) * sb;
+    }
+    for (; k0 < K; k0 += 4) {
         const int kk = k0 + lk;
         R a = 0, b = 0;
-        if (i < M && kk < K) a = ta ? A[kk + (long)i * lda] : A[i + (long)kk * lda];
-        if (j < N && kk < K) b = tb ? B[j + (long)kk * ldb] : B[kk + (long)j * ldb];
+        if (iok && kk < K) a = ta ? A[kk + (long)i * lda] : A[i + (long)kk * lda];
+        if (jok && kk < K) b = tb ? B[j + (long)kk * ldb] : B[kk + (long)j * ldb];
         acc = Mma<R>::op(a, b, acc);
     }
 #pragma unroll
@@ -1559,23 +1666,38 @@ __global__ __launch_bounds__(kThreads) void k_big_gemm(const BoxMeta* __restrict
         default: Mm = k; Nn = k; Kk = nr; alpha = -1; A = V.E; lda = k; B = V.E; ldb = k; tb = true;
                  beta = 1; C = V.Bss; Cin = V.Ass; ldc = k; break;
     }
-    const int tm = (Mm + 15) >> 4, tn = (Nn + 15) >> 4;
-    const int t = (int)blockIdx.y * kWaves + (threadIdx.x >> 6);
-    if (t >= tm * tn) return;
-    const int i0 = (t % tm) << 4, j0 = (t / tm) << 4;
-    if (upper && i0 > j0 + 15) return;
-    if constexpr (BF16)
-        tile_gemm_bf16(i0, j0, Mm, Nn, Kk, alpha, A, lda, ta, B, ldb, tb, beta, Cin, C, ldc);
-    else
-        tile_gemm<R>(i0, j0, Mm, Nn, Kk, alpha, A, lda, ta, B, ldb, tb, beta, Cin, C, ldc);
+    if constexpr (BF16) {
+        const int tm = (Mm + 15) >> 4, tn = (Nn + 15) >> 4;
+        for (int t = (int)blockIdx.y * 16 + (threadIdx.x >> 6); t < min(tm * tn, ((int)blockIdx.y + 1) * 16);
+             t += kWaves) {
+            const int i0 = (t % tm) << 4, j0 = (t / tm) << 4;
+            if (upper && i0 > j0 + 15) continue;
+            tile_gemm_bf16(i0, j0, Mm, Nn, Kk, alpha, A, lda, ta, B, ldb, tb, beta, Cin, C, ldc);
+        }
+    } else {
+        // one 64 x 64 tile of C per workgroup
+        const int tm = (Mm + 63) >> 6, tn = (Nn + 63) >> 6;
+        const int t = (int)blockIdx.y;
+        if (t >= tm * tn) return;
+        const int i0 = (t % tm) << 6, j0 = (t / tm) << 6;
+        if (upper && i0 > j0 + 63) return;
+        __shared__ BgShared<R> sh;
+        if (ta)
+            block_gemm64<R, true, false>(sh, i0, j0, Mm, Nn, Kk, alpha, A, lda, B, ldb, beta, Cin, C, ldc, upper);
+        else if (tb)
+            block_gemm64<R, false, true>(sh, i0, j0, Mm, Nn, Kk, alpha, A, lda, B, ldb, beta, Cin, C, ldc, upper);
+        else
+            block_gemm64<R, false, false>(sh, i0, j0, Mm, Nn, Kk, alpha, A, lda, B, ldb, beta, Cin, C, ldc, upper);
+    }
 }
 
 template <typename R>
 void launch_big_schur(int nbig, int np_max, const BoxMeta* meta, const int* list, int phase, const int* perm,
                       const int* k, const R* App, const double* T64, R* Wk, R* F, bool bf16, hipStream_t s) {
     if (nbig == 0) return;
-    const int t1 = (np_max + 15) / 16;
-    const dim3 grid(nbig, (t1 * t1 + kWaves - 1) / kWaves);
+    // 64 x 64 tiles of C (the bfloat16 form: sixteen 16 x 16 tiles per workgroup)
+    const int t1 = (np_max + 63) / 64;
+    const dim3 grid(nbig, t1 * t1);
     auto gemm = [&](int op) {
         if constexpr (sizeof(R) == 4) {
             if (bf16) {
@@ -1708,8 +1830,10 @@ __global__ __launch_bounds__(kThreads) void k_bchol_update(const BoxMeta* __rest
     const int ti = (int)(t - (long)tj * (tj + 1) / 2);
     const int r0 = base + ti * 64, q0 = base + tj * 64;
     const R* P = V.Brr + J;   // panel rows J.., column c at P + c*nr
-    wg_gemm<R>(min(64, nr - r0), min(64, nr - q0), jb, (R)-1, P + (long)r0 * nr, nr, true, P + (long)q0 * nr, nr,
-               false, (R)1, V.Brr + r0 + (long)q0 * nr, nr, ti == tj);
+    __shared__ BgShared<R> sh;
+    R* Ct = V.Brr + r0 + (long)q0 * nr;
+    block_gemm64<R, true, false>(sh, 0, 0, min(64, nr - r0), min(64, nr - q0), jb, (R)-1, P + (long)r0 * nr, nr,
+                                 P + (long)q0 * nr, nr, (R)1, Ct, Ct, nr, ti == tj);
 }
 
 // Inverse, block column J > 0: V = G_{0:J,J} Z_J (into W), then
@@ -1726,12 +1850,14 @@ __global__ __launch_bounds__(kThreads) void k_binv(const BoxMeta* __restrict__ m
     const int r0 = blockIdx.y * 64;
     if (r0 >= J) return;
     const int rows = min(64, J - r0);
+    __shared__ BgShared<R> sh;
     if (stage == 0) {
-        wg_gemm<R>(rows, jb, jb, (R)1, V.Brr + r0 + (long)J * nr, nr, false, V.Gi + J + (long)J * nr, nr, false,
-                   (R)0, V.W + r0, nr);
+        block_gemm64<R, false, false>(sh, 0, 0, rows, jb, jb, (R)1, V.Brr + r0 + (long)J * nr, nr,
+                                      V.Gi + J + (long)J * nr, nr, (R)0, V.W + r0, V.W + r0, nr, false);
     } else {
-        wg_gemm<R>(rows, jb, J - r0, (R)-1, V.Gi + r0 + (long)r0 * nr, nr, false, V.W + r0, nr, false, (R)0,
-                   V.Gi + r0 + (long)J * nr, nr);
+        R* Ct = V.Gi + r0 + (long)J * nr;
+        block_gemm64<R, false, false>(sh, 0, 0, rows, jb, J - r0, (R)-1, V.Gi + r0 + (long)r0 * nr, nr, V.W + r0,
+                                      nr, (R)0, Ct, Ct, nr, false);
     }
 }
 
