@@ -44,28 +44,62 @@ __global__ __launch_bounds__(kThreads) void k_proxy_matrix(ProblemView P,
                                                            const int* __restrict__ cidx,
                                                            const double* __restrict__ pxdir,
                                                            int npxy, R* __restrict__ Y) {
+    // rows (near-field points, then proxy points) staged in LDS in chunks of kPxRows:
+    // coordinates, row scale (1 for proxy rows) and grid index (-1 for proxy rows);
+    // the workgroup's columns then run over the chunk with one row per thread
+    constexpr int kPxRows = 512;
+    __shared__ double sx[D][kPxRows];
+    __shared__ double srs[kPxRows];
+    __shared__ long sgi[kPxRows];
     const BoxMeta M = meta[blockIdx.x];
-    const long total = (long)M.m * M.np;
+    const int per = (M.np + gridDim.y - 1) / gridDim.y;
+    const int c_lo = blockIdx.y * per, c_hi = min(M.np, c_lo + per);
+    if (c_lo >= c_hi) return;
+    const int tid = threadIdx.x;
     R* Yb = Y + M.y;
-    for (long e = (long)blockIdx.y * kThreads + threadIdx.x; e < total; e += (long)gridDim.y * kThreads) {
-        const int row = (int)(e % M.m);
-        const int col = (int)(e / M.m);
-        const long gj = cidx[act[M.act + col]];
-        double val;
-        if (row < M.nnear) {
-            const long gi = cidx[nearl[M.near + row]];
-            val = matrix_entry<D>(P, gi, gj);
-        } else {
-            const int q = row - M.nnear;
-            double r2 = 0.0;
+    for (int r0 = 0; r0 < M.m; r0 += kPxRows) {
+        const int nrow = min(kPxRows, M.m - r0);
+        __syncthreads();
+        for (int rr = tid; rr < nrow; rr += kThreads) {
+            const int row = r0 + rr;
+            if (row < M.nnear) {
+                const long gi = cidx[nearl[M.near + row]];
 #pragma unroll
-            for (int t = 0; t < D; ++t) {
-                double dx = M.ctr[t] + M.rho * pxdir[q * D + t] - P.pts[t * P.N + gj];
-                r2 += dx * dx;
+                for (int t = 0; t < D; ++t) sx[t][rr] = P.pts[t * P.N + gi];
+                srs[rr] = P.rs[gi];
+                sgi[rr] = gi;
+            } else {
+                const int q = row - M.nnear;
+#pragma unroll
+                for (int t = 0; t < D; ++t) sx[t][rr] = M.ctr[t] + M.rho * pxdir[q * D + t];
+                srs[rr] = 1.0;
+                sgi[rr] = -1;
             }
-            val = laplace_from_r2<D>(r2) * P.w[gj];
         }
-        Yb[e] = (R)val;
+        __syncthreads();
+        for (int col = c_lo; col < c_hi; ++col) {
+            const long gj = cidx[act[M.act + col]];
+            double xj[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) xj[t] = P.pts[t * P.N + gj];
+            const double wj = P.w[gj];
+            R* yc = Yb + (long)col * M.m + r0;
+            for (int rr = tid; rr < nrow; rr += kThreads) {
+                double val;
+                if (sgi[rr] == gj) {
+                    val = P.diag[gj];
+                } else {
+                    double r2 = 0.0;
+#pragma unroll
+                    for (int t = 0; t < D; ++t) {
+                        const double dx = sx[t][rr] - xj[t];
+                        r2 += dx * dx;
+                    }
+                    val = srs[rr] * laplace_from_r2<D>(r2) * wj;
+                }
+                yc[rr] = (R)val;
+            }
+        }
     }
 }
 
