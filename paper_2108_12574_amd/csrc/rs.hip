@@ -1167,26 +1167,60 @@ __global__ __launch_bounds__(kThreads) void k_box_matrix(ProblemView P,
                                                          const int* __restrict__ cidx,
                                                          const ChildRef<R>* __restrict__ ch,
                                                          R* __restrict__ App) {
+    // rows staged in LDS in chunks of kBmRows (grid index, coordinates, row scale and
+    // the child reference); the workgroup's columns then run over the chunk
+    constexpr int kBmRows = 512;
+    __shared__ double sx[D][kBmRows];
+    __shared__ double srs[kBmRows];
+    __shared__ long sgi[kBmRows];
+    __shared__ ChildRef<R> sref[kBmRows];
     const BoxMeta M = meta[blockIdx.x];
     const int np = M.np;
-    const long total = (long)np * np;
+    const int per = (np + gridDim.y - 1) / gridDim.y;
+    const int c_lo = blockIdx.y * per, c_hi = min(np, c_lo + per);
+    if (c_lo >= c_hi) return;
+    const int tid = threadIdx.x;
+    const bool parent = M.ch >= 0;
     R* A = App + M.app;
-    for (long e = (long)blockIdx.y * kThreads + threadIdx.x; e < total; e += (long)gridDim.y * kThreads) {
-        const int a = (int)(e % np);
-        const int c = (int)(e / np);
-        R val;
-        if (M.ch >= 0) {
-            const ChildRef<R> ra = ch[M.ch + a];
-            const ChildRef<R> rc = ch[M.ch + c];
-            if (ra.bss == rc.bss) {
-                val = ra.bss[ra.pos + (long)rc.pos * ra.ldk];
-            } else {
-                val = (R)matrix_entry<D>(P, cidx[act[M.act + a]], cidx[act[M.act + c]]);
-            }
-        } else {
-            val = (R)matrix_entry<D>(P, cidx[act[M.act + a]], cidx[act[M.act + c]]);
+    for (int r0 = 0; r0 < np; r0 += kBmRows) {
+        const int nrow = min(kBmRows, np - r0);
+        __syncthreads();
+        for (int rr = tid; rr < nrow; rr += kThreads) {
+            const long gi = cidx[act[M.act + r0 + rr]];
+#pragma unroll
+            for (int t = 0; t < D; ++t) sx[t][rr] = P.pts[t * P.N + gi];
+            srs[rr] = P.rs[gi];
+            sgi[rr] = gi;
+            if (parent) sref[rr] = ch[M.ch + r0 + rr];
         }
-        A[e] = val;
+        __syncthreads();
+        for (int c = c_lo; c < c_hi; ++c) {
+            const long gj = cidx[act[M.act + c]];
+            double xj[D];
+#pragma unroll
+            for (int t = 0; t < D; ++t) xj[t] = P.pts[t * P.N + gj];
+            const double wj = P.w[gj];
+            ChildRef<R> rc;
+            if (parent) rc = ch[M.ch + c];
+            R* ac = A + (long)c * np + r0;
+            for (int rr = tid; rr < nrow; rr += kThreads) {
+                R val;
+                if (parent && sref[rr].bss == rc.bss) {
+                    val = sref[rr].bss[sref[rr].pos + (long)rc.pos * sref[rr].ldk];
+                } else if (sgi[rr] == gj) {
+                    val = (R)P.diag[gj];
+                } else {
+                    double r2 = 0.0;
+#pragma unroll
+                    for (int t = 0; t < D; ++t) {
+                        const double dx = sx[t][rr] - xj[t];
+                        r2 += dx * dx;
+                    }
+                    val = (R)(srs[rr] * laplace_from_r2<D>(r2) * wj);
+                }
+                ac[rr] = val;
+            }
+        }
     }
 }
 
