@@ -820,83 +820,91 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         // largest box side), so the search is linear in the number of boxes.
         std::vector<std::vector<int>> nearl(L.nbox);
         if (!root) {
+            struct SubGrid {
+                int b0 = -1, nb = 0, smax = 1;
+                int glo[3] = {INT_MAX, INT_MAX, INT_MAX}, ghi[3] = {0, 0, 0}, gdim[3] = {1, 1, 1};
+                std::vector<std::vector<int>> bucket;
+                int cell_of(int t, int x) const { return std::min(gdim[t] - 1, std::max(0, (x - glo[t]) / smax)); }
+            };
+            std::vector<SubGrid> grids(D);
             for (int i = 0; i < D; ++i) {
                 if (L.sub_start[i] < 0) continue;
-                const int b0 = L.sub_start[i];
-                const int nb = (int)Q->subs[i].levels[l].size();
-                int smax = 1, glo[3] = {INT_MAX, INT_MAX, INT_MAX}, ghi[3] = {0, 0, 0};
-                for (int b = 0; b < nb; ++b)
+                SubGrid& G = grids[i];
+                G.b0 = L.sub_start[i];
+                G.nb = (int)Q->subs[i].levels[l].size();
+                for (int b = 0; b < G.nb; ++b)
                     for (int t = 0; t < d; ++t) {
-                        smax = std::max(smax, bhi[(b0 + b) * 3 + t] - blo[(b0 + b) * 3 + t]);
-                        glo[t] = std::min(glo[t], blo[(b0 + b) * 3 + t]);
-                        ghi[t] = std::max(ghi[t], blo[(b0 + b) * 3 + t]);
+                        G.smax = std::max(G.smax, bhi[(G.b0 + b) * 3 + t] - blo[(G.b0 + b) * 3 + t]);
+                        G.glo[t] = std::min(G.glo[t], blo[(G.b0 + b) * 3 + t]);
+                        G.ghi[t] = std::max(G.ghi[t], blo[(G.b0 + b) * 3 + t]);
                     }
-                int gdim[3] = {1, 1, 1};
-                for (int t = 0; t < d; ++t) gdim[t] = (ghi[t] - glo[t]) / smax + 1;
-                std::vector<std::vector<int>> bucket((size_t)gdim[0] * gdim[1] * gdim[2]);
-                auto cell_of = [&](int t, int x) { return std::min(gdim[t] - 1, std::max(0, (x - glo[t]) / smax)); };
-                for (int b = 0; b < nb; ++b) {
-                    long cidx = 0;
-                    for (int t = d - 1; t >= 0; --t) cidx = cidx * gdim[t] + cell_of(t, blo[(b0 + b) * 3 + t]);
-                    bucket[cidx].push_back(b);
+                for (int t = 0; t < d; ++t) G.gdim[t] = (G.ghi[t] - G.glo[t]) / G.smax + 1;
+                G.bucket.resize((size_t)G.gdim[0] * G.gdim[1] * G.gdim[2]);
+                for (int b = 0; b < G.nb; ++b) {
+                    long ci = 0;
+                    for (int t = d - 1; t >= 0; --t) ci = ci * G.gdim[t] + G.cell_of(t, blo[(G.b0 + b) * 3 + t]);
+                    G.bucket[ci].push_back(b);
                 }
-                // boxes are independent: split them over host threads
-                auto near_of = [&](int b) {
-                    const int B = b0 + b;
-                    int Lside = 0;
-                    long c2[3] = {0, 0, 0};
+            }
+            // the near field of box B (subdomain i, index b): active slots of the other
+            // boxes of its subdomain within the proxy radius of its centre
+            auto near_of = [&](int B) {
+                const SubGrid& G = grids[L.box_sub[B]];
+                const int b = B - G.b0;
+                int Lside = 0;
+                long c2[3] = {0, 0, 0};
+                for (int t = 0; t < d; ++t) {
+                    Lside = std::max(Lside, bhi[B * 3 + t] - blo[B * 3 + t]);
+                    c2[t] = blo[B * 3 + t] + bhi[B * 3 + t];
+                }
+                const double rad = o->proxy_ratio * Lside;          // grid units
+                const double R2 = (2.0 * rad) * (2.0 * rad);        // half-cell units, squared
+                int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
+                for (int t = 0; t < d; ++t) {
+                    // a box reaching within rad of the centre has its lower corner in
+                    // [centre - rad - smax, centre + rad]
+                    clo[t] = G.cell_of(t, (int)std::floor(0.5 * c2[t] - rad) - G.smax);
+                    chi[t] = G.cell_of(t, (int)std::ceil(0.5 * c2[t] + rad));
+                }
+                std::vector<int> cand;
+                for (int z = clo[2]; z <= chi[2]; ++z)
+                    for (int y = clo[1]; y <= chi[1]; ++y)
+                        for (int x = clo[0]; x <= chi[0]; ++x) {
+                            const auto& bk = G.bucket[((size_t)z * G.gdim[1] + y) * G.gdim[0] + x];
+                            cand.insert(cand.end(), bk.begin(), bk.end());
+                        }
+                std::sort(cand.begin(), cand.end());   // the order of an all-pairs scan
+                for (int b2 : cand) {
+                    if (b2 == b) continue;
+                    const int B2 = G.b0 + b2;
+                    double md = 0.0;
                     for (int t = 0; t < d; ++t) {
-                        Lside = std::max(Lside, bhi[B * 3 + t] - blo[B * 3 + t]);
-                        c2[t] = blo[B * 3 + t] + bhi[B * 3 + t];
+                        double lo2 = 2.0 * blo[B2 * 3 + t], hi2 = 2.0 * bhi[B2 * 3 + t];
+                        double dd = std::max(0.0, std::max(lo2 - c2[t], c2[t] - hi2));
+                        md += dd * dd;
                     }
-                    const double rad = o->proxy_ratio * Lside;          // grid units
-                    const double R2 = (2.0 * rad) * (2.0 * rad);        // half-cell units, squared
-                    int clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
-                    for (int t = 0; t < d; ++t) {
-                        // a box reaching within rad of the centre has its lower corner in
-                        // [centre - rad - smax, centre + rad]
-                        clo[t] = cell_of(t, (int)std::floor(0.5 * c2[t] - rad) - smax);
-                        chi[t] = cell_of(t, (int)std::ceil(0.5 * c2[t] + rad));
-                    }
-                    std::vector<int> cand;
-                    for (int z = clo[2]; z <= chi[2]; ++z)
-                        for (int y = clo[1]; y <= chi[1]; ++y)
-                            for (int x = clo[0]; x <= chi[0]; ++x) {
-                                const auto& bk = bucket[((size_t)z * gdim[1] + y) * gdim[0] + x];
-                                cand.insert(cand.end(), bk.begin(), bk.end());
-                            }
-                    std::sort(cand.begin(), cand.end());   // the order of an all-pairs scan
-                    for (int b2 : cand) {
-                        if (b2 == b) continue;
-                        const int B2 = b0 + b2;
-                        double md = 0.0;
+                    if (md >= R2) continue;
+                    for (int slot : act[B2]) {
+                        long s2 = 0;
                         for (int t = 0; t < d; ++t) {
-                            double lo2 = 2.0 * blo[B2 * 3 + t], hi2 = 2.0 * bhi[B2 * 3 + t];
-                            double dd = std::max(0.0, std::max(lo2 - c2[t], c2[t] - hi2));
-                            md += dd * dd;
+                            const long off = hc[(size_t)t * nslot + slot] - c2[t];
+                            s2 += off * off;
                         }
-                        if (md >= R2) continue;
-                        for (int slot : act[B2]) {
-                            long s2 = 0;
-                            for (int t = 0; t < d; ++t) {
-                                const long off = hc[(size_t)t * nslot + slot] - c2[t];
-                                s2 += off * off;
-                            }
-                            if ((double)s2 < R2) nearl[B].push_back(slot);
-                        }
+                        if ((double)s2 < R2) nearl[B].push_back(slot);
                     }
-                };
-                const int nt = std::min(nthreads, std::max(1, nb / 64));
-                if (nt <= 1) {
-                    for (int b = 0; b < nb; ++b) near_of(b);
-                } else {
-                    std::vector<std::thread> pool;
-                    for (int w = 0; w < nt; ++w)
-                        pool.emplace_back([&, w] {
-                            for (int b = w; b < nb; b += nt) near_of(b);
-                        });
-                    for (auto& th : pool) th.join();
                 }
+            };
+            // boxes are independent: one pool of host threads over all boxes of the level
+            const int nt = std::min(nthreads, std::max(1, L.nbox / 64));
+            if (nt <= 1) {
+                for (int B = 0; B < L.nbox; ++B) near_of(B);
+            } else {
+                std::vector<std::thread> pool;
+                for (int w = 0; w < nt; ++w)
+                    pool.emplace_back([&, w] {
+                        for (int B = w; B < L.nbox; B += nt) near_of(B);
+                    });
+                for (auto& th : pool) th.join();
             }
         }
         // metadata and offsets

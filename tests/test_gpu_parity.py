@@ -641,3 +641,41 @@ def test_partition_count_sweep(case):
             lo, hi = (1.4, 2.6) if d == 2 else (2.0, 5.0)
             assert lo <= S / S_prev <= hi, (S_prev, S)
         S_prev = S
+
+
+def test_sketched_leaf_ids_96cube_sampled():
+    # 3D 96^3 (N/M = 512, 1728 leaf boxes of up to 1000 points), tol 1e-3, 256 proxy
+    # points, randomized IDs, FP32 factors: the leaf level runs one workgroup per box on
+    # sketches of 608 rows (the register-resident update up to 1024 rows); sampled leaf
+    # IDs against the oracle's sketched ID of the same proxy matrix and signs
+    from oracle import sketch
+    P, O = gpu_problem(3, 96)
+    part = cbd.Partition(P, 12, 1, cbd.MODE_CBD, 0)
+    F = cbd.Factor(P, part, tol=1e-3, n_pxy=256, precision=cbd.PREC_FP32, sketch_seed=1)
+    assert len(F.level(0)[0]) >= 1024
+    opart = dd.Partition(3, 96, 12, 1, dd.CBD)
+    rng = np.random.default_rng(6)
+    n = O.n
+    for i in (0, 7):
+        sd = opart.subdomains[i]
+        for b in rng.choice(len(sd.leaves), 2, replace=False):
+            b = int(b)
+            lo, hi, st, cnt = sd.leaves[b]
+            p = np.arange(st, st + cnt)
+            others = np.setdiff1d(np.arange(len(sd.index)), p)
+            lo, hi = np.array(lo), np.array(hi)
+            J = np.stack([sd.index % n, (sd.index // n) % n, sd.index // (n * n)], axis=1)
+            off = 2 * J[others] + 1 - (lo + hi)
+            near = others[np.sum(off * off, axis=1) < (2 * 1.5 * np.max(hi - lo)) ** 2]
+            ctr = 0.5 * (lo + hi) / n
+            pxy = ctr + 1.5 * np.max(hi - lo) / n * rs.proxy_directions(3, 256)
+            xp = O.x[sd.index[p]]
+            Kp = 1.0 / (4 * np.pi * np.linalg.norm(pxy[:, None] - xp[None], axis=2))
+            Y = np.vstack([O.block(sd.index[near], sd.index[p]), Kp * O.weight * O.c[sd.index[p]]])
+            rowkeys = np.concatenate([sd.index[near], O.N + np.arange(256)])
+            k, perm, T, sketched = sketch.interp_decomp_sketched(Y, 1e-3, 1, sketch.box_key(i, 0, b), rowkeys)
+            print("subdomain", i, "leaf", b, "Y", Y.shape, "k", k, "sketched", sketched, flush=True)
+            assert sketched and sketch.sketch_size(*Y.shape) > 512
+            g = F.box(i, 0, b)
+            assert np.array_equal(g["sk"], p[perm[:k]]), (i, b)
+            assert rel(g["T"], T) <= 1e-5
