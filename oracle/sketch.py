@@ -11,14 +11,10 @@ an ell x m matrix of independent random signs.  If Y = Y[:, s] T exactly with
 k columns and ell > k, then Z = Z[:, s] T, so the ID of Z is an ID of Y; for
 numerically low-rank Y the error stays near the tolerance with high
 probability.  Readings (the paper gives no details):
-* sketch sizes, tried in turn (an adaptive range finder, after Halko,
-  Martinsson and Tropp): 64, 128, 256, ... below the cap ceil(3 n / 5) + 8, then
-  the cap; no sketch when the cap >= min(m, n);
+* sketch size ell = ceil(3 n / 5) + 8; no sketch when ell >= min(m, n);
 * the CPQR of Z uses the same rank and tie rules as the deterministic ID;
 * a sketch whose rank k exceeds ell - 8 is taken as saturated (the sketch may
-  have missed part of the range): the next size is tried, and after the cap the
-  box falls back to the deterministic ID.  The sketch of ell rows is the first
-  ell rows of the sketch of the cap (the signs depend on the row index only);
+  have missed part of the range): the box falls back to the deterministic ID;
 * the signs are a counter-based hash, so that any implementation can draw the
   same Omega: sign(seed, box key, i, row key) is the top bit of the splitmix64
   output function (Steele, Lea and Flood, OOPSLA 2014) applied to
@@ -34,7 +30,6 @@ from .cpqr import interp_decomp, TIE_FP64
 M64 = (1 << 64) - 1
 G1, G2, G3 = 0x9E3779B97F4A7C15, 0xD1B54A32D192ED03, 0x8CB92BA72F3D8DD7
 OVER = 8
-BASE = 64
 
 
 def mix64(x):
@@ -62,34 +57,19 @@ def signs(seed, key, ell, rowkeys):
 
 
 def sketch_size(m, n):
-    """The cap of the sketch size for an m x n matrix, or 0 when the deterministic ID
-    is used directly."""
+    """ell for an m x n matrix, or 0 when the deterministic ID is used directly."""
     ell = (3 * n + 4) // 5 + OVER
     return ell if ell < min(m, n) else 0
 
 
-def sketch_sizes(m, n):
-    """The sketch sizes tried in turn: BASE, 2 BASE, 4 BASE, ... below the cap, then the cap."""
-    cap = sketch_size(m, n)
-    if not cap:
-        return []
-    sizes, ell = [], BASE
-    while ell < cap:
-        sizes.append(ell)
-        ell *= 2
-    return sizes + [cap]
-
-
 def interp_decomp_sketched(Y, tol, seed, key, rowkeys, tie=TIE_FP64):
-    """ID of the columns of Y from the CPQR of Omega Y, Omega of the first sketch size
-    that does not saturate.  Returns (k, perm, T, sketched)."""
+    """ID of the columns of Y from the CPQR of Omega Y.  Returns (k, perm, T, sketched)."""
     m, n = Y.shape
-    sizes = sketch_sizes(m, n)
-    if sizes:
-        om = signs(seed, key, sizes[-1], rowkeys)
-        for ell in sizes:
-            k, perm, T = interp_decomp(om[:ell] @ Y, tol, tie)
-            if k <= ell - OVER:
-                return k, perm, T, True
+    ell = sketch_size(m, n)
+    if ell:
+        Z = signs(seed, key, ell, rowkeys) @ Y
+        k, perm, T = interp_decomp(Z, tol, tie)
+        if k <= ell - OVER:
+            return k, perm, T, True
     k, perm, T = interp_decomp(Y, tol, tie)
     return k, perm, T, False

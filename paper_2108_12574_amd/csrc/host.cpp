@@ -670,22 +670,12 @@ namespace {
 // fewer boxes use the stepped QR that spreads each box over many workgroups.
 constexpr int kStepBoxes = 1024;
 
-// Randomized ID: the cap of the sketch rows of an m x np proxy matrix (0: no sketch),
-// the margin below ell that a sketch's rank must stay under to be accepted, and the
-// sizes tried in turn (kSketchBase, doubling, below the cap; then the cap).
+// Randomized ID: rows of the sketch of an m x np proxy matrix (0: no sketch), and the
+// margin below ell that a sketch's rank must stay under to be accepted.
 constexpr int kSketchOver = 8;
-constexpr int kSketchBase = 64;
 int sketch_rows(int m, int np) {
     const int ell = (3 * np + 4) / 5 + kSketchOver;
     return ell < std::min(m, np) ? ell : 0;
-}
-std::vector<int> sketch_sizes(int m, int np) {
-    std::vector<int> sizes;
-    const int cap = sketch_rows(m, np);
-    if (!cap) return sizes;
-    for (int ell = kSketchBase; ell < cap; ell *= 2) sizes.push_back(ell);
-    sizes.push_back(cap);
-    return sizes;
 }
 
 double cpqr_flops(double m, double n, double k) {
@@ -1015,7 +1005,6 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         R* FF = (R*)L.d_F;
         std::vector<int> kpred;
         std::vector<int> kall, sk_ell;   // ranks (host copy kept for the upload) and sketch rows per box
-        std::vector<double> sk_extra;     // flops of saturated sketches per box
         if (!root && o->mlp) {
             std::vector<float> feats((size_t)L.nbox * kMlpFeatures), yhat(L.nbox);
             for (int B = 0; B < L.nbox; ++B)
@@ -1037,7 +1026,6 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         }
         kall.assign(L.nbox, 0);
         sk_ell.assign(L.nbox, 0);
-        sk_extra.assign(L.nbox, 0.0);
         for (size_t ci = 0; ci + 1 < cut.size(); ++ci) {
         const int b0 = cut[ci], b1 = cut[ci + 1], nbc = b1 - b0;
         // chunk-based views: the level's offsets (meta y, f, app) land in the chunk buffers
@@ -1170,38 +1158,36 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             };
             std::vector<int> det;   // boxes with the deterministic ID
             if (o->id_sketch) {
-                // randomized ID: the CPQR of Z = Omega Y (ell x np, random signs) for the
-                // sketch sizes of the box in turn; a sketch that saturates moves the box to
-                // the next size, and after the last size to the deterministic ID.  The
-                // sketch of ell rows is the first ell rows of any larger one.
+                // randomized ID: the CPQR of Z = Omega Y (ell x np, random signs), ell from
+                // the box shape; a saturated sketch falls back to the deterministic ID
+                std::vector<BoxMeta> zm;
+                std::vector<int> zb, zpred;
                 std::vector<unsigned long long> keys(nbc);
-                std::vector<std::vector<int>> sizes(nbc);
-                std::vector<int> tsz(nbc, 0), pend;
+                std::vector<BoxMeta> zall(L.meta.begin() + b0, L.meta.begin() + b1);
+                std::vector<long> boff(nbc, 0);   // offsets of the boxes' sign words
+                long o_z = 0, o_bits = 0, mw_max = 0;
                 for (int B = b0; B < b1; ++B) {
+                    const BoxMeta& M = L.meta[B];
+                    const int ell = sketch_rows(M.m, M.np);
                     keys[B - b0] = ((unsigned long long)L.box_sub[B] << 40) | ((unsigned long long)l << 32) |
                                    (unsigned long long)L.box_idx[B];
-                    sizes[B - b0] = sketch_sizes(L.meta[B].m, L.meta[B].np);
-                    if (sizes[B - b0].empty()) det.push_back(B);
-                    else pend.push_back(B);
-                }
-                while (!pend.empty()) {
-                    std::vector<BoxMeta> zm, zall(L.meta.begin() + b0, L.meta.begin() + b1);
-                    std::vector<int> zpred;
-                    std::vector<long> boff(nbc, 0);   // offsets of the boxes' sign words
-                    long o_z = 0, o_bits = 0, mw_max = 0;
-                    for (BoxMeta& M : zall) M.m = 0;  // boxes without a sketch in this round
-                    for (int B : pend) {
-                        const int e = B - b0, ell = sizes[e][tsz[e]];
-                        zall[e].m = ell;
-                        zall[e].y = o_z;
-                        o_z += (long)ell * L.meta[B].np;
-                        boff[e] = o_bits;
-                        const long mw = (long)L.meta[B].m * ((ell + 31) / 32);
-                        o_bits += mw;
-                        mw_max = std::max(mw_max, mw);
-                        zm.push_back(zall[e]);
+                    zall[B - b0].m = ell;
+                    zall[B - b0].y = o_z;
+                    o_z += (long)ell * M.np;
+                    boff[B - b0] = o_bits;
+                    const long mw = (long)M.m * ((ell + 31) / 32);
+                    o_bits += mw;
+                    mw_max = std::max(mw_max, mw);
+                    if (ell) {
+                        sk_ell[B] = ell;
+                        zm.push_back(zall[B - b0]);
+                        zb.push_back(B);
                         if (!kpred.empty()) zpred.push_back(std::min(kpred[B], ell));
+                    } else {
+                        det.push_back(B);
                     }
+                }
+                if (!zb.empty()) {
                     if ((rc = zbuf.ensure(sizeof(BoxMeta) * nbc + sizeof(unsigned long long) * nbc +
                                           sizeof(long) * nbc + sizeof(double) * std::max(o_z, 1L) +
                                           sizeof(unsigned) * std::max(o_bits, 1L))))
@@ -1217,26 +1203,18 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                     HIPCHK(hipMemcpyAsync(d_boff, boff.data(), sizeof(long) * nbc, hipMemcpyHostToDevice, s));
                     launch_sketch(nbc, np_max_c, mw_max, d_meta_c, d_zall, Y, (const int*)nearbuf.p, Q->d_cidx,
                                   P->N, o->sketch_seed, d_keys, d_boff, d_bits, Z, s);
-                    std::vector<int> kz, next;
-                    if ((rc = id_batch(zm, Z, zpred, kz))) return rc;   // (synchronizes the stream)
-                    for (size_t q = 0; q < pend.size(); ++q) {
-                        const int B = pend[q], e = B - b0, ell = sizes[e][tsz[e]];
-                        if (kz[q] <= ell - kSketchOver) {
-                            kall[B] = kz[q];
-                            sk_ell[B] = ell;
-                            F->sketched++;
+                    std::vector<int> kz;
+                    if ((rc = id_batch(zm, Z, zpred, kz))) return rc;
+                    for (size_t e = 0; e < zb.size(); ++e) {
+                        if (kz[e] > sk_ell[zb[e]] - kSketchOver) {
+                            det.push_back(zb[e]);       // saturated sketch
+                            sk_ell[zb[e]] = 0;
+                            F->sketch_fallbacks++;
                         } else {
-                            // saturated: the work of this size is spent
-                            sk_extra[B] += 2.0 * ell * L.meta[B].m * L.meta[B].np + cpqr_flops(ell, L.meta[B].np, kz[q]);
-                            if (++tsz[e] < (int)sizes[e].size()) {
-                                next.push_back(B);
-                            } else {
-                                det.push_back(B);
-                                F->sketch_fallbacks++;
-                            }
+                            kall[zb[e]] = kz[e];
+                            F->sketched++;
                         }
                     }
-                    pend.swap(next);
                 }
                 std::sort(det.begin(), det.end());
             } else {
@@ -1332,7 +1310,6 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             if (!root) {
                 const int ell = B < (int)sk_ell.size() ? sk_ell[B] : 0;
                 F->flops += ell ? 2.0 * ell * L.meta[B].m * np + cpqr_flops(ell, np, k) : cpqr_flops(L.meta[B].m, np, k);
-                F->flops += sk_extra[B];
             }
             F->flops += elim_flops(k, nr);
         }

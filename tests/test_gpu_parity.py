@@ -637,18 +637,17 @@ def test_partition_count_sweep(case):
         assert it <= it_paper + 10
         assert 0.5 * S_paper <= S <= 2.0 * S_paper
         if S_prev is not None:
-            # 2^d times more partitions: S grows by about 2 (2D) or 4 (3D; the last 3D
-            # step has leaves of 8 points, where the asymptotic rank bound is loose)
-            lo, hi = (1.4, 2.6) if d == 2 else (2.0, 6.0)
+            # 2^d times more partitions: S grows by about 2 (2D) or 4 (3D)
+            lo, hi = (1.4, 2.6) if d == 2 else (2.0, 5.0)
             assert lo <= S / S_prev <= hi, (S_prev, S)
         S_prev = S
 
 
 def test_sketched_leaf_ids_96cube_sampled():
     # 3D 96^3 (N/M = 512, 1728 leaf boxes of up to 1000 points), tol 1e-3, 256 proxy
-    # points, randomized IDs, FP32 factors: the leaf level runs one workgroup per box
-    # through the adaptive sketch sizes (64, 128, ... up to 608 rows); sampled leaf IDs
-    # against the oracle's sketched ID of the same proxy matrix and signs
+    # points, randomized IDs, FP32 factors: the leaf level runs one workgroup per box on
+    # sketches of up to 608 rows (the register-resident update up to 1024 rows); sampled
+    # leaf IDs against the oracle's sketched ID of the same proxy matrix and signs
     from oracle import sketch
     P, O = gpu_problem(3, 96)
     part = cbd.Partition(P, 12, 1, cbd.MODE_CBD, 0)

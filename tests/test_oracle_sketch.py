@@ -30,22 +30,6 @@ def test_sketch_size_rule():
     assert sketch.sketch_size(400, 100) == 68          # ceil(300/5) + 8
     assert sketch.sketch_size(60, 100) == 0             # not below min(m, n)
     assert sketch.sketch_size(1000, 7) == 0
-    assert sketch.sketch_sizes(400, 100) == [64, 68]
-    assert sketch.sketch_sizes(5000, 1000) == [64, 128, 256, 512, 608]
-    assert sketch.sketch_sizes(300, 90) == [62]
-    assert sketch.sketch_sizes(60, 100) == []
-
-
-def test_saturated_size_moves_to_the_next_size():
-    # rank 100 > 64 - 8: the 64-row sketch saturates, the 128-row one reproduces Y exactly
-    rng = np.random.default_rng(1)
-    m, n, r = 1000, 400, 100
-    Y = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
-    assert sketch.sketch_sizes(m, n) == [64, 128, 248]
-    k, perm, T, used = sketch.interp_decomp_sketched(Y, 1e-12, 3, 11, np.arange(m))
-    assert used and k == r
-    err = np.linalg.norm(Y[:, perm[k:]] - Y[:, perm[:k]] @ T)
-    assert err <= 1e-10 * np.linalg.norm(Y)
 
 
 @pytest.mark.parametrize("r", [5, 20, 40])
