@@ -2035,6 +2035,10 @@ __global__ __launch_bounds__(kThreads) void k_apply_level(const BoxMeta* __restr
     }
     __syncthreads();
     if (nr > 0) {
+        // the three products (on matrix cores from 8 right-hand sides on), on the transposed
+        // local block (column c of v is row c of the nc x np block sv^T, leading dimension rc):
+        //   tmp^T = v_r^T - v_s^T X1,  v_r^T = tmp^T G^{-1} (forward) or tmp^T G^{-T},
+        //   v_s^T -= v_r^T X2^T   (G^{-1} is stored with a zero lower triangle)
         const R* T = F + M.f;
         const R* E = T + (long)k * nr;
         const R* Gi = E + (long)k * nr;
@@ -2042,31 +2046,41 @@ __global__ __launch_bounds__(kThreads) void k_apply_level(const BoxMeta* __restr
         R* vr = sv + (long)k * rc;
         const R* X1 = forward ? T : E;   // applied first (transposed)
         const R* X2 = forward ? E : T;   // applied last
-        for (long e = tid; e < (long)nr * nc; e += kThreads) {
-            const int i = (int)(e / nc), c = (int)(e % nc);
-            R s = vr[i * rc + c];
-            for (int a = 0; a < k; ++a) s -= X1[a + (long)i * k] * vs[a * rc + c];
-            tmp[i * rc + c] = s;
-        }
-        __syncthreads();
-        for (long e = tid; e < (long)nr * nc; e += kThreads) {
-            const int i = (int)(e / nc), c = (int)(e % nc);
-            R s = 0;
-            if (forward) {
-                for (int j = 0; j <= i; ++j) s += Gi[j + (long)i * nr] * tmp[j * rc + c];
-            } else {
-                for (int j = i; j < nr; ++j) s += Gi[i + (long)j * nr] * tmp[j * rc + c];
+        if (nc >= 8) {
+            for (long e = tid; e < (long)nr * rc; e += kThreads) tmp[e] = vr[e];
+            __syncthreads();
+            if (k > 0) wg_gemm<R>(nc, nr, k, (R)-1, vs, rc, false, X1, k, false, (R)1, tmp, rc);
+            wg_gemm<R>(nc, nr, nr, (R)1, tmp, rc, false, Gi, nr, !forward, (R)0, vr, rc);
+            if (k > 0) wg_gemm<R>(nc, k, nr, (R)-1, vr, rc, false, X2, k, true, (R)1, vs, rc);
+        } else {
+            // a few right-hand sides: one output entry per thread (16 x 16 matrix-core
+            // tiles would be mostly empty)
+            for (long e = tid; e < (long)nr * nc; e += kThreads) {
+                const int i = (int)(e / nc), c = (int)(e % nc);
+                R sum = vr[i * rc + c];
+                for (int a = 0; a < k; ++a) sum -= X1[a + (long)i * k] * vs[a * rc + c];
+                tmp[i * rc + c] = sum;
             }
-            vr[i * rc + c] = s;
+            __syncthreads();
+            for (long e = tid; e < (long)nr * nc; e += kThreads) {
+                const int i = (int)(e / nc), c = (int)(e % nc);
+                R sum = 0;
+                if (forward) {
+                    for (int j = 0; j <= i; ++j) sum += Gi[j + (long)i * nr] * tmp[j * rc + c];
+                } else {
+                    for (int j = i; j < nr; ++j) sum += Gi[i + (long)j * nr] * tmp[j * rc + c];
+                }
+                vr[i * rc + c] = sum;
+            }
+            __syncthreads();
+            for (long e = tid; e < (long)k * nc; e += kThreads) {
+                const int a = (int)(e / nc), c = (int)(e % nc);
+                R sum = vs[a * rc + c];
+                for (int i = 0; i < nr; ++i) sum -= X2[a + (long)i * k] * vr[i * rc + c];
+                vs[a * rc + c] = sum;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        for (long e = tid; e < (long)k * nc; e += kThreads) {
-            const int a = (int)(e / nc), c = (int)(e % nc);
-            R s = vs[a * rc + c];
-            for (int i = 0; i < nr; ++i) s -= X2[a + (long)i * k] * vr[i * rc + c];
-            vs[a * rc + c] = s;
-        }
-        __syncthreads();
     }
     for (long e = tid; e < (long)np * nc; e += kThreads) {
         const int a = (int)(e / nc), c = (int)(e % nc);
