@@ -789,9 +789,14 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                     }
                     if (pl == 0) {
                         const Leaf& lf = sd.leaves[b];
-                        for (int e = 0; e < lf.count; ++e) a.push_back((int)(sd.offset + lf.start + e));
+                        a.resize(lf.count);
+                        for (int e = 0; e < lf.count; ++e) a[e] = (int)(sd.offset + lf.start + e);
                     } else {
                         const Level& PLv = F->levels[pl - 1];
+                        int nsk = 0;
+                        for (int c : pb.children) nsk += PLv.k[PLv.sub_start[i] + c];
+                        a.reserve(nsk);
+                        ch.reserve(nsk);
                         for (int c : pb.children) {
                             const int cb = PLv.sub_start[i] + c;
                             const BoxMeta& cm = PLv.meta[cb];
@@ -867,6 +872,8 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                     chi[t] = G.cell_of(t, (int)std::ceil(0.5 * c2[t] + rad));
                 }
                 std::vector<int> cand;
+                cand.reserve(64);
+                nearl[B].reserve(8 * act[B].size());
                 for (int z = clo[2]; z <= chi[2]; ++z)
                     for (int y = clo[1]; y <= chi[1]; ++y)
                         for (int x = clo[0]; x <= chi[0]; ++x) {
