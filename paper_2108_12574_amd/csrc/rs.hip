@@ -1348,11 +1348,6 @@ __device__ void block_gemm64(BgShared<R>& sh, int i0, int j0, int M, int N, int 
     __syncthreads();
 }
 
-// C (M x N, column-major, ldc) = beta C + alpha op(A) op(B), op(A) M x K, op(B) K x N;
-// ta/tb select the transposes (A[k + i*lda] / B[j + k*ldb]).  All threads of the
-// workgroup call it; 16 x 16 output tiles are spread over the waves.  With
-// upper != 0 tiles entirely below the diagonal are skipped (symmetric results
-// whose upper triangle is used).  Ends with a workgroup barrier.
 // One 16 x 16 tile (rows i0.., columns j0..) of C = beta C_in + alpha op(A) op(B),
 // computed by one wave; C_in may be C itself.
 template <typename R>
