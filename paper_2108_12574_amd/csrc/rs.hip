@@ -184,33 +184,41 @@ __device__ __forceinline__ void reflect_columns(double* Yb, int m, int j, int c_
 }
 
 // Register-resident form of reflect_columns for m - j <= 64 NR rows: a wave loads
-// all rows of G columns at once (clamped addresses, masked values), so the loads
-// of a column are in flight together and the column is read once; the per-lane
-// sums run over the same rows in the same order as reflect_columns, so the
-// results are the same.
+// all rows of G columns at once, so the loads of a column are in flight together
+// and the column is read once.  The loads and stores go through a buffer resource
+// per column (base in scalar registers, one offset register for all rows; loads
+// past the column's end return 0, where the reflector is 0 too).  The per-lane
+// sums run over the same rows in the same order as reflect_columns, so the results
+// are the same.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t column_rsrc(const double* Yb, int m, int j, int c, int rows) {
+    // 0x00020000: the gfx9 buffer-resource word 3 for raw (untyped) accesses
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(Yb + (long)c * m + j), (short)0, rows * (int)sizeof(double),
+                                             0x00020000);
+}
+
 template <int NR>
 __device__ __forceinline__ void reflect_columns_reg(double* Yb, int m, int j, int c_lo, int c_hi,
                                                     const double* v, double beta, double* norms) {
+    typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(__amdgpu_buffer_rsrc_t(), 0, 0, 0)) b64;
     constexpr int G = NR > 12 ? 1 : 2;
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // column bases in SGPRs
     const int rows = m - j;
     for (int c0 = c_lo + wid; c0 < c_hi; c0 += G * kWaves) {
-        double* col[G];
+        __amdgpu_buffer_rsrc_t rs[G];
         bool ok[G];
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int c = c0 + u * kWaves;
             ok[u] = c < c_hi;
-            col[u] = Yb + (long)(ok[u] ? c : c0) * m + j;
+            rs[u] = column_rsrc(Yb, m, j, ok[u] ? c : c0, rows);
         }
         double a[G][NR];
 #pragma unroll
-        for (int i = 0; i < NR; ++i) {
-            const int rr = min(lane + 64 * i, rows - 1);
+        for (int i = 0; i < NR; ++i)
 #pragma unroll
-            for (int u = 0; u < G; ++u) a[u][i] = col[u][rr];
-        }
+            for (int u = 0; u < G; ++u)
+                a[u][i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs[u], (lane + 64 * i) * 8, 0, 0));
         double sd[G];
 #pragma unroll
         for (int u = 0; u < G; ++u) sd[u] = 0.0;
@@ -223,6 +231,9 @@ __device__ __forceinline__ void reflect_columns_reg(double* Yb, int m, int j, in
         }
 #pragma unroll
         for (int u = 0; u < G; ++u) sd[u] = wave_sum(sd[u]) * beta;
+        // compiler-only barrier: the reflector is read from LDS again below instead of
+        // being kept in registers through the reduction
+        __asm__ volatile("" ::: "memory");
         double q[G];
 #pragma unroll
         for (int u = 0; u < G; ++u) q[u] = 0.0;
@@ -234,7 +245,7 @@ __device__ __forceinline__ void reflect_columns_reg(double* Yb, int m, int j, in
 #pragma unroll
                 for (int u = 0; u < G; ++u) {
                     const double y = a[u][i] - sd[u] * vv;
-                    if (ok[u]) col[u][rr] = y;
+                    if (ok[u]) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64, y), rs[u], rr * 8, 0, 0);
                     if (rr > 0) q[u] += y * y;
                 }
             }
@@ -544,6 +555,7 @@ void launch_qr_step(int nbox, int np_max, int m_max, const BoxMeta* meta, double
     if (nbox == 0) return;
     hipLaunchKernelGGL(k_qr_pivot, dim3(nbox), dim3(kThreads), 0, s, meta, Y, st, j, tol, tie);
     // rows of the update: at most m_max - j; the register form holds up to 64 NR of them
+    // (3072 rows; within 256 registers per lane)
     const int cb = (m_max - j + 63) / 64;
     const dim3 grid(nbox, (np_max + kQrCols - 1) / kQrCols);
     const size_t shm = (size_t)m_max * sizeof(double);
@@ -559,6 +571,10 @@ void launch_qr_step(int nbox, int np_max, int m_max, const BoxMeta* meta, double
         hipLaunchKernelGGL(k_qr_update<16>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
     else if (cb <= 24)
         hipLaunchKernelGGL(k_qr_update<24>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+    else if (cb <= 32)
+        hipLaunchKernelGGL(k_qr_update<32>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+    else if (cb <= 48)
+        hipLaunchKernelGGL(k_qr_update<48>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
     else
         hipLaunchKernelGGL(k_qr_update<0>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
 }
