@@ -702,3 +702,21 @@ def test_leaf_ids_64cube_m16_sampled():
             g = F.box(i, 0, int(b))
             assert np.array_equal(g["sk"], sk), (i, b)
             assert rel(g["T"], T) <= 1e-5
+
+
+def test_leaf_ids_48cube_m4_sampled():
+    # 3D 48^3, CBD m = 4 (64 leaf boxes of up to 2548 points), tol 1e-3, deterministic
+    # IDs: the stepped QR runs on proxy matrices of about 2100 rows (the register-
+    # resident update for 2048 to 3072 rows); sampled leaf IDs against the oracle
+    P, O = gpu_problem(3, 48)
+    part = cbd.Partition(P, 4, 1, cbd.MODE_CBD, 0)
+    F = cbd.Factor(P, part, tol=1e-3, n_pxy=256, precision=cbd.PREC_FP32)
+    opart = dd.Partition(3, 48, 4, 1, dd.CBD)
+    rng = np.random.default_rng(9)
+    for i in (1, 4):
+        sd = opart.subdomains[i]
+        for b in rng.choice(len(sd.leaves), 2, replace=False):
+            sk, T = _single_leaf_factor_3d(O, sd, int(b), tol=1e-3)
+            g = F.box(i, 0, int(b))
+            assert np.array_equal(g["sk"], sk), (i, b)
+            assert rel(g["T"], T) <= 1e-5
