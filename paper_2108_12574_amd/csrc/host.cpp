@@ -1085,7 +1085,18 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                     const BoxMeta* qmeta = d_bm;
                     double* QY = Ymat;
                     int q_m_max = m_max;
-                    const bool tall = sum_y >= 2 * sum_r && (double)sum_y * sizeof(double) >= 32.0 * (1 << 20);
+                    // Compress when the matrices are tall and the rows saved over the pivot
+                    // steps outweigh the compression: each step streams the trailing block
+                    // (about 16 bytes per entry at about 5 TB/s), while the Householder QR costs
+                    // about 0.3 ms per 16 columns with the panel in registers (up to 2560 rows),
+                    // 4 ms per 32 columns otherwise.  The number of steps is the largest
+                    // predicted rank, or a quarter of the widest box without a prediction.
+                    int k_est = k_max / 4;
+                    if (!bpred.empty()) k_est = *std::max_element(bpred.begin(), bpred.end());
+                    const double t_saved = (double)k_est * (double)(sum_y - sum_r) * 16.0 / 5e12;
+                    const double t_compress = m_max <= 2560 ? (k_max + 15) / 16 * 0.3e-3 : (k_max + 31) / 32 * 4e-3;
+                    const bool tall = sum_y >= 2 * sum_r && (double)sum_y * sizeof(double) >= 32.0 * (1 << 20) &&
+                                      t_saved > t_compress;
                     if (o->row_compression == CBD_ROWS_ALWAYS || (o->row_compression == CBD_ROWS_AUTO && tall)) {
                         cmh = bm;
                         long o_r = 0;
