@@ -58,6 +58,12 @@ WORKLOADS = {
                     prec="fp32", coef=False, sketch=True, fft=True, dense=False, variants=False,
                     label="3D 256^3 (N=16777216), CBD m=32 (N/M=512), tol 1e-3, 256 proxy pts, sketched IDs, "
                           "1 RHS, FP32 factors, FFT matvec in PCG (no dense product: 2.8e14 pairs)"),
+    # the paper's own 512^2 row of its 2D weak-scaling table: tolerance 1e-3, constant
+    # coefficients, one right-hand side, FFT products, FP64 factors, PCG to 1e-12
+    "512sq_paper": dict(d=2, n=512, m=64, mode="cbd", delta=1, leaf=0, tol=1e-3, npxy=64, nrhs=1,
+                        prec="fp64", coef=False, fft=True, dense=False, variants=False, pcg_tol=1e-12,
+                        label="2D 512^2 at the paper's settings: CBD m=64, tol 1e-3, b=c=1, FP64 factors, "
+                              "1 RHS, FFT products, PCG to 1e-12"),
     "global512": dict(d=2, n=512, m=1, mode="jacobi", delta=0, leaf=8, tol=1e-6, npxy=64, nrhs=64,
                       prec="fp32", coef=True,
                       label="2D 512^2, global RS (one subdomain, 8x8 leaf tiles), b=c=1+0.5sin(2pi x1)cos(2pi x2), "
@@ -141,6 +147,7 @@ def main():
     prec = {"fp32": cbd.PREC_FP32, "fp64": cbd.PREC_FP64}[W["prec"]]
     sk_seed = 1 if W.get("sketch") else None      # randomized IDs
     use_fft = bool(W.get("fft"))                   # PCG products by FFT (workloads too large for the dense form)
+    pcg_tol = W.get("pcg_tol", 1e-10)              # relative residual of the timed PCG
     dense = W.get("dense", True)                   # time the dense matvec (autotune, roofline)
     full = W.get("variants", True)                 # the variants (no predictor, FFT, sketch, bf16, FP64 form)
     N = n ** d
@@ -179,7 +186,7 @@ def main():
         fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=sk_seed)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        u, its, rr = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200, fft=use_fft)
+        u, its, rr = cbd.pcg_solve(P, fac, F_rhs, tol=pcg_tol, maxit=200, fft=use_fft)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return fac, its, rr, t1 - t0, t2 - t1
