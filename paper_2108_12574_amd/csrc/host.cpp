@@ -1095,8 +1095,11 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                     if (!bpred.empty()) k_est = *std::max_element(bpred.begin(), bpred.end());
                     const double t_saved = (double)k_est * (double)(sum_y - sum_r) * 16.0 / 5e12;
                     const double t_compress = m_max <= 2560 ? (k_max + 15) / 16 * 0.3e-3 : (k_max + 31) / 32 * 4e-3;
-                    const bool tall = sum_y >= 2 * sum_r && (double)sum_y * sizeof(double) >= 32.0 * (1 << 20) &&
-                                      t_saved > t_compress;
+                    // (matrices taller than the update kernel's LDS allows are always compressed)
+                    const bool too_tall = (size_t)m_max * sizeof(double) > 65536;
+                    const bool tall = too_tall || (sum_y >= 2 * sum_r &&
+                                                   (double)sum_y * sizeof(double) >= 32.0 * (1 << 20) &&
+                                                   t_saved > t_compress);
                     if (o->row_compression == CBD_ROWS_ALWAYS || (o->row_compression == CBD_ROWS_AUTO && tall)) {
                         cmh = bm;
                         long o_r = 0;

@@ -720,3 +720,18 @@ def test_leaf_ids_48cube_m4_sampled():
             g = F.box(i, 0, int(b))
             assert np.array_equal(g["sk"], sk), (i, b)
             assert rel(g["T"], T) <= 1e-5
+
+
+def test_global_rs_512_tall_levels():
+    # 512^2 global RS (one subdomain, 8 x 8 leaf tiles), tol 1e-6: the top levels have
+    # proxy matrices of more than 8192 rows, which must be row-compressed before the
+    # stepped QR whatever the cost rule says; PCG on one right-hand side
+    P, O = gpu_problem(2, 512, coef=True)
+    part = cbd.Partition(P, 1, 0, cbd.MODE_JACOBI, 8)
+    F = cbd.Factor(P, part, tol=1e-6, n_pxy=64, precision=cbd.PREC_FP32)
+    sch = F.schedule()
+    print("global 512^2: root", F.stats()["S"], "row-compressed levels", sch["row_compressed"], flush=True)
+    assert sch["row_compressed"] >= 1
+    f = torch.tensor(synth.rhs(O.N, 1, seed=0)[0], device=DEV)
+    u, it, rr = cbd.pcg_solve(P, F, f, tol=1e-10, maxit=50)
+    assert rr <= 1e-10 and it <= 6
