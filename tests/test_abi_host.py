@@ -41,6 +41,38 @@ def test_errors_are_reported_without_gpu():
         cbd.Partition((2, 30), 4)
 
 
+def test_every_compute_entry_point_rejects_bad_arguments_on_the_host():
+    """Each entry point checks its arguments before any device call, so a
+    NULL handle or pointer, a nonpositive count or an unknown option returns
+    EARG with a message naming the call, with no GPU present."""
+    L = cbd.lib()
+    import ctypes
+    h = ctypes.c_void_p()
+    buf = ctypes.c_void_p(16)  # never dereferenced: each call fails before
+    it, rr = ctypes.c_int(), ctypes.c_double()
+    opts = _lib.RSOpts()
+    cases = [
+        ("ie_assemble", lambda: L.ie_assemble(4, 16, 0, None, None, buf, buf, buf, buf, None, ctypes.byref(h))),
+        ("ie_assemble", lambda: L.ie_assemble(2, 1, 0, None, None, buf, buf, buf, buf, None, ctypes.byref(h))),
+        ("ie_assemble", lambda: L.ie_assemble(2, 16, 0, None, None, None, buf, buf, buf, None, ctypes.byref(h))),
+        ("kernel_matvec", lambda: L.kernel_matvec(None, 1, buf, ctypes.c_void_p(32), None)),
+        ("kernel_matvec_fft", lambda: L.kernel_matvec_fft(None, 1, buf, ctypes.c_void_p(32), None)),
+        ("cbd_fft_prepare", lambda: L.cbd_fft_prepare(None, 1, None)),
+        ("rs_factor_batched", lambda: L.rs_factor_batched(None, None, ctypes.byref(opts), None, ctypes.byref(h))),
+        ("rs_apply", lambda: L.rs_apply(None, 1, buf, ctypes.c_void_p(32), None)),
+        ("pcg_solve", lambda: L.pcg_solve(None, None, 1, buf, buf, 1e-10, 10, 0, buf, 0,
+                                          ctypes.byref(it), ctypes.byref(rr), None)),
+        ("rank_mlp_forward", lambda: L.rank_mlp_forward(None, 4, buf, buf, None)),
+        ("rank_mlp_adam", lambda: L.rank_mlp_adam(buf, buf, buf, buf, 0, ctypes.c_float(1e-3), None)),
+        ("dd_partition_info", lambda: L.dd_partition_info(None, None, None, None, None)),
+        ("rs_factor_stats", lambda: L.rs_factor_stats(None, None, None, None, None)),
+        ("cbd_timing_get", lambda: L.cbd_timing_get(None, None, None)),
+    ]
+    for name, call in cases:
+        assert call() == _lib.EARG, name
+        assert L.cbd_last_error().startswith(name.encode()), (name, L.cbd_last_error())
+
+
 CASES = [
     (2, 64, 16, 1, dd.CBD, 0),
     (2, 256, 4, 8, dd.SCHWARZ, 8),
