@@ -19,7 +19,8 @@
  *    on it and return; calls that return host results (ranks, iteration counts,
  *    statistics) synchronize the stream first.
  *  - Return value: 0 = success, < 0 = error (nothing usable was produced; the
- *    message is in cbd_last_error()), > 0 = warning (result produced).
+ *    message is in cbd_last_error(), which holds the last failure of the
+ *    calling thread), > 0 = warning (result produced).
  */
 #ifndef CBD_H
 #define CBD_H
