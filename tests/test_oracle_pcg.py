@@ -9,6 +9,9 @@ conjugate gradients that do not depend on its own recurrences.
 * With M = A^{-1} one step solves the system.
 * For a fixed linear SPD preconditioner, r_{j+1}.z_j = 0, so the flexible
   (Polak-Ribiere) beta equals the standard one and both give the same iterates.
+* For a preconditioner that changes between iterations, the loss of
+  conjugacy between consecutive directions follows in closed form from the
+  recurrences, and differs between the two betas.
 """
 import numpy as np
 import pytest
@@ -108,3 +111,51 @@ def test_zero_right_hand_side_column_is_left_alone():
     U, its, rr = pcg.pcg(_mv(A), None, F, tol=1e-12, maxit=100)
     assert its[1] == 0 and rr[1] == 0.0 and not U[:, 1].any()
     assert np.allclose(U[:, [0, 2]], np.linalg.solve(A, F[:, [0, 2]]), atol=1e-10)
+
+
+def _variable_diag_precond(d0, d1):
+    """z = diag(d_{c mod 2}) r on the c-th call of one solve (a preconditioner
+    that changes between iterations, as an inexact inner solve does)."""
+    calls = [0]
+
+    def apply(X):
+        d = d0 if calls[0] % 2 == 0 else d1
+        calls[0] += 1
+        return d[:, None] * X
+    return apply
+
+
+@pytest.mark.parametrize("flexible", [False, True])
+def test_conjugacy_defect_with_a_variable_preconditioner(flexible):
+    """With x_{i+1} = x_i + alpha_i p_i, r_{i+1} = r_i - alpha_i A p_i and
+    p_i.A p_i = r_i.z_i / alpha_i, the next direction p_{i+1} = z_{i+1} + beta_i p_i
+    has p_{i+1}.A p_i = (z_{i+1}.r_i - z_{i+1}.r_{i+1} + beta_i r_i.z_i) / alpha_i:
+    z_{i+1}.r_i / alpha_i for the standard beta and
+    (z_{i+1}.r_i - r_{i+1}.z_i) / alpha_i for the flexible one.  Both sides are
+    rebuilt here from the iterates alone: alpha_i p_i = x_{i+1} - x_i."""
+    rng = np.random.default_rng(31)
+    n = 40
+    A = _spd_with_spectrum(np.linspace(1.0, 300.0, n), seed=32)
+    f = rng.standard_normal(n)
+    d0 = 1.0 / np.diag(A)
+    d1 = d0 * rng.uniform(0.3, 3.0, n)
+
+    def iterate(t):
+        if t == 0:
+            return np.zeros(n)
+        return pcg.pcg(_mv(A), _variable_diag_precond(d0, d1), f, tol=0.0, maxit=t, flexible=flexible)[0]
+
+    x = [iterate(t) for t in range(7)]
+    r = [f - A @ xi for xi in x]
+    z = [(d0 if i % 2 == 0 else d1) * r[i] for i in range(7)]
+    seen = []
+    for i in range(5):
+        dx, dx1 = x[i + 1] - x[i], x[i + 2] - x[i + 1]
+        a_i = (dx @ A @ dx) / (r[i] @ z[i])
+        a_i1 = (dx1 @ A @ dx1) / (r[i + 1] @ z[i + 1])
+        lhs = (dx1 / a_i1) @ A @ (dx / a_i)
+        rhs = (z[i + 1] @ r[i] - (r[i + 1] @ z[i] if flexible else 0.0)) / a_i
+        scale = np.linalg.norm(dx1 / a_i1) * np.linalg.norm(A @ dx / a_i)
+        assert abs(lhs - rhs) <= 1e-8 * scale, (i, lhs, rhs, scale)
+        seen.append(abs(rhs) / scale)
+    assert max(seen) > 1e-4     # the preconditioner change is visible
