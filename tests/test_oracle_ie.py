@@ -81,6 +81,13 @@ def test_coefficients_scale_rows_and_columns():
     c = 2.0 - b
     p2 = ie.Problem(2, n, b=b, c=c)
     assert p2.block([3], [7])[0, 0] == pytest.approx(b[3] * p0.block([3], [7])[0, 0] * c[7], rel=1e-15)
+    # the diagonal: b_i c_i times the self-cell integral, in 2D and 3D
+    assert p2.diag() == pytest.approx(b * c * ie.self_cell_integral(2, 1.0 / n), rel=1e-15)
+    q0 = ie.Problem(3, 5)
+    b3 = synth.coef_smooth(3, 5)
+    q1 = ie.Problem(3, 5, b=b3, c=1.0 / b3)
+    assert np.allclose(q1.diag(), np.diag(q1.dense()), rtol=1e-15, atol=0)
+    assert np.allclose(q1.diag(), q0.diag(), rtol=1e-14, atol=0)
 
 
 def test_coef_field_range():
