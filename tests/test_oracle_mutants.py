@@ -65,6 +65,13 @@ MUTANTS = [
      "return 1.0 - top.astype(np.float64)"),
     ("sketch.py", ["test_oracle_sketch.py"], "x = base + i * np.uint64(G2) + r * np.uint64(G3)",
      "x = base + i * np.uint64(G2) + r * np.uint64(0)"),
+    ("dd.py", ["test_oracle_dd.py", "test_oracle_tables.py"], "color = sum((k[t] % 2) << t for t in range(d))",
+     "color = sum((k[t] % 2) for t in range(d))"),
+    ("dd.py", ["test_oracle_dd.py", "test_oracle_tables.py"],
+     "lo = [max(0, k[t] * s - delta) for t in range(d)]\n"
+     "                hi = [min(n, (k[t] + 1) * s + delta) for t in range(d)]\n                regions_of[color]",
+     "lo = [max(0, k[t] * s) for t in range(d)]\n"
+     "                hi = [min(n, (k[t] + 1) * s + delta) for t in range(d)]\n                regions_of[color]"),
     ("pcg.py", ["test_oracle_pcg.py"], "p[:, act] = znew + beta * p[:, act]", "p[:, act] = znew - beta * p[:, act]"),
     ("pcg.py", ["test_oracle_pcg.py"], "beta = rznew / rz[act]", "beta = np.sum(r[:, act] * z[:, act], axis=0) / rz[act]"),
     ("pcg.py", ["test_oracle_pcg.py"], "z[:, act] = znew", "pass"),
