@@ -44,3 +44,28 @@ def test_adam_reduces_a_quadratic_and_fits_a_line():
         loss, g = mlp.loss_and_grad(p, X, t)
         p, m, v = mlp.adam(p, g, m, v, s, 1e-2)
     assert loss < 0.02 * l0
+
+
+def test_adam_first_step_and_gradient_scale_invariance():
+    """Two properties of Adam (Kingma and Ba, Section 2.1) that do not restate its
+    update: the bias-corrected first step moves each parameter by lr * |g| / (|g| + eps)
+    against the sign of g, the step size lr when |g| >> eps and less when |g| is
+    near eps; and rescaling every gradient by c > 0 leaves the trajectory unchanged
+    while |g| >> eps."""
+    lr, eps = 1e-2, 1e-8
+    g = np.array([3.0, -0.5, 1e-4, -1e-6, 2e-8, 0.0])
+    p0 = np.zeros_like(g)
+    p1, m, v = mlp.adam(p0, g, np.zeros_like(g), np.zeros_like(g), 1, lr)
+    step = -(p1 - p0)
+    assert np.allclose(step, lr * g / (np.abs(g) + eps), rtol=1e-12, atol=0)
+    assert abs(step[3]) > 0.98 * lr and abs(step[4]) < 0.7 * lr and step[5] == 0.0
+
+    rng = np.random.default_rng(4)
+    gs = rng.standard_normal((12, 8)) * rng.uniform(0.5, 2.0, (12, 1))
+    traj = []
+    for c in (1.0, 1e3):
+        p, m, v = np.zeros(8), np.zeros(8), np.zeros(8)
+        for s, gt in enumerate(gs, start=1):
+            p, m, v = mlp.adam(p, c * gt, m, v, s, lr)
+        traj.append(p)
+    assert np.allclose(traj[0], traj[1], rtol=1e-6, atol=1e-9)

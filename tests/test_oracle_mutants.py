@@ -72,6 +72,15 @@ MUTANTS = [
      "                hi = [min(n, (k[t] + 1) * s + delta) for t in range(d)]\n                regions_of[color]",
      "lo = [max(0, k[t] * s) for t in range(d)]\n"
      "                hi = [min(n, (k[t] + 1) * s + delta) for t in range(d)]\n                regions_of[color]"),
+    ("mlp.py", ["test_oracle_mlp.py"], "u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000",
+     "u = (u + 0x8000) & 0xFFFF0000"),
+    ("mlp.py", ["test_oracle_mlp.py"], "dz2 = np.outer(dy, W3) * (z2 > 0)", "dz2 = np.outer(dy, W3)"),
+    ("mlp.py", ["test_oracle_mlp.py"], "dz1 = (dz2 @ W2) * (z1 > 0)", "dz1 = (dz2 @ W2.T) * (z1 > 0)"),
+    ("mlp.py", ["test_oracle_mlp.py"], "dy = 2.0 * r / n", "dy = 2.0 * r"),
+    ("mlp.py", ["test_oracle_mlp.py"], "vh = v / (1 - b2 ** step)", "vh = v"),
+    ("mlp.py", ["test_oracle_mlp.py"], "return p - lr * mh / (np.sqrt(vh) + eps), m, v",
+     "return p - lr * mh / np.sqrt(vh + eps), m, v"),
+    ("mlp.py", ["test_oracle_mlp.py"], "m = b1 * m + (1 - b1) * g", "m = b1 * m + g"),
     ("pcg.py", ["test_oracle_pcg.py"], "p[:, act] = znew + beta * p[:, act]", "p[:, act] = znew - beta * p[:, act]"),
     ("pcg.py", ["test_oracle_pcg.py"], "beta = rznew / rz[act]", "beta = np.sum(r[:, act] * z[:, act], axis=0) / rz[act]"),
     ("pcg.py", ["test_oracle_pcg.py"], "z[:, act] = znew", "pass"),
