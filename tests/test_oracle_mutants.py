@@ -81,6 +81,12 @@ MUTANTS = [
     ("mlp.py", ["test_oracle_mlp.py"], "return p - lr * mh / (np.sqrt(vh) + eps), m, v",
      "return p - lr * mh / np.sqrt(vh + eps), m, v"),
     ("mlp.py", ["test_oracle_mlp.py"], "m = b1 * m + (1 - b1) * g", "m = b1 * m + g"),
+    ("precond.py", ["test_oracle_tables.py"],
+     "Minv[np.ix_(sd.index, sd.index)] += cho_solve(fc, np.eye(len(sd.index)))",
+     "Minv[np.ix_(sd.index, sd.index)] = cho_solve(fc, np.eye(len(sd.index)))"),
+    ("precond.py", ["test_oracle_tables.py"], "z[sd.index] += cho_solve(fc, r[sd.index])",
+     "z[sd.index] = cho_solve(fc, r[sd.index])"),
+    ("precond.py", ["test_oracle_tables.py"], "S = L.T @ Minv @ L", "S = L @ Minv @ L.T"),
     ("pcg.py", ["test_oracle_pcg.py"], "p[:, act] = znew + beta * p[:, act]", "p[:, act] = znew - beta * p[:, act]"),
     ("pcg.py", ["test_oracle_pcg.py"], "beta = rznew / rz[act]", "beta = np.sum(r[:, act] * z[:, act], axis=0) / rz[act]"),
     ("pcg.py", ["test_oracle_pcg.py"], "z[:, act] = znew", "pass"),
