@@ -109,7 +109,8 @@ def _run_one(base, idx, module, pins, orig, planted):
     assert src.count(orig) == 1, (module, orig)
     open(path, "w").write(src.replace(orig, planted))
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-m", "not slow"] +
-                       ["tests/" + p for p in pins], capture_output=True, text=True, cwd=d, timeout=600)
+                       ["tests/" + p for p in pins], capture_output=True, text=True, cwd=d, timeout=600,
+                       env=dict(os.environ, OMP_NUM_THREADS="2", OPENBLAS_NUM_THREADS="2"))
     return r.returncode, r.stdout[-300:]
 
 
