@@ -88,6 +88,17 @@ def measured_traffic():
     return rec["traffic_bytes"]
 
 
+def oracle_solution(args_workload, n):
+    """The stored FP64 oracle solution of column 0 (tests/golden), written by
+    tests/golden/make_solution_fixture.py from the oracle's RS-PCG to 1e-12; None for
+    workloads without one."""
+    import numpy as np
+    if args_workload != "512sq":
+        return None
+    path = os.path.join(ROOT, "tests", "golden", "u_%dsq_cbd_col0.npy" % n)
+    return np.load(path) if os.path.exists(path) else None
+
+
 def train_rank_predictor(cbd, dev):
     """Skeleton-rank MLP trained by the library's kernels on (features, rank) pairs
     of the 64^2 (tol 1e-8), 256^2 Schwarz (tol 1e-6) and 512^2 (tol 1e-6)
@@ -120,7 +131,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="512sq", choices=sorted(WORKLOADS))
-    ap.add_argument("--fp64-cols", type=int, default=2,
+    ap.add_argument("--fp64-cols", type=int, default=8,
                     help="columns solved one at a time to time the plain FP64 form")
     ap.add_argument("--factor-only", action="store_true",
                     help="run one factorization of the workload (no predictor, no PCG) and print its time; "
@@ -189,7 +200,7 @@ def main():
         u, its, rr = cbd.pcg_solve(P, fac, F_rhs, tol=pcg_tol, maxit=200, fft=use_fft)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        return fac, its, rr, t1 - t0, t2 - t1
+        return fac, u, its, rr, t1 - t0, t2 - t1
 
     for w in range(args.warmup):
         step()
@@ -200,7 +211,7 @@ def main():
     tf, ts, its_all, rr_all = [], [], [], []
     t_start = time.perf_counter()
     for k in range(args.steps):
-        fac, its, rr, a, b = step()
+        fac, u_main, its, rr, a, b = step()
         tf.append(a)
         ts.append(b)
         its_all.append(its)
@@ -226,6 +237,16 @@ def main():
         del fac_nm
     pcg_s = float(np.mean(ts))
     n_it = its_all[-1]
+    u_ref = oracle_solution(args.workload, n)
+    u_err = {}
+
+    def uerr(name, u0):
+        """|u - u_oracle| / |u_oracle| over all N entries of column 0."""
+        if u_ref is not None:
+            u0 = u0.double().cpu().numpy()
+            u_err[name] = float(np.linalg.norm(u0 - u_ref) / np.linalg.norm(u_ref))
+
+    uerr("mixed_batched", u_main[0])
 
     if mv_n == 0 and dense:
         # the PCG used FFT products: time one dense product for the roofline record
@@ -241,14 +262,16 @@ def main():
     achieved = mv_flops / mv_avg_s / 1e12 if mv_avg_s else None
 
     pcg_fft_s, its_fft, rr_fft, sketched, bf16 = None, [0], [0.0], None, None
-    f64_factor, f64_pcg, ncols, its64 = None, None, 0, []
+    f64_factor, f64_pcg, ncols, its64, f64_batched = None, None, 0, [], None
     if full:
         # the paper's matvec (FFT on the uniform grid) with the same factors, for comparison
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, its_fft, rr_fft = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200, fft=True)
+        u_fft, its_fft, rr_fft = cbd.pcg_solve(P, fac, F_rhs, tol=1e-10, maxit=200, fft=True)
         torch.cuda.synchronize()
         pcg_fft_s = time.perf_counter() - t0
+        uerr("fft_matvec", u_fft[0])
+        del u_fft
         log("pcg with the FFT matvec: %.3f s, iterations %d-%d" % (pcg_fft_s, min(its_fft), max(its_fft)))
 
         # randomized IDs: the CPQR of a random-sign sketch of each proxy matrix (the scheme of
@@ -259,8 +282,10 @@ def main():
         torch.cuda.synchronize()
         sk_factor = time.perf_counter() - t0
         t0 = time.perf_counter()
-        _, its_sk, rr_sk = cbd.pcg_solve(P, fac_sk, F_rhs, tol=1e-10, maxit=200, fft=use_fft)
+        u_sk, its_sk, rr_sk = cbd.pcg_solve(P, fac_sk, F_rhs, tol=1e-10, maxit=200, fft=use_fft)
         torch.cuda.synchronize()
+        uerr("sketched_id", u_sk[0])
+        del u_sk
         sk_sched = fac_sk.schedule()
         sketched = {"factor_s": sk_factor, "factor_gflops": fac_sk.stats()["flops"] / sk_factor / 1e9,
                     "pcg_s": time.perf_counter() - t0, "n_it": [min(its_sk), max(its_sk)], "max_relres": max(rr_sk),
@@ -278,8 +303,11 @@ def main():
             torch.cuda.synchronize()
             bf_factor = time.perf_counter() - t0
             t0 = time.perf_counter()
-            _, its_bf, rr_bf = cbd.pcg_solve(P, fac_bf, F_rhs, tol=1e-10, maxit=400, flexible=True, fft=use_fft)
+            u_bf, its_bf, rr_bf = cbd.pcg_solve(P, fac_bf, F_rhs, tol=1e-10, maxit=400, flexible=True,
+                                                fft=use_fft)
             torch.cuda.synchronize()
+            uerr("bf16_gemm_flexible", u_bf[0])
+            del u_bf
             bf16 = {"factor_s": bf_factor, "pcg_s": time.perf_counter() - t0, "n_it": [min(its_bf), max(its_bf)],
                     "max_relres": max(rr_bf), "pcg": "flexible"}
             del fac_bf
@@ -297,12 +325,28 @@ def main():
         its64 = []
         ncols = min(args.fp64_cols, nrhs)
         for c in range(ncols):
-            _, it, _ = cbd.pcg_solve(P, fac64, F_rhs[c], tol=1e-10, maxit=200, fft=use_fft)
+            u64, it, _ = cbd.pcg_solve(P, fac64, F_rhs[c], tol=1e-10, maxit=200, fft=use_fft)
             its64.append(it)
+            if c == 0:
+                torch.cuda.synchronize()
+                t_pause = time.perf_counter()
+                uerr("fp64_one_column", u64)
+                t0 += time.perf_counter() - t_pause     # the host-side comparison is not timed
         torch.cuda.synchronize()
         f64_per_col = (time.perf_counter() - t0) / max(ncols, 1)
         f64_pcg = f64_per_col * nrhs if ncols > 0 else float("nan")
         log("fp64 form: factor %.3f s, %.3f s per column" % (f64_factor, f64_per_col))
+        # the same FP64 factors on all right-hand sides at once: separates what the
+        # precision buys (FP32 vs FP64 factors, both batched) from what batching buys
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u64b, its64b, rr64b = cbd.pcg_solve(P, fac64, F_rhs, tol=1e-10, maxit=200, fft=use_fft)
+        torch.cuda.synchronize()
+        f64_batched = {"pcg_s": time.perf_counter() - t0, "n_it": [min(its64b), max(its64b)],
+                       "max_relres": max(rr64b)}
+        uerr("fp64_batched", u64b[0])
+        del u64b
+        log("fp64 factors, batched: %s" % f64_batched)
 
     cpu = None
     if args.cpu_rows < 0:
@@ -363,17 +407,34 @@ def main():
                            "host_syncs_with": sched["host_syncs"], "host_syncs_without": sched_nm["host_syncs"],
                            "mispredicted_boxes": sched["mispredicted"]},
         "fp64_form": {"factor_s": f64_factor, "pcg_s_est": f64_pcg, "cols_timed": ncols,
-                      "n_it": its64,
+                      "n_it": its64, "estimate": True,
                       "note": "PCG time measured on %d columns solved one at a time, scaled to %d"
                               % (ncols, nrhs)} if full else None,
-        "speedup_mixed_vs_fp64": {"pcg": f64_pcg / pcg_s, "factor": f64_factor / factor_s,
-                                  "total": (f64_pcg + f64_factor) / (pcg_s + factor_s)} if full else None,
+        "fp64_factors_batched": f64_batched,
+        "speedup_mixed_vs_fp64": {
+            "total": (f64_pcg + f64_factor) / (pcg_s + factor_s),
+            "pcg": f64_pcg / pcg_s, "factor": f64_factor / factor_s,
+            "precision_pcg": f64_batched["pcg_s"] / pcg_s,
+            "batching_pcg": f64_pcg / f64_batched["pcg_s"],
+            "note": "precision_pcg: FP64 vs FP32 factors, both on all right-hand sides at once; "
+                    "batching_pcg: FP64 factors one column at a time (estimated from the timed "
+                    "columns) vs all at once"} if full else None,
+        "u_err_vs_fp64_oracle": u_err or None,
+        "u_err_note": ("column 0 of each form against the stored FP64 oracle solution "
+                       "(oracle RS-PCG to 1e-12, tests/golden/u_512sq_cbd_col0.npy)") if u_err else None,
         "roofline": {"kernel": "kernel_matvec (FP64, %d RHS)" % nrhs, "bound": "mfma",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic() if args.workload == "512sq" else None,
                      "work": "2 N^2 nrhs FP64 flops per launch on FP64 MFMA (the N^2 kernel "
                              "evaluations run on the VALU and are not counted)"} if achieved else None,
+        "factor_roofline": {"kernel": "rs_factor_batched (whole factorization)", "bound": "fp64",
+                            "achieved": st["flops"] / factor_s / 1e12, "peak": FP64_PEAK_TFLOPS,
+                            "unit": "TFLOP/s", "frac": st["flops"] / factor_s / 1e12 / FP64_PEAK_TFLOPS,
+                            "work": "per-box flop formulas of the ID (FP64), elimination and root "
+                                    "Cholesky over the factor wall time; the ID, which dominates, runs "
+                                    "in FP64, so the FP64 peak is the bound (FP32 peak for the "
+                                    "elimination alone is 157.3)"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -58,7 +58,7 @@ typedef struct cbd_problem_s* cbd_problem;
 typedef struct cbd_partition_s* cbd_partition;
 typedef struct cbd_factor_s* cbd_factor;
 
-/* Options of the RS factorization (Section 3.2). */
+/* Options of the RS factorization (Section 4.2). */
 typedef struct {
     double tol;          /* relative accuracy eps of every ID, (e:id_err) */
     int n_pxy;           /* proxy points on the circle (2D) / sphere (3D) around a box */
@@ -110,7 +110,7 @@ int ie_assemble(int d, int n, int grid, const double* b, const double* c,
 int cbd_problem_free(cbd_problem p);
 
 /* dd_partition - build the domain decomposition of Sections 2.2-2.3 and the
- * box hierarchy RS uses inside every subdomain (Section 3.2) for the n^d grid.
+ * box hierarchy RS uses inside every subdomain (Section 4.2) for the n^d grid.
  * Host only: needs no GPU.
  *  d: 2 or 3; n: points per axis;
  *  m: partitions per axis (n % m == 0); delta: extension layers per side

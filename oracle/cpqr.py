@@ -1,6 +1,6 @@
 """Interpolative decomposition by truncated column-pivoted QR.
 
-Section 3.2, (e:id)/(e:id_err): the columns p of a block are split into
+Section 4.2, (e:id)/(e:id_err): the columns p of a block are split into
 skeletons s and redundant columns r with A_{qr} ~= A_{qs} T.  The paper cites
 Cheng et al. for the ID; that construction is a column-pivoted (Businger-Golub)
 QR: at each step the column with the largest remaining 2-norm is moved to the

@@ -3,7 +3,7 @@
 Sections 2.2-2.3 of the paper: uniform partition (e:dd), one-layer extension,
 Schwarz subdomains (e:first), coloring-based subdomains (e:cbd)/(e:second),
 block-Jacobi subdomains (table t:dd); and the hierarchical partitioning of a
-subdomain used by recursive skeletonization (Section 3.2, around (e:oi) and
+subdomain used by recursive skeletonization (Section 4.2, around (e:oi) and
 (e:schur): leaf regions, merged by spatial proximity until one box is left).
 
 Readings (where the paper leaves a choice):

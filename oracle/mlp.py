@@ -3,7 +3,7 @@
 The paper has no learned component; this is the project's addition: a small MLP
 that maps features of a box (known before its ID: level, box side, active DOFs,
 near-field DOFs, ID tolerance, dimension) to log2(k + 1), k the numerical rank
-the pivoted QR will find (Section 3.2, (e:id)).
+the pivoted QR will find (Section 4.2, (e:id)).
 
 Network: x (F) -> W1 x + b1 -> ReLU -> W2 h + b2 -> ReLU -> W3 h + b3 (scalar).
 Weights are rounded to bfloat16 (round to nearest, ties to even) before use;

@@ -1,6 +1,6 @@
 """Recursive skeletonization (RS) of every subdomain matrix A_i, and its apply.
 
-Section 3.2 of the paper.  For each subdomain (subproblem A_i = R_i A R_i^T,
+Section 4.2 of the paper.  For each subdomain (subproblem A_i = R_i A R_i^T,
 (e:ai)), level by level over the box hierarchy of oracle.dd:
 
 1. for every box p at the level: compress its off-diagonal block with an ID
@@ -16,8 +16,12 @@ Section 3.2 of the paper.  For each subdomain (subproblem A_i = R_i A R_i^T,
 4. one box left: Cholesky of the last Schur complement.
 
 All boxes of a level are compressed against the DOFs active at the start of
-the level (level-parallel reading; the paper proceeds box by box).  Boxes of a
-level touch disjoint index sets, so their order does not matter.
+the level (level-parallel reading).  The paper proceeds box by box: once a box
+is eliminated, its redundant DOFs leave the active set, so a later box of the
+same level sees only the earlier boxes' skeletons in its near field (the
+off-diagonal blocks between boxes are unchanged by an elimination, (e:schur)).
+order="sequential" takes that reading, in the level's box order; the
+level-parallel near fields are supersets of those rows.
 
 The apply (the inverse of the factorization, used for T^{-1} of (e:ad)):
 forward over levels  v_r -= T^T v_s; v_r = G^{-T} v_r; v_s -= E v_r,
@@ -75,10 +79,14 @@ class SubdomainFactor:
 
 
 def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP64,
-                     keep_matrices=False, sketch_seed=None, sub=0):
-    """RS factorization of A_i for one subdomain (Section 3.2).  With sketch_seed set,
+                     keep_matrices=False, sketch_seed=None, sub=0, order="level"):
+    """RS factorization of A_i for one subdomain (Section 4.2).  With sketch_seed set,
     every ID is the randomized one of oracle.sketch (subdomain index `sub` enters
-    the box keys of the random signs)."""
+    the box keys of the random signs).  order: "level" (near fields from the DOFs
+    active at the start of the level) or "sequential" (box by box: the redundant
+    DOFs of boxes already eliminated at this level are no longer active)."""
+    if order not in ("level", "sequential"):
+        raise ValueError("order must be 'level' or 'sequential'")
     if prob.grid != ie.GRID_CELL:
         raise ValueError("RS is defined on the cell-centred grid")
     d, n, h = prob.d, prob.n, prob.h
@@ -95,6 +103,7 @@ def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP6
         boxes = sd.levels[l]
         owner = np.concatenate([np.full(len(a), bi) for bi, a in enumerate(active)])
         allact = np.concatenate(active)
+        alive = np.ones(len(allact), dtype=bool)      # still active (sequential order)
         lvl = []
         for bi, box in enumerate(boxes):
             p = active[bi]
@@ -103,7 +112,7 @@ def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP6
             L = int(np.max(hi - lo))
             # near field: other boxes' active DOFs strictly inside the proxy surface,
             # tested exactly in half-cell units: |2j+1-(lo+hi)|^2 < (2 ratio L)^2
-            cand = allact[owner != bi]
+            cand = allact[(owner != bi) & alive]
             off = 2 * J[cand] + 1 - (lo + hi)[None, :]
             near = cand[np.sum(off * off, axis=1) < (2.0 * proxy_ratio * L) ** 2]
             ctr = 0.5 * (lo + hi) * h
@@ -143,6 +152,8 @@ def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP6
                 E = np.zeros((k, 0))
                 Bss = Ass.copy()
             lvl.append(BoxFactor(p[ps], p[pr], T, G, E, Bss))
+            if order == "sequential":
+                alive[np.isin(allact, p[pr])] = False
         f.levels.append(lvl)
         # next level: union of children's skeletons; matrix per (e:schur)
         new_active, new_mat = [], []
@@ -177,10 +188,11 @@ def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP6
 class RSPreconditioner:
     """T^{-1} = sum_i R_i^T A_i^{-1} R_i (e:ad) with A_i^{-1} applied through RS factors."""
 
-    def __init__(self, prob, part, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP64, sketch_seed=None):
+    def __init__(self, prob, part, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP64, sketch_seed=None,
+                 order="level"):
         self.prob, self.part = prob, part
         self.subs = [factor_subdomain(prob, part, sd, tol, n_pxy, proxy_ratio, tie,
-                                      sketch_seed=sketch_seed, sub=i)
+                                      sketch_seed=sketch_seed, sub=i, order=order)
                      for i, sd in enumerate(part.subdomains)]
 
     def apply_sub(self, i, v):

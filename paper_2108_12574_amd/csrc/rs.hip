@@ -1,4 +1,4 @@
-// Recursive-skeletonization kernels (Section 3.2): proxy/near-field matrices,
+// Recursive-skeletonization kernels (Section 4.2): proxy/near-field matrices,
 // truncated column-pivoted QR (the ID), box-matrix assembly (e:schur),
 // compress-then-eliminate ((e:al), (e:alu), (e:b)), and the level sweeps of
 // the factor apply.  Every kernel processes a whole level batch: one

@@ -1,4 +1,4 @@
-"""Pins of the oracle's interpolative decomposition (Section 3.2, (e:id)/(e:id_err))."""
+"""Pins of the oracle's interpolative decomposition (Section 4.2, (e:id)/(e:id_err))."""
 import numpy as np
 import pytest
 import scipy.linalg

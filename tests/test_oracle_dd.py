@@ -1,4 +1,4 @@
-"""Pins of the oracle's decompositions (Sections 2.2-2.3) and box hierarchy (Section 3.2)."""
+"""Pins of the oracle's decompositions (Sections 2.2-2.3) and box hierarchy (Section 4.2)."""
 import numpy as np
 import pytest
 

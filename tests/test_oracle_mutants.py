@@ -5,9 +5,11 @@ plausible mistake in one oracle module (a dropped term, a flipped sign, a
 wrong index, a transposed operand, a wrong constant), and runs that module's
 pin files there.  The pins pass on the real oracle, so each run must fail.
 
-Left out on purpose: the sign of the Householder vector in the CPQR. Either
-sign gives a valid reflector, and T = R11^{-1} R12, the pivots and the ranks
-do not depend on it; only the rounding does.
+Left out on purpose, being equivalent: the sign of the Householder vector in
+the CPQR (either sign gives a valid reflector, and T = R11^{-1} R12, the pivots
+and the ranks do not depend on it; only the rounding does), and the value the
+FFT product's periodic kernel takes at offset n (an output point inside the grid
+never reaches it: i - j stays within [-(n-1), n-1]).
 """
 import concurrent.futures
 import os
@@ -57,6 +59,12 @@ MUTANTS = [
      "Yp = ie.kernel(d, np.sqrt(np.sum(diff * diff, axis=2)))"),
     ("rs.py", ["test_oracle_rs.py"], "Y = np.vstack([Yn, Yp])", "Y = Yp"),
     ("rs.py", ["test_oracle_rs.py"], "mat[blk] = lvl[ca].Bss", "mat[blk] = prob.block(gidx[sks[a]], gidx[sks[a]])"),
+    ("rs.py", ["test_oracle_rs.py"], "phi = j * (np.pi * (3.0 - np.sqrt(5.0)))", "phi = j * 0.05"),
+    ("rs.py", ["test_oracle_rs.py"], "z = 1.0 - (2.0 * j + 1.0) / n_pxy", "z = 1.0 - (j + 0.5) / n_pxy"),
+    ("rs.py", ["test_oracle_rs.py"], "alive[np.isin(allact, p[pr])] = False", "pass"),
+    ("fftmv.py", ["test_oracle_fftmv.py"], "v = (prob.c * Xc[:, c]).reshape(shape)", "v = Xc[:, c].reshape(shape)"),
+    ("fftmv.py", ["test_oracle_fftmv.py"], "Y[:, c] = prob.b * y + prob.b * prob.c * prob.a_self * Xc[:, c]",
+     "Y[:, c] = prob.b * y + prob.b * prob.b * prob.a_self * Xc[:, c]"),
     ("sketch.py", ["test_oracle_sketch.py"], "z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)",
      "z = (z ^ (z >> np.uint64(31))) * np.uint64(0xBF58476D1CE4E5B9)"),
     ("sketch.py", ["test_oracle_sketch.py"], "if k <= ell - OVER:", "if k <= ell:"),

@@ -127,3 +127,19 @@ def test_pcg_iterations_exact_subsolves(row):
         u, it, rr = pcg.pcg(lambda X: A @ X, P.apply, f, tol=1e-12, maxit=400)
         assert rr <= 1e-12
         assert abs(it - row[key]) <= 2, (key, it, row[key])
+
+
+@pytest.mark.parametrize("row", GOLD["t_it_m48_3d"]["rows"], ids=lambda r: "n%d" % r["n"])
+def test_pcg_iterations_exact_subsolves_3d(row):
+    # 3D half of t:it_m48 (cell-centred grid).  CBD partitions are 4 points wide per
+    # axis (the reading recorded with the table entry)
+    n = row["n"]
+    prob = ie.Problem(3, n)
+    A = prob.dense()
+    f = synth.rhs(prob.N, 1, seed=0)[0]
+    w = GOLD["t_it_m48_3d"]["cbd_points_per_partition_axis"]
+    for key, mode, m in [("jacobi", dd.JACOBI, 2), ("schwarz", dd.SCHWARZ, 2), ("cbd", dd.CBD, n // w)]:
+        P = precond.ExactPreconditioner(prob, dd.Partition(3, n, m, 1, mode), A)
+        u, it, rr = pcg.pcg(lambda X: A @ X, P.apply, f, tol=1e-12, maxit=400)
+        assert rr <= 1e-12
+        assert abs(it - row[key]) <= 2, (key, it, row[key])
