@@ -125,6 +125,74 @@ def train_rank_predictor(cbd, dev):
     return net
 
 
+# Size series for the complexity study of Section 4.4: (n, m) pairs.  "sublinear": m
+# is the divisor of n closest (in log) to n^(6/7) in 2D (M ~ N^(6/7)) or n^(3/4) in 3D
+# (M ~ N^(3/4)), the partition counts of the corollary th:optimal; "fixed": N/M = 64
+# (2D) and 512 (3D), the layouts of the paper's weak-scaling tables.  Settings of those
+# tables: tol 1e-3, b = c = 1, FP64 factors, FFT products, PCG to 1e-10.
+SERIES = {
+    "2d": dict(d=2, npxy=64, sublinear=[(120, 60), (240, 120), (480, 240), (960, 320), (1920, 640)],
+               fixed=[(128, 16), (256, 32), (512, 64), (1024, 128), (2048, 256)],
+               theory={"sublinear": {"t_f": 9 / 7, "m_f": 8 / 7}}),
+    "3d": dict(d=3, npxy=256, sublinear=[(16, 8), (24, 12), (32, 16), (48, 16), (96, 32)],
+               fixed=[(32, 4), (64, 8), (128, 16)],
+               theory={"sublinear": {"t_f": 3 / 2, "m_f": 5 / 4}}),
+}
+
+
+def run_series(kind):
+    """One JSON line: per size N, M, S, t_f, m_f, n_it, t_pcg for both layouts, and the
+    least-squares exponents of t_f and m_f against N."""
+    import numpy as np
+    import torch
+
+    import paper_2108_12574_amd as cbd
+    import synth
+
+    dev = torch.device("cuda:0")
+    cfg = SERIES[kind]
+    d = cfg["d"]
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    out = {"series": kind, "settings": "CBD, overlap 1, tol 1e-3, %d proxy points, b = c = 1, FP64 factors, "
+                                      "1 RHS f ~ N(0,1) seed 0, FFT products, PCG to 1e-10" % cfg["npxy"],
+           "theory": cfg["theory"], "rows": {}, "fit": {}}
+    for layout in ("sublinear", "fixed"):
+        rows = []
+        for n, m in cfg[layout]:
+            N = n ** d
+            P = cbd.Problem(d, n, device=dev)
+            part = cbd.Partition(P, m, 1, cbd.MODE_CBD, 0)
+            f = torch.tensor(synth.rhs(N, 1, seed=0), device=dev)
+            P.fft_prepare(max_pairs=1)
+            opts = dict(tol=1e-3, n_pxy=cfg["npxy"], proxy_ratio=1.5, precision=cbd.PREC_FP64, apply_rhs=1,
+                        sketch_seed=1 if d == 3 else None)
+            fac = cbd.Factor(P, part, **opts)            # warm-up; sizes the workspace
+            hint, ws = fac.ranks.cpu(), fac.ws
+            del fac
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fac = cbd.Factor(P, part, rank_hint=hint, ws=ws, **opts)
+            torch.cuda.synchronize()
+            t_f = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            u, it, rr = cbd.pcg_solve(P, fac, f[0], tol=1e-10, maxit=300, fft=True)
+            torch.cuda.synchronize()
+            t_pcg = time.perf_counter() - t0
+            st = fac.stats()
+            row = {"n": n, "m": m, "N": N, "M": m ** d, "S_max": max(st["S"]), "t_f": t_f,
+                   "m_f_bytes": st["bytes"], "flops": st["flops"], "n_it": it, "relres": rr, "t_pcg": t_pcg}
+            log(layout, row)
+            rows.append(row)
+            del fac, u, P, part
+            torch.cuda.empty_cache()
+        out["rows"][layout] = rows
+        lN = np.log([r["N"] for r in rows])
+        out["fit"][layout] = {q: float(np.polyfit(lN, np.log([r[k] for r in rows]), 1)[0])
+                              for q, k in (("t_f", "t_f"), ("m_f", "m_f_bytes"), ("flops", "flops"),
+                                           ("M", "M"))}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,11 +207,18 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=-1,
                     help="rows of the oracle's dense matvec timed for the CPU baseline (0: skip; "
                          "-1: about 12 s of host work, 16384 rows at 512^2 with 64 RHS)")
+    ap.add_argument("--series", choices=sorted(SERIES),
+                    help="instead of the benchmark line: factor and solve a series of grid sizes with the "
+                         "partition count growing sublinearly (Section 4.4) and with N/M fixed, and fit "
+                         "the exponents of t_f and m_f in N")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the "
               "path is not implemented", file=sys.stderr)
         sys.exit(2)
+    if args.series:
+        run_series(args.series)
+        return
 
     import numpy as np
     import torch
@@ -192,14 +267,26 @@ def main():
     mlp_train_s = time.perf_counter() - t0
     log("rank predictor trained in %.2f s" % mlp_train_s)
 
+    # The factor's device workspace and the PCG's are allocated once, before the timed
+    # steps (sized by a first factorization), so that no step allocates device memory.
+    fac0 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=sk_seed,
+                      apply_rhs=nrhs)
+    ws_factor = torch.empty(int(fac0.ws_used * 1.05) + (1 << 20), dtype=torch.uint8, device=dev)
+    del fac0
+    ws_pcg = cbd.pcg_workspace(P, nrhs)
+    box = {"fac": None}
+
     def step():
+        box["fac"] = None           # the previous factor views ws_factor: release it first
         t0 = time.perf_counter()
-        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=sk_seed)
+        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=sk_seed,
+                         apply_rhs=nrhs, ws=ws_factor)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        u, its, rr = cbd.pcg_solve(P, fac, F_rhs, tol=pcg_tol, maxit=200, fft=use_fft)
+        u, its, rr = cbd.pcg_solve(P, fac, F_rhs, tol=pcg_tol, maxit=200, fft=use_fft, ws=ws_pcg)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        box["fac"] = fac
         return fac, u, its, rr, t1 - t0, t2 - t1
 
     for w in range(args.warmup):

@@ -12,9 +12,12 @@
  *    vectors are FP64 device memory.
  *  - "device" pointers are HIP device allocations owned by the caller; the
  *    library keeps no reference to them after the call returns, except where a
- *    handle documents that it views them (cbd_problem views its four arrays).
+ *    handle documents that it views them (cbd_problem views its four arrays and
+ *    the FFT workspace; cbd_factor views its workspace).  The library allocates
+ *    no device memory: every device array, workspaces included, comes from the
+ *    caller, and *_workspace* calls give the sizes.
  *  - Handles are host objects owned by the library and released with the
- *    matching *_free call.  A factor owns the device memory holding the factors.
+ *    matching *_free call.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue work
  *    on it and return; calls that return host results (ranks, iteration counts,
  *    statistics) synchronize the stream first.
@@ -35,7 +38,9 @@ extern "C" {
 #define CBD_EARG (-1)        /* invalid argument (sizes, modes, NULL pointers) */
 #define CBD_EHIP (-2)        /* a HIP runtime call failed */
 #define CBD_ENOTSPD (-3)     /* a Cholesky factorization met a non-positive pivot */
-#define CBD_ENOMEM (-4)      /* device or host allocation failed */
+#define CBD_ENOMEM (-4)      /* a host allocation failed */
+#define CBD_EWORKSPACE (-5)  /* the caller's workspace is too small (the message and, where the
+                                call has one, an out-parameter give the bytes needed) */
 #define CBD_WNOTCONV 1       /* PCG stopped at maxit before reaching tol */
 
 #define CBD_GRID_CELL 0      /* x_t = (j_t + 1/2)/n (Section 2.1) */
@@ -79,7 +84,9 @@ typedef struct {
                             takes the truncated CPQR of Z = Omega Y, Omega ell x m of random
                             signs, ell = ceil(3 n_p / 5) + 8, when ell < min(m, n_p); a sketch
                             whose rank exceeds ell - 8 is discarded for the deterministic ID.
-                            0: deterministic IDs everywhere */
+                            With a predicted rank k_p (rank predictor or rank_hint), a first
+                            sketch of 4 k_p + 32 rows is tried when smaller, and kept when its
+                            rank k <= rows / 4.  0: deterministic IDs everywhere */
     unsigned long long sketch_seed;  /* seed of the random signs: the splitmix64 output
                             function of seed + key G1 + i G2 + rowkey G3 (mod 2^64), sign
                             from its top bit; key = (subdomain << 40) | (level << 32) | box,
@@ -88,8 +95,12 @@ typedef struct {
                             G3 = 0x8CB92BA72F3D8DD7 */
     size_t workspace_bytes;  /* bound on the factorization's scratch per level (proxy
                             matrices, elimination work, FP64 T, box matrices): a level's boxes
-                            are processed in chunks of consecutive boxes within it; 0: 64 GiB.
-                            Factor storage is not counted */
+                            are processed in chunks of consecutive boxes within it whose scratch
+                            fits this bound and what is left of the workspace; 0: no bound
+                            beyond the workspace.  Factor storage is not counted */
+    int apply_rhs;       /* right-hand sides one pass of rs_apply handles (the factor's apply
+                            buffers hold this many columns; more columns are applied in blocks
+                            of this size); 0: 64 */
 } cbd_rs_opts;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -134,19 +145,50 @@ int dd_subdomain_info(cbd_partition q, int i, int* size, int* n_leaves, int* roo
 int dd_subdomain_index(cbd_partition q, int i, int* index);
 int dd_level_boxes(cbd_partition q, int i, int level, int* n_boxes, int* lohi, int* parent);
 
+/* rs_factor_rank_count - number of compressed boxes of a factorization of this
+ * partition with these options: the length of rank_hint and ranks_out below.  Boxes
+ * are counted level by level (leaves first); within a level subdomain by subdomain,
+ * and within a subdomain in the partition's box order (dd_level_boxes).  A
+ * subdomain contributes at level l when its root level is above l.  Host only. */
+int rs_factor_rank_count(cbd_partition q, const cbd_rs_opts* opts, int* count);
+
+/* rs_factor_workspace - bytes of workspace to pass to rs_factor_batched.  With
+ * rank_hint (host, rs_factor_rank_count ints: ranks of an earlier factorization of
+ * the same layout, e.g. its ranks_out) the factor storage is exact for those ranks;
+ * without, a box of n_p DOFs is guessed to keep a log10(1/tol) n_p^((d-1)/d)
+ * skeletons (a = 0.55 in 2D, 0.4 in 3D).  Scratch is estimated for the largest
+ * level, capped by opts->workspace_bytes.  A workspace that turns out
+ * too small makes rs_factor_batched fail with CBD_EWORKSPACE and report what it
+ * needed; more scratch than the estimate only means fewer chunks.  Host only. */
+int rs_factor_workspace(cbd_problem p, cbd_partition q, const cbd_rs_opts* opts,
+                        const int* rank_hint, size_t* bytes);
+
 /* rs_factor_batched - RS factorization of every subdomain matrix A_i = R_i A R_i^T
- * (e:ai) of the partition, level by level: at each level every box of every
- * subdomain is compressed with an ID of its proxy/near-field matrix ((e:id), the
+ * (e:ai) of the partition, level by level (Section 4.2): at each level every box of
+ * every subdomain is compressed with an ID of its proxy/near-field matrix ((e:id), the
  * proxy trick) and eliminated ((e:al), (e:alu), (e:b)); the last Schur complement
  * (e:schur) of each subdomain is factored by Cholesky.  All boxes of one level,
  * across all subdomains, are processed by the same kernel launches.
  * The factor keeps (per box) skeleton/redundant index lists, T, E = B_sr G^{-1},
- * G^{-1} (B_rr = G^T G) and B_ss, in opts->precision.  It allocates its own
- * device memory (released by rs_factor_free) and synchronizes `stream` once per
- * level to read the ranks.  The partition must be of the problem's grid (same d
- * and n, cell-centred points).  Errors: CBD_ENOTSPD names the level and box. */
+ * G^{-1} (B_rr = G^T G) and B_ss, in opts->precision.
+ *  rank_hint: host, rs_factor_rank_count ints, or NULL: expected ranks (for example
+ *    ranks_out of an earlier factorization); they schedule the pivoted QR (its first
+ *    run of steps without host checks, the row-compression choice) and override the
+ *    rank predictor for that purpose.  Ranks are decided by the QR alone.
+ *  ws, ws_bytes: device workspace, 256-byte aligned, caller-owned; the factor views
+ *    it (factor arrays, the partition's index maps, the apply's buffers), so it must
+ *    outlive the factor.  Its contents on entry do not matter.
+ *  ranks_out: device, rs_factor_rank_count ints, or NULL: the rank of every
+ *    compressed box.
+ *  ws_used: host, or NULL: bytes of ws the factorization used (its high-water mark);
+ *    on CBD_EWORKSPACE, that plus the request that did not fit (a lower bound on the
+ *    bytes needed).
+ * Synchronizes `stream` once per level to read the ranks.  The partition must be of
+ * the problem's grid (same d and n, cell-centred points).  Errors: CBD_ENOTSPD names
+ * the level and box; CBD_EWORKSPACE when ws is too small. */
 int rs_factor_batched(cbd_problem p, cbd_partition q, const cbd_rs_opts* opts,
-                      void* stream, cbd_factor* out);
+                      const int* rank_hint, void* ws, size_t ws_bytes, int* ranks_out,
+                      size_t* ws_used, void* stream, cbd_factor* out);
 int rs_factor_free(cbd_factor f);
 
 /* Statistics of a factor: per subdomain DOFs at the last level (S_i, array of D
@@ -195,9 +237,11 @@ int rs_factor_root(cbd_factor f, int i, int* S, int* idx, double* Ginv);
  *  the stepped QR, boxes whose rank exceeded the predicted budget, the mean
  *  absolute rank prediction error (0 without a predictor), the number of batches
  *  whose proxy matrices were row-compressed before the pivoted QR, the boxes whose
- *  ID came from a sketch and those whose sketch saturated, and the number of level
- *  chunks processed (the number of levels when no level was split).  Any output may
- *  be NULL. */
+ *  ID came from a sketch and those whose sketch saturated, the number of level
+ *  chunks processed (the number of levels when no level was split), and, of the
+ *  sketched boxes, those whose ID came from the rank-sized first sketch (4 k_p + 32
+ *  rows for a predicted rank k_p, kept when k <= rows / 4) and those whose rank-sized
+ *  sketch was not kept.  Any output may be NULL. */
 #define CBD_MLP_FEATURES 6
 #define CBD_MLP_WIDTH 64
 int rank_mlp_params(void);
@@ -210,13 +254,22 @@ int rank_mlp_adam(float* params, const float* grad, float* m, float* v, int step
 int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* X, int* k);
 int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
                        double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks,
-                       int* chunks);
+                       int* chunks, int* sketched_pred, int* sketch_pred_rejected);
 
 /* rs_apply - z = T^{-1} r = sum_i R_i^T A_i^{-1} R_i r, (e:ad), with every A_i^{-1}
  * applied through its RS factor: gather, forward sweep over levels, root solve,
  * backward sweep, and a deterministic scatter-add over overlapping subdomains.
+ * Columns are processed in blocks of opts.apply_rhs.  Uses the factor's workspace:
+ * calls on one factor must not overlap in time.
  *  r, z: device, N x nrhs column-major FP64 (may not alias). */
 int rs_apply(cbd_factor f, int nrhs, const double* r, double* z, void* stream);
+
+/* rs_apply_sub - one term of that sum: z = R_i^T A_i^{-1} R_i r for subdomain i
+ * ((e:ai), (e:ad)); z is zero outside Omega_i.  With A_i^{-1} exact, P_i = R_i^T
+ * A_i^{-1} R_i A fixes every vector supported in Omega_i (lemma l:subdomain of
+ * Section 3.2); with the RS factor, up to its accuracy.  Arguments as rs_apply;
+ * 0 <= i < number of subdomains. */
+int rs_apply_sub(cbd_factor f, int i, int nrhs, const double* r, double* z, void* stream);
 
 /* kernel_matvec - y = A x with A of ie_assemble, entries generated on the fly in
  * FP64 (the dense product; the paper uses FFTs for it, Section 5).
@@ -228,21 +281,25 @@ int kernel_matvec(cbd_problem p, int nrhs, const double* x, double* y, void* str
  * with g[delta] = K(spacing |delta|) (g[0] = 0), computed by circulant embedding
  * in a P^d grid (P the smallest power of two >= 2n - 1, at most 4096); the
  * diagonal term is added exactly.  Two right-hand sides share one complex
- * transform.  cbd_fft_prepare allocates the embedded kernel's transform and a
- * workspace of max_pairs complex P^d arrays (owned by the problem, freed with
- * it) and synchronizes `stream`; kernel_matvec_fft then takes the same x, y as
- * kernel_matvec (N x nrhs column-major, FP64, no aliasing). */
-int cbd_fft_prepare(cbd_problem p, int max_pairs, void* stream);
+ * transform.  cbd_fft_prepare lays out, in ws (device, 256-byte aligned, at least
+ * cbd_fft_workspace_bytes(d, n, max_pairs) bytes, caller-owned; the problem views
+ * it until the next cbd_fft_prepare or cbd_problem_free), the embedded kernel's
+ * transform, the twiddle factors and max_pairs complex P^d work arrays, and
+ * synchronizes `stream`; kernel_matvec_fft then takes the same x, y as
+ * kernel_matvec (N x nrhs column-major, FP64, no aliasing).  Calls of
+ * kernel_matvec_fft on one problem must not overlap in time (shared work arrays). */
+size_t cbd_fft_workspace_bytes(int d, int n, int max_pairs);
+int cbd_fft_prepare(cbd_problem p, int max_pairs, void* ws, size_t ws_bytes, void* stream);
 int kernel_matvec_fft(cbd_problem p, int nrhs, const double* x, double* y, void* stream);
 
 /* cbd_autotune_matvec - choose the matvec's tile shape (rows per wave: 16, 32 or
  * 64) for this problem and nrhs by timing each candidate with HIP events on
  * `stream`; later kernel_matvec calls with the
  * same number of 16-column right-hand-side blocks use it.  Each candidate runs on
- * the first min(grid, 1024) workgroups.  Allocates and frees
- * two temporary N x min(nrhs, 64) device arrays.  *choice (may be NULL)
- * receives the rows per wave / 16. */
-int cbd_autotune_matvec(cbd_problem p, int nrhs, void* stream, int* choice);
+ * the first min(grid, 1024) workgroups.  x, y: device scratch of N x min(nrhs, 64)
+ * doubles each (overwritten; distinct).  *choice (may be NULL) receives the rows
+ * per wave / 16. */
+int cbd_autotune_matvec(cbd_problem p, int nrhs, double* x, double* y, void* stream, int* choice);
 
 /* pcg_solve - preconditioned CG (Section 5) on A u = f for nrhs independent
  * right-hand sides: u0 = 0, stop a column when ||r||_2/||f||_2 <= tol (the

@@ -76,15 +76,17 @@ class SubdomainFactor:
         self.root_G = None     # upper Cholesky factor of the last Schur complement
         self.root_A = None
         self.sketched = 0      # boxes whose ID came from a sketch
+        self.sketched_pred = 0 # of those, from the rank-sized first sketch
 
 
 def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP64,
-                     keep_matrices=False, sketch_seed=None, sub=0, order="level"):
+                     keep_matrices=False, sketch_seed=None, sub=0, order="level", rank_pred=None):
     """RS factorization of A_i for one subdomain (Section 4.2).  With sketch_seed set,
     every ID is the randomized one of oracle.sketch (subdomain index `sub` enters
     the box keys of the random signs).  order: "level" (near fields from the DOFs
     active at the start of the level) or "sequential" (box by box: the redundant
-    DOFs of boxes already eliminated at this level are no longer active)."""
+    DOFs of boxes already eliminated at this level are no longer active).  rank_pred:
+    {(level, box): predicted rank} for the first, rank-sized sketch of oracle.sketch."""
     if order not in ("level", "sequential"):
         raise ValueError("order must be 'level' or 'sequential'")
     if prob.grid != ie.GRID_CELL:
@@ -126,9 +128,11 @@ def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP6
                 k, perm, T = interp_decomp(Y, tol, tie)
             else:
                 rowkeys = np.concatenate([gidx[near], prob.N + np.arange(len(dirs))])
+                k_pred = None if rank_pred is None else rank_pred.get((l, bi))
                 k, perm, T, used = sketch.interp_decomp_sketched(
-                    Y, tol, sketch_seed, sketch.box_key(sub, l, bi), rowkeys, tie)
-                f.sketched += int(used)
+                    Y, tol, sketch_seed, sketch.box_key(sub, l, bi), rowkeys, tie, k_pred=k_pred)
+                f.sketched += int(used > 0)
+                f.sketched_pred += int(used == 2)
             ps, pr = perm[:k], perm[k:]
             App = boxmat[bi]
             Ass = App[np.ix_(ps, ps)]
@@ -189,10 +193,12 @@ class RSPreconditioner:
     """T^{-1} = sum_i R_i^T A_i^{-1} R_i (e:ad) with A_i^{-1} applied through RS factors."""
 
     def __init__(self, prob, part, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP64, sketch_seed=None,
-                 order="level"):
+                 order="level", rank_pred=None):
+        """rank_pred: {(subdomain, level, box): predicted rank} or None (sketched IDs only)."""
         self.prob, self.part = prob, part
+        per_sub = lambda i: None if rank_pred is None else {(l, b): k for (j, l, b), k in rank_pred.items() if j == i}
         self.subs = [factor_subdomain(prob, part, sd, tol, n_pxy, proxy_ratio, tie,
-                                      sketch_seed=sketch_seed, sub=i, order=order)
+                                      sketch_seed=sketch_seed, sub=i, order=order, rank_pred=per_sub(i))
                      for i, sd in enumerate(part.subdomains)]
 
     def apply_sub(self, i, v):

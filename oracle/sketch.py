@@ -15,6 +15,12 @@ probability.  Readings (the paper gives no details):
 * the CPQR of Z uses the same rank and tie rules as the deterministic ID;
 * a sketch whose rank k exceeds ell - 8 is taken as saturated (the sketch may
   have missed part of the range): the box falls back to the deterministic ID;
+* with a predicted rank k_p of the box (from the rank predictor, or the ranks of
+  an earlier factorization), a first sketch of ell_p = 4 k_p + 32 rows is tried
+  when that is below the shape-based size; its ID is kept if k <= ell_p / 4 (an
+  oversampling of four, after Halko, Martinsson and Tropp's analysis of the
+  range finder), else the box goes on to the shape-based sketch.  The first
+  ell_p rows of Omega are the same in both (the signs depend on the row index);
 * the signs are a counter-based hash, so that any implementation can draw the
   same Omega: sign(seed, box key, i, row key) is the top bit of the splitmix64
   output function (Steele, Lea and Flood, OOPSLA 2014) applied to
@@ -62,14 +68,33 @@ def sketch_size(m, n):
     return ell if ell < min(m, n) else 0
 
 
-def interp_decomp_sketched(Y, tol, seed, key, rowkeys, tie=TIE_FP64):
-    """ID of the columns of Y from the CPQR of Omega Y.  Returns (k, perm, T, sketched)."""
+PRED_FACTOR, PRED_EXTRA = 4, 32
+
+
+def predicted_sketch_size(m, n, k_pred):
+    """ell from a predicted rank, or 0 when it would not be below the shape-based size."""
+    ell_shape = sketch_size(m, n)
+    ell = PRED_FACTOR * max(int(k_pred), 0) + PRED_EXTRA
+    return ell if ell_shape and ell < ell_shape else 0
+
+
+def interp_decomp_sketched(Y, tol, seed, key, rowkeys, tie=TIE_FP64, k_pred=None):
+    """ID of the columns of Y from the CPQR of Omega Y.  Returns (k, perm, T, how) with how
+    0 (deterministic ID), 1 (shape-based sketch) or 2 (rank-sized sketch).
+    k_pred: a predicted rank of the box, or None."""
     m, n = Y.shape
+    if k_pred is not None:
+        ell = predicted_sketch_size(m, n, k_pred)
+        if ell:
+            Z = signs(seed, key, ell, rowkeys) @ Y
+            k, perm, T = interp_decomp(Z, tol, tie)
+            if PRED_FACTOR * k <= ell:
+                return k, perm, T, 2
     ell = sketch_size(m, n)
     if ell:
         Z = signs(seed, key, ell, rowkeys) @ Y
         k, perm, T = interp_decomp(Z, tol, tie)
         if k <= ell - OVER:
-            return k, perm, T, True
+            return k, perm, T, 1
     k, perm, T = interp_decomp(Y, tol, tie)
-    return k, perm, T, False
+    return k, perm, T, 0

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (GRID_CELL, GRID_NODE, MODE_CBD, MODE_JACOBI, MODE_SCHWARZ, PREC_BF16GEMM,
                    PREC_FP32, PREC_FP64, ROWS_ALWAYS, ROWS_AUTO, ROWS_NEVER, CbdError, check, lib)
 
-__all__ = ["Problem", "Partition", "Factor", "RankMLP", "pcg_solve", "timing", "CbdError",
+__all__ = ["Problem", "Partition", "Factor", "RankMLP", "pcg_solve", "pcg_workspace", "timing", "CbdError",
            "GRID_CELL", "GRID_NODE", "MODE_JACOBI", "MODE_SCHWARZ", "MODE_CBD",
            "PREC_FP64", "PREC_FP32", "PREC_BF16GEMM", "ROWS_AUTO", "ROWS_NEVER", "ROWS_ALWAYS"]
 
@@ -79,8 +79,11 @@ class Problem:
         return y[0] if one else y
 
     def fft_prepare(self, max_pairs=8):
-        """Set up the FFT matvec (cbd_fft_prepare)."""
-        check(lib().cbd_fft_prepare(self.handle, max_pairs, _stream(self.device)))
+        """Set up the FFT matvec (cbd_fft_prepare) in a workspace this object keeps."""
+        nb = lib().cbd_fft_workspace_bytes(self.d, self.n, max_pairs)
+        ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        check(lib().cbd_fft_prepare(self.handle, max_pairs, _ptr(ws), nb, _stream(self.device)))
+        self._fft_ws = ws
 
     def matvec_fft(self, x):
         """y = A x by FFT (kernel_matvec_fft); needs fft_prepare()."""
@@ -93,7 +96,12 @@ class Problem:
     def autotune_matvec(self, nrhs):
         """Pick the matvec tile shape for nrhs right-hand sides (cbd_autotune_matvec)."""
         ch = ctypes.c_int()
-        check(lib().cbd_autotune_matvec(self.handle, nrhs, _stream(self.device), ctypes.byref(ch)))
+        cols = min(nrhs, 64)
+        x = torch.empty(cols, self.N, dtype=torch.float64, device=self.device)
+        y = torch.empty_like(x)
+        check(lib().cbd_autotune_matvec(self.handle, nrhs, _ptr(x), _ptr(y), _stream(self.device),
+                                        ctypes.byref(ch)))
+        torch.cuda.synchronize(self.device)
         return ch.value
 
     def __del__(self, _free=_free):   # bound now: module globals are gone at shutdown
@@ -143,21 +151,59 @@ class Partition:
 
 
 class Factor:
-    """RS factors of all subdomain matrices (rs_factor_batched) and T^{-1} (rs_apply)."""
+    """RS factors of all subdomain matrices (rs_factor_batched) and T^{-1} (rs_apply).
+
+    The factor lives in a device workspace this object owns (a uint8 tensor, or `ws`
+    if given), sized by rs_factor_workspace from `rank_hint` (ranks of an earlier
+    factorization of the same layout, e.g. another Factor's `ranks`); if the ranks
+    outgrow it, the library reports the bytes it needed and the call is repeated
+    with more (up to three times).  `ranks` (device int32) holds every compressed box's
+    rank in rs_factor_rank_count order."""
 
     def __init__(self, problem, partition, tol=1e-6, n_pxy=64, proxy_ratio=1.5,
                  precision=PREC_FP64, exact=False, mlp=None, row_compression=ROWS_AUTO, sketch_seed=None,
-                 workspace_bytes=0):
+                 workspace_bytes=0, apply_rhs=64, rank_hint=None, ws=None):
         self.problem, self.partition = problem, partition
         self.precision = precision
         opts = _lib.RSOpts(tol, n_pxy, proxy_ratio, precision, 1 if exact else 0,
                            mlp.params.data_ptr() if mlp is not None else None, row_compression,
                            0 if sketch_seed is None else 1, 0 if sketch_seed is None else int(sketch_seed),
-                           int(workspace_bytes))
-        h = ctypes.c_void_p()
-        check(lib().rs_factor_batched(problem.handle, partition.handle, ctypes.byref(opts),
-                                      _stream(problem.device), ctypes.byref(h)))
+                           int(workspace_bytes), int(apply_rhs))
+        self.opts = opts
+        cnt = ctypes.c_int()
+        check(lib().rs_factor_rank_count(partition.handle, ctypes.byref(opts), ctypes.byref(cnt)))
+        self.n_ranks = cnt.value
+        hint = None
+        if rank_hint is not None:
+            import numpy as np
+            hint = np.ascontiguousarray(torch.as_tensor(rank_hint).cpu().numpy(), dtype=np.int32)
+            if hint.size != self.n_ranks:
+                raise ValueError("rank_hint needs %d entries" % self.n_ranks)
+        hp = hint.ctypes.data_as(ctypes.c_void_p) if hint is not None else None
+        self.ranks = torch.zeros(max(self.n_ranks, 1), dtype=torch.int32, device=problem.device)
+        if ws is None:
+            nb = ctypes.c_size_t()
+            check(lib().rs_factor_workspace(problem.handle, partition.handle, ctypes.byref(opts), hp,
+                                            ctypes.byref(nb)))
+            # an estimate above the free device memory is cut to it: levels then run in chunks
+            free = torch.cuda.mem_get_info(problem.device)[0]
+            ws = torch.empty(int(min(nb.value, 0.9 * free)), dtype=torch.uint8, device=problem.device)
+        for attempt in range(4):
+            h, used = ctypes.c_void_p(), ctypes.c_size_t()
+            rc = lib().rs_factor_batched(problem.handle, partition.handle, ctypes.byref(opts), hp, _ptr(ws),
+                                         ws.numel(), _ptr(self.ranks), ctypes.byref(used),
+                                         _stream(problem.device), ctypes.byref(h))
+            if rc != _lib.EWORKSPACE or attempt == 3:
+                break
+            # ranks above the estimate: the library reports a lower bound of what it needs
+            # (up to the level that did not fit); grow past it with room for later levels
+            grow = int(max(used.value * 1.5, ws.numel() * 2))
+            del ws
+            ws = torch.empty(grow, dtype=torch.uint8, device=problem.device)
+        check(rc)
         self.handle = h
+        self.ws = ws
+        self.ws_used = used.value
 
     def apply(self, r):
         """z = T^{-1} r for r of shape (N,) or (nrhs, N)."""
@@ -165,6 +211,14 @@ class Factor:
         r = _vec(r, self.problem.N, self.problem.device)
         z = torch.empty_like(r)
         check(lib().rs_apply(self.handle, r.shape[0], _ptr(r), _ptr(z), _stream(self.problem.device)))
+        return z[0] if one else z
+
+    def apply_sub(self, i, r):
+        """z = R_i^T A_i^{-1} R_i r, subdomain i's term of T^{-1} r (rs_apply_sub)."""
+        one = r.dim() == 1
+        r = _vec(r, self.problem.N, self.problem.device)
+        z = torch.empty_like(r)
+        check(lib().rs_apply_sub(self.handle, i, r.shape[0], _ptr(r), _ptr(z), _stream(self.problem.device)))
         return z[0] if one else z
 
     def stats(self):
@@ -221,16 +275,18 @@ class Factor:
         return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts])
 
     def schedule(self):
-        """Stream synchronizations, stepped-QR launch pairs, mispredicted boxes, mean |k - k_pred|
-        and row-compressed levels of the factorization (rs_factor_schedule)."""
-        s, q, m, e, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
-        sk, fb, ch = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        check(lib().rs_factor_schedule(self.handle, ctypes.byref(s), ctypes.byref(q), ctypes.byref(m),
-                                       ctypes.byref(e), ctypes.byref(c), ctypes.byref(sk), ctypes.byref(fb),
-                                       ctypes.byref(ch)))
-        return {"host_syncs": s.value, "qr_steps": q.value, "mispredicted": m.value,
-                "mean_abs_err": e.value, "row_compressed": c.value, "sketched": sk.value,
-                "sketch_fallbacks": fb.value, "chunks": ch.value}
+        """Stream synchronizations, stepped-QR launch pairs, mispredicted boxes, mean |k - k_pred|,
+        row-compressed levels, sketch counts and level chunks of the factorization
+        (rs_factor_schedule)."""
+        v = [ctypes.c_int() for _ in range(10)]
+        e = ctypes.c_double()
+        check(lib().rs_factor_schedule(self.handle, ctypes.byref(v[0]), ctypes.byref(v[1]), ctypes.byref(v[2]),
+                                       ctypes.byref(e), ctypes.byref(v[3]), ctypes.byref(v[4]), ctypes.byref(v[5]),
+                                       ctypes.byref(v[6]), ctypes.byref(v[7]), ctypes.byref(v[8])))
+        return {"host_syncs": v[0].value, "qr_steps": v[1].value, "mispredicted": v[2].value,
+                "mean_abs_err": e.value, "row_compressed": v[3].value, "sketched": v[4].value,
+                "sketch_fallbacks": v[5].value, "chunks": v[6].value, "sketched_pred": v[7].value,
+                "sketch_pred_rejected": v[8].value}
 
     def root(self, i):
         import numpy as np
@@ -302,17 +358,23 @@ class RankMLP:
         return torch.clamp(torch.round(torch.exp2(y) - 1.0), min=0).to(torch.int64)
 
 
-def pcg_solve(problem, factor, f, tol=1e-10, maxit=200, flexible=False, graph=False, fft=False):
+def pcg_workspace(problem, nrhs):
+    """A device workspace for pcg_solve with nrhs right-hand sides (pcg_workspace_bytes)."""
+    return torch.empty(lib().pcg_workspace_bytes(problem.N, nrhs), dtype=torch.uint8, device=problem.device)
+
+
+def pcg_solve(problem, factor, f, tol=1e-10, maxit=200, flexible=False, graph=False, fft=False, ws=None):
     """PCG on A u = f (pcg_solve).  f: (N,) or (nrhs, N).  Returns (u, iters, relres).
 
     graph=True replays each iteration from captured HIP graphs (needs a non-default
-    current stream)."""
+    current stream).  ws: a workspace from pcg_workspace (allocated here if None)."""
     one = f.dim() == 1
     f = _vec(f, problem.N, problem.device)
     nrhs = f.shape[0]
     u = torch.empty_like(f)
     nb = lib().pcg_workspace_bytes(problem.N, nrhs)
-    ws = torch.empty(nb, dtype=torch.uint8, device=problem.device)
+    if ws is None or ws.numel() < nb:
+        ws = pcg_workspace(problem, nrhs)
     iters = (ctypes.c_int * nrhs)()
     relres = (ctypes.c_double * nrhs)()
     flags = (1 if flexible else 0) | (2 if graph else 0) | (4 if fft else 0)

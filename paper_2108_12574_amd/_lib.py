@@ -13,7 +13,7 @@ GRID_CELL, GRID_NODE = 0, 1
 MODE_JACOBI, MODE_SCHWARZ, MODE_CBD = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_BF16GEMM = 0, 1, 2
 ROWS_AUTO, ROWS_NEVER, ROWS_ALWAYS = 0, 1, 2
-OK, EARG, EHIP, ENOTSPD, ENOMEM, WNOTCONV = 0, -1, -2, -3, -4, 1
+OK, EARG, EHIP, ENOTSPD, ENOMEM, EWORKSPACE, WNOTCONV = 0, -1, -2, -3, -4, -5, 1
 
 
 class RSOpts(ctypes.Structure):
@@ -21,7 +21,7 @@ class RSOpts(ctypes.Structure):
                 ("proxy_ratio", ctypes.c_double), ("precision", ctypes.c_int),
                 ("exact", ctypes.c_int), ("mlp", ctypes.c_void_p), ("row_compression", ctypes.c_int),
                 ("id_sketch", ctypes.c_int), ("sketch_seed", ctypes.c_ulonglong),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("apply_rhs", ctypes.c_int)]
 
 
 # (name, restype, argtypes) of every exported symbol of include/cbd.h
@@ -37,17 +37,22 @@ SIGNATURES = [
     ("dd_subdomain_info", _i, [_vp, _i, _ip, _ip, _ip]),
     ("dd_subdomain_index", _i, [_vp, _i, _ip]),
     ("dd_level_boxes", _i, [_vp, _i, _i, _ip, _ip, _ip]),
-    ("rs_factor_batched", _i, [_vp, _vp, ctypes.POINTER(RSOpts), _vp, ctypes.POINTER(_vp)]),
+    ("rs_factor_rank_count", _i, [_vp, ctypes.POINTER(RSOpts), _ip]),
+    ("rs_factor_workspace", _i, [_vp, _vp, ctypes.POINTER(RSOpts), _vp, ctypes.POINTER(_sz)]),
+    ("rs_factor_batched", _i, [_vp, _vp, ctypes.POINTER(RSOpts), _vp, _vp, _sz, _vp, ctypes.POINTER(_sz), _vp,
+                               ctypes.POINTER(_vp)]),
     ("rs_factor_free", _i, [_vp]),
     ("rs_factor_stats", _i, [_vp, _ip, _ip, ctypes.POINTER(_sz), _dp]),
     ("rs_factor_level", _i, [_vp, _i, _ip, _ip, _ip, _ip]),
     ("rs_factor_box", _i, [_vp, _i, _i, _i, _ip, _ip, _ip, _ip, _dp, _dp, _dp, _dp]),
     ("rs_factor_root", _i, [_vp, _i, _ip, _ip, _dp]),
     ("rs_apply", _i, [_vp, _i, _vp, _vp, _vp]),
+    ("rs_apply_sub", _i, [_vp, _i, _i, _vp, _vp, _vp]),
     ("kernel_matvec", _i, [_vp, _i, _vp, _vp, _vp]),
-    ("cbd_fft_prepare", _i, [_vp, _i, _vp]),
+    ("cbd_fft_workspace_bytes", _sz, [_i, _i, _i]),
+    ("cbd_fft_prepare", _i, [_vp, _i, _vp, _sz, _vp]),
     ("kernel_matvec_fft", _i, [_vp, _i, _vp, _vp, _vp]),
-    ("cbd_autotune_matvec", _i, [_vp, _i, _vp, _ip]),
+    ("cbd_autotune_matvec", _i, [_vp, _i, _vp, _vp, _vp, _ip]),
     ("pcg_workspace_bytes", _sz, [_l, _i]),
     ("pcg_solve", _i, [_vp, _vp, _i, _vp, _vp, _d, _i, _i, _vp, _sz, _ip, _dp, _vp]),
     ("rank_mlp_params", _i, []),
@@ -56,7 +61,7 @@ SIGNATURES = [
     ("rank_mlp_loss_grad", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     ("rank_mlp_adam", _i, [_vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp]),
     ("rs_factor_features", _i, [_vp, _i, _ip, ctypes.POINTER(ctypes.c_float), _ip]),
-    ("rs_factor_schedule", _i, [_vp, _ip, _ip, _ip, _dp, _ip, _ip, _ip, _ip]),
+    ("rs_factor_schedule", _i, [_vp, _ip, _ip, _ip, _dp, _ip, _ip, _ip, _ip, _ip, _ip]),
     ("cbd_timing_enable", _i, [_i]),
     ("cbd_timing_get", _i, [ctypes.c_char_p, _dp, ctypes.POINTER(_l)]),
     ("cbd_timing_reset", _i, []),

@@ -119,17 +119,14 @@ struct cbd_problem_s {
     double h, weight, a_self;
     double *pts, *diag, *w, *rs;
     int mv_rb[4] = {0, 0, 0, 0};   // tuned matvec row blocks per wave, per RHS-block count (0: default)
-    // FFT matvec state (cbd_fft_prepare)
+    // FFT matvec state (cbd_fft_prepare): views of the caller's workspace
     int fft_P = 0, fft_logP = 0, fft_pairs = 0;
     double* fft_ghat = nullptr;
     double2* fft_tw = nullptr;
     double2* fft_buf = nullptr;
-    ~cbd_problem_s() {
-        if (fft_ghat) (void)hipFree(fft_ghat);
-        if (fft_tw) (void)hipFree(fft_tw);
-        if (fft_buf) (void)hipFree(fft_buf);
+    ProblemView view() const {
+        return ProblemView{d, n, N, pts, diag, w, rs, grid == CBD_GRID_CELL ? 1.0 / n : 1.0 / (n - 1)};
     }
-    ProblemView view() const { return ProblemView{d, n, N, pts, diag, w, rs}; }
 };
 
 // Exact integral of K over the cell [-h/2, h/2]^d (diagonal of (e:a_2d)/(e:a_3d)).
@@ -195,31 +192,50 @@ extern "C" int kernel_matvec(cbd_problem p, int nrhs, const double* x, double* y
     return CBD_OK;
 }
 
-extern "C" int cbd_fft_prepare(cbd_problem p, int max_pairs, void* stream) {
-    if (!p || max_pairs < 1) return fail(CBD_EARG, "cbd_fft_prepare: bad argument");
-    int P = 2, logP = 1;
-    while (P < 2 * p->n - 1) {
+namespace {
+int fft_size(int n, int* logP) {
+    int P = 2, l = 1;
+    while (P < 2 * n - 1) {
         P <<= 1;
-        ++logP;
+        ++l;
     }
+    if (logP) *logP = l;
+    return P;
+}
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace
+
+extern "C" size_t cbd_fft_workspace_bytes(int d, int n, int max_pairs) {
+    if ((d != 2 && d != 3) || n < 2 || max_pairs < 1) return 0;
+    const int P = fft_size(n, nullptr);
+    size_t vol = 1;
+    for (int t = 0; t < d; ++t) vol *= (size_t)P;
+    return al256(sizeof(double) * vol) + al256(sizeof(double2) * (P / 2)) + al256(sizeof(double2) * vol * max_pairs);
+}
+
+extern "C" int cbd_fft_prepare(cbd_problem p, int max_pairs, void* ws, size_t ws_bytes, void* stream) {
+    if (!p || max_pairs < 1 || !ws) return fail(CBD_EARG, "cbd_fft_prepare: bad argument");
+    int logP = 0;
+    const int P = fft_size(p->n, &logP);
     if (P > 4096) return fail(CBD_EARG, "cbd_fft_prepare: transform length above 4096 (n > 2048)");
+    if (((uintptr_t)ws & 255) != 0) return fail(CBD_EARG, "cbd_fft_prepare: ws must be 256-byte aligned");
+    if (ws_bytes < cbd_fft_workspace_bytes(p->d, p->n, max_pairs))
+        return fail(CBD_EWORKSPACE, "cbd_fft_prepare: workspace too small (need " +
+                                        std::to_string(cbd_fft_workspace_bytes(p->d, p->n, max_pairs)) + " bytes)");
     long vol = 1;
     for (int t = 0; t < p->d; ++t) vol *= P;
     hipStream_t s = (hipStream_t)stream;
-    if (p->fft_ghat) (void)hipFree(p->fft_ghat);
-    if (p->fft_tw) (void)hipFree(p->fft_tw);
-    if (p->fft_buf) (void)hipFree(p->fft_buf);
-    p->fft_ghat = nullptr;
-    p->fft_tw = nullptr;
-    p->fft_buf = nullptr;
+    char* b = (char*)ws;
     p->fft_P = 0;
-    HIPCHK(hipMalloc(&p->fft_ghat, sizeof(double) * vol));
-    HIPCHK(hipMalloc(&p->fft_tw, sizeof(double2) * (P / 2)));
-    HIPCHK(hipMalloc(&p->fft_buf, sizeof(double2) * vol * max_pairs));
+    p->fft_ghat = (double*)b;
+    b += al256(sizeof(double) * vol);
+    p->fft_tw = (double2*)b;
+    b += al256(sizeof(double2) * (P / 2));
+    p->fft_buf = (double2*)b;
     std::vector<double2> tw(P / 2);
     const double pi = 3.14159265358979323846;
     for (int k = 0; k < P / 2; ++k) tw[k] = make_double2(std::cos(2.0 * pi * k / P), -std::sin(2.0 * pi * k / P));
-    HIPCHK(hipMemcpy(p->fft_tw, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(p->fft_tw, tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice, s));
     const double spacing = p->grid == CBD_GRID_CELL ? 1.0 / p->n : 1.0 / (p->n - 1);
     launch_fft_prepare(p->view(), P, logP, spacing, p->fft_buf, p->fft_ghat, p->fft_tw, s);
     HIPCHK(hipGetLastError());
@@ -244,14 +260,11 @@ extern "C" int kernel_matvec_fft(cbd_problem p, int nrhs, const double* x, doubl
     return CBD_OK;
 }
 
-extern "C" int cbd_autotune_matvec(cbd_problem p, int nrhs, void* stream, int* choice) {
-    if (!p || nrhs < 1) return fail(CBD_EARG, "cbd_autotune_matvec: bad argument");
+extern "C" int cbd_autotune_matvec(cbd_problem p, int nrhs, double* x, double* y, void* stream, int* choice) {
+    if (!p || nrhs < 1 || !x || !y || x == y) return fail(CBD_EARG, "cbd_autotune_matvec: bad argument");
     hipStream_t s = (hipStream_t)stream;
     const int nb = matvec_nb(nrhs);
     const int cols = std::min(nrhs, 64);
-    double *x = nullptr, *y = nullptr;
-    HIPCHK(hipMalloc(&x, sizeof(double) * p->N * cols));
-    HIPCHK(hipMalloc(&y, sizeof(double) * p->N * cols));
     launch_fill(x, 1.0, p->N * cols, s);
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
@@ -279,8 +292,6 @@ extern "C" int cbd_autotune_matvec(cbd_problem p, int nrhs, void* stream, int* c
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    (void)hipFree(x);
-    (void)hipFree(y);
     HIPCHK(hipGetLastError());
     p->mv_rb[nb - 1] = best;
     if (choice) *choice = best;
@@ -322,32 +333,23 @@ struct cbd_partition_s {
     int d, n, m, delta, mode, leaf_side, Lt, Lr;
     std::vector<Sub> subs;
     long total = 0;
-    // device copies, uploaded on first use
-    int* d_cidx = nullptr;      // slot -> global index
-    int* d_inv_ptr = nullptr;   // N+1
-    int* d_inv_slot = nullptr;  // total
-    std::vector<int> cidx;
-    int upload() {
-        if (d_cidx) return CBD_OK;
-        long N = 1;
-        for (int t = 0; t < d; ++t) N *= n;
-        std::vector<int> cnt(N + 1, 0);
-        for (long e = 0; e < total; ++e) cnt[cidx[e] + 1]++;
-        for (long g = 0; g < N; ++g) cnt[g + 1] += cnt[g];
-        std::vector<int> slot(total), fill(cnt.begin(), cnt.end() - 1);
-        for (long e = 0; e < total; ++e) slot[fill[cidx[e]]++] = (int)e;
-        HIPCHK(hipMalloc(&d_cidx, sizeof(int) * total));
-        HIPCHK(hipMalloc(&d_inv_ptr, sizeof(int) * (N + 1)));
-        HIPCHK(hipMalloc(&d_inv_slot, sizeof(int) * total));
-        HIPCHK(hipMemcpy(d_cidx, cidx.data(), sizeof(int) * total, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(d_inv_ptr, cnt.data(), sizeof(int) * (N + 1), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(d_inv_slot, slot.data(), sizeof(int) * total, hipMemcpyHostToDevice));
-        return CBD_OK;
-    }
-    ~cbd_partition_s() {
-        if (d_cidx) (void)hipFree(d_cidx);
-        if (d_inv_ptr) (void)hipFree(d_inv_ptr);
-        if (d_inv_slot) (void)hipFree(d_inv_slot);
+    std::vector<int> cidx;      // slot -> global index
+    // inverse map in CSR form: the slots holding grid point g are inv_slot[inv_ptr[g] ..
+    // inv_ptr[g + 1]), in subdomain order (built on first use; host only)
+    std::vector<int> inv_ptr, inv_slot;
+    std::once_flag inv_once;
+    void build_inverse() {
+        std::call_once(inv_once, [this] {
+            long N = 1;
+            for (int t = 0; t < d; ++t) N *= n;
+            std::vector<int> cnt(N + 1, 0);
+            for (long e = 0; e < total; ++e) cnt[cidx[e] + 1]++;
+            for (long g = 0; g < N; ++g) cnt[g + 1] += cnt[g];
+            std::vector<int> slot(total), fill(cnt.begin(), cnt.end() - 1);
+            for (long e = 0; e < total; ++e) slot[fill[cidx[e]]++] = (int)e;
+            inv_ptr = std::move(cnt);
+            inv_slot = std::move(slot);
+        });
     }
 };
 
@@ -572,16 +574,70 @@ extern "C" int dd_level_boxes(cbd_partition q, int i, int level, int* n_boxes, i
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename T>
-T* dalloc(size_t n, int& rc) {
-    T* p = nullptr;
-    if (n == 0) n = 1;
-    if (hipMalloc(&p, sizeof(T) * n) != hipSuccess) {
-        rc = fail(CBD_ENOMEM, "hipMalloc failed");
-        return nullptr;
+// A factorization's share of the caller's workspace.  Persistent arrays (box lists,
+// factor slots, the partition's device index maps, the apply's buffers) are taken
+// from the bottom; scratch from the top, as a stack that is cut back at every level
+// and every chunk of a level.  All work of a factorization is enqueued on one stream,
+// so scratch given back is reused only by work enqueued after the work that used it.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, lo = 0, hi = 0, peak = 0;
+    size_t short_by = 0;      // a request that did not fit: the bytes missing
+    static size_t al(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~(size_t)255; }
+    void init(void* p, size_t bytes) {
+        base = (char*)p;
+        cap = bytes & ~(size_t)255;
+        lo = 0;
+        hi = cap;
+        peak = 0;
+        short_by = 0;
     }
-    return p;
-}
+    void track() { peak = std::max(peak, lo + (cap - hi)); }
+    size_t free_bytes() const { return hi - lo; }
+    void* low(size_t b) {
+        b = al(b);
+        if (b > hi - lo) {
+            short_by = b - (hi - lo);
+            return nullptr;
+        }
+        void* p = base + lo;
+        lo += b;
+        track();
+        return p;
+    }
+    void* high(size_t b) {
+        b = al(b);
+        if (b > hi - lo) {
+            short_by = b - (hi - lo);
+            return nullptr;
+        }
+        hi -= b;
+        track();
+        return base + hi;
+    }
+};
+
+// Scratch buffer of a level or chunk, carved from the top of the arena; growing it
+// takes a new region (the old one is given back with the next cut).
+struct ScratchBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    Arena* A = nullptr;
+    int ensure(size_t b) {
+        if (b <= bytes && p) return CBD_OK;
+        void* q = A->high(b);
+        if (!q)
+            return fail(CBD_EWORKSPACE, "rs_factor_batched: workspace too small (" + std::to_string(A->short_by) +
+                                            " more bytes needed for scratch)");
+        p = q;
+        bytes = b;
+        return CBD_OK;
+    }
+    void reset() {
+        p = nullptr;
+        bytes = 0;
+    }
+};
 
 struct Level {
     bool root = false;
@@ -593,45 +649,10 @@ struct Level {
     std::vector<int> sub_start;         // first batch index of each subdomain (-1: absent)
     int np_max = 0, m_max = 0;
     long tot_act = 0, tot_f = 0;
+    // device arrays of the level, in the caller's workspace
     BoxMeta* d_meta = nullptr;
     int *d_act = nullptr, *d_sr = nullptr, *d_perm = nullptr, *d_k = nullptr;
     void* d_F = nullptr;
-    void release() {
-        if (d_meta) (void)hipFree(d_meta);
-        if (d_act) (void)hipFree(d_act);
-        if (d_sr) (void)hipFree(d_sr);
-        if (d_perm) (void)hipFree(d_perm);
-        if (d_k) (void)hipFree(d_k);
-        if (d_F) (void)hipFree(d_F);
-        d_meta = nullptr;
-        d_act = d_sr = d_perm = d_k = nullptr;
-        d_F = nullptr;
-    }
-};
-
-// grow-only device buffer
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    int ensure(size_t b) {
-        if (b <= bytes) return CBD_OK;
-        if (p) {
-            // queued kernels of an earlier level may still use the old buffer
-            (void)hipDeviceSynchronize();
-            (void)hipFree(p);
-        }
-        p = nullptr;
-        bytes = 0;
-        if (hipMalloc(&p, b) != hipSuccess) return fail(CBD_ENOMEM, "hipMalloc of workspace failed");
-        bytes = b;
-        return CBD_OK;
-    }
-    ~DevBuf() {
-        if (p) {
-            (void)hipDeviceSynchronize();
-            (void)hipFree(p);
-        }
-    }
 };
 
 }  // namespace
@@ -648,6 +669,8 @@ struct cbd_factor_s {
     int hqr_levels = 0;       // stepped batches whose proxy matrices were row-compressed first
     int sketched = 0;         // boxes whose ID came from a sketch
     int sketch_fallbacks = 0; // boxes whose sketch saturated (deterministic ID instead)
+    int sketched_pred = 0;    // boxes whose ID came from the rank-sized first sketch
+    int sketch_pred_rejected = 0;   // boxes whose rank-sized sketch was not kept
     int chunks = 0;           // level chunks (more than the number of levels when the workspace is bounded)
     double pred_abs_err = 0.0;
     int pred_count = 0;
@@ -657,11 +680,12 @@ struct cbd_factor_s {
     std::vector<int> S;
     size_t bytes = 0;
     double flops = 0.0;
-    DevBuf v;                    // local vectors of the apply
-    DevBuf t1, t2;               // root-level buffers of the apply for large roots
-    ~cbd_factor_s() {
-        for (auto& l : levels) l.release();
-    }
+    Arena ws;                    // the caller's workspace (the factor views it)
+    int *d_cidx = nullptr, *d_inv_ptr = nullptr, *d_inv_slot = nullptr;   // partition maps
+    int apply_rhs = 0;           // columns the apply buffers hold
+    void *v = nullptr, *t1 = nullptr, *t2 = nullptr;   // apply: local vectors, large-root buffers
+    std::vector<int> stage;      // host source of an upload in flight
+    std::vector<int> ranks;      // host source of the ranks_out upload
 };
 
 namespace {
@@ -676,6 +700,14 @@ constexpr int kSketchOver = 8;
 int sketch_rows(int m, int np) {
     const int ell = (3 * np + 4) / 5 + kSketchOver;
     return ell < std::min(m, np) ? ell : 0;
+}
+// Rows of the first sketch from a predicted rank k_p (0: none): 4 k_p + 32 when below the
+// shape-based size; its ID is kept when k <= ell / 4.
+constexpr int kSketchPredFactor = 4, kSketchPredExtra = 32;
+int predicted_sketch_rows(int m, int np, int kp) {
+    const int shape = sketch_rows(m, np);
+    const int ell = kSketchPredFactor * std::max(kp, 0) + kSketchPredExtra;
+    return shape && ell < shape ? ell : 0;
 }
 
 double cpqr_flops(double m, double n, double k) {
@@ -718,11 +750,38 @@ std::vector<double> proxy_dirs(int d, int npxy) {
     return dir;
 }
 
+// Persistent bytes of the workspace for one level's arrays (as factor_impl takes them).
+size_t level_bytes(long nbox, long n_act, long n_f, size_t esize) {
+    return Arena::al(sizeof(BoxMeta) * nbox) + 3 * Arena::al(sizeof(int) * n_act) + Arena::al(sizeof(int) * nbox) +
+           Arena::al(esize * n_f);
+}
+
+// Bytes of the apply's buffers for `cols` right-hand sides.
+size_t apply_bytes(long total, long root_boxes, int root_np_max, int cols, size_t esize) {
+    size_t b = Arena::al(esize * (size_t)total * cols);
+    if (root_np_max >= kBigBox) b += 2 * Arena::al(esize * (size_t)root_boxes * root_np_max * cols);
+    return b;
+}
+
 template <typename R>
-int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipStream_t s,
-                cbd_factor_s* F) {
-    int rc = Q->upload();
-    if (rc) return rc;
+int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, const int* hint, int* ranks_out,
+                hipStream_t s, cbd_factor_s* F) {
+    int rc = CBD_OK;
+    Arena& A = F->ws;
+    auto short_of = [&](const char* what) {
+        return fail(CBD_EWORKSPACE, std::string("rs_factor_batched: workspace too small (") + what + ": " +
+                                        std::to_string(A.short_by) + " more bytes needed)");
+    };
+    // the partition's index maps: slot -> point, and point -> slots for the scatter-add
+    Q->build_inverse();
+    const long N_ = P->N;
+    F->d_cidx = (int*)A.low(sizeof(int) * Q->total);
+    F->d_inv_ptr = (int*)A.low(sizeof(int) * (N_ + 1));
+    F->d_inv_slot = (int*)A.low(sizeof(int) * Q->total);
+    if (!F->d_cidx || !F->d_inv_ptr || !F->d_inv_slot) return short_of("partition maps");
+    HIPCHK(hipMemcpyAsync(F->d_cidx, Q->cidx.data(), sizeof(int) * Q->total, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(F->d_inv_ptr, Q->inv_ptr.data(), sizeof(int) * (N_ + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(F->d_inv_slot, Q->inv_slot.data(), sizeof(int) * Q->total, hipMemcpyHostToDevice, s));
     const int d = P->d, n = P->n;
     const ProblemView PV = P->view();
     const int D = (int)Q->subs.size();
@@ -733,9 +792,15 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
     const double tie = 1e-10;
     const bool bf16 = o->precision == CBD_PREC_BF16GEMM;
     std::vector<double> hdir = proxy_dirs(d, std::max(npxy, 1));
-    DevBuf dirbuf, ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, statbuf, qrbuf, mlpbuf, listbuf, hqrbuf, idbuf, zbuf;
-    if ((rc = dirbuf.ensure(sizeof(double) * hdir.size()))) return rc;
-    HIPCHK(hipMemcpyAsync(dirbuf.p, hdir.data(), sizeof(double) * hdir.size(), hipMemcpyHostToDevice, s));
+    // level-wide scratch (cut back at every level) and chunk scratch (at every chunk)
+    ScratchBuf ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, mlpbuf;
+    ScratchBuf qrbuf, listbuf, hqrbuf, idbuf, zbuf;
+    for (ScratchBuf* b : {&ybuf, &wbuf, &t64buf, &appbuf, &nearbuf, &chbuf, &mlpbuf, &qrbuf, &listbuf, &hqrbuf,
+                          &idbuf, &zbuf})
+        b->A = &A;
+    double* d_dir = (double*)A.low(sizeof(double) * hdir.size());
+    if (!d_dir) return short_of("proxy directions");
+    HIPCHK(hipMemcpyAsync(d_dir, hdir.data(), sizeof(double) * hdir.size(), hipMemcpyHostToDevice, s));
 
     int Lmax = 0;
     if (!o->exact)
@@ -743,8 +808,10 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
     F->n_compress = Lmax;
     // one Cholesky-breakdown slot per level, read once at the end: the host plans a
     // level while the previous level's elimination runs
-    if ((rc = statbuf.ensure(sizeof(int) * (Lmax + 1)))) return rc;
-    HIPCHK(hipMemsetAsync(statbuf.p, 0, sizeof(int) * (Lmax + 1), s));
+    int* d_stat = (int*)A.low(sizeof(int) * (Lmax + 1));
+    if (!d_stat) return short_of("status slots");
+    F->stage.assign(Lmax + 1, 0);   // kept alive with the factor until the copy is done
+    HIPCHK(hipMemcpyAsync(d_stat, F->stage.data(), sizeof(int) * (Lmax + 1), hipMemcpyHostToDevice, s));
     std::vector<std::vector<int>> keep;   // host sources of uploads still in flight
     // grid coordinates of a global index
     // half-cell coordinates 2 j_t + 1 of every slot (near-field tests in integers)
@@ -758,6 +825,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         }
     }
     const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    long hint_off = 0;   // first entry of the current level in hint[]
 
     for (int l = 0; l <= Lmax; ++l) {
         const bool root = (l == Lmax);
@@ -949,50 +1017,109 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         }
         L.tot_act = o_act;
         L.tot_f = o_f;
-        // device arrays of the level (kept for the apply)
-        L.d_meta = dalloc<BoxMeta>(L.nbox, rc);
-        L.d_act = dalloc<int>(o_act, rc);
-        L.d_sr = dalloc<int>(o_act, rc);
-        L.d_perm = dalloc<int>(o_act, rc);
-        L.d_k = dalloc<int>(L.nbox, rc);
-        L.d_F = dalloc<R>(o_f, rc);
-        if (rc) return rc;
+        // the previous level's scratch is given back: its work is enqueued before any of
+        // this level's
+        A.hi = A.cap;
+        for (ScratchBuf* b : {&ybuf, &wbuf, &t64buf, &appbuf, &nearbuf, &chbuf, &mlpbuf, &qrbuf, &listbuf, &hqrbuf,
+                              &idbuf, &zbuf})
+            b->reset();
+        // device arrays of the level (kept for the apply), in the order level_bytes counts them
+        L.d_meta = (BoxMeta*)A.low(sizeof(BoxMeta) * L.nbox);
+        L.d_act = L.d_meta ? (int*)A.low(sizeof(int) * o_act) : nullptr;
+        L.d_sr = L.d_act ? (int*)A.low(sizeof(int) * o_act) : nullptr;
+        L.d_perm = L.d_sr ? (int*)A.low(sizeof(int) * o_act) : nullptr;
+        L.d_k = L.d_perm ? (int*)A.low(sizeof(int) * L.nbox) : nullptr;
+        L.d_F = L.d_k ? A.low(sizeof(R) * o_f) : nullptr;
+        if (!L.d_F) return short_of(("factor arrays of level " + std::to_string(l)).c_str());
         F->bytes += sizeof(R) * (size_t)o_f;
         // The level's boxes go through the proxy matrices, IDs and elimination in chunks
         // of consecutive boxes whose scratch (Y, elimination work, FP64 T, box matrices)
-        // fits the workspace budget; the factor arrays stay level-wide.
-        std::vector<int> cut{0};
-        long cy = 0, cf = 0, ca = 0, my = 1, mf = 1, ma = 1;
+        // fits what is left of the workspace (and opts->workspace_bytes); the factor
+        // arrays stay level-wide.  The level's scratch buffers are sized once, for the
+        // largest chunk.
+        std::vector<int> cut;
+        long my = 1, mf = 1, ma = 1;
+        size_t need = 0;
+        double hqr = 0.0, zb = 0.0;
         {
-            const double budget = o->workspace_bytes ? (double)o->workspace_bytes : 64.0 * (1L << 30);
-            double acc = 0.0;
-            for (int B = 0; B < L.nbox; ++B) {
-                const BoxMeta& M = L.meta[B];
-                const long yb = std::max((long)M.m * M.np, (long)M.np * M.np + kScratchCols * M.np);
-                const long fb = (long)M.np * M.np;
-                const double bytes = (double)yb * (2 * sizeof(double) + sizeof(R)) + (double)fb * (sizeof(double) + sizeof(R));
-                if (B > cut.back() && acc + bytes > budget) {
-                    cut.push_back(B);
-                    acc = 0.0;
-                    cy = cf = ca = 0;
+            auto est = [&](const BoxMeta& M) {
+                const double yb = (double)std::max((long)M.m * M.np, (long)M.np * M.np + kScratchCols * M.np);
+                const double fb = (double)M.np * M.np;
+                return yb * (sizeof(double) + sizeof(R)) + fb * (sizeof(double) + sizeof(R));
+            };
+            auto al = [](double b) { return Arena::al((size_t)b); };
+            const bool sk = o->id_sketch != 0 && !root;
+            double budget = std::min((double)A.free_bytes(),
+                                     o->workspace_bytes ? (double)o->workspace_bytes : 1e300);
+            for (;;) {
+                cut.assign(1, 0);
+                double acc = 0.0;
+                for (int B = 0; B < L.nbox; ++B) {
+                    const double e = est(L.meta[B]);
+                    if (B > cut.back() && acc + e > budget) {
+                        cut.push_back(B);
+                        acc = 0.0;
+                    }
+                    acc += e;
                 }
-                acc += bytes;
-                cy += yb;
-                cf += fb;
-                ca += fb;
-                my = std::max(my, cy);
-                mf = std::max(mf, cf);
-                ma = std::max(ma, ca);
+                cut.push_back(L.nbox);
+                // exact scratch of this cut: level-wide buffers for the largest chunk
+                my = mf = ma = 1;
+                hqr = zb = 0.0;
+                for (size_t c = 0; c + 1 < cut.size(); ++c) {
+                    long cy = 0, cf = 0, o_r = 0, o_z = 0, o_bits = 0;
+                    int mmax = 0;
+                    const int nb = cut[c + 1] - cut[c];
+                    for (int B = cut[c]; B < cut[c + 1]; ++B) {
+                        const BoxMeta& M = L.meta[B];
+                        cy += std::max((long)M.m * M.np, (long)M.np * M.np + kScratchCols * M.np);
+                        cf += (long)M.np * M.np;
+                        o_r += (long)std::min(M.m, M.np) * M.np;
+                        mmax = std::max(mmax, M.m);
+                        const int ell = sk ? sketch_rows(M.m, M.np) : 0;
+                        o_z += (long)ell * M.np;
+                        o_bits += (long)M.m * ((ell + 31) / 32);
+                    }
+                    my = std::max(my, cy);
+                    mf = std::max(mf, cf);
+                    ma = std::max(ma, cf);
+                    // row compression runs only in the stepped QR (few boxes, or matrices too
+                    // large for one workgroup's LDS)
+                    int npmax = 0;
+                    for (int B = cut[c]; B < cut[c + 1]; ++B) npmax = std::max(npmax, L.meta[B].np);
+                    const size_t shm = (size_t)(npmax + mmax) * sizeof(double) + (size_t)npmax * sizeof(int);
+                    if (!root && o->row_compression != CBD_ROWS_NEVER && (nb < kStepBoxes || shm > 65536))
+                        hqr = std::max(hqr, (double)sizeof(BoxMeta) * nb +
+                                                8.0 * ((double)nb * kHqrTw + o_act + (double)nb * kHqrVbuf(mmax) +
+                                                       std::max(o_r, 1L)));
+                    if (sk)
+                        zb = std::max(zb, (double)(sizeof(BoxMeta) + 8 + 8) * nb + 8.0 * std::max(o_z, 1L) +
+                                              4.0 * std::max(o_bits, 1L));
+                }
+                need = al(8.0 * my) + al((double)sizeof(R) * my) + al(8.0 * mf) + al((double)sizeof(R) * ma) +
+                       al(4.0 * std::max(o_near, 1L)) + al((double)sizeof(ChildRef<R>) * std::max(o_ch, 1L)) +
+                       (o->mlp && !root ? al(4.0 * L.nbox * (kMlpFeatures + 1)) : 0) +
+                       al(8.0 * (3.0 * o_act + 2.0 * L.nbox) + 4.0 * (o_act + 2.0 * L.nbox)) +
+                       al((double)(sizeof(BoxMeta) + 4) * L.nbox) + al(4.0 * L.nbox) + (hqr > 0 ? al(hqr) : 0) + (sk ? al(zb) : 0);
+                if (need <= A.free_bytes()) break;
+                if ((int)cut.size() - 1 >= L.nbox) {
+                    A.short_by = need - A.free_bytes();
+                    return short_of(("scratch of level " + std::to_string(l)).c_str());
+                }
+                budget *= 0.7;
             }
-            cut.push_back(L.nbox);
+            if ((rc = ybuf.ensure(sizeof(double) * my)) || (rc = wbuf.ensure(sizeof(R) * my)) ||
+                (rc = t64buf.ensure(sizeof(double) * mf)) || (rc = appbuf.ensure(sizeof(R) * ma)) ||
+                (rc = nearbuf.ensure(sizeof(int) * std::max(o_near, 1L))) ||
+                (rc = chbuf.ensure(sizeof(ChildRef<R>) * std::max(o_ch, 1L))) ||
+                (o->mlp && !root && (rc = mlpbuf.ensure(sizeof(float) * (size_t)L.nbox * (kMlpFeatures + 1)))) ||
+                (rc = qrbuf.ensure(sizeof(double) * (3 * o_act + 2 * L.nbox) + sizeof(int) * (o_act + 2 * L.nbox))) ||
+                (rc = idbuf.ensure((sizeof(BoxMeta) + sizeof(int)) * L.nbox)) ||
+                (rc = listbuf.ensure(sizeof(int) * L.nbox)) || (hqr > 0 && (rc = hqrbuf.ensure((size_t)hqr))) ||
+                (sk && (rc = zbuf.ensure((size_t)zb))))
+                return rc;
         }
         F->chunks += (int)cut.size() - 1;
-        if ((rc = ybuf.ensure(sizeof(double) * my))) return rc;
-        if ((rc = wbuf.ensure(sizeof(R) * my))) return rc;
-        if ((rc = t64buf.ensure(sizeof(double) * mf))) return rc;
-        if ((rc = appbuf.ensure(sizeof(R) * ma))) return rc;
-        if ((rc = nearbuf.ensure(sizeof(int) * std::max(o_near, 1L)))) return rc;
-        if ((rc = chbuf.ensure(sizeof(ChildRef<R>) * std::max(o_ch, 1L)))) return rc;
         std::vector<int> hact, hnear;
         std::vector<ChildRef<R>> hch;
         hact.reserve(o_act);
@@ -1031,6 +1158,13 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 kpred[B] = std::max(0, std::min(kmax, (int)std::lround(std::isfinite(kp) ? kp : (double)kmax)));
             }
         }
+        if (!root && hint) {
+            // ranks of an earlier factorization of the same layout: the same use as predictions
+            kpred.resize(L.nbox);
+            for (int B = 0; B < L.nbox; ++B)
+                kpred[B] = std::max(0, std::min(std::min(L.meta[B].m, L.meta[B].np), hint[hint_off + B]));
+        }
+        if (!root) hint_off += L.nbox;
         kall.assign(L.nbox, 0);
         sk_ell.assign(L.nbox, 0);
         for (size_t ci = 0; ci + 1 < cut.size(); ++ci) {
@@ -1044,10 +1178,10 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
         int* d_k_c = L.d_k + b0;
         int np_max_c = 0;
         for (int B = b0; B < b1; ++B) np_max_c = std::max(np_max_c, L.meta[B].np);
-        int* d_status = (int*)statbuf.p + l;
+        int* d_status = d_stat + l;
         if (!root) {
-            launch_proxy_matrix<double>(PV, nbc, d_meta_c, L.d_act, (const int*)nearbuf.p, Q->d_cidx,
-                                        (const double*)dirbuf.p, npxy, Y, s);
+            launch_proxy_matrix<double>(PV, nbc, d_meta_c, L.d_act, (const int*)nearbuf.p, F->d_cidx,
+                                        d_dir, npxy, Y, s);
             // The ID of a batch of boxes (bm: their metadata, m rows of Ymat each, at the
             // offsets bm[].y), with k into kb (host, one per batch box).
             auto id_batch = [&](const std::vector<BoxMeta>& bm, double* Ymat, const std::vector<int>& bpred,
@@ -1067,7 +1201,11 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                 HIPCHK(hipMemcpyAsync(d_bm, bm.data(), sizeof(BoxMeta) * nb, hipMemcpyHostToDevice, s));
                 const size_t shm = (size_t)(np_max + m_max) * sizeof(double) + (size_t)np_max * sizeof(int);
                 std::vector<BoxMeta> cmh;   // compact metadata of row-compressed boxes
-                if (nb >= kStepBoxes && shm <= 65536) {
+                if (cpqr_reg_fits(m_max, np_max)) {
+                    // small boxes: the whole matrix in one workgroup's registers
+                    launch_cpqr_reg(nb, np_max, m_max, d_bm, Ymat, L.d_act, L.d_sr, L.d_perm, d_kb, T64, o->tol, tie,
+                                    s);
+                } else if (nb >= kStepBoxes && shm <= 65536) {
                     // many boxes: one workgroup per box
                     launch_cpqr(nb, d_bm, Ymat, L.d_act, L.d_sr, L.d_perm, d_kb, T64, o->tol, tie, m_max, np_max, s);
                 } else {
@@ -1179,40 +1317,42 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             };
             std::vector<int> det;   // boxes with the deterministic ID
             if (o->id_sketch) {
-                // randomized ID: the CPQR of Z = Omega Y (ell x np, random signs), ell from
-                // the box shape; a saturated sketch falls back to the deterministic ID
-                std::vector<BoxMeta> zm;
-                std::vector<int> zb, zpred;
+                // randomized ID: the CPQR of Z = Omega Y (ell x np, random signs).  With a
+                // predicted rank k_p, a first sketch of 4 k_p + 32 rows, kept if k <= ell / 4;
+                // then the shape-based sketch, kept unless saturated (k > ell - 8); then the
+                // deterministic ID
                 std::vector<unsigned long long> keys(nbc);
-                std::vector<BoxMeta> zall(L.meta.begin() + b0, L.meta.begin() + b1);
-                std::vector<long> boff(nbc, 0);   // offsets of the boxes' sign words
-                long o_z = 0, o_bits = 0, mw_max = 0;
-                for (int B = b0; B < b1; ++B) {
-                    const BoxMeta& M = L.meta[B];
-                    const int ell = sketch_rows(M.m, M.np);
+                for (int B = b0; B < b1; ++B)
                     keys[B - b0] = ((unsigned long long)L.box_sub[B] << 40) | ((unsigned long long)l << 32) |
                                    (unsigned long long)L.box_idx[B];
-                    zall[B - b0].m = ell;
-                    zall[B - b0].y = o_z;
-                    o_z += (long)ell * M.np;
-                    boff[B - b0] = o_bits;
-                    const long mw = (long)M.m * ((ell + 31) / 32);
-                    o_bits += mw;
-                    mw_max = std::max(mw_max, mw);
-                    if (ell) {
-                        sk_ell[B] = ell;
+                // one pass over `boxes` (ell_of: sketch rows per chunk box); boxes whose ID is
+                // not accepted go to `rejected`
+                auto sketch_pass = [&](const std::vector<int>& boxes, const std::vector<int>& ell_of, bool pred,
+                                       std::vector<int>& rejected) -> int {
+                    std::vector<BoxMeta> zall(L.meta.begin() + b0, L.meta.begin() + b1), zm;
+                    std::vector<long> boff(nbc, 0);   // offsets of the boxes' sign words
+                    std::vector<int> zpred;
+                    for (BoxMeta& Z : zall) Z.m = 0;
+                    long o_z = 0, o_bits = 0, mw_max = 0;
+                    for (int B : boxes) {
+                        const BoxMeta& M = L.meta[B];
+                        const int ell = ell_of[B - b0];
+                        zall[B - b0].m = ell;
+                        zall[B - b0].y = o_z;
+                        o_z += (long)ell * M.np;
+                        boff[B - b0] = o_bits;
+                        const long mw = (long)M.m * ((ell + 31) / 32);
+                        o_bits += mw;
+                        mw_max = std::max(mw_max, mw);
                         zm.push_back(zall[B - b0]);
-                        zb.push_back(B);
                         if (!kpred.empty()) zpred.push_back(std::min(kpred[B], ell));
-                    } else {
-                        det.push_back(B);
                     }
-                }
-                if (!zb.empty()) {
-                    if ((rc = zbuf.ensure(sizeof(BoxMeta) * nbc + sizeof(unsigned long long) * nbc +
-                                          sizeof(long) * nbc + sizeof(double) * std::max(o_z, 1L) +
-                                          sizeof(unsigned) * std::max(o_bits, 1L))))
-                        return rc;
+                    if (boxes.empty()) return CBD_OK;
+                    int rc3;
+                    if ((rc3 = zbuf.ensure(sizeof(BoxMeta) * nbc + sizeof(unsigned long long) * nbc +
+                                           sizeof(long) * nbc + sizeof(double) * std::max(o_z, 1L) +
+                                           sizeof(unsigned) * std::max(o_bits, 1L))))
+                        return rc3;
                     BoxMeta* d_zall = (BoxMeta*)zbuf.p;
                     unsigned long long* d_keys = (unsigned long long*)(d_zall + nbc);
                     long* d_boff = (long*)(d_keys + nbc);
@@ -1222,20 +1362,43 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                     HIPCHK(hipMemcpyAsync(d_keys, keys.data(), sizeof(unsigned long long) * nbc,
                                           hipMemcpyHostToDevice, s));
                     HIPCHK(hipMemcpyAsync(d_boff, boff.data(), sizeof(long) * nbc, hipMemcpyHostToDevice, s));
-                    launch_sketch(nbc, np_max_c, mw_max, d_meta_c, d_zall, Y, (const int*)nearbuf.p, Q->d_cidx,
+                    launch_sketch(nbc, np_max_c, mw_max, d_meta_c, d_zall, Y, (const int*)nearbuf.p, F->d_cidx,
                                   P->N, o->sketch_seed, d_keys, d_boff, d_bits, Z, s);
                     std::vector<int> kz;
-                    if ((rc = id_batch(zm, Z, zpred, kz))) return rc;
-                    for (size_t e = 0; e < zb.size(); ++e) {
-                        if (kz[e] > sk_ell[zb[e]] - kSketchOver) {
-                            det.push_back(zb[e]);       // saturated sketch
-                            sk_ell[zb[e]] = 0;
-                            F->sketch_fallbacks++;
-                        } else {
-                            kall[zb[e]] = kz[e];
+                    if ((rc3 = id_batch(zm, Z, zpred, kz))) return rc3;   // synchronizes: the uploads are done
+                    for (size_t e = 0; e < boxes.size(); ++e) {
+                        const int B = boxes[e], ell = ell_of[B - b0];
+                        const bool ok = pred ? kSketchPredFactor * kz[e] <= ell : kz[e] <= ell - kSketchOver;
+                        if (ok) {
+                            kall[B] = kz[e];
+                            sk_ell[B] = ell;
                             F->sketched++;
+                            F->sketched_pred += pred;
+                        } else {
+                            rejected.push_back(B);
+                            F->sketch_pred_rejected += pred;
                         }
                     }
+                    return CBD_OK;
+                };
+                std::vector<int> ell_p(nbc, 0), ell_s(nbc, 0), pass1, pass2;
+                for (int B = b0; B < b1; ++B) {
+                    const BoxMeta& M = L.meta[B];
+                    ell_s[B - b0] = sketch_rows(M.m, M.np);
+                    if (!kpred.empty()) ell_p[B - b0] = predicted_sketch_rows(M.m, M.np, kpred[B]);
+                    if (ell_p[B - b0]) pass1.push_back(B);
+                    else if (ell_s[B - b0]) pass2.push_back(B);
+                    else det.push_back(B);
+                }
+                std::vector<int> rej1, rej2;
+                if ((rc = sketch_pass(pass1, ell_p, true, rej1))) return rc;
+                pass2.insert(pass2.end(), rej1.begin(), rej1.end());
+                std::sort(pass2.begin(), pass2.end());
+                if ((rc = sketch_pass(pass2, ell_s, false, rej2))) return rc;
+                for (int B : rej2) {
+                    det.push_back(B);        // saturated sketch
+                    sk_ell[B] = 0;
+                    F->sketch_fallbacks++;
                 }
                 std::sort(det.begin(), det.end());
             } else {
@@ -1275,7 +1438,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             L.k.assign(L.nbox, 0);
             L.sr = hact;
         }
-        launch_box_matrix<R>(PV, nbc, d_meta_c, L.d_act, Q->d_cidx,
+        launch_box_matrix<R>(PV, nbc, d_meta_c, L.d_act, F->d_cidx,
                              o_ch ? (const ChildRef<R>*)chbuf.p : nullptr, App, s);
         // boxes with many DOFs: Cholesky and inverse as multi-workgroup launch sequences
         // (lists hold chunk-local box indices)
@@ -1308,16 +1471,20 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
                                 bf16, s);
         }
         if (cut.size() > 2) {
-            // a breakdown names a chunk-local box: check before the next chunk
-            int st_c = 0;
-            HIPCHK(hipMemcpyAsync(&st_c, d_status, sizeof(int), hipMemcpyDeviceToHost, s));
+            // a breakdown names a chunk-local box: check before the next chunk (every
+            // level so far, so that the lowest failing level is the one reported)
+            std::vector<int> st(l + 1, 0);
+            HIPCHK(hipMemcpyAsync(st.data(), d_stat, sizeof(int) * (l + 1), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             F->host_syncs++;
-            if (st_c) {
-                const int B = b0 + st_c - 1;
-                return fail(CBD_ENOTSPD, "rs_factor_batched: Cholesky breakdown at level " + std::to_string(l) +
-                                             (root ? " (root)" : "") + ", subdomain " +
-                                             std::to_string(L.box_sub[B]) + ", box " + std::to_string(L.box_idx[B]));
+            for (int l2 = 0; l2 <= l; ++l2) {
+                if (!st[l2]) continue;
+                const Level& L2 = F->levels[l2];
+                // level l2 < l was not chunked; this level's slot names a box of this chunk
+                const int B = (l2 == l ? b0 : 0) + st[l2] - 1;
+                return fail(CBD_ENOTSPD, "rs_factor_batched: Cholesky breakdown at level " + std::to_string(l2) +
+                                             (L2.root ? " (root)" : "") + ", subdomain " +
+                                             std::to_string(L2.box_sub[B]) + ", box " + std::to_string(L2.box_idx[B]));
             }
         }
         }   // chunks
@@ -1335,9 +1502,31 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
             F->flops += elim_flops(k, nr);
         }
     }
+    // the apply's buffers: local vectors of every subdomain for apply_rhs columns, and
+    // the box-contiguous buffers of large roots
+    A.hi = A.cap;
+    {
+        const Level& RL = F->levels.back();
+        F->apply_rhs = o->apply_rhs > 0 ? o->apply_rhs : 64;
+        F->v = A.low(sizeof(R) * (size_t)Q->total * F->apply_rhs);
+        if (!F->v) return short_of("apply buffers");
+        if (RL.np_max >= kBigBox) {
+            const size_t b = sizeof(R) * (size_t)RL.nbox * RL.np_max * F->apply_rhs;
+            F->t1 = A.low(b);
+            F->t2 = F->t1 ? A.low(b) : nullptr;
+            if (!F->t2) return short_of("apply buffers of large roots");
+        }
+    }
+    // ranks of every compressed box, in level and batch order
+    if (ranks_out) {
+        F->ranks.clear();
+        for (int l = 0; l < Lmax; ++l) F->ranks.insert(F->ranks.end(), F->levels[l].k.begin(), F->levels[l].k.end());
+        if (!F->ranks.empty())
+            HIPCHK(hipMemcpyAsync(ranks_out, F->ranks.data(), sizeof(int) * F->ranks.size(), hipMemcpyHostToDevice, s));
+    }
     // breakdowns (one slot per level; a split level was checked chunk by chunk)
     std::vector<int> status(Lmax + 1, 0);
-    HIPCHK(hipMemcpyAsync(status.data(), statbuf.p, sizeof(int) * (Lmax + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(status.data(), d_stat, sizeof(int) * (Lmax + 1), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     F->host_syncs++;
     for (int l = 0; l <= Lmax; ++l) {
@@ -1356,30 +1545,156 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, hipS
 
 }  // namespace
 
-extern "C" int rs_factor_batched(cbd_problem p, cbd_partition q, const cbd_rs_opts* o, void* stream,
-                                 cbd_factor* out) {
-    if (!p || !q || !o || !out) return fail(CBD_EARG, "rs_factor_batched: NULL argument");
-    if (q->d != p->d || q->n != p->n)
-        return fail(CBD_EARG, "rs_factor_batched: partition is for another grid");
-    if (p->grid != CBD_GRID_CELL) return fail(CBD_EARG, "rs_factor_batched: RS needs the cell-centred grid");
+namespace {
+int check_factor_args(cbd_problem p, cbd_partition q, const cbd_rs_opts* o, const char* who) {
+    if (!p || !q || !o) return fail(CBD_EARG, std::string(who) + ": NULL argument");
+    if (q->d != p->d || q->n != p->n) return fail(CBD_EARG, std::string(who) + ": partition is for another grid");
+    if (p->grid != CBD_GRID_CELL) return fail(CBD_EARG, std::string(who) + ": RS needs the cell-centred grid");
     if (!o->exact && (o->n_pxy < 1 || !(o->tol >= 0.0) || !(o->proxy_ratio > 0.75)))
-        return fail(CBD_EARG, "rs_factor_batched: need n_pxy >= 1, tol >= 0, proxy_ratio > 0.75");
+        return fail(CBD_EARG, std::string(who) + ": need n_pxy >= 1, tol >= 0, proxy_ratio > 0.75");
     if (o->precision != CBD_PREC_FP64 && o->precision != CBD_PREC_FP32 && o->precision != CBD_PREC_BF16GEMM)
-        return fail(CBD_EARG, "rs_factor_batched: unknown precision");
+        return fail(CBD_EARG, std::string(who) + ": unknown precision");
+    if (o->apply_rhs < 0) return fail(CBD_EARG, std::string(who) + ": negative apply_rhs");
+    return CBD_OK;
+}
+
+// Boxes of every compressed level in batch order (subdomain by subdomain): at level l,
+// subdomain i contributes its partition boxes at l when its root lies above l.
+int compressed_levels(const cbd_partition_s* q, const cbd_rs_opts* o) {
+    int Lmax = 0;
+    if (!o->exact)
+        for (auto& sd : q->subs) Lmax = std::max(Lmax, sd.root_level);
+    return Lmax;
+}
+}  // namespace
+
+extern "C" int rs_factor_rank_count(cbd_partition q, const cbd_rs_opts* o, int* count) {
+    if (!q || !o || !count) return fail(CBD_EARG, "rs_factor_rank_count: NULL argument");
+    const int Lmax = compressed_levels(q, o);
+    long c = 0;
+    for (int l = 0; l < Lmax; ++l)
+        for (auto& sd : q->subs)
+            if (sd.root_level > l) c += (long)sd.levels[l].size();
+    *count = (int)c;
+    return CBD_OK;
+}
+
+extern "C" int rs_factor_workspace(cbd_problem p, cbd_partition q, const cbd_rs_opts* o, const int* rank_hint,
+                                   size_t* bytes) {
+    int rc = check_factor_args(p, q, o, "rs_factor_workspace");
+    if (rc) return rc;
+    if (!bytes) return fail(CBD_EARG, "rs_factor_workspace: bytes is NULL");
+    const size_t es = o->precision == CBD_PREC_FP64 ? 8 : 4;
+    const int d = p->d, D = (int)q->subs.size();
+    const int Lmax = compressed_levels(q, o);
+    const int npxy = o->exact ? 0 : o->n_pxy;
+    size_t persistent = Arena::al(sizeof(int) * q->total) * 2 + Arena::al(sizeof(int) * (p->N + 1)) +
+                        Arena::al(sizeof(double) * std::max(npxy, 1) * d) + Arena::al(sizeof(int) * (Lmax + 1));
+    size_t scratch = 0, fixed = 0;   // chunkable scratch of the largest level; per-level lists
+    // active DOFs per box, level by level: leaves hold their points; a parent holds
+    // the skeletons of its children (hinted ranks, or a guess without hints)
+    std::vector<std::vector<long>> np(D);
+    for (int i = 0; i < D; ++i)
+        for (auto& lf : q->subs[i].leaves) np[i].push_back(lf.count);
+    long h = 0;
+    // without hints, a box of n_p DOFs is guessed to keep a_d log10(1/tol) n_p^((d-1)/d)
+    // skeletons (ranks grow with the box surface and the digits asked for), a_2 = 0.55,
+    // a_3 = 0.4; near-field rows are estimated as 6 n_p (2D) or 12 n_p (3D)
+    const double digits = std::max(1.0, -std::log10(std::max(o->tol, 1e-300)));
+    auto guess = [&](long np_) -> long {
+        if (o->exact) return np_;
+        const double a = d == 2 ? 0.55 : 0.4;
+        return (long)std::ceil(a * digits * std::pow((double)np_, (d - 1.0) / d));
+    };
+    const double mrow = d == 2 ? 6.0 : 12.0;
+    std::vector<std::vector<long>> kk(D);
+    for (int l = 0; l <= Lmax; ++l) {
+        const bool root = l == Lmax;
+        long nbox = 0, n_act = 0, n_f = 0;
+        double sc = 0.0;
+        for (int i = 0; i < D; ++i) {
+            const Sub& sd = q->subs[i];
+            if (!root && sd.root_level <= l) continue;
+            if (root) {
+                long npr = 0;
+                if (o->exact) {
+                    npr = (long)sd.index.size();
+                } else {
+                    for (long v : np[i]) npr += v;   // the root box of this subdomain
+                }
+                nbox += 1;
+                n_act += npr;
+                n_f += npr * npr;
+                sc += (double)(npr * npr) * (2 * 8 + 2 * es) + (double)kScratchCols * npr * (8 + es);
+                continue;
+            }
+            kk[i].assign(np[i].size(), 0);
+            for (size_t b = 0; b < np[i].size(); ++b) {
+                const long n_ = np[i][b];
+                long k = rank_hint ? rank_hint[h++] : guess(n_);
+                k = std::max(0L, std::min(n_, k));
+                kk[i][b] = k;
+                nbox += 1;
+                n_act += n_;
+                n_f += n_ * n_;
+                const double m = npxy + mrow * n_;
+                sc += (m * n_ + n_ * n_ + kScratchCols * n_) * (8 + es) + (double)n_ * n_ * (8 + es) + 8.0 * n_ * n_;
+            }
+            // parents at level l + 1 (or the root): sums of their children's ranks
+            if (l + 1 <= sd.root_level) {
+                std::vector<long> next(sd.levels[l + 1].size(), 0);
+                for (size_t b = 0; b < sd.levels[l].size(); ++b) next[sd.levels[l][b].parent] += kk[i][b];
+                np[i] = next;
+            }
+        }
+        persistent += level_bytes(nbox, n_act, n_f, es);
+        scratch = std::max(scratch, (size_t)sc);
+        // scratch that is level-wide whatever the chunking: near-field and child lists,
+        // pivoted-QR state, batch metadata
+        fixed = std::max(fixed, (size_t)(4.0 * mrow * n_act + 64.0 * n_act + 512.0 * nbox) + (16u << 10));
+    }
+    // apply buffers (the root boxes' sizes are the last level's)
+    {
+        long rb = 0, rnp = 0;
+        for (int i = 0; i < D; ++i) {
+            long v = 0;
+            if (o->exact) v = (long)q->subs[i].index.size();
+            else for (long x : np[i]) v += x;
+            rb += 1;
+            rnp = std::max(rnp, v);
+        }
+        persistent += apply_bytes(q->total, rb, (int)rnp, o->apply_rhs > 0 ? o->apply_rhs : 64, es);
+    }
+    if (o->workspace_bytes) scratch = std::min(scratch, (size_t)o->workspace_bytes);
+    *bytes = persistent + scratch + fixed + ((size_t)1 << 20);
+    return CBD_OK;
+}
+
+extern "C" int rs_factor_batched(cbd_problem p, cbd_partition q, const cbd_rs_opts* o, const int* rank_hint,
+                                 void* ws, size_t ws_bytes, int* ranks_out, size_t* ws_used, void* stream,
+                                 cbd_factor* out) {
+    int rc = check_factor_args(p, q, o, "rs_factor_batched");
+    if (rc) return rc;
+    if (!out || !ws) return fail(CBD_EARG, "rs_factor_batched: NULL argument");
+    if (((uintptr_t)ws & 255) != 0) return fail(CBD_EARG, "rs_factor_batched: ws must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     auto* F = new cbd_factor_s;
     F->prob = p;
     F->part = q;
-    F->prec = o->precision;
     F->esize = o->precision == CBD_PREC_FP64 ? 8 : 4;
     F->prec = o->precision == CBD_PREC_FP64 ? CBD_PREC_FP64 : CBD_PREC_FP32;   // storage precision
     F->tol = o->tol;
-    int rc;
+    F->ws.init(ws, ws_bytes);
     {
         ScopedTimer tm("factor", s);
-        rc = o->precision == CBD_PREC_FP64 ? factor_impl<double>(p, q, o, s, F)
-                                           : factor_impl<float>(p, q, o, s, F);
+        try {
+            rc = o->precision == CBD_PREC_FP64 ? factor_impl<double>(p, q, o, rank_hint, ranks_out, s, F)
+                                               : factor_impl<float>(p, q, o, rank_hint, ranks_out, s, F);
+        } catch (const std::bad_alloc&) {
+            rc = fail(CBD_ENOMEM, "rs_factor_batched: host allocation failed");
+        }
     }
+    if (ws_used) *ws_used = rc == CBD_EWORKSPACE ? F->ws.peak + F->ws.short_by : F->ws.peak;
     if (rc) {
         (void)hipStreamSynchronize(s);
         delete F;
@@ -1471,44 +1786,38 @@ extern "C" int rs_factor_root(cbd_factor f, int i, int* S, int* idx, double* Gin
 // Large root boxes are applied by GEMMs through global buffers instead of LDS.
 static bool root_uses_gemm(const Level& L) { return L.root && L.np_max >= kBigBox; }
 
-// Allocate the apply's buffers for nrhs columns ahead of time (stream capture).
-static int apply_prepare(cbd_factor f, int nrhs) {
-    int rc = f->v.ensure(f->esize * (size_t)f->part->total * nrhs);
-    if (rc) return rc;
-    const Level& R = f->levels.back();
-    if (root_uses_gemm(R)) {
-        const size_t b = f->esize * (size_t)R.nbox * R.np_max * nrhs;
-        if ((rc = f->t1.ensure(b)) || (rc = f->t2.ensure(b))) return rc;
-    }
-    return CBD_OK;
-}
-
+// z = sum_i R_i^T A_i^{-1} R_i r over the subdomains whose slots lie in [s0, s1) (all of
+// them: the whole range), in blocks of at most apply_rhs columns.
 template <typename R>
-static int apply_impl(cbd_factor f, int nrhs, const double* r, double* z, hipStream_t s) {
+static int apply_impl(cbd_factor f, int nrhs, const double* r, double* z, long s0, long s1, hipStream_t s) {
     cbd_partition_s* Q = f->part;
-    int rc = apply_prepare(f, nrhs);
-    if (rc) return rc;
-    R* v = (R*)f->v.p;
+    R* v = (R*)f->v;
     for (const Level& L : f->levels)
         if (!root_uses_gemm(L) && (size_t)2 * L.np_max * sizeof(R) > 65536)
             return fail(CBD_EARG, "rs_apply: box of " + std::to_string(L.np_max) + " DOFs exceeds the LDS of the apply kernel");
-    launch_gather<R>(r, f->prob->N, nrhs, Q->d_cidx, Q->total, v, s);
+    const long N = f->prob->N;
     const int nl = (int)f->levels.size();
-    for (int l = 0; l < nl; ++l) {
-        const Level& L = f->levels[l];
-        if (root_uses_gemm(L)) {   // forward and backward root solve at once
-            launch_root_apply<R>(L.nbox, L.np_max, 0, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs,
-                                 (R*)f->t1.p, (R*)f->t2.p, s);
-            continue;
+    for (int c0 = 0; c0 < nrhs; c0 += f->apply_rhs) {
+        const int nc = std::min(f->apply_rhs, nrhs - c0);
+        const double* rc = r + (long)c0 * N;
+        double* zc = z + (long)c0 * N;
+        launch_gather<R>(rc, N, nc, f->d_cidx, Q->total, s0, s1, v, s);
+        for (int l = 0; l < nl; ++l) {
+            const Level& L = f->levels[l];
+            if (root_uses_gemm(L)) {   // forward and backward root solve at once
+                launch_root_apply<R>(L.nbox, L.np_max, 0, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nc,
+                                     (R*)f->t1, (R*)f->t2, s);
+                continue;
+            }
+            launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nc, L.np_max, true, s);
         }
-        launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, true, s);
+        for (int l = nl - 1; l >= 0; --l) {
+            const Level& L = f->levels[l];
+            if (root_uses_gemm(L)) continue;
+            launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nc, L.np_max, false, s);
+        }
+        launch_scatter<R>(v, nc, f->d_inv_ptr, f->d_inv_slot, N, zc, s);
     }
-    for (int l = nl - 1; l >= 0; --l) {
-        const Level& L = f->levels[l];
-        if (root_uses_gemm(L)) continue;
-        launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, false, s);
-    }
-    launch_scatter<R>(v, nrhs, Q->d_inv_ptr, Q->d_inv_slot, f->prob->N, z, s);
     HIPCHK(hipGetLastError());
     return CBD_OK;
 }
@@ -1518,7 +1827,20 @@ extern "C" int rs_apply(cbd_factor f, int nrhs, const double* r, double* z, void
     if (r == z) return fail(CBD_EARG, "rs_apply: r and z alias");
     hipStream_t s = (hipStream_t)stream;
     ScopedTimer tm("apply", s);
-    return f->prec == CBD_PREC_FP64 ? apply_impl<double>(f, nrhs, r, z, s) : apply_impl<float>(f, nrhs, r, z, s);
+    const long tot = f->part->total;
+    return f->prec == CBD_PREC_FP64 ? apply_impl<double>(f, nrhs, r, z, 0, tot, s)
+                                    : apply_impl<float>(f, nrhs, r, z, 0, tot, s);
+}
+
+extern "C" int rs_apply_sub(cbd_factor f, int i, int nrhs, const double* r, double* z, void* stream) {
+    if (!f || !r || !z || nrhs < 1) return fail(CBD_EARG, "rs_apply_sub: bad argument");
+    if (r == z) return fail(CBD_EARG, "rs_apply_sub: r and z alias");
+    if (i < 0 || i >= (int)f->part->subs.size()) return fail(CBD_EARG, "rs_apply_sub: bad subdomain");
+    hipStream_t s = (hipStream_t)stream;
+    const Sub& sd = f->part->subs[i];
+    const long s0 = sd.offset, s1 = sd.offset + (long)sd.index.size();
+    return f->prec == CBD_PREC_FP64 ? apply_impl<double>(f, nrhs, r, z, s0, s1, s)
+                                    : apply_impl<float>(f, nrhs, r, z, s0, s1, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1569,7 +1891,7 @@ extern "C" int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* 
 
 extern "C" int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
                                   double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks,
-                                  int* chunks) {
+                                  int* chunks, int* sketched_pred, int* sketch_pred_rejected) {
     if (!f) return fail(CBD_EARG, "rs_factor_schedule: NULL factor");
     if (host_syncs) *host_syncs = f->host_syncs;
     if (qr_steps) *qr_steps = f->qr_steps;
@@ -1579,6 +1901,8 @@ extern "C" int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, 
     if (sketched) *sketched = f->sketched;
     if (sketch_fallbacks) *sketch_fallbacks = f->sketch_fallbacks;
     if (chunks) *chunks = f->chunks;
+    if (sketched_pred) *sketched_pred = f->sketched_pred;
+    if (sketch_pred_rejected) *sketch_pred_rejected = f->sketch_pred_rejected;
     return CBD_OK;
 }
 
@@ -1725,31 +2049,25 @@ extern "C" int pcg_solve(cbd_problem p, cbd_factor fac, int nrhs, const double* 
     if ((rc = q.precond(w.r, w.z, s))) return rc;
     launch_copy(w.p, w.z, NV, s);
     launch_dot(w.r, w.z, N, nrhs, w.partial, w.rz, s);
-    hipGraphExec_t gA = nullptr, gB = nullptr;
-    auto cleanup = [&]() {
-        if (gA) (void)hipGraphExecDestroy(gA);
-        if (gB) (void)hipGraphExecDestroy(gB);
-    };
+    // the executable graphs are destroyed on every return path
+    struct Graphs {
+        hipGraphExec_t a = nullptr, b = nullptr;
+        ~Graphs() {
+            if (a) (void)hipGraphExecDestroy(a);
+            if (b) (void)hipGraphExecDestroy(b);
+        }
+    } graphs;
+    hipGraphExec_t& gA = graphs.a;
+    hipGraphExec_t& gB = graphs.b;
     if (graph && maxit > 0 && n_active > 0) {
-        // everything a captured launch needs is allocated beforehand
-        if (fac && (rc = apply_prepare(fac, nrhs))) return rc;
         HIPCHK(hipStreamSynchronize(s));
-        if ((rc = capture(s, [&](hipStream_t cs) { return q.seqA(cs); }, &gA))) {
-            cleanup();
-            return rc;
-        }
-        if ((rc = capture(s, [&](hipStream_t cs) { return q.seqB(cs); }, &gB))) {
-            cleanup();
-            return rc;
-        }
+        if ((rc = capture(s, [&](hipStream_t cs) { return q.seqA(cs); }, &gA))) return rc;
+        if ((rc = capture(s, [&](hipStream_t cs) { return q.seqB(cs); }, &gB))) return rc;
     }
     for (int it = 1; it <= maxit && n_active > 0; ++it) {
         if (graph) {
             hipError_t e = hipGraphLaunch(gA, s);
-            if (e != hipSuccess) {
-                cleanup();
-                return fail(CBD_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
-            }
+            if (e != hipSuccess) return fail(CBD_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
         } else if ((rc = q.seqA(s))) {
             return rc;
         }
@@ -1767,17 +2085,13 @@ extern "C" int pcg_solve(cbd_problem p, cbd_factor fac, int nrhs, const double* 
         HIPCHK(hipMemcpyAsync(w.active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
         if (graph) {
             hipError_t e = hipGraphLaunch(gB, s);
-            if (e != hipSuccess) {
-                cleanup();
-                return fail(CBD_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
-            }
+            if (e != hipSuccess) return fail(CBD_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
         } else if ((rc = q.seqB(s))) {
             return rc;
         }
         HIPCHK(hipGetLastError());
     }
     HIPCHK(hipStreamSynchronize(s));
-    cleanup();
     // active[] on the host stays alive until the last async copy is done (synchronized above)
     return n_active > 0 ? CBD_WNOTCONV : CBD_OK;
 }

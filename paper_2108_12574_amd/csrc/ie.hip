@@ -1,5 +1,6 @@
 // Discretization (Section 2.1) and the dense on-the-fly product y = A x.
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -213,13 +214,196 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
     }
 }
 
-// c log F_j and 1/F_j (F_j = (1 + (j + 1/2)/2048)/2, c = -1/(4 pi)), uploaded once per device.
+// The same product on the 2D uniform grid, with the entries taken from a table.
+// Grid points are g = j1 + n j2 and x_i - x_j = spacing (j(i) - j(j)), so an entry
+// depends only on the offset (Delta1, Delta2) (the translation invariance the FFT form
+// uses as well).  A workgroup's rows are R = 64 kRB consecutive points of one grid
+// line, and a source tile is 64 consecutive points of one line (n a multiple of R);
+// the pair then meets only R + 63 offsets: Delta2 fixed and Delta1 = (i1_0 - j1_0) +
+// delta - 63 for delta = row offset - source offset + 63.  Each tile's R + 63 kernel
+// values are evaluated once into LDS (the pair i = j gets 0: the diagonal is added at
+// the end), and a lane's A operand is one LDS read at delta.  Products, summation
+// order and epilogue are those of k_matvec.
+template <int kRB>
+struct MvGridShared {
+    double swx[64 * kLdw];
+    double ktab[64 * kRB + 64];
+};
+
+template <int NB, int kRB>
+__global__ __launch_bounds__(kMvThreads) void k_matvec_grid2(ProblemView P, int nrhs,
+                                                             const double* __restrict__ x,
+                                                             double* __restrict__ y) {
+    __shared__ MvGridShared<kRB> sh;
+    constexpr int kR = kMvWaves * kRB * 16;   // rows per workgroup
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const long N = P.N;
+    const int n = P.n;
+    const int r0 = blockIdx.y * 64;
+    const long iw = (long)blockIdx.x * kR;            // first row of the workgroup
+    const long ibase = iw + wave * (kRB * 16);
+    const int li = lane & 15, lk = lane >> 4;
+    const long i2 = iw / n, i1_0 = iw % n;
+    const double sp2 = P.spacing * P.spacing;
+    // per-lane table position of row li, source lk at K-step 0 and row block 0
+    const int d0 = wave * (kRB * 16) + li - lk + 63;
+
+    v4d acc[kRB][NB];
+#pragma unroll
+    for (int rb = 0; rb < kRB; ++rb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    for (long j0 = 0; j0 < N; j0 += kTJ) {
+        __syncthreads();
+        {
+            // kernel values of the tile pair's offsets
+            const long d2 = i2 - j0 / n;
+            const long d1base = i1_0 - (j0 % n) - 63;
+            for (int e = tid; e < kR + 63; e += kMvThreads) {
+                const long d1 = d1base + e;
+                const long q = d1 * d1 + d2 * d2;
+                sh.ktab[e] = q == 0 ? 0.0 : laplace_from_r2<2>((double)q * sp2);
+            }
+            // w_j x_j, [rhs][j] (zero for padding columns)
+            const int sj = tid % kTJ, sr = tid / kTJ;
+            const long j = j0 + sj;
+            const double wj = P.w[j];
+            constexpr int kQ = NB * 16 / kSR;
+            double v[kQ];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int rr = min(r0 + sr + kSR * q, nrhs - 1);
+                v[q] = x[(long)rr * N + j];
+            }
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int r = sr + kSR * q;
+                sh.swx[r * kLdw + sj] = (r0 + r < nrhs) ? wj * v[q] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int ks = 0; ks < kTJ / 4; ++ks) {
+            const int jj = ks * 4 + lk;
+            const double* ta = sh.ktab + (d0 - ks * 4);
+            double a[kRB];
+#pragma unroll
+            for (int rb = 0; rb < kRB; ++rb) a[rb] = ta[rb * 16];
+            double b[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) b[nb] = sh.swx[(nb * 16 + li) * kLdw + jj];
+#pragma unroll
+            for (int rb = 0; rb < kRB; ++rb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[rb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[nb], acc[rb][nb], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int rb = 0; rb < kRB; ++rb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const long i = ibase + rb * 16 + 4 * v + lk;
+            const double bi = P.rs[i], di = P.diag[i];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int r = r0 + nb * 16 + li;
+                if (r < nrhs) {
+                    const long o = (long)r * N + i;
+                    y[o] = bi * acc[rb][nb][v] + di * x[o];
+                }
+            }
+        }
+    }
+}
+
+// One right-hand side on the 2D grid: grid lines take the place of the right-hand
+// sides in the MFMA columns.  Output line j2 receives, for every line offset Delta2,
+// the Toeplitz block T_Delta2 (entries K(spacing |(Delta1, Delta2)|)) times source line
+// j2 - Delta2, so 16 output lines b .. b + 15 share the A operand T_Delta2 and take
+// their B columns from 16 different source lines (zero where j2 - Delta2 leaves the
+// grid).  A workgroup owns 64 rows of 16 lines and runs over Delta2 = b - (n - 1) ..
+// b + 15 and source tiles of 64 points; A comes from the tile's table of 127 offsets as
+// in k_matvec_grid2.  The next tile's x and w are loaded into registers while the
+// current one is multiplied.  Every output sums its sources in ascending Delta2 and,
+// within a line, ascending position.
+struct MvLinesShared {
+    double sb[16 * kLdw];
+    double ktab[128];
+};
+
+__global__ __launch_bounds__(kMvThreads) void k_matvec_lines2(ProblemView P, const double* __restrict__ x,
+                                                              double* __restrict__ y) {
+    __shared__ MvLinesShared sh;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int n = P.n;
+    const long a = (long)blockIdx.x * 64;          // first row (position in the line)
+    const long b = (long)blockIdx.y * 16;          // first output line
+    const int li = lane & 15, lk = lane >> 4;
+    const double sp2 = P.spacing * P.spacing;
+    const int d0 = wave * 16 + li - lk + 63;
+    const int ntile = n / kTJ;
+    const long dlo = b - (n - 1), dhi = b + 15;
+    const long niter = (dhi - dlo + 1) * ntile;
+    // staging role: line column c = tid / 16, positions jj = (tid % 16) + 16 q
+    const int sc = tid >> 4, sj = tid & 15;
+    double xv[4], wv[4];
+    auto load = [&](long it) {
+        const long d2 = dlo + it / ntile;
+        const long t0 = (it % ntile) * kTJ;
+        const long src = b + sc - d2;                // source line of column sc
+        const bool in = src >= 0 && src < n;
+        const long base = (in ? src : 0) * (long)n + t0 + sj;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            xv[q] = in ? x[base + 16 * q] : 0.0;
+            wv[q] = in ? P.w[base + 16 * q] : 0.0;
+        }
+    };
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    load(0);
+    for (long it = 0; it < niter; ++it) {
+        const long d2 = dlo + it / ntile;
+        const long t0 = (it % ntile) * kTJ;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh.sb[sc * kLdw + sj + 16 * q] = wv[q] * xv[q];
+        if (tid < 127) {
+            const long d1 = a - t0 - 63 + tid;
+            const long qd = d1 * d1 + d2 * d2;
+            sh.ktab[tid] = qd == 0 ? 0.0 : laplace_from_r2<2>((double)qd * sp2);
+        }
+        if (it + 1 < niter) load(it + 1);
+        __syncthreads();
+#pragma unroll 4
+        for (int ks = 0; ks < kTJ / 4; ++ks) {
+            const double av = sh.ktab[d0 - 4 * ks];
+            const double bv = sh.sb[li * kLdw + 4 * ks + lk];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+    }
+    // register v of lane l: row 4 v + l / 16 of the wave's 16 rows, line b + l % 16
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const long i = (b + li) * (long)n + a + wave * 16 + 4 * v + lk;
+        y[i] = P.rs[i] * acc[v] + P.diag[i] * x[i];
+    }
+}
+
+// c log F_j and 1/F_j (F_j = (1 + (j + 1/2)/2048)/2, c = -1/(4 pi)): a device symbol,
+// filled once per device; host code passes its device address (hipGetSymbolAddress).
+__device__ __align__(256) double g_logtab[2 * kLogTab];
+
 static const double* log_table() {
-    static double* dtab[64] = {nullptr};
+    static std::mutex mx;
+    static const double* addr[64] = {nullptr};
     int dev = 0;
-    (void)hipGetDevice(&dev);
-    if (dev < 0 || dev >= 64) return nullptr;
-    if (!dtab[dev]) {
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mx);
+    if (!addr[dev]) {
         static double h[2 * kLogTab];
         const long double c = -0.25L / 3.141592653589793238462643383279502884L;
         for (int j = 0; j < kLogTab; ++j) {
@@ -227,15 +411,20 @@ static const double* log_table() {
             h[2 * j] = (double)(c * std::log(F));
             h[2 * j + 1] = (double)(1.0L / F);
         }
-        double* d = nullptr;
-        if (hipMalloc(&d, sizeof(h)) != hipSuccess) return nullptr;
+        void* d = nullptr;
+        if (hipGetSymbolAddress(&d, HIP_SYMBOL(g_logtab)) != hipSuccess || !d) return nullptr;
         if (hipMemcpy(d, h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
-        dtab[dev] = d;
+        addr[dev] = (const double*)d;
     }
-    return dtab[dev];
+    return addr[dev];
 }
 
 bool matvec_prepare() { return log_table() != nullptr; }
+
+// The table form needs whole grid lines per workgroup and per source tile.
+static bool matvec_grid_form(const ProblemView& P, int rb) {
+    return P.d == 2 && P.n % matvec_rows_per_block(rb) == 0 && P.n % kTJ == 0;
+}
 
 template <int D, int NB, int RB>
 static void matvec_launch(const ProblemView& P, int nrhs, const double* x, double* y, int max_blocks,
@@ -244,6 +433,10 @@ static void matvec_launch(const ProblemView& P, int nrhs, const double* x, doubl
     int blocks = (int)((P.N + rows - 1) / rows);
     if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
     dim3 grid(blocks, (nrhs + 63) / 64);
+    if (D == 2 && matvec_grid_form(P, RB)) {
+        hipLaunchKernelGGL((k_matvec_grid2<NB, RB>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y);
+        return;
+    }
     hipLaunchKernelGGL((k_matvec<D, NB, RB>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y, log_table());
 }
 
@@ -268,8 +461,20 @@ int matvec_default_rb(int nb) { return nb <= 2 ? 4 : 2; }
 
 void launch_matvec(const ProblemView& P, int nrhs, const double* x, double* y, int rb, int max_blocks,
                    hipStream_t s) {
+    if (nrhs == 1 && P.d == 2 && P.n % kTJ == 0 && max_blocks <= 0) {
+        // one right-hand side: grid lines fill the MFMA columns
+        hipLaunchKernelGGL(k_matvec_lines2, dim3(P.n / 64, P.n / 16), dim3(kMvThreads), 0, s, P, x, y);
+        return;
+    }
     const int nb = matvec_nb(nrhs);
     if (rb <= 0) rb = matvec_default_rb(nb);
+    // 2D grids whose lines hold whole workgroups use the table form: the largest row
+    // block count up to rb that fits
+    if (P.d == 2 && !matvec_grid_form(P, rb)) {
+        int r = rb;
+        while (r > 1 && !matvec_grid_form(P, r)) r /= 2;
+        if (matvec_grid_form(P, r)) rb = r;
+    }
     if (P.d == 2) {
         switch (nb) {
             case 1: matvec_rb<2, 1>(P, nrhs, x, y, rb, max_blocks, s); break;

@@ -20,6 +20,7 @@ struct ProblemView {
     const double* diag;  // b_i c_i A_ii
     const double* w;     // h^d c_j (column scale)
     const double* rs;    // b_i (row scale)
+    double spacing;      // distance between neighbouring grid points
 };
 
 // Natural logarithm of a positive, finite, normal double.  Range reduction
@@ -131,6 +132,11 @@ void launch_cpqr(int nbox, const BoxMeta* meta, double* Y, const int* act, int* 
                  int* k, double* T64, double tol, double tie, int m_max, int np_max, hipStream_t s);
 
 // State of the stepped pivoted QR between launches (per-level device arrays).
+// Register-resident pivoted QR of small boxes (at most 256 rows and 104 columns): one
+// 512-thread workgroup per box; outputs as launch_cpqr.
+bool cpqr_reg_fits(int m_max, int np_max);
+void launch_cpqr_reg(int nbox, int np_max, int m_max, const BoxMeta* meta, double* Y, const int* act, int* sr,
+                     int* perm, int* k, double* T64, double tol, double tie, hipStream_t s);
 struct QrState {
     double* norms;   // remaining column norms, per box at its act offset
     double* alpha;   // diagonal of R, per box at its act offset
@@ -185,8 +191,9 @@ void launch_root_apply(int nbox, int np_max, int unused, const BoxMeta* meta, co
 constexpr int kBigBox = 512;        // boxes with at least this many DOFs use the multi-workgroup path
 constexpr int kScratchCols = 64;    // elimination scratch per box: np^2 + kScratchCols * np
 
+// v[slot * nrhs + c] = r[c * N + cidx[slot]] for slots in [s0, s1), zero elsewhere
 template <typename R>
-void launch_gather(const double* r, long N, int nrhs, const int* cidx, long total, R* v,
+void launch_gather(const double* r, long N, int nrhs, const int* cidx, long total, long s0, long s1, R* v,
                    hipStream_t s);
 template <typename R>
 void launch_scatter(const R* v, int nrhs, const int* inv_ptr, const int* inv_slot, long N,

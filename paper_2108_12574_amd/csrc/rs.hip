@@ -383,6 +383,171 @@ void launch_cpqr(int nbox, const BoxMeta* meta, double* Y, const int* act, int* 
                            tie);
 }
 
+// Register-resident form for levels of many small boxes (at most 8 CPW columns and
+// 64 NR rows): one 512-thread workgroup per box holds the whole matrix in registers
+// (column q in wave q % 8, slot q / 8; lane l holds rows l + 64 t), so a pivot step
+// moves no matrix data through memory.  Columns are never moved: their current
+// positions are kept in LDS (pos, and inv for position -> column), which is all the
+// tie rule needs.  Per step: the largest remaining norm and the lowest position
+// within the tie window (two workgroup reductions); the pivot column's owner builds
+// the reflector in LDS; every wave reflects its columns and recomputes their norms
+// over the rows below the step.  The same arithmetic as k_cpqr per column (dot
+// product, update, norm), with sums in a different order.  At the end the R rows
+// 0 .. k-1 are written to Y in position order, and k, perm and sr as k_cpqr does;
+// T comes from k_qr_coeff.
+constexpr int kRegThreads = 512, kRegWaves = kRegThreads / 64;
+
+template <int CPW, int NR>
+__global__ __launch_bounds__(kRegThreads) void k_cpqr_reg(const BoxMeta* __restrict__ meta,
+                                                          double* __restrict__ Y, const int* __restrict__ act,
+                                                          int* __restrict__ sr, int* __restrict__ perm,
+                                                          int* __restrict__ kout, double tol, double tie) {
+    constexpr int kCols = kRegWaves * CPW, kRows = 64 * NR;
+    __shared__ double nrm[kCols];
+    __shared__ int pos[kCols], inv[kCols];
+    __shared__ double vbuf[kRows];
+    __shared__ double red[kRegWaves];
+    __shared__ int redi[kRegWaves];
+    __shared__ double s_beta;
+    const BoxMeta M = meta[blockIdx.x];
+    const int m = M.m, np = M.np;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double* Yb = Y + M.y;
+    double col[CPW][NR];
+    // load; norms of the full columns
+#pragma unroll
+    for (int sl = 0; sl < CPW; ++sl) {
+        const int q = sl * kRegWaves + w;
+        double ss = 0.0;
+#pragma unroll
+        for (int t = 0; t < NR; ++t) {
+            const int r = lane + 64 * t;
+            col[sl][t] = (q < np && r < m) ? Yb[r + (long)q * m] : 0.0;
+            ss += col[sl][t] * col[sl][t];
+        }
+        ss = wave_sum(ss);
+        if (lane == 0 && q < np) nrm[q] = sqrt(ss);
+    }
+    for (int q = tid; q < np; q += kRegThreads) {
+        pos[q] = q;
+        inv[q] = q;
+    }
+    for (int r = tid; r < kRows; r += kRegThreads) vbuf[r] = 0.0;
+    __syncthreads();
+    const int kmax = m < np ? m : np;
+    double nu0 = 0.0;
+    int k = 0;
+    for (int j = 0; j < kmax; ++j) {
+        // largest remaining norm (columns at positions >= j)
+        double lm = 0.0;
+        if (lane < CPW) {
+            const int q = lane * kRegWaves + w;
+            if (q < np && pos[q] >= j) lm = nrm[q];
+        }
+        lm = wave_max(lm);
+        if (lane == 0) red[w] = lm;
+        __syncthreads();
+        double mx = red[0];
+#pragma unroll
+        for (int u = 1; u < kRegWaves; ++u) mx = red[u] > mx ? red[u] : mx;
+        if (j == 0) nu0 = mx;
+        if (nu0 == 0.0 || mx <= tol * nu0) break;     // uniform over the workgroup
+        const double thr = mx - tie * nu0;
+        int lp = INT_MAX;
+        if (lane < CPW) {
+            const int q = lane * kRegWaves + w;
+            if (q < np && pos[q] >= j && nrm[q] >= thr) lp = pos[q];
+        }
+        lp = wave_min_int(lp);
+        if (lane == 0) redi[w] = lp;
+        __syncthreads();
+        int pp = redi[0];
+#pragma unroll
+        for (int u = 1; u < kRegWaves; ++u) pp = redi[u] < pp ? redi[u] : pp;
+        const int qp = inv[pp];                        // pivot column
+        const int qj = inv[j];                         // column at position j
+        const double xn = nrm[qp];
+        // reflector of the pivot column, built by its owner wave into vbuf
+        if (w == qp % kRegWaves) {
+            const int sl = qp / kRegWaves;
+            double x0 = 0.0;
+#pragma unroll
+            for (int s2 = 0; s2 < CPW; ++s2)
+                if (s2 == sl)
+#pragma unroll
+                    for (int t = 0; t < NR; ++t)
+                        if (lane + 64 * t == j) x0 = col[s2][t];
+            x0 = __shfl(x0, j & 63);
+            // (the lane holding row j broadcast it; every lane of the wave now has x0)
+            const double alpha = x0 >= 0.0 ? -xn : xn;
+            const double vn2 = 2.0 * xn * xn + 2.0 * fabs(x0) * xn;
+#pragma unroll
+            for (int s2 = 0; s2 < CPW; ++s2)
+                if (s2 == sl)
+#pragma unroll
+                    for (int t = 0; t < NR; ++t) {
+                        const int r = lane + 64 * t;
+                        if (r < kRows) vbuf[r] = r < j ? 0.0 : (r == j ? x0 - alpha : col[s2][t]);
+                        if (r == j) col[s2][t] = alpha;
+                        else if (r > j) col[s2][t] = 0.0;
+                    }
+            if (lane == 0) s_beta = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+        }
+        if (tid == 0) {
+            pos[qj] = pp;
+            inv[pp] = qj;
+            pos[qp] = j;
+            inv[j] = qp;
+        }
+        __syncthreads();
+        const double beta = s_beta;
+        double vr[NR];
+#pragma unroll
+        for (int t = 0; t < NR; ++t) vr[t] = vbuf[lane + 64 * t];
+        // reflect every remaining column of this wave; norms over the rows below j
+#pragma unroll
+        for (int sl = 0; sl < CPW; ++sl) {
+            const int q = sl * kRegWaves + w;
+            if (q >= np || pos[q] <= j) continue;      // (uniform over the wave)
+            double dt = 0.0;
+#pragma unroll
+            for (int t = 0; t < NR; ++t) dt = fma(vr[t], col[sl][t], dt);
+            dt = wave_sum(dt) * beta;
+            double ss = 0.0;
+#pragma unroll
+            for (int t = 0; t < NR; ++t) {
+                col[sl][t] = fma(-dt, vr[t], col[sl][t]);
+                const double y = lane + 64 * t > j ? col[sl][t] : 0.0;
+                ss = fma(y, y, ss);
+            }
+            ss = wave_sum(ss);
+            if (lane == 0) nrm[q] = sqrt(ss);
+        }
+        k = j + 1;
+        __syncthreads();
+    }
+    // R rows 0 .. k-1 (in position order) back to Y; rank, column order, skeleton lists
+#pragma unroll
+    for (int sl = 0; sl < CPW; ++sl) {
+        const int q = sl * kRegWaves + w;
+        if (q >= np) continue;
+        const int c = pos[q];
+#pragma unroll
+        for (int t = 0; t < NR; ++t) {
+            const int r = lane + 64 * t;
+            if (r < k) Yb[r + (long)c * m] = col[sl][t];
+        }
+    }
+    if (tid == 0) kout[blockIdx.x] = k;
+    for (int c = tid; c < np; c += kRegThreads) {
+        const int q = inv[c];
+        perm[M.act + c] = q;
+        sr[M.act + c] = act[M.act + q];
+    }
+}
+
+bool cpqr_reg_fits(int m_max, int np_max) { return m_max <= 64 * 4 && np_max <= kRegWaves * 13; }
+
 // Stepped form for levels with few, large boxes: one launch pair per pivot step
 // (pivot + reflector: one workgroup per box; update: kQrCols columns per
 // workgroup), so that all CUs share the reflections of the few boxes.  The
@@ -584,6 +749,20 @@ void launch_qr_finish(int nbox, int np_max, const BoxMeta* meta, double* Y, cons
     hipLaunchKernelGGL(k_qr_finish, dim3(nbox), dim3(kThreads), 0, s, meta, Y, st, act, sr, perm, k);
     hipLaunchKernelGGL(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s,
                        meta, Y, k, T64);
+}
+
+void launch_cpqr_reg(int nbox, int np_max, int m_max, const BoxMeta* meta, double* Y, const int* act, int* sr,
+                     int* perm, int* k, double* T64, double tol, double tie, hipStream_t s) {
+    if (nbox == 0) return;
+    // (up to 13 columns of 4 x 64 rows per wave: 104 registers of matrix, no spills)
+    if (np_max <= kRegWaves * 8)
+        hipLaunchKernelGGL((k_cpqr_reg<8, 4>), dim3(nbox), dim3(kRegThreads), 0, s, meta, Y, act, sr, perm, k, tol,
+                           tie);
+    else
+        hipLaunchKernelGGL((k_cpqr_reg<13, 4>), dim3(nbox), dim3(kRegThreads), 0, s, meta, Y, act, sr, perm, k,
+                           tol, tie);
+    hipLaunchKernelGGL(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s, meta,
+                       Y, k, T64);
 }
 
 // ---- row compression of tall proxy matrices ---------------------------------
@@ -1979,24 +2158,25 @@ void launch_big_cholesky_inverse(int nbig, int nr_max, const BoxMeta* meta, cons
 
 // ---- apply ------------------------------------------------------------------
 // v: local vectors of all subdomains, slot-major (v[slot * nrhs + c]).
+// Slots outside [s0, s1) are set to zero (the apply of one subdomain's term).
 template <typename R>
 __global__ void k_gather(const double* __restrict__ r, long N, int nrhs, const int* __restrict__ cidx,
-                         long total, R* __restrict__ v) {
+                         long total, long s0, long s1, R* __restrict__ v) {
     const long n = total * nrhs;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
         const long slot = e / nrhs;
         const int c = (int)(e % nrhs);
-        v[e] = (R)r[(long)c * N + cidx[slot]];
+        v[e] = (slot >= s0 && slot < s1) ? (R)r[(long)c * N + cidx[slot]] : (R)0;
     }
 }
 
 template <typename R>
-void launch_gather(const double* r, long N, int nrhs, const int* cidx, long total, R* v,
+void launch_gather(const double* r, long N, int nrhs, const int* cidx, long total, long s0, long s1, R* v,
                    hipStream_t s) {
     long n = total * nrhs;
     long b = (n + 255) / 256;
     if (b > 8192) b = 8192;
-    hipLaunchKernelGGL((k_gather<R>), dim3((int)b), dim3(256), 0, s, r, N, nrhs, cidx, total, v);
+    hipLaunchKernelGGL((k_gather<R>), dim3((int)b), dim3(256), 0, s, r, N, nrhs, cidx, total, s0, s1, v);
 }
 
 // z[:, g] = sum over the subdomain slots holding point g, in a fixed order
@@ -2181,7 +2361,7 @@ template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta
                                                  R*, int*, hipStream_t);                            \
     template void launch_root_apply<R>(int, int, int, const BoxMeta*, const int*, const int*, const R*, \
                                        R*, int, R*, R*, hipStream_t);                               \
-    template void launch_gather<R>(const double*, long, int, const int*, long, R*, hipStream_t);   \
+    template void launch_gather<R>(const double*, long, int, const int*, long, long, long, R*, hipStream_t); \
     template void launch_scatter<R>(const R*, int, const int*, const int*, long, double*,          \
                                     hipStream_t);                                                   \
     template void launch_apply_level<R>(int, const BoxMeta*, const int*, const int*, const R*, R*,  \

@@ -57,9 +57,14 @@ def test_every_compute_entry_point_rejects_bad_arguments_on_the_host():
         ("ie_assemble", lambda: L.ie_assemble(2, 16, 0, None, None, None, buf, buf, buf, None, ctypes.byref(h))),
         ("kernel_matvec", lambda: L.kernel_matvec(None, 1, buf, ctypes.c_void_p(32), None)),
         ("kernel_matvec_fft", lambda: L.kernel_matvec_fft(None, 1, buf, ctypes.c_void_p(32), None)),
-        ("cbd_fft_prepare", lambda: L.cbd_fft_prepare(None, 1, None)),
-        ("rs_factor_batched", lambda: L.rs_factor_batched(None, None, ctypes.byref(opts), None, ctypes.byref(h))),
+        ("cbd_fft_prepare", lambda: L.cbd_fft_prepare(None, 1, buf, 1 << 20, None)),
+        ("cbd_autotune_matvec", lambda: L.cbd_autotune_matvec(None, 1, buf, ctypes.c_void_p(32), None, None)),
+        ("rs_factor_batched", lambda: L.rs_factor_batched(None, None, ctypes.byref(opts), None, buf, 1 << 20,
+                                                          None, None, None, ctypes.byref(h))),
+        ("rs_factor_workspace", lambda: L.rs_factor_workspace(None, None, ctypes.byref(opts), None, None)),
+        ("rs_factor_rank_count", lambda: L.rs_factor_rank_count(None, ctypes.byref(opts), None)),
         ("rs_apply", lambda: L.rs_apply(None, 1, buf, ctypes.c_void_p(32), None)),
+        ("rs_apply_sub", lambda: L.rs_apply_sub(None, 0, 1, buf, ctypes.c_void_p(32), None)),
         ("pcg_solve", lambda: L.pcg_solve(None, None, 1, buf, buf, 1e-10, 10, 0, buf, 0,
                                           ctypes.byref(it), ctypes.byref(rr), None)),
         ("rank_mlp_forward", lambda: L.rank_mlp_forward(None, 4, buf, buf, None)),
@@ -118,3 +123,30 @@ def test_header_constants_match_the_binding():
             assert getattr(_lib, name) == int(val), name
             seen += 1
     assert seen >= 15
+
+
+@pytest.mark.parametrize("d,n,m,mode,leaf", [(2, 64, 16, cbd.MODE_CBD, 0), (2, 64, 4, cbd.MODE_SCHWARZ, 8),
+                                             (3, 16, 4, cbd.MODE_CBD, 0), (2, 32, 1, cbd.MODE_JACOBI, 4)])
+def test_rank_count_is_the_number_of_compressed_boxes(d, n, m, mode, leaf):
+    # the length of rank_hint / ranks_out: boxes of every level below the highest root,
+    # of the subdomains whose root lies above that level
+    import ctypes
+    part = cbd.Partition((d, n), m, 1, mode, leaf)
+    roots = [part.subdomain(i)[2] for i in range(part.D)]
+    Lmax = max(roots)
+    want = sum(len(part.level_boxes(i, l)[0]) for l in range(Lmax) for i in range(part.D) if roots[i] > l)
+    opts = _lib.RSOpts(1e-6, 64, 1.5, 0, 0, None, 0, 0, 0, 0, 0)
+    cnt = ctypes.c_int()
+    assert cbd.lib().rs_factor_rank_count(part.handle, ctypes.byref(opts), ctypes.byref(cnt)) == 0
+    assert cnt.value == want
+    opts.exact = 1      # exact subsolves: no compressed level
+    assert cbd.lib().rs_factor_rank_count(part.handle, ctypes.byref(opts), ctypes.byref(cnt)) == 0
+    assert cnt.value == 0
+
+
+def test_fft_workspace_size():
+    L = cbd.lib()
+    # 512^2: P = 1024, kernel transform + twiddles + 3 complex work arrays
+    want = 8 * 1024 ** 2 + 16 * 512 + 16 * 1024 ** 2 * 3
+    assert L.cbd_fft_workspace_bytes(2, 512, 3) == want
+    assert L.cbd_fft_workspace_bytes(4, 512, 3) == 0 and L.cbd_fft_workspace_bytes(2, 512, 0) == 0

@@ -49,9 +49,29 @@ def test_assemble_and_matvec(d, n, nrhs):
     assert np.abs(y - yr).max() <= 1e-13 * np.abs(yr).max()
 
 
-def test_matvec_node_grid_and_single_rhs_vector():
-    P = cbd.Problem(2, 24, grid=cbd.GRID_NODE, device=DEV)
-    O = ie.Problem(2, 24, grid=ie.GRID_NODE)
+@pytest.mark.parametrize("n,nrhs,coef", [(64, 1, True), (64, 20, False), (128, 5, True), (128, 64, True),
+                                         (256, 3, False), (256, 70, True), (128, 1, False), (512, 1, True)])
+def test_matvec_grid_table_form(n, nrhs, coef):
+    # 2D grids whose lines hold whole workgroups (n a multiple of 64) take the entries
+    # from per-tile tables of the grid offsets (one right-hand side: grid lines as the
+    # MFMA columns); same product as the oracle's
+    P, O = gpu_problem(2, n, coef=coef)
+    x = synth.rhs(O.N, nrhs, seed=11)
+    y = P.matvec(torch.tensor(x, device=DEV)).cpu().numpy()
+    if n <= 128:
+        ref = cmatvec.matvec(O, x.T).T
+    else:
+        rows = np.random.default_rng(3).choice(O.N, 64, replace=False)
+        ref = cmatvec.matvec(O, x.T, rows=rows).T
+        y = y[:, rows]
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n", [24, 64])
+def test_matvec_node_grid_and_single_rhs_vector(n):
+    # n = 64 takes the table form with the node grid's spacing 1/(n - 1)
+    P = cbd.Problem(2, n, grid=cbd.GRID_NODE, device=DEV)
+    O = ie.Problem(2, n, grid=ie.GRID_NODE)
     x = synth.rhs(O.N, 1, seed=2)[0]
     y = P.matvec(torch.tensor(x, device=DEV)).cpu().numpy()
     assert y.shape == (O.N,)
@@ -168,7 +188,11 @@ def test_exact_subsolves_match_oracle(mode, m, delta):
     dict(d=2, n=60, m=6, delta=2, mode=2, leaf=4, tol=1e-6, npxy=48, coef=False),     # CBD + tiles, ragged
     dict(d=3, n=16, m=4, delta=1, mode=2, leaf=0, tol=1e-6, npxy=256, coef=False),    # 3D
     dict(d=2, n=64, m=1, delta=0, mode=0, leaf=8, tol=1e-8, npxy=64, coef=False),     # global RS
-], ids=["coef", "schwarz_tiles", "cbd_tiles", "3d", "global_rs"])
+    # sublinear partition counts (M ~ N^(6/7) in 2D, N^(3/4) in 3D, Section 4.4): partitions
+    # of 3 x 3 and 2 x 2 x 2 points
+    dict(d=2, n=120, m=40, delta=1, mode=2, leaf=0, tol=1e-6, npxy=64, coef=True),
+    dict(d=3, n=12, m=6, delta=1, mode=2, leaf=0, tol=1e-6, npxy=256, coef=False),
+], ids=["coef", "schwarz_tiles", "cbd_tiles", "3d", "global_rs", "sublinear_2d", "sublinear_3d"])
 def test_factor_and_apply_other_layouts(case):
     print("case", case, flush=True)
     P, O = gpu_problem(case["d"], case["n"], case["coef"])
@@ -548,6 +572,54 @@ def test_sketched_ids_match_oracle(case):
     assert rel(z, R.apply(r.T).T) <= 1e-10
 
 
+def _hint_dict(opart, hint):
+    """{(subdomain, level, box): rank} from a flat rank list in the factor's batch order
+    (level by level; within a level subdomain by subdomain, boxes in partition order)."""
+    out, h = {}, 0
+    Lmax = max(sd.root_level for sd in opart.subdomains)
+    for l in range(Lmax):
+        for i, sd in enumerate(opart.subdomains):
+            if sd.root_level <= l:
+                continue
+            for b in range(len(sd.levels[l])):
+                out[(i, l, b)] = int(hint[h])
+                h += 1
+    assert h == len(hint)
+    return out
+
+
+@pytest.mark.parametrize("case,scale", [("2d64_m4", 1.0), ("2d64_m4", 0.5), ("3d32_m4", 1.0)])
+def test_rank_sized_sketches_match_oracle(case, scale):
+    # rank hints (a deterministic factorization's ranks, or half of them) size a first,
+    # smaller sketch per box; kept when k <= rows / 4, else the shape-based sketch runs.
+    # Box by box equal to the oracle's sketched RS given the same predictions
+    if case == "2d64_m4":
+        d, n, m, delta, mode, leaf, tol, npxy = 2, 64, 4, 1, dd.CBD, 0, 1e-6, 64
+    else:    # the paper's 3D layout (8^3 points per partition) at its tolerance
+        d, n, m, delta, mode, leaf, tol, npxy = 3, 32, 4, 1, dd.CBD, 0, 1e-3, 256
+    P, O = gpu_problem(d, n)
+    part = cbd.Partition(P, m, delta, mode, leaf)
+    opart = dd.Partition(d, n, m, delta, mode, leaf)
+    F0 = cbd.Factor(P, part, tol=tol, n_pxy=npxy)
+    hint = (F0.ranks[:F0.n_ranks].cpu().numpy() * scale).astype(np.int32)
+    F = cbd.Factor(P, part, tol=tol, n_pxy=npxy, sketch_seed=777, rank_hint=hint)
+    R = rs.RSPreconditioner(O, opart, tol, n_pxy=npxy, sketch_seed=777, rank_pred=_hint_dict(opart, hint))
+    sch = F.schedule()
+    opred = sum(s.sketched_pred for s in R.subs)
+    print(case, scale, "sketched", sch["sketched"], "rank-sized", sch["sketched_pred"], "rejected",
+          sch["sketch_pred_rejected"], "oracle rank-sized", opred, flush=True)
+    assert sch["sketched"] == sum(s.sketched for s in R.subs)
+    assert sch["sketched_pred"] == opred
+    if scale == 1.0:
+        assert opred > 0
+    else:
+        assert sch["sketch_pred_rejected"] > 0
+    _compare_factor(F, R, opart, tol_T=1e-7)
+    r = synth.rhs(O.N, 3, seed=4)
+    z = F.apply(torch.tensor(r, device=DEV)).cpu().numpy()
+    assert rel(z, R.apply(r.T).T) <= 1e-10
+
+
 def test_sketched_ids_full_size_pcg():
     # 512^2 benchmark layout with randomized IDs (FP32 factors): PCG reaches 1e-10 in
     # about as many iterations as with deterministic IDs; true residual on sampled rows
@@ -580,7 +652,9 @@ def test_chunked_levels_give_the_same_factors(case):
         P, _ = gpu_problem(2, 64)
         part, tol = cbd.Partition(P, 16, 1, cbd.MODE_CBD, 0), 1e-8
         seed = 7 if case == "cfg1_sketch" else None
-    F0 = cbd.Factor(P, part, tol=tol, n_pxy=64, sketch_seed=seed)
+    # a generous workspace: no level is split
+    big = torch.empty(1 << 30, dtype=torch.uint8, device=DEV)
+    F0 = cbd.Factor(P, part, tol=tol, n_pxy=64, sketch_seed=seed, ws=big)
     F1 = cbd.Factor(P, part, tol=tol, n_pxy=64, sketch_seed=seed, workspace_bytes=2 << 20)
     s0, s1 = F0.schedule(), F1.schedule()
     nlev = F0.stats()["levels"]

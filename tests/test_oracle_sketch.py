@@ -91,3 +91,62 @@ def test_sketched_preconditioner_keeps_the_iteration_count():
     it0 = pcg.pcg(lambda x: A @ x, R0.apply, f, tol=1e-10, maxit=200)[1]
     it1 = pcg.pcg(lambda x: A @ x, R1.apply, f, tol=1e-10, maxit=200)[1]
     assert abs(it1 - it0) <= 1
+
+
+def test_predicted_sketch_size_rule():
+    # 4 k_p + 32 rows when below the shape-based size, else none
+    assert sketch.predicted_sketch_size(400, 300, 10) == 72        # shape size 188
+    assert sketch.predicted_sketch_size(400, 300, 38) == 184
+    assert sketch.predicted_sketch_size(400, 300, 40) == 0         # 192 >= 188
+    assert sketch.predicted_sketch_size(60, 300, 1) == 0           # no sketch at all
+
+
+@pytest.mark.parametrize("r", [5, 20, 35])
+def test_predicted_size_sketch_is_exact_on_low_rank(r):
+    rng = np.random.default_rng(r)
+    m, n = 400, 300
+    Y = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
+    k, perm, T, used = sketch.interp_decomp_sketched(Y, 1e-12, 3, 11, np.arange(m), k_pred=r)
+    assert used and k == r
+    assert np.linalg.norm(Y[:, perm[k:]] - Y[:, perm[:k]] @ T) <= 1e-10 * np.linalg.norm(Y)
+
+
+def test_rejected_prediction_gives_the_shape_sketch():
+    # rank 20 with a prediction of 0: the 32-row sketch finds k = 20 > 32/4, so the box
+    # goes on to the shape-based sketch, and the result is the one without a prediction
+    rng = np.random.default_rng(1)
+    m, n = 400, 300
+    Y = rng.standard_normal((m, 20)) @ rng.standard_normal((20, n))
+    a = sketch.interp_decomp_sketched(Y, 1e-12, 3, 11, np.arange(m), k_pred=0)
+    b = sketch.interp_decomp_sketched(Y, 1e-12, 3, 11, np.arange(m))
+    assert a[0] == b[0] == 20 and a[3] and b[3]
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+@pytest.mark.parametrize("scale", [1.0, 0.5])
+def test_predicted_size_sketched_rs_id_error(scale):
+    # 64^2 with 4^2 partitions (boxes of 324 points), tol 1e-6: with predictions equal to
+    # (or half) the deterministic ranks, every ID still meets the accuracy target against
+    # the box's full far field
+    O = ie.Problem(2, 64)
+    part = dd.Partition(2, 64, 4, 1, dd.CBD)
+    tol = 1e-6
+    sd = part.subdomains[0]
+    f0 = rs.factor_subdomain(O, part, sd, tol, 64)
+    pred = {(0, b): int(scale * len(bf.sk)) for b, bf in enumerate(f0.levels[0])}
+    assert all(sketch.predicted_sketch_size(400, len(bf.sk) + len(bf.rd), pred[(0, b)])
+               for b, bf in enumerate(f0.levels[0]))
+    f = rs.factor_subdomain(O, part, sd, tol, 64, sketch_seed=5, sub=0, rank_pred=pred)
+    assert f.sketched > 0
+    if scale == 1.0:
+        assert f.sketched_pred > 0      # the rank-sized sketch was accepted
+    g = sd.index
+    worst = 0.0
+    for b in f.levels[0]:
+        p = np.concatenate([b.sk, b.rd])
+        far = np.setdiff1d(np.arange(len(g)), p)
+        Ysk, Yrd = O.block(g[far], g[b.sk]), O.block(g[far], g[b.rd])
+        if len(b.rd):
+            worst = max(worst, np.linalg.norm(Yrd - Ysk @ b.T) / np.linalg.norm(np.hstack([Ysk, Yrd])))
+    print("worst relative far-field ID error", worst)
+    assert worst <= 30 * tol
