@@ -343,6 +343,18 @@ def main():
         torch.cuda.synchronize()
         cbd.timing.enable(False)
         mv_ms, mv_n = cbd.timing.get("matvec")
+    # one product with a single right-hand side (the plain FP64 form's matvec)
+    mv1_ms = None
+    if dense:
+        cbd.timing.reset()
+        cbd.timing.enable(True)
+        for _ in range(3):
+            P.matvec(F_rhs[0])
+        torch.cuda.synchronize()
+        cbd.timing.enable(False)
+        t1, n1 = cbd.timing.get("matvec")
+        mv1_ms = t1 / max(n1, 1)
+        cbd.timing.reset()
     # matvec roofline: product flops 2 N^2 nrhs per launch (kernel evaluations extra)
     mv_avg_s = mv_ms / 1e3 / mv_n if mv_n else None
     mv_flops = 2.0 * N * N * nrhs
@@ -481,6 +493,7 @@ def main():
         "n_it": [min(n_it), max(n_it)],
         "max_relres": max(rr_all),
         "matvec_avg_ms": mv_avg_s * 1e3 if mv_avg_s else None,
+        "matvec_1rhs_ms": mv1_ms,
         "apply_avg_ms": ap_ms / max(ap_n, 1),
         "matvec_tile_rows_per_wave": 16 * tile,
         "sketched_id_variant": sketched,
