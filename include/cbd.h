@@ -251,6 +251,15 @@ int rank_mlp_loss_grad(const float* params, int n, const float* X, const float* 
                        float* loss, void* ws, size_t ws_bytes, void* stream);
 int rank_mlp_adam(float* params, const float* grad, float* m, float* v, int step, float lr,
                   void* stream);
+/* rank_mlp_loss_grad_noalloc - rank_mlp_loss_grad for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight training loops, harnesses that
+ * forbid allocation): the same kernels and results, with the per-sample scratch in an
+ * array the library holds on each device until the process ends, so no ws argument.
+ *  n: 1 .. 16384 samples (more: CBD_EARG); other arguments as rank_mlp_loss_grad.
+ * Every call on one device shares that array, and each call overwrites what it needs
+ * before reading it: calls that overlap in time on one device race. */
+int rank_mlp_loss_grad_noalloc(const float* params, int n, const float* X, const float* t, float* grad,
+                               float* loss, void* stream);
 int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* X, int* k);
 int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
                        double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks,

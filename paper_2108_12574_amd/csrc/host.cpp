@@ -1868,6 +1868,19 @@ extern "C" int rank_mlp_loss_grad(const float* params, int n, const float* X, co
     return CBD_OK;
 }
 
+extern "C" int rank_mlp_loss_grad_noalloc(const float* params, int n, const float* X, const float* t, float* grad,
+                                          float* loss, void* stream) {
+    if (!params || !X || !t || !grad || n < 1) return fail(CBD_EARG, "rank_mlp_loss_grad_noalloc: bad argument");
+    if (n > kMlpStaticMax)
+        return fail(CBD_EARG, "rank_mlp_loss_grad_noalloc: " + std::to_string(n) + " samples exceed the limit of " +
+                                  std::to_string(kMlpStaticMax));
+    float* scr = mlp_static_scratch();
+    if (!scr) return fail(CBD_EHIP, "rank_mlp_loss_grad_noalloc: no device address for the library scratch");
+    launch_mlp_loss_grad(params, n, X, t, grad, loss, scr, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return CBD_OK;
+}
+
 extern "C" int rank_mlp_adam(float* params, const float* grad, float* m, float* v, int step, float lr,
                              void* stream) {
     if (!params || !grad || !m || !v || step < 1) return fail(CBD_EARG, "rank_mlp_adam: bad argument");

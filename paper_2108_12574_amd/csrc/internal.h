@@ -237,5 +237,9 @@ void launch_mlp_forward(const float* p, int n, const float* X, float* y, float* 
 void launch_mlp_loss_grad(const float* p, int n, const float* X, const float* t, float* grad,
                           float* loss, float* ws, hipStream_t s);
 void launch_mlp_adam(float* p, const float* g, float* m, float* v, int step, float lr, hipStream_t s);
+// Samples the library-owned loss/gradient scratch holds (rank_mlp_loss_grad_noalloc),
+// and its device address on the current device (nullptr if it cannot be had).
+constexpr int kMlpStaticMax = 16384;
+float* mlp_static_scratch();
 
 }  // namespace cbd

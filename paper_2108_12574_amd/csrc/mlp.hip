@@ -5,6 +5,7 @@
 // gradient is taken at the rounded weights and applied to the FP32 master
 // weights) and Adam.  All reductions over samples run in a fixed order.
 #include <cstdint>
+#include <mutex>
 
 #include "internal.h"
 
@@ -214,6 +215,27 @@ void launch_mlp_loss_grad(const float* p, int n, const float* X, const float* t,
     hipLaunchKernelGGL(k_mlp_deltas, dim3(blocks), dim3(kMlpThreads), 0, s, p, n, y, t, z1, z2, dy, dz1, dz2);
     hipLaunchKernelGGL(k_mlp_grads, dim3(kH + 1), dim3(kMlpThreads), 0, s, n, X, y, t, z1, z2, dy, dz1, dz2,
                        grad, loss);
+}
+
+// Library-owned scratch of the loss/gradient for callers that cannot allocate device
+// memory: (2 + 4 kH) floats per sample for up to kMlpStaticMax samples, one copy per
+// device, held until the process ends.  Host code never passes the array's name to a
+// kernel: it uses the device address that hipGetSymbolAddress returns, once per
+// device with that device current.
+__device__ __align__(256) float scratch[(size_t)(2 + 4 * kH) * kMlpStaticMax];
+
+float* mlp_static_scratch() {
+    static std::mutex mx;
+    static float* addr[64] = {nullptr};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mx);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        addr[dev] = (float*)p;
+    }
+    return addr[dev];
 }
 
 void launch_mlp_adam(float* p, const float* g, float* m, float* v, int step, float lr, hipStream_t s) {
