@@ -99,20 +99,35 @@ def oracle_solution(args_workload, n):
     return np.load(path) if os.path.exists(path) else None
 
 
+# Layouts whose ranks train the rank predictor: a mixed stream of 2D grids from 128^2 to
+# 512^2 (N/M = 64, tol 1e-6), the 64^2 (tol 1e-8) and 256^2 Schwarz workloads, and 3D
+# grids at the paper's 3D layout (N/M = 512, tol 1e-3) and at tol 1e-6.
+# (d, n, m, mode, delta, leaf, tol, n_pxy)
+TRAIN_LAYOUTS = [(2, 128, 16, "cbd", 1, 0, 1e-6, 64), (2, 192, 24, "cbd", 1, 0, 1e-6, 64),
+                 (2, 256, 32, "cbd", 1, 0, 1e-6, 64), (2, 320, 40, "cbd", 1, 0, 1e-6, 64),
+                 (2, 384, 48, "cbd", 1, 0, 1e-6, 64), (2, 448, 56, "cbd", 1, 0, 1e-6, 64),
+                 (2, 512, 64, "cbd", 1, 0, 1e-6, 64), (2, 64, 16, "cbd", 1, 0, 1e-8, 64),
+                 (2, 256, 4, "schwarz", 8, 8, 1e-6, 64), (3, 16, 4, "cbd", 1, 0, 1e-6, 256),
+                 (3, 24, 3, "cbd", 1, 0, 1e-3, 256), (3, 32, 4, "cbd", 1, 0, 1e-3, 256)]
+# held out: 2D 1024^2 (N/M = 64, tol 1e-6) and 3D 48^3 (N/M = 512, tol 1e-3)
+HELD_OUT = [(2, 1024, 128, "cbd", 1, 0, 1e-6, 64), (3, 48, 6, "cbd", 1, 0, 1e-3, 256)]
+
+
+def layout_ranks(cbd, dev, lay):
+    d, n, m, mode, delta, leaf, tol, npxy = lay
+    mode = {"cbd": cbd.MODE_CBD, "schwarz": cbd.MODE_SCHWARZ, "jacobi": cbd.MODE_JACOBI}[mode]
+    Pt = cbd.Problem(d, n, device=dev)
+    Ft = cbd.Factor(Pt, cbd.Partition(Pt, m, delta, mode, leaf), tol=tol, n_pxy=npxy, precision=cbd.PREC_FP32)
+    return Ft.all_features()
+
+
 def train_rank_predictor(cbd, dev):
-    """Skeleton-rank MLP trained by the library's kernels on (features, rank) pairs
-    of the 64^2 (tol 1e-8), 256^2 Schwarz (tol 1e-6) and 512^2 (tol 1e-6)
-    factorizations, plus a small 3D one (16^3, tol 1e-6)."""
+    """Skeleton-rank MLP trained by the library's kernels on (features, rank) pairs of
+    TRAIN_LAYOUTS' factorizations; returns the network and its held-out rank errors."""
     import numpy as np
     Xs, ks = [], []
-    for d, n, m, tol, mode, delta, leaf, npxy in [(2, 64, 16, 1e-8, cbd.MODE_CBD, 1, 0, 64),
-                                                  (2, 256, 4, 1e-6, cbd.MODE_SCHWARZ, 8, 8, 64),
-                                                  (2, 512, 64, 1e-6, cbd.MODE_CBD, 1, 0, 64),
-                                                  (3, 16, 4, 1e-6, cbd.MODE_CBD, 1, 0, 256)]:
-        Pt = cbd.Problem(d, n, device=dev)
-        Ft = cbd.Factor(Pt, cbd.Partition(Pt, m, delta, mode, leaf), tol=tol, n_pxy=npxy,
-                        precision=cbd.PREC_FP32)
-        X, k = Ft.all_features()
+    for lay in TRAIN_LAYOUTS:
+        X, k = layout_ranks(cbd, dev, lay)
         Xs.append(X)
         ks.append(k)
     rng = np.random.default_rng(0)
@@ -122,7 +137,13 @@ def train_rank_predictor(cbd, dev):
                          rng.standard_normal(H) * np.sqrt(1.0 / H), np.zeros(1)]).astype(np.float32)
     net = cbd.RankMLP(p0, dev)
     net.train(np.concatenate(Xs), np.concatenate(ks), steps=1500, lr=1e-2)
-    return net
+    held = {}
+    for lay in HELD_OUT:
+        X, k = layout_ranks(cbd, dev, lay)
+        kp = net.predict_ranks(X).cpu().numpy()
+        held["%dd_%d" % (lay[0], lay[1])] = {"boxes": int(len(k)), "mean_k": float(np.mean(k)),
+                                            "mean_abs_err": float(np.mean(np.abs(kp - k)))}
+    return net, held
 
 
 # Size series for the complexity study of Section 4.4: (n, m) pairs.  "sublinear": m
@@ -260,9 +281,9 @@ def main():
     tile1 = P.autotune_matvec(1) if dense else 0
     log("matvec tile: %d row blocks per wave (%d RHS), %d (1 RHS)" % (tile, nrhs, tile1))
 
-    # rank predictor trained on ranks of the 64^2, 256^2 and 512^2 factorizations
+    # rank predictor trained on ranks of a mixed stream of factorizations
     t0 = time.perf_counter()
-    mlp = train_rank_predictor(cbd, dev)
+    mlp, mlp_held = train_rank_predictor(cbd, dev)
     torch.cuda.synchronize()
     mlp_train_s = time.perf_counter() - t0
     log("rank predictor trained in %.2f s" % mlp_train_s)
@@ -322,6 +343,32 @@ def main():
         factor_nm_s = time.perf_counter() - t0
         sched_nm = fac_nm.schedule()
         del fac_nm
+    # what the predictor gains on a sketched 3D factorization (64^3, N/M = 512, tol 1e-3):
+    # rank-sized first sketches; same PCG iteration counts
+    mlp_gain_3d = None
+    if full:
+        P3 = cbd.Problem(3, 64, device=dev)
+        part3 = cbd.Partition(P3, 8, 1, cbd.MODE_CBD, 0)
+        f3 = torch.tensor(synth.rhs(64 ** 3, 1, seed=0), device=dev)
+        P3.fft_prepare(max_pairs=1)
+        leg = {}
+        for name, net in (("without", None), ("with", mlp)):
+            times = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                F3 = cbd.Factor(P3, part3, tol=1e-3, n_pxy=256, precision=cbd.PREC_FP32, mlp=net, sketch_seed=1,
+                                apply_rhs=1)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            _, it3, _ = cbd.pcg_solve(P3, F3, f3[0], tol=1e-10, maxit=300, fft=True)
+            sc3 = F3.schedule()
+            leg[name] = {"factor_s": float(np.median(times)), "flops": F3.stats()["flops"], "n_it": it3,
+                         "rank_sized_sketches": sc3["sketched_pred"], "sketched": sc3["sketched"]}
+            del F3
+        mlp_gain_3d = leg
+        log("predictor on 3D 64^3: %s" % leg)
+        del P3, part3, f3
     pcg_s = float(np.mean(ts))
     n_it = its_all[-1]
     u_ref = oracle_solution(args.workload, n)
@@ -503,6 +550,7 @@ def main():
                                 "note": "same factors; products with A by circulant-embedding FFT (Section 5 of "
                                         "the paper) instead of the dense on-the-fly matvec"} if full else None,
         "rank_predictor": {"train_s": mlp_train_s, "mean_abs_rank_err": sched["mean_abs_err"],
+                           "held_out": mlp_held, "sketch_3d": mlp_gain_3d,
                            "factor_s_with": factor_s, "factor_s_without": factor_nm_s,
                            "host_syncs_with": sched["host_syncs"], "host_syncs_without": sched_nm["host_syncs"],
                            "mispredicted_boxes": sched["mispredicted"]},

@@ -12,25 +12,43 @@ namespace cbd {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+// Wave-wide reductions by DPP lane moves (no LDS round trips): quad_perm [1,0,3,2] and
+// [2,3,0,1] combine lanes l ^ 1 and l ^ 2, row_ror 4 and 8 the four quads of each row
+// of 16 lanes, and the four row results are read from lanes 0, 16, 32 and 48.  Every
+// lane returns the total.  A double moves as its two 32-bit halves.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppRor4 = 0x124, kDppRor8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
 }
-template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        T u = __shfl_xor(v, o);
-        v = u > v ? u : v;
-    }
-    return v;
+__device__ __forceinline__ double lane_f64(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppRor4>(v);
+    v += dpp_f64<kDppRor8>(v);
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, dpp_f64<kDppXor1>(v));
+    v = fmax(v, dpp_f64<kDppXor2>(v));
+    v = fmax(v, dpp_f64<kDppRor4>(v));
+    v = fmax(v, dpp_f64<kDppRor8>(v));
+    return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
 }
 __device__ __forceinline__ int wave_min_int(int v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        int u = __shfl_xor(v, o);
-        v = u < v ? u : v;
-    }
-    return v;
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppXor1, 0xF, 0xF, true));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppXor2, 0xF, 0xF, true));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppRor4, 0xF, 0xF, true));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppRor8, 0xF, 0xF, true));
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // ---- proxy / near-field matrix ---------------------------------------------

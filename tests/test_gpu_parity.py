@@ -669,9 +669,12 @@ def test_chunked_levels_give_the_same_factors(case):
             count[i] = b + 1
             g0, g1 = F0.box(i, l, b), F1.box(i, l, b)
             assert np.array_equal(g0["sk"], g1["sk"]) and np.array_equal(g0["rd"], g1["rd"])
+            # a chunk can send a batch to another form of the pivoted QR (register-resident
+            # or streamed), whose sums run in another order: T, E, G^-1 agree to the
+            # cond(R11)-limited tolerance of the oracle comparisons
             for key in ("T", "E", "Ginv", "Bss"):
                 if g0[key].size:
-                    assert rel(g1[key], g0[key]) <= 1e-9, (l, i, b, key)
+                    assert rel(g1[key], g0[key]) <= 1e-7, (l, i, b, key)
     r = torch.tensor(synth.rhs(P.N, 2, seed=3), device=DEV)
     z0, z1 = F0.apply(r), F1.apply(r)
     assert (z1 - z0).norm() <= 1e-10 * z0.norm()
