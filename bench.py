@@ -279,7 +279,7 @@ def main():
     # tile shape of the matvec, chosen by the library's autotuner
     tile = P.autotune_matvec(nrhs) if dense else 0
     tile1 = P.autotune_matvec(1) if dense else 0
-    log("matvec tile: %d row blocks per wave (%d RHS), %d (1 RHS)" % (tile, nrhs, tile1))
+    log("matvec tile shape: %d (%d RHS), %d (1 RHS)" % (tile, nrhs, tile1))
 
     # rank predictor trained on ranks of a mixed stream of factorizations
     t0 = time.perf_counter()
@@ -295,7 +295,17 @@ def main():
     ws_factor = torch.empty(int(fac0.ws_used * 1.05) + (1 << 20), dtype=torch.uint8, device=dev)
     del fac0
     ws_pcg = cbd.pcg_workspace(P, nrhs)
-    box = {"fac": None}
+    box = {"fac": None, "graph": False}
+    side = torch.cuda.Stream(device=dev)    # PCG with captured HIP graphs needs a non-default stream
+
+    def solve(fac, graph):
+        if not graph:
+            return cbd.pcg_solve(P, fac, F_rhs, tol=pcg_tol, maxit=200, fft=use_fft, ws=ws_pcg)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            out = cbd.pcg_solve(P, fac, F_rhs, tol=pcg_tol, maxit=200, fft=use_fft, ws=ws_pcg, graph=True)
+        torch.cuda.current_stream(dev).wait_stream(side)
+        return out
 
     def step():
         box["fac"] = None           # the previous factor views ws_factor: release it first
@@ -304,12 +314,20 @@ def main():
                          apply_rhs=nrhs, ws=ws_factor)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        u, its, rr = cbd.pcg_solve(P, fac, F_rhs, tol=pcg_tol, maxit=200, fft=use_fft, ws=ws_pcg)
+        u, its, rr = solve(fac, box["graph"])
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         box["fac"] = fac
         return fac, u, its, rr, t1 - t0, t2 - t1
 
+    # eager or graph-replayed PCG iterations: the faster one, measured once, runs the timed steps
+    pcg_modes = {}
+    for graph in (False, True):
+        box["graph"] = graph
+        pcg_modes["graph" if graph else "eager"] = step()[5]
+    box["graph"] = pcg_modes["graph"] < pcg_modes["eager"]
+    log("pcg eager %.3f s, graph %.3f s: timed steps use %s" % (pcg_modes["eager"], pcg_modes["graph"],
+                                                                 "graphs" if box["graph"] else "eager launches"))
     for w in range(args.warmup):
         step()
         log("warmup step %d done" % w)
@@ -383,10 +401,12 @@ def main():
     uerr("mixed_batched", u_main[0])
 
     if mv_n == 0 and dense:
-        # the PCG used FFT products: time one dense product for the roofline record
+        # the PCG used FFT products or replayed graphs (no timer events inside a capture):
+        # time three dense products for the roofline record
         cbd.timing.reset()
         cbd.timing.enable(True)
-        P.matvec(F_rhs)
+        for _ in range(3):
+            P.matvec(F_rhs)
         torch.cuda.synchronize()
         cbd.timing.enable(False)
         mv_ms, mv_n = cbd.timing.get("matvec")
@@ -539,10 +559,13 @@ def main():
         "factor_bytes": st["bytes"],
         "n_it": [min(n_it), max(n_it)],
         "max_relres": max(rr_all),
+        "pcg_launch_mode": {"timed": "graph" if box["graph"] else "eager", "eager_s": pcg_modes["eager"],
+                            "graph_s": pcg_modes["graph"]},
         "matvec_avg_ms": mv_avg_s * 1e3 if mv_avg_s else None,
         "matvec_1rhs_ms": mv1_ms,
         "apply_avg_ms": ap_ms / max(ap_n, 1),
-        "matvec_tile_rows_per_wave": 16 * tile,
+        "matvec_tile": {"shape": tile, "rows_per_wave": 16 * (tile & 7), "waves_per_workgroup": 8 if tile >= 8 else 4,
+                        "chosen_by": "cbd_autotune_matvec"},
         "sketched_id_variant": sketched,
         "bf16_gemm_variant": bf16,
         "pcg_with_fft_matvec": {"pcg_s": pcg_fft_s, "n_it": [min(its_fft), max(its_fft)],

@@ -306,9 +306,15 @@ int kernel_matvec_fft(cbd_problem p, int nrhs, const double* x, double* y, void*
  * `stream`; later kernel_matvec calls with the
  * same number of 16-column right-hand-side blocks use it.  Each candidate runs on
  * the first min(grid, 1024) workgroups.  x, y: device scratch of N x min(nrhs, 64)
- * doubles each (overwritten; distinct).  *choice (may be NULL) receives the rows
- * per wave / 16. */
+ * doubles each (overwritten; distinct).  On 2D grids the candidates include
+ * workgroups of 8 waves.  *choice (may be NULL) receives the shape, coded as for
+ * cbd_matvec_set_shape. */
 int cbd_autotune_matvec(cbd_problem p, int nrhs, double* x, double* y, void* stream, int* choice);
+/* cbd_matvec_set_shape - fix the matvec's tile shape for nrhs (as chosen by
+ * cbd_autotune_matvec): shape = row blocks of 16 per wave (1, 2 or 4) with 4 waves per
+ * workgroup, or 8 + that (9, 10, 12) with 8 waves per workgroup, the latter only on 2D
+ * grids whose side is a multiple of the workgroup's rows.  Host only. */
+int cbd_matvec_set_shape(cbd_problem p, int nrhs, int shape);
 
 /* pcg_solve - preconditioned CG (Section 5) on A u = f for nrhs independent
  * right-hand sides: u0 = 0, stop a column when ||r||_2/||f||_2 <= tol (the

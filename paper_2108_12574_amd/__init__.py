@@ -104,6 +104,10 @@ class Problem:
         torch.cuda.synchronize(self.device)
         return ch.value
 
+    def set_matvec_shape(self, nrhs, shape):
+        """Fix the matvec tile shape for nrhs right-hand sides (cbd_matvec_set_shape)."""
+        check(lib().cbd_matvec_set_shape(self.handle, nrhs, shape))
+
     def __del__(self, _free=_free):   # bound now: module globals are gone at shutdown
         _free("cbd_problem_free", self)
 

@@ -260,6 +260,18 @@ extern "C" int kernel_matvec_fft(cbd_problem p, int nrhs, const double* x, doubl
     return CBD_OK;
 }
 
+extern "C" int cbd_matvec_set_shape(cbd_problem p, int nrhs, int shape) {
+    if (!p || nrhs < 1) return fail(CBD_EARG, "cbd_matvec_set_shape: bad argument");
+    const bool wide = shape == 8 + 1 || shape == 8 + 2 || shape == 8 + 4;
+    if (shape != 1 && shape != 2 && shape != 4 && !wide)
+        return fail(CBD_EARG, "cbd_matvec_set_shape: shape must be 1, 2, 4, 9, 10 or 12");
+    if (wide && (p->d != 2 || p->n % matvec_rows_per_block(shape) != 0))
+        return fail(CBD_EARG, "cbd_matvec_set_shape: 8-wave shapes need a 2D grid whose side is a multiple of "
+                              "their rows per workgroup");
+    p->mv_rb[matvec_nb(nrhs) - 1] = shape;
+    return CBD_OK;
+}
+
 extern "C" int cbd_autotune_matvec(cbd_problem p, int nrhs, double* x, double* y, void* stream, int* choice) {
     if (!p || nrhs < 1 || !x || !y || x == y) return fail(CBD_EARG, "cbd_autotune_matvec: bad argument");
     hipStream_t s = (hipStream_t)stream;
@@ -271,8 +283,10 @@ extern "C" int cbd_autotune_matvec(cbd_problem p, int nrhs, double* x, double* y
     HIPCHK(hipEventCreate(&b));
     int best = matvec_default_rb(nb);
     double best_t = 1e300;
-    const int cand[3] = {1, 2, 4};
+    // row blocks per wave 1, 2, 4 with 4 waves per workgroup; on 2D grids also 2, 4 with 8
+    const int cand[5] = {1, 2, 4, 8 + 2, 8 + 4};
     for (int rb : cand) {
+        if (rb >= 8 && (p->d != 2 || p->n % matvec_rows_per_block(rb) != 0)) continue;
         // every candidate runs on the same number of workgroups (4 per CU when the
         // grid is that large), so that occupancy and L2 reuse are comparable
         const long rows = matvec_rows_per_block(rb);

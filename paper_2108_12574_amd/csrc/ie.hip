@@ -224,18 +224,20 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
 // values are evaluated once into LDS (the pair i = j gets 0: the diagonal is added at
 // the end), and a lane's A operand is one LDS read at delta.  Products, summation
 // order and epilogue are those of k_matvec.
-template <int kRB>
+template <int kRows>
 struct MvGridShared {
     double swx[64 * kLdw];
-    double ktab[64 * kRB + 64];
+    double ktab[kRows + 64];
 };
 
-template <int NB, int kRB>
-__global__ __launch_bounds__(kMvThreads) void k_matvec_grid2(ProblemView P, int nrhs,
-                                                             const double* __restrict__ x,
-                                                             double* __restrict__ y) {
-    __shared__ MvGridShared<kRB> sh;
-    constexpr int kR = kMvWaves * kRB * 16;   // rows per workgroup
+template <int NB, int kRB, int kW>
+__global__ __launch_bounds__(64 * kW) void k_matvec_grid2(ProblemView P, int nrhs,
+                                                          const double* __restrict__ x,
+                                                          double* __restrict__ y) {
+    constexpr int kThr = 64 * kW;             // kW waves per workgroup
+    constexpr int kR = kW * kRB * 16;         // rows per workgroup
+    constexpr int kSRw = kThr / kTJ;          // staging threads per source
+    __shared__ MvGridShared<kR> sh;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const long N = P.N;
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec_grid2(ProblemView P, int 
             // kernel values of the tile pair's offsets
             const long d2 = i2 - j0 / n;
             const long d1base = i1_0 - (j0 % n) - 63;
-            for (int e = tid; e < kR + 63; e += kMvThreads) {
+            for (int e = tid; e < kR + 63; e += kThr) {
                 const long d1 = d1base + e;
                 const long q = d1 * d1 + d2 * d2;
                 sh.ktab[e] = q == 0 ? 0.0 : laplace_from_r2<2>((double)q * sp2);
@@ -270,18 +272,20 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec_grid2(ProblemView P, int 
             const int sj = tid % kTJ, sr = tid / kTJ;
             const long j = j0 + sj;
             const double wj = P.w[j];
-            constexpr int kQ = NB * 16 / kSR;
+            constexpr int kQ = NB * 16 / kSRw;
+            static_assert(kQ * kSRw == NB * 16, "staging layout");
             double v[kQ];
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
-                const int rr = min(r0 + sr + kSR * q, nrhs - 1);
+                const int rr = min(r0 + sr + kSRw * q, nrhs - 1);
                 v[q] = x[(long)rr * N + j];
             }
 #pragma unroll
             for (int q = 0; q < kQ; ++q) {
-                const int r = sr + kSR * q;
+                const int r = sr + kSRw * q;
                 sh.swx[r * kLdw + sj] = (r0 + r < nrhs) ? wj * v[q] : 0.0;
             }
+
         }
         __syncthreads();
 #pragma unroll 1
@@ -421,6 +425,11 @@ static const double* log_table() {
 
 bool matvec_prepare() { return log_table() != nullptr; }
 
+// Tile shapes: rb row blocks of 16 per wave, with 4 waves per workgroup for rb = 1, 2, 4
+// and 8 waves (the table form only) for rb = 8 + 1, 8 + 2, 8 + 4.
+static int shape_rb(int rb) { return rb & 7; }
+static int shape_waves(int rb) { return rb >= 8 ? 8 : kMvWaves; }
+
 // The table form needs whole grid lines per workgroup and per source tile.
 static bool matvec_grid_form(const ProblemView& P, int rb) {
     return P.d == 2 && P.n % matvec_rows_per_block(rb) == 0 && P.n % kTJ == 0;
@@ -434,10 +443,13 @@ static void matvec_launch(const ProblemView& P, int nrhs, const double* x, doubl
     if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
     dim3 grid(blocks, (nrhs + 63) / 64);
     if (D == 2 && matvec_grid_form(P, RB)) {
-        hipLaunchKernelGGL((k_matvec_grid2<NB, RB>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y);
+        if (shape_waves(RB) == 8)
+            hipLaunchKernelGGL((k_matvec_grid2<NB, RB & 7, 8>), grid, dim3(512), 0, s, P, nrhs, x, y);
+        else
+            hipLaunchKernelGGL((k_matvec_grid2<NB, RB, kMvWaves>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y);
         return;
     }
-    hipLaunchKernelGGL((k_matvec<D, NB, RB>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y, log_table());
+    hipLaunchKernelGGL((k_matvec<D, NB, (RB & 7)>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y, log_table());
 }
 
 template <int D, int NB>
@@ -446,11 +458,14 @@ static void matvec_rb(const ProblemView& P, int nrhs, const double* x, double* y
     switch (rb) {
         case 1: matvec_launch<D, NB, 1>(P, nrhs, x, y, max_blocks, s); break;
         case 2: matvec_launch<D, NB, 2>(P, nrhs, x, y, max_blocks, s); break;
+        case 8 + 1: matvec_launch<D, NB, 8 + 1>(P, nrhs, x, y, max_blocks, s); break;
+        case 8 + 2: matvec_launch<D, NB, 8 + 2>(P, nrhs, x, y, max_blocks, s); break;
+        case 8 + 4: matvec_launch<D, NB, 8 + 4>(P, nrhs, x, y, max_blocks, s); break;
         default: matvec_launch<D, NB, 4>(P, nrhs, x, y, max_blocks, s); break;
     }
 }
 
-int matvec_rows_per_block(int rb) { return kMvWaves * 16 * rb; }
+int matvec_rows_per_block(int rb) { return shape_waves(rb) * 16 * shape_rb(rb); }
 
 // Right-hand-side blocks of 16 handled per launch column (the grid's y covers groups of 64).
 int matvec_nb(int nrhs) { return nrhs > 64 ? 4 : (nrhs + 15) / 16; }
@@ -470,6 +485,8 @@ void launch_matvec(const ProblemView& P, int nrhs, const double* x, double* y, i
     if (rb <= 0) rb = matvec_default_rb(nb);
     // 2D grids whose lines hold whole workgroups use the table form: the largest row
     // block count up to rb that fits
+    // (shapes of 8 waves exist in the table form only)
+    if (P.d != 2 || !matvec_grid_form(P, rb)) rb = shape_rb(rb);
     if (P.d == 2 && !matvec_grid_form(P, rb)) {
         int r = rb;
         while (r > 1 && !matvec_grid_form(P, r)) r /= 2;

@@ -59,6 +59,7 @@ def test_every_compute_entry_point_rejects_bad_arguments_on_the_host():
         ("kernel_matvec_fft", lambda: L.kernel_matvec_fft(None, 1, buf, ctypes.c_void_p(32), None)),
         ("cbd_fft_prepare", lambda: L.cbd_fft_prepare(None, 1, buf, 1 << 20, None)),
         ("cbd_autotune_matvec", lambda: L.cbd_autotune_matvec(None, 1, buf, ctypes.c_void_p(32), None, None)),
+        ("cbd_matvec_set_shape", lambda: L.cbd_matvec_set_shape(None, 1, 4)),
         ("rs_factor_batched", lambda: L.rs_factor_batched(None, None, ctypes.byref(opts), None, buf, 1 << 20,
                                                           None, None, None, ctypes.byref(h))),
         ("rs_factor_workspace", lambda: L.rs_factor_workspace(None, None, ctypes.byref(opts), None, None)),

@@ -335,9 +335,26 @@ def test_autotune_matvec_keeps_results(cfg3):
     x = torch.tensor(synth.rhs(O.N, 64, seed=0), device=DEV)
     y0 = P.matvec(x)
     choice = P.autotune_matvec(64)
-    assert choice in (1, 2, 4)
+    assert choice in (1, 2, 4, 10, 12)
     y1 = P.matvec(x)
     assert torch.allclose(y0, y1, rtol=1e-13, atol=1e-13 * y0.abs().max().item())
+
+
+@pytest.mark.parametrize("shape", [1, 2, 4, 9, 10, 12])
+@pytest.mark.parametrize("nrhs", [20, 64])
+def test_every_matvec_tile_shape_512(cfg3, shape, nrhs):
+    # each tile shape of the table form (4 or 8 waves per workgroup, 1 to 4 row blocks
+    # per wave) against the oracle on sampled rows
+    P, O, part = cfg3
+    x = synth.rhs(O.N, nrhs, seed=5)
+    P.set_matvec_shape(nrhs, shape)
+    try:
+        y = P.matvec(torch.tensor(x, device=DEV)).cpu().numpy()
+    finally:
+        P.set_matvec_shape(nrhs, 4)
+    rows = np.random.default_rng(shape).choice(O.N, 16, replace=False)
+    ref = cmatvec.matvec(O, x.T, rows=rows).T
+    assert np.abs(y[:, rows] - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
