@@ -161,7 +161,14 @@ SERIES = {
 }
 
 
-def run_series(kind):
+def id_method(cbd, choice, tol):
+    """CBD_ID_GRAM for choice "gram", or "auto" when tol >= 1e-7; else CBD_ID_QR."""
+    if choice == "gram" or (choice == "auto" and tol >= 1e-7):
+        return cbd.ID_GRAM
+    return cbd.ID_QR
+
+
+def run_series(kind, id_choice="auto"):
     """One JSON line: per size N, M, S, t_f, m_f, n_it, t_pcg for both layouts, and the
     least-squares exponents of t_f and m_f against N."""
     import numpy as np
@@ -176,6 +183,7 @@ def run_series(kind):
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     out = {"series": kind, "settings": "CBD, overlap 1, tol 1e-3, %d proxy points, b = c = 1, FP64 factors, "
                                       "1 RHS f ~ N(0,1) seed 0, FFT products, PCG to 1e-10" % cfg["npxy"],
+           "id_method": "gram" if id_method(cbd, id_choice, 1e-3) == cbd.ID_GRAM else "qr",
            "theory": cfg["theory"], "rows": {}, "fit": {}}
     for layout in ("sublinear", "fixed"):
         rows = []
@@ -186,7 +194,7 @@ def run_series(kind):
             f = torch.tensor(synth.rhs(N, 1, seed=0), device=dev)
             P.fft_prepare(max_pairs=1)
             opts = dict(tol=1e-3, n_pxy=cfg["npxy"], proxy_ratio=1.5, precision=cbd.PREC_FP64, apply_rhs=1,
-                        sketch_seed=1 if d == 3 else None)
+                        sketch_seed=1 if d == 3 else None, id_method=id_method(cbd, id_choice, 1e-3))
             fac = cbd.Factor(P, part, **opts)            # warm-up; sizes the workspace
             hint, ws = fac.ranks.cpu(), fac.ws
             del fac
@@ -228,6 +236,10 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=-1,
                     help="rows of the oracle's dense matvec timed for the CPU baseline (0: skip; "
                          "-1: about 12 s of host work, 16384 rows at 512^2 with 64 RHS)")
+    ap.add_argument("--id", choices=["auto", "qr", "gram"], default="auto",
+                    help="IDs of the levels of few, large boxes: column-pivoted Householder QR, or the pivoted "
+                         "Cholesky of the Gram matrix (same ID in exact arithmetic; tol >= 1e-7); auto: gram "
+                         "when the workload's tol allows it")
     ap.add_argument("--series", choices=sorted(SERIES),
                     help="instead of the benchmark line: factor and solve a series of grid sizes with the "
                          "partition count growing sublinearly (Section 4.4) and with N/M fixed, and fit "
@@ -238,7 +250,7 @@ def main():
               "path is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.series:
-        run_series(args.series)
+        run_series(args.series, args.id)
         return
 
     import numpy as np
@@ -257,6 +269,7 @@ def main():
     pcg_tol = W.get("pcg_tol", 1e-10)              # relative residual of the timed PCG
     dense = W.get("dense", True)                   # time the dense matvec (autotune, roofline)
     full = W.get("variants", True)                 # the variants (no predictor, FFT, sketch, bf16, FP64 form)
+    idm = id_method(cbd, args.id, tol)
     N = n ** d
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     coef = torch.tensor(synth.coef_smooth(d, n)) if W["coef"] else None
@@ -267,7 +280,8 @@ def main():
 
     if args.factor_only:
         t0 = time.perf_counter()
-        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, sketch_seed=sk_seed)
+        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, sketch_seed=sk_seed,
+                         id_method=idm)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         st = fac.stats()
@@ -291,7 +305,7 @@ def main():
     # The factor's device workspace and the PCG's are allocated once, before the timed
     # steps (sized by a first factorization), so that no step allocates device memory.
     fac0 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=sk_seed,
-                      apply_rhs=nrhs)
+                      apply_rhs=nrhs, id_method=idm)
     ws_factor = torch.empty(int(fac0.ws_used * 1.05) + (1 << 20), dtype=torch.uint8, device=dev)
     del fac0
     ws_pcg = cbd.pcg_workspace(P, nrhs)
@@ -311,7 +325,7 @@ def main():
         box["fac"] = None           # the previous factor views ws_factor: release it first
         t0 = time.perf_counter()
         fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=sk_seed,
-                         apply_rhs=nrhs, ws=ws_factor)
+                         apply_rhs=nrhs, ws=ws_factor, id_method=idm)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         u, its, rr = solve(fac, box["graph"])
@@ -356,7 +370,8 @@ def main():
     if full:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        fac_nm = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, sketch_seed=sk_seed)
+        fac_nm = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, sketch_seed=sk_seed,
+                            id_method=idm)
         torch.cuda.synchronize()
         factor_nm_s = time.perf_counter() - t0
         sched_nm = fac_nm.schedule()
@@ -376,7 +391,7 @@ def main():
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 F3 = cbd.Factor(P3, part3, tol=1e-3, n_pxy=256, precision=cbd.PREC_FP32, mlp=net, sketch_seed=1,
-                                apply_rhs=1)
+                                apply_rhs=1, id_method=id_method(cbd, args.id, 1e-3))
                 torch.cuda.synchronize()
                 times.append(time.perf_counter() - t0)
             _, it3, _ = cbd.pcg_solve(P3, F3, f3[0], tol=1e-10, maxit=300, fft=True)
@@ -427,7 +442,7 @@ def main():
     mv_flops = 2.0 * N * N * nrhs
     achieved = mv_flops / mv_avg_s / 1e12 if mv_avg_s else None
 
-    pcg_fft_s, its_fft, rr_fft, sketched, bf16 = None, [0], [0.0], None, None
+    pcg_fft_s, its_fft, rr_fft, sketched, bf16, alt_id = None, [0], [0.0], None, None, None
     f64_factor, f64_pcg, ncols, its64, f64_batched = None, None, 0, [], None
     if full:
         # the paper's matvec (FFT on the uniform grid) with the same factors, for comparison
@@ -444,7 +459,8 @@ def main():
         # the paper's last 3D runs); same predictor, same PCG
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        fac_sk = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=1)
+        fac_sk = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=1,
+                            id_method=idm)
         torch.cuda.synchronize()
         sk_factor = time.perf_counter() - t0
         t0 = time.perf_counter()
@@ -459,13 +475,42 @@ def main():
         del fac_sk
         log("sketched IDs: %s" % sketched)
 
+        # the other route to the same IDs: column-pivoted Householder QR, as (e:id) states it,
+        # when the timed steps take the pivoted Cholesky of the Gram matrix (or the reverse)
+        alt_idm = cbd.ID_QR if idm == cbd.ID_GRAM else (cbd.ID_GRAM if tol >= 1e-7 else None)
+        if alt_idm is not None:
+            alt_name = "qr" if alt_idm == cbd.ID_QR else "gram"
+            fac_alt = None
+            tts = []
+            for _ in range(2):
+                del fac_alt
+                fac_alt = None
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fac_alt = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp,
+                                     sketch_seed=sk_seed, apply_rhs=nrhs, id_method=alt_idm)
+                torch.cuda.synchronize()
+                tts.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            u_alt, its_alt, rr_alt = cbd.pcg_solve(P, fac_alt, F_rhs, tol=1e-10, maxit=200, fft=use_fft)
+            torch.cuda.synchronize()
+            alt_pcg = time.perf_counter() - t0
+            uerr(alt_name + "_id", u_alt[0])
+            del u_alt
+            st_alt = fac_alt.stats()
+            alt_id = {"id_method": alt_name, "factor_s": min(tts), "factor_gflops": st_alt["flops"] / min(tts) / 1e9,
+                      "S_last_level": st_alt["S"], "pcg_s": alt_pcg, "n_it": [min(its_alt), max(its_alt)],
+                      "max_relres": max(rr_alt), "host_syncs": fac_alt.schedule()["host_syncs"]}
+            del fac_alt
+            log("%s IDs: %s" % (alt_name, alt_id))
+
         # the bfloat16-GEMM variant of the factors (Schur products on bf16 operands)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         bf16 = None
         try:
             fac_bf = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_BF16GEMM, mlp=mlp,
-                                sketch_seed=sk_seed)
+                                sketch_seed=sk_seed, id_method=idm)
             torch.cuda.synchronize()
             bf_factor = time.perf_counter() - t0
             t0 = time.perf_counter()
@@ -484,7 +529,8 @@ def main():
         # plain FP64 form: FP64 factors, right-hand sides one at a time
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        fac64 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_FP64, sketch_seed=sk_seed)
+        fac64 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_FP64, sketch_seed=sk_seed,
+                           id_method=idm)
         torch.cuda.synchronize()
         f64_factor = time.perf_counter() - t0
         t0 = time.perf_counter()
@@ -551,7 +597,7 @@ def main():
                          if prec == cbd.PREC_FP32 else "f64 throughout"),
         "data": "synthetic",
         "config": {"workload": W["label"], "name": args.workload, "nrhs": nrhs, "n": n, "d": d,
-                   "gpus": 1},
+                   "gpus": 1, "id_method": "gram" if idm == cbd.ID_GRAM else "qr"},
         "factor_s": factor_s,
         "factor_gflops": st["flops"] / factor_s / 1e9,
         "factor_flops": st["flops"],
@@ -567,6 +613,7 @@ def main():
         "matvec_tile": {"shape": tile, "rows_per_wave": 16 * (tile & 7), "waves_per_workgroup": 8 if tile >= 8 else 4,
                         "chosen_by": "cbd_autotune_matvec"},
         "sketched_id_variant": sketched,
+        "other_id_method": alt_id,
         "bf16_gemm_variant": bf16,
         "pcg_with_fft_matvec": {"pcg_s": pcg_fft_s, "n_it": [min(its_fft), max(its_fft)],
                                 "max_relres": max(rr_fft),
@@ -602,10 +649,11 @@ def main():
         "factor_roofline": {"kernel": "rs_factor_batched (whole factorization)", "bound": "fp64",
                             "achieved": st["flops"] / factor_s / 1e12, "peak": FP64_PEAK_TFLOPS,
                             "unit": "TFLOP/s", "frac": st["flops"] / factor_s / 1e12 / FP64_PEAK_TFLOPS,
-                            "work": "per-box flop formulas of the ID (FP64), elimination and root "
-                                    "Cholesky over the factor wall time; the ID, which dominates, runs "
-                                    "in FP64, so the FP64 peak is the bound (FP32 peak for the "
-                                    "elimination alone is 157.3)"},
+                            "work": "per-box flop formulas of the ID (FP64; the truncated pivoted QR's "
+                                    "count, whichever route computes it), elimination and root "
+                                    "Cholesky over the factor wall time; the ID runs in FP64, so the "
+                                    "FP64 peak is the bound (FP32 peak for the elimination alone is "
+                                    "157.3)"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

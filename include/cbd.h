@@ -59,6 +59,9 @@ extern "C" {
 #define CBD_ROWS_NEVER 1
 #define CBD_ROWS_ALWAYS 2
 
+#define CBD_ID_QR 0          /* cbd_rs_opts.id_method: see below */
+#define CBD_ID_GRAM 1
+
 typedef struct cbd_problem_s* cbd_problem;
 typedef struct cbd_partition_s* cbd_partition;
 typedef struct cbd_factor_s* cbd_factor;
@@ -101,6 +104,16 @@ typedef struct {
     int apply_rhs;       /* right-hand sides one pass of rs_apply handles (the factor's apply
                             buffers hold this many columns; more columns are applied in blocks
                             of this size); 0: 64 */
+    int id_method;       /* how every ID is computed.  CBD_ID_QR (0): truncated
+                            column-pivoted Householder QR, as (e:id) states it.  CBD_ID_GRAM
+                            (1): truncated pivoted Cholesky of the Gram matrix G = Y^T Y (FP64
+                            matrix cores for G and the trailing updates, panels of 32 pivots):
+                            the Schur-complement diagonal is the squared trailing column norm,
+                            so pivots, ranks and T = R11^{-1} R12 equal the QR's in exact
+                            arithmetic; in FP64 the squared norms carry a rounding floor near
+                            1e-16 |Y|^2, so it is meant for tol >= 1e-7 (the ID's residual then
+                            stays within the tolerance) and is refused for smaller tol.  Boxes
+                            of more than 4096 active DOFs use the QR in both modes */
 } cbd_rs_opts;
 
 /* Message of the last failed call on this thread ("" if none). */

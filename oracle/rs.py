@@ -79,6 +79,30 @@ class SubdomainFactor:
         self.sketched_pred = 0 # of those, from the rank-sized first sketch
 
 
+def proxy_matrix(prob, sd, box, p, cand, n_pxy=64, proxy_ratio=1.5):
+    """The matrix whose ID compresses box `box` of subdomain sd (step 1 above):
+    rows A(near, p) for the candidates `cand` (subdomain-local indices of other
+    boxes' active DOFs) strictly inside the proxy surface, tested exactly in
+    half-cell units, |2j+1-(lo+hi)|^2 < (2 ratio L)^2; then the kernel from the
+    proxy points ctr + rho dir_q to the box's points, scaled by the column weights.
+    Returns (Y, near)."""
+    d, n, h = prob.d, prob.n, prob.h
+    gidx = sd.index
+    lo, hi = np.array(box.lo), np.array(box.hi)
+    L = int(np.max(hi - lo))
+    cand = np.asarray(cand, dtype=np.int64)
+    off = 2 * _grid_coords(gidx[cand], n, d) + 1 - (lo + hi)[None, :]
+    near = cand[np.sum(off * off, axis=1) < (2.0 * proxy_ratio * L) ** 2]
+    ctr = 0.5 * (lo + hi) * h
+    rho = proxy_ratio * L * h
+    pxy = ctr[None, :] + rho * proxy_directions(d, n_pxy)
+    Yn = prob.block(gidx[near], gidx[p])
+    diff = pxy[:, None, :] - prob.x[gidx[p]][None, :, :]
+    w = prob.weight * prob.c[gidx[p]]          # column scale of a proxy row
+    Yp = ie.kernel(d, np.sqrt(np.sum(diff * diff, axis=2))) * w[None, :]
+    return np.vstack([Yn, Yp]), near
+
+
 def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP64,
                      keep_matrices=False, sketch_seed=None, sub=0, order="level", rank_pred=None):
     """RS factorization of A_i for one subdomain (Section 4.2).  With sketch_seed set,
@@ -91,12 +115,8 @@ def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP6
         raise ValueError("order must be 'level' or 'sequential'")
     if prob.grid != ie.GRID_CELL:
         raise ValueError("RS is defined on the cell-centred grid")
-    d, n, h = prob.d, prob.n, prob.h
     gidx = sd.index
-    X = prob.x[gidx]
-    J = _grid_coords(gidx, n, d)
-    dirs = proxy_directions(d, n_pxy)
-    w = prob.weight * prob.c[gidx]          # column scale of a proxy row
+    n_dirs = len(proxy_directions(prob.d, n_pxy))
     f = SubdomainFactor()
     # level 0: each leaf box holds its points; its matrix is A(p, p)
     active = [np.arange(st, st + cnt) for (_, _, st, cnt) in sd.leaves]
@@ -109,25 +129,12 @@ def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP6
         lvl = []
         for bi, box in enumerate(boxes):
             p = active[bi]
-            lo = np.array(box.lo)
-            hi = np.array(box.hi)
-            L = int(np.max(hi - lo))
-            # near field: other boxes' active DOFs strictly inside the proxy surface,
-            # tested exactly in half-cell units: |2j+1-(lo+hi)|^2 < (2 ratio L)^2
-            cand = allact[(owner != bi) & alive]
-            off = 2 * J[cand] + 1 - (lo + hi)[None, :]
-            near = cand[np.sum(off * off, axis=1) < (2.0 * proxy_ratio * L) ** 2]
-            ctr = 0.5 * (lo + hi) * h
-            rho = proxy_ratio * L * h
-            pxy = ctr[None, :] + rho * dirs
-            Yn = prob.block(gidx[near], gidx[p])
-            diff = pxy[:, None, :] - X[p][None, :, :]
-            Yp = ie.kernel(d, np.sqrt(np.sum(diff * diff, axis=2))) * w[p][None, :]
-            Y = np.vstack([Yn, Yp])
+            # near field: other boxes' active DOFs strictly inside the proxy surface
+            Y, near = proxy_matrix(prob, sd, box, p, allact[(owner != bi) & alive], n_pxy, proxy_ratio)
             if sketch_seed is None:
                 k, perm, T = interp_decomp(Y, tol, tie)
             else:
-                rowkeys = np.concatenate([gidx[near], prob.N + np.arange(len(dirs))])
+                rowkeys = np.concatenate([gidx[near], prob.N + np.arange(n_dirs)])
                 k_pred = None if rank_pred is None else rank_pred.get((l, bi))
                 k, perm, T, used = sketch.interp_decomp_sketched(
                     Y, tol, sketch_seed, sketch.box_key(sub, l, bi), rowkeys, tie, k_pred=k_pred)

@@ -12,11 +12,12 @@ import torch
 
 from . import _lib
 from ._lib import (GRID_CELL, GRID_NODE, MODE_CBD, MODE_JACOBI, MODE_SCHWARZ, PREC_BF16GEMM,
-                   PREC_FP32, PREC_FP64, ROWS_ALWAYS, ROWS_AUTO, ROWS_NEVER, CbdError, check, lib)
+                   PREC_FP32, PREC_FP64, ROWS_ALWAYS, ROWS_AUTO, ROWS_NEVER, ID_QR, ID_GRAM, CbdError, check,
+                   lib)
 
 __all__ = ["Problem", "Partition", "Factor", "RankMLP", "pcg_solve", "pcg_workspace", "timing", "CbdError",
            "GRID_CELL", "GRID_NODE", "MODE_JACOBI", "MODE_SCHWARZ", "MODE_CBD",
-           "PREC_FP64", "PREC_FP32", "PREC_BF16GEMM", "ROWS_AUTO", "ROWS_NEVER", "ROWS_ALWAYS"]
+           "PREC_FP64", "PREC_FP32", "PREC_BF16GEMM", "ROWS_AUTO", "ROWS_NEVER", "ROWS_ALWAYS", "ID_QR", "ID_GRAM"]
 
 
 def _free(fn, obj):
@@ -166,13 +167,13 @@ class Factor:
 
     def __init__(self, problem, partition, tol=1e-6, n_pxy=64, proxy_ratio=1.5,
                  precision=PREC_FP64, exact=False, mlp=None, row_compression=ROWS_AUTO, sketch_seed=None,
-                 workspace_bytes=0, apply_rhs=64, rank_hint=None, ws=None):
+                 workspace_bytes=0, apply_rhs=64, rank_hint=None, ws=None, id_method=ID_QR):
         self.problem, self.partition = problem, partition
         self.precision = precision
         opts = _lib.RSOpts(tol, n_pxy, proxy_ratio, precision, 1 if exact else 0,
                            mlp.params.data_ptr() if mlp is not None else None, row_compression,
                            0 if sketch_seed is None else 1, 0 if sketch_seed is None else int(sketch_seed),
-                           int(workspace_bytes), int(apply_rhs))
+                           int(workspace_bytes), int(apply_rhs), int(id_method))
         self.opts = opts
         cnt = ctypes.c_int()
         check(lib().rs_factor_rank_count(partition.handle, ctypes.byref(opts), ctypes.byref(cnt)))

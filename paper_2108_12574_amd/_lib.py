@@ -13,6 +13,7 @@ GRID_CELL, GRID_NODE = 0, 1
 MODE_JACOBI, MODE_SCHWARZ, MODE_CBD = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_BF16GEMM = 0, 1, 2
 ROWS_AUTO, ROWS_NEVER, ROWS_ALWAYS = 0, 1, 2
+ID_QR, ID_GRAM = 0, 1
 OK, EARG, EHIP, ENOTSPD, ENOMEM, EWORKSPACE, WNOTCONV = 0, -1, -2, -3, -4, -5, 1
 
 
@@ -21,7 +22,7 @@ class RSOpts(ctypes.Structure):
                 ("proxy_ratio", ctypes.c_double), ("precision", ctypes.c_int),
                 ("exact", ctypes.c_int), ("mlp", ctypes.c_void_p), ("row_compression", ctypes.c_int),
                 ("id_sketch", ctypes.c_int), ("sketch_seed", ctypes.c_ulonglong),
-                ("workspace_bytes", ctypes.c_size_t), ("apply_rhs", ctypes.c_int)]
+                ("workspace_bytes", ctypes.c_size_t), ("apply_rhs", ctypes.c_int), ("id_method", ctypes.c_int)]
 
 
 # (name, restype, argtypes) of every exported symbol of include/cbd.h

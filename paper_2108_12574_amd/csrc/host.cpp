@@ -633,6 +633,14 @@ struct Arena {
 
 // Scratch buffer of a level or chunk, carved from the top of the arena; growing it
 // takes a new region (the old one is given back with the next cut).
+// Scratch of the Gram-matrix ID for a batch of nb boxes with o_g = sum n_p^2 Gram
+// entries, in a level of o_act active DOFs: G, its offsets, and the panel state.
+size_t gram_bytes(long o_g, int nb, long o_act) {
+    return Arena::al(sizeof(double) * (size_t)o_g) + Arena::al(sizeof(long) * nb) +
+           Arena::al(sizeof(double) * o_act) + Arena::al(sizeof(double) * nb) + 2 * Arena::al(sizeof(int) * o_act) +
+           Arena::al(sizeof(int) * (size_t)nb * kPcholPanel) + Arena::al(sizeof(int) * 3 * (size_t)nb);
+}
+
 struct ScratchBuf {
     void* p = nullptr;
     size_t bytes = 0;
@@ -686,6 +694,7 @@ struct cbd_factor_s {
     int sketched_pred = 0;    // boxes whose ID came from the rank-sized first sketch
     int sketch_pred_rejected = 0;   // boxes whose rank-sized sketch was not kept
     int chunks = 0;           // level chunks (more than the number of levels when the workspace is bounded)
+    int gram_batches = 0;     // batches whose ID came from the pivoted Cholesky of the Gram matrix
     double pred_abs_err = 0.0;
     int pred_count = 0;
     size_t esize;
@@ -808,9 +817,9 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
     std::vector<double> hdir = proxy_dirs(d, std::max(npxy, 1));
     // level-wide scratch (cut back at every level) and chunk scratch (at every chunk)
     ScratchBuf ybuf, wbuf, t64buf, appbuf, nearbuf, chbuf, mlpbuf;
-    ScratchBuf qrbuf, listbuf, hqrbuf, idbuf, zbuf;
+    ScratchBuf qrbuf, listbuf, hqrbuf, idbuf, zbuf, grambuf;
     for (ScratchBuf* b : {&ybuf, &wbuf, &t64buf, &appbuf, &nearbuf, &chbuf, &mlpbuf, &qrbuf, &listbuf, &hqrbuf,
-                          &idbuf, &zbuf})
+                          &idbuf, &zbuf, &grambuf})
         b->A = &A;
     double* d_dir = (double*)A.low(sizeof(double) * hdir.size());
     if (!d_dir) return short_of("proxy directions");
@@ -1035,7 +1044,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
         // this level's
         A.hi = A.cap;
         for (ScratchBuf* b : {&ybuf, &wbuf, &t64buf, &appbuf, &nearbuf, &chbuf, &mlpbuf, &qrbuf, &listbuf, &hqrbuf,
-                              &idbuf, &zbuf})
+                              &idbuf, &zbuf, &grambuf})
             b->reset();
         // device arrays of the level (kept for the apply), in the order level_bytes counts them
         L.d_meta = (BoxMeta*)A.low(sizeof(BoxMeta) * L.nbox);
@@ -1054,7 +1063,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
         std::vector<int> cut;
         long my = 1, mf = 1, ma = 1;
         size_t need = 0;
-        double hqr = 0.0, zb = 0.0;
+        double hqr = 0.0, zb = 0.0, gb = 0.0;
         {
             auto est = [&](const BoxMeta& M) {
                 const double yb = (double)std::max((long)M.m * M.np, (long)M.np * M.np + kScratchCols * M.np);
@@ -1079,7 +1088,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                 cut.push_back(L.nbox);
                 // exact scratch of this cut: level-wide buffers for the largest chunk
                 my = mf = ma = 1;
-                hqr = zb = 0.0;
+                hqr = zb = gb = 0.0;
                 for (size_t c = 0; c + 1 < cut.size(); ++c) {
                     long cy = 0, cf = 0, o_r = 0, o_z = 0, o_bits = 0;
                     int mmax = 0;
@@ -1106,6 +1115,11 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                         hqr = std::max(hqr, (double)sizeof(BoxMeta) * nb +
                                                 8.0 * ((double)nb * kHqrTw + o_act + (double)nb * kHqrVbuf(mmax) +
                                                        std::max(o_r, 1L)));
+                    if (!root && o->id_method == CBD_ID_GRAM) {
+                        long o_g = 0;
+                        for (int B = cut[c]; B < cut[c + 1]; ++B) o_g += (long)L.meta[B].np * L.meta[B].np;
+                        gb = std::max(gb, (double)gram_bytes(o_g, nb, o_act));
+                    }
                     if (sk)
                         zb = std::max(zb, (double)(sizeof(BoxMeta) + 8 + 8) * nb + 8.0 * std::max(o_z, 1L) +
                                               4.0 * std::max(o_bits, 1L));
@@ -1114,7 +1128,8 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                        al(4.0 * std::max(o_near, 1L)) + al((double)sizeof(ChildRef<R>) * std::max(o_ch, 1L)) +
                        (o->mlp && !root ? al(4.0 * L.nbox * (kMlpFeatures + 1)) : 0) +
                        al(8.0 * (3.0 * o_act + 2.0 * L.nbox) + 4.0 * (o_act + 2.0 * L.nbox)) +
-                       al((double)(sizeof(BoxMeta) + 4) * L.nbox) + al(4.0 * L.nbox) + (hqr > 0 ? al(hqr) : 0) + (sk ? al(zb) : 0);
+                       al((double)(sizeof(BoxMeta) + 4) * L.nbox) + al(4.0 * L.nbox) + (hqr > 0 ? al(hqr) : 0) + (sk ? al(zb) : 0) +
+                       (gb > 0 ? al(gb) : 0);
                 if (need <= A.free_bytes()) break;
                 if ((int)cut.size() - 1 >= L.nbox) {
                     A.short_by = need - A.free_bytes();
@@ -1129,7 +1144,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                 (o->mlp && !root && (rc = mlpbuf.ensure(sizeof(float) * (size_t)L.nbox * (kMlpFeatures + 1)))) ||
                 (rc = qrbuf.ensure(sizeof(double) * (3 * o_act + 2 * L.nbox) + sizeof(int) * (o_act + 2 * L.nbox))) ||
                 (rc = idbuf.ensure((sizeof(BoxMeta) + sizeof(int)) * L.nbox)) ||
-                (rc = listbuf.ensure(sizeof(int) * L.nbox)) || (hqr > 0 && (rc = hqrbuf.ensure((size_t)hqr))) ||
+                (rc = listbuf.ensure(sizeof(int) * L.nbox)) || (hqr > 0 && (rc = hqrbuf.ensure((size_t)hqr))) || (gb > 0 && (rc = grambuf.ensure((size_t)gb))) ||
                 (sk && (rc = zbuf.ensure((size_t)zb))))
                 return rc;
         }
@@ -1215,11 +1230,72 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                 HIPCHK(hipMemcpyAsync(d_bm, bm.data(), sizeof(BoxMeta) * nb, hipMemcpyHostToDevice, s));
                 const size_t shm = (size_t)(np_max + m_max) * sizeof(double) + (size_t)np_max * sizeof(int);
                 std::vector<BoxMeta> cmh;   // compact metadata of row-compressed boxes
-                if (cpqr_reg_fits(m_max, np_max)) {
+                const bool reg = cpqr_reg_fits(m_max, np_max);
+                const bool onewg = !reg && nb >= kStepBoxes && shm <= 65536;
+                const bool gram = o->id_method == CBD_ID_GRAM && pchol_panel_lds(np_max) <= 65536;
+                if (gram) {
+                    // the ID from the pivoted Cholesky of G = Y^T Y, by panels of kPcholPanel
+                    // pivots (one launch pair per panel)
+                    std::vector<long> goffs(nb);
+                    long o_g = 0;
+                    for (int i = 0; i < nb; ++i) {
+                        goffs[i] = o_g;
+                        o_g += (long)bm[i].np * bm[i].np;
+                    }
+                    const size_t gbytes = gram_bytes(o_g, nb, o_act);
+                    if ((rc2 = grambuf.ensure(gbytes))) return rc2;
+                    char* gp = (char*)grambuf.p;
+                    double* Gm = (double*)gp;
+                    gp += Arena::al(sizeof(double) * (size_t)o_g);
+                    long* d_goff = (long*)gp;
+                    gp += Arena::al(sizeof(long) * nb);
+                    GramState gs;
+                    gs.rdiag = (double*)gp;
+                    gp += Arena::al(sizeof(double) * o_act);
+                    gs.nu0 = (double*)gp;
+                    gp += Arena::al(sizeof(double) * nb);
+                    gs.pv = (int*)gp;
+                    gp += Arena::al(sizeof(int) * o_act);
+                    gs.pos = (int*)gp;
+                    gp += Arena::al(sizeof(int) * o_act);
+                    gs.piv = (int*)gp;
+                    gp += Arena::al(sizeof(int) * (size_t)nb * kPcholPanel);
+                    gs.done = (int*)gp;
+                    gs.k = gs.done + nb;
+                    gs.jend = gs.k + nb;
+                    HIPCHK(hipMemcpyAsync(d_goff, goffs.data(), sizeof(long) * nb, hipMemcpyHostToDevice, s));
+                    launch_gram(nb, np_max, d_bm, Ymat, d_goff, Gm, s);
+                    int jmax = 0;
+                    for (const BoxMeta& M : bm) jmax = std::max(jmax, std::min(M.m, M.np));
+                    // panels before the first check: enough for the largest predicted rank
+                    // (with a margin), else two
+                    int first = 2;
+                    if (!bpred.empty()) {
+                        const int kp = *std::max_element(bpred.begin(), bpred.end());
+                        first = ((kp * 11 + 9) / 10 + 2 + kPcholPanel - 1) / kPcholPanel;
+                    }
+                    std::vector<int> done(nb);
+                    int panels = 0;
+                    for (int j0 = 0; j0 <= jmax; j0 += kPcholPanel) {
+                        launch_pchol_panel(nb, np_max, d_bm, d_goff, Gm, gs, j0, o->tol, tie, s);
+                        ++panels;
+                        if (panels < first && j0 + kPcholPanel <= jmax) continue;
+                        HIPCHK(hipMemcpyAsync(done.data(), gs.done, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+                        HIPCHK(hipStreamSynchronize(s));
+                        F->host_syncs++;
+                        bool all = true;
+                        for (int v : done) all = all && v;
+                        if (all) break;
+                    }
+                    F->qr_steps += panels;
+                    F->gram_batches++;
+                    launch_pchol_finish(nb, np_max, d_bm, d_goff, Gm, gs, Ymat, L.d_act, L.d_sr, L.d_perm, d_kb, T64,
+                                        s);
+                } else if (reg) {
                     // small boxes: the whole matrix in one workgroup's registers
                     launch_cpqr_reg(nb, np_max, m_max, d_bm, Ymat, L.d_act, L.d_sr, L.d_perm, d_kb, T64, o->tol, tie,
                                     s);
-                } else if (nb >= kStepBoxes && shm <= 65536) {
+                } else if (onewg) {
                     // many boxes: one workgroup per box
                     launch_cpqr(nb, d_bm, Ymat, L.d_act, L.d_sr, L.d_perm, d_kb, T64, o->tol, tie, m_max, np_max, s);
                 } else {
@@ -1569,6 +1645,10 @@ int check_factor_args(cbd_problem p, cbd_partition q, const cbd_rs_opts* o, cons
     if (o->precision != CBD_PREC_FP64 && o->precision != CBD_PREC_FP32 && o->precision != CBD_PREC_BF16GEMM)
         return fail(CBD_EARG, std::string(who) + ": unknown precision");
     if (o->apply_rhs < 0) return fail(CBD_EARG, std::string(who) + ": negative apply_rhs");
+    if (o->id_method != CBD_ID_QR && o->id_method != CBD_ID_GRAM)
+        return fail(CBD_EARG, std::string(who) + ": unknown id_method");
+    if (o->id_method == CBD_ID_GRAM && !o->exact && !(o->tol >= 1e-7))
+        return fail(CBD_EARG, std::string(who) + ": CBD_ID_GRAM needs tol >= 1e-7");
     return CBD_OK;
 }
 

@@ -146,6 +146,26 @@ struct QrState {
     int* done;       // per box: stopped
     int* k;          // per box: rank once stopped
 };
+// ID by pivoted Cholesky of the Gram matrix (rs.hip): state between panel launches.
+constexpr int kPcholPanel = 32;   // pivots per panel
+struct GramState {
+    double* rdiag;   // R_jj, per box at its act offset (by step)
+    int* pv;         // position -> column, per box at its act offset
+    int* pos;        // column -> position, per box at its act offset
+    int* piv;        // per box: the columns chosen in the current panel (kPcholPanel)
+    double* nu0;     // per box: largest column norm of Y
+    int* done;       // per box: stopped
+    int* k;          // per box: rank once stopped
+    int* jend;       // per box: steps taken so far
+};
+void launch_gram(int nbox, int np_max, const BoxMeta* meta, const double* Y, const long* goff, double* G,
+                 hipStream_t s);
+size_t pchol_panel_lds(int np_max);
+void launch_pchol_panel(int nbox, int np_max, const BoxMeta* meta, const long* goff, double* G,
+                        const GramState& st, int j0, double tol, double tie, hipStream_t s);
+void launch_pchol_finish(int nbox, int np_max, const BoxMeta* meta, const long* goff, const double* G,
+                         const GramState& st, double* Y, const int* act, int* sr, int* perm, int* k, double* T64,
+                         hipStream_t s);
 void launch_qr_init(int nbox, int np_max, const BoxMeta* meta, const double* Y, const QrState& st,
                     hipStream_t s);
 void launch_qr_step(int nbox, int np_max, int m_max, const BoxMeta* meta, double* Y, const QrState& st,

@@ -2364,6 +2364,351 @@ void launch_root_apply(int nbox, int np_max, int unused, const BoxMeta* meta, co
     hipLaunchKernelGGL((k_root_move<R>), dim3(nbox, 64), dim3(256), 0, s, meta, sr, v, nrhs, t1, ts, 0);
 }
 
+// ---- the ID from the Gram matrix -------------------------------------------
+// For a proxy matrix Y (m x np) the pivoted Cholesky factorization of G = Y^T Y
+// chooses the same columns as the column-pivoted QR of Y: after j steps the
+// Schur-complement diagonal d_i of G is the squared norm of column i of Y with its
+// projection on the j chosen columns removed, i.e. the squared trailing-block norm
+// the QR compares.  The Cholesky factor gives R = L^T of that QR (rows up to sign,
+// which T = R11^{-1} R12 does not see), so the ID of (e:id) is the same in exact
+// arithmetic.  G comes from one product on FP64 matrix cores; the factorization
+// runs in panels of kPcholPanel pivots: within a panel (one workgroup per box) each
+// new column of L is formed from G's pivot column and the panel's earlier columns
+// (left-looking), then the trailing part of G takes the panel's rank-kPcholPanel
+// update on matrix cores (many workgroups per box).  Column p of G, once p is
+// chosen at step j, holds column j of L; the updates skip chosen rows and columns.
+constexpr int kGramTile = 64;              // output tile of the Gram and update products
+constexpr int kGramK = 32;                 // rows of Y staged per pass of the Gram product
+constexpr int kGramLd = kGramTile + 1;     // LDS row stride (doubles)
+constexpr int kPcholThreads = 512;
+constexpr int kPcholWaves = kPcholThreads / 64;
+
+__device__ __forceinline__ void lower_tile(int t, int& ti, int& tj) {
+    int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    ti = i;
+    tj = t - i * (i + 1) / 2;
+}
+
+// G = Y^T Y (np x np, column-major, at goff[b]) for the lower 64 x 64 tiles; each
+// off-diagonal tile is also written to its mirror.  Wave w computes a 32 x 32 part
+// (2 x 2 blocks of v_mfma_f64_16x16x4f64); Y is staged 32 rows at a time in LDS,
+// the next rows loaded into registers during the products.
+__global__ __launch_bounds__(kThreads) void k_gram(const BoxMeta* __restrict__ meta, const double* __restrict__ Y,
+                                                   const long* __restrict__ goff, double* __restrict__ G) {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __shared__ double sI[kGramK * kGramLd], sJ[kGramK * kGramLd];
+    const int b = blockIdx.y;
+    const BoxMeta M = meta[b];
+    const int m = M.m, np = M.np, nt = (np + kGramTile - 1) / kGramTile;
+    if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+    int ti, tj;
+    lower_tile(blockIdx.x, ti, tj);
+    const int I0 = ti * kGramTile, J0 = tj * kGramTile;
+    const double* Yb = Y + M.y;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int wi = (wid >> 1) * 32, wj = (wid & 1) * 32;
+    constexpr int kCols = kThreads / kGramK;           // columns per staging pass
+    constexpr int kPass = kGramTile / kCols;
+    const int sr = tid % kGramK, sc = tid / kGramK;
+    double nI[kPass], nJ[kPass];
+    auto fetch = [&](int k0) {
+        const int r = k0 + sr;
+#pragma unroll
+        for (int u = 0; u < kPass; ++u) {
+            const int ci = I0 + sc + kCols * u, cj = J0 + sc + kCols * u;
+            nI[u] = (r < m && ci < np) ? Yb[r + (long)ci * m] : 0.0;
+            nJ[u] = (r < m && cj < np) ? Yb[r + (long)cj * m] : 0.0;
+        }
+    };
+    v4 acc[2][2];
+#pragma unroll
+    for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+        for (int qj = 0; qj < 2; ++qj) acc[qi][qj] = v4{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    for (int k0 = 0; k0 < m; k0 += kGramK) {
+#pragma unroll
+        for (int u = 0; u < kPass; ++u) {
+            sI[sr * kGramLd + sc + kCols * u] = nI[u];
+            sJ[sr * kGramLd + sc + kCols * u] = nJ[u];
+        }
+        __syncthreads();
+        if (k0 + kGramK < m) fetch(k0 + kGramK);
+#pragma unroll
+        for (int kk = 0; kk < kGramK; kk += 4) {
+            double a[2], bb[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                a[q] = sI[(kk + lk) * kGramLd + wi + 16 * q + li];
+                bb[q] = sJ[(kk + lk) * kGramLd + wj + 16 * q + li];
+            }
+#pragma unroll
+            for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+                for (int qj = 0; qj < 2; ++qj)
+                    acc[qi][qj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[qi], bb[qj], acc[qi][qj], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // accumulator (qi, qj) register v: G row i = I0 + wi + 16 qi + 4 v + lk, column j = J0 + wj + 16 qj + li
+    double* Gb = G + goff[b];
+#pragma unroll
+    for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+        for (int qj = 0; qj < 2; ++qj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = I0 + wi + 16 * qi + 4 * v + lk, j = J0 + wj + 16 * qj + li;
+                if (i < np && j < np) {
+                    Gb[j + (long)i * np] = acc[qi][qj][v];
+                    if (ti != tj) Gb[i + (long)j * np] = acc[qi][qj][v];
+                }
+            }
+}
+
+// One panel of at most kPcholPanel pivots per box (one workgroup per box, from step
+// j0).  LDS: d (Schur diagonal), pos (column -> position), pv (position -> column).
+// Row i of every column of L is read and written by thread i % kPcholThreads only,
+// so the panel's columns need no cross-thread visibility of global memory.  A step
+// takes three barriers: the largest remaining norm (each thread's part comes from
+// its rows of the previous step's update), the lowest position within the tie
+// window (reduced as position * 4096 + column, so the pivot column needs no
+// lookup), and the pivot row of the panel's earlier columns.
+constexpr int kPcholMaxCols = 4096;   // columns per box (LDS: 16 bytes each)
+__global__ __launch_bounds__(kPcholThreads) void k_pchol_panel(const BoxMeta* __restrict__ meta,
+                                                               const long* __restrict__ goff, double* __restrict__ G,
+                                                               GramState st, int j0, double tol, double tie) {
+    extern __shared__ char smem_raw[];
+    __shared__ double red[kPcholWaves];
+    __shared__ int redi[kPcholWaves];
+    __shared__ double s_c[kPcholPanel];
+    __shared__ int s_piv[kPcholPanel];
+    __shared__ double s_r;
+    const int b = blockIdx.x;
+    if (j0 > 0 && st.done[b]) return;
+    const BoxMeta M = meta[b];
+    const int np = M.np, kmax = min(M.m, np);
+    double* Gb = G + goff[b];
+    double* d = reinterpret_cast<double*>(smem_raw);
+    int* pos = reinterpret_cast<int*>(d + np);
+    int* pv = pos + np;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double lm = 0.0;   // largest d over this thread's unchosen rows
+    for (int i = tid; i < np; i += kPcholThreads) {
+        const int q = j0 == 0 ? i : st.pos[M.act + i];
+        pos[i] = q;
+        pv[i] = j0 == 0 ? i : st.pv[M.act + i];
+        d[i] = q >= j0 ? Gb[i + (long)i * np] : 0.0;
+        if (q >= j0) lm = fmax(lm, d[i]);
+    }
+    double nu0 = j0 == 0 ? 0.0 : st.nu0[b];
+    __syncthreads();
+    int taken = 0, stop_k = -1;
+    for (int jj = 0; jj < kPcholPanel; ++jj) {
+        const int j = j0 + jj;
+        if (j >= kmax) {
+            stop_k = kmax;
+            break;
+        }
+        lm = wave_max(lm);
+        if (lane == 0) red[wid] = lm;
+        __syncthreads();
+        double mx = red[0];
+#pragma unroll
+        for (int w = 1; w < kPcholWaves; ++w) mx = fmax(mx, red[w]);
+        const double nmax = sqrt(mx);
+        if (j == 0) nu0 = nmax;
+        if (nu0 == 0.0 || nmax <= tol * nu0) {
+            stop_k = j;
+            break;
+        }
+        const double thr = nmax - tie * nu0;
+        int key = INT_MAX;
+        for (int i = tid; i < np; i += kPcholThreads)
+            if (pos[i] >= j && sqrt(fmax(d[i], 0.0)) >= thr) key = min(key, pos[i] * kPcholMaxCols + i);
+        key = wave_min_int(key);
+        if (lane == 0) redi[wid] = key;
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < kPcholWaves; ++w) key = min(key, redi[w]);
+        const int P = key / kPcholMaxCols, p = key % kPcholMaxCols;
+        if (tid == 0) {
+            const int q = pv[j];
+            pv[j] = p;
+            pv[P] = q;
+            pos[q] = P;
+            pos[p] = j;
+            s_piv[jj] = p;
+        }
+        // row p of the panel's earlier columns, read by the thread that wrote them
+        if (tid == p % kPcholThreads) {
+            for (int q = 0; q < jj; ++q) s_c[q] = Gb[p + (long)s_piv[q] * np];
+            s_r = sqrt(d[p]);
+            st.rdiag[M.act + j] = s_r;
+        }
+        __syncthreads();
+        const double r = s_r;
+        double* gp = Gb + (long)p * np;
+        lm = 0.0;
+        for (int i = tid; i < np; i += kPcholThreads) {
+            if (pos[i] <= j) continue;   // chosen (p now sits at position j)
+            double w0 = gp[i], w1 = 0.0, w2 = 0.0, w3 = 0.0;
+            int q = 0;
+            for (; q + 4 <= jj; q += 4) {
+                w0 -= Gb[i + (long)s_piv[q] * np] * s_c[q];
+                w1 -= Gb[i + (long)s_piv[q + 1] * np] * s_c[q + 1];
+                w2 -= Gb[i + (long)s_piv[q + 2] * np] * s_c[q + 2];
+                w3 -= Gb[i + (long)s_piv[q + 3] * np] * s_c[q + 3];
+            }
+            for (; q < jj; ++q) w0 -= Gb[i + (long)s_piv[q] * np] * s_c[q];
+            const double l = ((w0 + w1) + (w2 + w3)) / r;
+            gp[i] = l;
+            d[i] -= l * l;
+            lm = fmax(lm, d[i]);
+        }
+        taken = jj + 1;
+    }
+    __syncthreads();
+    for (int i = tid; i < np; i += kPcholThreads) {
+        st.pos[M.act + i] = pos[i];
+        st.pv[M.act + i] = pv[i];
+    }
+    if (tid < taken) st.piv[(long)b * kPcholPanel + tid] = s_piv[tid];
+    if (tid == 0) {
+        st.jend[b] = j0 + taken;
+        if (j0 == 0) st.nu0[b] = nu0;
+        st.done[b] = stop_k >= 0;
+        if (stop_k >= 0) st.k[b] = stop_k;
+    }
+}
+
+// Trailing update of a panel: G(i, l) -= sum_q L(i, q) L(l, q) over the panel's
+// columns q, for rows and columns not yet chosen, in 64 x 64 tiles (all np^2 of
+// them) on FP64 MFMA.  The accumulator's lanes run along rows i (consecutive in
+// memory): the block computed is L_J L_I^T, whose (l, i) entry updates G(i, l).
+__global__ __launch_bounds__(kThreads) void k_pchol_update(const BoxMeta* __restrict__ meta,
+                                                           const long* __restrict__ goff, double* __restrict__ G,
+                                                           GramState st, int j0) {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __shared__ double sI[kPcholPanel * kGramTile], sJ[kPcholPanel * kGramTile];
+    __shared__ int fI[kGramTile], fJ[kGramTile];
+    const int b = blockIdx.y;
+    const int kt = st.jend[b] - j0;
+    if (kt <= 0) return;
+    const BoxMeta M = meta[b];
+    const int np = M.np, nt = (np + kGramTile - 1) / kGramTile;
+    if ((int)blockIdx.x >= nt * nt) return;
+    const int I0 = ((int)blockIdx.x % nt) * kGramTile, J0 = ((int)blockIdx.x / nt) * kGramTile;
+    const int jend = j0 + kt;
+    double* Gb = G + goff[b];
+    const int* piv = st.piv + (long)b * kPcholPanel;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, li = lane & 15, lk = lane >> 4;
+    for (int e = tid; e < kPcholPanel * kGramTile; e += kThreads) {
+        const int q = e / kGramTile, i = e % kGramTile;
+        const bool ok = q < kt;
+        const long col = ok ? (long)piv[q] * np : 0;
+        sI[e] = (ok && I0 + i < np) ? Gb[I0 + i + col] : 0.0;
+        sJ[e] = (ok && J0 + i < np) ? Gb[J0 + i + col] : 0.0;
+    }
+    for (int e = tid; e < kGramTile; e += kThreads) {
+        fI[e] = I0 + e < np && st.pos[M.act + I0 + e] >= jend;
+        fJ[e] = J0 + e < np && st.pos[M.act + J0 + e] >= jend;
+    }
+    __syncthreads();
+    const int wi = (wid & 1) * 32, wj = (wid >> 1) * 32;
+    v4 acc[2][2];
+#pragma unroll
+    for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+        for (int qj = 0; qj < 2; ++qj) acc[qi][qj] = v4{0.0, 0.0, 0.0, 0.0};
+    const int ksteps = (kt + 3) / 4;
+    for (int ks = 0; ks < ksteps; ++ks) {
+        const int q = 4 * ks + lk;
+        double a[2], bb[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            a[u] = sJ[q * kGramTile + wj + 16 * u + li];    // A(l, q) = L(J0 + l, q)
+            bb[u] = sI[q * kGramTile + wi + 16 * u + li];   // B(q, i) = L(I0 + i, q)
+        }
+#pragma unroll
+        for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+            for (int qj = 0; qj < 2; ++qj)
+                acc[qi][qj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[qj], bb[qi], acc[qi][qj], 0, 0, 0);
+    }
+    // accumulator (qi, qj) register v: l = wj + 16 qj + 4 v + lk, i = wi + 16 qi + li
+#pragma unroll
+    for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+        for (int qj = 0; qj < 2; ++qj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = wi + 16 * qi + li, l = wj + 16 * qj + 4 * v + lk;
+                if (fI[i] && fJ[l]) {
+                    double* g = Gb + (I0 + i) + (long)(J0 + l) * np;
+                    *g -= acc[qi][qj][v];
+                }
+            }
+}
+
+// R rows 0..k-1 into Y (ld m, columns in position order) as the QR leaves them, and
+// k, perm and sr as k_qr_finish writes them.
+__global__ __launch_bounds__(kThreads) void k_pchol_finish(const BoxMeta* __restrict__ meta,
+                                                           const long* __restrict__ goff,
+                                                           const double* __restrict__ G, GramState st,
+                                                           double* __restrict__ Y, const int* __restrict__ act,
+                                                           int* __restrict__ sr, int* __restrict__ perm,
+                                                           int* __restrict__ kout) {
+    const int b = blockIdx.x;
+    const BoxMeta M = meta[b];
+    const int m = M.m, np = M.np;
+    const int k = st.done[b] ? st.k[b] : min(m, np);
+    const double* Gb = G + goff[b];
+    double* Yb = Y + M.y;
+    const int* pv = st.pv + M.act;
+    for (long e = threadIdx.x; e < (long)k * np; e += kThreads) {
+        const int a = (int)(e % k), c = (int)(e / k);
+        double v = 0.0;
+        if (c == a)
+            v = st.rdiag[M.act + a];
+        else if (c > a)
+            v = Gb[pv[c] + (long)pv[a] * np];
+        Yb[a + (long)c * m] = v;
+    }
+    if (threadIdx.x == 0) kout[b] = k;
+    for (int c = threadIdx.x; c < np; c += kThreads) {
+        const int p = pv[c];
+        perm[M.act + c] = p;
+        sr[M.act + c] = act[M.act + p];
+    }
+}
+
+void launch_gram(int nbox, int np_max, const BoxMeta* meta, const double* Y, const long* goff, double* G,
+                 hipStream_t s) {
+    if (nbox == 0) return;
+    const int nt = (np_max + kGramTile - 1) / kGramTile;
+    hipLaunchKernelGGL(k_gram, dim3(nt * (nt + 1) / 2, nbox), dim3(kThreads), 0, s, meta, Y, goff, G);
+}
+size_t pchol_panel_lds(int np_max) { return (size_t)np_max * (sizeof(double) + 2 * sizeof(int)); }
+void launch_pchol_panel(int nbox, int np_max, const BoxMeta* meta, const long* goff, double* G,
+                        const GramState& st, int j0, double tol, double tie, hipStream_t s) {
+    if (nbox == 0) return;
+    hipLaunchKernelGGL(k_pchol_panel, dim3(nbox), dim3(kPcholThreads), pchol_panel_lds(np_max), s, meta, goff, G,
+                       st, j0, tol, tie);
+    const int nt = (np_max + kGramTile - 1) / kGramTile;
+    hipLaunchKernelGGL(k_pchol_update, dim3(nt * nt, nbox), dim3(kThreads), 0, s, meta, goff, G, st, j0);
+}
+void launch_pchol_finish(int nbox, int np_max, const BoxMeta* meta, const long* goff, const double* G,
+                         const GramState& st, double* Y, const int* act, int* sr, int* perm, int* k, double* T64,
+                         hipStream_t s) {
+    if (nbox == 0) return;
+    hipLaunchKernelGGL(k_pchol_finish, dim3(nbox), dim3(kThreads), 0, s, meta, goff, G, st, Y, act, sr, perm, k);
+    hipLaunchKernelGGL(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s,
+                       meta, Y, k, T64);
+}
+
 // explicit instantiations
 template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta*, const int*,
                                           const int*, const int*, const double*, int, double*,

@@ -6,9 +6,10 @@ RS-PCG to relative residual 1e-12 (tests/golden/make_solution_fixture.py); their
 true residual is checked on the CPU (tests/test_golden_solution.py), and the
 oracle's own 1e-10 iterate lies within 1e-11 of them.  Every GPU form here runs
 PCG to 1e-10 and must match u to 1e-8 relative (2-norm over all N entries):
-FP64 factors; FP32 factors; bfloat16-GEMM factors with flexible PCG; column 0
-of the 64-right-hand-side batched solve; and the FFT product in place of the
-dense one.
+FP64 factors; FP32 factors; bfloat16-GEMM factors with flexible PCG; FP32
+factors whose large-box IDs come from the pivoted Cholesky of the Gram matrix
+(CBD_ID_GRAM); column 0 of the 64-right-hand-side batched solve; and the FFT
+product in place of the dense one.
 """
 import json
 import os
@@ -50,13 +51,13 @@ def _err(u, u_ref):
     return float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16gemm_flexible", "fp32_fft"])
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16gemm_flexible", "fp32_fft", "fp32_gram"])
 def test_single_rhs_solution_matches_oracle(setup, form):
     rec, u_ref, P, part, F = setup
     prec = {"fp64": cbd.PREC_FP64, "fp32": cbd.PREC_FP32, "bf16gemm_flexible": cbd.PREC_BF16GEMM,
-            "fp32_fft": cbd.PREC_FP32}[form]
+            "fp32_fft": cbd.PREC_FP32, "fp32_gram": cbd.PREC_FP32}[form]
     fac = cbd.Factor(P, part, tol=rec["rs_tol"], n_pxy=rec["n_pxy"], proxy_ratio=rec["proxy_ratio"],
-                     precision=prec)
+                     precision=prec, id_method=cbd.ID_GRAM if form.endswith("gram") else cbd.ID_QR)
     fft = form.endswith("fft")
     if fft:
         P.fft_prepare(max_pairs=1)
@@ -67,14 +68,15 @@ def test_single_rhs_solution_matches_oracle(setup, form):
     assert err <= 1e-8, err
 
 
-def test_batched_64_rhs_column0_matches_oracle(setup):
+@pytest.mark.parametrize("idm", ["qr", "gram"])
+def test_batched_64_rhs_column0_matches_oracle(setup, idm):
     rec, u_ref, P, part, F = setup
     fac = cbd.Factor(P, part, tol=rec["rs_tol"], n_pxy=rec["n_pxy"], proxy_ratio=rec["proxy_ratio"],
-                     precision=cbd.PREC_FP32)
+                     precision=cbd.PREC_FP32, id_method=cbd.ID_GRAM if idm == "gram" else cbd.ID_QR)
     U, its, rr = cbd.pcg_solve(P, fac, F, tol=1e-10, maxit=400)
     err = _err(U[0], u_ref)
-    print("batched fp32 n=%d: iterations %d-%d, |u0 - u_oracle|/|u_oracle| = %.2e"
-          % (rec["n"], min(its), max(its), err))
+    print("batched fp32 %s n=%d: iterations %d-%d, |u0 - u_oracle|/|u_oracle| = %.2e"
+          % (idm, rec["n"], min(its), max(its), err))
     assert max(rr) <= 1e-10
     assert err <= 1e-8, err
     # the batched column and a lone solve of it differ only by rounding (the 64-column

@@ -55,9 +55,9 @@ MUTANTS = [
     ("rs.py", ["test_oracle_rs.py"], "v[b.sk] -= b.T @ vr", "v[b.sk] += b.T @ vr"),
     ("rs.py", ["test_oracle_rs.py"], "z[sd.index] += self.apply_sub(i, R[sd.index])",
      "z[sd.index] = self.apply_sub(i, R[sd.index])"),
-    ("rs.py", ["test_oracle_rs.py"], "Yp = ie.kernel(d, np.sqrt(np.sum(diff * diff, axis=2))) * w[p][None, :]",
+    ("rs.py", ["test_oracle_rs.py"], "Yp = ie.kernel(d, np.sqrt(np.sum(diff * diff, axis=2))) * w[None, :]",
      "Yp = ie.kernel(d, np.sqrt(np.sum(diff * diff, axis=2)))"),
-    ("rs.py", ["test_oracle_rs.py"], "Y = np.vstack([Yn, Yp])", "Y = Yp"),
+    ("rs.py", ["test_oracle_rs.py"], "return np.vstack([Yn, Yp]), near", "return Yp, near"),
     ("rs.py", ["test_oracle_rs.py"], "mat[blk] = lvl[ca].Bss", "mat[blk] = prob.block(gidx[sks[a]], gidx[sks[a]])"),
     ("rs.py", ["test_oracle_rs.py"], "phi = j * (np.pi * (3.0 - np.sqrt(5.0)))", "phi = j * 0.05"),
     ("rs.py", ["test_oracle_rs.py"], "z = 1.0 - (2.0 * j + 1.0) / n_pxy", "z = 1.0 - (j + 0.5) / n_pxy"),
