@@ -233,6 +233,10 @@ def main():
     ap.add_argument("--factor-only", action="store_true",
                     help="run one factorization of the workload (no predictor, no PCG) and print its time; "
                          "for counter profiles of the factor kernels")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="autotune the dense matvec, then run three products with the workload's right-hand "
+                         "sides and three plain copies of as many doubles (the traffic counters' calibration); "
+                         "for counter profiles of the matvec")
     ap.add_argument("--cpu-rows", type=int, default=-1,
                     help="rows of the oracle's dense matvec timed for the CPU baseline (0: skip; "
                          "-1: about 12 s of host work, 16384 rows at 512^2 with 64 RHS)")
@@ -287,6 +291,22 @@ def main():
         st = fac.stats()
         print(json.dumps({"workload": W["label"], "factor_s": t, "factor_flops": st["flops"],
                           "factor_gflops": st["flops"] / t / 1e9, "schedule": fac.schedule()}))
+        return
+
+    if args.matvec_only:
+        tile = P.autotune_matvec(nrhs)
+        cbd.timing.reset()
+        cbd.timing.enable(True)
+        for _ in range(3):
+            y = P.matvec(F_rhs)
+        torch.cuda.synchronize()
+        cbd.timing.enable(False)
+        ms, cnt = cbd.timing.get("matvec")
+        for _ in range(3):
+            y.copy_(F_rhs)       # N x nrhs doubles read and written
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": W["label"], "tile_shape": tile, "matvec_avg_ms": ms / max(cnt, 1),
+                          "copy_bytes_each_way": 8 * N * nrhs}))
         return
 
     P.fft_prepare(max_pairs=8)
