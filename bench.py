@@ -326,8 +326,10 @@ def main():
     # steps (sized by a first factorization), so that no step allocates device memory.
     fac0 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=sk_seed,
                       apply_rhs=nrhs, id_method=idm)
-    ws_factor = torch.empty(int(fac0.ws_used * 1.05) + (1 << 20), dtype=torch.uint8, device=dev)
-    del fac0
+    used0 = fac0.ws_used
+    del fac0                    # its own workspace goes before the timed steps' is allocated
+    torch.cuda.empty_cache()
+    ws_factor = torch.empty(int(used0 * 1.05) + (1 << 20), dtype=torch.uint8, device=dev)
     ws_pcg = cbd.pcg_workspace(P, nrhs)
     box = {"fac": None, "graph": False}
     side = torch.cuda.Stream(device=dev)    # PCG with captured HIP graphs needs a non-default stream
