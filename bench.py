@@ -222,6 +222,83 @@ def run_series(kind, id_choice="auto"):
     print(json.dumps(out))
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and the cores this process may use."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return name, cores
+
+
+def oracle_rs_sample(fac, O, opart, tol, npxy, nrhs, per_level=3):
+    """The oracle's RS factorization and apply timed on sampled boxes and scaled by the
+    box counts.  For every compressed level, per_level boxes of subdomain 0 (evenly
+    spaced) take the oracle's steps with the GPU factor's active DOFs: the proxy matrix
+    (oracle.rs.proxy_matrix, near field from the level's other active DOFs), the ID
+    (oracle.cpqr.interp_decomp), the elimination (oracle.rs.eliminate_box, with the
+    kernel block of the box's DOFs standing in for its Schur-complement block: same
+    sizes and flops), and the forward and backward sweep steps of the apply on nrhs
+    columns; each level's mean per box is scaled by its boxes over all subdomains.
+    The roots: a Cholesky factorization and a solve of each subdomain's root size.
+    Returns (factor_s, apply_s, detail)."""
+    import numpy as np
+    from scipy.linalg import cho_factor, cho_solve
+    from oracle import rs
+    from oracle.cpqr import interp_decomp
+    rng = np.random.default_rng(0)
+    nlev = fac.stats()["levels"]
+    t_fac = t_app = 0.0
+    detail = []
+    sd = opart.subdomains[0]
+    for l in range(min(nlev, sd.root_level)):
+        total = len(fac.level(l)[0])                       # boxes of the level, all subdomains
+        boxes = [fac.box(0, l, b) for b in range(len(sd.levels[l]))]
+        act = [np.concatenate([g["sk"], g["rd"]]).astype(np.int64) for g in boxes]
+        allact = np.concatenate(act)
+        pick = np.unique(np.linspace(0, len(boxes) - 1, min(per_level, len(boxes))).round().astype(int))
+        tf = ta = 0.0
+        for b in pick:
+            p = act[b]
+            t0 = time.perf_counter()
+            Y, _ = rs.proxy_matrix(O, sd, sd.levels[l][b], p, np.setdiff1d(allact, p), npxy)
+            k, perm, T = interp_decomp(Y, tol)
+            G, E, Bss = rs.eliminate_box(O.block(sd.index[p], sd.index[p]), perm[:k], perm[k:], T)
+            t1 = time.perf_counter()
+            bf = rs.BoxFactor(perm[:k], perm[k:], T, G, E, Bss)
+            v = rng.standard_normal((len(p), nrhs))
+            t2 = time.perf_counter()
+            rs.box_forward(bf, v)
+            rs.box_backward(bf, v)
+            t3 = time.perf_counter()
+            tf += t1 - t0
+            ta += t3 - t2
+        tf, ta = tf / len(pick) * total, ta / len(pick) * total
+        t_fac += tf
+        t_app += ta
+        detail.append({"level": l, "boxes": total, "sampled": int(len(pick)), "factor_s": tf, "apply_s": ta})
+    for i in range(len(opart.subdomains)):
+        S = fac.stats()["S"][i]
+        if S == 0:
+            continue
+        idx = fac.root(i)[0]
+        A = O.block(opart.subdomains[i].index[idx], opart.subdomains[i].index[idx])
+        t0 = time.perf_counter()
+        c = cho_factor(A)
+        t1 = time.perf_counter()
+        cho_solve(c, rng.standard_normal((S, nrhs)))
+        t2 = time.perf_counter()
+        t_fac += t1 - t0
+        t_app += t2 - t1
+    detail.append({"roots": len(opart.subdomains)})
+    return t_fac, t_app, detail
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -587,7 +664,7 @@ def main():
         # the row cost is proportional to N * nrhs
         args.cpu_rows = int(min(N, max(64, 16384.0 * (512 ** 2 * 64) / (float(N) * nrhs) / (4 if d == 3 else 1))))
     if args.cpu_rows > 0:
-        from oracle import cmatvec, ie
+        from oracle import cmatvec, dd, ie
         O = ie.Problem(d, n, b=None if coef is None else coef.numpy(), c=None if coef is None else coef.numpy())
         rows = np.random.default_rng(0).choice(N, args.cpu_rows, replace=False)
         X = F_rhs.cpu().numpy().T.copy()
@@ -596,12 +673,25 @@ def main():
         t_rows = time.perf_counter() - t0
         per_matvec = t_rows * N / args.cpu_rows
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": per_matvec * max(n_it), "unit": "s", "cores": threads, "kind": "oracle",
-               "sample": "oracle dense FP64 matvec (plain C, OpenMP) on %d of %d rows x %d RHS "
-                         "(%.2f s), scaled by N/rows to one matvec (%.1f s) and by the %d PCG "
-                         "iterations; the oracle's RS apply and factor are not included"
-                         % (args.cpu_rows, N, nrhs, t_rows, per_matvec, max(n_it))}
-        log("cpu baseline sample %.2f s" % t_rows)
+        model, avail = cpu_model()
+        log("cpu baseline matvec sample %.2f s" % t_rows)
+        # the oracle's RS factor and apply on sampled boxes (the PCG's other per-iteration step)
+        omode = {"cbd": dd.CBD, "schwarz": dd.SCHWARZ, "jacobi": dd.JACOBI}[W["mode"]]
+        opart = dd.Partition(d, n, W["m"], W["delta"], omode, W["leaf"])
+        t0 = time.perf_counter()
+        o_fac, o_app, o_detail = oracle_rs_sample(fac, O, opart, tol, npxy, nrhs)
+        log("cpu baseline RS sample %.2f s: factor %.1f s, apply %.2f s (scaled)"
+            % (time.perf_counter() - t0, o_fac, o_app))
+        cpu = {"value": (per_matvec + o_app) * max(n_it), "unit": "s", "cores": threads, "kind": "oracle",
+               "cpu_model": model, "cores_available": avail,
+               "factor_s": o_fac, "factor_gflops": st["flops"] / o_fac / 1e9 if o_fac > 0 else None,
+               "matvec_s": per_matvec, "apply_s": o_app, "rs_levels": o_detail,
+               "sample": "PCG time = %d iterations x (one matvec + one apply).  Matvec: the oracle's dense FP64 "
+                         "product (plain C, OpenMP, %d threads) on %d of %d rows x %d RHS (%.2f s), scaled by "
+                         "N/rows (%.1f s).  Apply and factor: the oracle's RS steps (numpy/scipy) on %s boxes "
+                         "per level of subdomain 0, scaled by each level's box count over all subdomains, plus "
+                         "the roots' Cholesky and solve (apply %.2f s, factor %.1f s)"
+                         % (max(n_it), threads, args.cpu_rows, N, nrhs, t_rows, per_matvec, "3", o_app, o_fac)}
 
     out = {
         "metric": METRIC,

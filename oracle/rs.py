@@ -103,6 +103,49 @@ def proxy_matrix(prob, sd, box, p, cand, n_pxy=64, proxy_ratio=1.5):
     return np.vstack([Yn, Yp]), near
 
 
+def eliminate_box(App, ps, pr, T):
+    """Compress-then-eliminate one box (step 2 above): App its box matrix, ps / pr the
+    positions of its skeleton / redundant DOFs in App, T its ID coefficients.
+    Returns (G, E, B_ss); raises NotSPDError if B_rr is not positive definite."""
+    Ass = App[np.ix_(ps, ps)]
+    Asr = App[np.ix_(ps, pr)]
+    Ars = App[np.ix_(pr, ps)]
+    Arr = App[np.ix_(pr, pr)]
+    # (e:al)
+    Brr = Arr - Ars @ T - T.T @ Asr + T.T @ Ass @ T
+    Bsr = Asr - Ass @ T
+    if len(pr) == 0:
+        return np.zeros((0, 0)), np.zeros((len(ps), 0)), Ass.copy()
+    Brr = 0.5 * (Brr + Brr.T)
+    try:
+        G = cholesky(Brr, lower=False)
+    except np.linalg.LinAlgError:
+        raise NotSPDError("B_rr not SPD")
+    # (e:alu)/(e:b): E = B_sr G^{-1}, B_ss = A_ss - E E^T
+    E = solve_triangular(G, Bsr.T, trans="T", lower=False).T
+    return G, E, Ass - E @ E.T
+
+
+def box_forward(b, v):
+    """The forward sweep's step for box b (a BoxFactor) on v (rows: the DOFs b.sk, b.rd index)."""
+    if len(b.rd) == 0:
+        return
+    vr = v[b.rd] - b.T.T @ v[b.sk]
+    vr = solve_triangular(b.G, vr, trans="T", lower=False)
+    v[b.sk] -= b.E @ vr
+    v[b.rd] = vr
+
+
+def box_backward(b, v):
+    """The backward sweep's step for box b on v."""
+    if len(b.rd) == 0:
+        return
+    vr = v[b.rd] - b.E.T @ v[b.sk]
+    vr = solve_triangular(b.G, vr, lower=False)
+    v[b.sk] -= b.T @ vr
+    v[b.rd] = vr
+
+
 def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP64,
                      keep_matrices=False, sketch_seed=None, sub=0, order="level", rank_pred=None):
     """RS factorization of A_i for one subdomain (Section 4.2).  With sketch_seed set,
@@ -141,27 +184,10 @@ def factor_subdomain(prob, part, sd, tol, n_pxy=64, proxy_ratio=1.5, tie=TIE_FP6
                 f.sketched += int(used > 0)
                 f.sketched_pred += int(used == 2)
             ps, pr = perm[:k], perm[k:]
-            App = boxmat[bi]
-            Ass = App[np.ix_(ps, ps)]
-            Asr = App[np.ix_(ps, pr)]
-            Ars = App[np.ix_(pr, ps)]
-            Arr = App[np.ix_(pr, pr)]
-            # (e:al)
-            Brr = Arr - Ars @ T - T.T @ Asr + T.T @ Ass @ T
-            Bsr = Asr - Ass @ T
-            if len(pr) > 0:
-                Brr = 0.5 * (Brr + Brr.T)
-                try:
-                    G = cholesky(Brr, lower=False)
-                except np.linalg.LinAlgError:
-                    raise NotSPDError(f"B_rr not SPD at level {l} box {bi}")
-                # (e:alu)/(e:b): E = B_sr G^{-1}, B_ss = A_ss - E E^T
-                E = solve_triangular(G, Bsr.T, trans="T", lower=False).T
-                Bss = Ass - E @ E.T
-            else:
-                G = np.zeros((0, 0))
-                E = np.zeros((k, 0))
-                Bss = Ass.copy()
+            try:
+                G, E, Bss = eliminate_box(boxmat[bi], ps, pr, T)
+            except NotSPDError:
+                raise NotSPDError(f"B_rr not SPD at level {l} box {bi}")
             lvl.append(BoxFactor(p[ps], p[pr], T, G, E, Bss))
             if order == "sequential":
                 alive[np.isin(allact, p[pr])] = False
@@ -214,22 +240,12 @@ class RSPreconditioner:
         v = np.array(v, dtype=np.float64, copy=True)
         for lvl in f.levels:
             for b in lvl:
-                if len(b.rd) == 0:
-                    continue
-                vr = v[b.rd] - b.T.T @ v[b.sk]
-                vr = solve_triangular(b.G, vr, trans="T", lower=False)
-                v[b.sk] -= b.E @ vr
-                v[b.rd] = vr
+                box_forward(b, v)
         if len(f.root):
             v[f.root] = cho_solve((f.root_G, False), v[f.root])
         for lvl in reversed(f.levels):
             for b in lvl:
-                if len(b.rd) == 0:
-                    continue
-                vr = v[b.rd] - b.E.T @ v[b.sk]
-                vr = solve_triangular(b.G, vr, lower=False)
-                v[b.sk] -= b.T @ vr
-                v[b.rd] = vr
+                box_backward(b, v)
         return v
 
     def apply(self, r):

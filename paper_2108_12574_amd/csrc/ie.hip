@@ -257,37 +257,47 @@ __global__ __launch_bounds__(64 * kW) void k_matvec_grid2(ProblemView P, int nrh
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = v4d{0.0, 0.0, 0.0, 0.0};
 
+    // The next tile's inputs are fetched into registers during the current tile's
+    // products (its x and w values, and its offsets' kernel values), so the staging
+    // between the barriers is LDS writes only.
+    const int sj = tid % kTJ, sr = tid / kTJ;
+    constexpr int kQ = NB * 16 / kSRw;
+    static_assert(kQ * kSRw == NB * 16, "staging layout");
+    constexpr int kKT = (kR + 63 + kThr - 1) / kThr;   // table entries per thread
+    double v[kQ], wj, kt[kKT];
+    auto fetch = [&](long j0) {
+        const long j = j0 + sj;
+        wj = P.w[j];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const int rr = min(r0 + sr + kSRw * q, nrhs - 1);
+            v[q] = x[(long)rr * N + j];
+        }
+        const long d2 = i2 - j0 / n;
+        const long d1base = i1_0 - (j0 % n) - 63;
+#pragma unroll
+        for (int u = 0; u < kKT; ++u) {
+            const int e = tid + u * kThr;
+            const long d1 = d1base + e;
+            const long q = d1 * d1 + d2 * d2;
+            kt[u] = (e >= kR + 63 || q == 0) ? 0.0 : laplace_from_r2<2>((double)q * sp2);
+        }
+    };
+    fetch(0);
     for (long j0 = 0; j0 < N; j0 += kTJ) {
         __syncthreads();
-        {
-            // kernel values of the tile pair's offsets
-            const long d2 = i2 - j0 / n;
-            const long d1base = i1_0 - (j0 % n) - 63;
-            for (int e = tid; e < kR + 63; e += kThr) {
-                const long d1 = d1base + e;
-                const long q = d1 * d1 + d2 * d2;
-                sh.ktab[e] = q == 0 ? 0.0 : laplace_from_r2<2>((double)q * sp2);
-            }
-            // w_j x_j, [rhs][j] (zero for padding columns)
-            const int sj = tid % kTJ, sr = tid / kTJ;
-            const long j = j0 + sj;
-            const double wj = P.w[j];
-            constexpr int kQ = NB * 16 / kSRw;
-            static_assert(kQ * kSRw == NB * 16, "staging layout");
-            double v[kQ];
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                const int rr = min(r0 + sr + kSRw * q, nrhs - 1);
-                v[q] = x[(long)rr * N + j];
-            }
+        for (int u = 0; u < kKT; ++u) {
+            const int e = tid + u * kThr;
+            if (e < kR + 63) sh.ktab[e] = kt[u];
+        }
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                const int r = sr + kSRw * q;
-                sh.swx[r * kLdw + sj] = (r0 + r < nrhs) ? wj * v[q] : 0.0;
-            }
-
+        for (int q = 0; q < kQ; ++q) {
+            const int r = sr + kSRw * q;
+            sh.swx[r * kLdw + sj] = (r0 + r < nrhs) ? wj * v[q] : 0.0;
         }
         __syncthreads();
+        if (j0 + kTJ < N) fetch(j0 + kTJ);
 #pragma unroll 1
         for (int ks = 0; ks < kTJ / 4; ++ks) {
             const int jj = ks * 4 + lk;
@@ -443,7 +453,7 @@ static void matvec_launch(const ProblemView& P, int nrhs, const double* x, doubl
     if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
     dim3 grid(blocks, (nrhs + 63) / 64);
     if (D == 2 && matvec_grid_form(P, RB)) {
-        if (shape_waves(RB) == 8)
+        if constexpr (RB >= 8)
             hipLaunchKernelGGL((k_matvec_grid2<NB, RB & 7, 8>), grid, dim3(512), 0, s, P, nrhs, x, y);
         else
             hipLaunchKernelGGL((k_matvec_grid2<NB, RB, kMvWaves>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y);

@@ -50,7 +50,7 @@ MUTANTS = [
     ("rs.py", ["test_oracle_rs.py"], "Bsr = Asr - Ass @ T", "Bsr = Asr + Ass @ T"),
     ("rs.py", ["test_oracle_rs.py"], 'E = solve_triangular(G, Bsr.T, trans="T", lower=False).T',
      'E = solve_triangular(G, Bsr.T, trans="N", lower=False).T'),
-    ("rs.py", ["test_oracle_rs.py"], "Bss = Ass - E @ E.T", "Bss = Ass + E @ E.T"),
+    ("rs.py", ["test_oracle_rs.py"], "return G, E, Ass - E @ E.T", "return G, E, Ass + E @ E.T"),
     ("rs.py", ["test_oracle_rs.py"], "vr = v[b.rd] - b.T.T @ v[b.sk]", "vr = v[b.rd] + b.T.T @ v[b.sk]"),
     ("rs.py", ["test_oracle_rs.py"], "v[b.sk] -= b.T @ vr", "v[b.sk] += b.T @ vr"),
     ("rs.py", ["test_oracle_rs.py"], "z[sd.index] += self.apply_sub(i, R[sd.index])",
