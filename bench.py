@@ -236,10 +236,10 @@ def cpu_model():
     return name, cores
 
 
-def oracle_rs_sample(fac, O, opart, tol, npxy, nrhs, per_level=3):
+def oracle_rs_sample(fac, O, opart, tol, npxy, nrhs, per_level=4):
     """The oracle's RS factorization and apply timed on sampled boxes and scaled by the
-    box counts.  For every compressed level, per_level boxes of subdomain 0 (evenly
-    spaced) take the oracle's steps with the GPU factor's active DOFs: the proxy matrix
+    box counts.  For every compressed level, per_level boxes of subdomain 0 (drawn
+    with a fixed seed) take the oracle's steps with the GPU factor's active DOFs: the proxy matrix
     (oracle.rs.proxy_matrix, near field from the level's other active DOFs), the ID
     (oracle.cpqr.interp_decomp), the elimination (oracle.rs.eliminate_box, with the
     kernel block of the box's DOFs standing in for its Schur-complement block: same
@@ -261,7 +261,7 @@ def oracle_rs_sample(fac, O, opart, tol, npxy, nrhs, per_level=3):
         boxes = [fac.box(0, l, b) for b in range(len(sd.levels[l]))]
         act = [np.concatenate([g["sk"], g["rd"]]).astype(np.int64) for g in boxes]
         allact = np.concatenate(act)
-        pick = np.unique(np.linspace(0, len(boxes) - 1, min(per_level, len(boxes))).round().astype(int))
+        pick = np.sort(rng.choice(len(boxes), min(per_level, len(boxes)), replace=False))
         tf = ta = 0.0
         for b in pick:
             p = act[b]
@@ -691,7 +691,7 @@ def main():
                          "N/rows (%.1f s).  Apply and factor: the oracle's RS steps (numpy/scipy) on %s boxes "
                          "per level of subdomain 0, scaled by each level's box count over all subdomains, plus "
                          "the roots' Cholesky and solve (apply %.2f s, factor %.1f s)"
-                         % (max(n_it), threads, args.cpu_rows, N, nrhs, t_rows, per_matvec, "3", o_app, o_fac)}
+                         % (max(n_it), threads, args.cpu_rows, N, nrhs, t_rows, per_matvec, "4", o_app, o_fac)}
 
     out = {
         "metric": METRIC,
