@@ -222,6 +222,23 @@ def run_series(kind, id_choice="auto"):
     print(json.dumps(out))
 
 
+def library_dgemm_tflops(dev, n=8192, reps=3):
+    """FP64 TFLOP/s of the vendor library's GEMM (torch.matmul) on n x n operands: the
+    rate FP64 matrix-core code reaches on this GPU in practice, beside the nominal peak."""
+    import torch
+    a = torch.randn(n, n, dtype=torch.float64, device=dev)
+    b = torch.randn(n, n, dtype=torch.float64, device=dev)
+    c = a @ b
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        c = a @ b
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    del a, b, c
+    return 2.0 * n ** 3 / t / 1e12
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo) and the cores this process may use."""
     name = "unknown"
@@ -383,7 +400,7 @@ def main():
             y.copy_(F_rhs)       # N x nrhs doubles read and written
         torch.cuda.synchronize()
         print(json.dumps({"workload": W["label"], "tile_shape": tile, "matvec_avg_ms": ms / max(cnt, 1),
-                          "copy_bytes_each_way": 8 * N * nrhs}))
+                          "copy_bytes_each_way": 8 * N * nrhs, "library_dgemm_tflops": library_dgemm_tflops(dev)}))
         return
 
     P.fft_prepare(max_pairs=8)
@@ -659,6 +676,7 @@ def main():
         del u64b
         log("fp64 factors, batched: %s" % f64_batched)
 
+    dgemm_ref = library_dgemm_tflops(dev) if achieved else None
     cpu = None
     if args.cpu_rows < 0:
         # the row cost is proportional to N * nrhs
@@ -756,6 +774,7 @@ def main():
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic() if args.workload == "512sq" else None,
+                     "library_dgemm_tflops": dgemm_ref,
                      "work": "2 N^2 nrhs FP64 flops per launch on FP64 MFMA (the N^2 kernel "
                              "evaluations run on the VALU and are not counted)"} if achieved else None,
         "factor_roofline": {"kernel": "rs_factor_batched (whole factorization)", "bound": "fp64",
