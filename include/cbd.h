@@ -113,7 +113,8 @@ typedef struct {
                             arithmetic; in FP64 the squared norms carry a rounding floor near
                             1e-16 |Y|^2, so it is meant for tol >= 1e-7 (the ID's residual then
                             stays within the tolerance) and is refused for smaller tol.  Boxes
-                            of more than 4096 active DOFs use the QR in both modes */
+                            with more active DOFs than the pivot kernel's LDS holds (16 bytes
+                            each: about 10000 on gfx950) use the QR in both modes */
 } cbd_rs_opts;
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -1232,7 +1232,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                 std::vector<BoxMeta> cmh;   // compact metadata of row-compressed boxes
                 const bool reg = cpqr_reg_fits(m_max, np_max);
                 const bool onewg = !reg && nb >= kStepBoxes && shm <= 65536;
-                const bool gram = o->id_method == CBD_ID_GRAM && pchol_panel_lds(np_max) <= 65536;
+                const bool gram = o->id_method == CBD_ID_GRAM && pchol_panel_lds(np_max) <= pchol_panel_lds_limit();
                 if (gram) {
                     // the ID from the pivoted Cholesky of G = Y^T Y, by panels of kPcholPanel
                     // pivots (one launch pair per panel)

@@ -3,7 +3,10 @@
 // compress-then-eliminate ((e:al), (e:alu), (e:b)), and the level sweeps of
 // the factor apply.  Every kernel processes a whole level batch: one
 // workgroup per box, all boxes of all subdomains in one launch.
+#include <algorithm>
 #include <climits>
+#include <mutex>
+#include <vector>
 
 #include "internal.h"
 
@@ -2476,7 +2479,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(const BoxMeta* __restrict__ m
 // its rows of the previous step's update), the lowest position within the tie
 // window (reduced as position * 4096 + column, so the pivot column needs no
 // lookup), and the pivot row of the panel's earlier columns.
-constexpr int kPcholMaxCols = 4096;   // columns per box (LDS: 16 bytes each)
+constexpr int kPcholMaxCols = 16384;  // key range of the pivot reduction (LDS: 16 bytes per column)
 __global__ __launch_bounds__(kPcholThreads) void k_pchol_panel(const BoxMeta* __restrict__ meta,
                                                                const long* __restrict__ goff, double* __restrict__ G,
                                                                GramState st, int j0, double tol, double tie) {
@@ -2692,6 +2695,29 @@ void launch_gram(int nbox, int np_max, const BoxMeta* meta, const double* Y, con
     hipLaunchKernelGGL(k_gram, dim3(nt * (nt + 1) / 2, nbox), dim3(kThreads), 0, s, meta, Y, goff, G);
 }
 size_t pchol_panel_lds(int np_max) { return (size_t)np_max * (sizeof(double) + 2 * sizeof(int)); }
+
+// Largest dynamic LDS the panel kernel may take on the current device: the device's LDS
+// per workgroup less 1 KB for the kernel's own arrays (160 KB per workgroup on gfx950).
+size_t pchol_panel_lds_limit() {
+    static std::mutex mu;
+    static std::vector<size_t> lim;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 65536 - 1024;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)lim.size() <= dev) lim.resize(dev + 1, 0);
+    if (!lim[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        lim[dev] = (size_t)v - 1024;
+        // let the panel kernel take all of it (above 64 KB the launch needs the attribute)
+        if (lim[dev] > 65536 &&
+            hipFuncSetAttribute((const void*)k_pchol_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lim[dev]) != hipSuccess)
+            lim[dev] = 65536 - 1024;
+    }
+    return std::min(lim[dev], pchol_panel_lds(kPcholMaxCols));
+}
 void launch_pchol_panel(int nbox, int np_max, const BoxMeta* meta, const long* goff, double* G,
                         const GramState& st, int j0, double tol, double tie, hipStream_t s) {
     if (nbox == 0) return;
