@@ -1275,16 +1275,16 @@ __global__ __launch_bounds__(kThreads) void k_sketch_signs(const BoxMeta* __rest
     bits[boff[b] + e] = hw;
 }
 
-// Z = Omega Y on FP64 MFMA, a 64 x 128 tile of Z per workgroup (wave w: rows
-// 16 w .. 16 w + 15 of the tile, eight 16 x 16 accumulators).  Rows of Y stream
-// through LDS in chunks of kSkK (coalesced column segments), with the tile's
-// signs for them expanded from the bit words; the next chunk's loads are issued
-// before the current chunk is multiplied.  Every entry of Z sums over the rows in
-// steps of four in ascending order.
-constexpr int kSkI = 64, kSkC = 128, kSkK = 32;
-constexpr int kSkLdA = kSkI + 16;    // LDS row strides (doubles) that spread the operand reads over the banks
-constexpr int kSkLdB = kSkC + 1;
-
+// Z = Omega Y on FP64 MFMA.  A workgroup computes a tile of Z of kWaves * 16 * RBW
+// sketch rows and C columns (wave w: RBW row blocks of 16 of it, C / 16
+// accumulators each); a taller tile reads Y fewer times (Y is read once per tile
+// row).  Rows of Y stream through LDS in chunks of kSkK (coalesced column segments)
+// with the tile's sign words for them; each lane expands its A operand from a bit.
+// The next chunk's loads are issued before the current chunk is multiplied.  Every
+// entry of Z sums over the rows in steps of four in ascending order; rows of Z past
+// ell are computed and dropped.
+constexpr int kSkK = 32;
+template <int RBW, int C>
 __global__ __launch_bounds__(kThreads) void k_sketch(const BoxMeta* __restrict__ meta,
                                                      const BoxMeta* __restrict__ zmeta,
                                                      const double* __restrict__ Y,
@@ -1292,74 +1292,80 @@ __global__ __launch_bounds__(kThreads) void k_sketch(const BoxMeta* __restrict__
                                                      const unsigned* __restrict__ bits,
                                                      double* __restrict__ Z, int ti) {
     typedef double v4 __attribute__((ext_vector_type(4)));
-    __shared__ double sA[kSkK * kSkLdA];
-    __shared__ double sB[kSkK * kSkLdB];
+    constexpr int I = kWaves * 16 * RBW;   // sketch rows per workgroup
+    constexpr int NW = I / 32;             // sign words per Y row of the tile
+    constexpr int LdB = C + 1;
+    constexpr int QY = C / 8;              // Y values staged per thread
+    __shared__ double sB[kSkK * LdB];
+    __shared__ unsigned sW[kSkK * NW];
     const int b = blockIdx.x;
     const BoxMeta M = meta[b];
     const int ell = zmeta[b].m, np = M.np, m = M.m;
-    const int i0 = (int)(blockIdx.y % ti) * kSkI, c0 = (int)(blockIdx.y / ti) * kSkC;
+    const int i0 = (int)(blockIdx.y % ti) * I, c0 = (int)(blockIdx.y / ti) * C;
     if (ell == 0 || i0 >= ell || c0 >= np) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
-    v4 acc[kSkC / 16];
+    v4 acc[RBW][C / 16];
 #pragma unroll
-    for (int t = 0; t < kSkC / 16; ++t) acc[t] = v4{0, 0, 0, 0};
-    // staging roles: chunk row sr of Y columns c0 + 32 w + 2 q + (lane >> 5) (each load
-    // instruction reads two 32-row column segments); signs of sketch row i0 + lane for
-    // chunk rows w + 4q
-    const int sr = lane & 31, sc0 = w * 32 + (lane >> 5);
+    for (int rb = 0; rb < RBW; ++rb)
+#pragma unroll
+        for (int t = 0; t < C / 16; ++t) acc[rb][t] = v4{0, 0, 0, 0};
+    // staging roles: chunk row sr of Y columns w C/4 + (lane >> 5) + 2 q; sign word u of
+    // chunk row kw (threads below kSkK * NW)
+    const int sr = lane & 31, sc0 = w * (C / 4) + (lane >> 5);
     const double* Ybox = Y + M.y;
-    const int ia = i0 + lane, nw = (ell + 31) >> 5;
-    const bool iin = ia < ell;
-    const unsigned* brow = bits + boff[b] + min(ia >> 5, nw - 1);
-    const int ib = ia & 31;
-    constexpr int kQ = kSkK / kWaves;
-    double yv[16];
-    unsigned sw[kQ];
+    const int nw = (ell + 31) >> 5;
+    const int kw = tid / NW, u = tid % NW;
+    const bool wrole = tid < kSkK * NW && (i0 >> 5) + u < nw;
+    const unsigned* wsrc = bits + boff[b] + (i0 >> 5) + u;
+    double yv[QY];
+    unsigned sw = 0;
+    auto fetch = [&](int k) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-        yv[q] = Ybox[(long)min(c0 + sc0 + 2 * q, np - 1) * m + min(sr, m - 1)];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) sw[q] = brow[(long)min(w + kWaves * q, m - 1) * nw];
+        for (int q = 0; q < QY; ++q)
+            yv[q] = Ybox[(long)min(c0 + sc0 + 2 * q, np - 1) * m + min(k + sr, m - 1)];
+        if (wrole) sw = wsrc[(long)min(k + kw, m - 1) * nw];
+    };
+    fetch(0);
     for (int k0 = 0; k0 < m; k0 += kSkK) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < QY; ++q) {
             const int cc = sc0 + 2 * q;
-            sB[sr * kSkLdB + cc] = (c0 + cc < np && k0 + sr < m) ? yv[q] : 0.0;
+            sB[sr * LdB + cc] = (c0 + cc < np && k0 + sr < m) ? yv[q] : 0.0;
         }
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            const int kk = w + kWaves * q;
-            sA[kk * kSkLdA + lane] = (iin && k0 + kk < m) ? (((sw[q] >> ib) & 1u) ? -1.0 : 1.0) : 0.0;
-        }
-        if (k0 + kSkK < m) {
-            const int k1 = k0 + kSkK;
-#pragma unroll
-            for (int q = 0; q < 16; ++q)
-                yv[q] = Ybox[(long)min(c0 + sc0 + 2 * q, np - 1) * m + min(k1 + sr, m - 1)];
-#pragma unroll
-            for (int q = 0; q < kQ; ++q) sw[q] = brow[(long)min(k1 + w + kWaves * q, m - 1) * nw];
-        }
+        if (tid < kSkK * NW) sW[tid] = wrole ? sw : 0u;
         __syncthreads();
+        if (k0 + kSkK < m) fetch(k0 + kSkK);
 #pragma unroll 2
         for (int ks = 0; ks < kSkK / 4; ++ks) {
             const int kk = ks * 4 + lk;
-            const double a = sA[kk * kSkLdA + w * 16 + li];
+            double a[RBW];
 #pragma unroll
-            for (int t = 0; t < kSkC / 16; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sB[kk * kSkLdB + t * 16 + li], acc[t], 0, 0, 0);
+            for (int rb = 0; rb < RBW; ++rb) {
+                const int r = w * 16 * RBW + rb * 16 + li;   // sketch row within the tile
+                a[rb] = ((sW[kk * NW + (r >> 5)] >> (r & 31)) & 1u) ? -1.0 : 1.0;
+            }
+#pragma unroll
+            for (int t = 0; t < C / 16; ++t) {
+                const double bv = sB[kk * LdB + t * 16 + li];
+#pragma unroll
+                for (int rb = 0; rb < RBW; ++rb)
+                    acc[rb][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], bv, acc[rb][t], 0, 0, 0);
+            }
         }
     }
     double* Zb = Z + zmeta[b].y;
 #pragma unroll
-    for (int t = 0; t < kSkC / 16; ++t) {
-        const int c = c0 + t * 16 + li;
+    for (int rb = 0; rb < RBW; ++rb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int ii = i0 + w * 16 + 4 * v + lk;
-            if (ii < ell && c < np) Zb[ii + (long)c * ell] = acc[t][v];
+        for (int t = 0; t < C / 16; ++t) {
+            const int c = c0 + t * 16 + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ii = i0 + w * 16 * RBW + rb * 16 + 4 * v + lk;
+                if (ii < ell && c < np) Zb[ii + (long)c * ell] = acc[rb][t][v];
+            }
         }
-    }
 }
 
 void launch_sketch(int nbox, int np_max, long mw_max, const BoxMeta* meta, const BoxMeta* zmeta, const double* Y,
@@ -1369,8 +1375,10 @@ void launch_sketch(int nbox, int np_max, long mw_max, const BoxMeta* meta, const
     hipLaunchKernelGGL(k_sketch_signs, dim3(nbox, (unsigned)((mw_max + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                        s, meta, zmeta, nearl, cidx, N, seed, keys, boff, bits);
     // ell < np for every sketched box, so np_max bounds both dimensions of Z
-    const int ti = (np_max + kSkI - 1) / kSkI, tc = (np_max + kSkC - 1) / kSkC;
-    hipLaunchKernelGGL(k_sketch, dim3(nbox, ti * tc), dim3(kThreads), 0, s, meta, zmeta, Y, boff, bits, Z, ti);
+    constexpr int RBW = 2, C = 128, I = kWaves * 16 * RBW;
+    const int ti = (np_max + I - 1) / I, tc = (np_max + C - 1) / C;
+    hipLaunchKernelGGL((k_sketch<RBW, C>), dim3(nbox, ti * tc), dim3(kThreads), 0, s, meta, zmeta, Y, boff, bits, Z,
+                       ti);
 }
 
 // ---- box matrix A_pp --------------------------------------------------------
