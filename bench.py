@@ -73,9 +73,10 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (and matrix) peak
 FP32_PEAK_TFLOPS = 157.3
 
 
-def measured_traffic():
+def measured_traffic(shape):
     """HBM bytes per launch of the 512^2 64-RHS matvec from the committed rocprofv3
-    counter summary, or None if the kernel source changed since it was taken."""
+    counter summary, or None if the kernel source changed since it was taken or the
+    counters were taken for another tile shape."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "kernel_matvec_2d_512sq_64rhs.traffic.json")
     try:
@@ -83,7 +84,7 @@ def measured_traffic():
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     except (OSError, ValueError, KeyError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256") or rec.get("shape") != shape:
         return None
     return rec["traffic_bytes"]
 
@@ -780,7 +781,7 @@ def main():
         "roofline": {"kernel": "kernel_matvec (FP64, %d RHS)" % nrhs, "bound": "mfma",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic() if args.workload == "512sq" else None,
+                     "traffic": measured_traffic(tile) if args.workload == "512sq" else None,
                      "library_dgemm_tflops": dgemm_ref,
                      "work": "2 N^2 nrhs FP64 flops per launch on FP64 MFMA (the N^2 kernel "
                              "evaluations run on the VALU and are not counted)"} if achieved else None,
