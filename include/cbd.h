@@ -321,8 +321,9 @@ int kernel_matvec_fft(cbd_problem p, int nrhs, const double* x, double* y, void*
  * same number of 16-column right-hand-side blocks use it.  Each candidate runs on
  * the first min(grid, 1024) workgroups.  x, y: device scratch of N x min(nrhs, 64)
  * doubles each (overwritten; distinct).  On 2D grids the candidates include
- * workgroups of 8 waves.  *choice (may be NULL) receives the shape, coded as for
- * cbd_matvec_set_shape. */
+ * workgroups of 8 waves.  Times within 1% of the best count as ties, which go to
+ * the shape with more rows per workgroup (it reads x fewer times).  *choice (may be
+ * NULL) receives the shape, coded as for cbd_matvec_set_shape. */
 int cbd_autotune_matvec(cbd_problem p, int nrhs, double* x, double* y, void* stream, int* choice);
 /* cbd_matvec_set_shape - fix the matvec's tile shape for nrhs (as chosen by
  * cbd_autotune_matvec): shape = row blocks of 16 per wave (1, 2 or 4) with 4 waves per

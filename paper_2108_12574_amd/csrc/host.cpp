@@ -299,7 +299,9 @@ extern "C" int cbd_autotune_matvec(cbd_problem p, int nrhs, double* x, double* y
         float ms = 0.f;
         if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
         const double per_row = ms / (double)(blocks * rows);
-        if (per_row < best_t) {
+        // candidates come in order of rows per workgroup; within 1% of the best time the
+        // later one wins (a taller row band reads x fewer times)
+        if (per_row < best_t * 1.01) {
             best_t = per_row;
             best = rb;
         }
