@@ -1889,7 +1889,7 @@ static int apply_impl(cbd_factor f, int nrhs, const double* r, double* z, long s
     cbd_partition_s* Q = f->part;
     R* v = (R*)f->v;
     for (const Level& L : f->levels)
-        if (!root_uses_gemm(L) && (size_t)2 * L.np_max * sizeof(R) > 65536)
+        if (!root_uses_gemm(L) && (size_t)2 * L.np_max * sizeof(R) > apply_level_lds_limit<R>())
             return fail(CBD_EARG, "rs_apply: box of " + std::to_string(L.np_max) + " DOFs exceeds the LDS of the apply kernel");
     const long N = f->prob->N;
     const int nl = (int)f->levels.size();

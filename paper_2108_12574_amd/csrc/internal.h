@@ -162,6 +162,9 @@ void launch_gram(int nbox, int np_max, const BoxMeta* meta, const double* Y, con
                  hipStream_t s);
 size_t pchol_panel_lds(int np_max);
 size_t pchol_panel_lds_limit();
+size_t dyn_lds_limit(const void* kernel);
+template <typename R>
+size_t apply_level_lds_limit();
 void launch_pchol_panel(int nbox, int np_max, const BoxMeta* meta, const long* goff, double* G,
                         const GramState& st, int j0, double tol, double tie, hipStream_t s);
 void launch_pchol_finish(int nbox, int np_max, const BoxMeta* meta, const long* goff, const double* G,

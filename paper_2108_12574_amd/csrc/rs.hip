@@ -5,7 +5,9 @@
 // workgroup per box, all boxes of all subdomains in one launch.
 #include <algorithm>
 #include <climits>
+#include <map>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -52,6 +54,28 @@ __device__ __forceinline__ int wave_min_int(int v) {
     v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppRor8, 0xF, 0xF, true));
     return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
                min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+// Largest dynamic LDS `kernel` may take on the current device: the device's LDS per
+// workgroup less 1 KB for the kernel's own arrays (160 KB per workgroup on gfx950).
+// Above 64 KB a launch needs the kernel's attribute raised, which is done here once
+// per kernel and device (64 KB less 1 KB if that fails).
+size_t dyn_lds_limit(const void* kernel) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, size_t> lim;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 65536 - 1024;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& l = lim[{kernel, dev}];
+    if (!l) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        l = (size_t)v - 1024;
+        if (l > 65536 && hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l) != hipSuccess)
+            l = 65536 - 1024;
+    }
+    return l;
 }
 
 // ---- proxy / near-field matrix ---------------------------------------------
@@ -2341,6 +2365,11 @@ __global__ __launch_bounds__(kThreads) void k_apply_level(const BoxMeta* __restr
 }
 
 template <typename R>
+size_t apply_level_lds_limit() {
+    return dyn_lds_limit((const void*)k_apply_level<R>);
+}
+
+template <typename R>
 void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int* k, const R* F, R* v,
                         int nrhs, int np_max, bool forward, hipStream_t s) {
     if (nbox == 0) return;
@@ -2349,6 +2378,8 @@ void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int*
     // 2.04 and 2.18 ms for 32, 64 and 8)
     int rc = 16;
     while (rc > 1 && (size_t)2 * np_max * rc * sizeof(R) > 65536) rc >>= 1;
+    // (boxes whose one column exceeds 64 KB take more, up to the device's limit; the
+    // caller has checked that against apply_level_lds_limit)
     if (rc > nrhs) rc = nrhs;
     size_t shm = (size_t)2 * np_max * rc * sizeof(R);
     dim3 grid(nbox, (nrhs + rc - 1) / rc);
@@ -2738,27 +2769,9 @@ void launch_gram(int nbox, int np_max, const BoxMeta* meta, const double* Y, con
 }
 size_t pchol_panel_lds(int np_max) { return (size_t)np_max * (sizeof(double) + 2 * sizeof(int)); }
 
-// Largest dynamic LDS the panel kernel may take on the current device: the device's LDS
-// per workgroup less 1 KB for the kernel's own arrays (160 KB per workgroup on gfx950).
+// Largest dynamic LDS the panel kernel may take on the current device.
 size_t pchol_panel_lds_limit() {
-    static std::mutex mu;
-    static std::vector<size_t> lim;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 65536 - 1024;
-    std::lock_guard<std::mutex> lock(mu);
-    if ((int)lim.size() <= dev) lim.resize(dev + 1, 0);
-    if (!lim[dev]) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
-            v = 65536;
-        lim[dev] = (size_t)v - 1024;
-        // let the panel kernel take all of it (above 64 KB the launch needs the attribute)
-        if (lim[dev] > 65536 &&
-            hipFuncSetAttribute((const void*)k_pchol_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lim[dev]) != hipSuccess)
-            lim[dev] = 65536 - 1024;
-    }
-    return std::min(lim[dev], pchol_panel_lds(kPcholMaxCols));
+    return std::min(dyn_lds_limit((const void*)k_pchol_panel), pchol_panel_lds(kPcholMaxCols));
 }
 void launch_pchol_panel(int nbox, int np_max, const BoxMeta* meta, const long* goff, double* G,
                         const GramState& st, int j0, double tol, double tie, hipStream_t s) {
@@ -2796,7 +2809,8 @@ template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta
     template void launch_scatter<R>(const R*, int, const int*, const int*, long, double*,          \
                                     hipStream_t);                                                   \
     template void launch_apply_level<R>(int, const BoxMeta*, const int*, const int*, const R*, R*,  \
-                                        int, int, bool, hipStream_t);
+                                        int, int, bool, hipStream_t);                               \
+    template size_t apply_level_lds_limit<R>();
 CBD_INST(double)
 CBD_INST(float)
 #undef CBD_INST
