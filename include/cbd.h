@@ -210,8 +210,9 @@ int rs_factor_free(cbd_factor f);
  * storage, and the algorithmic flops of the factorization (ID by truncated CPQR,
  * elimination and root Cholesky).  Per box with m proxy+near rows, n_p active
  * DOFs, rank k and n_r = n_p - k: ID 4 m n_p k - 2 (m + n_p) k^2 + 4 k^3 / 3;
- * elimination 4 k^2 n_r + 3 k n_r^2 + 2 n_r^3 / 3; the root box counts as an
- * elimination with k = 0. */
+ * elimination 4 k^2 n_r + 3 k n_r^2 + n_r^3 / 3 (the method's operations, with E
+ * from a triangular solve; the explicit inverse the factor stores is not counted);
+ * the root box counts as an elimination with k = 0. */
 int rs_factor_stats(cbd_factor f, int* S, int* n_levels, size_t* bytes, double* flops);
 
 /* Per-level ranks: number of boxes at `level` (all subdomains, in batch order)

@@ -739,9 +739,10 @@ double cpqr_flops(double m, double n, double k) {
     return 4.0 * m * n * k - 2.0 * (m + n) * k * k + 4.0 * k * k * k / 3.0;
 }
 double elim_flops(double k, double nr) {
-    // T solve, B_sr, B_rr (symmetric), Cholesky, G^{-1}, E, B_ss (symmetric)
-    return k * k * nr + 2.0 * k * k * nr + 2.0 * nr * nr * k + nr * nr * nr / 3.0 + nr * nr * nr / 3.0 +
-           k * nr * nr + k * k * nr;
+    // the method's work: B_sr, B_rr (symmetric), Cholesky, E by a triangular solve, B_ss
+    // (symmetric).  The explicit G^{-1} this library stores for the apply is its own
+    // choice and is not counted.
+    return k * k * nr + 2.0 * k * k * nr + 2.0 * nr * nr * k + nr * nr * nr / 3.0 + k * nr * nr + k * k * nr;
 }
 
 // Features of a box known before its ID (input of the rank predictor).

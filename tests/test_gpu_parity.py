@@ -257,6 +257,18 @@ def test_full_size_matvec_sampled_rows(cfg3):
     assert np.abs(y[:, rows].T - yr).max() <= 1e-12 * np.abs(yr).max()
 
 
+@pytest.mark.parametrize("nrhs", [1, 64])
+def test_full_size_1024_dense_matvec_sampled_rows(nrhs):
+    # the dense product at 1024^2 (N = 1048576) with coefficients: one right-hand side
+    # takes the grid-line form, 64 the table form; sampled rows against the oracle's C sum
+    P, O = gpu_problem(2, 1024, coef=True)
+    x = synth.rhs(O.N, nrhs, seed=2)
+    y = P.matvec(torch.tensor(x, device=DEV)).cpu().numpy()
+    rows = np.concatenate([[0, O.N - 1, 1023, O.N // 2], np.random.default_rng(3).choice(O.N, 12, replace=False)])
+    yr = cmatvec.matvec(O, x.T, rows=rows)          # (rows, nrhs)
+    assert np.abs(y[:, rows].T - yr).max() <= 1e-12 * np.abs(yr).max()
+
+
 @pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
 def test_full_size_leaf_ids_sampled(cfg3, prec):
     # the first level depends on geometry only: sampled leaf boxes' skeletons
