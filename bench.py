@@ -741,6 +741,8 @@ def main():
         "factor_flops": st["flops"],
         "S_last_level": st["S"],
         "factor_bytes": st["bytes"],
+        "factor_launches": sched["launches"],
+        "factor_host_syncs": sched["host_syncs"],
         "n_it": [min(n_it), max(n_it)],
         "max_relres": max(rr_all),
         "pcg_launch_mode": {"timed": "graph" if box["graph"] else "eager", "eager_s": pcg_modes["eager"],

@@ -256,7 +256,8 @@ int rs_factor_root(cbd_factor f, int i, int* S, int* idx, double* Ginv);
  *  chunks processed (the number of levels when no level was split), and, of the
  *  sketched boxes, those whose ID came from the rank-sized first sketch (4 k_p + 32
  *  rows for a predicted rank k_p, kept when k <= rows / 4) and those whose rank-sized
- *  sketch was not kept.  Any output may be NULL. */
+ *  sketch was not kept, and the kernel launches of the factorization (copies not
+ *  counted).  Any output may be NULL. */
 #define CBD_MLP_FEATURES 6
 #define CBD_MLP_WIDTH 64
 int rank_mlp_params(void);
@@ -278,7 +279,7 @@ int rank_mlp_loss_grad_noalloc(const float* params, int n, const float* X, const
 int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* X, int* k);
 int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
                        double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks,
-                       int* chunks, int* sketched_pred, int* sketch_pred_rejected);
+                       int* chunks, int* sketched_pred, int* sketch_pred_rejected, long* launches);
 
 /* rs_apply - z = T^{-1} r = sum_i R_i^T A_i^{-1} R_i r, (e:ad), with every A_i^{-1}
  * applied through its RS factor: gather, forward sweep over levels, root solve,

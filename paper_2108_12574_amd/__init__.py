@@ -285,13 +285,14 @@ class Factor:
         (rs_factor_schedule)."""
         v = [ctypes.c_int() for _ in range(10)]
         e = ctypes.c_double()
+        nl = ctypes.c_long()
         check(lib().rs_factor_schedule(self.handle, ctypes.byref(v[0]), ctypes.byref(v[1]), ctypes.byref(v[2]),
                                        ctypes.byref(e), ctypes.byref(v[3]), ctypes.byref(v[4]), ctypes.byref(v[5]),
-                                       ctypes.byref(v[6]), ctypes.byref(v[7]), ctypes.byref(v[8])))
+                                       ctypes.byref(v[6]), ctypes.byref(v[7]), ctypes.byref(v[8]), ctypes.byref(nl)))
         return {"host_syncs": v[0].value, "qr_steps": v[1].value, "mispredicted": v[2].value,
                 "mean_abs_err": e.value, "row_compressed": v[3].value, "sketched": v[4].value,
                 "sketch_fallbacks": v[5].value, "chunks": v[6].value, "sketched_pred": v[7].value,
-                "sketch_pred_rejected": v[8].value}
+                "sketch_pred_rejected": v[8].value, "launches": nl.value}
 
     def root(self, i):
         import numpy as np

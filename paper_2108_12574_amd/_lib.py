@@ -64,7 +64,7 @@ SIGNATURES = [
     ("rank_mlp_adam", _i, [_vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp]),
     ("rank_mlp_loss_grad_noalloc", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
     ("rs_factor_features", _i, [_vp, _i, _ip, ctypes.POINTER(ctypes.c_float), _ip]),
-    ("rs_factor_schedule", _i, [_vp, _ip, _ip, _ip, _dp, _ip, _ip, _ip, _ip, _ip, _ip]),
+    ("rs_factor_schedule", _i, [_vp, _ip, _ip, _ip, _dp, _ip, _ip, _ip, _ip, _ip, _ip, ctypes.POINTER(_l)]),
     ("cbd_timing_enable", _i, [_i]),
     ("cbd_timing_get", _i, [ctypes.c_char_p, _dp, ctypes.POINTER(_l)]),
     ("cbd_timing_reset", _i, []),

@@ -145,7 +145,7 @@ static void fft_all_axes(double2* buf, int d, int P, int logP, int batch, const 
     for (int t = 0; t < d; ++t) vol *= P;
     long inner = 1;
     for (int a = 0; a < d; ++a) {
-        hipLaunchKernelGGL(k_fft_lines, dim3((unsigned)(vol / P), batch), dim3(kFftThreads),
+        CBD_LAUNCH(k_fft_lines, dim3((unsigned)(vol / P), batch), dim3(kFftThreads),
                            (size_t)P * sizeof(double2), s, buf, P, logP, vol, inner, tw, inverse);
         inner *= P;
     }
@@ -156,12 +156,12 @@ void launch_fft_prepare(const ProblemView& Pv, int P, int logP, double spacing, 
     long vol = 1;
     for (int t = 0; t < Pv.d; ++t) vol *= P;
     if (Pv.d == 2)
-        hipLaunchKernelGGL(k_fft_generator<2>, dim3(grid_for(vol)), dim3(256), 0, s, gbuf, Pv.n, P, spacing);
+        CBD_LAUNCH(k_fft_generator<2>, dim3(grid_for(vol)), dim3(256), 0, s, gbuf, Pv.n, P, spacing);
     else
-        hipLaunchKernelGGL(k_fft_generator<3>, dim3(grid_for(vol)), dim3(256), 0, s, gbuf, Pv.n, P, spacing);
+        CBD_LAUNCH(k_fft_generator<3>, dim3(grid_for(vol)), dim3(256), 0, s, gbuf, Pv.n, P, spacing);
     fft_all_axes(gbuf, Pv.d, P, logP, 1, tw, 0, s);
     // the transform of the even generator is real: keep the real part
-    hipLaunchKernelGGL(k_fft_real, dim3(grid_for(vol)), dim3(256), 0, s, gbuf, ghat, vol);
+    CBD_LAUNCH(k_fft_real, dim3(grid_for(vol)), dim3(256), 0, s, gbuf, ghat, vol);
 }
 
 void launch_matvec_fft(const ProblemView& Pv, int P, int logP, const double* ghat, const double2* tw,
@@ -171,19 +171,19 @@ void launch_matvec_fft(const ProblemView& Pv, int P, int logP, const double* gha
     for (int c0 = 0; c0 < nrhs; c0 += 2 * max_pairs) {
         const int pairs = (int)((nrhs - c0 + 1) / 2 < max_pairs ? (nrhs - c0 + 1) / 2 : max_pairs);
         if (Pv.d == 2)
-            hipLaunchKernelGGL(k_fft_pack<2>, dim3(grid_for(vol * pairs)), dim3(256), 0, s, Pv, P, nrhs, c0, pairs,
+            CBD_LAUNCH(k_fft_pack<2>, dim3(grid_for(vol * pairs)), dim3(256), 0, s, Pv, P, nrhs, c0, pairs,
                                x, buf);
         else
-            hipLaunchKernelGGL(k_fft_pack<3>, dim3(grid_for(vol * pairs)), dim3(256), 0, s, Pv, P, nrhs, c0, pairs,
+            CBD_LAUNCH(k_fft_pack<3>, dim3(grid_for(vol * pairs)), dim3(256), 0, s, Pv, P, nrhs, c0, pairs,
                                x, buf);
         fft_all_axes(buf, Pv.d, P, logP, pairs, tw, 0, s);
-        hipLaunchKernelGGL(k_fft_scale, dim3(grid_for(vol * pairs)), dim3(256), 0, s, buf, ghat, vol, pairs);
+        CBD_LAUNCH(k_fft_scale, dim3(grid_for(vol * pairs)), dim3(256), 0, s, buf, ghat, vol, pairs);
         fft_all_axes(buf, Pv.d, P, logP, pairs, tw, 1, s);
         if (Pv.d == 2)
-            hipLaunchKernelGGL(k_fft_unpack<2>, dim3(grid_for(Pv.N * pairs)), dim3(256), 0, s, Pv, P, nrhs, c0,
+            CBD_LAUNCH(k_fft_unpack<2>, dim3(grid_for(Pv.N * pairs)), dim3(256), 0, s, Pv, P, nrhs, c0,
                                pairs, x, buf, y);
         else
-            hipLaunchKernelGGL(k_fft_unpack<3>, dim3(grid_for(Pv.N * pairs)), dim3(256), 0, s, Pv, P, nrhs, c0,
+            CBD_LAUNCH(k_fft_unpack<3>, dim3(grid_for(Pv.N * pairs)), dim3(256), 0, s, Pv, P, nrhs, c0,
                                pairs, x, buf, y);
     }
 }

@@ -19,6 +19,8 @@
 
 using namespace cbd;
 
+thread_local long cbd::g_launches = 0;
+
 // ---------------------------------------------------------------------------
 // errors, timing
 // ---------------------------------------------------------------------------
@@ -697,6 +699,7 @@ struct cbd_factor_s {
     int sketch_pred_rejected = 0;   // boxes whose rank-sized sketch was not kept
     int chunks = 0;           // level chunks (more than the number of levels when the workspace is bounded)
     int gram_batches = 0;     // batches whose ID came from the pivoted Cholesky of the Gram matrix
+    long launches = 0;        // kernel launches of the factorization
     double pred_abs_err = 0.0;
     int pred_count = 0;
     size_t esize;
@@ -1784,12 +1787,14 @@ extern "C" int rs_factor_batched(cbd_problem p, cbd_partition q, const cbd_rs_op
     F->ws.init(ws, ws_bytes);
     {
         ScopedTimer tm("factor", s);
+        const long l0 = g_launches;
         try {
             rc = o->precision == CBD_PREC_FP64 ? factor_impl<double>(p, q, o, rank_hint, ranks_out, s, F)
                                                : factor_impl<float>(p, q, o, rank_hint, ranks_out, s, F);
         } catch (const std::bad_alloc&) {
             rc = fail(CBD_ENOMEM, "rs_factor_batched: host allocation failed");
         }
+        F->launches = g_launches - l0;
     }
     if (ws_used) *ws_used = rc == CBD_EWORKSPACE ? F->ws.peak + F->ws.short_by : F->ws.peak;
     if (rc) {
@@ -2001,8 +2006,9 @@ extern "C" int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* 
 
 extern "C" int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
                                   double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks,
-                                  int* chunks, int* sketched_pred, int* sketch_pred_rejected) {
+                                  int* chunks, int* sketched_pred, int* sketch_pred_rejected, long* launches) {
     if (!f) return fail(CBD_EARG, "rs_factor_schedule: NULL factor");
+    if (launches) *launches = f->launches;
     if (host_syncs) *host_syncs = f->host_syncs;
     if (qr_steps) *qr_steps = f->qr_steps;
     if (mispredicted) *mispredicted = f->mispredicted;

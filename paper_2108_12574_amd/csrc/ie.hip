@@ -31,7 +31,7 @@ void launch_assemble(int d, int n, int grid, const double* b, const double* c, d
     long N = 1;
     for (int t = 0; t < d; ++t) N *= n;
     int blocks = (int)((N + 255) / 256);
-    hipLaunchKernelGGL(k_assemble, dim3(blocks), dim3(256), 0, s, d, n, grid, N, b, c, pts, diag,
+    CBD_LAUNCH(k_assemble, dim3(blocks), dim3(256), 0, s, d, n, grid, N, b, c, pts, diag,
                        w, rs, a_self, weight);
 }
 
@@ -454,12 +454,12 @@ static void matvec_launch(const ProblemView& P, int nrhs, const double* x, doubl
     dim3 grid(blocks, (nrhs + 63) / 64);
     if (D == 2 && matvec_grid_form(P, RB)) {
         if constexpr (RB >= 8)
-            hipLaunchKernelGGL((k_matvec_grid2<NB, RB & 7, 8>), grid, dim3(512), 0, s, P, nrhs, x, y);
+            CBD_LAUNCH((k_matvec_grid2<NB, RB & 7, 8>), grid, dim3(512), 0, s, P, nrhs, x, y);
         else
-            hipLaunchKernelGGL((k_matvec_grid2<NB, RB, kMvWaves>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y);
+            CBD_LAUNCH((k_matvec_grid2<NB, RB, kMvWaves>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y);
         return;
     }
-    hipLaunchKernelGGL((k_matvec<D, NB, (RB & 7)>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y, log_table());
+    CBD_LAUNCH((k_matvec<D, NB, (RB & 7)>), grid, dim3(kMvThreads), 0, s, P, nrhs, x, y, log_table());
 }
 
 template <int D, int NB>
@@ -488,7 +488,7 @@ void launch_matvec(const ProblemView& P, int nrhs, const double* x, double* y, i
                    hipStream_t s) {
     if (nrhs == 1 && P.d == 2 && P.n % kTJ == 0 && max_blocks <= 0) {
         // one right-hand side: grid lines fill the MFMA columns
-        hipLaunchKernelGGL(k_matvec_lines2, dim3(P.n / 64, P.n / 16), dim3(kMvThreads), 0, s, P, x, y);
+        CBD_LAUNCH(k_matvec_lines2, dim3(P.n / 64, P.n / 16), dim3(kMvThreads), 0, s, P, x, y);
         return;
     }
     const int nb = matvec_nb(nrhs);

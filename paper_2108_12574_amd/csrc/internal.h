@@ -8,6 +8,14 @@
 
 namespace cbd {
 
+// Kernel launches issued by this host thread (the factorization reports its count).
+extern thread_local long g_launches;
+#define CBD_LAUNCH(...)                \
+    do {                               \
+        ++::cbd::g_launches;           \
+        hipLaunchKernelGGL(__VA_ARGS__); \
+    } while (0)
+
 constexpr double kInv2Pi = 0.15915494309189533577;   // 1/(2 pi)
 constexpr double kInv4Pi = 0.07957747154594766788;   // 1/(4 pi)
 

@@ -198,7 +198,7 @@ __global__ void k_mlp_adam(float* __restrict__ p, const float* __restrict__ g, f
 void launch_mlp_forward(const float* p, int n, const float* X, float* y, float* z1, float* z2,
                         hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_mlp_forward, dim3((n + kMlpThreads - 1) / kMlpThreads), dim3(kMlpThreads), 0, s, p,
+    CBD_LAUNCH(k_mlp_forward, dim3((n + kMlpThreads - 1) / kMlpThreads), dim3(kMlpThreads), 0, s, p,
                        n, X, y, z1, z2);
 }
 
@@ -211,9 +211,9 @@ void launch_mlp_loss_grad(const float* p, int n, const float* X, const float* t,
     float* dz1 = z2 + (long)n * kH;
     float* dz2 = dz1 + (long)n * kH;
     const int blocks = (n + kMlpThreads - 1) / kMlpThreads;
-    hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(kMlpThreads), 0, s, p, n, X, y, z1, z2);
-    hipLaunchKernelGGL(k_mlp_deltas, dim3(blocks), dim3(kMlpThreads), 0, s, p, n, y, t, z1, z2, dy, dz1, dz2);
-    hipLaunchKernelGGL(k_mlp_grads, dim3(kH + 1), dim3(kMlpThreads), 0, s, n, X, y, t, z1, z2, dy, dz1, dz2,
+    CBD_LAUNCH(k_mlp_forward, dim3(blocks), dim3(kMlpThreads), 0, s, p, n, X, y, z1, z2);
+    CBD_LAUNCH(k_mlp_deltas, dim3(blocks), dim3(kMlpThreads), 0, s, p, n, y, t, z1, z2, dy, dz1, dz2);
+    CBD_LAUNCH(k_mlp_grads, dim3(kH + 1), dim3(kMlpThreads), 0, s, n, X, y, t, z1, z2, dy, dz1, dz2,
                        grad, loss);
 }
 
@@ -240,7 +240,7 @@ float* mlp_static_scratch() {
 
 void launch_mlp_adam(float* p, const float* g, float* m, float* v, int step, float lr, hipStream_t s) {
     const float c1 = 1.f - powf(0.9f, (float)step), c2 = 1.f - powf(0.999f, (float)step);
-    hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, p, g, m, v, kMlpParams,
+    CBD_LAUNCH(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, p, g, m, v, kMlpParams,
                        lr, c1, c2);
 }
 

@@ -44,9 +44,9 @@ __global__ __launch_bounds__(kVecThreads) void k_dot_final(const double* __restr
 
 void launch_dot(const double* a, const double* b, long N, int nrhs, double* partial, double* out,
                 hipStream_t s) {
-    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks, nrhs), dim3(kVecThreads), 0, s, a, b, N,
+    CBD_LAUNCH(k_dot_partial, dim3(kDotBlocks, nrhs), dim3(kVecThreads), 0, s, a, b, N,
                        partial);
-    hipLaunchKernelGGL(k_dot_final, dim3(nrhs), dim3(kVecThreads), 0, s, partial, out);
+    CBD_LAUNCH(k_dot_final, dim3(nrhs), dim3(kVecThreads), 0, s, partial, out);
 }
 
 __global__ void k_pcg_alpha(const double* rz, const double* pq, const int* active, double* alpha,
@@ -57,7 +57,7 @@ __global__ void k_pcg_alpha(const double* rz, const double* pq, const int* activ
 
 void launch_pcg_alpha(const double* rz, const double* pq, const int* active, double* alpha,
                       int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, s, rz, pq, active, alpha,
+    CBD_LAUNCH(k_pcg_alpha, dim3((nrhs + 63) / 64), dim3(64), 0, s, rz, pq, active, alpha,
                        nrhs);
 }
 
@@ -78,7 +78,7 @@ void launch_pcg_update_ur(double* u, double* r, const double* p, const double* q
                           const double* alpha, long N, int nrhs, hipStream_t s) {
     int blocks = (int)((N + kVecThreads - 1) / kVecThreads);
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_pcg_update_ur, dim3(blocks, nrhs), dim3(kVecThreads), 0, s, u, r, p, q,
+    CBD_LAUNCH(k_pcg_update_ur, dim3(blocks, nrhs), dim3(kVecThreads), 0, s, u, r, p, q,
                        alpha, N);
 }
 
@@ -93,7 +93,7 @@ __global__ void k_pcg_beta(const double* rz_new, double* rz, const int* active, 
 
 void launch_pcg_beta(const double* rz_new, double* rz, const int* active, double* beta, int nrhs,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_beta, dim3((nrhs + 63) / 64), dim3(64), 0, s, rz_new, rz, active, beta,
+    CBD_LAUNCH(k_pcg_beta, dim3((nrhs + 63) / 64), dim3(64), 0, s, rz_new, rz, active, beta,
                        nrhs);
 }
 
@@ -110,7 +110,7 @@ void launch_pcg_update_p(double* p, const double* z, const double* beta, long N,
                          hipStream_t s) {
     int blocks = (int)((N + kVecThreads - 1) / kVecThreads);
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_pcg_update_p, dim3(blocks, nrhs), dim3(kVecThreads), 0, s, p, z, beta, N);
+    CBD_LAUNCH(k_pcg_update_p, dim3(blocks, nrhs), dim3(kVecThreads), 0, s, p, z, beta, N);
 }
 
 __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, long n) {
@@ -135,13 +135,13 @@ static int vec_blocks(long n) {
 }
 
 void launch_copy(double* dst, const double* src, long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, dst, src, n);
+    CBD_LAUNCH(k_copy, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, dst, src, n);
 }
 void launch_fill(double* dst, double v, long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, dst, v, n);
+    CBD_LAUNCH(k_fill, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, dst, v, n);
 }
 void launch_sub(double* dst, const double* a, const double* b, long n, hipStream_t s) {
-    hipLaunchKernelGGL(k_sub, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, dst, a, b, n);
+    CBD_LAUNCH(k_sub, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, dst, a, b, n);
 }
 
 }  // namespace cbd

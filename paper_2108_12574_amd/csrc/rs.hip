@@ -155,10 +155,10 @@ void launch_proxy_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, co
     if (nbox == 0) return;
     dim3 grid(nbox, 8);
     if (P.d == 2)
-        hipLaunchKernelGGL((k_proxy_matrix<2, R>), grid, dim3(kThreads), 0, s, P, meta, act, nearl,
+        CBD_LAUNCH((k_proxy_matrix<2, R>), grid, dim3(kThreads), 0, s, P, meta, act, nearl,
                            cidx, pxdir, npxy, Y);
     else
-        hipLaunchKernelGGL((k_proxy_matrix<3, R>), grid, dim3(kThreads), 0, s, P, meta, act, nearl,
+        CBD_LAUNCH((k_proxy_matrix<3, R>), grid, dim3(kThreads), 0, s, P, meta, act, nearl,
                            cidx, pxdir, npxy, Y);
 }
 
@@ -421,10 +421,10 @@ void launch_cpqr(int nbox, const BoxMeta* meta, double* Y, const int* act, int* 
     if (nbox == 0) return;
     size_t shm = (size_t)(np_max + m_max) * sizeof(double) + (size_t)np_max * sizeof(int);
     if (m_max <= 512)
-        hipLaunchKernelGGL(k_cpqr<8>, dim3(nbox), dim3(kThreads), shm, s, meta, Y, act, sr, perm, k, T64, tol,
+        CBD_LAUNCH(k_cpqr<8>, dim3(nbox), dim3(kThreads), shm, s, meta, Y, act, sr, perm, k, T64, tol,
                            tie);
     else
-        hipLaunchKernelGGL(k_cpqr<16>, dim3(nbox), dim3(kThreads), shm, s, meta, Y, act, sr, perm, k, T64, tol,
+        CBD_LAUNCH(k_cpqr<16>, dim3(nbox), dim3(kThreads), shm, s, meta, Y, act, sr, perm, k, T64, tol,
                            tie);
 }
 
@@ -757,42 +757,42 @@ __global__ __launch_bounds__(kThreads) void k_qr_coeff(const BoxMeta* __restrict
 void launch_qr_init(int nbox, int np_max, const BoxMeta* meta, const double* Y, const QrState& st,
                     hipStream_t s) {
     if (nbox == 0) return;
-    hipLaunchKernelGGL(k_qr_init, dim3(nbox, (np_max + kQrCols - 1) / kQrCols), dim3(kThreads), 0, s, meta,
+    CBD_LAUNCH(k_qr_init, dim3(nbox, (np_max + kQrCols - 1) / kQrCols), dim3(kThreads), 0, s, meta,
                        Y, st);
 }
 void launch_qr_step(int nbox, int np_max, int m_max, const BoxMeta* meta, double* Y, const QrState& st,
                     int j, double tol, double tie, hipStream_t s) {
     if (nbox == 0) return;
-    hipLaunchKernelGGL(k_qr_pivot, dim3(nbox), dim3(kThreads), 0, s, meta, Y, st, j, tol, tie);
+    CBD_LAUNCH(k_qr_pivot, dim3(nbox), dim3(kThreads), 0, s, meta, Y, st, j, tol, tie);
     // rows of the update: at most m_max - j; the register form holds up to 64 NR of them
     // (3072 rows; within 256 registers per lane)
     const int cb = (m_max - j + 63) / 64;
     const dim3 grid(nbox, (np_max + kQrCols - 1) / kQrCols);
     const size_t shm = (size_t)m_max * sizeof(double);
     if (cb <= 2)
-        hipLaunchKernelGGL(k_qr_update<2>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+        CBD_LAUNCH(k_qr_update<2>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
     else if (cb <= 4)
-        hipLaunchKernelGGL(k_qr_update<4>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+        CBD_LAUNCH(k_qr_update<4>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
     else if (cb <= 8)
-        hipLaunchKernelGGL(k_qr_update<8>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+        CBD_LAUNCH(k_qr_update<8>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
     else if (cb <= 12)
-        hipLaunchKernelGGL(k_qr_update<12>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+        CBD_LAUNCH(k_qr_update<12>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
     else if (cb <= 16)
-        hipLaunchKernelGGL(k_qr_update<16>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+        CBD_LAUNCH(k_qr_update<16>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
     else if (cb <= 24)
-        hipLaunchKernelGGL(k_qr_update<24>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+        CBD_LAUNCH(k_qr_update<24>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
     else if (cb <= 32)
-        hipLaunchKernelGGL(k_qr_update<32>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+        CBD_LAUNCH(k_qr_update<32>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
     else if (cb <= 48)
-        hipLaunchKernelGGL(k_qr_update<48>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+        CBD_LAUNCH(k_qr_update<48>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
     else
-        hipLaunchKernelGGL(k_qr_update<0>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
+        CBD_LAUNCH(k_qr_update<0>, grid, dim3(kThreads), shm, s, meta, Y, st, j);
 }
 void launch_qr_finish(int nbox, int np_max, const BoxMeta* meta, double* Y, const QrState& st, const int* act,
                       int* sr, int* perm, int* k, double* T64, hipStream_t s) {
     if (nbox == 0) return;
-    hipLaunchKernelGGL(k_qr_finish, dim3(nbox), dim3(kThreads), 0, s, meta, Y, st, act, sr, perm, k);
-    hipLaunchKernelGGL(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s,
+    CBD_LAUNCH(k_qr_finish, dim3(nbox), dim3(kThreads), 0, s, meta, Y, st, act, sr, perm, k);
+    CBD_LAUNCH(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s,
                        meta, Y, k, T64);
 }
 
@@ -801,12 +801,12 @@ void launch_cpqr_reg(int nbox, int np_max, int m_max, const BoxMeta* meta, doubl
     if (nbox == 0) return;
     // (up to 13 columns of 4 x 64 rows per wave: 104 registers of matrix, no spills)
     if (np_max <= kRegWaves * 8)
-        hipLaunchKernelGGL((k_cpqr_reg<8, 4>), dim3(nbox), dim3(kRegThreads), 0, s, meta, Y, act, sr, perm, k, tol,
+        CBD_LAUNCH((k_cpqr_reg<8, 4>), dim3(nbox), dim3(kRegThreads), 0, s, meta, Y, act, sr, perm, k, tol,
                            tie);
     else
-        hipLaunchKernelGGL((k_cpqr_reg<13, 4>), dim3(nbox), dim3(kRegThreads), 0, s, meta, Y, act, sr, perm, k,
+        CBD_LAUNCH((k_cpqr_reg<13, 4>), dim3(nbox), dim3(kRegThreads), 0, s, meta, Y, act, sr, perm, k,
                            tol, tie);
-    hipLaunchKernelGGL(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s, meta,
+    CBD_LAUNCH(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s, meta,
                        Y, k, T64);
 }
 
@@ -1235,22 +1235,22 @@ void launch_hqr(int nbox, int np_max, int m_max, int k_max, const BoxMeta* meta,
     const int pw = rr <= 5 ? kHqrRegW : kHqrPanel;
     for (int j0 = 0; j0 < k_max; j0 += pw) {
         if (rr <= 2)
-            hipLaunchKernelGGL(k_hqr_panel_reg<2>, dim3(nbox), dim3(kHqrRegThreads), 0, s, meta, Y, j0, Tw, alpha,
+            CBD_LAUNCH(k_hqr_panel_reg<2>, dim3(nbox), dim3(kHqrRegThreads), 0, s, meta, Y, j0, Tw, alpha,
                                Vbuf, vstride);
         else if (rr == 3)
-            hipLaunchKernelGGL(k_hqr_panel_reg<3>, dim3(nbox), dim3(kHqrRegThreads), 0, s, meta, Y, j0, Tw, alpha,
+            CBD_LAUNCH(k_hqr_panel_reg<3>, dim3(nbox), dim3(kHqrRegThreads), 0, s, meta, Y, j0, Tw, alpha,
                                Vbuf, vstride);
         else if (rr <= 5)
-            hipLaunchKernelGGL(k_hqr_panel_reg<5>, dim3(nbox), dim3(kHqrRegThreads), 0, s, meta, Y, j0, Tw, alpha,
+            CBD_LAUNCH(k_hqr_panel_reg<5>, dim3(nbox), dim3(kHqrRegThreads), 0, s, meta, Y, j0, Tw, alpha,
                                Vbuf, vstride);
         else
-            hipLaunchKernelGGL(k_hqr_panel, dim3(nbox), dim3(kHqrThreads), 0, s, meta, Y, j0, Tw, alpha, Vbuf,
+            CBD_LAUNCH(k_hqr_panel, dim3(nbox), dim3(kHqrThreads), 0, s, meta, Y, j0, Tw, alpha, Vbuf,
                                vstride);
         if (j0 + pw < np_max)
-            hipLaunchKernelGGL(k_hqr_update, dim3(nbox, ct), dim3(kThreads), 0, s, meta, Y, j0, pw, Tw, Vbuf,
+            CBD_LAUNCH(k_hqr_update, dim3(nbox, ct), dim3(kThreads), 0, s, meta, Y, j0, pw, Tw, Vbuf,
                                vstride);
     }
-    hipLaunchKernelGGL(k_hqr_compact, dim3(nbox, 16), dim3(kThreads), 0, s, meta, Y, alpha, cmeta, Rc);
+    CBD_LAUNCH(k_hqr_compact, dim3(nbox, 16), dim3(kThreads), 0, s, meta, Y, alpha, cmeta, Rc);
 }
 
 // ---- randomized ID: the sketch Z = Omega Y -----------------------------------
@@ -1396,12 +1396,12 @@ void launch_sketch(int nbox, int np_max, long mw_max, const BoxMeta* meta, const
                    const int* nearl, const int* cidx, long N, unsigned long long seed,
                    const unsigned long long* keys, const long* boff, unsigned* bits, double* Z, hipStream_t s) {
     if (nbox == 0) return;
-    hipLaunchKernelGGL(k_sketch_signs, dim3(nbox, (unsigned)((mw_max + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+    CBD_LAUNCH(k_sketch_signs, dim3(nbox, (unsigned)((mw_max + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                        s, meta, zmeta, nearl, cidx, N, seed, keys, boff, bits);
     // ell < np for every sketched box, so np_max bounds both dimensions of Z
     constexpr int RBW = 2, C = 128, I = kWaves * 16 * RBW;
     const int ti = (np_max + I - 1) / I, tc = (np_max + C - 1) / C;
-    hipLaunchKernelGGL((k_sketch<RBW, C>), dim3(nbox, ti * tc), dim3(kThreads), 0, s, meta, zmeta, Y, boff, bits, Z,
+    CBD_LAUNCH((k_sketch<RBW, C>), dim3(nbox, ti * tc), dim3(kThreads), 0, s, meta, zmeta, Y, boff, bits, Z,
                        ti);
 }
 
@@ -1478,10 +1478,10 @@ void launch_box_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, cons
     if (nbox == 0) return;
     dim3 grid(nbox, 16);
     if (P.d == 2)
-        hipLaunchKernelGGL((k_box_matrix<2, R>), grid, dim3(kThreads), 0, s, P, meta, act, cidx, ch,
+        CBD_LAUNCH((k_box_matrix<2, R>), grid, dim3(kThreads), 0, s, P, meta, act, cidx, ch,
                            App);
     else
-        hipLaunchKernelGGL((k_box_matrix<3, R>), grid, dim3(kThreads), 0, s, P, meta, act, cidx, ch,
+        CBD_LAUNCH((k_box_matrix<3, R>), grid, dim3(kThreads), 0, s, P, meta, act, cidx, ch,
                            App);
 }
 
@@ -2012,14 +2012,14 @@ void launch_big_schur(int nbig, int np_max, const BoxMeta* meta, const int* list
     auto gemm = [&](int op) {
         if constexpr (sizeof(R) == 4) {
             if (bf16) {
-                hipLaunchKernelGGL((k_big_gemm<R, true>), grid, dim3(kThreads), 0, s, meta, list, k, Wk, F, op);
+                CBD_LAUNCH((k_big_gemm<R, true>), grid, dim3(kThreads), 0, s, meta, list, k, Wk, F, op);
                 return;
             }
         }
-        hipLaunchKernelGGL((k_big_gemm<R, false>), grid, dim3(kThreads), 0, s, meta, list, k, Wk, F, op);
+        CBD_LAUNCH((k_big_gemm<R, false>), grid, dim3(kThreads), 0, s, meta, list, k, Wk, F, op);
     };
     if (phase == 1) {
-        hipLaunchKernelGGL((k_big_gather<R>), dim3(nbig, 64), dim3(kThreads), 0, s, meta, list, perm, k, App, T64,
+        CBD_LAUNCH((k_big_gather<R>), dim3(nbig, 64), dim3(kThreads), 0, s, meta, list, perm, k, App, T64,
                            Wk, F);
         gemm(0);
         gemm(1);
@@ -2178,12 +2178,12 @@ void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, const int*
     if (nbox == 0) return;
     if constexpr (sizeof(R) == 4) {
         if (bf16) {
-            hipLaunchKernelGGL((k_eliminate<R, true>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App,
+            CBD_LAUNCH((k_eliminate<R, true>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App,
                                T64, Wk, F, status);
             return;
         }
     }
-    hipLaunchKernelGGL((k_eliminate<R, false>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App, T64,
+    CBD_LAUNCH((k_eliminate<R, false>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App, T64,
                        Wk, F, status);
 }
 
@@ -2192,20 +2192,20 @@ void launch_big_cholesky_inverse(int nbig, int nr_max, const BoxMeta* meta, cons
                                  R* Wk, R* F, int* status, hipStream_t s) {
     if (nbig == 0) return;
     for (int J = 0; J < nr_max; J += kBig) {
-        hipLaunchKernelGGL((k_bchol_diag<R>), dim3(nbig), dim3(kThreads), 0, s, meta, list, k, Wk, F, J, status);
+        CBD_LAUNCH((k_bchol_diag<R>), dim3(nbig), dim3(kThreads), 0, s, meta, list, k, Wk, F, J, status);
         const int rem = nr_max - J - kBig;
         if (rem > 0) {
-            hipLaunchKernelGGL((k_bchol_panel<R>), dim3(nbig, (rem + kPanel - 1) / kPanel), dim3(kThreads), 0, s,
+            CBD_LAUNCH((k_bchol_panel<R>), dim3(nbig, (rem + kPanel - 1) / kPanel), dim3(kThreads), 0, s,
                                meta, list, k, Wk, F, J);
             const int tiles = (rem + 63) / 64;
-            hipLaunchKernelGGL((k_bchol_update<R>), dim3(nbig, tiles * (tiles + 1) / 2), dim3(kThreads), 0, s,
+            CBD_LAUNCH((k_bchol_update<R>), dim3(nbig, tiles * (tiles + 1) / 2), dim3(kThreads), 0, s,
                                meta, list, k, Wk, F, J);
         }
     }
     for (int J = kBig; J < nr_max; J += kBig) {
         const int chunks = (J + 63) / 64;
-        hipLaunchKernelGGL((k_binv<R>), dim3(nbig, chunks), dim3(kThreads), 0, s, meta, list, k, Wk, F, J, 0);
-        hipLaunchKernelGGL((k_binv<R>), dim3(nbig, chunks), dim3(kThreads), 0, s, meta, list, k, Wk, F, J, 1);
+        CBD_LAUNCH((k_binv<R>), dim3(nbig, chunks), dim3(kThreads), 0, s, meta, list, k, Wk, F, J, 0);
+        CBD_LAUNCH((k_binv<R>), dim3(nbig, chunks), dim3(kThreads), 0, s, meta, list, k, Wk, F, J, 1);
     }
 }
 
@@ -2247,7 +2247,7 @@ void launch_gather(const double* r, long N, int nrhs, const int* cidx, long tota
                    hipStream_t s) {
     if (total == 0 || nrhs == 0) return;
     const long b = (total + kGT - 1) / kGT;
-    hipLaunchKernelGGL((k_gather<R>), dim3((unsigned)b), dim3(256), 0, s, r, N, nrhs, cidx, total, s0, s1, v);
+    CBD_LAUNCH((k_gather<R>), dim3((unsigned)b), dim3(256), 0, s, r, N, nrhs, cidx, total, s0, s1, v);
 }
 
 // z[:, g] = sum over the subdomain slots holding point g, in a fixed order (the
@@ -2284,7 +2284,7 @@ void launch_scatter(const R* v, int nrhs, const int* inv_ptr, const int* inv_slo
                     hipStream_t s) {
     if (N == 0 || nrhs == 0) return;
     const long b = (N + kGT - 1) / kGT;
-    hipLaunchKernelGGL((k_scatter<R>), dim3((unsigned)b), dim3(256), 0, s, v, nrhs, inv_ptr, inv_slot, N, z);
+    CBD_LAUNCH((k_scatter<R>), dim3((unsigned)b), dim3(256), 0, s, v, nrhs, inv_ptr, inv_slot, N, z);
 }
 
 // One level of the apply sweep, one workgroup per (box, chunk of rc columns).
@@ -2383,7 +2383,7 @@ void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int*
     if (rc > nrhs) rc = nrhs;
     size_t shm = (size_t)2 * np_max * rc * sizeof(R);
     dim3 grid(nbox, (nrhs + rc - 1) / rc);
-    hipLaunchKernelGGL((k_apply_level<R>), grid, dim3(kThreads), shm, s, meta, sr, k, F, v, nrhs, rc,
+    CBD_LAUNCH((k_apply_level<R>), grid, dim3(kThreads), shm, s, meta, sr, k, F, v, nrhs, rc,
                        forward ? 1 : 0);
 }
 
@@ -2434,10 +2434,10 @@ void launch_root_apply(int nbox, int np_max, int unused, const BoxMeta* meta, co
     if (nbox == 0) return;
     const long ts = (long)np_max * nrhs;
     const int chunks = (np_max + 63) / 64;
-    hipLaunchKernelGGL((k_root_move<R>), dim3(nbox, 64), dim3(256), 0, s, meta, sr, v, nrhs, t1, ts, 1);
-    hipLaunchKernelGGL((k_root_trmm<R>), dim3(nbox, chunks), dim3(kThreads), 0, s, meta, F, nrhs, t1, t2, ts, 1);
-    hipLaunchKernelGGL((k_root_trmm<R>), dim3(nbox, chunks), dim3(kThreads), 0, s, meta, F, nrhs, t2, t1, ts, 0);
-    hipLaunchKernelGGL((k_root_move<R>), dim3(nbox, 64), dim3(256), 0, s, meta, sr, v, nrhs, t1, ts, 0);
+    CBD_LAUNCH((k_root_move<R>), dim3(nbox, 64), dim3(256), 0, s, meta, sr, v, nrhs, t1, ts, 1);
+    CBD_LAUNCH((k_root_trmm<R>), dim3(nbox, chunks), dim3(kThreads), 0, s, meta, F, nrhs, t1, t2, ts, 1);
+    CBD_LAUNCH((k_root_trmm<R>), dim3(nbox, chunks), dim3(kThreads), 0, s, meta, F, nrhs, t2, t1, ts, 0);
+    CBD_LAUNCH((k_root_move<R>), dim3(nbox, 64), dim3(256), 0, s, meta, sr, v, nrhs, t1, ts, 0);
 }
 
 // ---- the ID from the Gram matrix -------------------------------------------
@@ -2765,7 +2765,7 @@ void launch_gram(int nbox, int np_max, const BoxMeta* meta, const double* Y, con
                  hipStream_t s) {
     if (nbox == 0) return;
     const int nt = (np_max + kGramTile - 1) / kGramTile;
-    hipLaunchKernelGGL(k_gram, dim3(nt * (nt + 1) / 2, nbox), dim3(kThreads), 0, s, meta, Y, goff, G);
+    CBD_LAUNCH(k_gram, dim3(nt * (nt + 1) / 2, nbox), dim3(kThreads), 0, s, meta, Y, goff, G);
 }
 size_t pchol_panel_lds(int np_max) { return (size_t)np_max * (sizeof(double) + 2 * sizeof(int)); }
 
@@ -2776,17 +2776,17 @@ size_t pchol_panel_lds_limit() {
 void launch_pchol_panel(int nbox, int np_max, const BoxMeta* meta, const long* goff, double* G,
                         const GramState& st, int j0, double tol, double tie, hipStream_t s) {
     if (nbox == 0) return;
-    hipLaunchKernelGGL(k_pchol_panel, dim3(nbox), dim3(kPcholThreads), pchol_panel_lds(np_max), s, meta, goff, G,
+    CBD_LAUNCH(k_pchol_panel, dim3(nbox), dim3(kPcholThreads), pchol_panel_lds(np_max), s, meta, goff, G,
                        st, j0, tol, tie);
     const int nt = (np_max + kGramTile - 1) / kGramTile;
-    hipLaunchKernelGGL(k_pchol_update, dim3(nt * nt, nbox), dim3(kThreads), 0, s, meta, goff, G, st, j0);
+    CBD_LAUNCH(k_pchol_update, dim3(nt * nt, nbox), dim3(kThreads), 0, s, meta, goff, G, st, j0);
 }
 void launch_pchol_finish(int nbox, int np_max, const BoxMeta* meta, const long* goff, const double* G,
                          const GramState& st, double* Y, const int* act, int* sr, int* perm, int* k, double* T64,
                          hipStream_t s) {
     if (nbox == 0) return;
-    hipLaunchKernelGGL(k_pchol_finish, dim3(nbox), dim3(kThreads), 0, s, meta, goff, G, st, Y, act, sr, perm, k);
-    hipLaunchKernelGGL(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s,
+    CBD_LAUNCH(k_pchol_finish, dim3(nbox), dim3(kThreads), 0, s, meta, goff, G, st, Y, act, sr, perm, k);
+    CBD_LAUNCH(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s,
                        meta, Y, k, T64);
 }
 
