@@ -332,6 +332,9 @@ def main():
                     help="autotune the dense matvec, then run three products with the workload's right-hand "
                          "sides and three plain copies of as many doubles (the traffic counters' calibration); "
                          "for counter profiles of the matvec")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="factor the workload once (no predictor), then run ten preconditioner applies on its "
+                         "right-hand sides; for profiles of the apply")
     ap.add_argument("--cpu-rows", type=int, default=-1,
                     help="rows of the oracle's dense matvec timed for the CPU baseline (0: skip; "
                          "-1: about 12 s of host work, 16384 rows at 512^2 with 64 RHS)")
@@ -393,6 +396,22 @@ def main():
                                   "factorization's launch sequence between HIP events on its stream",
                           "factor_flops": st["flops"], "factor_gflops": st["flops"] / t_gpu / 1e9,
                           "schedule": fac.schedule()}))
+        return
+
+    if args.apply_only:
+        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, sketch_seed=sk_seed,
+                         id_method=idm, apply_rhs=nrhs)
+        z = fac.apply(F_rhs)
+        torch.cuda.synchronize()
+        cbd.timing.reset()
+        cbd.timing.enable(True)
+        for _ in range(10):
+            z = fac.apply(F_rhs)
+        torch.cuda.synchronize()
+        cbd.timing.enable(False)
+        ms, cnt = cbd.timing.get("apply")
+        print(json.dumps({"workload": W["label"], "apply_avg_ms": ms / max(cnt, 1), "factor_bytes": fac.stats()["bytes"],
+                          "nrhs": nrhs}))
         return
 
     if args.matvec_only:
