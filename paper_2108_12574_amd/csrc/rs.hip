@@ -2295,11 +2295,18 @@ __global__ __launch_bounds__(kThreads) void k_apply_level(const BoxMeta* __restr
                                                           const int* __restrict__ sr,
                                                           const int* __restrict__ kk,
                                                           const R* __restrict__ F, R* __restrict__ v,
-                                                          int nrhs, int rc, int forward) {
+                                                          int nbox, int nrhs, int rc, int forward) {
     extern __shared__ char smem_raw[];
-    const BoxMeta M = meta[blockIdx.x];
-    const int np = M.np, k = kk[blockIdx.x], nr = np - k;
-    const int c0 = blockIdx.y * rc;
+    // Workgroup ids go round-robin over the 8 XCDs, each with its own L2: the column
+    // groups of one box take ids 8 apart (same XCD, dispatched together), so all but
+    // the first read the box's factor from that L2.
+    const int ng = (nrhs + rc - 1) / rc;
+    const int xcd = (int)(blockIdx.x % 8), slot = (int)(blockIdx.x / 8);
+    const int b = (slot / ng) * 8 + xcd, grp = slot % ng;
+    if (b >= nbox) return;
+    const BoxMeta M = meta[b];
+    const int np = M.np, k = kk[b], nr = np - k;
+    const int c0 = grp * rc;
     const int nc = (nrhs - c0) < rc ? (nrhs - c0) : rc;
     const int tid = threadIdx.x;
     R* sv = reinterpret_cast<R*>(smem_raw);   // np x rc, rows s then r
@@ -2382,9 +2389,10 @@ void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int*
     // caller has checked that against apply_level_lds_limit)
     if (rc > nrhs) rc = nrhs;
     size_t shm = (size_t)2 * np_max * rc * sizeof(R);
-    dim3 grid(nbox, (nrhs + rc - 1) / rc);
-    CBD_LAUNCH((k_apply_level<R>), grid, dim3(kThreads), shm, s, meta, sr, k, F, v, nrhs, rc,
-                       forward ? 1 : 0);
+    const long ng = (nrhs + rc - 1) / rc;
+    const long blocks = (nbox + 7) / 8 * 8 * ng;
+    CBD_LAUNCH((k_apply_level<R>), dim3((unsigned)blocks), dim3(kThreads), shm, s, meta, sr, k, F, v, nbox, nrhs,
+               rc, forward ? 1 : 0);
 }
 
 // Root boxes too large for the LDS apply: v_root <- G^{-1} G^{-T} v_root as two
