@@ -2041,50 +2041,63 @@ __global__ __launch_bounds__(kThreads) void k_bchol_diag(const BoxMeta* __restri
                                                          R* __restrict__ F, int J, int* __restrict__ status) {
     __shared__ R sA[kBig][kBig + 1];
     __shared__ R sZ[kBig][kBig + 1];
-    __shared__ int s_fail;
+    __shared__ R sP[kWaves][kBig];
+    __shared__ R sInv[kBig];
+    static_assert(kWaves == 4, "the partial sums below are four");
     const int b = list[blockIdx.x];
     const ElimView<R> V = elim_view<R>(meta[b], kk[b], Wk, F);
     const int nr = V.nr;
     if (J >= nr) return;
-    const int jb = min(kBig, nr - J), tid = threadIdx.x;
+    const int jb = min(kBig, nr - J), tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int e = tid; e < jb * jb; e += kThreads) {
         const int a = e % jb, c = e / jb;
         sA[a][c] = V.Brr[(J + a) + (long)(J + c) * nr];
     }
-    if (tid == 0) s_fail = 0;
     __syncthreads();
+    // Right-looking Cholesky, one barrier per step: step j subtracts a_j a_j^T / d_j from
+    // the trailing upper triangle (row a = j + 1 + lane, columns of this wave's class
+    // mod 4), and scales row j - 1, which no step reads again; the diagonal keeps d_j
+    // until the end.
     for (int j = 0; j < jb; ++j) {
-        if (tid == 0) {
-            const R d = sA[j][j];
-            if (!(d > (R)0)) s_fail = 1;
-            else sA[j][j] = sqrt(d);
+        const R d = sA[j][j];
+        if (!(d > (R)0)) {
+            if (tid == 0) status[0] = b + 1;
+            return;
         }
-        __syncthreads();
-        if (s_fail) break;
-        for (int c = j + 1 + tid; c < jb; c += kThreads) sA[j][c] /= sA[j][j];
-        __syncthreads();
-        const int rem = jb - j - 1;
-        for (int e = tid; e < rem * rem; e += kThreads) {
-            const int a = j + 1 + e % rem, c = j + 1 + e / rem;
-            if (a <= c) sA[a][c] -= sA[j][a] * sA[j][c];
+        if (j > 0) {
+            const R rp = sqrt(sA[j - 1][j - 1]);
+            for (int c = j + tid; c < jb; c += kThreads) sA[j - 1][c] /= rp;
+        }
+        const int a = j + 1 + lane;
+        if (a < jb) {
+            const R ga = sA[j][a] / d;
+            int c = j + 1 + w;
+            if (c < a) c += (a - c + kWaves - 1) / kWaves * kWaves;
+            for (; c < jb; c += kWaves) sA[a][c] -= ga * sA[j][c];
         }
         __syncthreads();
     }
-    if (s_fail) {
-        if (tid == 0) status[0] = b + 1;
-        return;
-    }
-    // Z = G_JJ^{-1}, column c by back substitution
-    for (int c = tid; c < jb; c += kThreads) {
-        for (int a = jb - 1; a > c; --a) sZ[a][c] = (R)0;
-        sZ[c][c] = (R)1 / sA[c][c];
-        for (int a = c - 1; a >= 0; --a) {
-            R s = 0;
-            for (int q = a + 1; q <= c; ++q) s += sA[a][q] * sZ[q][c];
-            sZ[a][c] = -s / sA[a][a];
-        }
+    if (tid < jb) sA[tid][tid] = sqrt(sA[tid][tid]);
+    __syncthreads();
+    // Z = G_JJ^{-1} (upper triangular) by rows from the bottom: row a from the rows
+    // below it, each entry's sum split over the four waves
+    if (tid < jb) sInv[tid] = (R)1 / sA[tid][tid];
+    for (int e = tid; e < jb * jb; e += kThreads) {
+        const int a = e % jb, c = e / jb;
+        if (a > c) sZ[a][c] = (R)0;
     }
     __syncthreads();
+    for (int a = jb - 1; a >= 0; --a) {
+        const int c = lane;
+        R part = 0;
+        if (c > a && c < jb)
+            for (int q = a + 1 + w; q <= c; q += kWaves) part += sA[a][q] * sZ[q][c];
+        sP[w][lane] = part;
+        __syncthreads();
+        if (w == 0 && c >= a && c < jb)
+            sZ[a][c] = c == a ? sInv[a] : -sInv[a] * ((sP[0][c] + sP[1][c]) + (sP[2][c] + sP[3][c]));
+        __syncthreads();
+    }
     for (int e = tid; e < jb * jb; e += kThreads) {
         const int a = e % jb, c = e / jb;
         if (a <= c) V.Brr[(J + a) + (long)(J + c) * nr] = sA[a][c];
