@@ -1541,7 +1541,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
         std::vector<int> small, big;
         int np_big = 0;
         for (int B = b0; B < b1; ++B) {
-            if (L.meta[B].np >= kBigBox) {
+            if (L.meta[B].np >= kBigElim) {
                 big.push_back(B - b0);
                 np_big = std::max(np_big, L.meta[B].np);
             } else {

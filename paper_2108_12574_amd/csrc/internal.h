@@ -220,7 +220,9 @@ void launch_big_cholesky_inverse(int nbig, int nr_max, const BoxMeta* meta, cons
 template <typename R>
 void launch_root_apply(int nbox, int np_max, int unused, const BoxMeta* meta, const int* sr, const int* k,
                        const R* F, R* v, int nrhs, R* t1, R* t2, hipStream_t s);
-constexpr int kBigBox = 512;        // boxes with at least this many DOFs use the multi-workgroup path
+constexpr int kBigBox = 512;        // roots with at least this many DOFs are applied by GEMMs
+constexpr int kBigElim = 256;       // boxes with at least this many DOFs are eliminated by the
+                                    // multi-workgroup path (512^2 factor 23 -> 21.5 ms against 512)
 constexpr int kScratchCols = 64;    // elimination scratch per box: np^2 + kScratchCols * np
 
 // v[slot * nrhs + c] = r[c * N + cidx[slot]] for slots in [s0, s1), zero elsewhere

@@ -1912,7 +1912,7 @@ __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restric
     }
 }
 
-// Large boxes (np >= kBigBox): the gathers and Schur products of the elimination as
+// Large boxes (np >= kBigElim): the gathers and Schur products of the elimination as
 // multi-workgroup launches.  Every workgroup takes kWaves 16 x 16 output tiles of
 // one box's product, with the per-tile arithmetic of the one-workgroup path.
 template <typename R>
