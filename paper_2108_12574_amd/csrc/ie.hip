@@ -217,18 +217,20 @@ __global__ __launch_bounds__(kMvThreads) void k_matvec(ProblemView P, int nrhs,
 // The same product on the 2D uniform grid, with the entries taken from a table.
 // Grid points are g = j1 + n j2 and x_i - x_j = spacing (j(i) - j(j)), so an entry
 // depends only on the offset (Delta1, Delta2) (the translation invariance the FFT form
-// uses as well).  A workgroup's rows are R = 64 kRB consecutive points of one grid
-// line, and a source tile is 64 consecutive points of one line (n a multiple of R);
-// the pair then meets only R + 63 offsets: Delta2 fixed and Delta1 = (i1_0 - j1_0) +
-// delta - 63 for delta = row offset - source offset + 63.  Each tile's R + 63 kernel
-// values are evaluated once into LDS (the pair i = j gets 0: the diagonal is added at
-// the end), and a lane's A operand is one LDS read at delta.  Products, summation
-// order and epilogue are those of k_matvec.
-template <int kRows>
+// uses as well).  A workgroup's rows are R = 16 kW kRB consecutive points of one grid
+// line, and a source tile is T consecutive points of one line (T = 64 with 4 waves,
+// 128 with 8; n a multiple of R and T); the pair then meets only R + T - 1 offsets:
+// Delta2 fixed and Delta1 = (i1_0 - j1_0) + delta - (T - 1) for delta = row offset -
+// source offset + T - 1.  Each tile's R + T - 1 kernel values are evaluated once into
+// LDS (the pair i = j gets 0: the diagonal is added at the end), and a lane's A
+// operand is one LDS read at delta.  Products, summation order and epilogue are those
+// of k_matvec.
+template <int kRows, int kT>
 struct MvGridShared {
-    double swx[64 * kLdw];
-    double ktab[kRows + 64];
+    double swx[64 * (kT + 2)];
+    double ktab[kRows + kT];
 };
+constexpr int grid_tile(int waves) { return waves == 8 ? 128 : kTJ; }
 
 template <int NB, int kRB, int kW>
 __global__ __launch_bounds__(64 * kW) void k_matvec_grid2(ProblemView P, int nrhs,
@@ -236,8 +238,10 @@ __global__ __launch_bounds__(64 * kW) void k_matvec_grid2(ProblemView P, int nrh
                                                           double* __restrict__ y) {
     constexpr int kThr = 64 * kW;             // kW waves per workgroup
     constexpr int kR = kW * kRB * 16;         // rows per workgroup
-    constexpr int kSRw = kThr / kTJ;          // staging threads per source
-    __shared__ MvGridShared<kR> sh;
+    constexpr int kT = grid_tile(kW);         // sources per tile
+    constexpr int kLd = kT + 2;               // LDS row stride of the [rhs][j] tile
+    constexpr int kSRw = kThr / kT;           // staging threads per source
+    __shared__ MvGridShared<kR, kT> shb[2];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const long N = P.N;
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(64 * kW) void k_matvec_grid2(ProblemView P, int nrh
     const long i2 = iw / n, i1_0 = iw % n;
     const double sp2 = P.spacing * P.spacing;
     // per-lane table position of row li, source lk at K-step 0 and row block 0
-    const int d0 = wave * (kRB * 16) + li - lk + 63;
+    const int d0 = wave * (kRB * 16) + li - lk + (kT - 1);
 
     v4d acc[kRB][NB];
 #pragma unroll
@@ -257,13 +261,14 @@ __global__ __launch_bounds__(64 * kW) void k_matvec_grid2(ProblemView P, int nrh
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    // The next tile's inputs are fetched into registers during the current tile's
-    // products (its x and w values, and its offsets' kernel values), so the staging
-    // between the barriers is LDS writes only.
-    const int sj = tid % kTJ, sr = tid / kTJ;
+    // Software pipeline over source tiles, two LDS buffers: during tile t's products
+    // the next tile's staging (x, w and the offsets' kernel values, fetched into
+    // registers one tile earlier) is written to the other buffer, and the tile after
+    // that is fetched; one barrier per tile.
+    const int sj = tid % kT, sr = tid / kT;
     constexpr int kQ = NB * 16 / kSRw;
     static_assert(kQ * kSRw == NB * 16, "staging layout");
-    constexpr int kKT = (kR + 63 + kThr - 1) / kThr;   // table entries per thread
+    constexpr int kKT = (kR + kT - 1 + kThr - 1) / kThr;   // table entries per thread
     double v[kQ], wj, kt[kKT];
     auto fetch = [&](long j0) {
         const long j = j0 + sj;
@@ -274,32 +279,38 @@ __global__ __launch_bounds__(64 * kW) void k_matvec_grid2(ProblemView P, int nrh
             v[q] = x[(long)rr * N + j];
         }
         const long d2 = i2 - j0 / n;
-        const long d1base = i1_0 - (j0 % n) - 63;
+        const long d1base = i1_0 - (j0 % n) - (kT - 1);
 #pragma unroll
         for (int u = 0; u < kKT; ++u) {
             const int e = tid + u * kThr;
             const long d1 = d1base + e;
             const long q = d1 * d1 + d2 * d2;
-            kt[u] = (e >= kR + 63 || q == 0) ? 0.0 : laplace_from_r2<2>((double)q * sp2);
+            kt[u] = (e >= kR + kT - 1 || q == 0) ? 0.0 : laplace_from_r2<2>((double)q * sp2);
         }
     };
-    fetch(0);
-    for (long j0 = 0; j0 < N; j0 += kTJ) {
-        __syncthreads();
+    auto stage = [&](MvGridShared<kR, kT>& sh) {
 #pragma unroll
         for (int u = 0; u < kKT; ++u) {
             const int e = tid + u * kThr;
-            if (e < kR + 63) sh.ktab[e] = kt[u];
+            if (e < kR + kT - 1) sh.ktab[e] = kt[u];
         }
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
             const int r = sr + kSRw * q;
-            sh.swx[r * kLdw + sj] = (r0 + r < nrhs) ? wj * v[q] : 0.0;
+            sh.swx[r * kLd + sj] = (r0 + r < nrhs) ? wj * v[q] : 0.0;
         }
-        __syncthreads();
-        if (j0 + kTJ < N) fetch(j0 + kTJ);
+    };
+    fetch(0);
+    stage(shb[0]);
+    if (kT < N) fetch(kT);
+    __syncthreads();
+    int cur = 0;
+    for (long j0 = 0; j0 < N; j0 += kT) {
+        if (j0 + kT < N) stage(shb[cur ^ 1]);
+        if (j0 + 2 * kT < N) fetch(j0 + 2 * kT);
+        const MvGridShared<kR, kT>& sh = shb[cur];
 #pragma unroll 1
-        for (int ks = 0; ks < kTJ / 4; ++ks) {
+        for (int ks = 0; ks < kT / 4; ++ks) {
             const int jj = ks * 4 + lk;
             const double* ta = sh.ktab + (d0 - ks * 4);
             double a[kRB];
@@ -307,13 +318,15 @@ __global__ __launch_bounds__(64 * kW) void k_matvec_grid2(ProblemView P, int nrh
             for (int rb = 0; rb < kRB; ++rb) a[rb] = ta[rb * 16];
             double b[NB];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) b[nb] = sh.swx[(nb * 16 + li) * kLdw + jj];
+            for (int nb = 0; nb < NB; ++nb) b[nb] = sh.swx[(nb * 16 + li) * kLd + jj];
 #pragma unroll
             for (int rb = 0; rb < kRB; ++rb)
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     acc[rb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[nb], acc[rb][nb], 0, 0, 0);
         }
+        __syncthreads();
+        cur ^= 1;
     }
 #pragma unroll
     for (int rb = 0; rb < kRB; ++rb) {
@@ -442,7 +455,7 @@ static int shape_waves(int rb) { return rb >= 8 ? 8 : kMvWaves; }
 
 // The table form needs whole grid lines per workgroup and per source tile.
 static bool matvec_grid_form(const ProblemView& P, int rb) {
-    return P.d == 2 && P.n % matvec_rows_per_block(rb) == 0 && P.n % kTJ == 0;
+    return P.d == 2 && P.n % matvec_rows_per_block(rb) == 0 && P.n % grid_tile(shape_waves(rb)) == 0;
 }
 
 template <int D, int NB, int RB>
