@@ -2784,7 +2784,7 @@ __global__ __launch_bounds__(kThreads) void k_pchol_finish(const BoxMeta* __rest
 
 void launch_gram(int nbox, int np_max, const BoxMeta* meta, const double* Y, const long* goff, double* G,
                  hipStream_t s) {
-    if (nbox == 0) return;
+    if (nbox == 0 || np_max == 0) return;
     const int nt = (np_max + kGramTile - 1) / kGramTile;
     CBD_LAUNCH(k_gram, dim3(nt * (nt + 1) / 2, nbox), dim3(kThreads), 0, s, meta, Y, goff, G);
 }
@@ -2800,15 +2800,16 @@ void launch_pchol_panel(int nbox, int np_max, const BoxMeta* meta, const long* g
     CBD_LAUNCH(k_pchol_panel, dim3(nbox), dim3(kPcholThreads), pchol_panel_lds(np_max), s, meta, goff, G,
                        st, j0, tol, tie);
     const int nt = (np_max + kGramTile - 1) / kGramTile;
-    CBD_LAUNCH(k_pchol_update, dim3(nt * nt, nbox), dim3(kThreads), 0, s, meta, goff, G, st, j0);
+    if (nt > 0) CBD_LAUNCH(k_pchol_update, dim3(nt * nt, nbox), dim3(kThreads), 0, s, meta, goff, G, st, j0);
 }
 void launch_pchol_finish(int nbox, int np_max, const BoxMeta* meta, const long* goff, const double* G,
                          const GramState& st, double* Y, const int* act, int* sr, int* perm, int* k, double* T64,
                          hipStream_t s) {
     if (nbox == 0) return;
     CBD_LAUNCH(k_pchol_finish, dim3(nbox), dim3(kThreads), 0, s, meta, goff, G, st, Y, act, sr, perm, k);
-    CBD_LAUNCH(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s,
-                       meta, Y, k, T64);
+    if (np_max > 0)
+        CBD_LAUNCH(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s, meta, Y, k,
+                   T64);
 }
 
 // explicit instantiations
