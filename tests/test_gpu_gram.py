@@ -127,3 +127,46 @@ def test_gram_needs_a_tolerance_above_its_rounding_floor():
     with pytest.raises(cbd.CbdError) as e:
         cbd.Factor(P, part, tol=1e-8, n_pxy=64, id_method=cbd.ID_GRAM)
     assert e.value.code == -1
+
+
+def test_gram_route_with_sketches_chunks_and_hints():
+    # the Gram route composes with the other factorization options: random-sign sketches
+    # (the ID of Z = Omega Y), levels split into chunks by a small workspace, and rank
+    # hints; the chunked and hinted factors equal the plain one
+    P = cbd.Problem(3, 16, device=DEV)
+    O = ie.Problem(3, 16)
+    part = cbd.Partition(P, 4, 1, cbd.MODE_CBD, 0)
+    opart = dd.Partition(3, 16, 4, 1, dd.CBD)
+    kw = dict(tol=1e-3, n_pxy=256, sketch_seed=1, id_method=cbd.ID_GRAM)
+    F = cbd.Factor(P, part, **kw)
+    sc = F.schedule()
+    assert sc["sketched"] > 0
+    # a sketched ID meets the tolerance on Z = Omega Y; on Y its residual is held to the
+    # bound the oracle's sketched pins use (30 tol nu_0), beside the QR route's
+    w, nb = _id_bound(F, O, opart, 1e-3, 256)
+    wq, _ = _id_bound(cbd.Factor(P, part, tol=1e-3, n_pxy=256, sketch_seed=1, id_method=cbd.ID_QR), O, opart,
+                      1e-3, 256)
+    print("sketched IDs: residual / (tol nu0) Gram %.3f, QR %.3f over %d boxes, %d sketched"
+          % (w, wq, nb, sc["sketched"]), flush=True)
+    assert w <= 30.0
+    Fc = cbd.Factor(P, part, workspace_bytes=16 << 20, **kw)
+    Fh = cbd.Factor(P, part, rank_hint=F.ranks.cpu(), **kw)
+    assert Fc.schedule()["chunks"] > sc["chunks"]
+    r = torch.tensor(synth.rhs(P.N, 2, seed=7), device=DEV)
+    z = F.apply(r)
+    for G in (Fc, Fh):
+        assert torch.equal(G.ranks, F.ranks)
+        assert (G.apply(r) - z).norm() <= 1e-12 * z.norm()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_gram_route_pcg_against_dense_solve(prec):
+    P = cbd.Problem(2, 64, device=DEV)
+    O = ie.Problem(2, 64)
+    part = cbd.Partition(P, 8, 1, cbd.MODE_CBD, 0)
+    F = cbd.Factor(P, part, tol=1e-6, n_pxy=64, precision=prec, id_method=cbd.ID_GRAM)
+    f = synth.rhs(O.N, 1, seed=8)[0]
+    u, it, rr = cbd.pcg_solve(P, F, torch.tensor(f, device=DEV), tol=1e-10, maxit=200)
+    ud = np.linalg.solve(O.dense(), f)
+    print("Gram route %s: %d iterations, u vs dense %.2e" % (("fp64", "fp32")[prec], it, rel(u.cpu().numpy(), ud)))
+    assert rr <= 1e-10 and rel(u.cpu().numpy(), ud) <= 1e-8
