@@ -2693,7 +2693,9 @@ __global__ __launch_bounds__(kThreads) void k_pchol_update(const BoxMeta* __rest
     __shared__ int fI[kGramTile], fJ[kGramTile];
     const int b = blockIdx.y;
     const int kt = st.jend[b] - j0;
-    if (kt <= 0) return;
+    // a box that stopped in this panel needs no trailing update: only its chosen columns
+    // (L) are read again
+    if (kt <= 0 || st.done[b]) return;
     const BoxMeta M = meta[b];
     const int np = M.np, nt = (np + kGramTile - 1) / kGramTile;
     if ((int)blockIdx.x >= nt * nt) return;
