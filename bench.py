@@ -452,7 +452,7 @@ def main():
     torch.cuda.empty_cache()
     ws_factor = torch.empty(int(used0 * 1.05) + (1 << 20), dtype=torch.uint8, device=dev)
     ws_pcg = cbd.pcg_workspace(P, nrhs)
-    box = {"fac": None, "graph": False}
+    box = {"fac": None, "graph": False, "replay": False}
     side = torch.cuda.Stream(device=dev)    # PCG with captured HIP graphs needs a non-default stream
 
     def solve(fac, graph):
@@ -464,18 +464,28 @@ def main():
         torch.cuda.current_stream(dev).wait_stream(side)
         return out
 
-    def step():
-        box["fac"] = None           # the previous factor views ws_factor: release it first
+    def factor_step():
         t0 = time.perf_counter()
-        fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=sk_seed,
-                         apply_rhs=nrhs, ws=ws_factor, id_method=idm)
+        # graph mode: the factorization of the previous step replayed from its captured graph
+        # (every kernel runs again on the data; the host side is checked against the recording)
+        if box["replay"] and box["fac"] is not None and box["fac"].captured and box["fac"].replay():
+            fac = box["fac"]
+        else:
+            box["fac"] = None           # the previous factor views ws_factor: release it first
+            fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp,
+                             sketch_seed=sk_seed, apply_rhs=nrhs, ws=ws_factor, id_method=idm, record=box["replay"])
+            if box["replay"]:
+                fac.capture()
         torch.cuda.synchronize()
+        box["fac"] = fac
+        return fac, time.perf_counter() - t0
+
+    def step():
+        fac, t_fac = factor_step()
         t1 = time.perf_counter()
         u, its, rr = solve(fac, box["graph"])
         torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        box["fac"] = fac
-        return fac, u, its, rr, t1 - t0, t2 - t1
+        return fac, u, its, rr, t_fac, time.perf_counter() - t1
 
     # eager or graph-replayed PCG iterations: the faster one, measured once, runs the timed steps
     pcg_modes = {}
@@ -485,6 +495,18 @@ def main():
     box["graph"] = pcg_modes["graph"] < pcg_modes["eager"]
     log("pcg eager %.3f s, graph %.3f s: timed steps use %s" % (pcg_modes["eager"], pcg_modes["graph"],
                                                                  "graphs" if box["graph"] else "eager launches"))
+    # the factorization launched eagerly (host planning, a synchronization per rank read)
+    # or replayed from a graph captured after an eager run: the faster one runs the timed steps
+    # (factorizations of a second or more are left eager: launch overhead is no part of them)
+    fac_modes = {"eager": min(factor_step()[1] for _ in range(2)), "graph": None}
+    if fac_modes["eager"] < 1.0:
+        box["replay"] = True
+        factor_step()                   # eager, recorded, captured
+        fac_modes["graph"] = min(factor_step()[1] for _ in range(2))
+        box["replay"] = fac_modes["graph"] < fac_modes["eager"]
+    log("factor eager %.4f s, graph replay %s s: timed steps use %s"
+        % (fac_modes["eager"], "%.4f" % fac_modes["graph"] if fac_modes["graph"] else "-",
+           "replays" if box["replay"] else "eager launches"))
     for w in range(args.warmup):
         step()
         log("warmup step %d done" % w)
@@ -761,7 +783,14 @@ def main():
         "S_last_level": st["S"],
         "factor_bytes": st["bytes"],
         "factor_launches": sched["launches"],
-        "factor_host_syncs": sched["host_syncs"],
+        "factor_host_syncs": 1 if box["replay"] else sched["host_syncs"],
+        "factor_launch_mode": {"timed": "graph" if box["replay"] else "eager", "eager_s": fac_modes["eager"],
+                               "graph_s": fac_modes["graph"], "eager_host_syncs": sched["host_syncs"],
+                               "note": "graph: the factorization captured after an eager run (rs_factor_capture) "
+                                       "and replayed every step (rs_factor_replay): every kernel runs again on the "
+                                       "data, each value the eager run read back is checked on the device, one "
+                                       "synchronization; eager: host planning between levels and a "
+                                       "synchronization per read"},
         "n_it": [min(n_it), max(n_it)],
         "max_relres": max(rr_all),
         "pcg_launch_mode": {"timed": "graph" if box["graph"] else "eager", "eager_s": pcg_modes["eager"],
@@ -780,7 +809,7 @@ def main():
                                         "the paper) instead of the dense on-the-fly matvec"} if full else None,
         "rank_predictor": {"train_s": mlp_train_s, "mean_abs_rank_err": sched["mean_abs_err"],
                            "held_out": mlp_held, "sketch_3d": mlp_gain_3d,
-                           "factor_s_with": factor_s, "factor_s_without": factor_nm_s,
+                           "factor_s_with": fac_modes["eager"], "factor_s_without": factor_nm_s,
                            "host_syncs_with": sched["host_syncs"], "host_syncs_without": sched_nm["host_syncs"],
                            "mispredicted_boxes": sched["mispredicted"]},
         "fp64_form": {"factor_s": f64_factor, "pcg_s_est": f64_pcg, "cols_timed": ncols,

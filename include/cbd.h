@@ -41,6 +41,8 @@ extern "C" {
 #define CBD_ENOMEM (-4)      /* a host allocation failed */
 #define CBD_EWORKSPACE (-5)  /* the caller's workspace is too small (the message and, where the
                                 call has one, an out-parameter give the bytes needed) */
+#define CBD_EREPLAN (-6)     /* a replayed factorization read something other than its recording
+                                (rs_factor_replay): factor again with rs_factor_batched */
 #define CBD_WNOTCONV 1       /* PCG stopped at maxit before reaching tol */
 
 #define CBD_GRID_CELL 0      /* x_t = (j_t + 1/2)/n (Section 2.1) */
@@ -115,6 +117,10 @@ typedef struct {
                             stays within the tolerance) and is refused for smaller tol.  Boxes
                             with more active DOFs than the pivot kernel's LDS holds (16 bytes
                             each: about 10000 on gfx950) use the QR in both modes */
+    int record;          /* 1: keep what the factorization uploads to and reads from the
+                            device, in order, so that rs_factor_capture can turn it into a
+                            graph (host memory of the order of the factor's index lists);
+                            0: nothing kept */
 } cbd_rs_opts;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -280,6 +286,36 @@ int rs_factor_features(cbd_factor f, int level, int* n_boxes, float* X, int* k);
 int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispredicted,
                        double* mean_abs_err, int* row_compressed, int* sketched, int* sketch_fallbacks,
                        int* chunks, int* sketched_pred, int* sketch_pred_rejected, long* launches);
+
+/* Graph replay of a factorization (the factorization of Section 4.2, re-run whole).
+ * An eager rs_factor_batched with opts.record = 1 leaves a recording of its host side:
+ * every upload (box lists, near fields, metadata) and every read (ranks, skeleton
+ * lists, stop flags of the pivoted QR or Cholesky, rank predictions, breakdown slots).
+ * rs_factor_capture re-plays that host side without running anything and captures the
+ * same kernel sequence, on the same workspace addresses, into one executable graph:
+ * uploads become copies from gws, and each read becomes a check of the device value
+ * against the recorded one.  rs_factor_replay launches the graph on `stream`, so every
+ * kernel of the factorization runs again on the problem's current device data (pts,
+ * diag, w, rowscale), and synchronizes once to read the checks.  When every read
+ * matches, every decision of the host is the one an eager factorization of that data
+ * would take, so the factor is that factorization's (CBD_OK; the factor's host-side
+ * statistics are unchanged).  Otherwise it returns CBD_EREPLAN and the factor is
+ * marked stale (rs_apply refuses it) until it is freed: factor again with
+ * rs_factor_batched.  With every read matching, a breakdown returns CBD_ENOTSPD (the
+ * factor also stale); after a read that differs, CBD_EREPLAN is returned whatever
+ * followed.
+ *  rs_factor_graph_bytes: bytes of gws for a factor made with opts.record = 1 (0
+ *    otherwise).
+ *  rs_factor_capture: gws device, 256-byte aligned, caller-owned, at least
+ *    rs_factor_graph_bytes; it must outlive the factor and stay untouched.  The
+ *    factor's workspace, the problem's arrays and opts.mlp must stay where they are.
+ *    Does not write ranks_out.  Synchronizes `stream` once (the upload of gws); the
+ *    capture itself runs on a stream of its own.  Capturing again replaces the graph.
+ *  rs_factor_replay: calls on one factor, and any other use of its workspace
+ *    (rs_apply), must not overlap in time. */
+size_t rs_factor_graph_bytes(cbd_factor f);
+int rs_factor_capture(cbd_factor f, void* gws, size_t gws_bytes, void* stream);
+int rs_factor_replay(cbd_factor f, void* stream);
 
 /* rs_apply - z = T^{-1} r = sum_i R_i^T A_i^{-1} R_i r, (e:ad), with every A_i^{-1}
  * applied through its RS factor: gather, forward sweep over levels, root solve,

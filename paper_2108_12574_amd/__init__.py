@@ -167,14 +167,15 @@ class Factor:
 
     def __init__(self, problem, partition, tol=1e-6, n_pxy=64, proxy_ratio=1.5,
                  precision=PREC_FP64, exact=False, mlp=None, row_compression=ROWS_AUTO, sketch_seed=None,
-                 workspace_bytes=0, apply_rhs=64, rank_hint=None, ws=None, id_method=ID_QR):
+                 workspace_bytes=0, apply_rhs=64, rank_hint=None, ws=None, id_method=ID_QR, record=False):
         self.problem, self.partition = problem, partition
         self.precision = precision
         opts = _lib.RSOpts(tol, n_pxy, proxy_ratio, precision, 1 if exact else 0,
                            mlp.params.data_ptr() if mlp is not None else None, row_compression,
                            0 if sketch_seed is None else 1, 0 if sketch_seed is None else int(sketch_seed),
-                           int(workspace_bytes), int(apply_rhs), int(id_method))
+                           int(workspace_bytes), int(apply_rhs), int(id_method), 1 if record else 0)
         self.opts = opts
+        self._mlp = mlp   # its parameters must outlive a captured graph
         cnt = ctypes.c_int()
         check(lib().rs_factor_rank_count(partition.handle, ctypes.byref(opts), ctypes.byref(cnt)))
         self.n_ranks = cnt.value
@@ -209,6 +210,31 @@ class Factor:
         self.handle = h
         self.ws = ws
         self.ws_used = used.value
+
+    def capture(self):
+        """Capture the factorization as a graph (rs_factor_capture; needs record=True).
+        The graph workspace is a uint8 tensor this object keeps."""
+        nb = lib().rs_factor_graph_bytes(self.handle)
+        if nb == 0:
+            raise ValueError("capture needs a Factor made with record=True")
+        gws = torch.empty(nb, dtype=torch.uint8, device=self.problem.device)
+        check(lib().rs_factor_capture(self.handle, _ptr(gws), nb, _stream(self.problem.device)))
+        self._gws = gws
+
+    @property
+    def captured(self):
+        """True once capture() has made a graph of this factorization."""
+        return getattr(self, "_gws", None) is not None
+
+    def replay(self):
+        """Run the factorization again by replaying its graph (rs_factor_replay).  True
+        when it reproduced the recording (the factor is valid for the problem's current
+        data); False when it did not (the factor is stale: make a new Factor)."""
+        rc = lib().rs_factor_replay(self.handle, _stream(self.problem.device))
+        if rc == _lib.EREPLAN:
+            return False
+        check(rc)
+        return True
 
     def apply(self, r):
         """z = T^{-1} r for r of shape (N,) or (nrhs, N)."""

@@ -14,7 +14,7 @@ MODE_JACOBI, MODE_SCHWARZ, MODE_CBD = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_BF16GEMM = 0, 1, 2
 ROWS_AUTO, ROWS_NEVER, ROWS_ALWAYS = 0, 1, 2
 ID_QR, ID_GRAM = 0, 1
-OK, EARG, EHIP, ENOTSPD, ENOMEM, EWORKSPACE, WNOTCONV = 0, -1, -2, -3, -4, -5, 1
+OK, EARG, EHIP, ENOTSPD, ENOMEM, EWORKSPACE, EREPLAN, WNOTCONV = 0, -1, -2, -3, -4, -5, -6, 1
 
 
 class RSOpts(ctypes.Structure):
@@ -22,7 +22,8 @@ class RSOpts(ctypes.Structure):
                 ("proxy_ratio", ctypes.c_double), ("precision", ctypes.c_int),
                 ("exact", ctypes.c_int), ("mlp", ctypes.c_void_p), ("row_compression", ctypes.c_int),
                 ("id_sketch", ctypes.c_int), ("sketch_seed", ctypes.c_ulonglong),
-                ("workspace_bytes", ctypes.c_size_t), ("apply_rhs", ctypes.c_int), ("id_method", ctypes.c_int)]
+                ("workspace_bytes", ctypes.c_size_t), ("apply_rhs", ctypes.c_int), ("id_method", ctypes.c_int),
+                ("record", ctypes.c_int)]
 
 
 # (name, restype, argtypes) of every exported symbol of include/cbd.h
@@ -43,6 +44,9 @@ SIGNATURES = [
     ("rs_factor_batched", _i, [_vp, _vp, ctypes.POINTER(RSOpts), _vp, _vp, _sz, _vp, ctypes.POINTER(_sz), _vp,
                                ctypes.POINTER(_vp)]),
     ("rs_factor_free", _i, [_vp]),
+    ("rs_factor_graph_bytes", _sz, [_vp]),
+    ("rs_factor_capture", _i, [_vp, _vp, _sz, _vp]),
+    ("rs_factor_replay", _i, [_vp, _vp]),
     ("rs_factor_stats", _i, [_vp, _ip, _ip, ctypes.POINTER(_sz), _dp]),
     ("rs_factor_level", _i, [_vp, _i, _ip, _ip, _ip, _ip]),
     ("rs_factor_box", _i, [_vp, _i, _i, _i, _ip, _ip, _ip, _ip, _dp, _dp, _dp, _dp]),

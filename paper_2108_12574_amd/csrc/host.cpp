@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -665,6 +666,24 @@ struct ScratchBuf {
     }
 };
 
+// The host side of an eager factorization, kept for rs_factor_capture: the options and
+// rank hints it ran with, and every upload and read in order (payloads at 16-byte
+// aligned offsets).
+struct FactorTape {
+    cbd_rs_opts opts{};
+    bool has_hint = false;
+    std::vector<int> hint;
+    std::vector<char> up, rd;
+    std::vector<size_t> up_off, up_len, rd_off, rd_len;
+    static void add(std::vector<char>& v, std::vector<size_t>& off, std::vector<size_t>& len, const void* p,
+                    size_t b) {
+        off.push_back(v.size());
+        len.push_back(b);
+        v.resize(v.size() + ((b + 15) & ~(size_t)15));
+        if (b) std::memcpy(v.data() + off.back(), p, b);
+    }
+};
+
 struct Level {
     bool root = false;
     int nbox = 0;
@@ -714,9 +733,79 @@ struct cbd_factor_s {
     void *v = nullptr, *t1 = nullptr, *t2 = nullptr;   // apply: local vectors, large-root buffers
     std::vector<int> stage;      // host source of an upload in flight
     std::vector<int> ranks;      // host source of the ranks_out upload
+    int* d_stat = nullptr;       // breakdown slots, one per level
+    // graph replay (rs_factor_capture / rs_factor_replay)
+    std::unique_ptr<FactorTape> tape;
+    hipGraphExec_t graph = nullptr;
+    char* gws = nullptr;         // flag word, then the device copies of the tape's payloads
+    long graph_launches = 0;     // kernels in the graph
+    int stale = 0;               // a replay did not reproduce the recording
+    ~cbd_factor_s() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+    }
 };
 
 namespace {
+
+// Every upload to and read from the device of a factorization goes through here.
+// EAGER runs them; RECORD runs them and appends them to the tape; CAPTURE (inside a
+// stream capture) runs nothing on the host side of the device: an upload becomes a copy
+// from the device copy of the recorded payload (after checking that the host plan
+// produced the same bytes), and a read returns the recorded bytes and enqueues a check
+// of the device value against them.
+struct FactorIo {
+    enum Mode { EAGER, RECORD, CAPTURE } mode = EAGER;
+    FactorTape* tape = nullptr;
+    const char* d_up = nullptr;   // CAPTURE: device copies of tape->up and tape->rd
+    const char* d_rd = nullptr;
+    int* flag = nullptr;          // CAPTURE: set where a read differs
+    size_t ui = 0, ri = 0;        // CAPTURE: next upload / read of the tape
+    int* syncs = nullptr;         // counter of stream synchronizations
+    int plan_differs() const {
+        return fail(CBD_EREPLAN, "rs_factor_capture: the host plan differs from the recorded one");
+    }
+    int up(void* dst, const void* src, size_t b, hipStream_t s) {
+        if (!b) return CBD_OK;
+        if (mode == CAPTURE) {
+            if (ui >= tape->up_len.size() || tape->up_len[ui] != b ||
+                std::memcmp(tape->up.data() + tape->up_off[ui], src, b) != 0)
+                return plan_differs();
+            if (b % 4 != 0 || (uintptr_t)dst % 4 != 0) return fail(CBD_EARG, "rs_factor_capture: unaligned upload");
+            launch_copy_words(dst, d_up + tape->up_off[ui], b, s);
+            ++ui;
+            return CBD_OK;
+        }
+        if (mode == RECORD) FactorTape::add(tape->up, tape->up_off, tape->up_len, src, b);
+        HIPCHK(hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, s));
+        return CBD_OK;
+    }
+    // device src -> host dst, then the host waits for it (and for all work before it).
+    // check = false: a read of breakdown slots, which a replay reports by itself
+    int rd(void* dst, const void* src, size_t b, hipStream_t s, bool check = true) {
+        if (mode == CAPTURE) {
+            if (ri >= tape->rd_len.size() || tape->rd_len[ri] != b) return plan_differs();
+            if (b % 4 != 0 || (uintptr_t)src % 4 != 0) return fail(CBD_EARG, "rs_factor_capture: unaligned read");
+            if (b && check) {
+                std::memcpy(dst, tape->rd.data() + tape->rd_off[ri], b);
+                launch_check_words(src, d_rd + tape->rd_off[ri], b, flag, s);
+            }
+            ++ri;
+            return CBD_OK;
+        }
+        if (b) HIPCHK(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ++*syncs;
+        if (mode == RECORD) FactorTape::add(tape->rd, tape->rd_off, tape->rd_len, dst, b);
+        return CBD_OK;
+    }
+    // the host waits for the uploads so far (their host sources may go)
+    int sync(hipStream_t s) {
+        if (mode == CAPTURE) return CBD_OK;
+        HIPCHK(hipStreamSynchronize(s));
+        ++*syncs;
+        return CBD_OK;
+    }
+};
 
 // Levels with at least this many boxes run the ID with one workgroup per box;
 // fewer boxes use the stepped QR that spreads each box over many workgroups.
@@ -794,8 +883,9 @@ size_t apply_bytes(long total, long root_boxes, int root_np_max, int cols, size_
 
 template <typename R>
 int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, const int* hint, int* ranks_out,
-                hipStream_t s, cbd_factor_s* F) {
+                hipStream_t s, cbd_factor_s* F, FactorIo& io) {
     int rc = CBD_OK;
+    io.syncs = &F->host_syncs;
     Arena& A = F->ws;
     auto short_of = [&](const char* what) {
         return fail(CBD_EWORKSPACE, std::string("rs_factor_batched: workspace too small (") + what + ": " +
@@ -808,9 +898,10 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
     F->d_inv_ptr = (int*)A.low(sizeof(int) * (N_ + 1));
     F->d_inv_slot = (int*)A.low(sizeof(int) * Q->total);
     if (!F->d_cidx || !F->d_inv_ptr || !F->d_inv_slot) return short_of("partition maps");
-    HIPCHK(hipMemcpyAsync(F->d_cidx, Q->cidx.data(), sizeof(int) * Q->total, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(F->d_inv_ptr, Q->inv_ptr.data(), sizeof(int) * (N_ + 1), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(F->d_inv_slot, Q->inv_slot.data(), sizeof(int) * Q->total, hipMemcpyHostToDevice, s));
+    if ((rc = io.up(F->d_cidx, Q->cidx.data(), sizeof(int) * Q->total, s)) ||
+        (rc = io.up(F->d_inv_ptr, Q->inv_ptr.data(), sizeof(int) * (N_ + 1), s)) ||
+        (rc = io.up(F->d_inv_slot, Q->inv_slot.data(), sizeof(int) * Q->total, s)))
+        return rc;
     const int d = P->d, n = P->n;
     const ProblemView PV = P->view();
     const int D = (int)Q->subs.size();
@@ -829,7 +920,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
         b->A = &A;
     double* d_dir = (double*)A.low(sizeof(double) * hdir.size());
     if (!d_dir) return short_of("proxy directions");
-    HIPCHK(hipMemcpyAsync(d_dir, hdir.data(), sizeof(double) * hdir.size(), hipMemcpyHostToDevice, s));
+    if ((rc = io.up(d_dir, hdir.data(), sizeof(double) * hdir.size(), s))) return rc;
 
     int Lmax = 0;
     if (!o->exact)
@@ -839,8 +930,9 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
     // level while the previous level's elimination runs
     int* d_stat = (int*)A.low(sizeof(int) * (Lmax + 1));
     if (!d_stat) return short_of("status slots");
+    F->d_stat = d_stat;
     F->stage.assign(Lmax + 1, 0);   // kept alive with the factor until the copy is done
-    HIPCHK(hipMemcpyAsync(d_stat, F->stage.data(), sizeof(int) * (Lmax + 1), hipMemcpyHostToDevice, s));
+    if ((rc = io.up(d_stat, F->stage.data(), sizeof(int) * (Lmax + 1), s))) return rc;
     std::vector<std::vector<int>> keep;   // host sources of uploads still in flight
     // grid coordinates of a global index
     // half-cell coordinates 2 j_t + 1 of every slot (near-field tests in integers)
@@ -1165,12 +1257,11 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
             hnear.insert(hnear.end(), nearl[B].begin(), nearl[B].end());
             hch.insert(hch.end(), chl[B].begin(), chl[B].end());
         }
-        HIPCHK(hipMemcpyAsync(L.d_meta, L.meta.data(), sizeof(BoxMeta) * L.nbox, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(L.d_act, hact.data(), sizeof(int) * o_act, hipMemcpyHostToDevice, s));
-        if (o_near)
-            HIPCHK(hipMemcpyAsync(nearbuf.p, hnear.data(), sizeof(int) * o_near, hipMemcpyHostToDevice, s));
-        if (o_ch)
-            HIPCHK(hipMemcpyAsync(chbuf.p, hch.data(), sizeof(ChildRef<R>) * o_ch, hipMemcpyHostToDevice, s));
+        if ((rc = io.up(L.d_meta, L.meta.data(), sizeof(BoxMeta) * L.nbox, s)) ||
+            (rc = io.up(L.d_act, hact.data(), sizeof(int) * o_act, s)) ||
+            (rc = io.up(nearbuf.p, hnear.data(), sizeof(int) * o_near, s)) ||
+            (rc = io.up(chbuf.p, hch.data(), sizeof(ChildRef<R>) * o_ch, s)))
+            return rc;
         R* FF = (R*)L.d_F;
         std::vector<int> kpred;
         std::vector<int> kall, sk_ell;   // ranks (host copy kept for the upload) and sketch rows per box
@@ -1181,11 +1272,9 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
             if ((rc = mlpbuf.ensure(sizeof(float) * (size_t)L.nbox * (kMlpFeatures + 1)))) return rc;
             float* dX = (float*)mlpbuf.p;
             float* dy = dX + (size_t)L.nbox * kMlpFeatures;
-            HIPCHK(hipMemcpyAsync(dX, feats.data(), sizeof(float) * feats.size(), hipMemcpyHostToDevice, s));
+            if ((rc = io.up(dX, feats.data(), sizeof(float) * feats.size(), s))) return rc;
             launch_mlp_forward(o->mlp, L.nbox, dX, dy, nullptr, nullptr, s);
-            HIPCHK(hipMemcpyAsync(yhat.data(), dy, sizeof(float) * L.nbox, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            F->host_syncs++;
+            if ((rc = io.rd(yhat.data(), dy, sizeof(float) * L.nbox, s))) return rc;
             kpred.resize(L.nbox);
             for (int B = 0; B < L.nbox; ++B) {
                 const int kmax = std::min(L.meta[B].m, L.meta[B].np);
@@ -1233,7 +1322,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                 if ((rc2 = idbuf.ensure(sizeof(BoxMeta) * nb + sizeof(int) * nb))) return rc2;
                 BoxMeta* d_bm = (BoxMeta*)idbuf.p;
                 int* d_kb = (int*)(d_bm + nb);
-                HIPCHK(hipMemcpyAsync(d_bm, bm.data(), sizeof(BoxMeta) * nb, hipMemcpyHostToDevice, s));
+                if ((rc2 = io.up(d_bm, bm.data(), sizeof(BoxMeta) * nb, s))) return rc2;
                 const size_t shm = (size_t)(np_max + m_max) * sizeof(double) + (size_t)np_max * sizeof(int);
                 std::vector<BoxMeta> cmh;   // compact metadata of row-compressed boxes
                 const bool reg = cpqr_reg_fits(m_max, np_max);
@@ -1269,7 +1358,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                     gs.done = (int*)gp;
                     gs.k = gs.done + nb;
                     gs.jend = gs.k + nb;
-                    HIPCHK(hipMemcpyAsync(d_goff, goffs.data(), sizeof(long) * nb, hipMemcpyHostToDevice, s));
+                    if ((rc2 = io.up(d_goff, goffs.data(), sizeof(long) * nb, s))) return rc2;
                     launch_gram(nb, np_max, d_bm, Ymat, d_goff, Gm, s);
                     int jmax = 0;
                     for (const BoxMeta& M : bm) jmax = std::max(jmax, std::min(M.m, M.np));
@@ -1286,9 +1375,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                         launch_pchol_panel(nb, np_max, d_bm, d_goff, Gm, gs, j0, o->tol, tie, s);
                         ++panels;
                         if (panels < first && j0 + kPcholPanel <= jmax) continue;
-                        HIPCHK(hipMemcpyAsync(done.data(), gs.done, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
-                        HIPCHK(hipStreamSynchronize(s));
-                        F->host_syncs++;
+                        if ((rc2 = io.rd(done.data(), gs.done, sizeof(int) * nb, s))) return rc2;
                         bool all = true;
                         for (int v : done) all = all && v;
                         if (all) break;
@@ -1353,7 +1440,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                         double* halpha = Tw + (size_t)nb * kHqrTw;
                         double* Vb = halpha + o_act;
                         double* Rc = Vb + nv;
-                        HIPCHK(hipMemcpyAsync(d_cm, cmh.data(), sizeof(BoxMeta) * nb, hipMemcpyHostToDevice, s));
+                        if ((rc2 = io.up(d_cm, cmh.data(), sizeof(BoxMeta) * nb, s))) return rc2;
                         launch_hqr(nb, np_max, m_max, k_max, d_bm, Ymat, Tw, halpha, Vb, d_cm, Rc, s);
                         F->hqr_levels++;
                         qmeta = d_cm;
@@ -1377,9 +1464,8 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                     for (const BoxMeta& M : bm) jmax = std::max(jmax, std::min(M.m, M.np));
                     std::vector<int> done(nb);
                     auto all_done = [&](bool& all) -> int {
-                        HIPCHK(hipMemcpyAsync(done.data(), st.done, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
-                        HIPCHK(hipStreamSynchronize(s));
-                        F->host_syncs++;
+                        int rc3;
+                        if ((rc3 = io.rd(done.data(), st.done, sizeof(int) * nb, s))) return rc3;
                         all = true;
                         for (int v : done) all = all && v;
                         return CBD_OK;
@@ -1406,10 +1492,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                     }
                     launch_qr_finish(nb, np_max, qmeta, QY, st, L.d_act, L.d_sr, L.d_perm, d_kb, T64, s);
                 }
-                HIPCHK(hipMemcpyAsync(kb.data(), d_kb, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                F->host_syncs++;
-                return CBD_OK;
+                return io.rd(kb.data(), d_kb, sizeof(int) * nb, s);
             };
             std::vector<int> det;   // boxes with the deterministic ID
             if (o->id_sketch) {
@@ -1454,10 +1537,10 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
                     long* d_boff = (long*)(d_keys + nbc);
                     double* Z = (double*)(d_boff + nbc);
                     unsigned* d_bits = (unsigned*)(Z + std::max(o_z, 1L));
-                    HIPCHK(hipMemcpyAsync(d_zall, zall.data(), sizeof(BoxMeta) * nbc, hipMemcpyHostToDevice, s));
-                    HIPCHK(hipMemcpyAsync(d_keys, keys.data(), sizeof(unsigned long long) * nbc,
-                                          hipMemcpyHostToDevice, s));
-                    HIPCHK(hipMemcpyAsync(d_boff, boff.data(), sizeof(long) * nbc, hipMemcpyHostToDevice, s));
+                    if ((rc3 = io.up(d_zall, zall.data(), sizeof(BoxMeta) * nbc, s)) ||
+                        (rc3 = io.up(d_keys, keys.data(), sizeof(unsigned long long) * nbc, s)) ||
+                        (rc3 = io.up(d_boff, boff.data(), sizeof(long) * nbc, s)))
+                        return rc3;
                     launch_sketch(nbc, np_max_c, mw_max, d_meta_c, d_zall, Y, (const int*)nearbuf.p, F->d_cidx,
                                   P->N, o->sketch_seed, d_keys, d_boff, d_bits, Z, s);
                     std::vector<int> kz;
@@ -1516,21 +1599,20 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
             L.sr.resize(o_act);
             for (int B = b0; B < b1; ++B) L.k[B] = kall[B];
             const long a0 = L.meta[b0].act, a1 = b1 < L.nbox ? L.meta[b1].act : o_act;
-            HIPCHK(hipMemcpyAsync(d_k_c, L.k.data() + b0, sizeof(int) * nbc, hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(L.sr.data() + a0, L.d_sr + a0, sizeof(int) * (a1 - a0), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            F->host_syncs++;
+            if ((rc = io.up(d_k_c, L.k.data() + b0, sizeof(int) * nbc, s)) ||
+                (rc = io.rd(L.sr.data() + a0, L.d_sr + a0, sizeof(int) * (a1 - a0), s)))
+                return rc;
         } else if (ci == 0) {
             // root boxes: no compression, k = 0, identity order
             std::vector<int> zeros(L.nbox, 0), ident(o_act);
             for (int B = 0; B < L.nbox; ++B)
                 for (int e = 0; e < L.meta[B].np; ++e) ident[L.meta[B].act + e] = e;
-            HIPCHK(hipMemcpyAsync(L.d_k, zeros.data(), sizeof(int) * L.nbox, hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(L.d_perm, ident.data(), sizeof(int) * o_act, hipMemcpyHostToDevice, s));
-            HIPCHK(hipMemcpyAsync(L.d_sr, hact.data(), sizeof(int) * o_act, hipMemcpyHostToDevice, s));
+            if ((rc = io.up(L.d_k, zeros.data(), sizeof(int) * L.nbox, s)) ||
+                (rc = io.up(L.d_perm, ident.data(), sizeof(int) * o_act, s)) ||
+                (rc = io.up(L.d_sr, hact.data(), sizeof(int) * o_act, s)))
+                return rc;
             // the host vectors must stay alive until the copies finish
-            HIPCHK(hipStreamSynchronize(s));
-            F->host_syncs++;
+            if ((rc = io.sync(s))) return rc;
             L.k.assign(L.nbox, 0);
             L.sr = hact;
         }
@@ -1557,7 +1639,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
             keep.emplace_back(small);
             std::vector<int>& lists = keep.back();
             lists.insert(lists.end(), big.begin(), big.end());
-            HIPCHK(hipMemcpyAsync(d_small, lists.data(), sizeof(int) * lists.size(), hipMemcpyHostToDevice, s));
+            if ((rc = io.up(d_small, lists.data(), sizeof(int) * lists.size(), s))) return rc;
             launch_eliminate<R>((int)small.size(), d_meta_c, d_small, L.d_perm, d_k_c, App, T64, Wk, FF,
                                 d_status, bf16, s);
             launch_big_schur<R>((int)big.size(), np_big, d_meta_c, d_big, 1, L.d_perm, d_k_c, App, T64, Wk, FF,
@@ -1570,9 +1652,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
             // a breakdown names a chunk-local box: check before the next chunk (every
             // level so far, so that the lowest failing level is the one reported)
             std::vector<int> st(l + 1, 0);
-            HIPCHK(hipMemcpyAsync(st.data(), d_stat, sizeof(int) * (l + 1), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            F->host_syncs++;
+            if ((rc = io.rd(st.data(), d_stat, sizeof(int) * (l + 1), s, false))) return rc;
             for (int l2 = 0; l2 <= l; ++l2) {
                 if (!st[l2]) continue;
                 const Level& L2 = F->levels[l2];
@@ -1622,9 +1702,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
     }
     // breakdowns (one slot per level; a split level was checked chunk by chunk)
     std::vector<int> status(Lmax + 1, 0);
-    HIPCHK(hipMemcpyAsync(status.data(), d_stat, sizeof(int) * (Lmax + 1), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    F->host_syncs++;
+    if ((rc = io.rd(status.data(), d_stat, sizeof(int) * (Lmax + 1), s, false))) return rc;
     for (int l = 0; l <= Lmax; ++l) {
         if (!status[l]) continue;
         const Level& L = F->levels[l];
@@ -1789,8 +1867,21 @@ extern "C" int rs_factor_batched(cbd_problem p, cbd_partition q, const cbd_rs_op
         ScopedTimer tm("factor", s);
         const long l0 = g_launches;
         try {
-            rc = o->precision == CBD_PREC_FP64 ? factor_impl<double>(p, q, o, rank_hint, ranks_out, s, F)
-                                               : factor_impl<float>(p, q, o, rank_hint, ranks_out, s, F);
+            FactorIo io;
+            if (o->record) {
+                F->tape.reset(new FactorTape);
+                F->tape->opts = *o;
+                if (rank_hint) {
+                    int nh = 0;
+                    (void)rs_factor_rank_count(q, o, &nh);
+                    F->tape->has_hint = true;
+                    F->tape->hint.assign(rank_hint, rank_hint + nh);
+                }
+                io.mode = FactorIo::RECORD;
+                io.tape = F->tape.get();
+            }
+            rc = o->precision == CBD_PREC_FP64 ? factor_impl<double>(p, q, o, rank_hint, ranks_out, s, F, io)
+                                               : factor_impl<float>(p, q, o, rank_hint, ranks_out, s, F, io);
         } catch (const std::bad_alloc&) {
             rc = fail(CBD_ENOMEM, "rs_factor_batched: host allocation failed");
         }
@@ -1808,6 +1899,127 @@ extern "C" int rs_factor_batched(cbd_problem p, cbd_partition q, const cbd_rs_op
 
 extern "C" int rs_factor_free(cbd_factor f) {
     delete f;
+    return CBD_OK;
+}
+
+namespace {
+size_t al16(size_t b) { return (b + 15) & ~(size_t)15; }
+constexpr size_t kGwsFlag = 256;   // the check flag's share of gws
+}  // namespace
+
+extern "C" size_t rs_factor_graph_bytes(cbd_factor f) {
+    if (!f || !f->tape) return 0;
+    return kGwsFlag + al16(f->tape->up.size()) + al16(f->tape->rd.size());
+}
+
+extern "C" int rs_factor_capture(cbd_factor f, void* gws, size_t gws_bytes, void* stream) {
+    if (!f || !gws) return fail(CBD_EARG, "rs_factor_capture: NULL argument");
+    if (!f->tape) return fail(CBD_EARG, "rs_factor_capture: the factor was made without opts.record");
+    if (f->stale) return fail(CBD_EREPLAN, "rs_factor_capture: the factor is stale (a replay did not match)");
+    if (((uintptr_t)gws & 255) != 0) return fail(CBD_EARG, "rs_factor_capture: gws must be 256-byte aligned");
+    if (gws_bytes < rs_factor_graph_bytes(f)) return fail(CBD_EARG, "rs_factor_capture: gws too small");
+    FactorTape& T = *f->tape;
+    hipStream_t s = (hipStream_t)stream;
+    char* g = (char*)gws;
+    const size_t up_at = kGwsFlag, rd_at = kGwsFlag + al16(T.up.size());
+    if (!T.up.empty()) HIPCHK(hipMemcpyAsync(g + up_at, T.up.data(), T.up.size(), hipMemcpyHostToDevice, s));
+    if (!T.rd.empty()) HIPCHK(hipMemcpyAsync(g + rd_at, T.rd.data(), T.rd.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (f->graph) {
+        (void)hipGraphExecDestroy(f->graph);
+        f->graph = nullptr;
+    }
+    // a second pass over the host side, on a copy of the factor over the same workspace:
+    // the same allocations give the same device addresses
+    std::unique_ptr<cbd_factor_s> G(new cbd_factor_s);
+    G->prob = f->prob;
+    G->part = f->part;
+    G->esize = f->esize;
+    G->prec = f->prec;
+    G->tol = f->tol;
+    G->ws.init(f->ws.base, f->ws.cap);
+    FactorIo io;
+    io.mode = FactorIo::CAPTURE;
+    io.tape = &T;
+    io.d_up = g + up_at;
+    io.d_rd = g + rd_at;
+    io.flag = (int*)g;
+    hipStream_t cs = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } guard{cs};
+    hipGraph_t graph = nullptr;
+    const long l0 = g_launches;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(CBD_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    g_capturing = true;
+    int rc = CBD_OK;
+    try {
+        launch_set_word(io.flag, 0, cs);
+        const int* hint = T.has_hint ? T.hint.data() : nullptr;
+        rc = f->prec == CBD_PREC_FP64 ? factor_impl<double>(f->prob, f->part, &T.opts, hint, nullptr, cs, G.get(), io)
+                                      : factor_impl<float>(f->prob, f->part, &T.opts, hint, nullptr, cs, G.get(), io);
+    } catch (const std::bad_alloc&) {
+        rc = fail(CBD_ENOMEM, "rs_factor_capture: host allocation failed");
+    }
+    g_capturing = false;
+    e = hipStreamEndCapture(cs, &graph);
+    if (!rc && (io.ui != T.up_len.size() || io.ri != T.rd_len.size())) rc = io.plan_differs();
+    // the second pass must have laid the factor out exactly as the first
+    if (!rc) {
+        bool same = G->ws.lo == f->ws.lo && G->levels.size() == f->levels.size() && G->v == f->v &&
+                    G->t1 == f->t1 && G->d_stat == f->d_stat;
+        for (size_t l = 0; same && l < f->levels.size(); ++l)
+            same = G->levels[l].d_F == f->levels[l].d_F && G->levels[l].d_meta == f->levels[l].d_meta &&
+                   G->levels[l].nbox == f->levels[l].nbox;
+        if (!same) rc = io.plan_differs();
+    }
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(CBD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&f->graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        f->graph = nullptr;
+        return fail(CBD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    f->gws = g;
+    f->graph_launches = g_launches - l0;
+    return CBD_OK;
+}
+
+extern "C" int rs_factor_replay(cbd_factor f, void* stream) {
+    if (!f) return fail(CBD_EARG, "rs_factor_replay: NULL factor");
+    if (!f->graph) return fail(CBD_EARG, "rs_factor_replay: no graph (rs_factor_capture first)");
+    if (f->stale) return fail(CBD_EREPLAN, "rs_factor_replay: the factor is stale (a replay did not match)");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipGraphLaunch(f->graph, s));
+    const int nst = (int)f->stage.size();
+    std::vector<int> st(nst + 1, 0);
+    HIPCHK(hipMemcpyAsync(st.data(), f->gws, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(st.data() + 1, f->d_stat, sizeof(int) * nst, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // reads that differ come first: after one, the plan no longer fits the data and any
+    // breakdown may follow from that
+    if (st[0]) {
+        f->stale = 1;
+        return fail(CBD_EREPLAN, "rs_factor_replay: the factorization read values other than the recorded ones "
+                                 "(ranks, skeletons or stop flags changed); factor again");
+    }
+    for (int l = 0; l < nst; ++l) {
+        if (!st[l + 1]) continue;
+        f->stale = 1;
+        const Level& L = f->levels[l];
+        const int B = st[l + 1] - 1;
+        return fail(CBD_ENOTSPD, "rs_factor_replay: Cholesky breakdown at level " + std::to_string(l) +
+                                     (L.root ? " (root)" : "") + ", subdomain " +
+                                     std::to_string(B < L.nbox ? L.box_sub[B] : -1) + ", box " +
+                                     std::to_string(B < L.nbox ? L.box_idx[B] : -1));
+    }
     return CBD_OK;
 }
 
@@ -1927,6 +2139,7 @@ static int apply_impl(cbd_factor f, int nrhs, const double* r, double* z, long s
 extern "C" int rs_apply(cbd_factor f, int nrhs, const double* r, double* z, void* stream) {
     if (!f || !r || !z || nrhs < 1) return fail(CBD_EARG, "rs_apply: bad argument");
     if (r == z) return fail(CBD_EARG, "rs_apply: r and z alias");
+    if (f->stale) return fail(CBD_EREPLAN, "rs_apply: the factor is stale (a replay did not match)");
     hipStream_t s = (hipStream_t)stream;
     ScopedTimer tm("apply", s);
     const long tot = f->part->total;
@@ -1937,6 +2150,7 @@ extern "C" int rs_apply(cbd_factor f, int nrhs, const double* r, double* z, void
 extern "C" int rs_apply_sub(cbd_factor f, int i, int nrhs, const double* r, double* z, void* stream) {
     if (!f || !r || !z || nrhs < 1) return fail(CBD_EARG, "rs_apply_sub: bad argument");
     if (r == z) return fail(CBD_EARG, "rs_apply_sub: r and z alias");
+    if (f->stale) return fail(CBD_EREPLAN, "rs_apply_sub: the factor is stale (a replay did not match)");
     if (i < 0 || i >= (int)f->part->subs.size()) return fail(CBD_EARG, "rs_apply_sub: bad subdomain");
     hipStream_t s = (hipStream_t)stream;
     const Sub& sd = f->part->subs[i];
@@ -2131,6 +2345,7 @@ extern "C" int pcg_solve(cbd_problem p, cbd_factor fac, int nrhs, const double* 
     const long N = p->N;
     if (ws_bytes < pcg_workspace_bytes(N, nrhs)) return fail(CBD_EARG, "pcg_solve: workspace too small");
     if (fac && fac->prob != p) return fail(CBD_EARG, "pcg_solve: factor belongs to another problem");
+    if (fac && fac->stale) return fail(CBD_EREPLAN, "pcg_solve: the factor is stale (a replay did not match)");
     hipStream_t s = (hipStream_t)stream;
     const bool graph = (flags & CBD_PCG_GRAPH) != 0;
     if (graph && s == nullptr) return fail(CBD_EARG, "pcg_solve: graph mode needs a non-default stream");

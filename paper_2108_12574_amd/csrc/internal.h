@@ -257,6 +257,10 @@ void launch_pcg_update_p(double* p, const double* z, const double* beta, long N,
 void launch_copy(double* dst, const double* src, long n, hipStream_t s);
 void launch_fill(double* dst, double v, long n, hipStream_t s);
 void launch_sub(double* dst, const double* a, const double* b, long n, hipStream_t s);
+// 4-byte words (bytes a multiple of 4): copy; flag = 1 where a differs from ref; *p = v
+void launch_copy_words(void* dst, const void* src, size_t bytes, hipStream_t s);
+void launch_check_words(const void* a, const void* ref, size_t bytes, int* flag, hipStream_t s);
+void launch_set_word(int* p, int v, hipStream_t s);
 
 constexpr int kDotBlocks = 256;   // partial sums per right-hand side in launch_dot
 

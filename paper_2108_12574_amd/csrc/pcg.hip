@@ -144,4 +144,34 @@ void launch_sub(double* dst, const double* a, const double* b, long n, hipStream
     CBD_LAUNCH(k_sub, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, dst, a, b, n);
 }
 
+// ---- factorization replay: uploads from device copies, checks of recorded reads ----
+__global__ void k_copy_words(unsigned* __restrict__ dst, const unsigned* __restrict__ src, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+// flag = 1 if a and ref differ anywhere (every writer stores the same value)
+__global__ void k_check_words(const unsigned* __restrict__ a, const unsigned* __restrict__ ref, long n,
+                              int* __restrict__ flag) {
+    bool diff = false;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        diff = diff || a[i] != ref[i];
+    if (diff) *flag = 1;
+}
+__global__ void k_set_word(int* __restrict__ p, int v) {
+    if (threadIdx.x == 0) *p = v;
+}
+void launch_copy_words(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const long n = (long)(bytes / 4);
+    if (n > 0)
+        CBD_LAUNCH(k_copy_words, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, (unsigned*)dst, (const unsigned*)src,
+                   n);
+}
+void launch_check_words(const void* a, const void* ref, size_t bytes, int* flag, hipStream_t s) {
+    const long n = (long)(bytes / 4);
+    if (n > 0)
+        CBD_LAUNCH(k_check_words, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, (const unsigned*)a,
+                   (const unsigned*)ref, n, flag);
+}
+void launch_set_word(int* p, int v, hipStream_t s) { CBD_LAUNCH(k_set_word, dim3(1), dim3(64), 0, s, p, v); }
+
 }  // namespace cbd
