@@ -410,8 +410,13 @@ def main():
         torch.cuda.synchronize()
         cbd.timing.enable(False)
         ms, cnt = cbd.timing.get("apply")
+        levels = []
+        for l in range(fac.stats()["levels"] + 1):
+            k, npl, _ = fac.level(l)
+            levels.append({"level": l, "boxes": len(npl), "np_max": max(npl), "np_mean": float(np.mean(npl)),
+                           "k_mean": float(np.mean(k))})
         print(json.dumps({"workload": W["label"], "apply_avg_ms": ms / max(cnt, 1), "factor_bytes": fac.stats()["bytes"],
-                          "nrhs": nrhs}))
+                          "nrhs": nrhs, "levels": levels}))
         return
 
     if args.matvec_only:

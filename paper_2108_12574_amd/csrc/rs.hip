@@ -1608,7 +1608,9 @@ __device__ __forceinline__ void tile_gemm(int i0, int j0, int M, int N, int K, R
     v4 acc = {0, 0, 0, 0};
     const int i = i0 + li, j = j0 + li;
     // the lane's row of op(A) and column of op(B) (clamped to a valid one and masked),
-    // walked in steps of 4 along k; blocks of kU steps load before they multiply
+    // walked in steps of 4 along k, in batches of kU steps whose loads are all issued
+    // before any of them is used; the last, partial batch is masked the same way (no
+    // serial tail of dependent loads)
     constexpr int kU = 8;
     const bool iok = i < M, jok = j < N;
     const long sa = ta ? 1 : lda, sb = tb ? ldb : 1;
@@ -1627,12 +1629,18 @@ __device__ __forceinline__ void tile_gemm(int i0, int j0, int M, int N, int K, R
         pa += (long)(4 * kU) * sa;
         pb += (long)(4 * kU) * sb;
     }
-    for (; k0 < K; k0 += 4) {
-        const int kk = k0 + lk;
-        R a = 0, b = 0;
-        if (iok && kk < K) a = ta ? A[kk + (long)i * lda] : A[i + (long)kk * lda];
-        if (jok && kk < K) b = tb ? B[j + (long)kk * ldb] : B[kk + (long)j * ldb];
-        acc = Mma<R>::op(a, b, acc);
+    if (k0 < K) {
+        const int rem = K - k0 - lk;   // this lane's steps left: u < rem / 4 (rounded up)
+        R a[kU], b[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = 4 * u < rem;
+            a[u] = (ok && iok) ? pa[(long)(4 * u) * sa] : (R)0;
+            b[u] = (ok && jok) ? pb[(long)(4 * u) * sb] : (R)0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (4 * u < K - k0) acc = Mma<R>::op(a[u], b[u], acc);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
