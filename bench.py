@@ -410,13 +410,25 @@ def main():
         torch.cuda.synchronize()
         cbd.timing.enable(False)
         ms, cnt = cbd.timing.get("apply")
+        # the same with the apply's columns per workgroup tuned level by level
+        cols = fac.autotune_apply(F_rhs)
+        z = fac.apply(F_rhs)
+        torch.cuda.synchronize()
+        cbd.timing.reset()
+        cbd.timing.enable(True)
+        for _ in range(10):
+            z = fac.apply(F_rhs)
+        torch.cuda.synchronize()
+        cbd.timing.enable(False)
+        ms_t, cnt_t = cbd.timing.get("apply")
         levels = []
         for l in range(fac.stats()["levels"] + 1):
             k, npl, _ = fac.level(l)
             levels.append({"level": l, "boxes": len(npl), "np_max": max(npl), "np_mean": float(np.mean(npl)),
                            "k_mean": float(np.mean(k))})
-        print(json.dumps({"workload": W["label"], "apply_avg_ms": ms / max(cnt, 1), "factor_bytes": fac.stats()["bytes"],
-                          "nrhs": nrhs, "levels": levels}))
+        print(json.dumps({"workload": W["label"], "apply_avg_ms": ms / max(cnt, 1),
+                          "apply_tuned_ms": ms_t / max(cnt_t, 1), "apply_cols": cols,
+                          "factor_bytes": fac.stats()["bytes"], "nrhs": nrhs, "levels": levels}))
         return
 
     if args.matvec_only:
@@ -481,6 +493,8 @@ def main():
                              sketch_seed=sk_seed, apply_rhs=nrhs, ws=ws_factor, id_method=idm, record=box["replay"])
             if box["replay"]:
                 fac.capture()
+            if box.get("apply_cols"):
+                fac.set_apply_shapes(box["apply_cols"])
         torch.cuda.synchronize()
         box["fac"] = fac
         return fac, time.perf_counter() - t0
@@ -509,6 +523,10 @@ def main():
         factor_step()                   # eager, recorded, captured
         fac_modes["graph"] = min(factor_step()[1] for _ in range(2))
         box["replay"] = fac_modes["graph"] < fac_modes["eager"]
+    # the apply's columns per workgroup, tuned level by level on the current factor (the
+    # timed steps' factors take the same choices)
+    box["apply_cols"] = box["fac"].autotune_apply(F_rhs)
+    log("apply columns per workgroup by level: %s" % box["apply_cols"])
     log("factor eager %.4f s, graph replay %s s: timed steps use %s"
         % (fac_modes["eager"], "%.4f" % fac_modes["graph"] if fac_modes["graph"] else "-",
            "replays" if box["replay"] else "eager launches"))
@@ -803,6 +821,7 @@ def main():
         "matvec_avg_ms": mv_avg_s * 1e3 if mv_avg_s else None,
         "matvec_1rhs_ms": mv1_ms,
         "apply_avg_ms": ap_ms / max(ap_n, 1),
+        "apply_tile": {"cols_per_level": box["apply_cols"], "chosen_by": "cbd_autotune_apply"},
         "matvec_tile": {"shape": tile, "rows_per_wave": 16 * (tile & 7), "waves_per_workgroup": 8 if tile >= 8 else 4,
                         "chosen_by": "cbd_autotune_matvec"},
         "sketched_id_variant": sketched,

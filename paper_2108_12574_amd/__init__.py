@@ -244,6 +244,21 @@ class Factor:
         check(lib().rs_apply(self.handle, r.shape[0], _ptr(r), _ptr(z), _stream(self.problem.device)))
         return z[0] if one else z
 
+    def autotune_apply(self, r):
+        """Choose the apply sweep's columns per workgroup level by level (cbd_autotune_apply)
+        on a sample r of shape (nrhs, N); returns the choices (0: level applied by GEMMs)."""
+        r = _vec(r, self.problem.N, self.problem.device)
+        n = self.stats()["levels"] + 1
+        ch = (ctypes.c_int * n)()
+        check(lib().cbd_autotune_apply(self.handle, r.shape[0], _ptr(r), _stream(self.problem.device), ch))
+        return list(ch)
+
+    def set_apply_shapes(self, choices):
+        """Fix the apply's columns per workgroup per level (cbd_apply_set_shape), e.g. the
+        choices autotune_apply made on a factor of the same layout."""
+        for l, c in enumerate(choices):
+            check(lib().cbd_apply_set_shape(self.handle, l, int(c)))
+
     def apply_sub(self, i, r):
         """z = R_i^T A_i^{-1} R_i r, subdomain i's term of T^{-1} r (rs_apply_sub)."""
         one = r.dim() == 1

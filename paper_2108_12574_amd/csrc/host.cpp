@@ -694,6 +694,7 @@ struct Level {
     std::vector<int> sub_start;         // first batch index of each subdomain (-1: absent)
     int np_max = 0, m_max = 0;
     long tot_act = 0, tot_f = 0;
+    int apply_cols = 0;                 // the apply sweep's columns per workgroup (0: default)
     // device arrays of the level, in the caller's workspace
     BoxMeta* d_meta = nullptr;
     int *d_act = nullptr, *d_sr = nullptr, *d_perm = nullptr, *d_k = nullptr;
@@ -2123,16 +2124,100 @@ static int apply_impl(cbd_factor f, int nrhs, const double* r, double* z, long s
                                      (R*)f->t1, (R*)f->t2, s);
                 continue;
             }
-            launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nc, L.np_max, true, s);
+            launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nc, L.np_max, L.apply_cols,
+                                  true, s);
         }
         for (int l = nl - 1; l >= 0; --l) {
             const Level& L = f->levels[l];
             if (root_uses_gemm(L)) continue;
-            launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nc, L.np_max, false, s);
+            launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nc, L.np_max, L.apply_cols,
+                                  false, s);
         }
         launch_scatter<R>(v, nc, f->d_inv_ptr, f->d_inv_slot, N, zc, s);
     }
     HIPCHK(hipGetLastError());
+    return CBD_OK;
+}
+
+// cbd_autotune_apply: each level's candidates timed by forward and backward sweeps of
+// that level on the factor's local vectors (filled by a gather of r).
+template <typename R>
+static int autotune_apply_impl(cbd_factor f, int nrhs, const double* r, hipStream_t s, int* choices) {
+    cbd_partition_s* Q = f->part;
+    R* v = (R*)f->v;
+    const long N = f->prob->N;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    const size_t lim = apply_level_lds_limit<R>();
+    for (size_t l = 0; l < f->levels.size(); ++l) {
+        Level& L = f->levels[l];
+        if (choices) choices[l] = 0;
+        if (root_uses_gemm(L) || L.nbox == 0) continue;
+        int best = 0;
+        float best_t = 0.f;
+        for (int cols : {8, 16, 32, 64}) {
+            if (cols > nrhs && cols != 8) continue;
+            if ((size_t)2 * L.np_max * cols * sizeof(R) > lim) continue;
+            auto sweep = [&]() {
+                launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, cols, true,
+                                      s);
+                launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, cols, false,
+                                      s);
+            };
+            // one warm-up and three timed sweeps, each from freshly gathered vectors (repeated
+            // sweeps would scale them up by the inverse's norm every time)
+            float ms = 0.f;
+            for (int rep = 0; rep < 4; ++rep) {
+                launch_gather<R>(r, N, nrhs, f->d_cidx, Q->total, 0, Q->total, v, s);
+                HIPCHK(hipEventRecord(e0, s));
+                sweep();
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                float t = 0.f;
+                HIPCHK(hipEventElapsedTime(&t, e0, e1));
+                if (rep) ms += t;
+            }
+            // within 2% of the best counts as a tie, which goes to fewer columns per
+            // workgroup (more workgroups)
+            if (!best || ms < best_t * 0.98f) {
+                best = cols;
+                best_t = ms;
+            }
+        }
+        L.apply_cols = best;
+        if (choices) choices[l] = best;
+    }
+    HIPCHK(hipGetLastError());
+    return CBD_OK;
+}
+
+extern "C" int cbd_autotune_apply(cbd_factor f, int nrhs, const double* r, void* stream, int* choices) {
+    if (!f || !r || nrhs < 1) return fail(CBD_EARG, "cbd_autotune_apply: bad argument");
+    if (nrhs > f->apply_rhs) return fail(CBD_EARG, "cbd_autotune_apply: nrhs exceeds the factor's apply_rhs");
+    if (f->stale) return fail(CBD_EREPLAN, "cbd_autotune_apply: the factor is stale (a replay did not match)");
+    hipStream_t s = (hipStream_t)stream;
+    return f->prec == CBD_PREC_FP64 ? autotune_apply_impl<double>(f, nrhs, r, s, choices)
+                                    : autotune_apply_impl<float>(f, nrhs, r, s, choices);
+}
+
+extern "C" int cbd_apply_set_shape(cbd_factor f, int level, int cols) {
+    if (!f || level < 0 || level >= (int)f->levels.size()) return fail(CBD_EARG, "cbd_apply_set_shape: bad level");
+    if (cols != 0 && cols != 8 && cols != 16 && cols != 32 && cols != 64)
+        return fail(CBD_EARG, "cbd_apply_set_shape: cols must be 0, 8, 16, 32 or 64");
+    Level& L = f->levels[level];
+    const size_t es = f->prec == CBD_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const size_t lim = f->prec == CBD_PREC_FP64 ? apply_level_lds_limit<double>() : apply_level_lds_limit<float>();
+    if (cols && (size_t)2 * L.np_max * cols * es > lim)
+        return fail(CBD_EARG, "cbd_apply_set_shape: the level's boxes need more LDS at this width");
+    L.apply_cols = cols;
     return CBD_OK;
 }
 

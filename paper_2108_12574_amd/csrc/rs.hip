@@ -2399,13 +2399,17 @@ size_t apply_level_lds_limit() {
 
 template <typename R>
 void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int* k, const R* F, R* v,
-                        int nrhs, int np_max, bool forward, hipStream_t s) {
+                        int nrhs, int np_max, int cols, bool forward, hipStream_t s) {
     if (nbox == 0) return;
-    // columns per workgroup so that the local copy fits in 64 KiB of LDS
-    // (16 measured best at 512^2 with 64 right-hand sides: 1.73 ms per apply against 1.77,
-    // 2.04 and 2.18 ms for 32, 64 and 8)
-    int rc = 16;
-    while (rc > 1 && (size_t)2 * np_max * rc * sizeof(R) > 65536) rc >>= 1;
+    // columns per workgroup: `cols` when given (a tuned choice; the caller has checked
+    // its LDS against apply_level_lds_limit), else 16, fewer so that the local copy fits
+    // in 64 KiB of LDS (16 measured best over the whole apply at 512^2 with 64
+    // right-hand sides: 1.73 ms per apply against 1.77, 2.04 and 2.18 ms for 32, 64 and 8)
+    int rc = cols;
+    if (rc <= 0) {
+        rc = 16;
+        while (rc > 1 && (size_t)2 * np_max * rc * sizeof(R) > 65536) rc >>= 1;
+    }
     // (boxes whose one column exceeds 64 KB take more, up to the device's limit; the
     // caller has checked that against apply_level_lds_limit)
     if (rc > nrhs) rc = nrhs;
@@ -2841,7 +2845,7 @@ template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta
     template void launch_scatter<R>(const R*, int, const int*, const int*, long, double*,          \
                                     hipStream_t);                                                   \
     template void launch_apply_level<R>(int, const BoxMeta*, const int*, const int*, const R*, R*,  \
-                                        int, int, bool, hipStream_t);                               \
+                                        int, int, int, bool, hipStream_t);                          \
     template size_t apply_level_lds_limit<R>();
 CBD_INST(double)
 CBD_INST(float)
