@@ -332,20 +332,21 @@ int rs_apply(cbd_factor f, int nrhs, const double* r, double* z, void* stream);
  * 0 <= i < number of subdomains. */
 int rs_apply_sub(cbd_factor f, int i, int nrhs, const double* r, double* z, void* stream);
 
-/* cbd_autotune_apply - choose, level by level, the right-hand-side columns one
- * workgroup of the apply's level sweep takes (8, 16, 32 or 64; the default is 16, fewer
- * where a box's local vectors would pass 64 KB of LDS) by timing each candidate's
- * forward and backward sweep of that level with HIP events on `stream`; later
- * rs_apply calls on this factor use the choices.  The result does not depend on them
- * (from 8 columns on, every column's sums run in the same order).  r: device, N x
- * nrhs FP64, a sample right-hand side (read only); 1 <= nrhs <= opts.apply_rhs.
- * choices: host, (levels + 1) ints (rs_factor_stats' n_levels + 1), or NULL: the columns
- * per workgroup chosen per level (0 for a root level applied by GEMMs).  Uses the
- * factor's apply buffers: must not overlap in time with rs_apply on this factor.
- * cbd_apply_set_shape fixes a level's choice (0: the default), for example on a factor
- * of the same layout as a tuned one.  Host only. */
+/* cbd_autotune_apply - choose, level by level, the shape of the apply's level sweep:
+ * the right-hand-side columns one workgroup takes (8, 16, 32 or 64; default 16, fewer
+ * where a box's local vectors would pass 64 KB of LDS) and its threads (256 or 1024,
+ * the product tiles spread over 4 or 16 waves; default 1024 for boxes of 256 or more
+ * DOFs), by timing each candidate's forward and backward sweep of that level with HIP
+ * events on `stream`; later rs_apply calls on this factor use the choices.  The result
+ * does not depend on them (from 8 columns on, every column's sums run in the same
+ * order).  r: device, N x nrhs FP64, a sample right-hand side (read only);
+ * 1 <= nrhs <= opts.apply_rhs.  choices: host, 2 (levels + 1) ints (levels: rs_factor_stats'
+ * n_levels), or NULL: columns and threads per level (0, 0 for a root level applied by
+ * GEMMs).  Uses the factor's apply buffers: must not overlap in time with rs_apply on
+ * this factor.  cbd_apply_set_shape fixes a level's shape (0: the default), for example
+ * on a factor of the same layout as a tuned one.  Host only. */
 int cbd_autotune_apply(cbd_factor f, int nrhs, const double* r, void* stream, int* choices);
-int cbd_apply_set_shape(cbd_factor f, int level, int cols);
+int cbd_apply_set_shape(cbd_factor f, int level, int cols, int threads);
 
 /* kernel_matvec - y = A x with A of ie_assemble, entries generated on the fly in
  * FP64 (the dense product; the paper uses FFTs for it, Section 5).

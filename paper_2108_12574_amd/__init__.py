@@ -245,19 +245,19 @@ class Factor:
         return z[0] if one else z
 
     def autotune_apply(self, r):
-        """Choose the apply sweep's columns per workgroup level by level (cbd_autotune_apply)
-        on a sample r of shape (nrhs, N); returns the choices (0: level applied by GEMMs)."""
+        """Choose the apply sweep's shape level by level (cbd_autotune_apply) on a sample r
+        of shape (nrhs, N); returns [(columns, threads)] per level ((0, 0): applied by GEMMs)."""
         r = _vec(r, self.problem.N, self.problem.device)
         n = self.stats()["levels"] + 1
-        ch = (ctypes.c_int * n)()
+        ch = (ctypes.c_int * (2 * n))()
         check(lib().cbd_autotune_apply(self.handle, r.shape[0], _ptr(r), _stream(self.problem.device), ch))
-        return list(ch)
+        return [(ch[2 * l], ch[2 * l + 1]) for l in range(n)]
 
     def set_apply_shapes(self, choices):
-        """Fix the apply's columns per workgroup per level (cbd_apply_set_shape), e.g. the
-        choices autotune_apply made on a factor of the same layout."""
-        for l, c in enumerate(choices):
-            check(lib().cbd_apply_set_shape(self.handle, l, int(c)))
+        """Fix the apply's shape per level (cbd_apply_set_shape): (columns, threads) pairs,
+        e.g. the choices autotune_apply made on a factor of the same layout."""
+        for l, (c, t) in enumerate(choices):
+            check(lib().cbd_apply_set_shape(self.handle, l, int(c), int(t)))
 
     def apply_sub(self, i, r):
         """z = R_i^T A_i^{-1} R_i r, subdomain i's term of T^{-1} r (rs_apply_sub)."""

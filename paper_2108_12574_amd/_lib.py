@@ -60,7 +60,7 @@ SIGNATURES = [
     ("cbd_autotune_matvec", _i, [_vp, _i, _vp, _vp, _vp, _ip]),
     ("cbd_matvec_set_shape", _i, [_vp, _i, _i]),
     ("cbd_autotune_apply", _i, [_vp, _i, _vp, _vp, _ip]),
-    ("cbd_apply_set_shape", _i, [_vp, _i, _i]),
+    ("cbd_apply_set_shape", _i, [_vp, _i, _i, _i]),
     ("pcg_workspace_bytes", _sz, [_l, _i]),
     ("pcg_solve", _i, [_vp, _vp, _i, _vp, _vp, _d, _i, _i, _vp, _sz, _ip, _dp, _vp]),
     ("rank_mlp_params", _i, []),

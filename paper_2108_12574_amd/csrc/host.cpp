@@ -695,6 +695,7 @@ struct Level {
     int np_max = 0, m_max = 0;
     long tot_act = 0, tot_f = 0;
     int apply_cols = 0;                 // the apply sweep's columns per workgroup (0: default)
+    int apply_threads = 0;              // and threads per workgroup (256 or 1024; 0: default)
     // device arrays of the level, in the caller's workspace
     BoxMeta* d_meta = nullptr;
     int *d_act = nullptr, *d_sr = nullptr, *d_perm = nullptr, *d_k = nullptr;
@@ -2125,13 +2126,13 @@ static int apply_impl(cbd_factor f, int nrhs, const double* r, double* z, long s
                 continue;
             }
             launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nc, L.np_max, L.apply_cols,
-                                  true, s);
+                                  L.apply_threads, true, s);
         }
         for (int l = nl - 1; l >= 0; --l) {
             const Level& L = f->levels[l];
             if (root_uses_gemm(L)) continue;
             launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nc, L.np_max, L.apply_cols,
-                                  false, s);
+                                  L.apply_threads, false, s);
         }
         launch_scatter<R>(v, nc, f->d_inv_ptr, f->d_inv_slot, N, zc, s);
     }
@@ -2159,18 +2160,19 @@ static int autotune_apply_impl(cbd_factor f, int nrhs, const double* r, hipStrea
     const size_t lim = apply_level_lds_limit<R>();
     for (size_t l = 0; l < f->levels.size(); ++l) {
         Level& L = f->levels[l];
-        if (choices) choices[l] = 0;
+        if (choices) choices[2 * l] = choices[2 * l + 1] = 0;
         if (root_uses_gemm(L) || L.nbox == 0) continue;
-        int best = 0;
+        int best = 0, best_nt = 0;
         float best_t = 0.f;
-        for (int cols : {8, 16, 32, 64}) {
+        for (int cand = 0; cand < 8; ++cand) {
+            const int cols = 8 << (cand & 3), nt = cand < 4 ? 256 : 1024;
             if (cols > nrhs && cols != 8) continue;
             if ((size_t)2 * L.np_max * cols * sizeof(R) > lim) continue;
             auto sweep = [&]() {
-                launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, cols, true,
-                                      s);
-                launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, cols, false,
-                                      s);
+                launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, cols, nt,
+                                      true, s);
+                launch_apply_level<R>(L.nbox, L.d_meta, L.d_sr, L.d_k, (const R*)L.d_F, v, nrhs, L.np_max, cols, nt,
+                                      false, s);
             };
             // one warm-up and three timed sweeps, each from freshly gathered vectors (repeated
             // sweeps would scale them up by the inverse's norm every time)
@@ -2185,15 +2187,20 @@ static int autotune_apply_impl(cbd_factor f, int nrhs, const double* r, hipStrea
                 HIPCHK(hipEventElapsedTime(&t, e0, e1));
                 if (rep) ms += t;
             }
-            // within 2% of the best counts as a tie, which goes to fewer columns per
-            // workgroup (more workgroups)
+            // within 2% of the best counts as a tie, which goes to the earlier candidate
+            // (fewer columns and threads per workgroup)
             if (!best || ms < best_t * 0.98f) {
                 best = cols;
+                best_nt = nt;
                 best_t = ms;
             }
         }
         L.apply_cols = best;
-        if (choices) choices[l] = best;
+        L.apply_threads = best_nt;
+        if (choices) {
+            choices[2 * l] = best;
+            choices[2 * l + 1] = best_nt;
+        }
     }
     HIPCHK(hipGetLastError());
     return CBD_OK;
@@ -2208,16 +2215,19 @@ extern "C" int cbd_autotune_apply(cbd_factor f, int nrhs, const double* r, void*
                                     : autotune_apply_impl<float>(f, nrhs, r, s, choices);
 }
 
-extern "C" int cbd_apply_set_shape(cbd_factor f, int level, int cols) {
+extern "C" int cbd_apply_set_shape(cbd_factor f, int level, int cols, int threads) {
     if (!f || level < 0 || level >= (int)f->levels.size()) return fail(CBD_EARG, "cbd_apply_set_shape: bad level");
     if (cols != 0 && cols != 8 && cols != 16 && cols != 32 && cols != 64)
         return fail(CBD_EARG, "cbd_apply_set_shape: cols must be 0, 8, 16, 32 or 64");
+    if (threads != 0 && threads != 256 && threads != 1024)
+        return fail(CBD_EARG, "cbd_apply_set_shape: threads must be 0, 256 or 1024");
     Level& L = f->levels[level];
     const size_t es = f->prec == CBD_PREC_FP64 ? sizeof(double) : sizeof(float);
     const size_t lim = f->prec == CBD_PREC_FP64 ? apply_level_lds_limit<double>() : apply_level_lds_limit<float>();
     if (cols && (size_t)2 * L.np_max * cols * es > lim)
         return fail(CBD_EARG, "cbd_apply_set_shape: the level's boxes need more LDS at this width");
     L.apply_cols = cols;
+    L.apply_threads = threads;
     return CBD_OK;
 }
 

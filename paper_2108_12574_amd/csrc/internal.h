@@ -234,7 +234,7 @@ void launch_scatter(const R* v, int nrhs, const int* inv_ptr, const int* inv_slo
                     double* z, hipStream_t s);
 template <typename R>
 void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int* k, const R* F,
-                        R* v, int nrhs, int np_max, int cols, bool forward, hipStream_t s);
+                        R* v, int nrhs, int np_max, int cols, int threads, bool forward, hipStream_t s);
 
 // Matvec by FFT (fft.hip): ghat (P^d reals) is the transform of the kernel's circulant
 // generator; tw[k] = exp(-2 pi i k / P), k < P/2; buf holds max_pairs complex P^d arrays.

@@ -1656,13 +1656,14 @@ __device__ __forceinline__ void tile_gemm(int i0, int j0, int M, int N, int K, R
 // ta/tb select the transposes (A[k + i*lda] / B[j + k*ldb]).  All threads of the
 // workgroup call it; 16 x 16 output tiles are spread over the waves.  With
 // upper != 0 tiles entirely below the diagonal are skipped (symmetric results
-// whose upper triangle is used).  Ends with a workgroup barrier.
-template <typename R>
+// whose upper triangle is used).  NW: waves of the workgroup.  Ends with a workgroup
+// barrier.
+template <typename R, int NW = kWaves>
 __device__ void wg_gemm(int M, int N, int K, R alpha, const R* A, int lda, bool ta, const R* B, int ldb,
                         bool tb, R beta, R* C, int ldc, bool upper = false) {
     const int wid = threadIdx.x >> 6;
     const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
-    for (int t = wid; t < tm * tn; t += kWaves) {
+    for (int t = wid; t < tm * tn; t += NW) {
         const int i0 = (t % tm) << 4, j0 = (t / tm) << 4;
         if (upper && i0 > j0 + 15) continue;
         tile_gemm<R>(i0, j0, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, C, ldc);
@@ -2308,11 +2309,12 @@ void launch_scatter(const R* v, int nrhs, const int* inv_ptr, const int* inv_slo
     CBD_LAUNCH((k_scatter<R>), dim3((unsigned)b), dim3(256), 0, s, v, nrhs, inv_ptr, inv_slot, N, z);
 }
 
-// One level of the apply sweep, one workgroup per (box, chunk of rc columns).
+// One level of the apply sweep, one workgroup of NT threads per (box, chunk of rc
+// columns); NT = 1024 spreads the product tiles of large boxes over 16 waves.
 // forward:  t = v_r - T^T v_s;  v_r = G^{-T} t;  v_s -= E v_r
 // backward: t = v_r - E^T v_s;  v_r = G^{-1} t;  v_s -= T v_r
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_apply_level(const BoxMeta* __restrict__ meta,
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_apply_level(const BoxMeta* __restrict__ meta,
                                                           const int* __restrict__ sr,
                                                           const int* __restrict__ kk,
                                                           const R* __restrict__ F, R* __restrict__ v,
@@ -2333,7 +2335,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_level(const BoxMeta* __restr
     R* sv = reinterpret_cast<R*>(smem_raw);   // np x rc, rows s then r
     R* tmp = sv + (long)np * rc;              // nr x rc
     const int* ix = sr + M.act;
-    for (long e = tid; e < (long)np * nc; e += kThreads) {
+    for (long e = tid; e < (long)np * nc; e += NT) {
         const int a = (int)(e / nc), c = (int)(e % nc);
         sv[a * rc + c] = v[(long)ix[a] * nrhs + c0 + c];
     }
@@ -2351,22 +2353,22 @@ __global__ __launch_bounds__(kThreads) void k_apply_level(const BoxMeta* __restr
         const R* X1 = forward ? T : E;   // applied first (transposed)
         const R* X2 = forward ? E : T;   // applied last
         if (nc >= 8) {
-            for (long e = tid; e < (long)nr * rc; e += kThreads) tmp[e] = vr[e];
+            for (long e = tid; e < (long)nr * rc; e += NT) tmp[e] = vr[e];
             __syncthreads();
-            if (k > 0) wg_gemm<R>(nc, nr, k, (R)-1, vs, rc, false, X1, k, false, (R)1, tmp, rc);
-            wg_gemm<R>(nc, nr, nr, (R)1, tmp, rc, false, Gi, nr, !forward, (R)0, vr, rc);
-            if (k > 0) wg_gemm<R>(nc, k, nr, (R)-1, vr, rc, false, X2, k, true, (R)1, vs, rc);
+            if (k > 0) wg_gemm<R, NT / 64>(nc, nr, k, (R)-1, vs, rc, false, X1, k, false, (R)1, tmp, rc);
+            wg_gemm<R, NT / 64>(nc, nr, nr, (R)1, tmp, rc, false, Gi, nr, !forward, (R)0, vr, rc);
+            if (k > 0) wg_gemm<R, NT / 64>(nc, k, nr, (R)-1, vr, rc, false, X2, k, true, (R)1, vs, rc);
         } else {
             // a few right-hand sides: one output entry per thread (16 x 16 matrix-core
             // tiles would be mostly empty)
-            for (long e = tid; e < (long)nr * nc; e += kThreads) {
+            for (long e = tid; e < (long)nr * nc; e += NT) {
                 const int i = (int)(e / nc), c = (int)(e % nc);
                 R sum = vr[i * rc + c];
                 for (int a = 0; a < k; ++a) sum -= X1[a + (long)i * k] * vs[a * rc + c];
                 tmp[i * rc + c] = sum;
             }
             __syncthreads();
-            for (long e = tid; e < (long)nr * nc; e += kThreads) {
+            for (long e = tid; e < (long)nr * nc; e += NT) {
                 const int i = (int)(e / nc), c = (int)(e % nc);
                 R sum = 0;
                 if (forward) {
@@ -2377,7 +2379,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_level(const BoxMeta* __restr
                 vr[i * rc + c] = sum;
             }
             __syncthreads();
-            for (long e = tid; e < (long)k * nc; e += kThreads) {
+            for (long e = tid; e < (long)k * nc; e += NT) {
                 const int a = (int)(e / nc), c = (int)(e % nc);
                 R sum = vs[a * rc + c];
                 for (int i = 0; i < nr; ++i) sum -= X2[a + (long)i * k] * vr[i * rc + c];
@@ -2386,7 +2388,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_level(const BoxMeta* __restr
             __syncthreads();
         }
     }
-    for (long e = tid; e < (long)np * nc; e += kThreads) {
+    for (long e = tid; e < (long)np * nc; e += NT) {
         const int a = (int)(e / nc), c = (int)(e % nc);
         v[(long)ix[a] * nrhs + c0 + c] = sv[a * rc + c];
     }
@@ -2394,12 +2396,12 @@ __global__ __launch_bounds__(kThreads) void k_apply_level(const BoxMeta* __restr
 
 template <typename R>
 size_t apply_level_lds_limit() {
-    return dyn_lds_limit((const void*)k_apply_level<R>);
+    return std::min(dyn_lds_limit((const void*)k_apply_level<R, 256>), dyn_lds_limit((const void*)k_apply_level<R, 1024>));
 }
 
 template <typename R>
 void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int* k, const R* F, R* v,
-                        int nrhs, int np_max, int cols, bool forward, hipStream_t s) {
+                        int nrhs, int np_max, int cols, int threads, bool forward, hipStream_t s) {
     if (nbox == 0) return;
     // columns per workgroup: `cols` when given (a tuned choice; the caller has checked
     // its LDS against apply_level_lds_limit), else 16, fewer so that the local copy fits
@@ -2416,8 +2418,14 @@ void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int*
     size_t shm = (size_t)2 * np_max * rc * sizeof(R);
     const long ng = (nrhs + rc - 1) / rc;
     const long blocks = (nbox + 7) / 8 * 8 * ng;
-    CBD_LAUNCH((k_apply_level<R>), dim3((unsigned)blocks), dim3(kThreads), shm, s, meta, sr, k, F, v, nbox, nrhs,
-               rc, forward ? 1 : 0);
+    // 16 waves for boxes of 256 or more DOFs (few boxes, long products), unless given
+    if (threads <= 0) threads = np_max >= 256 ? 1024 : 256;
+    if (threads == 1024)
+        CBD_LAUNCH((k_apply_level<R, 1024>), dim3((unsigned)blocks), dim3(1024), shm, s, meta, sr, k, F, v, nbox,
+                   nrhs, rc, forward ? 1 : 0);
+    else
+        CBD_LAUNCH((k_apply_level<R, 256>), dim3((unsigned)blocks), dim3(256), shm, s, meta, sr, k, F, v, nbox, nrhs,
+                   rc, forward ? 1 : 0);
 }
 
 // Root boxes too large for the LDS apply: v_root <- G^{-1} G^{-T} v_root as two
@@ -2448,14 +2456,19 @@ __global__ __launch_bounds__(kThreads) void k_root_trmm(const BoxMeta* __restric
     const int r0 = blockIdx.y * 64;
     if (r0 >= n) return;
     const int rows = min(64, n - r0);
+    // columns c0.. of the right-hand sides: one 16-wide tile column per workgroup, so a
+    // wave has one 16 x 16 tile of the 64-row chunk
+    const int c0 = blockIdx.z * 16;
+    if (c0 >= nrhs) return;
+    const int ncol = min(16, nrhs - c0);
     const R* Gi = F + M.f;
-    const R* x = in + b * ts;
-    R* y = out + b * ts;
+    const R* x = in + b * ts + (long)c0 * n;
+    R* y = out + b * ts + (long)c0 * n;
     if (transpose) {   // y_rows = (G^{-1})^T x: entries G^{-1}[j][i], j <= i
         const int K = min(n, r0 + 64);
-        wg_gemm<R>(rows, nrhs, K, (R)1, Gi + (long)r0 * n, n, true, x, n, false, (R)0, y + r0, n);
+        wg_gemm<R>(rows, ncol, K, (R)1, Gi + (long)r0 * n, n, true, x, n, false, (R)0, y + r0, n);
     } else {           // y_rows = G^{-1} x: entries G^{-1}[i][j], j >= i
-        wg_gemm<R>(rows, nrhs, n - r0, (R)1, Gi + r0 + (long)r0 * n, n, false, x + r0, n, false, (R)0, y + r0, n);
+        wg_gemm<R>(rows, ncol, n - r0, (R)1, Gi + r0 + (long)r0 * n, n, false, x + r0, n, false, (R)0, y + r0, n);
     }
 }
 
@@ -2466,10 +2479,10 @@ void launch_root_apply(int nbox, int np_max, int unused, const BoxMeta* meta, co
     (void)k;
     if (nbox == 0) return;
     const long ts = (long)np_max * nrhs;
-    const int chunks = (np_max + 63) / 64;
+    const int chunks = (np_max + 63) / 64, groups = (nrhs + 15) / 16;
     CBD_LAUNCH((k_root_move<R>), dim3(nbox, 64), dim3(256), 0, s, meta, sr, v, nrhs, t1, ts, 1);
-    CBD_LAUNCH((k_root_trmm<R>), dim3(nbox, chunks), dim3(kThreads), 0, s, meta, F, nrhs, t1, t2, ts, 1);
-    CBD_LAUNCH((k_root_trmm<R>), dim3(nbox, chunks), dim3(kThreads), 0, s, meta, F, nrhs, t2, t1, ts, 0);
+    CBD_LAUNCH((k_root_trmm<R>), dim3(nbox, chunks, groups), dim3(kThreads), 0, s, meta, F, nrhs, t1, t2, ts, 1);
+    CBD_LAUNCH((k_root_trmm<R>), dim3(nbox, chunks, groups), dim3(kThreads), 0, s, meta, F, nrhs, t2, t1, ts, 0);
     CBD_LAUNCH((k_root_move<R>), dim3(nbox, 64), dim3(256), 0, s, meta, sr, v, nrhs, t1, ts, 0);
 }
 
@@ -2845,7 +2858,7 @@ template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta
     template void launch_scatter<R>(const R*, int, const int*, const int*, long, double*,          \
                                     hipStream_t);                                                   \
     template void launch_apply_level<R>(int, const BoxMeta*, const int*, const int*, const R*, R*,  \
-                                        int, int, int, bool, hipStream_t);                          \
+                                        int, int, int, int, bool, hipStream_t);                     \
     template size_t apply_level_lds_limit<R>();
 CBD_INST(double)
 CBD_INST(float)
