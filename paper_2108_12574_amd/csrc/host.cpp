@@ -2117,7 +2117,7 @@ static int apply_impl(cbd_factor f, int nrhs, const double* r, double* z, long s
         const int nc = std::min(f->apply_rhs, nrhs - c0);
         const double* rc = r + (long)c0 * N;
         double* zc = z + (long)c0 * N;
-        launch_gather<R>(rc, N, nc, f->d_cidx, Q->total, s0, s1, v, s);
+        launch_gather<R>(rc, N, nc, f->d_inv_ptr, f->d_inv_slot, s0, s1, v, s);
         for (int l = 0; l < nl; ++l) {
             const Level& L = f->levels[l];
             if (root_uses_gemm(L)) {   // forward and backward root solve at once
@@ -2178,7 +2178,7 @@ static int autotune_apply_impl(cbd_factor f, int nrhs, const double* r, hipStrea
             // sweeps would scale them up by the inverse's norm every time)
             float ms = 0.f;
             for (int rep = 0; rep < 4; ++rep) {
-                launch_gather<R>(r, N, nrhs, f->d_cidx, Q->total, 0, Q->total, v, s);
+                launch_gather<R>(r, N, nrhs, f->d_inv_ptr, f->d_inv_slot, 0, Q->total, v, s);
                 HIPCHK(hipEventRecord(e0, s));
                 sweep();
                 HIPCHK(hipEventRecord(e1, s));

@@ -225,10 +225,11 @@ constexpr int kBigElim = 256;       // boxes with at least this many DOFs are el
                                     // multi-workgroup path (512^2 factor 23 -> 21.5 ms against 512)
 constexpr int kScratchCols = 64;    // elimination scratch per box: np^2 + kScratchCols * np
 
-// v[slot * nrhs + c] = r[c * N + cidx[slot]] for slots in [s0, s1), zero elsewhere
+// v[slot * nrhs + c] = r[c * N + g] for the slots in [s0, s1) holding grid point g (the
+// inverse map inv_ptr/inv_slot), zero for the other slots
 template <typename R>
-void launch_gather(const double* r, long N, int nrhs, const int* cidx, long total, long s0, long s1, R* v,
-                   hipStream_t s);
+void launch_gather(const double* r, long N, int nrhs, const int* inv_ptr, const int* inv_slot, long s0, long s1,
+                   R* v, hipStream_t s);
 template <typename R>
 void launch_scatter(const R* v, int nrhs, const int* inv_ptr, const int* inv_slot, long N,
                     double* z, hipStream_t s);

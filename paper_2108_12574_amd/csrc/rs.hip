@@ -2234,70 +2234,108 @@ void launch_big_cholesky_inverse(int nbig, int nr_max, const BoxMeta* meta, cons
 // ---- apply ------------------------------------------------------------------
 // v: local vectors of all subdomains, slot-major (v[slot * nrhs + c]).
 // Slots outside [s0, s1) are set to zero (the apply of one subdomain's term).
-// Gather of the subdomains' local vectors, v[slot * nrhs + c] = r[c * N + cidx[slot]]
-// (zero outside the slot range [s0, s1)), through a 64-slot x 64-column LDS tile: the
-// reads run along slots (consecutive grid points within a subdomain), the writes
-// along right-hand sides, both coalesced.
+// Gather of the subdomains' local vectors, v[slot * nrhs + c] = r[c * N + g] for every
+// slot holding grid point g (zero outside the slot range [s0, s1)), 64 points per
+// workgroup: a 64-point x 64-column tile of r is read along points (contiguous in r,
+// every entry once) into LDS together with the points' slot lists (the inverse map),
+// then each wave writes whole slot rows (lane = right-hand side, contiguous in v).
 constexpr int kGT = 64;
+constexpr int kGatherSlots = 512;   // slot entries of a tile held in LDS (8 per point)
 template <typename R>
 __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ r, long N, int nrhs,
-                                                const int* __restrict__ cidx, long total, long s0, long s1,
-                                                R* __restrict__ v) {
+                                                const int* __restrict__ inv_ptr, const int* __restrict__ inv_slot,
+                                                long s0, long s1, R* __restrict__ v) {
     __shared__ R tile[kGT][kGT + 1];
-    const int t = threadIdx.x;
-    const long slot0 = (long)blockIdx.x * kGT;
-    const long slot = slot0 + (t % kGT);
-    const bool in = slot < total;
-    const bool live = in && slot >= s0 && slot < s1;
-    const long g = live ? cidx[slot] : 0;
-    const int nsl = (int)min((long)kGT, total - slot0);
+    __shared__ int sp[kGT + 1], ss[kGatherSlots];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const long g0 = (long)blockIdx.x * kGT;
+    const int npt = (int)min((long)kGT, N - g0);
+    if (t <= npt) sp[t] = inv_ptr[g0 + t];
+    __syncthreads();
+    const int q0 = sp[0], nq = sp[npt] - q0;
+    const bool in_lds = nq <= kGatherSlots;
+    if (in_lds)
+        for (int q = t; q < nq; q += 256) ss[q] = inv_slot[q0 + q];
     for (int c0 = 0; c0 < nrhs; c0 += kGT) {
         const int ncb = min(kGT, nrhs - c0);
+        for (int cc = w; cc < ncb; cc += 4)
+            tile[lane][cc] = lane < npt ? (R)r[(long)(c0 + cc) * N + g0 + lane] : (R)0;
         __syncthreads();
-        for (int cc = t / kGT; cc < ncb; cc += 256 / kGT)
-            tile[t % kGT][cc] = live ? (R)r[(long)(c0 + cc) * N + g] : (R)0;
+        if (lane < ncb)
+            for (int pt = w; pt < npt; pt += 4) {
+                const R x = tile[pt][lane];
+                for (int q = sp[pt]; q < sp[pt + 1]; ++q) {
+                    const long slot = in_lds ? ss[q - q0] : inv_slot[q];
+                    v[slot * nrhs + c0 + lane] = (slot >= s0 && slot < s1) ? x : (R)0;
+                }
+            }
         __syncthreads();
-        for (int idx = t; idx < nsl * ncb; idx += 256) {
-            const int sl = idx / ncb, cc = idx % ncb;
-            v[(slot0 + sl) * nrhs + c0 + cc] = tile[sl][cc];
-        }
     }
 }
 
 template <typename R>
-void launch_gather(const double* r, long N, int nrhs, const int* cidx, long total, long s0, long s1, R* v,
-                   hipStream_t s) {
-    if (total == 0 || nrhs == 0) return;
-    const long b = (total + kGT - 1) / kGT;
-    CBD_LAUNCH((k_gather<R>), dim3((unsigned)b), dim3(256), 0, s, r, N, nrhs, cidx, total, s0, s1, v);
+void launch_gather(const double* r, long N, int nrhs, const int* inv_ptr, const int* inv_slot, long s0, long s1,
+                   R* v, hipStream_t s) {
+    if (N == 0 || nrhs == 0) return;
+    const long b = (N + kGT - 1) / kGT;
+    CBD_LAUNCH((k_gather<R>), dim3((unsigned)b), dim3(256), 0, s, r, N, nrhs, inv_ptr, inv_slot, s0, s1, v);
 }
 
 // z[:, g] = sum over the subdomain slots holding point g, in a fixed order (the
-// inverse map's), for 64 points per workgroup: each wave sums whole slot rows
-// (lane = right-hand side, contiguous reads) into an LDS tile, which is written
-// along points (contiguous in z).
+// inverse map's), for 64 points per workgroup.  The points' slot lists come to LDS
+// first; wave w sums the slot rows (lane = right-hand side, contiguous reads) of its 16
+// points pt = w, w + 4, ..., taking the q-th slot of all 16 points in one round, so
+// their loads are in flight together; each point's sum still adds its slots in the
+// inverse map's order.  The sums go through an LDS tile and are written along points
+// (contiguous in z).
 template <typename R>
 __global__ __launch_bounds__(256) void k_scatter(const R* __restrict__ v, int nrhs, const int* __restrict__ inv_ptr,
                                                  const int* __restrict__ inv_slot, long N, double* __restrict__ z) {
     __shared__ double tile[kGT][kGT + 1];
+    __shared__ int sp[kGT + 1], ss[kGatherSlots];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const long g0 = (long)blockIdx.x * kGT;
     const int npt = (int)min((long)kGT, N - g0);
+    if (t <= npt) sp[t] = inv_ptr[g0 + t];
+    __syncthreads();
+    const int q0 = sp[0], nq = sp[npt] - q0;
+    const bool in_lds = nq <= kGatherSlots;
+    if (in_lds)
+        for (int q = t; q < nq; q += 256) ss[q] = inv_slot[q0 + q];
+    __syncthreads();
+    constexpr int kPer = kGT / 4;   // points per wave
+    int mult = 0;                   // most slots of one of this wave's points
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int pt = w + 4 * j;
+        if (pt < npt) mult = max(mult, sp[pt + 1] - sp[pt]);
+    }
     for (int c0 = 0; c0 < nrhs; c0 += kGT) {
         const int ncb = min(kGT, nrhs - c0);
-        __syncthreads();
-        for (int pt = w; pt < npt; pt += 4) {
-            const long g = g0 + pt;
-            double sum = 0.0;
-            if (lane < ncb)
-                for (int q = inv_ptr[g]; q < inv_ptr[g + 1]; ++q) sum += (double)v[(long)inv_slot[q] * nrhs + c0 + lane];
-            tile[pt][lane] = sum;
-        }
+        double acc[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) acc[j] = 0.0;
+        if (lane < ncb)
+            for (int e = 0; e < mult; ++e) {
+#pragma unroll
+                for (int j = 0; j < kPer; ++j) {
+                    const int pt = w + 4 * j;
+                    if (pt < npt && sp[pt] + e < sp[pt + 1]) {
+                        const int q = sp[pt] + e;
+                        const long slot = in_lds ? ss[q - q0] : inv_slot[q];
+                        acc[j] += (double)v[slot * nrhs + c0 + lane];
+                    }
+                }
+            }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            if (w + 4 * j < npt) tile[w + 4 * j][lane] = acc[j];
         __syncthreads();
         for (int idx = t; idx < npt * ncb; idx += 256) {
             const int cc = idx / npt, pt = idx % npt;
             z[(long)(c0 + cc) * N + g0 + pt] = tile[pt][cc];
         }
+        __syncthreads();
     }
 }
 
@@ -2854,7 +2892,8 @@ template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta
                                                  R*, int*, hipStream_t);                            \
     template void launch_root_apply<R>(int, int, int, const BoxMeta*, const int*, const int*, const R*, \
                                        R*, int, R*, R*, hipStream_t);                               \
-    template void launch_gather<R>(const double*, long, int, const int*, long, long, long, R*, hipStream_t); \
+    template void launch_gather<R>(const double*, long, int, const int*, const int*, long, long, R*,      \
+                                   hipStream_t);                                                    \
     template void launch_scatter<R>(const R*, int, const int*, const int*, long, double*,          \
                                     hipStream_t);                                                   \
     template void launch_apply_level<R>(int, const BoxMeta*, const int*, const int*, const R*, R*,  \
