@@ -334,9 +334,9 @@ int rs_apply_sub(cbd_factor f, int i, int nrhs, const double* r, double* z, void
 
 /* cbd_autotune_apply - choose, level by level, the shape of the apply's level sweep:
  * the right-hand-side columns one workgroup takes (8, 16, 32 or 64; default 16, fewer
- * where a box's local vectors would pass 64 KB of LDS) and its threads (256 or 1024,
- * the product tiles spread over 4 or 16 waves; default 1024 for boxes of 256 or more
- * DOFs), by timing each candidate's forward and backward sweep of that level with HIP
+ * where a box's local vectors would pass 64 KB of LDS) and its threads (256, 512 or
+ * 1024, the product tiles spread over 4, 8 or 16 waves; default 1024 for boxes of 256
+ * or more DOFs, else 256), by timing each candidate's forward and backward sweep of that level with HIP
  * events on `stream`; later rs_apply calls on this factor use the choices.  The result
  * does not depend on them (from 8 columns on, every column's sums run in the same
  * order).  r: device, N x nrhs FP64, a sample right-hand side (read only);

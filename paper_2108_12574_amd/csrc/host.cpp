@@ -2164,8 +2164,8 @@ static int autotune_apply_impl(cbd_factor f, int nrhs, const double* r, hipStrea
         if (root_uses_gemm(L) || L.nbox == 0) continue;
         int best = 0, best_nt = 0;
         float best_t = 0.f;
-        for (int cand = 0; cand < 8; ++cand) {
-            const int cols = 8 << (cand & 3), nt = cand < 4 ? 256 : 1024;
+        for (int cand = 0; cand < 12; ++cand) {
+            const int cols = 8 << (cand & 3), nt = 256 << (cand >> 2);
             if (cols > nrhs && cols != 8) continue;
             if ((size_t)2 * L.np_max * cols * sizeof(R) > lim) continue;
             auto sweep = [&]() {
@@ -2219,8 +2219,8 @@ extern "C" int cbd_apply_set_shape(cbd_factor f, int level, int cols, int thread
     if (!f || level < 0 || level >= (int)f->levels.size()) return fail(CBD_EARG, "cbd_apply_set_shape: bad level");
     if (cols != 0 && cols != 8 && cols != 16 && cols != 32 && cols != 64)
         return fail(CBD_EARG, "cbd_apply_set_shape: cols must be 0, 8, 16, 32 or 64");
-    if (threads != 0 && threads != 256 && threads != 1024)
-        return fail(CBD_EARG, "cbd_apply_set_shape: threads must be 0, 256 or 1024");
+    if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+        return fail(CBD_EARG, "cbd_apply_set_shape: threads must be 0, 256, 512 or 1024");
     Level& L = f->levels[level];
     const size_t es = f->prec == CBD_PREC_FP64 ? sizeof(double) : sizeof(float);
     const size_t lim = f->prec == CBD_PREC_FP64 ? apply_level_lds_limit<double>() : apply_level_lds_limit<float>();

@@ -2348,7 +2348,7 @@ void launch_scatter(const R* v, int nrhs, const int* inv_ptr, const int* inv_slo
 }
 
 // One level of the apply sweep, one workgroup of NT threads per (box, chunk of rc
-// columns); NT = 1024 spreads the product tiles of large boxes over 16 waves.
+// columns); NT = 512 or 1024 spreads the product tiles of a box over 8 or 16 waves.
 // forward:  t = v_r - T^T v_s;  v_r = G^{-T} t;  v_s -= E v_r
 // backward: t = v_r - E^T v_s;  v_r = G^{-1} t;  v_s -= T v_r
 template <typename R, int NT>
@@ -2434,7 +2434,8 @@ __global__ __launch_bounds__(NT) void k_apply_level(const BoxMeta* __restrict__ 
 
 template <typename R>
 size_t apply_level_lds_limit() {
-    return std::min(dyn_lds_limit((const void*)k_apply_level<R, 256>), dyn_lds_limit((const void*)k_apply_level<R, 1024>));
+    return std::min({dyn_lds_limit((const void*)k_apply_level<R, 256>), dyn_lds_limit((const void*)k_apply_level<R, 512>),
+                     dyn_lds_limit((const void*)k_apply_level<R, 1024>)});
 }
 
 template <typename R>
@@ -2460,6 +2461,9 @@ void launch_apply_level(int nbox, const BoxMeta* meta, const int* sr, const int*
     if (threads <= 0) threads = np_max >= 256 ? 1024 : 256;
     if (threads == 1024)
         CBD_LAUNCH((k_apply_level<R, 1024>), dim3((unsigned)blocks), dim3(1024), shm, s, meta, sr, k, F, v, nbox,
+                   nrhs, rc, forward ? 1 : 0);
+    else if (threads == 512)
+        CBD_LAUNCH((k_apply_level<R, 512>), dim3((unsigned)blocks), dim3(512), shm, s, meta, sr, k, F, v, nbox,
                    nrhs, rc, forward ? 1 : 0);
     else
         CBD_LAUNCH((k_apply_level<R, 256>), dim3((unsigned)blocks), dim3(256), shm, s, meta, sr, k, F, v, nbox, nrhs,

@@ -31,11 +31,11 @@ def test_tuned_and_fixed_shapes_give_the_default_result(prec, n, nrhs):
     choices = F.autotune_apply(R)
     nlev = F.stats()["levels"] + 1
     assert len(choices) == nlev
-    assert all(c in (0, 8, 16, 32, 64) and t in (0, 256, 1024) for c, t in choices), choices
+    assert all(c in (0, 8, 16, 32, 64) and t in (0, 256, 512, 1024) for c, t in choices), choices
     print("prec %d n %d nrhs %d: columns per level %s" % (prec, n, nrhs, choices))
     assert torch.equal(F.apply(R), z0)
     for cols in (8, 16, 32, 64):
-        for threads in (256, 1024):
+        for threads in (256, 512, 1024):
             try:
                 F.set_apply_shapes([(cols, threads)] * nlev)
             except cbd.CbdError:
@@ -52,6 +52,6 @@ def test_bad_shapes_are_refused():
     with pytest.raises(cbd.CbdError):
         F.set_apply_shapes([(12, 256)])
     with pytest.raises(cbd.CbdError):
-        F.set_apply_shapes([(16, 512)])
+        F.set_apply_shapes([(16, 768)])
     with pytest.raises(cbd.CbdError):
         F.set_apply_shapes([(16, 256)] * (F.stats()["levels"] + 2))   # one level too many
