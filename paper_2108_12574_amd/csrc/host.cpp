@@ -1623,17 +1623,19 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
         // boxes with many DOFs: Cholesky and inverse as multi-workgroup launch sequences
         // (lists hold chunk-local box indices)
         std::vector<int> small, big;
-        int np_big = 0;
+        int np_big = 0, nr_small = 0;   // largest box of the multi-workgroup path; largest n_r of the others
         for (int B = b0; B < b1; ++B) {
             if (L.meta[B].np >= kBigElim) {
                 big.push_back(B - b0);
                 np_big = std::max(np_big, L.meta[B].np);
             } else {
                 small.push_back(B - b0);
+                nr_small = std::max(nr_small, L.meta[B].np - L.k[B]);
             }
         }
         if (big.empty()) {
-            launch_eliminate<R>(nbc, d_meta_c, nullptr, L.d_perm, d_k_c, App, T64, Wk, FF, d_status, bf16, s);
+            launch_eliminate<R>(nbc, d_meta_c, nullptr, L.d_perm, d_k_c, App, T64, Wk, FF, d_status, bf16, nr_small,
+                                s);
         } else {
             if ((rc = listbuf.ensure(sizeof(int) * nbc))) return rc;
             int* d_small = (int*)listbuf.p;
@@ -1643,7 +1645,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
             lists.insert(lists.end(), big.begin(), big.end());
             if ((rc = io.up(d_small, lists.data(), sizeof(int) * lists.size(), s))) return rc;
             launch_eliminate<R>((int)small.size(), d_meta_c, d_small, L.d_perm, d_k_c, App, T64, Wk, FF,
-                                d_status, bf16, s);
+                                d_status, bf16, nr_small, s);
             launch_big_schur<R>((int)big.size(), np_big, d_meta_c, d_big, 1, L.d_perm, d_k_c, App, T64, Wk, FF,
                                 bf16, s);
             launch_big_cholesky_inverse<R>((int)big.size(), np_big, d_meta_c, d_big, d_k_c, Wk, FF, d_status, s);

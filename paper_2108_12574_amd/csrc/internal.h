@@ -205,7 +205,7 @@ void launch_box_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, cons
 template <typename R>
 void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, const int* perm,
                       const int* k, const R* App, const double* T64, R* Wk, R* F, int* status,
-                      bool bf16, hipStream_t s);
+                      bool bf16, int nr_max, hipStream_t s);
 // the elimination of the boxes in list as multi-workgroup launches: phase 1 up to B_rr,
 // phase 2 E and B_ss (the arithmetic of launch_eliminate, spread over many workgroups)
 template <typename R>

@@ -1869,7 +1869,12 @@ __device__ __forceinline__ ElimView<R> elim_view(const BoxMeta& M, int k, R* Wk,
     return v;
 }
 
-template <typename R, bool BF16>
+// Lds: the Cholesky of B_rr and the inverse run on copies in (dynamic) LDS, B_rr and
+// G^{-1} n_r x n_r each plus n_r x kBlk scratch, for boxes with n_r <= nr_cap (the host
+// reserves that much; a box needing more writes nothing); otherwise they run on the
+// box's scratch and factor slot in global memory, where every step of the column
+// loop waits on global loads.
+template <typename R, bool BF16, bool Lds>
 __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restrict__ meta,
                                                         const int* __restrict__ list,
                                                         const int* __restrict__ perm,
@@ -1877,13 +1882,57 @@ __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restric
                                                         const R* __restrict__ App,
                                                         const double* __restrict__ T64,
                                                         R* __restrict__ Wk, R* __restrict__ F,
-                                                        int* __restrict__ status) {
+                                                        int* __restrict__ status, int nr_cap) {
     __shared__ int s_fail;
+    extern __shared__ char smem_e[];
     const int b = list ? list[blockIdx.x] : blockIdx.x;
     const BoxMeta M = meta[b];
     const ElimView<R> V = elim_view<R>(M, kk[b], Wk, F);
     const int np = V.np, k = V.k, nr = V.nr;
     const int tid = threadIdx.x;
+    if (Lds && nr > nr_cap) return;
+    if (Lds) {
+        R* sS = reinterpret_cast<R*>(smem_e);   // B_rr, then its Cholesky factor G
+        R* sX = sS + (long)nr * nr;             // G^{-1}
+        R* sW = sX + (long)nr * nr;             // n_r x kBlk scratch of the inverse
+        const int* pv = perm + M.act;
+        const R* A = App + M.app;
+        for (long e = tid; e < (long)k * nr; e += kThreads) V.T[e] = (R)T64[M.f + e];
+        for (long e = tid; e < (long)k * k; e += kThreads) {
+            const int a = (int)(e % k), c = (int)(e / k);
+            V.Ass[e] = A[pv[a] + (long)pv[c] * np];
+        }
+        for (long e = tid; e < (long)k * nr; e += kThreads) {
+            const int a = (int)(e % k), i = (int)(e / k);
+            V.Bsr[e] = A[pv[a] + (long)pv[k + i] * np];
+        }
+        for (long e = tid; e < (long)nr * nr; e += kThreads) {
+            const int i = (int)(e % nr), c = (int)(e / nr);
+            V.Brr[e] = A[pv[k + i] + (long)pv[k + c] * np];
+        }
+        if (tid == 0) s_fail = 0;
+        __syncthreads();
+        if (k > 0 && nr > 0) {
+            schur_gemm<R, BF16>(nr, nr, k, (R)-1, V.T, k, true, V.Bsr, k, false, (R)1, V.Brr, nr, true);   // - T^T A_sr
+            schur_gemm<R, BF16>(k, nr, k, (R)-1, V.Ass, k, false, V.T, k, false, (R)1, V.Bsr, k);          // B_sr
+            schur_gemm<R, BF16>(nr, nr, k, (R)-1, V.Bsr, k, true, V.T, k, false, (R)1, V.Brr, nr, true);   // - B_sr^T T
+        }
+        for (long e = tid; e < (long)nr * nr; e += kThreads) sS[e] = V.Brr[e];
+        __syncthreads();
+        if (!wg_cholesky_upper<R>(nr, sS, nr, &s_fail)) {
+            if (tid == 0) status[0] = b + 1;
+            return;
+        }
+        wg_triangular_inverse<R>(nr, sS, nr, sX, sW);
+        for (long e = tid; e < (long)nr * nr; e += kThreads) V.Gi[e] = sX[e];
+        if (k > 0) {
+            schur_gemm<R, BF16>(k, nr, nr, (R)1, V.Bsr, k, false, sX, nr, false, (R)0, V.E, k);   // E = B_sr G^{-1}
+            for (long e = tid; e < (long)k * k; e += kThreads) V.Bss[e] = V.Ass[e];
+            __syncthreads();
+            schur_gemm<R, BF16>(k, k, nr, (R)-1, V.E, k, false, V.E, k, true, (R)1, V.Bss, k);    // B_ss = A_ss - E E^T
+        }
+        return;
+    }
     {
         const int* pv = perm + M.act;
         const R* A = App + M.app;
@@ -2194,19 +2243,37 @@ __global__ __launch_bounds__(kThreads) void k_binv(const BoxMeta* __restrict__ m
     }
 }
 
+// elements of LDS the elimination's Cholesky and inverse take for n_r redundant DOFs
+static size_t eliminate_lds(int nr) { return (size_t)(2L * nr * nr + (long)nr * kBlk); }
+
 template <typename R>
 void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, const int* perm, const int* k,
-                      const R* App, const double* T64, R* Wk, R* F, int* status, bool bf16, hipStream_t s) {
+                      const R* App, const double* T64, R* Wk, R* F, int* status, bool bf16, int nr_max,
+                      hipStream_t s) {
     if (nbox == 0) return;
+    // the Cholesky and inverse in LDS when the largest B_rr of the launch fits (above
+    // 64 KB a workgroup has a CU to itself)
+    const size_t shm = eliminate_lds(nr_max) * sizeof(R);
+    size_t lim = dyn_lds_limit((const void*)k_eliminate<R, false, true>);
+    if constexpr (sizeof(R) == 4) lim = std::min(lim, dyn_lds_limit((const void*)k_eliminate<R, true, true>));
+    const bool lds = nr_max > 0 && shm <= lim;
     if constexpr (sizeof(R) == 4) {
         if (bf16) {
-            CBD_LAUNCH((k_eliminate<R, true>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App,
-                               T64, Wk, F, status);
+            if (lds)
+                CBD_LAUNCH((k_eliminate<R, true, true>), dim3(nbox), dim3(kThreads), shm, s, meta, list, perm, k, App,
+                           T64, Wk, F, status, nr_max);
+            else
+                CBD_LAUNCH((k_eliminate<R, true, false>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App,
+                           T64, Wk, F, status, 0);
             return;
         }
     }
-    CBD_LAUNCH((k_eliminate<R, false>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App, T64,
-                       Wk, F, status);
+    if (lds)
+        CBD_LAUNCH((k_eliminate<R, false, true>), dim3(nbox), dim3(kThreads), shm, s, meta, list, perm, k, App, T64,
+                   Wk, F, status, nr_max);
+    else
+        CBD_LAUNCH((k_eliminate<R, false, false>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App, T64,
+                   Wk, F, status, 0);
 }
 
 template <typename R>
@@ -2889,7 +2956,7 @@ template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta
     template void launch_box_matrix<R>(const ProblemView&, int, const BoxMeta*, const int*,         \
                                        const int*, const ChildRef<R>*, R*, hipStream_t);            \
     template void launch_eliminate<R>(int, const BoxMeta*, const int*, const int*, const int*, \
-                                      const R*, const double*, R*, R*, int*, bool, hipStream_t);    \
+                                      const R*, const double*, R*, R*, int*, bool, int, hipStream_t); \
     template void launch_big_schur<R>(int, int, const BoxMeta*, const int*, int, const int*, const int*, \
                                       const R*, const double*, R*, R*, bool, hipStream_t);          \
     template void launch_big_cholesky_inverse<R>(int, int, const BoxMeta*, const int*, const int*, R*, \
