@@ -1618,7 +1618,7 @@ int factor_impl(cbd_problem_s* P, cbd_partition_s* Q, const cbd_rs_opts* o, cons
             L.k.assign(L.nbox, 0);
             L.sr = hact;
         }
-        launch_box_matrix<R>(PV, nbc, d_meta_c, L.d_act, F->d_cidx,
+        launch_box_matrix<R>(PV, nbc, np_max_c, d_meta_c, L.d_act, F->d_cidx,
                              o_ch ? (const ChildRef<R>*)chbuf.p : nullptr, App, s);
         // boxes with many DOFs: Cholesky and inverse as multi-workgroup launch sequences
         // (lists hold chunk-local box indices)

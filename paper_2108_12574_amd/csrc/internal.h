@@ -198,7 +198,7 @@ inline long kHqrVbuf(int m_max) { return 2L * m_max * 32; }
 void launch_hqr(int nbox, int np_max, int m_max, int k_max, const BoxMeta* meta, double* Y, double* Tw,
                 double* alpha, double* Vbuf, const BoxMeta* cmeta, double* Rc, hipStream_t s);
 template <typename R>
-void launch_box_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, const int* act,
+void launch_box_matrix(const ProblemView& P, int nbox, int np_max, const BoxMeta* meta, const int* act,
                        const int* cidx, const ChildRef<R>* ch, R* App, hipStream_t s);
 // the whole elimination of each box in one workgroup (list: box indices or NULL)
 // bf16: Schur-complement products with bfloat16 operands and FP32 accumulation (R = float)

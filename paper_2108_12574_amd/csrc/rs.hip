@@ -1408,6 +1408,10 @@ void launch_sketch(int nbox, int np_max, long mw_max, const BoxMeta* meta, const
 // ---- box matrix A_pp --------------------------------------------------------
 // Boxes made of grid points take kernel entries; a parent box takes its
 // children's B_ss on the diagonal blocks and kernel entries between children.
+// Workgroup (box, y) fills columns [c_lo, c_hi) of its box.  Columns and rows are
+// staged in LDS in chunks of kBm (grid index, coordinates, column weight or row scale,
+// child reference); then every thread takes entries of the chunk pair, rows fastest,
+// so the writes run down the column-major A and no thread waits on a global load.
 template <int D, typename R>
 __global__ __launch_bounds__(kThreads) void k_box_matrix(ProblemView P,
                                                          const BoxMeta* __restrict__ meta,
@@ -1415,13 +1419,10 @@ __global__ __launch_bounds__(kThreads) void k_box_matrix(ProblemView P,
                                                          const int* __restrict__ cidx,
                                                          const ChildRef<R>* __restrict__ ch,
                                                          R* __restrict__ App) {
-    // rows staged in LDS in chunks of kBmRows (grid index, coordinates, row scale and
-    // the child reference); the workgroup's columns then run over the chunk
-    constexpr int kBmRows = 512;
-    __shared__ double sx[D][kBmRows];
-    __shared__ double srs[kBmRows];
-    __shared__ long sgi[kBmRows];
-    __shared__ ChildRef<R> sref[kBmRows];
+    constexpr int kBm = 256;
+    __shared__ double rx[D][kBm], rsc[kBm], cx[D][kBm], cw[kBm];
+    __shared__ long rgi[kBm], cgi[kBm];
+    __shared__ ChildRef<R> rref[kBm], cref[kBm];
     const BoxMeta M = meta[blockIdx.x];
     const int np = M.np;
     const int per = (np + gridDim.y - 1) / gridDim.y;
@@ -1430,53 +1431,59 @@ __global__ __launch_bounds__(kThreads) void k_box_matrix(ProblemView P,
     const int tid = threadIdx.x;
     const bool parent = M.ch >= 0;
     R* A = App + M.app;
-    for (int r0 = 0; r0 < np; r0 += kBmRows) {
-        const int nrow = min(kBmRows, np - r0);
+    for (int cb = c_lo; cb < c_hi; cb += kBm) {
+        const int ncol = min(kBm, c_hi - cb);
         __syncthreads();
-        for (int rr = tid; rr < nrow; rr += kThreads) {
-            const long gi = cidx[act[M.act + r0 + rr]];
+        for (int i = tid; i < ncol; i += kThreads) {
+            const long gj = cidx[act[M.act + cb + i]];
 #pragma unroll
-            for (int t = 0; t < D; ++t) sx[t][rr] = P.pts[t * P.N + gi];
-            srs[rr] = P.rs[gi];
-            sgi[rr] = gi;
-            if (parent) sref[rr] = ch[M.ch + r0 + rr];
+            for (int t = 0; t < D; ++t) cx[t][i] = P.pts[t * P.N + gj];
+            cw[i] = P.w[gj];
+            cgi[i] = gj;
+            if (parent) cref[i] = ch[M.ch + cb + i];
         }
-        __syncthreads();
-        for (int c = c_lo; c < c_hi; ++c) {
-            const long gj = cidx[act[M.act + c]];
-            double xj[D];
+        for (int r0 = 0; r0 < np; r0 += kBm) {
+            const int nrow = min(kBm, np - r0);
+            if (r0 > 0) __syncthreads();
+            for (int i = tid; i < nrow; i += kThreads) {
+                const long gi = cidx[act[M.act + r0 + i]];
 #pragma unroll
-            for (int t = 0; t < D; ++t) xj[t] = P.pts[t * P.N + gj];
-            const double wj = P.w[gj];
-            ChildRef<R> rc;
-            if (parent) rc = ch[M.ch + c];
-            R* ac = A + (long)c * np + r0;
-            for (int rr = tid; rr < nrow; rr += kThreads) {
+                for (int t = 0; t < D; ++t) rx[t][i] = P.pts[t * P.N + gi];
+                rsc[i] = P.rs[gi];
+                rgi[i] = gi;
+                if (parent) rref[i] = ch[M.ch + r0 + i];
+            }
+            __syncthreads();
+            for (int e = tid; e < nrow * ncol; e += kThreads) {
+                const int rr = e % nrow, cc = e / nrow;
                 R val;
-                if (parent && sref[rr].bss == rc.bss) {
-                    val = sref[rr].bss[sref[rr].pos + (long)rc.pos * sref[rr].ldk];
-                } else if (sgi[rr] == gj) {
-                    val = (R)P.diag[gj];
+                if (parent && rref[rr].bss == cref[cc].bss) {
+                    val = rref[rr].bss[rref[rr].pos + (long)cref[cc].pos * rref[rr].ldk];
+                } else if (rgi[rr] == cgi[cc]) {
+                    val = (R)P.diag[cgi[cc]];
                 } else {
                     double r2 = 0.0;
 #pragma unroll
                     for (int t = 0; t < D; ++t) {
-                        const double dx = sx[t][rr] - xj[t];
+                        const double dx = rx[t][rr] - cx[t][cc];
                         r2 += dx * dx;
                     }
-                    val = (R)(srs[rr] * laplace_from_r2<D>(r2) * wj);
+                    val = (R)(rsc[rr] * laplace_from_r2<D>(r2) * cw[cc]);
                 }
-                ac[rr] = val;
+                A[(long)(cb + cc) * np + r0 + rr] = val;
             }
         }
     }
 }
 
 template <typename R>
-void launch_box_matrix(const ProblemView& P, int nbox, const BoxMeta* meta, const int* act,
+void launch_box_matrix(const ProblemView& P, int nbox, int np_max, const BoxMeta* meta, const int* act,
                        const int* cidx, const ChildRef<R>* ch, R* App, hipStream_t s) {
     if (nbox == 0) return;
-    dim3 grid(nbox, 16);
+    // workgroups per box: about 4096 entries each, at most 16, or more when the level has
+    // few boxes (up to about 1024 workgroups in all)
+    const int cap = std::min(256, std::max(16, 1024 / nbox));
+    dim3 grid(nbox, std::max(1, std::min(cap, (int)(((long)np_max * np_max + 4095) / 4096))));
     if (P.d == 2)
         CBD_LAUNCH((k_box_matrix<2, R>), grid, dim3(kThreads), 0, s, P, meta, act, cidx, ch,
                            App);
@@ -2953,7 +2960,7 @@ template void launch_proxy_matrix<double>(const ProblemView&, int, const BoxMeta
                                           const int*, const int*, const double*, int, double*,
                                           hipStream_t);
 #define CBD_INST(R)                                                                                 \
-    template void launch_box_matrix<R>(const ProblemView&, int, const BoxMeta*, const int*,         \
+    template void launch_box_matrix<R>(const ProblemView&, int, int, const BoxMeta*, const int*,    \
                                        const int*, const ChildRef<R>*, R*, hipStream_t);            \
     template void launch_eliminate<R>(int, const BoxMeta*, const int*, const int*, const int*, \
                                       const R*, const double*, R*, R*, int*, bool, int, hipStream_t); \
