@@ -391,11 +391,30 @@ def main():
         cbd.timing.enable(False)
         t_gpu = cbd.timing.get("factor")[0] / 1e3
         st = fac.stats()
+        sched = fac.schedule()
+        # the same factorization recorded, captured as a graph and replayed five times
+        replay = None
+        if t_gpu < 1.0:
+            del fac
+            fac = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, sketch_seed=sk_seed,
+                             id_method=idm, record=True)
+            fac.capture()
+            times = []
+            for _ in range(5):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ok = fac.replay()
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                assert ok
+            replay = {"replay_s": min(times), "replay_s_all": times, "gflops": st["flops"] / min(times) / 1e9}
         print(json.dumps({"workload": W["label"], "factor_s": t, "factor_gpu_s": t_gpu,
                           "note": "factor_s includes sizing and allocating the workspace; factor_gpu_s is the "
-                                  "factorization's launch sequence between HIP events on its stream",
+                                  "factorization's launch sequence between HIP events on its stream; replay: "
+                                  "the captured graph of the same factorization launched again (wall time, one "
+                                  "synchronization each)",
                           "factor_flops": st["flops"], "factor_gflops": st["flops"] / t_gpu / 1e9,
-                          "schedule": fac.schedule()}))
+                          "schedule": sched, "replay": replay}))
         return
 
     if args.apply_only:
@@ -645,12 +664,17 @@ def main():
 
         # randomized IDs: the CPQR of a random-sign sketch of each proxy matrix (the scheme of
         # the paper's last 3D runs); same predictor, same PCG
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fac_sk = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=1,
-                            id_method=idm)
-        torch.cuda.synchronize()
-        sk_factor = time.perf_counter() - t0
+        # (the better of two factorizations: the first may wait on device allocations)
+        sk_times = []
+        for _ in range(2):
+            fac_sk = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fac_sk = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=prec, mlp=mlp, sketch_seed=1,
+                                id_method=idm)
+            torch.cuda.synchronize()
+            sk_times.append(time.perf_counter() - t0)
+        sk_factor = min(sk_times)
         t0 = time.perf_counter()
         u_sk, its_sk, rr_sk = cbd.pcg_solve(P, fac_sk, F_rhs, tol=1e-10, maxit=200, fft=use_fft)
         torch.cuda.synchronize()
@@ -693,14 +717,18 @@ def main():
             log("%s IDs: %s" % (alt_name, alt_id))
 
         # the bfloat16-GEMM variant of the factors (Schur products on bf16 operands)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         bf16 = None
         try:
-            fac_bf = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_BF16GEMM, mlp=mlp,
-                                sketch_seed=sk_seed, id_method=idm)
-            torch.cuda.synchronize()
-            bf_factor = time.perf_counter() - t0
+            bf_times = []
+            for _ in range(2):   # the better of two, as above
+                fac_bf = None
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fac_bf = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_BF16GEMM,
+                                    mlp=mlp, sketch_seed=sk_seed, id_method=idm)
+                torch.cuda.synchronize()
+                bf_times.append(time.perf_counter() - t0)
+            bf_factor = min(bf_times)
             t0 = time.perf_counter()
             u_bf, its_bf, rr_bf = cbd.pcg_solve(P, fac_bf, F_rhs, tol=1e-10, maxit=400, flexible=True,
                                                 fft=use_fft)
@@ -715,12 +743,16 @@ def main():
         log("bf16-GEMM variant: %s" % bf16)
 
         # plain FP64 form: FP64 factors, right-hand sides one at a time
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fac64 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_FP64, sketch_seed=sk_seed,
-                           id_method=idm)
-        torch.cuda.synchronize()
-        f64_factor = time.perf_counter() - t0
+        f64_times = []
+        for _ in range(2):   # the better of two, as above
+            fac64 = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fac64 = cbd.Factor(P, part, tol=tol, n_pxy=npxy, proxy_ratio=1.5, precision=cbd.PREC_FP64,
+                               sketch_seed=sk_seed, id_method=idm)
+            torch.cuda.synchronize()
+            f64_times.append(time.perf_counter() - t0)
+        f64_factor = min(f64_times)
         t0 = time.perf_counter()
         its64 = []
         ncols = min(args.fp64_cols, nrhs)
