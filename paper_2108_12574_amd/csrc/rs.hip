@@ -1747,6 +1747,8 @@ __device__ __forceinline__ void schur_gemm(int M, int N, int K, R alpha, const R
 // T_I = R_II^{-1} (R12_I - R_{I,>I} T_{>I}); the update is an MFMA GEMM, the
 // diagonal solve one column per thread.  All threads of the workgroup call it.
 __device__ void id_coefficients(const double* Yb, int m, int np, int k, double* T, int c_lo, int c_hi) {
+    __shared__ double s_rblk[16][17];
+    __shared__ double s_x[16][kThreads];
     const int nr = c_hi - c_lo;
     if (nr <= 0 || k == 0) return;
     T += (long)c_lo * k;
@@ -1761,13 +1763,24 @@ __device__ void id_coefficients(const double* Yb, int m, int np, int k, double* 
         if (rest > 0)
             wg_gemm<double>(ib, nr, rest, -1.0, Yb + I + (long)(I + ib) * m, m, false, T + I + ib, k, false, 1.0,
                             T + I, k);
-        for (int c = threadIdx.x; c < nr; c += kThreads) {
-            double* tc = T + (long)c * k;
-            for (int a = I + ib - 1; a >= I; --a) {
-                double sum = tc[a];
-                for (int q = a + 1; q < I + ib; ++q) sum -= Yb[a + (long)q * m] * tc[q];
-                tc[a] = sum / Yb[a + (long)a * m];
+        // the diagonal block of R11 to LDS, and each thread's column of the block to its own
+        // LDS lane (s_x[u][thread], conflict-free), so the solve's dependent steps wait on
+        // LDS instead of global memory; the same operations in the same order as in place
+        for (int e = threadIdx.x; e < ib * ib; e += kThreads) {
+            const int a = e % ib, q = e / ib;
+            s_rblk[a][q] = Yb[(I + a) + (long)(I + q) * m];
+        }
+        __syncthreads();
+        const int t = threadIdx.x;
+        for (int c = t; c < nr; c += kThreads) {
+            double* tc = T + (long)c * k + I;
+            for (int u = 0; u < ib; ++u) s_x[u][t] = tc[u];
+            for (int a = ib - 1; a >= 0; --a) {
+                double sum = s_x[a][t];
+                for (int q = a + 1; q < ib; ++q) sum -= s_rblk[a][q] * s_x[q][t];
+                s_x[a][t] = sum / s_rblk[a][a];
             }
+            for (int u = 0; u < ib; ++u) tc[u] = s_x[u][t];
         }
         __syncthreads();
     }
