@@ -2907,34 +2907,51 @@ __global__ __launch_bounds__(kThreads) void k_pchol_update(const BoxMeta* __rest
 }
 
 // R rows 0..k-1 into Y (ld m, columns in position order) as the QR leaves them, and
-// k, perm and sr as k_qr_finish writes them.
+// k, perm and sr as k_qr_finish writes them.  Workgroup (t, b) takes the 64 x 64 tile t
+// of box b's R: row a of R at column c is L(pv[c], a), stored in G's column pv[a], so
+// the tile is read along c (rows of one column of G) into LDS and written along a
+// (down the columns of Y).  Tile 0 also writes k, perm and sr.
 __global__ __launch_bounds__(kThreads) void k_pchol_finish(const BoxMeta* __restrict__ meta,
                                                            const long* __restrict__ goff,
                                                            const double* __restrict__ G, GramState st,
                                                            double* __restrict__ Y, const int* __restrict__ act,
                                                            int* __restrict__ sr, int* __restrict__ perm,
                                                            int* __restrict__ kout) {
-    const int b = blockIdx.x;
+    __shared__ double tile[64][65];
+    const int b = blockIdx.y;
     const BoxMeta M = meta[b];
     const int m = M.m, np = M.np;
     const int k = st.done[b] ? st.k[b] : min(m, np);
+    const int* pv = st.pv + M.act;
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0) {
+        if (tid == 0) kout[b] = k;
+        for (int c = tid; c < np; c += kThreads) {
+            const int p = pv[c];
+            perm[M.act + c] = p;
+            sr[M.act + c] = act[M.act + p];
+        }
+    }
+    const int nta = (k + 63) / 64, ntc = (np + 63) / 64;
+    if ((int)blockIdx.x >= nta * ntc) return;
+    const int a0 = (int)(blockIdx.x % nta) * 64, c0 = (int)(blockIdx.x / nta) * 64;
     const double* Gb = G + goff[b];
     double* Yb = Y + M.y;
-    const int* pv = st.pv + M.act;
-    for (long e = threadIdx.x; e < (long)k * np; e += kThreads) {
-        const int a = (int)(e % k), c = (int)(e / k);
+    for (int idx = tid; idx < 64 * 64; idx += kThreads) {
+        const int cc = idx & 63, aa = idx >> 6, a = a0 + aa, c = c0 + cc;
         double v = 0.0;
-        if (c == a)
-            v = st.rdiag[M.act + a];
-        else if (c > a)
-            v = Gb[pv[c] + (long)pv[a] * np];
-        Yb[a + (long)c * m] = v;
+        if (a < k && c < np) {
+            if (c == a)
+                v = st.rdiag[M.act + a];
+            else if (c > a)
+                v = Gb[pv[c] + (long)pv[a] * np];
+        }
+        tile[aa][cc] = v;
     }
-    if (threadIdx.x == 0) kout[b] = k;
-    for (int c = threadIdx.x; c < np; c += kThreads) {
-        const int p = pv[c];
-        perm[M.act + c] = p;
-        sr[M.act + c] = act[M.act + p];
+    __syncthreads();
+    for (int idx = tid; idx < 64 * 64; idx += kThreads) {
+        const int aa = idx & 63, cc = idx >> 6, a = a0 + aa, c = c0 + cc;
+        if (a < k && c < np) Yb[a + (long)c * m] = tile[aa][cc];
     }
 }
 
@@ -2962,7 +2979,10 @@ void launch_pchol_finish(int nbox, int np_max, const BoxMeta* meta, const long* 
                          const GramState& st, double* Y, const int* act, int* sr, int* perm, int* k, double* T64,
                          hipStream_t s) {
     if (nbox == 0) return;
-    CBD_LAUNCH(k_pchol_finish, dim3(nbox), dim3(kThreads), 0, s, meta, goff, G, st, Y, act, sr, perm, k);
+    // 64 x 64 tiles of R (k <= n_p), at least one workgroup per box
+    const int nt = (np_max + 63) / 64;
+    CBD_LAUNCH(k_pchol_finish, dim3(std::max(1, nt * nt), nbox), dim3(kThreads), 0, s, meta, goff, G, st, Y, act, sr,
+               perm, k);
     if (np_max > 0)
         CBD_LAUNCH(k_qr_coeff, dim3(nbox, (np_max + kCoeffCols - 1) / kCoeffCols), dim3(kThreads), 0, s, meta, Y, k,
                    T64);
