@@ -2108,7 +2108,6 @@ static bool root_uses_gemm(const Level& L) { return L.root && L.np_max >= kBigBo
 // them: the whole range), in blocks of at most apply_rhs columns.
 template <typename R>
 static int apply_impl(cbd_factor f, int nrhs, const double* r, double* z, long s0, long s1, hipStream_t s) {
-    cbd_partition_s* Q = f->part;
     R* v = (R*)f->v;
     for (const Level& L : f->levels)
         if (!root_uses_gemm(L) && (size_t)2 * L.np_max * sizeof(R) > apply_level_lds_limit<R>())

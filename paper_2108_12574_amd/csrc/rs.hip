@@ -838,7 +838,7 @@ __global__ __launch_bounds__(kHqrThreads) void k_hqr_panel(const BoxMeta* __rest
     __shared__ double red[kHqrPanel][kHqrWaves];
     __shared__ double s_sc[kHqrPanel];
     __shared__ double s_T[kHqrPanel * kHqrPanel];
-    __shared__ double s_x0, s_xn2;
+    __shared__ double s_xn2;
     const int b = blockIdx.x;
     const BoxMeta M = meta[b];
     const int m = M.m, np = M.np, kmax = min(m, np);
