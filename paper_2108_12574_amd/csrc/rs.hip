@@ -2631,8 +2631,6 @@ void launch_root_apply(int nbox, int np_max, int unused, const BoxMeta* meta, co
 constexpr int kGramTile = 64;              // output tile of the Gram and update products
 constexpr int kGramK = 32;                 // rows of Y staged per pass of the Gram product
 constexpr int kGramLd = kGramTile + 1;     // LDS row stride (doubles)
-constexpr int kPcholThreads = 512;
-constexpr int kPcholWaves = kPcholThreads / 64;
 
 __device__ __forceinline__ void lower_tile(int t, int& ti, int& tj) {
     int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -2719,21 +2717,23 @@ __global__ __launch_bounds__(kThreads) void k_gram(const BoxMeta* __restrict__ m
             }
 }
 
-// One panel of at most kPcholPanel pivots per box (one workgroup per box, from step
-// j0).  LDS: d (Schur diagonal), pos (column -> position), pv (position -> column).
-// Row i of every column of L is read and written by thread i % kPcholThreads only,
+// One panel of at most kPcholPanel pivots per box (one workgroup of NT threads per box,
+// from step j0; NT = 128, 256 or 512 by the largest box of the batch, so that small
+// boxes' steps synchronize fewer waves).  LDS: d (Schur diagonal), pos (column -> position), pv (position -> column).
+// Row i of every column of L is read and written by thread i % NT only,
 // so the panel's columns need no cross-thread visibility of global memory.  A step
 // takes three barriers: the largest remaining norm (each thread's part comes from
 // its rows of the previous step's update), the lowest position within the tie
 // window (reduced as position * 4096 + column, so the pivot column needs no
 // lookup), and the pivot row of the panel's earlier columns.
 constexpr int kPcholMaxCols = 16384;  // key range of the pivot reduction (LDS: 16 bytes per column)
-__global__ __launch_bounds__(kPcholThreads) void k_pchol_panel(const BoxMeta* __restrict__ meta,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pchol_panel(const BoxMeta* __restrict__ meta,
                                                                const long* __restrict__ goff, double* __restrict__ G,
                                                                GramState st, int j0, double tol, double tie) {
     extern __shared__ char smem_raw[];
-    __shared__ double red[kPcholWaves];
-    __shared__ int redi[kPcholWaves];
+    __shared__ double red[(NT / 64)];
+    __shared__ int redi[(NT / 64)];
     __shared__ double s_c[kPcholPanel];
     __shared__ int s_piv[kPcholPanel];
     __shared__ double s_r;
@@ -2747,7 +2747,7 @@ __global__ __launch_bounds__(kPcholThreads) void k_pchol_panel(const BoxMeta* __
     int* pv = pos + np;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     double lm = 0.0;   // largest d over this thread's unchosen rows
-    for (int i = tid; i < np; i += kPcholThreads) {
+    for (int i = tid; i < np; i += NT) {
         const int q = j0 == 0 ? i : st.pos[M.act + i];
         pos[i] = q;
         pv[i] = j0 == 0 ? i : st.pv[M.act + i];
@@ -2768,7 +2768,7 @@ __global__ __launch_bounds__(kPcholThreads) void k_pchol_panel(const BoxMeta* __
         __syncthreads();
         double mx = red[0];
 #pragma unroll
-        for (int w = 1; w < kPcholWaves; ++w) mx = fmax(mx, red[w]);
+        for (int w = 1; w < (NT / 64); ++w) mx = fmax(mx, red[w]);
         const double nmax = sqrt(mx);
         if (j == 0) nu0 = nmax;
         if (nu0 == 0.0 || nmax <= tol * nu0) {
@@ -2777,13 +2777,13 @@ __global__ __launch_bounds__(kPcholThreads) void k_pchol_panel(const BoxMeta* __
         }
         const double thr = nmax - tie * nu0;
         int key = INT_MAX;
-        for (int i = tid; i < np; i += kPcholThreads)
+        for (int i = tid; i < np; i += NT)
             if (pos[i] >= j && sqrt(fmax(d[i], 0.0)) >= thr) key = min(key, pos[i] * kPcholMaxCols + i);
         key = wave_min_int(key);
         if (lane == 0) redi[wid] = key;
         __syncthreads();
 #pragma unroll
-        for (int w = 0; w < kPcholWaves; ++w) key = min(key, redi[w]);
+        for (int w = 0; w < (NT / 64); ++w) key = min(key, redi[w]);
         const int P = key / kPcholMaxCols, p = key % kPcholMaxCols;
         if (tid == 0) {
             const int q = pv[j];
@@ -2794,7 +2794,7 @@ __global__ __launch_bounds__(kPcholThreads) void k_pchol_panel(const BoxMeta* __
             s_piv[jj] = p;
         }
         // row p of the panel's earlier columns, read by the thread that wrote them
-        if (tid == p % kPcholThreads) {
+        if (tid == p % NT) {
             for (int q = 0; q < jj; ++q) s_c[q] = Gb[p + (long)s_piv[q] * np];
             s_r = sqrt(d[p]);
             st.rdiag[M.act + j] = s_r;
@@ -2803,7 +2803,7 @@ __global__ __launch_bounds__(kPcholThreads) void k_pchol_panel(const BoxMeta* __
         const double r = s_r;
         double* gp = Gb + (long)p * np;
         lm = 0.0;
-        for (int i = tid; i < np; i += kPcholThreads) {
+        for (int i = tid; i < np; i += NT) {
             if (pos[i] <= j) continue;   // chosen (p now sits at position j)
             double w0 = gp[i], w1 = 0.0, w2 = 0.0, w3 = 0.0;
             int q = 0;
@@ -2822,7 +2822,7 @@ __global__ __launch_bounds__(kPcholThreads) void k_pchol_panel(const BoxMeta* __
         taken = jj + 1;
     }
     __syncthreads();
-    for (int i = tid; i < np; i += kPcholThreads) {
+    for (int i = tid; i < np; i += NT) {
         st.pos[M.act + i] = pos[i];
         st.pv[M.act + i] = pv[i];
     }
@@ -2965,13 +2965,19 @@ size_t pchol_panel_lds(int np_max) { return (size_t)np_max * (sizeof(double) + 2
 
 // Largest dynamic LDS the panel kernel may take on the current device.
 size_t pchol_panel_lds_limit() {
-    return std::min(dyn_lds_limit((const void*)k_pchol_panel), pchol_panel_lds(kPcholMaxCols));
+    return std::min({dyn_lds_limit((const void*)k_pchol_panel<128>), dyn_lds_limit((const void*)k_pchol_panel<256>),
+                     dyn_lds_limit((const void*)k_pchol_panel<512>), pchol_panel_lds(kPcholMaxCols)});
 }
 void launch_pchol_panel(int nbox, int np_max, const BoxMeta* meta, const long* goff, double* G,
                         const GramState& st, int j0, double tol, double tie, hipStream_t s) {
     if (nbox == 0) return;
-    CBD_LAUNCH(k_pchol_panel, dim3(nbox), dim3(kPcholThreads), pchol_panel_lds(np_max), s, meta, goff, G,
-                       st, j0, tol, tie);
+    const size_t shm = pchol_panel_lds(np_max);
+    if (np_max <= 128)
+        CBD_LAUNCH(k_pchol_panel<128>, dim3(nbox), dim3(128), shm, s, meta, goff, G, st, j0, tol, tie);
+    else if (np_max <= 256)
+        CBD_LAUNCH(k_pchol_panel<256>, dim3(nbox), dim3(256), shm, s, meta, goff, G, st, j0, tol, tie);
+    else
+        CBD_LAUNCH(k_pchol_panel<512>, dim3(nbox), dim3(512), shm, s, meta, goff, G, st, j0, tol, tie);
     const int nt = (np_max + kGramTile - 1) / kGramTile;
     if (nt > 0) CBD_LAUNCH(k_pchol_update, dim3(nt * nt, nbox), dim3(kThreads), 0, s, meta, goff, G, st, j0);
 }
