@@ -348,8 +348,8 @@ def main():
                          "the exponents of t_f and m_f in N")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU sharding of the "
-              "path is not implemented", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only (--gpus 1); sharding the path over "
+              "several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.series:
         run_series(args.series, args.id)
