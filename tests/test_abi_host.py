@@ -151,3 +151,15 @@ def test_fft_workspace_size():
     want = 8 * 1024 ** 2 + 16 * 512 + 16 * 1024 ** 2 * 3
     assert L.cbd_fft_workspace_bytes(2, 512, 3) == want
     assert L.cbd_fft_workspace_bytes(4, 512, 3) == 0 and L.cbd_fft_workspace_bytes(2, 512, 0) == 0
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py runs on one GPU: --gpus above 1 exits with status 2 and says why, before
+    touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
