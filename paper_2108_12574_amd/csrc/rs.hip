@@ -1720,11 +1720,12 @@ __device__ __forceinline__ void tile_gemm_bf16(int i0, int j0, int M, int N, int
     }
 }
 
+template <int NW = kWaves>
 __device__ void wg_gemm_bf16(int M, int N, int K, float alpha, const float* A, int lda, bool ta, const float* B,
                              int ldb, bool tb, float beta, float* C, int ldc, bool upper = false) {
     const int wid = threadIdx.x >> 6;
     const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
-    for (int t = wid; t < tm * tn; t += kWaves) {
+    for (int t = wid; t < tm * tn; t += NW) {
         const int i0 = (t % tm) << 4, j0 = (t / tm) << 4;
         if (upper && i0 > j0 + 15) continue;
         tile_gemm_bf16(i0, j0, M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, C, ldc);
@@ -1734,13 +1735,13 @@ __device__ void wg_gemm_bf16(int M, int N, int K, float alpha, const float* A, i
 
 // Schur-complement products of the elimination: FP64/FP32 MFMA, or bfloat16
 // operands with FP32 accumulation when BF16 is set (float storage only).
-template <typename R, bool BF16>
+template <typename R, bool BF16, int NT = kThreads>
 __device__ __forceinline__ void schur_gemm(int M, int N, int K, R alpha, const R* A, int lda, bool ta, const R* B,
                                            int ldb, bool tb, R beta, R* C, int ldc, bool upper = false) {
     if constexpr (BF16)
-        wg_gemm_bf16(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, upper);
+        wg_gemm_bf16<NT / 64>(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, upper);
     else
-        wg_gemm<R>(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, upper);
+        wg_gemm<R, NT / 64>(M, N, K, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc, upper);
 }
 
 // T = R11^{-1} R12 by blocked back substitution over 16-row blocks, bottom up:
@@ -1790,7 +1791,7 @@ constexpr int kBlk = 16;   // block size of the blocked Cholesky / triangular in
 
 // Blocked right-looking Cholesky of the upper triangle of S (n x n, lds): S = G^T G,
 // G overwrites the upper triangle.  Returns false on a non-positive pivot.
-template <typename R>
+template <typename R, int NT = kThreads>
 __device__ bool wg_cholesky_upper(int n, R* S, int lds, int* s_fail) {
     const int tid = threadIdx.x;
     for (int J = 0; J < n; J += kBlk) {
@@ -1805,11 +1806,11 @@ __device__ bool wg_cholesky_upper(int n, R* S, int lds, int* s_fail) {
             __syncthreads();
             if (*s_fail) return false;
             const R g = S[c + (long)c * lds];
-            for (int q = c + 1 + tid; q < n; q += kThreads) S[c + (long)q * lds] /= g;
+            for (int q = c + 1 + tid; q < n; q += NT) S[c + (long)q * lds] /= g;
             __syncthreads();
             // rows c+1 .. J+jb-1 of the block row, all columns right of the diagonal
             const int rows = jb - jj - 1, cols = n - c - 1;
-            for (long e = tid; e < (long)rows * cols; e += kThreads) {
+            for (long e = tid; e < (long)rows * cols; e += NT) {
                 const int a = c + 1 + (int)(e % rows), q = c + 1 + (int)(e / rows);
                 if (q >= a) S[a + (long)q * lds] -= S[c + (long)a * lds] * S[c + (long)q * lds];
             }
@@ -1818,7 +1819,7 @@ __device__ bool wg_cholesky_upper(int n, R* S, int lds, int* s_fail) {
         const int rem = n - J - jb;
         if (rem > 0) {
             const R* P = S + J + (long)(J + jb) * lds;   // jb x rem panel of G
-            wg_gemm<R>(rem, rem, jb, (R)-1, P, lds, true, P, lds, false, (R)1,
+            wg_gemm<R, NT / 64>(rem, rem, jb, (R)-1, P, lds, true, P, lds, false, (R)1,
                        S + (J + jb) + (long)(J + jb) * lds, lds, true);
         }
     }
@@ -1827,16 +1828,16 @@ __device__ bool wg_cholesky_upper(int n, R* S, int lds, int* s_fail) {
 
 // X = G^{-1} for upper-triangular G (n x n, ldg), column-block by column-block:
 // X_JJ = G_JJ^{-1};  X_{0:J,J} = -X_{0:J,0:J} (G_{0:J,J} X_JJ).  W: n x kBlk scratch.
-template <typename R>
+template <typename R, int NT = kThreads>
 __device__ void wg_triangular_inverse(int n, const R* G, int ldg, R* X, R* W) {
     const int tid = threadIdx.x;
-    for (long e = tid; e < (long)n * n; e += kThreads) {
+    for (long e = tid; e < (long)n * n; e += NT) {
         const int a = (int)(e % n), c = (int)(e / n);
         if (a > c) X[e] = (R)0;
     }
     for (int J = 0; J < n; J += kBlk) {
         const int jb = min(kBlk, n - J);
-        for (int c = J + tid; c < J + jb; c += kThreads) {
+        for (int c = J + tid; c < J + jb; c += NT) {
             X[c + (long)c * n] = (R)1 / G[c + (long)c * ldg];
             for (int a = c - 1; a >= J; --a) {
                 R s = 0;
@@ -1846,8 +1847,8 @@ __device__ void wg_triangular_inverse(int n, const R* G, int ldg, R* X, R* W) {
         }
         __syncthreads();
         if (J > 0) {
-            wg_gemm<R>(J, jb, jb, (R)1, G + (long)J * ldg, ldg, false, X + J + (long)J * n, n, false, (R)0, W, J);
-            wg_gemm<R>(J, jb, J, (R)-1, X, n, false, W, J, false, (R)0, X + (long)J * n, n);
+            wg_gemm<R, NT / 64>(J, jb, jb, (R)1, G + (long)J * ldg, ldg, false, X + J + (long)J * n, n, false, (R)0, W, J);
+            wg_gemm<R, NT / 64>(J, jb, J, (R)-1, X, n, false, W, J, false, (R)0, X + (long)J * n, n);
         }
     }
 }
@@ -1894,8 +1895,8 @@ __device__ __forceinline__ ElimView<R> elim_view(const BoxMeta& M, int k, R* Wk,
 // reserves that much; a box needing more writes nothing); otherwise they run on the
 // box's scratch and factor slot in global memory, where every step of the column
 // loop waits on global loads.
-template <typename R, bool BF16, bool Lds>
-__global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restrict__ meta,
+template <typename R, bool BF16, bool Lds, int NT>
+__global__ __launch_bounds__(NT) void k_eliminate(const BoxMeta* __restrict__ meta,
                                                         const int* __restrict__ list,
                                                         const int* __restrict__ perm,
                                                         const int* __restrict__ kk,
@@ -1917,76 +1918,76 @@ __global__ __launch_bounds__(kThreads) void k_eliminate(const BoxMeta* __restric
         R* sW = sX + (long)nr * nr;             // n_r x kBlk scratch of the inverse
         const int* pv = perm + M.act;
         const R* A = App + M.app;
-        for (long e = tid; e < (long)k * nr; e += kThreads) V.T[e] = (R)T64[M.f + e];
-        for (long e = tid; e < (long)k * k; e += kThreads) {
+        for (long e = tid; e < (long)k * nr; e += NT) V.T[e] = (R)T64[M.f + e];
+        for (long e = tid; e < (long)k * k; e += NT) {
             const int a = (int)(e % k), c = (int)(e / k);
             V.Ass[e] = A[pv[a] + (long)pv[c] * np];
         }
-        for (long e = tid; e < (long)k * nr; e += kThreads) {
+        for (long e = tid; e < (long)k * nr; e += NT) {
             const int a = (int)(e % k), i = (int)(e / k);
             V.Bsr[e] = A[pv[a] + (long)pv[k + i] * np];
         }
-        for (long e = tid; e < (long)nr * nr; e += kThreads) {
+        for (long e = tid; e < (long)nr * nr; e += NT) {
             const int i = (int)(e % nr), c = (int)(e / nr);
             V.Brr[e] = A[pv[k + i] + (long)pv[k + c] * np];
         }
         if (tid == 0) s_fail = 0;
         __syncthreads();
         if (k > 0 && nr > 0) {
-            schur_gemm<R, BF16>(nr, nr, k, (R)-1, V.T, k, true, V.Bsr, k, false, (R)1, V.Brr, nr, true);   // - T^T A_sr
-            schur_gemm<R, BF16>(k, nr, k, (R)-1, V.Ass, k, false, V.T, k, false, (R)1, V.Bsr, k);          // B_sr
-            schur_gemm<R, BF16>(nr, nr, k, (R)-1, V.Bsr, k, true, V.T, k, false, (R)1, V.Brr, nr, true);   // - B_sr^T T
+            schur_gemm<R, BF16, NT>(nr, nr, k, (R)-1, V.T, k, true, V.Bsr, k, false, (R)1, V.Brr, nr, true);   // - T^T A_sr
+            schur_gemm<R, BF16, NT>(k, nr, k, (R)-1, V.Ass, k, false, V.T, k, false, (R)1, V.Bsr, k);          // B_sr
+            schur_gemm<R, BF16, NT>(nr, nr, k, (R)-1, V.Bsr, k, true, V.T, k, false, (R)1, V.Brr, nr, true);   // - B_sr^T T
         }
-        for (long e = tid; e < (long)nr * nr; e += kThreads) sS[e] = V.Brr[e];
+        for (long e = tid; e < (long)nr * nr; e += NT) sS[e] = V.Brr[e];
         __syncthreads();
-        if (!wg_cholesky_upper<R>(nr, sS, nr, &s_fail)) {
+        if (!wg_cholesky_upper<R, NT>(nr, sS, nr, &s_fail)) {
             if (tid == 0) status[0] = b + 1;
             return;
         }
-        wg_triangular_inverse<R>(nr, sS, nr, sX, sW);
-        for (long e = tid; e < (long)nr * nr; e += kThreads) V.Gi[e] = sX[e];
+        wg_triangular_inverse<R, NT>(nr, sS, nr, sX, sW);
+        for (long e = tid; e < (long)nr * nr; e += NT) V.Gi[e] = sX[e];
         if (k > 0) {
-            schur_gemm<R, BF16>(k, nr, nr, (R)1, V.Bsr, k, false, sX, nr, false, (R)0, V.E, k);   // E = B_sr G^{-1}
-            for (long e = tid; e < (long)k * k; e += kThreads) V.Bss[e] = V.Ass[e];
+            schur_gemm<R, BF16, NT>(k, nr, nr, (R)1, V.Bsr, k, false, sX, nr, false, (R)0, V.E, k);   // E = B_sr G^{-1}
+            for (long e = tid; e < (long)k * k; e += NT) V.Bss[e] = V.Ass[e];
             __syncthreads();
-            schur_gemm<R, BF16>(k, k, nr, (R)-1, V.E, k, false, V.E, k, true, (R)1, V.Bss, k);    // B_ss = A_ss - E E^T
+            schur_gemm<R, BF16, NT>(k, k, nr, (R)-1, V.E, k, false, V.E, k, true, (R)1, V.Bss, k);    // B_ss = A_ss - E E^T
         }
         return;
     }
     {
         const int* pv = perm + M.act;
         const R* A = App + M.app;
-        for (long e = tid; e < (long)k * nr; e += kThreads) V.T[e] = (R)T64[M.f + e];
-        for (long e = tid; e < (long)k * k; e += kThreads) {
+        for (long e = tid; e < (long)k * nr; e += NT) V.T[e] = (R)T64[M.f + e];
+        for (long e = tid; e < (long)k * k; e += NT) {
             const int a = (int)(e % k), c = (int)(e / k);
             V.Ass[e] = A[pv[a] + (long)pv[c] * np];
         }
-        for (long e = tid; e < (long)k * nr; e += kThreads) {
+        for (long e = tid; e < (long)k * nr; e += NT) {
             const int a = (int)(e % k), i = (int)(e / k);
             V.Bsr[e] = A[pv[a] + (long)pv[k + i] * np];
         }
-        for (long e = tid; e < (long)nr * nr; e += kThreads) {
+        for (long e = tid; e < (long)nr * nr; e += NT) {
             const int i = (int)(e % nr), c = (int)(e / nr);
             V.Brr[e] = A[pv[k + i] + (long)pv[k + c] * np];
         }
         if (tid == 0) s_fail = 0;
         __syncthreads();
         if (k > 0 && nr > 0) {
-            schur_gemm<R, BF16>(nr, nr, k, (R)-1, V.T, k, true, V.Bsr, k, false, (R)1, V.Brr, nr, true);   // - T^T A_sr
-            schur_gemm<R, BF16>(k, nr, k, (R)-1, V.Ass, k, false, V.T, k, false, (R)1, V.Bsr, k);          // B_sr
-            schur_gemm<R, BF16>(nr, nr, k, (R)-1, V.Bsr, k, true, V.T, k, false, (R)1, V.Brr, nr, true);   // - B_sr^T T
+            schur_gemm<R, BF16, NT>(nr, nr, k, (R)-1, V.T, k, true, V.Bsr, k, false, (R)1, V.Brr, nr, true);   // - T^T A_sr
+            schur_gemm<R, BF16, NT>(k, nr, k, (R)-1, V.Ass, k, false, V.T, k, false, (R)1, V.Bsr, k);          // B_sr
+            schur_gemm<R, BF16, NT>(nr, nr, k, (R)-1, V.Bsr, k, true, V.T, k, false, (R)1, V.Brr, nr, true);   // - B_sr^T T
         }
-        if (!wg_cholesky_upper<R>(nr, V.Brr, nr, &s_fail)) {
+        if (!wg_cholesky_upper<R, NT>(nr, V.Brr, nr, &s_fail)) {
             if (tid == 0) status[0] = b + 1;
             return;
         }
-        wg_triangular_inverse<R>(nr, V.Brr, nr, V.Gi, V.W);
+        wg_triangular_inverse<R, NT>(nr, V.Brr, nr, V.Gi, V.W);
     }
     if (k > 0) {
-        schur_gemm<R, BF16>(k, nr, nr, (R)1, V.Bsr, k, false, V.Gi, nr, false, (R)0, V.E, k);     // E = B_sr G^{-1}
-        for (long e = tid; e < (long)k * k; e += kThreads) V.Bss[e] = V.Ass[e];
+        schur_gemm<R, BF16, NT>(k, nr, nr, (R)1, V.Bsr, k, false, V.Gi, nr, false, (R)0, V.E, k);     // E = B_sr G^{-1}
+        for (long e = tid; e < (long)k * k; e += NT) V.Bss[e] = V.Ass[e];
         __syncthreads();
-        schur_gemm<R, BF16>(k, k, nr, (R)-1, V.E, k, false, V.E, k, true, (R)1, V.Bss, k);        // B_ss = A_ss - E E^T
+        schur_gemm<R, BF16, NT>(k, k, nr, (R)-1, V.E, k, false, V.E, k, true, (R)1, V.Bss, k);        // B_ss = A_ss - E E^T
     }
 }
 
@@ -2263,6 +2264,12 @@ __global__ __launch_bounds__(kThreads) void k_binv(const BoxMeta* __restrict__ m
     }
 }
 
+// threads of the elimination's workgroups on the LDS path when the launch's largest n_r
+// passes kElimWide (few workgroups fit a CU there; measured at 512^2: 512 threads faster
+// for n_r up to 85 and 120, slower for n_r up to 64)
+constexpr int kElimLdsThreads = 512;
+constexpr int kElimWide = 64;
+
 // elements of LDS the elimination's Cholesky and inverse take for n_r redundant DOFs
 static size_t eliminate_lds(int nr) { return (size_t)(2L * nr * nr + (long)nr * kBlk); }
 
@@ -2274,26 +2281,37 @@ void launch_eliminate(int nbox, const BoxMeta* meta, const int* list, const int*
     // the Cholesky and inverse in LDS when the largest B_rr of the launch fits (above
     // 64 KB a workgroup has a CU to itself)
     const size_t shm = eliminate_lds(nr_max) * sizeof(R);
-    size_t lim = dyn_lds_limit((const void*)k_eliminate<R, false, true>);
-    if constexpr (sizeof(R) == 4) lim = std::min(lim, dyn_lds_limit((const void*)k_eliminate<R, true, true>));
+    constexpr int NL = kElimLdsThreads, NG = kThreads;
+    size_t lim = std::min(dyn_lds_limit((const void*)k_eliminate<R, false, true, NL>),
+                          dyn_lds_limit((const void*)k_eliminate<R, false, true, NG>));
+    if constexpr (sizeof(R) == 4)
+        lim = std::min({lim, dyn_lds_limit((const void*)k_eliminate<R, true, true, NL>),
+                        dyn_lds_limit((const void*)k_eliminate<R, true, true, NG>)});
     const bool lds = nr_max > 0 && shm <= lim;
+    const bool wide = nr_max > kElimWide;
     if constexpr (sizeof(R) == 4) {
         if (bf16) {
-            if (lds)
-                CBD_LAUNCH((k_eliminate<R, true, true>), dim3(nbox), dim3(kThreads), shm, s, meta, list, perm, k, App,
+            if (lds && wide)
+                CBD_LAUNCH((k_eliminate<R, true, true, NL>), dim3(nbox), dim3(NL), shm, s, meta, list, perm, k, App,
+                           T64, Wk, F, status, nr_max);
+            else if (lds)
+                CBD_LAUNCH((k_eliminate<R, true, true, NG>), dim3(nbox), dim3(NG), shm, s, meta, list, perm, k, App,
                            T64, Wk, F, status, nr_max);
             else
-                CBD_LAUNCH((k_eliminate<R, true, false>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App,
+                CBD_LAUNCH((k_eliminate<R, true, false, NG>), dim3(nbox), dim3(NG), 0, s, meta, list, perm, k, App,
                            T64, Wk, F, status, 0);
             return;
         }
     }
-    if (lds)
-        CBD_LAUNCH((k_eliminate<R, false, true>), dim3(nbox), dim3(kThreads), shm, s, meta, list, perm, k, App, T64,
-                   Wk, F, status, nr_max);
+    if (lds && wide)
+        CBD_LAUNCH((k_eliminate<R, false, true, NL>), dim3(nbox), dim3(NL), shm, s, meta, list, perm, k, App, T64, Wk,
+                   F, status, nr_max);
+    else if (lds)
+        CBD_LAUNCH((k_eliminate<R, false, true, NG>), dim3(nbox), dim3(NG), shm, s, meta, list, perm, k, App, T64, Wk,
+                   F, status, nr_max);
     else
-        CBD_LAUNCH((k_eliminate<R, false, false>), dim3(nbox), dim3(kThreads), 0, s, meta, list, perm, k, App, T64,
-                   Wk, F, status, 0);
+        CBD_LAUNCH((k_eliminate<R, false, false, NG>), dim3(nbox), dim3(NG), 0, s, meta, list, perm, k, App, T64, Wk,
+                   F, status, 0);
 }
 
 template <typename R>
