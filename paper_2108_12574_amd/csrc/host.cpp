@@ -787,10 +787,8 @@ struct FactorIo {
         if (mode == CAPTURE) {
             if (ri >= tape->rd_len.size() || tape->rd_len[ri] != b) return plan_differs();
             if (b % 4 != 0 || (uintptr_t)src % 4 != 0) return fail(CBD_EARG, "rs_factor_capture: unaligned read");
-            if (b && check) {
-                std::memcpy(dst, tape->rd.data() + tape->rd_off[ri], b);
-                launch_check_words(src, d_rd + tape->rd_off[ri], b, flag, s);
-            }
+            if (b) std::memcpy(dst, tape->rd.data() + tape->rd_off[ri], b);
+            if (b && check) launch_check_words(src, d_rd + tape->rd_off[ri], b, flag, s);
             ++ri;
             return CBD_OK;
         }
