@@ -293,8 +293,9 @@ int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispre
  * lists, stop flags of the pivoted QR or Cholesky, rank predictions, breakdown slots).
  * rs_factor_capture re-plays that host side without running anything and captures the
  * same kernel sequence, on the same workspace addresses, into one executable graph:
- * uploads become copies from gws, and each read becomes a check of the device value
- * against the recorded one.  rs_factor_replay launches the graph on `stream`, so every
+ * uploads become copies from gws, and each read (but the breakdown slots, which the
+ * replay reads back itself) becomes a check of the device value against the recorded
+ * one.  rs_factor_replay launches the graph on `stream`, so every
  * kernel of the factorization runs again on the problem's current device data (pts,
  * diag, w, rowscale), and synchronizes once to read the checks.  When every read
  * matches, every decision of the host is the one an eager factorization of that data
@@ -312,7 +313,7 @@ int rs_factor_schedule(cbd_factor f, int* host_syncs, int* qr_steps, int* mispre
  *    Does not write ranks_out.  Synchronizes `stream` once (the upload of gws); the
  *    capture itself runs on a stream of its own.  Capturing again replaces the graph.
  *  rs_factor_replay: calls on one factor, and any other use of its workspace
- *    (rs_apply), must not overlap in time. */
+ *    (rs_apply), must not overlap in time.  CBD_EARG without a captured graph. */
 size_t rs_factor_graph_bytes(cbd_factor f);
 int rs_factor_capture(cbd_factor f, void* gws, size_t gws_bytes, void* stream);
 int rs_factor_replay(cbd_factor f, void* stream);
